@@ -1,0 +1,309 @@
+"""FP64 CPU reference ("oracle") for the EI-ZO hot path -- TEST INFRASTRUCTURE.
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
+use this package.  The product (the HIP library and its Python binding) never
+imports it.  The numerics live in `ezo_oracle.c` (plain C, double precision);
+this module compiles it with gcc and marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ezo_oracle.c")
+_SO = os.path.join(_HERE, "libezo_oracle.so")
+
+CERTIFIED, MAX_ITERS, IN_COLLISION, INVALID = 0, 1, 2, 3
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle (gcc -O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-Wno-unknown-pragmas", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        _lib = C.CDLL(_SO)
+        _declare(_lib)
+    return _lib
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_u8p = C.POINTER(C.c_uint8)
+_u32p = C.POINTER(C.c_uint32)
+
+
+class _Robot(C.Structure):
+    _fields_ = [("dof", C.c_int32), ("a", _dp), ("alpha", _dp), ("d", _dp),
+                ("q_lo", _dp), ("q_hi", _dp), ("n_spheres", C.c_int32),
+                ("sphere_link", _ip), ("sphere_xyz", _dp), ("sphere_r", _dp),
+                ("n_self", C.c_int32), ("self_pairs", _ip)]
+
+
+class Params(C.Structure):
+    _fields_ = [("eps", C.c_double), ("delta", C.c_double), ("tau", C.c_double),
+                ("step_back_max", C.c_double), ("t_col", C.c_double),
+                ("n_p", C.c_int32), ("n_f", C.c_int32), ("n_b", C.c_int32),
+                ("n_mix", C.c_int32), ("max_iters", C.c_int32),
+                ("seed", C.c_uint64), ("edge_id", C.c_int64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("planes", C.c_int32),
+                ("final_m", C.c_int64), ("test_collisions", C.c_int64),
+                ("samples", C.c_int64), ("checks", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _declare(L):
+    rp = C.POINTER(_Robot)
+    L.orc_link_frames.argtypes = [rp, _dp, _dp]
+    L.orc_sphere_centres.argtypes = [rp, _dp, _dp]
+    L.orc_check_config.argtypes = [rp, _dp, C.c_int32, _dp, _dp, _dp]
+    L.orc_check_batch.argtypes = [rp, _dp, C.c_int32, _dp, C.c_int64, _u8p, _dp, _dp, _dp]
+    L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+    L.orc_u01.argtypes = [C.c_uint32]
+    L.orc_u01.restype = C.c_double
+    L.orc_test_constants.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, _i64p, _i64p]
+    L.orc_hit_and_run.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, C.c_int32, C.c_uint64,
+                                  C.c_uint32, C.c_uint32, C.c_int64, _dp]
+    L.orc_project.argtypes = [C.c_int32, _dp, _dp, _dp, _dp, _dp]
+    L.orc_bisect_arm.argtypes = [rp, _dp, C.c_int32, _dp, _dp, _dp, C.c_int32, _dp, _dp, _dp, _dp, _dp]
+    L.orc_bisect_arm.restype = C.c_int
+    L.orc_bisect_balls.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, _dp, C.c_int32,
+                                   _dp, _dp, _dp, _dp, _dp]
+    L.orc_bisect_balls.restype = C.c_int
+    L.orc_place.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, _dp, C.c_int32, C.c_double,
+                            C.c_double, _dp, _dp, _ip, C.c_int32, _ip, _ip]
+    L.orc_place.restype = C.c_int
+    L.orc_eizo_arm.argtypes = [rp, _dp, C.c_int32, _dp, _dp, C.c_int32, _dp, _dp,
+                               C.POINTER(Params), _dp, _dp, C.c_int32, _ip, C.POINTER(Stats)]
+    L.orc_eizo_arm.restype = C.c_int
+    L.orc_eizo_balls.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, C.c_int32, _dp, _dp,
+                                 C.POINTER(Params), _dp, _dp, C.c_int32, _ip, C.POINTER(Stats)]
+    L.orc_eizo_balls.restype = C.c_int
+    L.orc_set_threads.argtypes = [C.c_int32]
+    L.orc_max_threads.restype = C.c_int32
+
+
+def _d(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _ptr(a, t=_dp):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+class Robot:
+    """Holds FP64 copies of a robot description (dict as produced by the
+    workload files) and the ctypes struct pointing at them."""
+
+    def __init__(self, desc: dict, self_pairs=None):
+        self.dof = int(desc["dof"])
+        self.a = _d(desc["a"])
+        self.alpha = _d(desc["alpha"])
+        self.d = _d(desc["d"])
+        self.q_lo = _d(desc["q_lo"])
+        self.q_hi = _d(desc["q_hi"])
+        self.sphere_link = np.ascontiguousarray(desc["sphere_link"], dtype=np.int32)
+        self.sphere_xyz = _d(desc["sphere_xyz"]).reshape(-1, 3)
+        self.sphere_r = _d(desc["sphere_r"])
+        sp = desc.get("self_pairs") if self_pairs is None else self_pairs
+        if sp is None:
+            sp = np.zeros((0, 2), np.int32)
+        self.self_pairs = np.ascontiguousarray(sp, dtype=np.int32).reshape(-1, 2)
+        self.n_spheres = len(self.sphere_r)
+        self._s = _Robot(self.dof, _ptr(self.a), _ptr(self.alpha), _ptr(self.d), _ptr(self.q_lo),
+                         _ptr(self.q_hi), self.n_spheres, _ptr(self.sphere_link, _ip),
+                         _ptr(self.sphere_xyz), _ptr(self.sphere_r), len(self.self_pairs),
+                         _ptr(self.self_pairs, _ip))
+
+    @property
+    def ref(self):
+        return C.byref(self._s)
+
+    def box(self):
+        """Domain D = joint-limit box as rows [+e_j <= hi_j] then [-e_j <= -lo_j]."""
+        A = np.concatenate([np.eye(self.dof), -np.eye(self.dof)])
+        b = np.concatenate([self.q_hi, -self.q_lo])
+        return A, b
+
+
+def set_threads(n: int):
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
+def link_frames(robot: Robot, q):
+    q = _d(q)
+    out = np.empty((robot.dof, 4, 4))
+    lib().orc_link_frames(robot.ref, _ptr(q), _ptr(out))
+    return out
+
+
+def sphere_centres(robot: Robot, q):
+    q = _d(q)
+    out = np.empty((robot.n_spheres, 3))
+    lib().orc_sphere_centres(robot.ref, _ptr(q), _ptr(out))
+    return out
+
+
+def check(robot: Robot, obs, q):
+    """Returns (flags u8[n], min_sd[n], sd_env[n], sd_self[n]) for q [n][dof]."""
+    q = _d(q).reshape(-1, robot.dof)
+    obs = _d(obs).reshape(-1, 4)
+    n = q.shape[0]
+    flags = np.empty(n, np.uint8)
+    sd, se, ss = np.empty(n), np.empty(n), np.empty(n)
+    lib().orc_check_batch(robot.ref, _ptr(obs), obs.shape[0], _ptr(q), n, _ptr(flags, _u8p),
+                          _ptr(sd), _ptr(se), _ptr(ss))
+    return flags, sd, se, ss
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty(4, np.uint32)
+    lib().orc_philox4x32_10(_ptr(c, _u32p), _ptr(k, _u32p), _ptr(out, _u32p))
+    return out
+
+
+def u01(x: int) -> float:
+    return float(lib().orc_u01(int(x) & 0xFFFFFFFF))
+
+
+def test_constants(eps, delta, tau, k):
+    M, T = C.c_int64(), C.c_int64()
+    lib().orc_test_constants(eps, delta, tau, int(k), C.byref(M), C.byref(T))
+    return M.value, T.value
+
+
+def hit_and_run(A, b, v1, v2, n_mix, seed, edge, k, n):
+    A = _d(A)
+    b = _d(b)
+    d = A.shape[1]
+    v1, v2 = _d(v1), _d(v2)
+    S = np.empty((n, d))
+    lib().orc_hit_and_run(d, _ptr(A), _ptr(b), A.shape[0], _ptr(v1), _ptr(v2), int(n_mix),
+                          int(seed), int(edge), int(k), int(n), _ptr(S))
+    return S
+
+
+def project(v1, v2, c):
+    v1, v2, c = _d(v1), _d(v2), _d(c)
+    cp = np.empty_like(c)
+    al = C.c_double()
+    lib().orc_project(len(c), _ptr(v1), _ptr(v2), _ptr(c), _ptr(cp), C.byref(al))
+    return cp, al.value
+
+
+def bisect_arm(robot: Robot, obs, v1, v2, c, n_b):
+    obs = _d(obs).reshape(-1, 4)
+    v1, v2, c = _d(v1), _d(v2), _d(c)
+    d = robot.dof
+    cs, ad, cp = np.empty(d), np.empty(d), np.empty(d)
+    t, m = C.c_double(), C.c_double()
+    p = lib().orc_bisect_arm(robot.ref, _ptr(obs), obs.shape[0], _ptr(v1), _ptr(v2), _ptr(c),
+                             int(n_b), _ptr(cs), C.byref(t), _ptr(ad), _ptr(cp), C.byref(m))
+    return dict(proj_collides=bool(p), c_star=cs, t_star=t.value, a=ad, c_proj=cp,
+                min_abs_sd=m.value)
+
+
+def bisect_balls(centres, radii, v1, v2, c, n_b):
+    centres, radii = _d(centres), _d(radii)
+    dim = centres.shape[1]
+    v1, v2, c = _d(v1), _d(v2), _d(c)
+    cs, ad, cp = np.empty(dim), np.empty(dim), np.empty(dim)
+    t, m = C.c_double(), C.c_double()
+    p = lib().orc_bisect_balls(dim, _ptr(centres), _ptr(radii), len(radii), _ptr(v1), _ptr(v2),
+                               _ptr(c), int(n_b), _ptr(cs), C.byref(t), _ptr(ad), _ptr(cp),
+                               C.byref(m))
+    return dict(proj_collides=bool(p), c_star=cs, t_star=t.value, a=ad, c_proj=cp,
+                min_abs_sd=m.value)
+
+
+def place(v1, v2, c_star, a_dir, t_star, n_f, step_back_max, t_col, A, b, cap=None):
+    """Append up to n_f planes to (A, b).  Returns (A_new, b_new, status, placed_idx)."""
+    v1, v2 = _d(v1), _d(v2)
+    d = len(v1)
+    c_star = _d(c_star).reshape(-1, d)
+    a_dir = _d(a_dir).reshape(-1, d)
+    t_star = _d(t_star)
+    n = len(t_star)
+    A = _d(A).reshape(-1, d)
+    b = _d(b)
+    F0 = len(b)
+    cap = F0 + n_f if cap is None else cap
+    Ab = np.zeros((cap, d))
+    bb = np.zeros(cap)
+    Ab[:F0] = A
+    bb[:F0] = b
+    nf = C.c_int32(F0)
+    idx = np.zeros(max(n_f, 1), np.int32)
+    npl = C.c_int32()
+    st = lib().orc_place(d, _ptr(v1), _ptr(v2), n, _ptr(c_star), _ptr(a_dir), _ptr(t_star),
+                         int(n_f), float(step_back_max), float(t_col), _ptr(Ab), _ptr(bb),
+                         C.byref(nf), cap, _ptr(idx, _ip), C.byref(npl))
+    return Ab[:nf.value], bb[:nf.value], st, idx[:npl.value]
+
+
+def make_params(eps=0.1, delta=0.05, tau=0.5, step_back_max=0.01, t_col=1e-4, n_p=1000, n_f=10,
+                n_b=11, n_mix=30, max_iters=50, seed=0, edge_id=0) -> Params:
+    return Params(eps, delta, tau, step_back_max, t_col, n_p, n_f, n_b, n_mix, max_iters,
+                  seed, edge_id)
+
+
+def _eizo_common(call, dof, A_D, b_D, v1, v2, prm: Params, cap):
+    A_D, b_D, v1, v2 = _d(A_D), _d(b_D), _d(v1), _d(v2)
+    if cap is None:
+        cap = len(b_D) + prm.n_f * prm.max_iters
+    A = np.zeros((cap, dof))
+    b = np.zeros(cap)
+    nf = C.c_int32()
+    st = Stats()
+    status = call(A_D, b_D, v1, v2, A, b, cap, nf, st)
+    return dict(status=status, A=A[:nf.value].copy(), b=b[:nf.value].copy(), stats=st.as_dict())
+
+
+def eizo_arm(robot: Robot, obs, v1, v2, prm: Params, cap=None):
+    obs = _d(obs).reshape(-1, 4)
+    A_D, b_D = robot.box()
+
+    def call(A_D, b_D, v1, v2, A, b, cap, nf, st):
+        return lib().orc_eizo_arm(robot.ref, _ptr(obs), obs.shape[0], _ptr(A_D), _ptr(b_D),
+                                  len(b_D), _ptr(v1), _ptr(v2), C.byref(prm), _ptr(A), _ptr(b),
+                                  cap, C.byref(nf), C.byref(st))
+    return _eizo_common(call, robot.dof, A_D, b_D, v1, v2, prm, cap)
+
+
+def eizo_balls(centres, radii, A_D, b_D, v1, v2, prm: Params, cap=None):
+    centres, radii = _d(centres), _d(radii)
+    dim = centres.shape[1]
+
+    def call(A_D, b_D, v1, v2, A, b, cap, nf, st):
+        return lib().orc_eizo_balls(dim, _ptr(centres), _ptr(radii), len(radii), _ptr(A_D),
+                                    _ptr(b_D), len(b_D), _ptr(v1), _ptr(v2), C.byref(prm),
+                                    _ptr(A), _ptr(b), cap, C.byref(nf), C.byref(st))
+    return _eizo_common(call, dim, A_D, b_D, v1, v2, prm, cap)
