@@ -1,0 +1,161 @@
+#!/usr/bin/env python
+"""Throughput of the EI-ZO hot path on one MI355X.
+
+A step is one pass of the whole hot path -- ezo_inflate_edges on the
+workload's edges (hit-and-run sampling, FK + collision checks, unadaptive
+test, projection + bisection, hyperplane placement, every iteration until
+every edge is certified) -- with all inputs resident in HBM.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dof7|batched|tiny]
+
+Prints one JSON line.  `value` = collision-checked configurations per second
+(exact checks counted by the library, summed over the step, divided by the
+step time); `edges_per_s` is the same run's edges inflated per second.
+`roofline` reports the dominant kernel phase timed live with hipEvents on the
+stream it runs on; `cpu_baseline` times the FP64 reference on one full
+inflation of the same workload (rank 0 only).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector peak
+FK_FLOP = 1800                # forward kinematics per configuration (7 links)
+PAIR_FLOP = 13                # one sphere-sphere signed-distance test
+
+WORKLOADS = {
+    "dof7": "7-DOF DH arm (7x10 spheres, 1500 self pairs), 512 obstacle spheres, one edge; "
+            "N_p=10000, eps=0.05, delta=0.05, tau=0.5, N_f=10, N_b=11, N_mix=60",
+    "batched": "7-DOF DH arm, 2048 obstacle spheres, 96 edges of 8 uneven paths in one call; "
+               "N_p=10000, eps=0.05, delta=0.05, N_mix=60",
+    "tiny": "3-DOF planar arm (12 spheres), 20 obstacle discs, one edge; N_p=1000, eps=0.1, delta=0.05",
+}
+
+
+def flop_per_check(n_spheres, n_obs, n_self):
+    return PAIR_FLOP * (n_spheres * n_obs + n_self) + FK_FLOP
+
+
+def cpu_baseline(name, data, desc, seed, edges_idx):
+    import numpy as np
+    import oracle
+    import workloads
+    orob = oracle.Robot(desc)
+    obs = data["obstacles"].astype(np.float64)
+    checks = 0
+    t0 = time.perf_counter()
+    for e in edges_idx:
+        v1, v2 = data["edges"][e].astype(np.float64)
+        prm = oracle.make_params(**workloads.PARAMS[name], seed=seed, edge_id=int(e))
+        out = oracle.eizo_arm(orob, obs, v1, v2, prm)
+        checks += out["stats"]["checks"]
+    dt = time.perf_counter() - t0
+    return {"value": checks / dt, "unit": "configs/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"FP64 reference EI-ZO on {len(edges_idx)} edge(s) of the '{name}' workload "
+                      f"(seed {seed}): {checks} exact checks in {dt:.2f} s",
+            "edges_per_s": len(edges_idx) / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="dof7", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the EI-ZO path of this library runs on a single MI355X "
+              "(edges shard across GPUs with no exchange; multi-GPU runs are not part of this build)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2504_10783_amd as ezo
+    import workloads
+
+    name = args.workload
+    data = workloads.load(name)
+    desc = workloads.robot(data)
+    ctx = ezo.Context(0)
+    rob = ezo.Robot(ctx, desc)
+    dev = torch.device("cuda", 0)
+    obs = torch.from_numpy(data["obstacles"]).to(dev)
+    edges = torch.from_numpy(data["edges"]).to(dev)
+    E = edges.shape[0]
+    prm = ezo.make_params(dof=desc["dof"], seed=args.seed, **workloads.PARAMS[name])
+    out = ezo.InflateResult(torch.empty((E, prm.face_capacity, rob.dof), dtype=torch.float32, device=dev),
+                            torch.empty((E, prm.face_capacity), dtype=torch.float32, device=dev),
+                            torch.empty(E, dtype=torch.int32, device=dev),
+                            torch.empty(E, dtype=torch.int32, device=dev), [])
+
+    def step():
+        ezo.inflate_edges(ctx, rob, obs, edges, prm, out=out)
+        return out.stats
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_phase_timing(True)
+    checks = samples = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = step()
+        checks += sum(s["exact_checks"] for s in st)
+        samples += sum(s["samples"] for s in st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    phase_ms, iters = ctx.phase_timing()
+    status = out.status.cpu().numpy()
+
+    # dominant kernel phase and its algorithmic work (all pairs of every check)
+    fpc = flop_per_check(rob.n_spheres, obs.shape[0], rob.n_self)
+    work = {"check": samples * fpc, "bisect": (checks - samples) * fpc}
+    dom = max(("check", "bisect"), key=lambda p: phase_ms[p])
+    dom_ms = phase_ms[dom]
+    achieved = work[dom] / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "kernel": "k_project_bisect" if dom == "bisect" else "k_check",
+                "avg_launch_ms": dom_ms / max(iters, 1), "launches": iters}
+
+    line = {
+        "metric": "collision-checked configs/sec and edges inflated/sec (7-DOF), % FP32 VALU peak",
+        "value": checks / dt,
+        "unit": "configs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{name}: {WORKLOADS[name]}", "edges": E, "n_obstacles": int(obs.shape[0]),
+                   "robot_spheres": rob.n_spheres, "self_pairs": rob.n_self},
+        "edges_per_s": E * args.steps / dt,
+        "checks_per_step": checks // args.steps,
+        "iterations_per_step": iters / args.steps,
+        "edge_status": {k: int(np.sum(status == v)) for k, v in
+                        (("certified", 0), ("max_iters", 1), ("in_collision", 2), ("invalid", 3))},
+        "phase_ms_per_step": {k: v / args.steps for k, v in phase_ms.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        idx = [0] if E == 1 else sorted({int(np.nonzero(data["path_id"] == p)[0][0]) for p in np.unique(data["path_id"])})
+        line["cpu_baseline"] = cpu_baseline(name, data, desc, args.seed, idx)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

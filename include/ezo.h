@@ -1,0 +1,270 @@
+/*
+ * ezo.h -- C ABI of the MI355X (gfx950) EI-ZO hot path.
+ *
+ * EI-ZO ("Edge Inflation Zero-Order", Alg. 1 of Werner et al., "Superfast
+ * Configuration-Space Convex Set Computation on GPUs for Online Motion
+ * Planning", arXiv 2504.10783) inflates a collision-free configuration-space
+ * segment L = conv{v1, v2} into a polytope P = {x : A x <= b} with L inside P,
+ * P inside the domain D, such that with probability >= 1 - delta at most an
+ * eps fraction of P's volume is in collision (eq:prob_polytope_cfree).  Its
+ * bulk is batched collision checking: forward kinematics of a serial arm
+ * followed by sphere-sphere tests (Sec. IV-D).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers marked "dev" are device pointers on the context's device (for
+ *   instance torch tensors' data_ptr()); "host" pointers are ordinary host
+ *   memory.  The caller owns every buffer it passes; the library keeps no
+ *   caller pointer after a call returns.
+ * - Work is enqueued on `stream` (a hipStream_t; NULL = the legacy default
+ *   stream).  Results in dev buffers are valid once that stream reaches them;
+ *   results in host buffers (stats) are valid when the call returns.
+ *   ezo_inflate_edges synchronises with `stream` internally (it polls one
+ *   4-byte counter per iteration); the other calls do not block.
+ * - Floating point on the device is FP32.  Robot descriptions are given in
+ *   FP64 and rounded to FP32 once, at ezo_robot_create.
+ * - Errors: every call returns EZO_OK (0) or a negative ezo_status; the text
+ *   of the last error on a context is returned by ezo_last_error.  Errors
+ *   never cross the ABI as exceptions.  Per-edge outcomes of an inflation are
+ *   reported in edge_status, so one colliding edge does not fail a batch.
+ * - Threading: one context per host thread.  Calls on one context must not
+ *   overlap.
+ * - Limits: dof <= EZO_MAX_DOF; spheres <= EZO_MAX_SPHERES.
+ */
+#ifndef EZO_H
+#define EZO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EZO_MAX_DOF 8
+#define EZO_MAX_SPHERES 1024
+
+typedef struct ezo_ctx ezo_ctx;
+typedef struct ezo_robot ezo_robot;
+typedef int32_t ezo_status;
+
+enum {
+    EZO_OK = 0,
+    EZO_E_INVALID = -1,     /* an argument is out of range or inconsistent   */
+    EZO_E_HIP = -2,         /* a HIP runtime call failed                      */
+    EZO_E_CAPACITY = -3,    /* face_capacity < 2 dof + n_f * max_iters        */
+    EZO_E_NOMEM = -4,       /* a device or host allocation failed             */
+    EZO_E_UNSUPPORTED = -5  /* shape beyond EZO_MAX_DOF / EZO_MAX_SPHERES     */
+};
+
+/* Per-edge outcome of an inflation (Alg. 1 and Sec. IV-C). */
+enum {
+    EZO_EDGE_CERTIFIED = 0,    /* the unadaptive test accepted P                      */
+    EZO_EDGE_MAX_ITERS = 1,    /* max_iters rounds without acceptance; P uncertified  */
+    EZO_EDGE_IN_COLLISION = 2, /* a candidate within t_col of L, or a projection onto
+                                  L in collision: L is likely in collision            */
+    EZO_EDGE_INVALID = 3       /* a vertex outside D or not finite; P = D             */
+};
+
+/* Serial arm with standard Denavit-Hartenberg links,
+ *   T_i = T_{i-1} Rz(q_i) Tz(d_i) Tx(a_i) Rx(alpha_i),  T_0 = identity,
+ * and collision spheres rigidly attached to links (Sec. IV-D: sphere
+ * geometries; Sec. II: kinematics and collision geometry are given).
+ * All arrays are host memory and are copied at ezo_robot_create. */
+typedef struct {
+    int32_t dof;                 /* 1..EZO_MAX_DOF                                   */
+    const double *dh_a;          /* [dof] link length a_i                            */
+    const double *dh_alpha;      /* [dof] link twist alpha_i                         */
+    const double *dh_d;          /* [dof] link offset d_i                            */
+    const double *q_lo, *q_hi;   /* [dof] joint limits; D = {q_lo <= q <= q_hi}      */
+    int32_t n_spheres;           /* 0..EZO_MAX_SPHERES                               */
+    const int32_t *sphere_link;  /* [S] link index 0..dof-1 of each sphere           */
+    const double *sphere_xyz;    /* [S][3] centre in the frame of its link           */
+    const double *sphere_r;      /* [S] radius (>= 0)                                */
+    int32_t n_self_pairs;        /* >= 0                                             */
+    const int32_t *self_pairs;   /* [P][2] sphere indices tested against each other  */
+} ezo_robot_desc;
+
+/* EI-ZO parameters: Alg. 1 Input (delta, eps, tau, Delta_max, N_p, N_f, N_b)
+ * plus the sampler's mixing steps N_mix (Sec. IV-D), the iteration cap N_it
+ * and the collision tolerance t_col (Sec. IV-C). */
+typedef struct {
+    double eps;              /* admissible fraction in collision, (0, 1)            */
+    double delta;            /* admissible uncertainty, (0, 1)                      */
+    double tau;              /* test decision threshold, (0, 1); typically 0.5      */
+    double step_back_max;    /* Delta_max > 0                                       */
+    double t_col;            /* candidates with dist <= t_col abort the edge        */
+    int32_t n_p;             /* N_p >= 1: samples updated per iteration             */
+    int32_t n_f;             /* N_f >= 1: faces placed per iteration                */
+    int32_t n_b;             /* N_b >= 0: bisection steps                           */
+    int32_t n_mix;           /* hit-and-run steps per sample, >= 0                  */
+    int32_t max_iters;       /* N_it >= 1                                           */
+    int32_t face_capacity;   /* rows reserved per edge in A/b, >= 2 dof + n_f N_it  */
+    uint64_t seed;           /* Philox key                                          */
+    int64_t edge_id_base;    /* edge e of this call draws the random stream of
+                                edge id (edge_id_base + e)                           */
+} ezo_params;
+
+typedef struct {
+    int32_t iterations;      /* unadaptive tests performed                          */
+    int32_t planes;          /* hyperplanes added to D                              */
+    int64_t final_m;         /* M_k of the last test                                */
+    int64_t test_collisions; /* collisions among the first M_k samples, last test   */
+    int64_t samples;         /* samples drawn (sum of |S| over iterations)          */
+    int64_t exact_checks;    /* configurations collision-checked                    */
+} ezo_edge_stats;
+
+/* ---- context and robot ------------------------------------------------- */
+
+/* Creates a context bound to HIP device `device`.  Allocates a small amount
+ * of device memory and one internal stream (default priority). */
+ezo_status ezo_ctx_create(int32_t device, ezo_ctx **out);
+void ezo_ctx_destroy(ezo_ctx *ctx);
+
+/* Text of the last error on ctx (or of the last failed ezo_ctx_create when
+ * ctx is NULL).  Valid until the next call on that context. */
+const char *ezo_last_error(const ezo_ctx *ctx);
+
+/* Uploads a robot (copied and rounded to FP32).  EZO_E_UNSUPPORTED beyond
+ * the limits; EZO_E_INVALID for out-of-range link or sphere indices. */
+ezo_status ezo_robot_create(ezo_ctx *ctx, const ezo_robot_desc *desc, ezo_robot **out);
+void ezo_robot_destroy(ezo_robot *robot);
+
+/* ---- collision checking (Sec. IV-D: PointsInCollision of Alg. 1) -------- */
+
+/* For each configuration q_i (i < n), element j at q[i*stride_n + j*stride_d]
+ * (dev, FP32), computes the minimum signed distance over
+ *   robot-obstacle pairs  |c_s - o| - r_s - r_o   (obstacles obs[n_obs][4] =
+ *                                                 x, y, z, r; dev, FP32)
+ *   listed self pairs     |c_s - c_t| - r_s - r_t
+ * and flags[i] = 1 iff that minimum is < 0 (dev u8[n]).
+ * If min_sd and min_sd_self are both NULL only flags are computed, and a
+ * configuration stops being tested at its first colliding pair.  Otherwise
+ * min_sd[i] (dev f32[n], may be NULL) receives the overall minimum and
+ * min_sd_self[i] (dev f32[n], may be NULL) the self-pair minimum (+inf when
+ * there are none).  n = 0 is a no-op. */
+ezo_status ezo_check_collisions(ezo_ctx *ctx, const ezo_robot *robot, const float *obs, int32_t n_obs,
+                                const float *q, int64_t n, int64_t stride_n, int64_t stride_d,
+                                uint8_t *flags, float *min_sd, float *min_sd_self, void *stream);
+
+/* Forward kinematics only: world-frame sphere centres, centres[i][s][0..2]
+ * (dev f32 [n][S][3]), for the same q layout as ezo_check_collisions. */
+ezo_status ezo_sphere_centres(ezo_ctx *ctx, const ezo_robot *robot, const float *q, int64_t n,
+                              int64_t stride_n, int64_t stride_d, float *centres, void *stream);
+
+/* ---- statistical test constants (Sec. IV-B) ----------------------------- */
+
+/* Host helper: delta_k = 6 delta / (pi^2 k^2), M_k = ceil(2 ln(1/delta_k) /
+ * (eps tau^2)), T_k = floor(M_k (1 - tau) eps + 1e-9); the test accepts iff
+ * the collisions among the first M_k samples are <= T_k. */
+ezo_status ezo_test_constants(double eps, double delta, double tau, int32_t k, int64_t *M, int64_t *T);
+
+/* ---- the steps of one EI-ZO iteration, on E edges at once --------------- */
+/* Layouts: edges dev f32 [E][2][dof] (v1 then v2); polytopes A dev f32
+ * [E][face_capacity][dof], b dev f32 [E][face_capacity], n_faces dev i32 [E];
+ * samples dev f32 [E][dof][sample_stride] (coordinate-major per edge);
+ * candidate arrays are [E][cand_capacity] (per coordinate: [E][dof][cand_capacity]). */
+
+/* UniformSample(P, .) of Alg. 1: n_samples hit-and-run walks per edge inside
+ * its current polytope (Sec. IV-B/IV-D).  Walk i of edge e starts at
+ * v1 + w (v2 - v1), w ~ U(0,1), then takes n_mix steps: direction
+ * u = g/|g|, g ~ N(0, I) by Box-Muller, chord [t_lo, t_hi] over all rows,
+ * t ~ U[t_lo, t_hi] (t = 0 if rounding empties the chord).  Randomness:
+ * Philox4x32-10, key = (seed low, seed high), counter = (i, edge_id_base + e,
+ * iteration, 16 s + word/4) with s = 0 for the start and 1..n_mix for steps;
+ * words map to (0,1) by ((x >> 9) + 1/2) 2^-23.  sample_stride >= n_samples. */
+ezo_status ezo_sample_polytopes(ezo_ctx *ctx, int32_t dof, const float *A, const float *b,
+                                const int32_t *n_faces, int32_t face_capacity, const float *edges,
+                                int32_t n_edges, int32_t n_samples, int32_t n_mix, uint64_t seed,
+                                int64_t edge_id_base, int32_t iteration, float *samples,
+                                int64_t sample_stride, void *stream);
+
+/* UnadaptiveTest of Alg. 1 plus candidate selection (Sec. IV-B): per edge,
+ * count = collisions among flags[e][0..M-1] (flags dev u8 [E][sample_stride],
+ * n_samples valid); accept[e] = count <= T (dev u8 [E]); test_count[e] =
+ * count (dev i32 [E]).  If not accepted, cand_idx[e][0..] (dev i32
+ * [E][cand_capacity]) receives the indices of the first min(n_p,
+ * #colliding) colliding samples in increasing order and n_cands[e] their
+ * number (dev i32 [E]); if accepted n_cands[e] = 0.  n_p <= cand_capacity. */
+ezo_status ezo_test_and_select(ezo_ctx *ctx, const uint8_t *flags, int32_t n_edges, int64_t sample_stride,
+                               int32_t n_samples, int64_t M, int64_t T, int32_t n_p, int32_t *cand_idx,
+                               int32_t *n_cands, int32_t cand_capacity, uint8_t *accept,
+                               int32_t *test_count, void *stream);
+
+/* ProjectPoints and UpdatePointsViaBisection of Alg. 1 (Sec. IV-A, IV-B):
+ * for candidate j < n_cands[e] with sample c = samples[e][:, cand_idx[e][j]]:
+ * c_proj = projection onto L (eq:proj, eq:proj_alpha), a = (c - c_proj) /
+ * |c - c_proj| (eq:dist_grad), proj_collides[e][j] = collision flag of
+ * c_proj (fail-fast check, Sec. IV-C), then n_b bisection steps on
+ * [c_proj, c] keeping the colliding end; c_star = that end,
+ * t_star = |c_star - c_proj|.  Outputs dev: c_star, a_dir f32
+ * [E][dof][cand_capacity], t_star f32 [E][cand_capacity], proj_collides
+ * u8 [E][cand_capacity]. */
+ezo_status ezo_project_bisect(ezo_ctx *ctx, const ezo_robot *robot, const float *obs, int32_t n_obs,
+                              const float *edges, int32_t n_edges, const float *samples,
+                              int64_t sample_stride, const int32_t *cand_idx, const int32_t *n_cands,
+                              int32_t cand_capacity, int32_t n_b, float *c_star, float *a_dir,
+                              float *t_star, uint8_t *proj_collides, void *stream);
+
+/* OrderAndPlaceHyperplanes of Alg. 1 (Sec. IV-B, step back Sec. IV-C): per
+ * edge whose edge_status is not yet final (< 0 means running; the call only
+ * reads/writes edges with edge_status[e] < 0), order candidates by (t_star,
+ * candidate index); repeatedly take the closest one not yet discarded: if
+ * its t_star <= t_col set edge_status[e] = EZO_EDGE_IN_COLLISION and stop;
+ * else append the row a^T x <= b - Delta with b = a^T c_star,
+ * r = max(a^T v1, a^T v2) - b + step_back_max and Delta = step_back_max - r
+ * if r > 0 else step_back_max; discard every candidate with
+ * a^T c_star > b - Delta.  At most n_f rows.  n_faces[e] is advanced;
+ * placed_idx (dev i32 [E][n_f], may be NULL) receives the candidate index of
+ * each new row; n_placed (dev i32 [E], may be NULL) their number.  If
+ * face_capacity would be exceeded the edge stops adding rows. */
+ezo_status ezo_place_hyperplanes(ezo_ctx *ctx, int32_t dof, const float *edges, int32_t n_edges,
+                                 const float *c_star, const float *a_dir, const float *t_star,
+                                 const int32_t *n_cands, int32_t cand_capacity, int32_t n_f,
+                                 double step_back_max, double t_col, float *A, float *b,
+                                 int32_t *n_faces, int32_t face_capacity, int32_t *edge_status,
+                                 int32_t *placed_idx, int32_t *n_placed, void *stream);
+
+/* ---- the whole method (Alg. 1) on E edges in one call ------------------- */
+
+/* Inflates every edge e (edges dev f32 [E][2][dof]) against the robot and
+ * obstacles: P_e = D (the robot's joint-limit box, rows +e_j <= q_hi then
+ * -e_j <= -q_lo), then for k = 1..max_iters: |S| = max(N_p, M_k) samples,
+ * collision checks, test (accept => CERTIFIED), candidates, projection +
+ * bisection, placement.  All edges advance together; finished edges are
+ * skipped.  Outputs: A dev f32 [E][face_capacity][dof], b dev f32
+ * [E][face_capacity], n_faces dev i32 [E], edge_status dev i32 [E] (EZO_EDGE_*),
+ * stats host [E] (may be NULL).  Returns EZO_E_CAPACITY if face_capacity <
+ * 2 dof + n_f max_iters.  Blocks until the stream has finished the call. */
+ezo_status ezo_inflate_edges(ezo_ctx *ctx, const ezo_robot *robot, const float *obs, int32_t n_obs,
+                             const float *edges, int32_t n_edges, const ezo_params *params, float *A,
+                             float *b, int32_t *n_faces, int32_t *edge_status, ezo_edge_stats *stats,
+                             void *stream);
+
+/* ---- instrumentation ------------------------------------------------- */
+
+/* Kernel phases of one inflation iteration, in launch order. */
+enum {
+    EZO_PHASE_SAMPLE = 0,        /* hit-and-run sampler                       */
+    EZO_PHASE_CHECK = 1,         /* collision checks of the samples           */
+    EZO_PHASE_TEST = 2,          /* unadaptive test + candidate selection     */
+    EZO_PHASE_BISECT = 3,        /* projection, fail-fast check, bisection    */
+    EZO_PHASE_PLACE = 4,         /* ordering and placing hyperplanes          */
+    EZO_PHASE_ADVANCE = 5,       /* iteration bookkeeping                     */
+    EZO_NUM_PHASES = 6
+};
+
+/* Enables (1) or disables (0) per-phase GPU timing of ezo_inflate_edges on
+ * this context: hipEvents are recorded between the phases of every iteration
+ * on the stream the kernels run on, and their elapsed times accumulate.
+ * Enabling resets the totals.  Timing adds a few microseconds per iteration. */
+ezo_status ezo_set_phase_timing(ezo_ctx *ctx, int32_t enable);
+
+/* Cumulative per-phase kernel time (ms_out[EZO_NUM_PHASES], host) and the
+ * number of timed iterations (iterations_out, host) since timing was enabled. */
+ezo_status ezo_get_phase_timing(const ezo_ctx *ctx, double *ms_out, int64_t *iterations_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EZO_H */

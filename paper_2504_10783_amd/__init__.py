@@ -1,0 +1,333 @@
+"""Python binding of the MI355X EI-ZO library (`libezo.so`, C ABI in include/ezo.h).
+
+Argument marshalling only: every step runs in the HIP kernels behind the C
+ABI.  Device buffers are torch tensors on the context's device; work goes to
+torch's current stream unless a stream is given.  The shared library must be
+built (`python -m paper_2504_10783_amd.build`); importing this package does
+not need a GPU, but every compute call does, and a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libezo.so")
+
+EZO_OK, EZO_E_INVALID, EZO_E_HIP, EZO_E_CAPACITY, EZO_E_NOMEM, EZO_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+CERTIFIED, MAX_ITERS, IN_COLLISION, INVALID = 0, 1, 2, 3
+MAX_DOF = 8
+
+EXPORTS = (
+    "ezo_ctx_create", "ezo_ctx_destroy", "ezo_last_error", "ezo_robot_create", "ezo_robot_destroy",
+    "ezo_check_collisions", "ezo_sphere_centres", "ezo_test_constants", "ezo_sample_polytopes",
+    "ezo_test_and_select", "ezo_project_bisect", "ezo_place_hyperplanes", "ezo_inflate_edges",
+    "ezo_set_phase_timing", "ezo_get_phase_timing",
+)
+PHASES = ("sample", "check", "test", "bisect", "place", "advance")
+
+
+class EzoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ezo error {code}: {msg}")
+        self.code = code
+
+
+class RobotDesc(C.Structure):
+    _fields_ = [("dof", C.c_int32), ("dh_a", C.POINTER(C.c_double)), ("dh_alpha", C.POINTER(C.c_double)),
+                ("dh_d", C.POINTER(C.c_double)), ("q_lo", C.POINTER(C.c_double)), ("q_hi", C.POINTER(C.c_double)),
+                ("n_spheres", C.c_int32), ("sphere_link", C.POINTER(C.c_int32)),
+                ("sphere_xyz", C.POINTER(C.c_double)), ("sphere_r", C.POINTER(C.c_double)),
+                ("n_self_pairs", C.c_int32), ("self_pairs", C.POINTER(C.c_int32))]
+
+
+class Params(C.Structure):
+    _fields_ = [("eps", C.c_double), ("delta", C.c_double), ("tau", C.c_double),
+                ("step_back_max", C.c_double), ("t_col", C.c_double), ("n_p", C.c_int32),
+                ("n_f", C.c_int32), ("n_b", C.c_int32), ("n_mix", C.c_int32), ("max_iters", C.c_int32),
+                ("face_capacity", C.c_int32), ("seed", C.c_uint64), ("edge_id_base", C.c_int64)]
+
+
+class EdgeStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("planes", C.c_int32), ("final_m", C.c_int64),
+                ("test_collisions", C.c_int64), ("samples", C.c_int64), ("exact_checks", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2504_10783_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+        L.ezo_ctx_create.argtypes = [i32, C.POINTER(vp)]
+        L.ezo_ctx_destroy.argtypes = [vp]
+        L.ezo_ctx_destroy.restype = None
+        L.ezo_last_error.argtypes = [vp]
+        L.ezo_last_error.restype = C.c_char_p
+        L.ezo_robot_create.argtypes = [vp, C.POINTER(RobotDesc), C.POINTER(vp)]
+        L.ezo_robot_destroy.argtypes = [vp]
+        L.ezo_robot_destroy.restype = None
+        L.ezo_check_collisions.argtypes = [vp, vp, vp, i32, vp, i64, i64, i64, vp, vp, vp, vp]
+        L.ezo_sphere_centres.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp]
+        L.ezo_test_constants.argtypes = [dbl, dbl, dbl, i32, C.POINTER(i64), C.POINTER(i64)]
+        L.ezo_sample_polytopes.argtypes = [vp, i32, vp, vp, vp, i32, vp, i32, i32, i32, u64, i64, i32, vp, i64, vp]
+        L.ezo_test_and_select.argtypes = [vp, vp, i32, i64, i32, i64, i64, i32, vp, vp, i32, vp, vp, vp]
+        L.ezo_project_bisect.argtypes = [vp, vp, vp, i32, vp, i32, vp, i64, vp, vp, i32, i32, vp, vp, vp, vp, vp]
+        L.ezo_place_hyperplanes.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, i32, i32, dbl, dbl, vp, vp, vp, i32,
+                                            vp, vp, vp, vp]
+        L.ezo_inflate_edges.argtypes = [vp, vp, vp, i32, vp, i32, C.POINTER(Params), vp, vp, vp, vp,
+                                        C.POINTER(EdgeStats), vp]
+        L.ezo_set_phase_timing.argtypes = [vp, i32]
+        L.ezo_get_phase_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
+        for name in EXPORTS:
+            fn = getattr(L, name)
+            if fn.restype is C.c_int:
+                fn.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _need(t, dtype, name, numel=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {numel}")
+
+
+def test_constants(eps: float, delta: float, tau: float, k: int):
+    """(M_k, T_k) of the unadaptive test, computed by the library."""
+    M, T = C.c_int64(), C.c_int64()
+    rc = lib().ezo_test_constants(eps, delta, tau, int(k), C.byref(M), C.byref(T))
+    if rc:
+        raise EzoError(rc, "bad test parameters")
+    return M.value, T.value
+
+
+class Context:
+    """An ezo context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        rc = lib().ezo_ctx_create(int(device), C.byref(h))
+        if rc:
+            raise EzoError(rc, lib().ezo_last_error(None).decode())
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().ezo_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_phase_timing(self, enable: bool):
+        """Per-phase GPU timing of inflate_edges (hipEvents on the kernels' stream)."""
+        self._check(lib().ezo_set_phase_timing(self.h, 1 if enable else 0))
+
+    def phase_timing(self):
+        """(dict phase -> cumulative ms, timed iterations) since timing was enabled."""
+        ms = (C.c_double * len(PHASES))()
+        it = C.c_int64()
+        self._check(lib().ezo_get_phase_timing(self.h, ms, C.byref(it)))
+        return {p: ms[i] for i, p in enumerate(PHASES)}, it.value
+
+    def _check(self, rc):
+        if rc:
+            raise EzoError(rc, lib().ezo_last_error(self.h).decode())
+
+
+class Robot:
+    """A robot uploaded to a context (DH arm + spheres + self pairs)."""
+
+    def __init__(self, ctx: Context, desc: dict):
+        self.ctx = ctx
+        f64 = lambda k: np.ascontiguousarray(desc[k], dtype=np.float64)
+        self._keep = dict(a=f64("a"), alpha=f64("alpha"), d=f64("d"), q_lo=f64("q_lo"), q_hi=f64("q_hi"),
+                          link=np.ascontiguousarray(desc["sphere_link"], dtype=np.int32),
+                          xyz=np.ascontiguousarray(desc["sphere_xyz"], dtype=np.float64).reshape(-1, 3),
+                          r=f64("sphere_r"),
+                          pairs=np.ascontiguousarray(desc.get("self_pairs", np.zeros((0, 2))),
+                                                     dtype=np.int32).reshape(-1, 2))
+        k = self._keep
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        self.dof = int(desc["dof"])
+        self.n_spheres = len(k["r"])
+        self.n_self = len(k["pairs"])
+        d = RobotDesc(self.dof, dp(k["a"]), dp(k["alpha"]), dp(k["d"]), dp(k["q_lo"]), dp(k["q_hi"]),
+                      self.n_spheres, ip(k["link"]), dp(k["xyz"]), dp(k["r"]), self.n_self, ip(k["pairs"]))
+        h = C.c_void_p()
+        ctx._check(lib().ezo_robot_create(ctx.h, C.byref(d), C.byref(h)))
+        self.h = h
+        self.q_lo = k["q_lo"]
+        self.q_hi = k["q_hi"]
+
+    def close(self):
+        if self.h:
+            lib().ezo_robot_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def check_collisions(ctx: Context, robot: Robot, obs, q, flags, min_sd=None, min_sd_self=None,
+                     stride_n=None, stride_d=None, n=None, stream=None):
+    """q: float32 CUDA tensor; by default [n][dof] (stride_n = dof,
+    stride_d = 1).  flags: uint8 [n]; min_sd / min_sd_self: float32 [n] or
+    None (both None = flags only, early exit)."""
+    torch = _torch()
+    _need(q, torch.float32, "q")
+    if stride_n is None:
+        if q.dim() != 2 or q.shape[1] != robot.dof:
+            raise ValueError("q must be [n][dof] unless strides are given")
+        n, stride_n, stride_d = q.shape[0], robot.dof, 1
+    else:
+        n_max = (q.numel() - 1 - (robot.dof - 1) * stride_d) // stride_n + 1 if q.numel() else 0
+        if n is None:
+            n = n_max
+        if n > n_max:
+            raise ValueError("q is too small for n configurations with these strides")
+    _need(obs, torch.float32, "obs")
+    n_obs = obs.numel() // 4
+    _need(flags, torch.uint8, "flags", n)
+    if min_sd is not None:
+        _need(min_sd, torch.float32, "min_sd", n)
+    if min_sd_self is not None:
+        _need(min_sd_self, torch.float32, "min_sd_self", n)
+    ctx._check(lib().ezo_check_collisions(ctx.h, robot.h, _ptr(obs), n_obs, _ptr(q), n, stride_n, stride_d,
+                                          _ptr(flags), _ptr(min_sd), _ptr(min_sd_self), _stream(stream)))
+
+
+def sphere_centres(ctx: Context, robot: Robot, q, out, stream=None):
+    """q: float32 [n][dof]; out: float32 [n][S][3]."""
+    torch = _torch()
+    _need(q, torch.float32, "q")
+    n = q.shape[0]
+    _need(out, torch.float32, "out", n * robot.n_spheres * 3)
+    ctx._check(lib().ezo_sphere_centres(ctx.h, robot.h, _ptr(q), n, robot.dof, 1, _ptr(out), _stream(stream)))
+
+
+def sample_polytopes(ctx: Context, dof, A, b, n_faces, edges, n_samples, n_mix, seed, iteration, samples,
+                     edge_id_base=0, stream=None):
+    """A: [E][cap][dof] f32, b: [E][cap] f32, n_faces: [E] i32, edges:
+    [E][2][dof] f32, samples: [E][dof][stride] f32 (stride >= n_samples)."""
+    torch = _torch()
+    E, cap = b.shape
+    for t, dt, nm in ((A, torch.float32, "A"), (b, torch.float32, "b"), (n_faces, torch.int32, "n_faces"),
+                      (edges, torch.float32, "edges"), (samples, torch.float32, "samples")):
+        _need(t, dt, nm)
+    stride = samples.shape[-1]
+    if samples.numel() < E * dof * stride:
+        raise ValueError("samples too small")
+    ctx._check(lib().ezo_sample_polytopes(ctx.h, int(dof), _ptr(A), _ptr(b), _ptr(n_faces), int(cap), _ptr(edges),
+                                          int(E), int(n_samples), int(n_mix), int(seed), int(edge_id_base),
+                                          int(iteration), _ptr(samples), int(stride), _stream(stream)))
+
+
+def test_and_select(ctx: Context, flags, n_samples, M, T, n_p, cand_idx, n_cands, accept=None, test_count=None,
+                    stream=None):
+    """flags: [E][stride] u8; cand_idx: [E][cap] i32; n_cands: [E] i32."""
+    torch = _torch()
+    E, stride = flags.shape
+    _need(flags, torch.uint8, "flags")
+    _need(cand_idx, torch.int32, "cand_idx")
+    _need(n_cands, torch.int32, "n_cands", E)
+    ctx._check(lib().ezo_test_and_select(ctx.h, _ptr(flags), int(E), int(stride), int(n_samples), int(M), int(T),
+                                         int(n_p), _ptr(cand_idx), _ptr(n_cands), int(cand_idx.shape[1]),
+                                         _ptr(accept), _ptr(test_count), _stream(stream)))
+
+
+def project_bisect(ctx: Context, robot: Robot, obs, edges, samples, cand_idx, n_cands, n_b, c_star, a_dir, t_star,
+                   proj_collides, stream=None):
+    """samples [E][dof][stride]; cand_idx [E][cap]; outputs c_star/a_dir
+    [E][dof][cap] f32, t_star [E][cap] f32, proj_collides [E][cap] u8."""
+    E, cap = cand_idx.shape
+    ctx._check(lib().ezo_project_bisect(ctx.h, robot.h, _ptr(obs), obs.numel() // 4, _ptr(edges), int(E),
+                                        _ptr(samples), int(samples.shape[-1]), _ptr(cand_idx), _ptr(n_cands),
+                                        int(cap), int(n_b), _ptr(c_star), _ptr(a_dir), _ptr(t_star),
+                                        _ptr(proj_collides), _stream(stream)))
+
+
+def place_hyperplanes(ctx: Context, dof, edges, c_star, a_dir, t_star, n_cands, n_f, step_back_max, t_col, A, b,
+                      n_faces, edge_status, placed_idx=None, n_placed=None, stream=None):
+    E, cap_c = t_star.shape
+    ctx._check(lib().ezo_place_hyperplanes(ctx.h, int(dof), _ptr(edges), int(E), _ptr(c_star), _ptr(a_dir),
+                                           _ptr(t_star), _ptr(n_cands), int(cap_c), int(n_f), float(step_back_max),
+                                           float(t_col), _ptr(A), _ptr(b), _ptr(n_faces), int(b.shape[1]),
+                                           _ptr(edge_status), _ptr(placed_idx), _ptr(n_placed), _stream(stream)))
+
+
+@dataclass
+class InflateResult:
+    A: object           # [E][cap][dof] float32 (device)
+    b: object           # [E][cap] float32 (device)
+    n_faces: object     # [E] int32 (device)
+    status: object      # [E] int32 (device)
+    stats: list         # per-edge dicts
+
+
+def make_params(eps, delta, tau=0.5, step_back_max=0.01, t_col=1e-4, n_p=1000, n_f=10, n_b=11, n_mix=30,
+                max_iters=50, face_capacity=None, seed=0, edge_id_base=0, dof=None) -> Params:
+    if face_capacity is None:
+        face_capacity = 2 * (dof or MAX_DOF) + n_f * max_iters
+    return Params(eps, delta, tau, step_back_max, t_col, n_p, n_f, n_b, n_mix, max_iters, face_capacity, seed,
+                  edge_id_base)
+
+
+def inflate_edges(ctx: Context, robot: Robot, obs, edges, params: Params, out=None, stream=None) -> InflateResult:
+    """edges: float32 CUDA tensor [E][2][dof].  Returns device tensors A, b,
+    n_faces, status and host per-edge stats."""
+    torch = _torch()
+    _need(edges, torch.float32, "edges")
+    _need(obs, torch.float32, "obs")
+    E = edges.shape[0]
+    cap = params.face_capacity
+    dev = edges.device
+    if out is None:
+        out = InflateResult(torch.empty((E, cap, robot.dof), dtype=torch.float32, device=dev),
+                            torch.empty((E, cap), dtype=torch.float32, device=dev),
+                            torch.empty(E, dtype=torch.int32, device=dev),
+                            torch.empty(E, dtype=torch.int32, device=dev), [])
+    st = (EdgeStats * max(E, 1))()
+    ctx._check(lib().ezo_inflate_edges(ctx.h, robot.h, _ptr(obs), obs.numel() // 4, _ptr(edges), int(E),
+                                       C.byref(params), _ptr(out.A), _ptr(out.b), _ptr(out.n_faces),
+                                       _ptr(out.status), st, _stream(stream)))
+    out.stats = [{k: getattr(st[e], k) for k, _ in EdgeStats._fields_} for e in range(E)]
+    return out

@@ -1,0 +1,688 @@
+// ezo_api.hip -- host runtime and C ABI of the EI-ZO hot path (declared in
+// include/ezo.h).  Contexts own a growable device workspace and one internal
+// stream; robots are uploaded once and rounded to FP32; the fused inflation
+// captures one iteration of kernels into a hipGraph and replays it, polling a
+// 4-byte active-edge counter after each replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ezo.h"
+#include "ezo_kernels.hpp"
+
+using namespace ezo;
+
+namespace {
+
+constexpr int kNumCU = 256;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct ezo_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;      // internal stream (default priority)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    size_t lds_cap = 65536;
+    std::string err;
+    std::vector<DevBuf> ws;            // named workspace slots
+    int* pinned = nullptr;             // host-pinned poll word
+    bool timing = false;               // per-phase timing of the fused loop
+    hipEvent_t tev[EZO_NUM_PHASES + 1] = {};
+    double phase_ms[EZO_NUM_PHASES] = {};
+    int64_t timed_iters = 0;
+};
+
+struct ezo_robot {
+    ezo_ctx* ctx = nullptr;
+    int dof = 0, S = 0, P = 0;
+    void* buf = nullptr;               // one device allocation holding everything below
+    RobotView view{};
+    const int* sorted_to_orig = nullptr;
+    const float* q_lo = nullptr;
+    const float* q_hi = nullptr;
+};
+
+static std::string g_create_err;
+
+namespace {
+
+enum Slot {
+    W_OBS_REC, W_OBS_CENTRE, W_SAMPLES, W_FLAGS, W_CAND, W_NCAND, W_CSTAR, W_ADIR, W_TSTAR, W_PCOL,
+    W_PANY, W_STATS, W_TABLE, W_KDEV, W_ACTIVE, W_NSLOTS
+};
+
+ezo_status fail(ezo_ctx* c, ezo_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    else g_create_err = buf;
+    return code;
+}
+
+#define HIP_TRY(ctx, call)                                                                      \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) return fail(ctx, EZO_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+ezo_status ws_get(ezo_ctx* c, int slot, size_t bytes, void** out) {
+    DevBuf& b = c->ws[slot];
+    if (bytes == 0) bytes = 16;
+    if (b.bytes < bytes) {
+        if (b.p) {
+            hipError_t e = hipFree(b.p);
+            (void)e;
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+        size_t nb = bytes + bytes / 4 + 256;
+        if (hipMalloc(&b.p, nb) != hipSuccess) {
+            b.p = nullptr;
+            return fail(c, EZO_E_NOMEM, "device allocation of %zu bytes failed", nb);
+        }
+        b.bytes = nb;
+    }
+    *out = b.p;
+    return EZO_OK;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Tile size for a tile check: largest T whose LDS fits and that still gives
+// at least ~4 workgroups per CU; W waves split the obstacles.
+int pick_T(const ezo_ctx* c, int64_t items, int S, int W) {
+    const int cand[4] = {64, 32, 16, 8};
+    int fit = 0;
+    for (int T : cand) {
+        if (tile_smem_bytes(T, S, W) > c->lds_cap) continue;
+        if (!fit) fit = T;
+        if (items / T >= 4 * kNumCU) return T;
+    }
+    if (!fit) {
+        for (int T : {4, 2, 1})
+            if (tile_smem_bytes(T, S, W) <= c->lds_cap) return T;
+        return 0;
+    }
+    // few items: smallest fitting tile gives the most workgroups
+    int best = fit;
+    for (int T : cand)
+        if (tile_smem_bytes(T, S, W) <= c->lds_cap) best = T;
+    return best;
+}
+
+int pick_W(int n_obs) {
+    if (n_obs >= 1024) return 8;
+    if (n_obs >= 128) return 8;
+    if (n_obs >= 16) return 4;
+    return 2;
+}
+
+ObsView obs_view(const ezo_robot* r, ezo_ctx* c, int n_obs, void* rec, void* centre) {
+    ObsView o;
+    o.n = n_obs;
+    o.rec = reinterpret_cast<const float4*>(rec);
+    o.centre = reinterpret_cast<const float4*>(centre);
+    (void)r;
+    (void)c;
+    return o;
+}
+
+ezo_status prep_obstacles(ezo_ctx* c, const float* obs, int n_obs, hipStream_t st, void** rec, void** centre) {
+    ezo_status s;
+    if ((s = ws_get(c, W_OBS_REC, sizeof(float4) * 2 * (size_t)std::max(n_obs, 1), rec)) != EZO_OK) return s;
+    if ((s = ws_get(c, W_OBS_CENTRE, sizeof(float4), centre)) != EZO_OK) return s;
+    hipLaunchKernelGGL(k_prep_obstacles, dim3(1), dim3(256), 0, st, obs, n_obs, (float4*)*rec, (float4*)*centre);
+    HIP_TRY(c, hipGetLastError());
+    return EZO_OK;
+}
+
+template <bool SD>
+ezo_status launch_check(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const float* q, int64_t n,
+                        int64_t sn, int64_t sd, int64_t q_batch, uint8_t* flags, float* min_sd,
+                        float* min_sd_self, int64_t out_batch, int n_batch, const int* status,
+                        const IterArgs& it, hipStream_t st) {
+    const int W = pick_W(ov.n);
+    const int T = pick_T(c, n * n_batch, r->S, W);
+    if (T == 0) return fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
+    const size_t lds = tile_smem_bytes(T, r->S, W);
+    const int64_t tiles = (n + T - 1) / T;
+    if (tiles <= 0) return EZO_OK;
+    dim3 grid((unsigned)tiles, (unsigned)n_batch), block(64 * W);
+#define EZO_LAUNCH_CHECK(TT)                                                                          \
+    hipLaunchKernelGGL((k_check<TT, SD>), grid, block, lds, st, r->view, ov, q, n, sn, sd, q_batch, flags, \
+                       min_sd, min_sd_self, out_batch, status, it)
+    switch (T) {
+        case 64: EZO_LAUNCH_CHECK(64); break;
+        case 32: EZO_LAUNCH_CHECK(32); break;
+        case 16: EZO_LAUNCH_CHECK(16); break;
+        case 8: EZO_LAUNCH_CHECK(8); break;
+        case 4: EZO_LAUNCH_CHECK(4); break;
+        case 2: EZO_LAUNCH_CHECK(2); break;
+        default: EZO_LAUNCH_CHECK(1); break;
+    }
+#undef EZO_LAUNCH_CHECK
+    HIP_TRY(c, hipGetLastError());
+    return EZO_OK;
+}
+
+ezo_status launch_sample(ezo_ctx* c, int dof, const float* A, const float* b, const int* n_faces, int cap,
+                         const float* edges, int E, int max_samples, int n_mix, uint64_t seed, int64_t eid0,
+                         float* S, int64_t stride, const int* status, const IterArgs& it, hipStream_t st) {
+    const int D = dof <= 4 ? 4 : 8;
+    const size_t lds = sizeof(float) * (size_t)cap * (D + 1);
+    if (lds > c->lds_cap) return fail(c, EZO_E_UNSUPPORTED, "face capacity %d too large for the sampler", cap);
+    dim3 grid((unsigned)((max_samples + 255) / 256), (unsigned)E), block(256);
+    if (max_samples <= 0 || E <= 0) return EZO_OK;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    if (D == 4)
+        hipLaunchKernelGGL(k_sample<4>, grid, block, lds, st, dof, A, b, n_faces, cap, edges, k0, k1, eid0, n_mix, S,
+                           stride, status, it);
+    else
+        hipLaunchKernelGGL(k_sample<8>, grid, block, lds, st, dof, A, b, n_faces, cap, edges, k0, k1, eid0, n_mix, S,
+                           stride, status, it);
+    HIP_TRY(c, hipGetLastError());
+    return EZO_OK;
+}
+
+ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const float* edges, int E,
+                                 const float* S, int64_t stride, const int* cand_idx, const int* n_cands,
+                                 int cand_cap, int n_b, float* c_star, float* a_dir, float* t_star,
+                                 uint8_t* pcol, uint8_t* pany, const int* status, hipStream_t st) {
+    const int W = pick_W(ov.n);
+    const int T = std::min(pick_T(c, (int64_t)cand_cap * E, r->S, W), 64);
+    if (T == 0) return fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
+    const size_t lds = tile_smem_bytes(T, r->S, W);
+    dim3 grid((unsigned)((cand_cap + T - 1) / T), (unsigned)E), block(64 * W);
+#define EZO_LAUNCH_PB(TT)                                                                                    \
+    hipLaunchKernelGGL(k_project_bisect<TT>, grid, block, lds, st, r->view, ov, edges, S, stride, cand_idx, \
+                       n_cands, cand_cap, n_b, c_star, a_dir, t_star, pcol, pany, status)
+    switch (T) {
+        case 64: EZO_LAUNCH_PB(64); break;
+        case 32: EZO_LAUNCH_PB(32); break;
+        case 16: EZO_LAUNCH_PB(16); break;
+        case 8: EZO_LAUNCH_PB(8); break;
+        case 4: EZO_LAUNCH_PB(4); break;
+        case 2: EZO_LAUNCH_PB(2); break;
+        default: EZO_LAUNCH_PB(1); break;
+    }
+#undef EZO_LAUNCH_PB
+    HIP_TRY(c, hipGetLastError());
+    return EZO_OK;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+ezo_status ezo_ctx_create(int32_t device, ezo_ctx** out) {
+    if (!out) return fail(nullptr, EZO_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(nullptr, EZO_E_HIP, "no HIP device");
+    if (device < 0 || device >= n) return fail(nullptr, EZO_E_INVALID, "device %d out of range", device);
+    if (hipSetDevice(device) != hipSuccess) return fail(nullptr, EZO_E_HIP, "hipSetDevice failed");
+    ezo_ctx* c = new ezo_ctx();
+    c->device = device;
+    c->ws.resize(W_NSLOTS);
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        c->lds_cap = std::min<size_t>((size_t)lds, 65536);
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void**)&c->pinned, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
+        ezo_ctx_destroy(c);
+        return fail(nullptr, EZO_E_HIP, "stream/event/pinned allocation failed");
+    }
+    *out = c;
+    return EZO_OK;
+}
+
+void ezo_ctx_destroy(ezo_ctx* c) {
+    if (!c) return;
+    hipError_t e;
+    e = hipSetDevice(c->device);
+    if (c->stream) e = hipStreamSynchronize(c->stream);
+    for (auto& b : c->ws)
+        if (b.p) e = hipFree(b.p);
+    if (c->pinned) e = hipHostFree(c->pinned);
+    if (c->ev_in) e = hipEventDestroy(c->ev_in);
+    if (c->ev_out) e = hipEventDestroy(c->ev_out);
+    for (auto& ev : c->tev)
+        if (ev) e = hipEventDestroy(ev);
+    if (c->stream) e = hipStreamDestroy(c->stream);
+    (void)e;
+    delete c;
+}
+
+const char* ezo_last_error(const ezo_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out) {
+    if (!c || !d || !out) return fail(c, EZO_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (d->dof < 1 || d->dof > EZO_MAX_DOF) return fail(c, EZO_E_UNSUPPORTED, "dof %d not in [1, %d]", d->dof, EZO_MAX_DOF);
+    if (d->n_spheres < 0 || d->n_spheres > EZO_MAX_SPHERES)
+        return fail(c, EZO_E_UNSUPPORTED, "n_spheres %d not in [0, %d]", d->n_spheres, EZO_MAX_SPHERES);
+    if (d->n_self_pairs < 0) return fail(c, EZO_E_INVALID, "n_self_pairs < 0");
+    if (!d->dh_a || !d->dh_alpha || !d->dh_d || !d->q_lo || !d->q_hi)
+        return fail(c, EZO_E_INVALID, "NULL DH or limit array");
+    if (d->n_spheres > 0 && (!d->sphere_link || !d->sphere_xyz || !d->sphere_r))
+        return fail(c, EZO_E_INVALID, "NULL sphere array");
+    if (d->n_self_pairs > 0 && !d->self_pairs) return fail(c, EZO_E_INVALID, "NULL self_pairs");
+    const int dof = d->dof, S = d->n_spheres, P = d->n_self_pairs;
+    for (int j = 0; j < dof; ++j)
+        if (!(d->q_lo[j] <= d->q_hi[j])) return fail(c, EZO_E_INVALID, "q_lo[%d] > q_hi[%d]", j, j);
+    for (int s = 0; s < S; ++s) {
+        if (d->sphere_link[s] < 0 || d->sphere_link[s] >= dof)
+            return fail(c, EZO_E_INVALID, "sphere %d has link %d", s, d->sphere_link[s]);
+        if (!(d->sphere_r[s] >= 0.0)) return fail(c, EZO_E_INVALID, "sphere %d has a negative radius", s);
+    }
+    for (int p = 0; p < 2 * P; ++p)
+        if (d->self_pairs[p] < 0 || d->self_pairs[p] >= S)
+            return fail(c, EZO_E_INVALID, "self pair entry %d = %d out of range", p, d->self_pairs[p]);
+    // sort spheres by link (stable), remember the original order
+    std::vector<int> order(S);
+    for (int s = 0; s < S; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return d->sphere_link[a] < d->sphere_link[b]; });
+    std::vector<int> orig_to_sorted(S);
+    for (int s = 0; s < S; ++s) orig_to_sorted[order[s]] = s;
+    std::vector<float4> dh(dof), sph(std::max(S, 1));
+    std::vector<int> link_begin(dof + 1, 0), s2o(std::max(S, 1));
+    std::vector<int2> pairs(std::max(P, 1));
+    std::vector<float> lim(2 * dof);
+    for (int j = 0; j < dof; ++j) {
+        dh[j] = make_float4((float)d->dh_a[j], (float)d->dh_d[j], (float)std::cos((double)(float)d->dh_alpha[j]),
+                            (float)std::sin((double)(float)d->dh_alpha[j]));
+        lim[j] = (float)d->q_lo[j];
+        lim[dof + j] = (float)d->q_hi[j];
+    }
+    for (int s = 0; s < S; ++s) {
+        const int o = order[s];
+        sph[s] = make_float4((float)d->sphere_xyz[3 * o], (float)d->sphere_xyz[3 * o + 1], (float)d->sphere_xyz[3 * o + 2],
+                             (float)d->sphere_r[o]);
+        s2o[s] = o;
+        link_begin[d->sphere_link[o] + 1]++;
+    }
+    for (int j = 0; j < dof; ++j) link_begin[j + 1] += link_begin[j];
+    for (int p = 0; p < P; ++p)
+        pairs[p] = make_int2(orig_to_sorted[d->self_pairs[2 * p]], orig_to_sorted[d->self_pairs[2 * p + 1]]);
+    // one allocation: [dh][sph][pairs][link_begin][s2o][limits]
+    size_t off_dh = 0;
+    size_t off_sph = off_dh + sizeof(float4) * dof;
+    size_t off_pairs = off_sph + sizeof(float4) * sph.size();
+    size_t off_lb = off_pairs + sizeof(int2) * pairs.size();
+    size_t off_s2o = off_lb + sizeof(int) * link_begin.size();
+    size_t off_lim = off_s2o + sizeof(int) * s2o.size();
+    size_t total = off_lim + sizeof(float) * lim.size();
+    std::vector<char> host(total);
+    memcpy(host.data() + off_dh, dh.data(), sizeof(float4) * dof);
+    memcpy(host.data() + off_sph, sph.data(), sizeof(float4) * sph.size());
+    memcpy(host.data() + off_pairs, pairs.data(), sizeof(int2) * pairs.size());
+    memcpy(host.data() + off_lb, link_begin.data(), sizeof(int) * link_begin.size());
+    memcpy(host.data() + off_s2o, s2o.data(), sizeof(int) * s2o.size());
+    memcpy(host.data() + off_lim, lim.data(), sizeof(float) * lim.size());
+    HIP_TRY(c, hipSetDevice(c->device));
+    void* buf = nullptr;
+    if (hipMalloc(&buf, total) != hipSuccess) return fail(c, EZO_E_NOMEM, "robot allocation failed");
+    if (hipMemcpy(buf, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+        hipError_t e = hipFree(buf);
+        (void)e;
+        return fail(c, EZO_E_HIP, "robot upload failed");
+    }
+    ezo_robot* r = new ezo_robot();
+    r->ctx = c;
+    r->dof = dof;
+    r->S = S;
+    r->P = P;
+    r->buf = buf;
+    char* b = reinterpret_cast<char*>(buf);
+    r->view.dof = dof;
+    r->view.n_spheres = S;
+    r->view.n_self = P;
+    r->view.dh = reinterpret_cast<const float4*>(b + off_dh);
+    r->view.sph = reinterpret_cast<const float4*>(b + off_sph);
+    r->view.pairs = reinterpret_cast<const int2*>(b + off_pairs);
+    r->view.link_begin = reinterpret_cast<const int*>(b + off_lb);
+    r->sorted_to_orig = reinterpret_cast<const int*>(b + off_s2o);
+    r->q_lo = reinterpret_cast<const float*>(b + off_lim);
+    r->q_hi = r->q_lo + dof;
+    *out = r;
+    return EZO_OK;
+}
+
+void ezo_robot_destroy(ezo_robot* r) {
+    if (!r) return;
+    hipError_t e = hipSetDevice(r->ctx->device);
+    if (r->buf) e = hipFree(r->buf);
+    (void)e;
+    delete r;
+}
+
+ezo_status ezo_test_constants(double eps, double delta, double tau, int32_t k, int64_t* M, int64_t* T) {
+    if (!M || !T || !(eps > 0 && eps < 1) || !(delta > 0 && delta < 1) || !(tau > 0 && tau < 1) || k < 1)
+        return EZO_E_INVALID;
+    const double pi = 3.14159265358979323846;
+    const double dk = 6.0 * delta / (pi * pi * (double)k * (double)k);
+    const double m = std::ceil(2.0 * std::log(1.0 / dk) / (eps * tau * tau));
+    *M = (int64_t)m;
+    *T = (int64_t)std::floor(m * (1.0 - tau) * eps + 1e-9);
+    return EZO_OK;
+}
+
+ezo_status ezo_check_collisions(ezo_ctx* c, const ezo_robot* r, const float* obs, int32_t n_obs, const float* q,
+                                int64_t n, int64_t stride_n, int64_t stride_d, uint8_t* flags, float* min_sd,
+                                float* min_sd_self, void* stream) {
+    if (!c) return EZO_E_INVALID;
+    if (!r) return fail(c, EZO_E_INVALID, "robot is NULL");
+    if (n < 0 || n_obs < 0) return fail(c, EZO_E_INVALID, "negative size");
+    if (n == 0) return EZO_OK;
+    if (!q || !flags || (n_obs > 0 && !obs)) return fail(c, EZO_E_INVALID, "NULL buffer");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = as_stream(stream);
+    void *rec, *cen;
+    ezo_status s = prep_obstacles(c, obs, n_obs, st, &rec, &cen);
+    if (s) return s;
+    ObsView ov = obs_view(r, c, n_obs, rec, cen);
+    IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
+    if (min_sd || min_sd_self)
+        return launch_check<true>(c, r, ov, q, n, stride_n, stride_d, 0, flags, min_sd, min_sd_self, 0, 1, nullptr,
+                                  it, st);
+    return launch_check<false>(c, r, ov, q, n, stride_n, stride_d, 0, flags, nullptr, nullptr, 0, 1, nullptr, it, st);
+}
+
+ezo_status ezo_sphere_centres(ezo_ctx* c, const ezo_robot* r, const float* q, int64_t n, int64_t stride_n,
+                              int64_t stride_d, float* centres, void* stream) {
+    if (!c) return EZO_E_INVALID;
+    if (!r || n < 0) return fail(c, EZO_E_INVALID, "bad argument");
+    if (n == 0 || r->S == 0) return EZO_OK;
+    if (!q || !centres) return fail(c, EZO_E_INVALID, "NULL buffer");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = as_stream(stream);
+    void *rec, *cen;
+    ezo_status s = prep_obstacles(c, nullptr, 0, st, &rec, &cen);   // zero shift
+    if (s) return s;
+    ObsView ov = obs_view(r, c, 0, rec, cen);
+    int T = 16;
+    while (T > 1 && tile_smem_bytes(T, r->S, 4) > c->lds_cap) T >>= 1;
+    const size_t lds = tile_smem_bytes(T, r->S, 4);
+    dim3 grid((unsigned)((n + T - 1) / T)), block(256);
+    switch (T) {
+        case 16: hipLaunchKernelGGL(k_centres<16>, grid, block, lds, st, r->view, ov, r->sorted_to_orig, q, n, stride_n, stride_d, centres); break;
+        case 8: hipLaunchKernelGGL(k_centres<8>, grid, block, lds, st, r->view, ov, r->sorted_to_orig, q, n, stride_n, stride_d, centres); break;
+        case 4: hipLaunchKernelGGL(k_centres<4>, grid, block, lds, st, r->view, ov, r->sorted_to_orig, q, n, stride_n, stride_d, centres); break;
+        case 2: hipLaunchKernelGGL(k_centres<2>, grid, block, lds, st, r->view, ov, r->sorted_to_orig, q, n, stride_n, stride_d, centres); break;
+        default: hipLaunchKernelGGL(k_centres<1>, grid, block, lds, st, r->view, ov, r->sorted_to_orig, q, n, stride_n, stride_d, centres); break;
+    }
+    HIP_TRY(c, hipGetLastError());
+    return EZO_OK;
+}
+
+ezo_status ezo_sample_polytopes(ezo_ctx* c, int32_t dof, const float* A, const float* b, const int32_t* n_faces,
+                                int32_t face_capacity, const float* edges, int32_t n_edges, int32_t n_samples,
+                                int32_t n_mix, uint64_t seed, int64_t edge_id_base, int32_t iteration,
+                                float* samples, int64_t sample_stride, void* stream) {
+    if (!c) return EZO_E_INVALID;
+    if (dof < 1 || dof > EZO_MAX_DOF || n_edges < 0 || n_samples < 0 || n_mix < 0 || iteration < 0 ||
+        face_capacity < 1 || sample_stride < n_samples)
+        return fail(c, EZO_E_INVALID, "bad sizes");
+    if (n_edges == 0 || n_samples == 0) return EZO_OK;
+    if (!A || !b || !n_faces || !edges || !samples) return fail(c, EZO_E_INVALID, "NULL buffer");
+    HIP_TRY(c, hipSetDevice(c->device));
+    IterArgs it{nullptr, nullptr, iteration, 0, 0, n_samples};
+    return launch_sample(c, dof, A, b, n_faces, face_capacity, edges, n_edges, n_samples, n_mix, seed, edge_id_base,
+                         samples, sample_stride, nullptr, it, as_stream(stream));
+}
+
+ezo_status ezo_test_and_select(ezo_ctx* c, const uint8_t* flags, int32_t n_edges, int64_t sample_stride,
+                               int32_t n_samples, int64_t M, int64_t T, int32_t n_p, int32_t* cand_idx,
+                               int32_t* n_cands, int32_t cand_capacity, uint8_t* accept, int32_t* test_count,
+                               void* stream) {
+    if (!c) return EZO_E_INVALID;
+    if (n_edges < 0 || n_samples < 0 || M < 0 || M > n_samples || n_p < 1 || n_p > cand_capacity ||
+        sample_stride < n_samples || M > 0x7fffffff)
+        return fail(c, EZO_E_INVALID, "bad sizes");
+    if (n_edges == 0) return EZO_OK;
+    if (!flags || !cand_idx || !n_cands) return fail(c, EZO_E_INVALID, "NULL buffer");
+    HIP_TRY(c, hipSetDevice(c->device));
+    IterArgs it{nullptr, nullptr, 0, (int)M, (int)std::min<int64_t>(T, 0x7fffffff), n_samples};
+    hipLaunchKernelGGL(k_test_select, dim3(n_edges), dim3(1024), 0, as_stream(stream), flags, sample_stride, n_p, 0,
+                       cand_idx, cand_capacity, n_cands, accept, test_count, nullptr, nullptr, it);
+    HIP_TRY(c, hipGetLastError());
+    return EZO_OK;
+}
+
+ezo_status ezo_project_bisect(ezo_ctx* c, const ezo_robot* r, const float* obs, int32_t n_obs, const float* edges,
+                              int32_t n_edges, const float* samples, int64_t sample_stride, const int32_t* cand_idx,
+                              const int32_t* n_cands, int32_t cand_capacity, int32_t n_b, float* c_star,
+                              float* a_dir, float* t_star, uint8_t* proj_collides, void* stream) {
+    if (!c) return EZO_E_INVALID;
+    if (!r || n_edges < 0 || n_obs < 0 || cand_capacity < 0 || n_b < 0) return fail(c, EZO_E_INVALID, "bad argument");
+    if (n_edges == 0 || cand_capacity == 0) return EZO_OK;
+    if (!edges || !samples || !cand_idx || !n_cands || !c_star || !a_dir || !t_star || !proj_collides ||
+        (n_obs > 0 && !obs))
+        return fail(c, EZO_E_INVALID, "NULL buffer");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = as_stream(stream);
+    void *rec, *cen;
+    ezo_status s = prep_obstacles(c, obs, n_obs, st, &rec, &cen);
+    if (s) return s;
+    ObsView ov = obs_view(r, c, n_obs, rec, cen);
+    return launch_project_bisect(c, r, ov, edges, n_edges, samples, sample_stride, cand_idx, n_cands, cand_capacity,
+                                 n_b, c_star, a_dir, t_star, proj_collides, nullptr, nullptr, st);
+}
+
+ezo_status ezo_place_hyperplanes(ezo_ctx* c, int32_t dof, const float* edges, int32_t n_edges, const float* c_star,
+                                 const float* a_dir, const float* t_star, const int32_t* n_cands,
+                                 int32_t cand_capacity, int32_t n_f, double step_back_max, double t_col, float* A,
+                                 float* b, int32_t* n_faces, int32_t face_capacity, int32_t* edge_status,
+                                 int32_t* placed_idx, int32_t* n_placed, void* stream) {
+    if (!c) return EZO_E_INVALID;
+    if (dof < 1 || dof > EZO_MAX_DOF || n_edges < 0 || cand_capacity < 0 || n_f < 0 || face_capacity < 1 ||
+        !finite_pos(step_back_max) || !std::isfinite(t_col))
+        return fail(c, EZO_E_INVALID, "bad argument");
+    if (n_edges == 0) return EZO_OK;
+    if (!edges || !c_star || !a_dir || !t_star || !n_cands || !A || !b || !n_faces || !edge_status)
+        return fail(c, EZO_E_INVALID, "NULL buffer");
+    if ((size_t)cand_capacity > c->lds_cap - 1024) return fail(c, EZO_E_UNSUPPORTED, "cand_capacity too large");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_place, dim3(n_edges), dim3(1024), (size_t)std::max(cand_capacity, 16), as_stream(stream), dof,
+                       edges, c_star, a_dir, t_star, n_cands, cand_capacity, n_f, (float)step_back_max, (float)t_col, A,
+                       b, n_faces, face_capacity, edge_status, placed_idx, n_placed, nullptr, nullptr);
+    HIP_TRY(c, hipGetLastError());
+    return EZO_OK;
+}
+
+ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, int32_t n_obs, const float* edges,
+                             int32_t n_edges, const ezo_params* p, float* A, float* b, int32_t* n_faces,
+                             int32_t* edge_status, ezo_edge_stats* stats, void* stream) {
+    if (!c) return EZO_E_INVALID;
+    if (!r || !p) return fail(c, EZO_E_INVALID, "NULL robot or params");
+    if (n_edges < 0 || n_obs < 0) return fail(c, EZO_E_INVALID, "negative size");
+    if (!(p->eps > 0 && p->eps < 1) || !(p->delta > 0 && p->delta < 1) || !(p->tau > 0 && p->tau < 1) ||
+        !finite_pos(p->step_back_max) || !std::isfinite(p->t_col) || p->n_p < 1 || p->n_f < 1 || p->n_b < 0 ||
+        p->n_mix < 0 || p->max_iters < 1)
+        return fail(c, EZO_E_INVALID, "parameter out of range");
+    const int dof = r->dof;
+    if ((int64_t)p->face_capacity < 2LL * dof + (int64_t)p->n_f * p->max_iters)
+        return fail(c, EZO_E_CAPACITY, "face_capacity %d < 2 dof + n_f max_iters = %lld", p->face_capacity,
+                    (long long)(2LL * dof + (int64_t)p->n_f * p->max_iters));
+    if (n_edges == 0) return EZO_OK;
+    if (!edges || !A || !b || !n_faces || !edge_status || (n_obs > 0 && !obs))
+        return fail(c, EZO_E_INVALID, "NULL buffer");
+    const int cap = p->face_capacity;
+    if (sizeof(float) * (size_t)cap * ((dof <= 4 ? 4 : 8) + 1) > c->lds_cap)
+        return fail(c, EZO_E_UNSUPPORTED, "face_capacity %d too large", cap);
+    if ((size_t)p->n_p > c->lds_cap - 1024) return fail(c, EZO_E_UNSUPPORTED, "n_p %d too large", p->n_p);
+    // per-iteration constants, FP64 on the host
+    std::vector<int4> table(p->max_iters + 2, make_int4(0, 0, 0, 0));
+    int S_cap = 0;
+    for (int k = 1; k <= p->max_iters; ++k) {
+        int64_t M, T;
+        ezo_test_constants(p->eps, p->delta, p->tau, k, &M, &T);
+        if (M > (1 << 28)) return fail(c, EZO_E_UNSUPPORTED, "M_%d = %lld samples is too many", k, (long long)M);
+        const int nS = (int)std::max<int64_t>(p->n_p, M);
+        table[k] = make_int4((int)M, (int)std::min<int64_t>(T, 1 << 30), nS, 0);
+        S_cap = std::max(S_cap, nS);
+    }
+    table[p->max_iters + 1] = table[p->max_iters];
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int E = n_edges;
+    const int64_t stride = ((int64_t)S_cap + 63) / 64 * 64;
+    const int cand_cap = p->n_p;
+    void *w_s, *w_f, *w_ci, *w_nc, *w_cs, *w_ad, *w_ts, *w_pc, *w_pa, *w_st, *w_tb, *w_k, *w_ac;
+    ezo_status s;
+    if ((s = ws_get(c, W_SAMPLES, sizeof(float) * (size_t)E * dof * stride, &w_s)) ||
+        (s = ws_get(c, W_FLAGS, (size_t)E * stride, &w_f)) ||
+        (s = ws_get(c, W_CAND, sizeof(int) * (size_t)E * cand_cap, &w_ci)) ||
+        (s = ws_get(c, W_NCAND, sizeof(int) * (size_t)E, &w_nc)) ||
+        (s = ws_get(c, W_CSTAR, sizeof(float) * (size_t)E * dof * cand_cap, &w_cs)) ||
+        (s = ws_get(c, W_ADIR, sizeof(float) * (size_t)E * dof * cand_cap, &w_ad)) ||
+        (s = ws_get(c, W_TSTAR, sizeof(float) * (size_t)E * cand_cap, &w_ts)) ||
+        (s = ws_get(c, W_PCOL, (size_t)E * cand_cap, &w_pc)) || (s = ws_get(c, W_PANY, (size_t)E, &w_pa)) ||
+        (s = ws_get(c, W_STATS, sizeof(EdgeStatsDev) * (size_t)E, &w_st)) ||
+        (s = ws_get(c, W_TABLE, sizeof(int4) * table.size(), &w_tb)) || (s = ws_get(c, W_KDEV, sizeof(int), &w_k)) ||
+        (s = ws_get(c, W_ACTIVE, sizeof(int), &w_ac)))
+        return s;
+    hipStream_t st = c->stream;
+    HIP_TRY(c, hipEventRecord(c->ev_in, as_stream(stream)));
+    HIP_TRY(c, hipStreamWaitEvent(st, c->ev_in, 0));
+    HIP_TRY(c, hipMemcpyAsync(w_tb, table.data(), sizeof(int4) * table.size(), hipMemcpyHostToDevice, st));
+    const int one = 1;
+    HIP_TRY(c, hipMemcpyAsync(w_k, &one, sizeof(int), hipMemcpyHostToDevice, st));
+    void *rec, *cen;
+    if ((s = prep_obstacles(c, obs, n_obs, st, &rec, &cen))) return s;
+    ObsView ov = obs_view(r, c, n_obs, rec, cen);
+    hipLaunchKernelGGL(k_init_edges, dim3((E + 63) / 64), dim3(64), 0, st, dof, r->q_lo, r->q_hi, edges, E, A, b,
+                       n_faces, cap, edge_status, (EdgeStatsDev*)w_st, (uint8_t*)w_pa);
+    HIP_TRY(c, hipGetLastError());
+    IterArgs it{(const int*)w_k, (const int4*)w_tb, 0, 0, 0, 0};
+    const uint32_t k0 = (uint32_t)p->seed, k1 = (uint32_t)(p->seed >> 32);
+    (void)k0;
+    (void)k1;
+    // ---- capture one iteration ----
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    ezo_status cs = EZO_OK;
+    auto mark = [&](int i) {
+        if (c->timing && cs == EZO_OK) {
+            hipError_t me = hipEventRecord(c->tev[i], st);
+            if (me != hipSuccess) cs = fail(c, EZO_E_HIP, "event record failed: %s", hipGetErrorString(me));
+        }
+    };
+    do {
+        mark(EZO_PHASE_SAMPLE);
+        if ((cs = launch_sample(c, dof, A, b, n_faces, cap, edges, E, S_cap, p->n_mix, p->seed, p->edge_id_base,
+                                (float*)w_s, stride, edge_status, it, st)))
+            break;
+        mark(EZO_PHASE_CHECK);
+        if ((cs = launch_check<false>(c, r, ov, (const float*)w_s, S_cap, 1, stride, (int64_t)dof * stride,
+                                      (uint8_t*)w_f, nullptr, nullptr, stride, E, edge_status, it, st)))
+            break;
+        mark(EZO_PHASE_TEST);
+        hipLaunchKernelGGL(k_test_select, dim3(E), dim3(1024), 0, st, (const uint8_t*)w_f, stride, p->n_p, p->n_b,
+                           (int*)w_ci, cand_cap, (int*)w_nc, nullptr, nullptr, edge_status, (EdgeStatsDev*)w_st, it);
+        mark(EZO_PHASE_BISECT);
+        if ((cs = launch_project_bisect(c, r, ov, edges, E, (const float*)w_s, stride, (const int*)w_ci,
+                                        (const int*)w_nc, cand_cap, p->n_b, (float*)w_cs, (float*)w_ad,
+                                        (float*)w_ts, (uint8_t*)w_pc, (uint8_t*)w_pa, edge_status, st)))
+            break;
+        mark(EZO_PHASE_PLACE);
+        hipLaunchKernelGGL(k_place, dim3(E), dim3(1024), (size_t)std::max(cand_cap, 16), st, dof, edges,
+                           (const float*)w_cs, (const float*)w_ad, (const float*)w_ts, (const int*)w_nc, cand_cap,
+                           p->n_f, (float)p->step_back_max, (float)p->t_col, A, b, n_faces, cap, edge_status,
+                           nullptr, nullptr, (const uint8_t*)w_pa, (EdgeStatsDev*)w_st);
+        mark(EZO_PHASE_ADVANCE);
+        hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, st, (int*)w_k, p->max_iters, edge_status, E, (int*)w_ac);
+        mark(EZO_NUM_PHASES);
+    } while (0);
+    hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (cs) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return cs;
+    }
+    if (ce != hipSuccess) return fail(c, EZO_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(c, EZO_E_HIP, "graph instantiation failed");
+    }
+    ezo_status result = EZO_OK;
+    for (int k = 1; k <= p->max_iters; ++k) {
+        hipError_t e1 = hipGraphLaunch(exec, st);
+        hipError_t e2 = hipMemcpyAsync(c->pinned, w_ac, sizeof(int), hipMemcpyDeviceToHost, st);
+        hipError_t e3 = hipStreamSynchronize(st);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+            result = fail(c, EZO_E_HIP, "iteration %d failed: %s", k,
+                          hipGetErrorString(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3)));
+            break;
+        }
+        if (c->timing) {
+            for (int ph = 0; ph < EZO_NUM_PHASES; ++ph) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, c->tev[ph], c->tev[ph + 1]) == hipSuccess) c->phase_ms[ph] += ms;
+            }
+            c->timed_iters++;
+        }
+        if (c->pinned[0] == 0) break;
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (result) return result;
+    if (stats) {
+        std::vector<EdgeStatsDev> hs(E);
+        HIP_TRY(c, hipMemcpyAsync(hs.data(), w_st, sizeof(EdgeStatsDev) * E, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+        for (int e = 0; e < E; ++e) {
+            stats[e].iterations = (int32_t)hs[e].iterations;
+            stats[e].planes = (int32_t)hs[e].planes;
+            stats[e].final_m = hs[e].final_m;
+            stats[e].test_collisions = hs[e].test_collisions;
+            stats[e].samples = hs[e].samples;
+            stats[e].exact_checks = hs[e].exact_checks;
+        }
+    }
+    HIP_TRY(c, hipEventRecord(c->ev_out, st));
+    HIP_TRY(c, hipStreamWaitEvent(as_stream(stream), c->ev_out, 0));
+    return EZO_OK;
+}
+
+ezo_status ezo_set_phase_timing(ezo_ctx* c, int32_t enable) {
+    if (!c) return EZO_E_INVALID;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (enable) {
+        for (auto& ev : c->tev)
+            if (!ev) HIP_TRY(c, hipEventCreate(&ev));
+    }
+    c->timing = enable != 0;
+    for (double& m : c->phase_ms) m = 0.0;
+    c->timed_iters = 0;
+    return EZO_OK;
+}
+
+ezo_status ezo_get_phase_timing(const ezo_ctx* c, double* ms_out, int64_t* iterations_out) {
+    if (!c || !ms_out) return EZO_E_INVALID;
+    for (int i = 0; i < EZO_NUM_PHASES; ++i) ms_out[i] = c->phase_ms[i];
+    if (iterations_out) *iterations_out = c->timed_iters;
+    return EZO_OK;
+}
+
+}  // extern "C"

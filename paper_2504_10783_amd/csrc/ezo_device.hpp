@@ -1,0 +1,330 @@
+// ezo_device.hpp -- device-side building blocks of the EI-ZO hot path on
+// gfx950: Philox4x32-10, DH forward kinematics into LDS, and the workgroup
+// "tile check" that decides collision for a tile of configurations.
+//
+// Tile check layout (one workgroup = W waves of 64 lanes):
+//   * a tile holds T configurations (T in {8,16,32,64}); lane l of every
+//     wave works on configuration (l % T) and on the sphere subset
+//     (l / T) of that configuration, so one wave covers all T
+//     configurations with 64/T lanes each;
+//   * the W waves split the obstacle list into W contiguous slices.  The
+//     obstacle index is wave-uniform, so obstacle records are read with
+//     scalar loads and enter the pair arithmetic as SGPR operands;
+//   * sphere centres of the tile live in LDS as [sphere][config] float4
+//     (x, y, z, r), written once by the FK phase and read by every wave.
+// Collision test per robot/obstacle pair, in a frame whose origin is the
+// centre of the obstacle cloud (keeps |c|^2 and |o|^2 small):
+//   v = (|c|^2 - r_c^2) + (|o|^2 - r_o^2) - 2 c.o - 2 r_c r_o = |c-o|^2 - (r_c+r_o)^2
+// so a pair collides iff v < 0 (5 VALU ops + a running min).  The
+// signed-distance mode evaluates |c - o| - r_o directly (difference form).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ezo {
+
+constexpr int kMaxDof = 8;
+constexpr float kHuge = 3.0e38f;
+
+// ---------------------------------------------------------------------------
+// Robot and obstacles as seen by kernels
+// ---------------------------------------------------------------------------
+struct RobotView {
+    int dof;
+    int n_spheres;
+    int n_self;
+    const float4* dh;          // [dof] (a, d, cos alpha, sin alpha)
+    const int* link_begin;     // [dof + 1] spheres of link i: [link_begin[i], link_begin[i+1])
+    const float4* sph;         // [S] local (x, y, z), r -- sorted by link
+    const int2* pairs;         // [P] self pairs, indices into the sorted order
+};
+
+// Read-only global memory viewed through the constant address space: loads
+// with a wave-uniform address then become scalar (s_load) loads.
+typedef __attribute__((address_space(4))) const float cfloat;
+
+__device__ __forceinline__ float4 cload4(const cfloat* p) { return make_float4(p[0], p[1], p[2], p[3]); }
+
+struct ObsView {
+    int n;
+    const float4* rec;         // [n][2]: (ox, oy, oz, ro), (-2ox, -2oy, -2oz, |o|^2 - ro^2), shifted frame
+    const float4* centre;      // [1] shift applied to world coordinates (x' = x - centre)
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11)
+// ---------------------------------------------------------------------------
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        U4 n;
+        n.x = hi1 ^ c.y ^ k0;
+        n.y = lo1;
+        n.z = hi0 ^ c.w ^ k1;
+        n.w = lo0;
+        c = n;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// word -> (0, 1): ((x >> 9) + 1/2) * 2^-23, exact in FP32
+__device__ __forceinline__ float u01(uint32_t x) {
+    return ((float)(x >> 9) + 0.5f) * (1.0f / 8388608.0f);
+}
+
+__device__ __forceinline__ uint32_t word_of(const U4& v, int i) {
+    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+
+// ---------------------------------------------------------------------------
+// Forward kinematics: compose T <- T * A_l with the standard DH matrix
+//   A = [[ct, -st ca,  st sa, a ct],
+//        [st,  ct ca, -ct sa, a st],
+//        [0,   sa,     ca,    d   ]]
+// R is row-major 3x3, p the translation.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void dh_compose(float R[9], float p[3], float ct, float st, float4 dh) {
+    const float a = dh.x, d = dh.y, ca = dh.z, sa = dh.w;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const float r0 = R[3 * r + 0], r1 = R[3 * r + 1], r2 = R[3 * r + 2];
+        const float u = fmaf(r0, ct, r1 * st);        // new column 0
+        const float w = fmaf(r1, ct, -r0 * st);       // R * (-st, ct, 0)
+        R[3 * r + 0] = u;
+        R[3 * r + 1] = fmaf(w, ca, r2 * sa);
+        R[3 * r + 2] = fmaf(r2, ca, -w * sa);
+        p[r] = fmaf(a, u, fmaf(d, r2, p[r]));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile shared-memory carve-up (dynamic LDS)
+// ---------------------------------------------------------------------------
+struct TileSmem {
+    float* q;          // [T][kMaxDof] configurations of the tile
+    float2* trig;      // [kMaxDof][T] (cos, sin) of each joint
+    float4* cen;       // [S][T] sphere centres (shifted frame) and radius
+    int* hit;          // [T] collision flag (flags mode) / validity
+    float* red;        // [2][W][T] partial minima (signed-distance mode)
+};
+
+__host__ __device__ inline size_t tile_smem_bytes(int T, int S, int W) {
+    size_t b = 0;
+    b += sizeof(float) * (size_t)T * kMaxDof;
+    b += sizeof(float2) * (size_t)kMaxDof * T;
+    b += sizeof(float4) * (size_t)(S > 0 ? S : 1) * T;
+    b += sizeof(int) * (size_t)T;
+    b += sizeof(float) * 2 * (size_t)W * T;
+    return (b + 15) & ~(size_t)15;
+}
+
+__device__ inline TileSmem carve_tile(char* base, int T, int S, int W) {
+    TileSmem t;
+    char* p = base;
+    t.cen = reinterpret_cast<float4*>(p);   p += sizeof(float4) * (size_t)(S > 0 ? S : 1) * T;
+    t.trig = reinterpret_cast<float2*>(p);  p += sizeof(float2) * (size_t)kMaxDof * T;
+    t.q = reinterpret_cast<float*>(p);      p += sizeof(float) * (size_t)T * kMaxDof;
+    t.red = reinterpret_cast<float*>(p);    p += sizeof(float) * 2 * (size_t)W * T;
+    t.hit = reinterpret_cast<int*>(p);
+    return t;
+}
+
+// FK phase: t.q[c][j] (c < n_valid) -> t.cen[s][c].  Ends with a barrier.
+__device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const TileSmem& t, int T, int n_valid) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int dof = rb.dof;
+    for (int i = tid; i < T * dof; i += nt) {
+        const int c = i % T, j = i / T;
+        float s = 0.f, co = 1.f;
+        if (c < n_valid) sincosf(t.q[c * kMaxDof + j], &s, &co);
+        t.trig[j * T + c] = make_float2(co, s);
+    }
+    __syncthreads();
+    const float4 sh = ob.centre[0];
+    for (int i = tid; i < T * dof; i += nt) {
+        const int c = i % T, link = i / T;
+        float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+        float p[3] = {-sh.x, -sh.y, -sh.z};
+        for (int l = 0; l <= link; ++l) {
+            const float2 cs = t.trig[l * T + c];
+            dh_compose(R, p, cs.x, cs.y, rb.dh[l]);
+        }
+        const int s1 = rb.link_begin[link + 1];
+        for (int s = rb.link_begin[link]; s < s1; ++s) {
+            const float4 ps = rb.sph[s];
+            float4 o;
+            o.x = fmaf(R[0], ps.x, fmaf(R[1], ps.y, fmaf(R[2], ps.z, p[0])));
+            o.y = fmaf(R[3], ps.x, fmaf(R[4], ps.y, fmaf(R[5], ps.z, p[1])));
+            o.z = fmaf(R[6], ps.x, fmaf(R[7], ps.y, fmaf(R[8], ps.z, p[2])));
+            o.w = ps.w;
+            t.cen[s * T + c] = o;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int wave_id() {
+    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+__device__ __forceinline__ bool wave_all(bool p) {
+    return __ballot(p) == __ballot(true);
+}
+
+// Flags-mode pair sweep.  Result: t.hit[c] = 1 iff configuration c collides
+// (invalid configurations c >= n_valid are reported as 1).  Barrier at exit.
+__device__ inline void tile_pairs_flags(const RobotView& rb, const ObsView& ob, const TileSmem& t, int T,
+                                        int n_valid) {
+    const int tid = threadIdx.x;
+    const int W = blockDim.x >> 6;
+    const int w = wave_id();
+    const int lane = tid & 63;
+    const int c = lane % T;
+    const int nsub = 64 / T;
+    const int j = lane / T;
+    volatile int* hit = t.hit;
+    const int S = rb.n_spheres;
+
+    // ---- self pairs (cheap; many configurations self-collide) ----
+    {
+        const int P = rb.n_self;
+        const int step = W * nsub;
+        for (int p0 = w * nsub; p0 < P; p0 += step) {
+            if (wave_all(hit[c] != 0)) break;
+            const int p = p0 + j;
+            if (p < P) {
+                const int2 pr = rb.pairs[p];
+                const float4 a = t.cen[pr.x * T + c];
+                const float4 b = t.cen[pr.y * T + c];
+                const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const float R = a.w + b.w;
+                if (d2 < R * R) hit[c] = 1;
+            }
+        }
+    }
+    // ---- robot/obstacle pairs: this wave's obstacle slice ----
+    const int o0 = (int)(((long)ob.n * w) / W);
+    const int o1 = (int)(((long)ob.n * (w + 1)) / W);
+    if (o1 > o0) {
+        for (int s0 = 0; s0 < S; s0 += 2 * nsub) {
+            if (wave_all(hit[c] != 0)) break;
+            const int sa = s0 + j, sb = s0 + nsub + j;
+            float4 A = sa < S ? t.cen[sa * T + c] : make_float4(0.f, 0.f, 0.f, 0.f);
+            float4 B = sb < S ? t.cen[sb * T + c] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float alA = sa < S ? fmaf(A.x, A.x, fmaf(A.y, A.y, fmaf(A.z, A.z, -A.w * A.w))) : kHuge;
+            const float alB = sb < S ? fmaf(B.x, B.x, fmaf(B.y, B.y, fmaf(B.z, B.z, -B.w * B.w))) : kHuge;
+            const float mA = -2.f * A.w, mB = -2.f * B.w;
+            float accA = kHuge, accB = kHuge;
+            const cfloat* rec = (const cfloat*)ob.rec;
+#pragma unroll 4
+            for (int o = o0; o < o1; ++o) {
+                const float4 P0 = cload4(rec + 8 * o);       // (ox, oy, oz, ro)
+                const float4 P1 = cload4(rec + 8 * o + 4);   // (-2ox, -2oy, -2oz, beta)
+                float vA = alA + P1.w;
+                float vB = alB + P1.w;
+                vA = fmaf(A.x, P1.x, vA);
+                vB = fmaf(B.x, P1.x, vB);
+                vA = fmaf(A.y, P1.y, vA);
+                vB = fmaf(B.y, P1.y, vB);
+                vA = fmaf(A.z, P1.z, vA);
+                vB = fmaf(B.z, P1.z, vB);
+                vA = fmaf(mA, P0.w, vA);
+                vB = fmaf(mB, P0.w, vB);
+                accA = fminf(accA, vA);
+                accB = fminf(accB, vB);
+            }
+            if (fminf(accA, accB) < 0.f) hit[c] = 1;
+        }
+    }
+    __syncthreads();
+}
+
+// Signed-distance pair sweep.  Results: t.red[0][0][c] = overall minimum,
+// t.red[1][0][c] = self minimum; t.hit[c] = (overall < 0).  Barrier at exit.
+__device__ inline void tile_pairs_sd(const RobotView& rb, const ObsView& ob, const TileSmem& t, int T,
+                                     int n_valid) {
+    const int tid = threadIdx.x;
+    const int W = blockDim.x >> 6;
+    const int w = wave_id();
+    const int lane = tid & 63;
+    const int c = lane % T;
+    const int nsub = 64 / T;
+    const int j = lane / T;
+    const int S = rb.n_spheres;
+    float env = INFINITY, self = INFINITY;
+    {
+        const int P = rb.n_self;
+        for (int p = w * nsub + j; p < P; p += W * nsub) {
+            const int2 pr = rb.pairs[p];
+            const float4 a = t.cen[pr.x * T + c];
+            const float4 b = t.cen[pr.y * T + c];
+            const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+            const float d = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+            self = fminf(self, d - a.w - b.w);
+        }
+    }
+    const int o0 = (int)(((long)ob.n * w) / W);
+    const int o1 = (int)(((long)ob.n * (w + 1)) / W);
+    if (o1 > o0) {
+        for (int s0 = 0; s0 < S; s0 += 2 * nsub) {
+            const int sa = s0 + j, sb = s0 + nsub + j;
+            const float4 A = sa < S ? t.cen[sa * T + c] : make_float4(kHuge, kHuge, kHuge, 0.f);
+            const float4 B = sb < S ? t.cen[sb * T + c] : make_float4(kHuge, kHuge, kHuge, 0.f);
+            float bestA = INFINITY, bestB = INFINITY;
+            const cfloat* rec = (const cfloat*)ob.rec;
+#pragma unroll 4
+            for (int o = o0; o < o1; ++o) {
+                const float4 P0 = cload4(rec + 8 * o);
+                const float ax = A.x - P0.x, ay = A.y - P0.y, az = A.z - P0.z;
+                const float bx = B.x - P0.x, by = B.y - P0.y, bz = B.z - P0.z;
+                const float dA = sqrtf(fmaf(ax, ax, fmaf(ay, ay, az * az)));
+                const float dB = sqrtf(fmaf(bx, bx, fmaf(by, by, bz * bz)));
+                bestA = fminf(bestA, dA - P0.w);
+                bestB = fminf(bestB, dB - P0.w);
+            }
+            if (sa < S) env = fminf(env, bestA - A.w);
+            if (sb < S) env = fminf(env, bestB - B.w);
+        }
+    }
+    // reduce over the lanes of one configuration, then over waves
+    for (int off = T; off < 64; off <<= 1) {
+        env = fminf(env, __shfl_xor(env, off));
+        self = fminf(self, __shfl_xor(self, off));
+    }
+    if (j == 0) {
+        t.red[(0 * W + w) * T + c] = fminf(env, self);
+        t.red[(1 * W + w) * T + c] = self;
+    }
+    __syncthreads();
+    if (tid < T) {
+        float m = INFINITY, s = INFINITY;
+        for (int k = 0; k < W; ++k) {
+            m = fminf(m, t.red[(0 * W + k) * T + tid]);
+            s = fminf(s, t.red[(1 * W + k) * T + tid]);
+        }
+        t.red[tid] = m;
+        t.red[W * T + tid] = s;
+        t.hit[tid] = (m < 0.f) ? 1 : 0;
+    }
+    __syncthreads();
+}
+
+// Whole tile check on t.q[0..n_valid).  Flags mode fills t.hit; signed-
+// distance mode also fills t.red[c] (overall) and t.red[W*T + c] (self).
+template <bool SD>
+__device__ inline void tile_check(const RobotView& rb, const ObsView& ob, const TileSmem& t, int T, int n_valid) {
+    tile_fk(rb, ob, t, T, n_valid);
+    if (threadIdx.x < (unsigned)T) t.hit[threadIdx.x] = (threadIdx.x < (unsigned)n_valid) ? 0 : 1;
+    __syncthreads();
+    if (SD) tile_pairs_sd(rb, ob, t, T, n_valid);
+    else tile_pairs_flags(rb, ob, t, T, n_valid);
+}
+
+}  // namespace ezo

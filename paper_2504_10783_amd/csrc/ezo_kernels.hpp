@@ -1,0 +1,564 @@
+// ezo_kernels.hpp -- the HIP kernels of the EI-ZO hot path (gfx950).
+//
+// Every kernel serves both the step-by-step entry points and the fused
+// inflation loop.  In the fused loop, per-iteration quantities (iteration k,
+// M_k, T_k, |S|) are read from device memory through IterArgs, so one
+// captured hipGraph can be replayed for every iteration; edges whose status
+// is final (>= 0) are skipped by every kernel.
+#pragma once
+#include "ezo_device.hpp"
+
+namespace ezo {
+
+// Per-iteration constants: either given directly, or looked up from
+// table[k] = (M_k, T_k, |S|_k, 0) with k = *k_dev.
+struct IterArgs {
+    const int* k_dev;     // NULL => use k, M, T, nS below
+    const int4* table;    // [max_iters + 1]
+    int k, M, T, nS;
+};
+
+struct IterVals { int k, M, T, nS; };
+
+__device__ __forceinline__ IterVals resolve(const IterArgs& a) {
+    IterVals v;
+    if (a.k_dev) {
+        v.k = *a.k_dev;
+        const int4 e = a.table[v.k];
+        v.M = e.x; v.T = e.y; v.nS = e.z;
+    } else {
+        v.k = a.k; v.M = a.M; v.T = a.T; v.nS = a.nS;
+    }
+    return v;
+}
+
+// Edge is still running (fused mode) -- or always, when no status array.
+__device__ __forceinline__ bool edge_running(const int* status, int e) {
+    return status == nullptr || status[e] < 0;
+}
+
+// ---------------------------------------------------------------------------
+// Obstacle preparation: centre of the bounding box of the obstacle centres,
+// then records (o', r), (-2 o', |o'|^2 - r^2) with o' = o - centre.
+// One workgroup.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_prep_obstacles(const float* __restrict__ obs, int n, float4* __restrict__ rec,
+                                                        float4* __restrict__ centre) {
+    __shared__ float red[6][256];
+    const int tid = threadIdx.x;
+    float mn[3] = {kHuge, kHuge, kHuge}, mx[3] = {-kHuge, -kHuge, -kHuge};
+    for (int o = tid; o < n; o += blockDim.x)
+        for (int k = 0; k < 3; ++k) {
+            const float v = obs[4 * (size_t)o + k];
+            mn[k] = fminf(mn[k], v);
+            mx[k] = fmaxf(mx[k], v);
+        }
+    for (int k = 0; k < 3; ++k) { red[k][tid] = mn[k]; red[3 + k][tid] = mx[k]; }
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s)
+            for (int k = 0; k < 3; ++k) {
+                red[k][tid] = fminf(red[k][tid], red[k][tid + s]);
+                red[3 + k][tid] = fmaxf(red[3 + k][tid], red[3 + k][tid + s]);
+            }
+        __syncthreads();
+    }
+    float cx = 0.f, cy = 0.f, cz = 0.f;
+    if (n > 0) {
+        cx = 0.5f * (red[0][0] + red[3][0]);
+        cy = 0.5f * (red[1][0] + red[4][0]);
+        cz = 0.5f * (red[2][0] + red[5][0]);
+    }
+    if (tid == 0) centre[0] = make_float4(cx, cy, cz, 0.f);
+    for (int o = tid; o < n; o += blockDim.x) {
+        const float x = obs[4 * (size_t)o + 0] - cx, y = obs[4 * (size_t)o + 1] - cy, z = obs[4 * (size_t)o + 2] - cz;
+        const float r = obs[4 * (size_t)o + 3];
+        rec[2 * (size_t)o] = make_float4(x, y, z, r);
+        rec[2 * (size_t)o + 1] = make_float4(-2.f * x, -2.f * y, -2.f * z, fmaf(x, x, fmaf(y, y, fmaf(z, z, -r * r))));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched collision check.  blockIdx.y = batch b (an edge in the fused loop),
+// blockIdx.x = tile.  q_b = q + b * q_batch; flags_b = flags + b * out_batch.
+// n = iteration's |S| when it.k_dev is set, else n_arg.
+// ---------------------------------------------------------------------------
+template <int T, bool SD>
+__global__ void __launch_bounds__(1024) k_check(RobotView rb, ObsView ob, const float* __restrict__ q, int64_t n_arg,
+                                                int64_t stride_n, int64_t stride_d, int64_t q_batch,
+                                                uint8_t* __restrict__ flags, float* __restrict__ min_sd,
+                                                float* __restrict__ min_sd_self, int64_t out_batch,
+                                                const int* __restrict__ status, IterArgs it) {
+    extern __shared__ __align__(16) char smem[];
+    const int b = blockIdx.y;
+    if (!edge_running(status, b)) return;
+    int64_t n = n_arg;
+    if (it.k_dev) n = resolve(it).nS;
+    const int64_t base = (int64_t)blockIdx.x * T;
+    if (base >= n) return;
+    const int nv = (int)((n - base) < T ? (n - base) : T);
+    const int W = blockDim.x >> 6;
+    TileSmem t = carve_tile(smem, T, rb.n_spheres, W);
+    const float* qb = q + b * q_batch;
+    for (int i = threadIdx.x; i < T * rb.dof; i += blockDim.x) {
+        const int c = i % T, j = i / T;
+        if (c < nv) t.q[c * kMaxDof + j] = qb[(base + c) * stride_n + j * stride_d];
+    }
+    __syncthreads();
+    tile_check<SD>(rb, ob, t, T, nv);
+    if (threadIdx.x < (unsigned)nv) {
+        const int64_t g = b * out_batch + base + threadIdx.x;
+        flags[g] = (uint8_t)t.hit[threadIdx.x];
+        if (SD) {
+            if (min_sd) min_sd[g] = t.red[threadIdx.x];
+            if (min_sd_self) min_sd_self[g] = t.red[W * T + threadIdx.x];
+        }
+    }
+}
+
+// Sphere centres in world coordinates, original sphere order.
+template <int T>
+__global__ void __launch_bounds__(256) k_centres(RobotView rb, ObsView ob, const int* __restrict__ sorted_to_orig,
+                                                 const float* __restrict__ q, int64_t n, int64_t stride_n,
+                                                 int64_t stride_d, float* __restrict__ out) {
+    extern __shared__ __align__(16) char smem[];
+    const int64_t base = (int64_t)blockIdx.x * T;
+    if (base >= n) return;
+    const int nv = (int)((n - base) < T ? (n - base) : T);
+    TileSmem t = carve_tile(smem, T, rb.n_spheres, blockDim.x >> 6);
+    for (int i = threadIdx.x; i < T * rb.dof; i += blockDim.x) {
+        const int c = i % T, j = i / T;
+        if (c < nv) t.q[c * kMaxDof + j] = q[(base + c) * stride_n + j * stride_d];
+    }
+    __syncthreads();
+    tile_fk(rb, ob, t, T, nv);
+    const float4 sh = ob.centre[0];
+    const int S = rb.n_spheres;
+    for (int i = threadIdx.x; i < nv * S; i += blockDim.x) {
+        const int c = i / S, s = i % S;
+        const float4 v = t.cen[s * T + c];
+        float* o = out + ((base + c) * S + sorted_to_orig[s]) * 3;
+        o[0] = v.x + sh.x;
+        o[1] = v.y + sh.y;
+        o[2] = v.z + sh.z;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hit-and-run sampler: one thread per walk, polytope rows of the edge in LDS.
+// blockIdx.y = edge.  Rows stored as [F][D] normals plus b[F].
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict__ A, const float* __restrict__ bvec,
+                                                const int* __restrict__ n_faces, int cap,
+                                                const float* __restrict__ edges, uint32_t key0, uint32_t key1,
+                                                int64_t edge_id_base, int n_mix, float* __restrict__ S,
+                                                int64_t stride, const int* __restrict__ status, IterArgs it) {
+    extern __shared__ __align__(16) char smem[];
+    const int e = blockIdx.y;
+    if (!edge_running(status, e)) return;
+    const IterVals iv = resolve(it);
+    const int F = min(max(n_faces[e], 0), cap);
+    float* rowA = reinterpret_cast<float*>(smem);        // [F][D]
+    float* rowb = rowA + (size_t)F * D;                   // [F]
+    const float* Ae = A + (size_t)e * cap * dof;
+    for (int i = threadIdx.x; i < F * D; i += blockDim.x) {
+        const int f = i / D, j = i % D;
+        rowA[i] = j < dof ? Ae[(size_t)f * dof + j] : 0.f;
+    }
+    for (int f = threadIdx.x; f < F; f += blockDim.x) rowb[f] = bvec[(size_t)e * cap + f];
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= iv.nS) return;
+    const float* v = edges + (size_t)e * 2 * dof;
+    const uint32_t eid = (uint32_t)(edge_id_base + e);
+    float x[D], u[D];
+    {
+        const U4 r = philox4x32_10(U4{(uint32_t)i, eid, (uint32_t)iv.k, 0u}, key0, key1);
+        const float w0 = u01(r.x);
+#pragma unroll
+        for (int j = 0; j < D; ++j) x[j] = j < dof ? fmaf(w0, v[dof + j] - v[j], v[j]) : 0.f;
+    }
+    const int npair = (dof + 1) >> 1;
+    for (int s = 1; s <= n_mix; ++s) {
+        // words 0 .. 2*npair-1: Box-Muller pairs; word 2*npair: position on the chord
+        float g[D + 1];
+        float wt = 0.5f;
+        U4 r = philox4x32_10(U4{(uint32_t)i, eid, (uint32_t)iv.k, 16u * (uint32_t)s}, key0, key1);
+        int call = 0;
+#pragma unroll
+        for (int m = 0; m < (D + 1) / 2; ++m) {
+            if (m < npair) {
+                const int w = 2 * m;
+                if (w / 4 != call) {
+                    call = w / 4;
+                    r = philox4x32_10(U4{(uint32_t)i, eid, (uint32_t)iv.k, 16u * (uint32_t)s + (uint32_t)call}, key0, key1);
+                }
+                const float ua = u01(word_of(r, w % 4));
+                const float ub = u01(word_of(r, (w + 1) % 4));
+                const float rad = sqrtf(-2.f * logf(ua));
+                float sn, cs;
+                sincospif(2.f * ub, &sn, &cs);
+                g[2 * m] = rad * cs;
+                if (2 * m + 1 < D + 1) g[2 * m + 1] = rad * sn;
+            }
+        }
+        {
+            const int w = 2 * npair;
+            if (w / 4 != call) {
+                call = w / 4;
+                r = philox4x32_10(U4{(uint32_t)i, eid, (uint32_t)iv.k, 16u * (uint32_t)s + (uint32_t)call}, key0, key1);
+            }
+            wt = u01(word_of(r, w % 4));
+        }
+        float nrm = 0.f;
+#pragma unroll
+        for (int j = 0; j < D; ++j) nrm = j < dof ? fmaf(g[j], g[j], nrm) : nrm;
+        const float inv = 1.0f / sqrtf(nrm);
+#pragma unroll
+        for (int j = 0; j < D; ++j) u[j] = j < dof ? g[j] * inv : 0.f;
+        float tlo = -INFINITY, thi = INFINITY;
+        for (int f = 0; f < F; ++f) {
+            float den = 0.f, ax = 0.f;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const float a = rowA[f * D + j];
+                den = fmaf(a, u[j], den);
+                ax = fmaf(a, x[j], ax);
+            }
+            const float tt = (rowb[f] - ax) / den;
+            if (den > 0.f) thi = fminf(thi, tt);
+            else if (den < 0.f) tlo = fmaxf(tlo, tt);
+        }
+        float tm = 0.f;
+        if (thi >= tlo && tlo > -INFINITY && thi < INFINITY) tm = fmaf(wt, thi - tlo, tlo);
+#pragma unroll
+        for (int j = 0; j < D; ++j) x[j] = fmaf(tm, u[j], x[j]);
+    }
+    float* Se = S + (size_t)e * dof * stride;
+    for (int j = 0; j < dof; ++j) Se[(size_t)j * stride + i] = x[j];
+}
+
+// ---------------------------------------------------------------------------
+// Unadaptive test + selection of the first N_p colliding samples.
+// One workgroup (1024 threads) per edge.
+// ---------------------------------------------------------------------------
+struct EdgeStatsDev {
+    long long iterations, planes, final_m, test_collisions, samples, exact_checks;
+};
+
+__global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict__ flags, int64_t stride, int n_p,
+                                                      int n_b, int* __restrict__ cand_idx, int cand_cap,
+                                                      int* __restrict__ n_cands, uint8_t* __restrict__ accept_out,
+                                                      int* __restrict__ count_out, int* __restrict__ status,
+                                                      EdgeStatsDev* __restrict__ stats, IterArgs it) {
+    __shared__ int wsum[16];
+    __shared__ int s_base;
+    const int e = blockIdx.x;
+    if (!edge_running(status, e)) {
+        if (threadIdx.x == 0 && n_cands) n_cands[e] = 0;
+        return;
+    }
+    const IterVals iv = resolve(it);
+    const uint8_t* fe = flags + (size_t)e * stride;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+    // count over the first M samples
+    int cnt = 0;
+    for (int i = tid; i < iv.M; i += blockDim.x) cnt += fe[i] ? 1 : 0;
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if (lane == 0) wsum[w] = cnt;
+    __syncthreads();
+    int total = 0;
+    for (int k = 0; k < nw; ++k) total += wsum[k];
+    const bool accept = total <= iv.T;
+    __syncthreads();
+    int taken = 0;
+    if (!accept) {
+        if (tid == 0) s_base = 0;
+        __syncthreads();
+        for (int c0 = 0; c0 < iv.nS; c0 += blockDim.x) {
+            const int i = c0 + tid;
+            const bool f = (i < iv.nS) && fe[i];
+            const unsigned long long m = __ballot(f);
+            const int before = __popcll(m & ((1ull << lane) - 1ull));
+            if (lane == 0) wsum[w] = __popcll(m);
+            __syncthreads();
+            int off = s_base;
+            for (int k = 0; k < w; ++k) off += wsum[k];
+            int chunk = 0;
+            for (int k = 0; k < nw; ++k) chunk += wsum[k];
+            const int pos = off + before;
+            if (f && pos < n_p) cand_idx[(size_t)e * cand_cap + pos] = i;
+            __syncthreads();
+            if (tid == 0) s_base += chunk;
+            __syncthreads();
+            if (s_base >= n_p) break;
+        }
+        taken = s_base < n_p ? s_base : n_p;
+    }
+    if (tid == 0) {
+        if (n_cands) n_cands[e] = taken;
+        if (accept_out) accept_out[e] = accept ? 1 : 0;
+        if (count_out) count_out[e] = total;
+        if (stats) {
+            EdgeStatsDev& s = stats[e];
+            s.iterations = iv.k;
+            s.final_m = iv.M;
+            s.test_collisions = total;
+            s.samples += iv.nS;
+            s.exact_checks += (long long)iv.nS + (long long)taken * (1 + n_b);
+        }
+        if (status && accept) status[e] = 0;   // EZO_EDGE_CERTIFIED
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Projection + fail-fast check + N_b bisection steps.  blockIdx.y = edge,
+// blockIdx.x = tile of T candidates.  Candidate state lives with the threads
+// c < T of wave 0; every check is a whole-workgroup tile check.
+// ---------------------------------------------------------------------------
+template <int T>
+__global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView ob, const float* __restrict__ edges,
+                                                         const float* __restrict__ S, int64_t stride,
+                                                         const int* __restrict__ cand_idx,
+                                                         const int* __restrict__ n_cands, int cand_cap, int n_b,
+                                                         float* __restrict__ c_star, float* __restrict__ a_dir,
+                                                         float* __restrict__ t_star,
+                                                         uint8_t* __restrict__ proj_collides,
+                                                         uint8_t* __restrict__ proj_any,
+                                                         const int* __restrict__ status) {
+    extern __shared__ __align__(16) char smem[];
+    const int e = blockIdx.y;
+    if (!edge_running(status, e)) return;
+    const int nc = min(max(n_cands[e], 0), cand_cap);
+    const int base = blockIdx.x * T;
+    if (base >= nc) return;
+    const int nv = (nc - base) < T ? (nc - base) : T;
+    const int dof = rb.dof;
+    const int W = blockDim.x >> 6;
+    TileSmem t = carve_tile(smem, T, rb.n_spheres, W);
+    const int tid = threadIdx.x;
+    const bool own = tid < nv;
+    float lo[kMaxDof], hi[kMaxDof], cp[kMaxDof];
+    const float* v = edges + (size_t)e * 2 * dof;
+    if (own) {
+        const int idx = min(max(cand_idx[(size_t)e * cand_cap + base + tid], 0), (int)(stride - 1));
+        const float* Se = S + (size_t)e * dof * stride;
+        float num = 0.f, den = 0.f;
+#pragma unroll
+        for (int j = 0; j < kMaxDof; ++j) {
+            hi[j] = j < dof ? Se[(size_t)j * stride + idx] : 0.f;
+            const float dv = j < dof ? v[dof + j] - v[j] : 0.f;
+            num = fmaf(hi[j] - (j < dof ? v[j] : 0.f), dv, num);
+            den = fmaf(dv, dv, den);
+        }
+        float alpha = 0.f;
+        if (den > 0.f) alpha = fminf(fmaxf(num / den, 0.f), 1.f);
+        float nrm = 0.f;
+#pragma unroll
+        for (int j = 0; j < kMaxDof; ++j) {
+            cp[j] = j < dof ? fmaf(alpha, v[dof + j], (1.f - alpha) * v[j]) : 0.f;
+            lo[j] = cp[j];
+            nrm = fmaf(hi[j] - cp[j], hi[j] - cp[j], nrm);
+        }
+        nrm = sqrtf(nrm);
+        const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
+        for (int j = 0; j < dof; ++j) {
+            a_dir[((size_t)e * dof + j) * cand_cap + base + tid] = (hi[j] - cp[j]) * inv;
+            t.q[tid * kMaxDof + j] = cp[j];
+        }
+    }
+    __syncthreads();
+    tile_check<false>(rb, ob, t, T, nv);
+    if (own) {
+        const int h = t.hit[tid];
+        proj_collides[(size_t)e * cand_cap + base + tid] = (uint8_t)h;
+        if (h && proj_any) proj_any[e] = 1;
+    }
+    for (int step = 0; step < n_b; ++step) {
+        __syncthreads();
+        if (own)
+            for (int j = 0; j < dof; ++j) t.q[tid * kMaxDof + j] = 0.5f * (lo[j] + hi[j]);
+        __syncthreads();
+        tile_check<false>(rb, ob, t, T, nv);
+        if (own) {
+            const bool h = t.hit[tid] != 0;
+#pragma unroll
+            for (int j = 0; j < kMaxDof; ++j) {
+                const float m = 0.5f * (lo[j] + hi[j]);
+                if (j < dof) {
+                    if (h) hi[j] = m;
+                    else lo[j] = m;
+                }
+            }
+        }
+    }
+    if (own) {
+        float ts = 0.f;
+        for (int j = 0; j < dof; ++j) {
+            c_star[((size_t)e * dof + j) * cand_cap + base + tid] = hi[j];
+            ts = fmaf(hi[j] - cp[j], hi[j] - cp[j], ts);
+        }
+        t_star[(size_t)e * cand_cap + base + tid] = sqrtf(ts);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ordering and placing hyperplanes: one workgroup (1024 threads) per edge,
+// n_f rounds of (argmin over alive candidates by (t*, index), broadcast row,
+// discard).  Alive flags in LDS.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict__ edges, const float* __restrict__ c_star,
+                                                const float* __restrict__ a_dir, const float* __restrict__ t_star,
+                                                const int* __restrict__ n_cands, int cand_cap, int n_f,
+                                                float step_back_max, float t_col, float* __restrict__ A,
+                                                float* __restrict__ bvec, int* __restrict__ n_faces, int cap,
+                                                int* __restrict__ status, int* __restrict__ placed_idx,
+                                                int* __restrict__ n_placed, const uint8_t* __restrict__ proj_any,
+                                                EdgeStatsDev* __restrict__ stats) {
+    extern __shared__ __align__(16) char smem[];
+    uint8_t* alive = reinterpret_cast<uint8_t*>(smem);                // [cand_cap]
+    __shared__ unsigned long long wmin[16];
+    __shared__ float row[kMaxDof + 1];
+    __shared__ int s_stop;
+    const int e = blockIdx.x;
+    if (status[e] >= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+    if (proj_any && proj_any[e]) {
+        if (tid == 0) {
+            status[e] = 2;   // EZO_EDGE_IN_COLLISION
+            if (n_placed) n_placed[e] = 0;
+        }
+        return;
+    }
+    const int n = min(max(n_cands[e], 0), cand_cap);
+    for (int j = tid; j < n; j += blockDim.x) alive[j] = 1;
+    const float* v = edges + (size_t)e * 2 * dof;
+    const float* cs = c_star + (size_t)e * dof * cand_cap;
+    const float* ad = a_dir + (size_t)e * dof * cand_cap;
+    const float* ts = t_star + (size_t)e * cand_cap;
+    int nf = min(max(n_faces[e], 0), cap);
+    int placed = 0;
+    if (tid == 0) s_stop = 0;
+    __syncthreads();
+    for (int round = 0; round < n_f; ++round) {
+        unsigned long long best = ~0ull;
+        for (int j = tid; j < n; j += blockDim.x)
+            if (alive[j]) {
+                const unsigned long long key = ((unsigned long long)__float_as_uint(ts[j]) << 32) | (unsigned)j;
+                best = key < best ? key : best;
+            }
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(best, off);
+            best = o < best ? o : best;
+        }
+        if (lane == 0) wmin[w] = best;
+        __syncthreads();
+        best = ~0ull;
+        for (int k = 0; k < nw; ++k) best = wmin[k] < best ? wmin[k] : best;
+        if (best == ~0ull) break;                         // no candidate left (uniform)
+        const int jb = (int)(best & 0xffffffffull);
+        if (tid == 0) {
+            if (ts[jb] <= t_col) {
+                s_stop = 1;
+                status[e] = 2;                            // EZO_EDGE_IN_COLLISION
+            } else if (nf >= cap) {
+                s_stop = 1;
+            } else {
+                float bj = 0.f, av1 = 0.f, av2 = 0.f;
+                for (int k = 0; k < dof; ++k) {
+                    const float a = ad[(size_t)k * cand_cap + jb];
+                    row[k] = a;
+                    bj = fmaf(a, cs[(size_t)k * cand_cap + jb], bj);
+                    av1 = fmaf(a, v[k], av1);
+                    av2 = fmaf(a, v[dof + k], av2);
+                }
+                const float r = fmaxf(av1, av2) - bj + step_back_max;
+                const float delta = r > 0.f ? step_back_max - r : step_back_max;
+                const float rhs = bj - delta;
+                row[kMaxDof] = rhs;
+                for (int k = 0; k < dof; ++k) A[((size_t)e * cap + nf) * dof + k] = row[k];
+                bvec[(size_t)e * cap + nf] = rhs;
+                if (placed_idx) placed_idx[(size_t)e * n_f + placed] = jb;
+            }
+        }
+        __syncthreads();
+        if (s_stop) break;
+        ++nf;
+        ++placed;
+        const float rhs = row[kMaxDof];
+        for (int j = tid; j < n; j += blockDim.x)
+            if (alive[j]) {
+                float ac = 0.f;
+                for (int k = 0; k < dof; ++k) ac = fmaf(row[k], cs[(size_t)k * cand_cap + j], ac);
+                if (ac > rhs) alive[j] = 0;
+            }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        n_faces[e] = nf;
+        if (n_placed) n_placed[e] = placed;
+        if (stats) stats[e].planes += placed;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused-loop bookkeeping
+// ---------------------------------------------------------------------------
+// P_e = D (box rows: +e_j <= hi_j, then -e_j <= -lo_j); status -1 (running) or
+// INVALID (3) when a vertex is outside D or not finite.
+__global__ void k_init_edges(int dof, const float* __restrict__ q_lo, const float* __restrict__ q_hi,
+                             const float* __restrict__ edges, int n_edges, float* __restrict__ A,
+                             float* __restrict__ bvec, int* __restrict__ n_faces, int cap, int* __restrict__ status,
+                             EdgeStatsDev* __restrict__ stats, uint8_t* __restrict__ proj_any) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_edges) return;
+    float* Ae = A + (size_t)e * cap * dof;
+    float* be = bvec + (size_t)e * cap;
+    for (int f = 0; f < 2 * dof; ++f) {
+        for (int j = 0; j < dof; ++j) Ae[(size_t)f * dof + j] = 0.f;
+        if (f < dof) {
+            Ae[(size_t)f * dof + f] = 1.f;
+            be[f] = q_hi[f];
+        } else {
+            Ae[(size_t)f * dof + (f - dof)] = -1.f;
+            be[f] = -q_lo[f - dof];
+        }
+    }
+    n_faces[e] = 2 * dof;
+    bool ok = true;
+    const float* v = edges + (size_t)e * 2 * dof;
+    for (int j = 0; j < 2 * dof; ++j) {
+        const float x = v[j];
+        const int jj = j % dof;
+        if (!(x == x) || isinf(x) || x < q_lo[jj] || x > q_hi[jj]) ok = false;
+    }
+    status[e] = ok ? -1 : 3;
+    stats[e] = EdgeStatsDev{0, 0, 0, 0, 0, 0};
+    proj_any[e] = 0;
+}
+
+// End of an iteration: at k == max_iters every running edge becomes
+// MAX_ITERS (1); count running edges; k <- k + 1.  One workgroup.
+__global__ void __launch_bounds__(256) k_advance(int* __restrict__ k_dev, int max_iters, int* __restrict__ status,
+                                                 int n_edges, int* __restrict__ active_count) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const int k = *k_dev;
+    int local = 0;
+    for (int e = threadIdx.x; e < n_edges; e += blockDim.x) {
+        if (status[e] < 0) {
+            if (k >= max_iters) status[e] = 1;   // EZO_EDGE_MAX_ITERS
+            else ++local;
+        }
+    }
+    atomicAdd(&cnt, local);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *active_count = cnt;
+        *k_dev = k + 1;
+    }
+}
+
+}  // namespace ezo

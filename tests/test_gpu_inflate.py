@@ -1,0 +1,266 @@
+"""GPU parity of the whole inflation (Alg. 1).
+
+The output polytope has no single correct value (randomised method; FP32 vs
+FP64 decisions may legitimately differ inside the signed-distance band), so:
+
+1. the fused entry point equals, bit for bit, the same algorithm driven step
+   by step through the C ABI, and every step of that driven run is replayed
+   on the oracle from the GPU's own inputs (sampler, flags outside the band,
+   test decision, candidates, bisection outside the band, placed rows);
+2. every returned polytope satisfies the invariants of Alg. 1 (L inside P,
+   P inside D, unit normals) and its status paths (Sec. IV-C);
+3. batched = per-edge calls, bit for bit (same random streams);
+4. status/iteration/face counts agree with full oracle runs on most seeds.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+from gpu_common import BAND, f32_up, load, print_case
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ezo():
+    import paper_2504_10783_amd as ezo
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return ezo
+
+
+@pytest.fixture(scope="module")
+def ctx(ezo):
+    return ezo.Context(0)
+
+
+def params(ezo, name, dof, **kw):
+    p = dict(workloads.PARAMS[name])
+    p.update(kw)
+    return ezo.make_params(dof=dof, **p)
+
+
+def run_fused(ezo, ctx, rob, data, edges, prm):
+    e = torch.from_numpy(np.ascontiguousarray(edges, np.float32)).cuda()
+    obs = torch.from_numpy(data["obstacles"]).cuda()
+    r = ezo.inflate_edges(ctx, rob, obs, e, prm)
+    torch.cuda.synchronize()
+    return (r.A.cpu().numpy(), r.b.cpu().numpy(), r.n_faces.cpu().numpy(), r.status.cpu().numpy(), r.stats)
+
+
+def run_driven(ezo, ctx, rob, data, edge, prm, replay=True):
+    """Alg. 1 on one edge, each step an ezo_* call; replays each step on the
+    oracle.  Returns (A, b, n_faces, status, report)."""
+    dof = rob.dof
+    cap = prm.face_capacity
+    orob = oracle.Robot(workloads.robot(data))
+    obs_np = f32_up(data["obstacles"])
+    v1, v2 = f32_up(edge)
+    box_A, box_b = orob.box()
+    A = torch.zeros((1, cap, dof), dtype=torch.float32, device="cuda")
+    b = torch.zeros((1, cap), dtype=torch.float32, device="cuda")
+    A[0, :2 * dof] = torch.from_numpy(box_A.astype(np.float32)).cuda()
+    b[0, :2 * dof] = torch.from_numpy(box_b.astype(np.float32)).cuda()
+    nf = torch.tensor([2 * dof], dtype=torch.int32, device="cuda")
+    status = torch.tensor([-1], dtype=torch.int32, device="cuda")
+    edges = torch.from_numpy(np.ascontiguousarray(edge[None], np.float32)).cuda()
+    obs = torch.from_numpy(data["obstacles"]).cuda()
+    Mmax, _ = ezo.test_constants(prm.eps, prm.delta, prm.tau, prm.max_iters)
+    stride = (max(prm.n_p, Mmax) + 63) // 64 * 64
+    S = torch.empty((1, dof, stride), dtype=torch.float32, device="cuda")
+    flags = torch.zeros((1, stride), dtype=torch.uint8, device="cuda")
+    ci = torch.empty((1, prm.n_p), dtype=torch.int32, device="cuda")
+    nc = torch.empty(1, dtype=torch.int32, device="cuda")
+    acc = torch.empty(1, dtype=torch.uint8, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int32, device="cuda")
+    cs = torch.empty((1, dof, prm.n_p), dtype=torch.float32, device="cuda")
+    ad = torch.empty((1, dof, prm.n_p), dtype=torch.float32, device="cuda")
+    ts = torch.empty((1, prm.n_p), dtype=torch.float32, device="cuda")
+    pc = torch.empty((1, prm.n_p), dtype=torch.uint8, device="cuda")
+    placed = torch.empty((1, prm.n_f), dtype=torch.int32, device="cuda")
+    npl = torch.empty(1, dtype=torch.int32, device="cuda")
+    rep = dict(iters=0, flag_band=0, bis_decided=0, bis_total=0, sampler_max_err=0.0)
+    for k in range(1, prm.max_iters + 1):
+        M, T = ezo.test_constants(prm.eps, prm.delta, prm.tau, k)
+        nS = max(prm.n_p, M)
+        F = nf.item()
+        Ak = A[0, :F].cpu().numpy()
+        bk = b[0, :F].cpu().numpy()
+        ezo.sample_polytopes(ctx, dof, A, b, nf, edges, nS, prm.n_mix, prm.seed, k, S,
+                             edge_id_base=prm.edge_id_base)
+        ezo.check_collisions(ctx, rob, obs, S[0], flags[0], stride_n=1, stride_d=stride, n=nS)
+        ezo.test_and_select(ctx, flags, nS, M, T, prm.n_p, ci, nc, acc, cnt)
+        torch.cuda.synchronize()
+        rep["iters"] = k
+        Sk = S[0, :, :nS].cpu().numpy().T
+        fk = flags[0, :nS].cpu().numpy()
+        if replay:
+            ref = oracle.hit_and_run(f32_up(Ak), f32_up(bk), v1, v2, prm.n_mix, prm.seed, prm.edge_id_base, k, nS)
+            err = np.abs(f32_up(Sk) - ref).max(axis=1)
+            rep["sampler_max_err"] = max(rep["sampler_max_err"], float(np.quantile(err, 0.99)))
+            assert np.mean(err <= 1e-4) >= 0.99
+            fo, sdo, *_ = oracle.check(orob, obs_np, f32_up(Sk))
+            out = np.abs(sdo) >= BAND
+            rep["flag_band"] += int(np.sum(~out))
+            assert np.array_equal(fk[out], fo[out])
+        c = int(fk[:M].sum())
+        assert cnt.item() == c and acc.item() == (c <= T)
+        if c <= T:
+            status.fill_(ezo.CERTIFIED)
+            break
+        idx = np.nonzero(fk)[0][:prm.n_p]
+        assert nc.item() == len(idx) and np.array_equal(ci[0, :len(idx)].cpu().numpy(), idx)
+        ezo.project_bisect(ctx, rob, obs, edges, S, ci, nc, prm.n_b, cs, ad, ts, pc)
+        torch.cuda.synchronize()
+        n = len(idx)
+        if replay:
+            sel = np.random.default_rng(k).choice(n, min(n, 64), replace=False)
+            for j in sel:
+                o = oracle.bisect_arm(orob, obs_np, v1, v2, f32_up(Sk[idx[j]]), prm.n_b)
+                rep["bis_total"] += 1
+                if o["min_abs_sd"] < BAND:
+                    continue
+                rep["bis_decided"] += 1
+                assert pc[0, j].item() == o["proj_collides"]
+                assert np.abs(cs[0, :, j].cpu().numpy() - o["c_star"]).max() <= 1e-5
+        if pc[0, :n].any():
+            status.fill_(ezo.IN_COLLISION)
+            break
+        F0 = nf.item()
+        ezo.place_hyperplanes(ctx, dof, edges, cs, ad, ts, nc, prm.n_f, prm.step_back_max, prm.t_col, A, b, nf,
+                              status, placed, npl)
+        torch.cuda.synchronize()
+        if replay:
+            csn = cs[0, :, :n].cpu().numpy().T
+            adn = ad[0, :, :n].cpu().numpy().T
+            tsn = ts[0, :n].cpu().numpy()
+            Ao, bo, st, pidx = oracle.place(v1, v2, f32_up(csn), f32_up(adn), f32_up(tsn), prm.n_f,
+                                            prm.step_back_max, prm.t_col, np.zeros((0, dof)), np.zeros(0))
+            kk = npl.item()
+            if st == oracle.IN_COLLISION:
+                assert status.item() == ezo.IN_COLLISION
+            else:
+                assert kk == len(pidx)
+                assert np.array_equal(placed[0, :kk].cpu().numpy(), pidx)
+                assert np.abs(b[0, F0:F0 + kk].cpu().numpy() - bo).max() <= 1e-5
+        if status.item() >= 0:
+            break
+    if status.item() < 0:
+        status.fill_(ezo.MAX_ITERS)
+    return (A.cpu().numpy(), b.cpu().numpy(), nf.cpu().numpy(), status.cpu().numpy(), rep)
+
+
+def check_invariants(A, b, nf, status, data, edges, dof):
+    orob = oracle.Robot(workloads.robot(data))
+    box_A, box_b = orob.box()
+    for e in range(len(nf)):
+        F = int(nf[e])
+        Ae, be = A[e, :F].astype(np.float64), b[e, :F].astype(np.float64)
+        assert np.array_equal(Ae[:2 * dof], box_A) and np.allclose(be[:2 * dof], box_b.astype(np.float32))
+        if status[e] == 3:
+            assert F == 2 * dof
+            continue
+        for v in edges[e].astype(np.float64):
+            assert np.all(Ae @ v <= be + 1e-5)
+        if F > 2 * dof:
+            assert np.abs(np.linalg.norm(Ae[2 * dof:], axis=1) - 1).max() < 1e-5
+
+
+@pytest.mark.parametrize("name", ["tiny", "dof7"])
+def test_fused_equals_driven_steps_and_replays_on_oracle(ezo, ctx, name):
+    print_case("fused vs driven", name)
+    data, desc = load(name)
+    rob = ezo.Robot(ctx, desc)
+    prm = params(ezo, name, desc["dof"], seed=11)
+    Af, bf, nff, stf, stats = run_fused(ezo, ctx, rob, data, data["edges"][:1], prm)
+    Ad, bd, nfd, std, rep = run_driven(ezo, ctx, rob, data, data["edges"][0], prm)
+    print(rep, stats[0])
+    assert std[0] == stf[0] == ezo.CERTIFIED
+    assert nfd[0] == nff[0]
+    F = int(nff[0])
+    assert np.array_equal(Af[0, :F], Ad[0, :F]) and np.array_equal(bf[0, :F], bd[0, :F])
+    assert stats[0]["iterations"] == rep["iters"]
+    assert stats[0]["planes"] == F - 2 * desc["dof"]
+    check_invariants(Af, bf, nff, stf, data, data["edges"][:1], desc["dof"])
+    if rep["bis_total"]:
+        assert rep["bis_decided"] >= 0.9 * rep["bis_total"]
+
+
+def test_status_paths(ezo, ctx):
+    data, desc = load("tiny")
+    rob = ezo.Robot(ctx, desc)
+    orob = oracle.Robot(desc)
+    dof = desc["dof"]
+    qs = np.random.default_rng(3).uniform(-np.pi, np.pi, size=(2000, 3))
+    f, sd, *_ = oracle.check(orob, f32_up(data["obstacles"]), qs)
+    q_bad = qs[np.argmin(sd)]
+    bad_edge = np.stack([np.clip(q_bad - 0.2, -3.1, 3.1), np.clip(q_bad + 0.2, -3.1, 3.1)])
+    outside = data["edges"][0].copy()
+    outside[1, 0] = 4.0
+    nan_edge = data["edges"][0].copy()
+    nan_edge[0, 1] = np.nan
+    edges = np.stack([data["edges"][0], bad_edge, outside, nan_edge]).astype(np.float32)
+    prm = params(ezo, "tiny", dof, seed=2)
+    A, b, nf, st, stats = run_fused(ezo, ctx, rob, data, edges, prm)
+    print_case("status", st, [s["iterations"] for s in stats])
+    assert list(st) == [ezo.CERTIFIED, ezo.IN_COLLISION, ezo.INVALID, ezo.INVALID]
+    assert nf[2] == nf[3] == 2 * dof
+    check_invariants(A, b, nf, st, data, edges, dof)
+    prm1 = params(ezo, "tiny", dof, seed=2, max_iters=1)
+    A, b, nf, st, stats = run_fused(ezo, ctx, rob, data, edges[:1], prm1)
+    assert st[0] == ezo.MAX_ITERS and stats[0]["iterations"] == 1
+    check_invariants(A, b, nf, st, data, edges[:1], dof)
+    small = params(ezo, "tiny", dof, seed=2, face_capacity=2 * dof + 10)
+    with pytest.raises(ezo.EzoError) as ei:
+        run_fused(ezo, ctx, rob, data, edges[:1], small)
+    assert ei.value.code == ezo.EZO_E_CAPACITY
+
+
+def test_batched_equals_per_edge_calls(ezo, ctx):
+    data, desc = load("batched")
+    rob = ezo.Robot(ctx, desc)
+    dof = desc["dof"]
+    prm = params(ezo, "batched", dof, seed=5)
+    print_case("batched 96 edges")
+    A, b, nf, st, stats = run_fused(ezo, ctx, rob, data, data["edges"], prm)
+    print("status counts", np.bincount(st, minlength=4), "faces", nf.min(), nf.max())
+    check_invariants(A, b, nf, st, data, data["edges"], dof)
+    assert np.mean(st == ezo.CERTIFIED) >= 0.9
+    for e in (0, 17, 95):
+        p1 = params(ezo, "batched", dof, seed=5, edge_id_base=e)
+        A1, b1, nf1, st1, _ = run_fused(ezo, ctx, rob, data, data["edges"][e:e + 1], p1)
+        assert st1[0] == st[e] and nf1[0] == nf[e]
+        F = int(nf[e])
+        assert np.array_equal(A1[0, :F], A[e, :F]) and np.array_equal(b1[0, :F], b[e, :F])
+
+
+def test_deterministic_repeat(ezo, ctx):
+    data, desc = load("dof7")
+    rob = ezo.Robot(ctx, desc)
+    prm = params(ezo, "dof7", desc["dof"], seed=4)
+    r1 = run_fused(ezo, ctx, rob, data, data["edges"], prm)
+    r2 = run_fused(ezo, ctx, rob, data, data["edges"], prm)
+    F = int(r1[2][0])
+    assert r1[2][0] == r2[2][0] and np.array_equal(r1[0][0, :F], r2[0][0, :F])
+
+
+def test_full_runs_agree_with_oracle_statistically(ezo, ctx):
+    data, desc = load("tiny")
+    rob = ezo.Robot(ctx, desc)
+    orob = oracle.Robot(desc)
+    v1, v2 = f32_up(data["edges"][0])
+    same_iters, same_faces, n = 0, 0, 12
+    for seed in range(n):
+        prm = params(ezo, "tiny", desc["dof"], seed=seed)
+        A, b, nf, st, stats = run_fused(ezo, ctx, rob, data, data["edges"][:1], prm)
+        o = oracle.eizo_arm(orob, f32_up(data["obstacles"]), v1, v2,
+                            oracle.make_params(**workloads.PARAMS["tiny"], seed=seed))
+        assert st[0] == o["status"]
+        same_iters += stats[0]["iterations"] == o["stats"]["iterations"]
+        if nf[0] == len(o["b"]):
+            same_faces += 1
+            assert np.abs(A[0, :nf[0]] - o["A"]).max() < 1e-3
+    print(f"same iterations {same_iters}/{n}, same faces {same_faces}/{n}")
+    assert same_iters >= 0.75 * n and same_faces >= 0.75 * n

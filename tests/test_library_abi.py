@@ -1,0 +1,62 @@
+"""CPU-only checks of the C ABI: the library loads, exports every entry point
+declared in include/ezo.h, and its host-side helpers agree with the oracle.
+No compute call is made here (no GPU in this environment)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ezo.h")
+
+
+@pytest.fixture(scope="module")
+def ezo():
+    import paper_2504_10783_amd as ezo
+    if not os.path.exists(ezo.LIB_PATH):
+        from paper_2504_10783_amd import build
+        build.build()
+    ezo.lib()
+    return ezo
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ezo_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("ezo_check_collisions", "ezo_inflate_edges", "ezo_ctx_create", "ezo_robot_create",
+              "ezo_sample_polytopes", "ezo_project_bisect", "ezo_place_hyperplanes", "ezo_test_and_select"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(ezo):
+    out = subprocess.check_output(["nm", "-D", "--defined-only", ezo.LIB_PATH], text=True)
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    assert set(ezo.EXPORTS) <= set(declared_functions())
+
+
+def test_library_carries_gfx950_code_object(ezo):
+    blob = open(ezo.LIB_PATH, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in blob
+
+
+def test_test_constants_match_oracle(ezo):
+    for eps, delta, tau in ((0.1, 0.05, 0.5), (0.05, 0.05, 0.5), (0.005, 0.005, 0.5), (0.01, 0.05, 0.3)):
+        for k in range(1, 60):
+            assert ezo.test_constants(eps, delta, tau, k) == oracle.test_constants(eps, delta, tau, k)
+
+
+def test_test_constants_reject_bad_arguments(ezo):
+    with pytest.raises(ezo.EzoError):
+        ezo.test_constants(0.0, 0.05, 0.5, 1)
+    with pytest.raises(ezo.EzoError):
+        ezo.test_constants(0.1, 0.05, 0.5, 0)
