@@ -254,9 +254,10 @@ enum {
 };
 
 /* Enables (1) or disables (0) per-phase GPU timing of ezo_inflate_edges on
- * this context: hipEvents are recorded between the phases of every iteration
- * on the stream the kernels run on, and their elapsed times accumulate.
- * Enabling resets the totals.  Timing adds a few microseconds per iteration. */
+ * this context.  While enabled, the iteration's kernels are launched directly
+ * (not through the replayed hipGraph) with hipEvents recorded between the
+ * phases on the stream the kernels run on, and the elapsed times accumulate.
+ * Results are identical either way.  Enabling resets the totals. */
 ezo_status ezo_set_phase_timing(ezo_ctx *ctx, int32_t enable);
 
 /* Cumulative per-phase kernel time (ms_out[EZO_NUM_PHASES], host) and the

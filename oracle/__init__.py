@@ -87,10 +87,10 @@ def _declare(L):
     L.orc_hit_and_run.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, C.c_int32, C.c_uint64,
                                   C.c_uint32, C.c_uint32, C.c_int64, _dp]
     L.orc_project.argtypes = [C.c_int32, _dp, _dp, _dp, _dp, _dp]
-    L.orc_bisect_arm.argtypes = [rp, _dp, C.c_int32, _dp, _dp, _dp, C.c_int32, _dp, _dp, _dp, _dp, _dp]
+    L.orc_bisect_arm.argtypes = [rp, _dp, C.c_int32, _dp, _dp, _dp, C.c_int32, _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_bisect_arm.restype = C.c_int
     L.orc_bisect_balls.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, _dp, C.c_int32,
-                                   _dp, _dp, _dp, _dp, _dp]
+                                   _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_bisect_balls.restype = C.c_int
     L.orc_place.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, _dp, C.c_int32, C.c_double,
                             C.c_double, _dp, _dp, _ip, C.c_int32, _ip, _ip]
@@ -224,11 +224,12 @@ def bisect_arm(robot: Robot, obs, v1, v2, c, n_b):
     v1, v2, c = _d(v1), _d(v2), _d(c)
     d = robot.dof
     cs, ad, cp = np.empty(d), np.empty(d), np.empty(d)
+    tr = np.empty(int(n_b) + 1)
     t, m = C.c_double(), C.c_double()
     p = lib().orc_bisect_arm(robot.ref, _ptr(obs), obs.shape[0], _ptr(v1), _ptr(v2), _ptr(c),
-                             int(n_b), _ptr(cs), C.byref(t), _ptr(ad), _ptr(cp), C.byref(m))
+                             int(n_b), _ptr(cs), C.byref(t), _ptr(ad), _ptr(cp), C.byref(m), _ptr(tr))
     return dict(proj_collides=bool(p), c_star=cs, t_star=t.value, a=ad, c_proj=cp,
-                min_abs_sd=m.value)
+                min_abs_sd=m.value, sd_trace=tr)
 
 
 def bisect_balls(centres, radii, v1, v2, c, n_b):
@@ -236,12 +237,13 @@ def bisect_balls(centres, radii, v1, v2, c, n_b):
     dim = centres.shape[1]
     v1, v2, c = _d(v1), _d(v2), _d(c)
     cs, ad, cp = np.empty(dim), np.empty(dim), np.empty(dim)
+    tr = np.empty(int(n_b) + 1)
     t, m = C.c_double(), C.c_double()
     p = lib().orc_bisect_balls(dim, _ptr(centres), _ptr(radii), len(radii), _ptr(v1), _ptr(v2),
                                _ptr(c), int(n_b), _ptr(cs), C.byref(t), _ptr(ad), _ptr(cp),
-                               C.byref(m))
+                               C.byref(m), _ptr(tr))
     return dict(proj_collides=bool(p), c_star=cs, t_star=t.value, a=ad, c_proj=cp,
-                min_abs_sd=m.value)
+                min_abs_sd=m.value, sd_trace=tr)
 
 
 def place(v1, v2, c_star, a_dir, t_star, n_f, step_back_max, t_col, A, b, cap=None):

@@ -340,12 +340,14 @@ void orc_project(int32_t d, const double *v1, const double *v2, const double *c,
  * collision (fail-fast), then n_b bisection steps on the segment
  * [c_proj, c] keeping the colliding end: mid = (lo + hi)/2, hi = mid if mid
  * collides else lo = mid.  c* = hi, t* = |c* - c_proj|.  Also reports the
- * smallest |sd| met at any evaluated point (projection and midpoints), so a
- * caller can tell when a lower-precision evaluation may legitimately decide
- * differently.  Returns 1 if c_proj collides. */
+ * smallest |sd| met at any evaluated point (projection and midpoints), and
+ * optionally every evaluated signed distance (sd_trace[0] = projection,
+ * sd_trace[1 + i] = midpoint of step i), so a caller can tell where a
+ * lower-precision evaluation may legitimately decide differently.  Returns 1
+ * if c_proj collides. */
 int orc_bisect(const void *scene, orc_sd_fn sd, int32_t d, const double *v1, const double *v2,
                const double *c, int32_t n_b, double *c_star, double *t_star, double *a_dir,
-               double *c_proj_out, double *min_abs_sd) {
+               double *c_proj_out, double *min_abs_sd, double *sd_trace) {
     double cp[64], lo[64], hi[64], mid[64];
     orc_project(d, v1, v2, c, cp, NULL);
     double nrm = 0.0;
@@ -354,11 +356,13 @@ int orc_bisect(const void *scene, orc_sd_fn sd, int32_t d, const double *v1, con
     for (int j = 0; j < d; ++j) a_dir[j] = nrm > 0.0 ? (c[j] - cp[j]) / nrm : 0.0;
     double sp = sd(scene, cp);
     double mabs = fabs(sp);
+    if (sd_trace) sd_trace[0] = sp;
     int proj_col = sp < 0.0;
     for (int j = 0; j < d; ++j) { lo[j] = cp[j]; hi[j] = c[j]; }
     for (int it = 0; it < n_b; ++it) {
         for (int j = 0; j < d; ++j) mid[j] = 0.5 * (lo[j] + hi[j]);
         double sm = sd(scene, mid);
+        if (sd_trace) sd_trace[1 + it] = sm;
         if (fabs(sm) < mabs) mabs = fabs(sm);
         if (sm < 0.0) memcpy(hi, mid, sizeof(double) * d);
         else memcpy(lo, mid, sizeof(double) * d);
@@ -517,7 +521,7 @@ int orc_eizo(const void *scene, orc_sd_fn sd, int32_t d, const double *A_D, cons
 #pragma omp parallel for schedule(dynamic, 4) reduction(| : any_proj)
         for (int j = 0; j < nc; ++j) {
             int p = orc_bisect(scene, sd, d, v1, v2, S + (size_t)cand[j] * d, prm->n_b, cs + (size_t)j * d,
-                               ts + j, ad + (size_t)j * d, NULL, NULL);
+                               ts + j, ad + (size_t)j * d, NULL, NULL, NULL);
             pc[j] = (uint8_t)p;
             any_proj |= p;
         }
@@ -552,17 +556,19 @@ int orc_eizo_balls(int32_t dim, const double *centres, const double *radii, int3
 
 int orc_bisect_arm(const orc_robot *rb, const double *obs, int32_t n_obs, const double *v1,
                    const double *v2, const double *c, int32_t n_b, double *c_star, double *t_star,
-                   double *a_dir, double *c_proj, double *min_abs_sd) {
+                   double *a_dir, double *c_proj, double *min_abs_sd, double *sd_trace) {
     orc_arm_scene sc = {rb, obs, n_obs};
-    return orc_bisect(&sc, orc_arm_sd, rb->dof, v1, v2, c, n_b, c_star, t_star, a_dir, c_proj, min_abs_sd);
+    return orc_bisect(&sc, orc_arm_sd, rb->dof, v1, v2, c, n_b, c_star, t_star, a_dir, c_proj, min_abs_sd,
+                      sd_trace);
 }
 
 int orc_bisect_balls(int32_t dim, const double *centres, const double *radii, int32_t n,
                      const double *v1, const double *v2, const double *c, int32_t n_b,
                      double *c_star, double *t_star, double *a_dir, double *c_proj,
-                     double *min_abs_sd) {
+                     double *min_abs_sd, double *sd_trace) {
     orc_ball_scene sc = {dim, centres, radii, n};
-    return orc_bisect(&sc, orc_ball_sd, dim, v1, v2, c, n_b, c_star, t_star, a_dir, c_proj, min_abs_sd);
+    return orc_bisect(&sc, orc_ball_sd, dim, v1, v2, c, n_b, c_star, t_star, a_dir, c_proj, min_abs_sd,
+                      sd_trace);
 }
 
 /* Threads used by the OpenMP loops above (0 = runtime default). */

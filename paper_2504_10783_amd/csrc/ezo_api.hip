@@ -578,34 +578,34 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
     const uint32_t k0 = (uint32_t)p->seed, k1 = (uint32_t)(p->seed >> 32);
     (void)k0;
     (void)k1;
-    // ---- capture one iteration ----
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    ezo_status cs = EZO_OK;
-    auto mark = [&](int i) {
-        if (c->timing && cs == EZO_OK) {
-            hipError_t me = hipEventRecord(c->tev[i], st);
-            if (me != hipSuccess) cs = fail(c, EZO_E_HIP, "event record failed: %s", hipGetErrorString(me));
-        }
-    };
-    do {
+    // ---- one iteration: six kernels on the internal stream ----
+    // Normal mode: captured once into a hipGraph and replayed.  Timing mode:
+    // launched directly with hipEvents recorded between the phases (event
+    // records inside a captured graph do not time the kernels).
+    auto launch_iteration = [&](bool marks) -> ezo_status {
+        ezo_status ls = EZO_OK;
+        auto mark = [&](int i) {
+            if (marks && ls == EZO_OK) {
+                hipError_t me = hipEventRecord(c->tev[i], st);
+                if (me != hipSuccess) ls = fail(c, EZO_E_HIP, "event record failed: %s", hipGetErrorString(me));
+            }
+        };
         mark(EZO_PHASE_SAMPLE);
-        if ((cs = launch_sample(c, dof, A, b, n_faces, cap, edges, E, S_cap, p->n_mix, p->seed, p->edge_id_base,
+        if ((ls = launch_sample(c, dof, A, b, n_faces, cap, edges, E, S_cap, p->n_mix, p->seed, p->edge_id_base,
                                 (float*)w_s, stride, edge_status, it, st)))
-            break;
+            return ls;
         mark(EZO_PHASE_CHECK);
-        if ((cs = launch_check<false>(c, r, ov, (const float*)w_s, S_cap, 1, stride, (int64_t)dof * stride,
+        if ((ls = launch_check<false>(c, r, ov, (const float*)w_s, S_cap, 1, stride, (int64_t)dof * stride,
                                       (uint8_t*)w_f, nullptr, nullptr, stride, E, edge_status, it, st)))
-            break;
+            return ls;
         mark(EZO_PHASE_TEST);
         hipLaunchKernelGGL(k_test_select, dim3(E), dim3(1024), 0, st, (const uint8_t*)w_f, stride, p->n_p, p->n_b,
                            (int*)w_ci, cand_cap, (int*)w_nc, nullptr, nullptr, edge_status, (EdgeStatsDev*)w_st, it);
         mark(EZO_PHASE_BISECT);
-        if ((cs = launch_project_bisect(c, r, ov, edges, E, (const float*)w_s, stride, (const int*)w_ci,
+        if ((ls = launch_project_bisect(c, r, ov, edges, E, (const float*)w_s, stride, (const int*)w_ci,
                                         (const int*)w_nc, cand_cap, p->n_b, (float*)w_cs, (float*)w_ad,
                                         (float*)w_ts, (uint8_t*)w_pc, (uint8_t*)w_pa, edge_status, st)))
-            break;
+            return ls;
         mark(EZO_PHASE_PLACE);
         hipLaunchKernelGGL(k_place, dim3(E), dim3(1024), (size_t)std::max(cand_cap, 16), st, dof, edges,
                            (const float*)w_cs, (const float*)w_ad, (const float*)w_ts, (const int*)w_nc, cand_cap,
@@ -614,20 +614,36 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
         mark(EZO_PHASE_ADVANCE);
         hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, st, (int*)w_k, p->max_iters, edge_status, E, (int*)w_ac);
         mark(EZO_NUM_PHASES);
-    } while (0);
-    hipError_t ce = hipStreamEndCapture(st, &graph);
-    if (cs) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return cs;
-    }
-    if (ce != hipSuccess) return fail(c, EZO_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
-    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        return fail(c, EZO_E_HIP, "graph instantiation failed");
+        if (ls == EZO_OK) {
+            hipError_t le = hipGetLastError();
+            if (le != hipSuccess) ls = fail(c, EZO_E_HIP, "kernel launch failed: %s", hipGetErrorString(le));
+        }
+        return ls;
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (!c->timing) {
+        HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        ezo_status cs = launch_iteration(false);
+        hipError_t ce = hipStreamEndCapture(st, &graph);
+        if (cs) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return cs;
+        }
+        if (ce != hipSuccess) return fail(c, EZO_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(c, EZO_E_HIP, "graph instantiation failed");
+        }
     }
     ezo_status result = EZO_OK;
     for (int k = 1; k <= p->max_iters; ++k) {
-        hipError_t e1 = hipGraphLaunch(exec, st);
+        hipError_t e1 = hipSuccess;
+        if (exec) {
+            e1 = hipGraphLaunch(exec, st);
+        } else if ((result = launch_iteration(true))) {
+            break;
+        }
         hipError_t e2 = hipMemcpyAsync(c->pinned, w_ac, sizeof(int), hipMemcpyDeviceToHost, st);
         hipError_t e3 = hipStreamSynchronize(st);
         if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
@@ -635,7 +651,7 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
                           hipGetErrorString(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3)));
             break;
         }
-        if (c->timing) {
+        if (!exec) {
             for (int ph = 0; ph < EZO_NUM_PHASES; ++ph) {
                 float ms = 0.f;
                 if (hipEventElapsedTime(&ms, c->tev[ph], c->tev[ph + 1]) == hipSuccess) c->phase_ms[ph] += ms;
@@ -644,8 +660,8 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
         }
         if (c->pinned[0] == 0) break;
     }
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (result) return result;
     if (stats) {
         std::vector<EdgeStatsDev> hs(E);

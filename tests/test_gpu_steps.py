@@ -14,7 +14,7 @@ import oracle
 import workloads
 from workloads import draw
 
-from gpu_common import BAND, f32_up, load, print_case
+from gpu_common import BAND, bisection_agreement, f32_up, load, print_case, sampler_agreement
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -67,14 +67,10 @@ def test_sampler_parity(ezo, ctx, name, iters, n_mix):
     got = S[0, :, :n].cpu().numpy().T.astype(np.float64)
     v1, v2 = f32_up(data["edges"][0])
     ref = oracle.hit_and_run(f32_up(A), f32_up(b), v1, v2, n_mix, 7, 5, 3, n)
-    err = np.abs(got - ref).max(axis=1)
-    print(f"sampler error: median {np.median(err):.2e}, p99 {np.quantile(err, 0.99):.2e}, max {err.max():.2e}")
-    assert np.all(got @ f32_up(A).T <= f32_up(b) + 1e-4)        # every sample in P
     if n_mix == 0:
-        assert err.max() <= 1e-6
+        assert np.abs(got - ref).max() <= 1e-6
     else:
-        assert np.mean(err <= 1e-4) >= 0.99
-        assert np.median(err) <= 1e-5
+        sampler_agreement(got, ref, f32_up(A), f32_up(b), f"{name} k={iters}")
 
 
 def test_test_and_select_bit_exact(ezo, ctx):
@@ -137,18 +133,15 @@ def test_project_bisect_parity(ezo, ctx, name, n):
     cs, ad, ts, pc = (x.cpu().numpy() for x in (cs, ad, ts, pc))
     orob = oracle.Robot(desc)
     v1, v2 = f32_up(data["edges"][0])
-    decided = 0
+    steps = []
     for j in range(n):
         o = oracle.bisect_arm(orob, f32_up(data["obstacles"]), v1, v2, f32_up(cand[j]), 11)
         assert np.abs(ad[0, :, j] - o["a"]).max() <= 1e-5
-        if o["min_abs_sd"] < BAND:
-            continue
-        decided += 1
-        assert pc[0, j] == o["proj_collides"]
-        assert np.abs(cs[0, :, j] - o["c_star"]).max() <= 1e-5
-        assert abs(ts[0, j] - o["t_star"]) <= 1e-5
-    print(f"decided outside the band: {decided} of {n}")
-    assert decided >= 0.95 * n
+        steps.append(bisection_agreement(cs[0, :, j], ts[0, j], pc[0, j], o, f32_up(cand[j])))
+    steps = np.array(steps)
+    print(f"bisection steps decided outside the band: mean {steps.mean():.2f} of 11; "
+          f"all 11 for {np.mean(steps == 11):.2f} of candidates")
+    assert np.mean(steps >= 8) >= 0.9
 
 
 def synthetic_candidates(rng, dof, n):
