@@ -185,15 +185,20 @@ ezo_status launch_sample(ezo_ctx* c, int dof, const float* A, const float* b, co
     const int D = dof <= 4 ? 4 : 8;
     const size_t lds = sizeof(float) * (size_t)cap * (D + 1);
     if (lds > c->lds_cap) return fail(c, EZO_E_UNSUPPORTED, "face capacity %d too large for the sampler", cap);
-    dim3 grid((unsigned)((max_samples + 255) / 256), (unsigned)E), block(256);
     if (max_samples <= 0 || E <= 0) return EZO_OK;
+    // lanes per walk: 8 when walks are few (fill the chip), else 4
+    const int L = ((int64_t)max_samples * E * 8 <= 64LL * 4 * 4 * kNumCU * 64) ? 8 : 4;
+    const int64_t threads = (int64_t)max_samples * L;
+    dim3 grid((unsigned)((threads + 255) / 256), (unsigned)E), block(256);
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    if (D == 4)
-        hipLaunchKernelGGL(k_sample<4>, grid, block, lds, st, dof, A, b, n_faces, cap, edges, k0, k1, eid0, n_mix, S,
-                           stride, status, it);
-    else
-        hipLaunchKernelGGL(k_sample<8>, grid, block, lds, st, dof, A, b, n_faces, cap, edges, k0, k1, eid0, n_mix, S,
-                           stride, status, it);
+#define EZO_LAUNCH_SAMPLE(DD, LL)                                                                                 \
+    hipLaunchKernelGGL((k_sample<DD, LL>), grid, block, lds, st, dof, A, b, n_faces, cap, edges, k0, k1, eid0, n_mix, \
+                       S, stride, status, it)
+    if (D == 4 && L == 8) EZO_LAUNCH_SAMPLE(4, 8);
+    else if (D == 4) EZO_LAUNCH_SAMPLE(4, 4);
+    else if (L == 8) EZO_LAUNCH_SAMPLE(8, 8);
+    else EZO_LAUNCH_SAMPLE(8, 4);
+#undef EZO_LAUNCH_SAMPLE
     HIP_TRY(c, hipGetLastError());
     return EZO_OK;
 }

@@ -145,15 +145,21 @@ __global__ void __launch_bounds__(256) k_centres(RobotView rb, ObsView ob, const
 }
 
 // ---------------------------------------------------------------------------
-// Hit-and-run sampler: one thread per walk, polytope rows of the edge in LDS.
-// blockIdx.y = edge.  Rows stored as [F][D] normals plus b[F].
+// Hit-and-run sampler.  A walk is carried by a group of L lanes (L in {4, 8})
+// that all hold its position x and direction u; per step, lane m < #calls
+// computes Philox call m, lane m < #pairs computes Box-Muller pair m, and the
+// words and normals are exchanged by shuffles; the polytope rows (LDS, shared
+// by the workgroup's walks, all from one edge = blockIdx.y) are split over
+// the L lanes and the chord ends are reduced with shuffle min/max.
+// Rows stored as [F][D] normals plus b[F].
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, int L>
 __global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict__ A, const float* __restrict__ bvec,
                                                 const int* __restrict__ n_faces, int cap,
                                                 const float* __restrict__ edges, uint32_t key0, uint32_t key1,
                                                 int64_t edge_id_base, int n_mix, float* __restrict__ S,
                                                 int64_t stride, const int* __restrict__ status, IterArgs it) {
+    static_assert(L == 4 || L == 8, "lanes per walk");
     extern __shared__ __align__(16) char smem[];
     const int e = blockIdx.y;
     if (!edge_running(status, e)) return;
@@ -168,57 +174,61 @@ __global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict
     }
     for (int f = threadIdx.x; f < F; f += blockDim.x) rowb[f] = bvec[(size_t)e * cap + f];
     __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= iv.nS) return;
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & (L - 1);                       // position in the walk's lane group
+    const int g0 = lane - sub;                            // first lane of the group
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / L;
+    // A group past the end still runs (its lanes feed no shuffles of others)
+    // but stores nothing; groups never straddle walks.
+    const bool live = i < iv.nS;
     const float* v = edges + (size_t)e * 2 * dof;
     const uint32_t eid = (uint32_t)(edge_id_base + e);
+    const uint32_t ii = (uint32_t)i, kk = (uint32_t)iv.k;
     float x[D], u[D];
     {
-        const U4 r = philox4x32_10(U4{(uint32_t)i, eid, (uint32_t)iv.k, 0u}, key0, key1);
+        const U4 r = philox4x32_10(U4{ii, eid, kk, 0u}, key0, key1);
         const float w0 = u01(r.x);
 #pragma unroll
         for (int j = 0; j < D; ++j) x[j] = j < dof ? fmaf(w0, v[dof + j] - v[j], v[j]) : 0.f;
     }
-    const int npair = (dof + 1) >> 1;
+    const int npair = (dof + 1) >> 1;                     // Box-Muller pairs (<= 4 <= L)
+    const int tword = 2 * npair;                          // word holding the chord position
+    const int ncall = (tword + 4) >> 2;                   // Philox calls per step (<= 3 <= L)
     for (int s = 1; s <= n_mix; ++s) {
-        // words 0 .. 2*npair-1: Box-Muller pairs; word 2*npair: position on the chord
-        float g[D + 1];
-        float wt = 0.5f;
-        U4 r = philox4x32_10(U4{(uint32_t)i, eid, (uint32_t)iv.k, 16u * (uint32_t)s}, key0, key1);
-        int call = 0;
-#pragma unroll
-        for (int m = 0; m < (D + 1) / 2; ++m) {
-            if (m < npair) {
-                const int w = 2 * m;
-                if (w / 4 != call) {
-                    call = w / 4;
-                    r = philox4x32_10(U4{(uint32_t)i, eid, (uint32_t)iv.k, 16u * (uint32_t)s + (uint32_t)call}, key0, key1);
-                }
-                const float ua = u01(word_of(r, w % 4));
-                const float ub = u01(word_of(r, (w + 1) % 4));
-                const float rad = sqrtf(-2.f * logf(ua));
-                float sn, cs;
-                sincospif(2.f * ub, &sn, &cs);
-                g[2 * m] = rad * cs;
-                if (2 * m + 1 < D + 1) g[2 * m + 1] = rad * sn;
-            }
-        }
-        {
-            const int w = 2 * npair;
-            if (w / 4 != call) {
-                call = w / 4;
-                r = philox4x32_10(U4{(uint32_t)i, eid, (uint32_t)iv.k, 16u * (uint32_t)s + (uint32_t)call}, key0, key1);
-            }
-            wt = u01(word_of(r, w % 4));
-        }
+        // Philox call `sub` of this step (lanes sub >= ncall compute a spare call)
+        const U4 r = philox4x32_10(U4{ii, eid, kk, 16u * (uint32_t)s + (uint32_t)(sub < ncall ? sub : 0)}, key0, key1);
+        // Box-Muller pair m = sub uses words 2m, 2m+1 = call m/2, components 2(m%2), 2(m%2)+1
+        const int src = g0 + (sub >> 1);
+        const uint32_t wx = __shfl((int)r.x, src), wy = __shfl((int)r.y, src);
+        const uint32_t wz = __shfl((int)r.z, src), ww = __shfl((int)r.w, src);
+        const bool hi = (sub & 1) != 0;
+        const float ua = u01(hi ? wz : wx);
+        const float ub = u01(hi ? ww : wy);
+        const float rad = sqrtf(-2.f * logf(ua));
+        float sn, cs;
+        sincospif(2.f * ub, &sn, &cs);
+        const float g_even = rad * cs, g_odd = rad * sn;
         float nrm = 0.f;
 #pragma unroll
-        for (int j = 0; j < D; ++j) nrm = j < dof ? fmaf(g[j], g[j], nrm) : nrm;
+        for (int m = 0; m < (D + 1) / 2; ++m) {
+            const float ge = __shfl(g_even, g0 + m);
+            const float go = __shfl(g_odd, g0 + m);
+            if (2 * m < D) u[2 * m] = (2 * m < dof) ? ge : 0.f;
+            if (2 * m + 1 < D) u[2 * m + 1] = (2 * m + 1 < dof) ? go : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j) nrm = fmaf(u[j], u[j], nrm);
         const float inv = 1.0f / sqrtf(nrm);
 #pragma unroll
-        for (int j = 0; j < D; ++j) u[j] = j < dof ? g[j] * inv : 0.f;
+        for (int j = 0; j < D; ++j) u[j] *= inv;
+        // chord position word: call tword/4, component tword%4
+        const int tsrc = g0 + (tword >> 2);
+        const uint32_t t0 = __shfl((int)r.x, tsrc), t1 = __shfl((int)r.y, tsrc);
+        const uint32_t t2 = __shfl((int)r.z, tsrc), t3 = __shfl((int)r.w, tsrc);
+        const int tc = tword & 3;
+        const float wt = u01(tc == 0 ? t0 : (tc == 1 ? t1 : (tc == 2 ? t2 : t3)));
         float tlo = -INFINITY, thi = INFINITY;
-        for (int f = 0; f < F; ++f) {
+        for (int f = sub; f < F; f += L) {
             float den = 0.f, ax = 0.f;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
@@ -230,13 +240,21 @@ __global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict
             if (den > 0.f) thi = fminf(thi, tt);
             else if (den < 0.f) tlo = fmaxf(tlo, tt);
         }
+#pragma unroll
+        for (int off = 1; off < L; off <<= 1) {
+            thi = fminf(thi, __shfl_xor(thi, off));
+            tlo = fmaxf(tlo, __shfl_xor(tlo, off));
+        }
         float tm = 0.f;
         if (thi >= tlo && tlo > -INFINITY && thi < INFINITY) tm = fmaf(wt, thi - tlo, tlo);
 #pragma unroll
         for (int j = 0; j < D; ++j) x[j] = fmaf(tm, u[j], x[j]);
     }
-    float* Se = S + (size_t)e * dof * stride;
-    for (int j = 0; j < dof; ++j) Se[(size_t)j * stride + i] = x[j];
+    if (live) {
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            if (j < dof && (j % L) == sub) S[((size_t)e * dof + j) * stride + i] = x[j];
+    }
 }
 
 // ---------------------------------------------------------------------------
