@@ -260,9 +260,13 @@ enum {
  * Results are identical either way.  Enabling resets the totals. */
 ezo_status ezo_set_phase_timing(ezo_ctx *ctx, int32_t enable);
 
-/* Cumulative per-phase kernel time (ms_out[EZO_NUM_PHASES], host) and the
- * number of timed iterations (iterations_out, host) since timing was enabled. */
-ezo_status ezo_get_phase_timing(const ezo_ctx *ctx, double *ms_out, int64_t *iterations_out);
+/* Cumulative per-phase kernel time (ms_out[EZO_NUM_PHASES], host), the
+ * number of timed iterations (iterations_out, host, may be NULL) and the
+ * number of sphere-sphere tests the collision-check phases performed
+ * (tests_out[EZO_NUM_PHASES], host, may be NULL; bound tests of the broad
+ * phase included, pairs it proved separated excluded) since timing was
+ * enabled.  Synchronises the context's stream when tests_out is given. */
+ezo_status ezo_get_phase_timing(ezo_ctx *ctx, double *ms_out, int64_t *iterations_out, int64_t *tests_out);
 
 #ifdef __cplusplus
 }

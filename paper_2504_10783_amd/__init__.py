@@ -86,7 +86,7 @@ def lib():
         L.ezo_inflate_edges.argtypes = [vp, vp, vp, i32, vp, i32, C.POINTER(Params), vp, vp, vp, vp,
                                         C.POINTER(EdgeStats), vp]
         L.ezo_set_phase_timing.argtypes = [vp, i32]
-        L.ezo_get_phase_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
+        L.ezo_get_phase_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(i64)]
         for name in EXPORTS:
             fn = getattr(L, name)
             if fn.restype is C.c_int:
@@ -157,12 +157,17 @@ class Context:
         """Per-phase GPU timing of inflate_edges (hipEvents on the kernels' stream)."""
         self._check(lib().ezo_set_phase_timing(self.h, 1 if enable else 0))
 
-    def phase_timing(self):
-        """(dict phase -> cumulative ms, timed iterations) since timing was enabled."""
+    def phase_timing(self, with_tests=False):
+        """(dict phase -> cumulative ms, timed iterations[, dict phase ->
+        sphere-sphere tests]) since timing was enabled."""
         ms = (C.c_double * len(PHASES))()
+        tests = (C.c_int64 * len(PHASES))()
         it = C.c_int64()
-        self._check(lib().ezo_get_phase_timing(self.h, ms, C.byref(it)))
-        return {p: ms[i] for i, p in enumerate(PHASES)}, it.value
+        self._check(lib().ezo_get_phase_timing(self.h, ms, C.byref(it), tests if with_tests else None))
+        out = ({p: ms[i] for i, p in enumerate(PHASES)}, it.value)
+        if with_tests:
+            out = out + ({p: tests[i] for i, p in enumerate(PHASES)},)
+        return out
 
     def _check(self, rc):
         if rc:

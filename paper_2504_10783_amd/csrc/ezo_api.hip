@@ -41,11 +41,13 @@ struct ezo_ctx {
     hipEvent_t tev[EZO_NUM_PHASES + 1] = {};
     double phase_ms[EZO_NUM_PHASES] = {};
     int64_t timed_iters = 0;
+    unsigned long long* d_tests = nullptr;   // [EZO_NUM_PHASES] sphere-sphere tests per phase
 };
 
 struct ezo_robot {
     ezo_ctx* ctx = nullptr;
     int dof = 0, S = 0, P = 0;
+    float r_max = 0.f;                 // largest sphere radius
     void* buf = nullptr;               // one device allocation holding everything below
     RobotView view{};
     const int* sorted_to_orig = nullptr;
@@ -58,7 +60,7 @@ static std::string g_create_err;
 namespace {
 
 enum Slot {
-    W_OBS_REC, W_OBS_CENTRE, W_SAMPLES, W_FLAGS, W_CAND, W_NCAND, W_CSTAR, W_ADIR, W_TSTAR, W_PCOL,
+    W_OBS_REC, W_OBS_CENTRE, W_GRID_GEOM, W_GRID_COUNT, W_GRID_LIST, W_SAMPLES, W_FLAGS, W_CAND, W_NCAND, W_CSTAR, W_ADIR, W_TSTAR, W_PCOL,
     W_PANY, W_STATS, W_TABLE, W_KDEV, W_ACTIVE, W_NSLOTS
 };
 
@@ -131,31 +133,46 @@ int pick_W(int n_obs) {
     return 2;
 }
 
-ObsView obs_view(const ezo_robot* r, ezo_ctx* c, int n_obs, void* rec, void* centre) {
-    ObsView o;
-    o.n = n_obs;
-    o.rec = reinterpret_cast<const float4*>(rec);
-    o.centre = reinterpret_cast<const float4*>(centre);
-    (void)r;
-    (void)c;
-    return o;
-}
+constexpr int kGridCap = 128;
 
-ezo_status prep_obstacles(ezo_ctx* c, const float* obs, int n_obs, hipStream_t st, void** rec, void** centre) {
+int grid_dim(int n_obs) { return n_obs >= 256 ? 32 : (n_obs >= 32 ? 16 : 8); }
+
+// Obstacle records, the frame shift and the broad-phase grid for one call.
+ezo_status prep_obstacles(ezo_ctx* c, const ezo_robot* r, const float* obs, int n_obs, hipStream_t st,
+                          ObsView* ov, GridView* gv) {
     ezo_status s;
-    if ((s = ws_get(c, W_OBS_REC, sizeof(float4) * 2 * (size_t)std::max(n_obs, 1), rec)) != EZO_OK) return s;
-    if ((s = ws_get(c, W_OBS_CENTRE, sizeof(float4), centre)) != EZO_OK) return s;
-    hipLaunchKernelGGL(k_prep_obstacles, dim3(1), dim3(256), 0, st, obs, n_obs, (float4*)*rec, (float4*)*centre);
+    void *rec, *centre, *geom, *count, *list;
+    const int G = grid_dim(n_obs);
+    const size_t cells = (size_t)G * G * G;
+    if ((s = ws_get(c, W_OBS_REC, sizeof(float4) * 2 * (size_t)std::max(n_obs, 1), &rec)) != EZO_OK) return s;
+    if ((s = ws_get(c, W_OBS_CENTRE, sizeof(float4), &centre)) != EZO_OK) return s;
+    if ((s = ws_get(c, W_GRID_GEOM, sizeof(GridGeom), &geom)) != EZO_OK) return s;
+    if ((s = ws_get(c, W_GRID_COUNT, sizeof(int) * cells, &count)) != EZO_OK) return s;
+    if ((s = ws_get(c, W_GRID_LIST, sizeof(unsigned short) * cells * kGridCap, &list)) != EZO_OK) return s;
+    hipLaunchKernelGGL(k_prep_obstacles, dim3(1), dim3(256), 0, st, obs, n_obs, (float4*)rec, (float4*)centre,
+                       (GridGeom*)geom, G, r ? r->r_max : 0.f);
+    hipLaunchKernelGGL(k_build_grid, dim3((unsigned)((cells * 64 + 255) / 256)), dim3(256), 0, st,
+                       (const float4*)rec, n_obs, (const GridGeom*)geom, G, kGridCap, (int*)count,
+                       (unsigned short*)list);
     HIP_TRY(c, hipGetLastError());
+    ov->n = n_obs;
+    ov->rec = (const float4*)rec;
+    ov->centre = (const float4*)centre;
+    gv->G = G;
+    gv->cap = kGridCap;
+    gv->geom = (const GridGeom*)geom;
+    gv->count = (const int*)count;
+    gv->list = (const unsigned short*)list;
+    gv->tests = nullptr;
     return EZO_OK;
 }
 
 template <bool SD>
-ezo_status launch_check(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const float* q, int64_t n,
+ezo_status launch_check(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const GridView& gv, const float* q, int64_t n,
                         int64_t sn, int64_t sd, int64_t q_batch, uint8_t* flags, float* min_sd,
                         float* min_sd_self, int64_t out_batch, int n_batch, const int* status,
                         const IterArgs& it, hipStream_t st) {
-    const int W = pick_W(ov.n);
+    const int W = SD ? pick_W(ov.n) : 4;
     const int T = pick_T(c, n * n_batch, r->S, W);
     if (T == 0) return fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
     const size_t lds = tile_smem_bytes(T, r->S, W);
@@ -163,7 +180,7 @@ ezo_status launch_check(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const
     if (tiles <= 0) return EZO_OK;
     dim3 grid((unsigned)tiles, (unsigned)n_batch), block(64 * W);
 #define EZO_LAUNCH_CHECK(TT)                                                                          \
-    hipLaunchKernelGGL((k_check<TT, SD>), grid, block, lds, st, r->view, ov, q, n, sn, sd, q_batch, flags, \
+    hipLaunchKernelGGL((k_check<TT, SD>), grid, block, lds, st, r->view, ov, gv, q, n, sn, sd, q_batch, flags, \
                        min_sd, min_sd_self, out_batch, status, it)
     switch (T) {
         case 64: EZO_LAUNCH_CHECK(64); break;
@@ -203,17 +220,18 @@ ezo_status launch_sample(ezo_ctx* c, int dof, const float* A, const float* b, co
     return EZO_OK;
 }
 
-ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const float* edges, int E,
+ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const GridView& gv,
+                                 const float* edges, int E,
                                  const float* S, int64_t stride, const int* cand_idx, const int* n_cands,
                                  int cand_cap, int n_b, float* c_star, float* a_dir, float* t_star,
                                  uint8_t* pcol, uint8_t* pany, const int* status, hipStream_t st) {
-    const int W = pick_W(ov.n);
+    const int W = 4;
     const int T = std::min(pick_T(c, (int64_t)cand_cap * E, r->S, W), 64);
     if (T == 0) return fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
     const size_t lds = tile_smem_bytes(T, r->S, W);
     dim3 grid((unsigned)((cand_cap + T - 1) / T), (unsigned)E), block(64 * W);
 #define EZO_LAUNCH_PB(TT)                                                                                    \
-    hipLaunchKernelGGL(k_project_bisect<TT>, grid, block, lds, st, r->view, ov, edges, S, stride, cand_idx, \
+    hipLaunchKernelGGL(k_project_bisect<TT>, grid, block, lds, st, r->view, ov, gv, edges, S, stride, cand_idx, \
                        n_cands, cand_cap, n_b, c_star, a_dir, t_star, pcol, pany, status)
     switch (T) {
         case 64: EZO_LAUNCH_PB(64); break;
@@ -274,6 +292,7 @@ void ezo_ctx_destroy(ezo_ctx* c) {
     if (c->ev_out) e = hipEventDestroy(c->ev_out);
     for (auto& ev : c->tev)
         if (ev) e = hipEventDestroy(ev);
+    if (c->d_tests) e = hipFree(c->d_tests);
     if (c->stream) e = hipStreamDestroy(c->stream);
     (void)e;
     delete c;
@@ -328,13 +347,53 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
         link_begin[d->sphere_link[o] + 1]++;
     }
     for (int j = 0; j < dof; ++j) link_begin[j + 1] += link_begin[j];
-    for (int p = 0; p < P; ++p)
-        pairs[p] = make_int2(orig_to_sorted[d->self_pairs[2 * p]], orig_to_sorted[d->self_pairs[2 * p + 1]]);
-    // one allocation: [dh][sph][pairs][link_begin][s2o][limits]
+    // self pairs grouped into blocks by (lower link, higher link)
+    std::vector<std::pair<std::pair<int, int>, int2>> keyed(P);
+    for (int p = 0; p < P; ++p) {
+        const int a = orig_to_sorted[d->self_pairs[2 * p]], bb = orig_to_sorted[d->self_pairs[2 * p + 1]];
+        const int la = d->sphere_link[d->self_pairs[2 * p]], lbk = d->sphere_link[d->self_pairs[2 * p + 1]];
+        keyed[p] = {{std::min(la, lbk), std::max(la, lbk)}, make_int2(a, bb)};
+    }
+    std::stable_sort(keyed.begin(), keyed.end(),
+                     [](const auto& x, const auto& y) { return x.first < y.first; });
+    std::vector<int4> blocks;
+    for (int p = 0; p < P; ++p) {
+        pairs[p] = keyed[p].second;
+        if (p == 0 || keyed[p].first != keyed[p - 1].first)
+            blocks.push_back(make_int4(keyed[p].first.first, keyed[p].first.second, p, 0));
+        blocks.back().w++;
+    }
+    if (blocks.empty()) blocks.push_back(make_int4(0, 0, 0, 0));
+    const int NB = P > 0 ? (int)blocks.size() : 0;
+    // bounding sphere of each link's spheres (link frame): centre of the
+    // centres' box, radius = max distance + sphere radius
+    std::vector<float4> lbound(dof, make_float4(0.f, 0.f, 0.f, 0.f));
+    float r_max = 0.f;
+    for (int j = 0; j < dof; ++j) {
+        const int s0 = link_begin[j], s1 = link_begin[j + 1];
+        if (s1 <= s0) continue;
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int s2 = s0; s2 < s1; ++s2) {
+            const double v[3] = {sph[s2].x, sph[s2].y, sph[s2].z};
+            for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], v[k]); hi[k] = std::max(hi[k], v[k]); }
+        }
+        const double cc[3] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])};
+        double R = 0.0;
+        for (int s2 = s0; s2 < s1; ++s2) {
+            const double dx = sph[s2].x - cc[0], dy = sph[s2].y - cc[1], dz = sph[s2].z - cc[2];
+            R = std::max(R, std::sqrt(dx * dx + dy * dy + dz * dz) + (double)sph[s2].w);
+        }
+        // small relative + absolute pad covers FP32 rounding of the transformed centres
+        lbound[j] = make_float4((float)cc[0], (float)cc[1], (float)cc[2], (float)(R * (1.0 + 1e-5) + 1e-5));
+    }
+    for (int s2 = 0; s2 < S; ++s2) r_max = std::max(r_max, sph[s2].w);
+    // one allocation: [dh][sph][pairs][lbound][blocks][link_begin][s2o][limits]
     size_t off_dh = 0;
     size_t off_sph = off_dh + sizeof(float4) * dof;
     size_t off_pairs = off_sph + sizeof(float4) * sph.size();
-    size_t off_lb = off_pairs + sizeof(int2) * pairs.size();
+    size_t off_lbd = off_pairs + sizeof(int2) * pairs.size();
+    size_t off_blk = off_lbd + sizeof(float4) * lbound.size();
+    size_t off_lb = off_blk + sizeof(int4) * blocks.size();
     size_t off_s2o = off_lb + sizeof(int) * link_begin.size();
     size_t off_lim = off_s2o + sizeof(int) * s2o.size();
     size_t total = off_lim + sizeof(float) * lim.size();
@@ -342,6 +401,8 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     memcpy(host.data() + off_dh, dh.data(), sizeof(float4) * dof);
     memcpy(host.data() + off_sph, sph.data(), sizeof(float4) * sph.size());
     memcpy(host.data() + off_pairs, pairs.data(), sizeof(int2) * pairs.size());
+    memcpy(host.data() + off_lbd, lbound.data(), sizeof(float4) * lbound.size());
+    memcpy(host.data() + off_blk, blocks.data(), sizeof(int4) * blocks.size());
     memcpy(host.data() + off_lb, link_begin.data(), sizeof(int) * link_begin.size());
     memcpy(host.data() + off_s2o, s2o.data(), sizeof(int) * s2o.size());
     memcpy(host.data() + off_lim, lim.data(), sizeof(float) * lim.size());
@@ -360,9 +421,13 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     r->P = P;
     r->buf = buf;
     char* b = reinterpret_cast<char*>(buf);
+    r->r_max = r_max;
     r->view.dof = dof;
     r->view.n_spheres = S;
     r->view.n_self = P;
+    r->view.n_blocks = NB;
+    r->view.lbound = reinterpret_cast<const float4*>(b + off_lbd);
+    r->view.blocks = reinterpret_cast<const int4*>(b + off_blk);
     r->view.dh = reinterpret_cast<const float4*>(b + off_dh);
     r->view.sph = reinterpret_cast<const float4*>(b + off_sph);
     r->view.pairs = reinterpret_cast<const int2*>(b + off_pairs);
@@ -403,15 +468,16 @@ ezo_status ezo_check_collisions(ezo_ctx* c, const ezo_robot* r, const float* obs
     if (!q || !flags || (n_obs > 0 && !obs)) return fail(c, EZO_E_INVALID, "NULL buffer");
     HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t st = as_stream(stream);
-    void *rec, *cen;
-    ezo_status s = prep_obstacles(c, obs, n_obs, st, &rec, &cen);
+    ObsView ov;
+    GridView gv;
+    ezo_status s = prep_obstacles(c, r, obs, n_obs, st, &ov, &gv);
     if (s) return s;
-    ObsView ov = obs_view(r, c, n_obs, rec, cen);
     IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
     if (min_sd || min_sd_self)
-        return launch_check<true>(c, r, ov, q, n, stride_n, stride_d, 0, flags, min_sd, min_sd_self, 0, 1, nullptr,
-                                  it, st);
-    return launch_check<false>(c, r, ov, q, n, stride_n, stride_d, 0, flags, nullptr, nullptr, 0, 1, nullptr, it, st);
+        return launch_check<true>(c, r, ov, gv, q, n, stride_n, stride_d, 0, flags, min_sd, min_sd_self, 0, 1,
+                                  nullptr, it, st);
+    return launch_check<false>(c, r, ov, gv, q, n, stride_n, stride_d, 0, flags, nullptr, nullptr, 0, 1, nullptr, it,
+                               st);
 }
 
 ezo_status ezo_sphere_centres(ezo_ctx* c, const ezo_robot* r, const float* q, int64_t n, int64_t stride_n,
@@ -422,10 +488,10 @@ ezo_status ezo_sphere_centres(ezo_ctx* c, const ezo_robot* r, const float* q, in
     if (!q || !centres) return fail(c, EZO_E_INVALID, "NULL buffer");
     HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t st = as_stream(stream);
-    void *rec, *cen;
-    ezo_status s = prep_obstacles(c, nullptr, 0, st, &rec, &cen);   // zero shift
+    ObsView ov;
+    GridView gv;
+    ezo_status s = prep_obstacles(c, r, nullptr, 0, st, &ov, &gv);   // zero shift
     if (s) return s;
-    ObsView ov = obs_view(r, c, 0, rec, cen);
     int T = 16;
     while (T > 1 && tile_smem_bytes(T, r->S, 4) > c->lds_cap) T >>= 1;
     const size_t lds = tile_smem_bytes(T, r->S, 4);
@@ -487,11 +553,11 @@ ezo_status ezo_project_bisect(ezo_ctx* c, const ezo_robot* r, const float* obs, 
         return fail(c, EZO_E_INVALID, "NULL buffer");
     HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t st = as_stream(stream);
-    void *rec, *cen;
-    ezo_status s = prep_obstacles(c, obs, n_obs, st, &rec, &cen);
+    ObsView ov;
+    GridView gv;
+    ezo_status s = prep_obstacles(c, r, obs, n_obs, st, &ov, &gv);
     if (s) return s;
-    ObsView ov = obs_view(r, c, n_obs, rec, cen);
-    return launch_project_bisect(c, r, ov, edges, n_edges, samples, sample_stride, cand_idx, n_cands, cand_capacity,
+    return launch_project_bisect(c, r, ov, gv, edges, n_edges, samples, sample_stride, cand_idx, n_cands, cand_capacity,
                                  n_b, c_star, a_dir, t_star, proj_collides, nullptr, nullptr, st);
 }
 
@@ -573,9 +639,9 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
     HIP_TRY(c, hipMemcpyAsync(w_tb, table.data(), sizeof(int4) * table.size(), hipMemcpyHostToDevice, st));
     const int one = 1;
     HIP_TRY(c, hipMemcpyAsync(w_k, &one, sizeof(int), hipMemcpyHostToDevice, st));
-    void *rec, *cen;
-    if ((s = prep_obstacles(c, obs, n_obs, st, &rec, &cen))) return s;
-    ObsView ov = obs_view(r, c, n_obs, rec, cen);
+    ObsView ov;
+    GridView gv;
+    if ((s = prep_obstacles(c, r, obs, n_obs, st, &ov, &gv))) return s;
     hipLaunchKernelGGL(k_init_edges, dim3((E + 63) / 64), dim3(64), 0, st, dof, r->q_lo, r->q_hi, edges, E, A, b,
                        n_faces, cap, edge_status, (EdgeStatsDev*)w_st, (uint8_t*)w_pa);
     HIP_TRY(c, hipGetLastError());
@@ -600,14 +666,19 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
                                 (float*)w_s, stride, edge_status, it, st)))
             return ls;
         mark(EZO_PHASE_CHECK);
-        if ((ls = launch_check<false>(c, r, ov, (const float*)w_s, S_cap, 1, stride, (int64_t)dof * stride,
+        GridView gvc = gv, gvb = gv;
+        if (marks && c->d_tests) {
+            gvc.tests = c->d_tests + EZO_PHASE_CHECK;
+            gvb.tests = c->d_tests + EZO_PHASE_BISECT;
+        }
+        if ((ls = launch_check<false>(c, r, ov, gvc, (const float*)w_s, S_cap, 1, stride, (int64_t)dof * stride,
                                       (uint8_t*)w_f, nullptr, nullptr, stride, E, edge_status, it, st)))
             return ls;
         mark(EZO_PHASE_TEST);
         hipLaunchKernelGGL(k_test_select, dim3(E), dim3(1024), 0, st, (const uint8_t*)w_f, stride, p->n_p, p->n_b,
                            (int*)w_ci, cand_cap, (int*)w_nc, nullptr, nullptr, edge_status, (EdgeStatsDev*)w_st, it);
         mark(EZO_PHASE_BISECT);
-        if ((ls = launch_project_bisect(c, r, ov, edges, E, (const float*)w_s, stride, (const int*)w_ci,
+        if ((ls = launch_project_bisect(c, r, ov, gvb, edges, E, (const float*)w_s, stride, (const int*)w_ci,
                                         (const int*)w_nc, cand_cap, p->n_b, (float*)w_cs, (float*)w_ad,
                                         (float*)w_ts, (uint8_t*)w_pc, (uint8_t*)w_pa, edge_status, st)))
             return ls;
@@ -692,6 +763,9 @@ ezo_status ezo_set_phase_timing(ezo_ctx* c, int32_t enable) {
     if (enable) {
         for (auto& ev : c->tev)
             if (!ev) HIP_TRY(c, hipEventCreate(&ev));
+        if (!c->d_tests) HIP_TRY(c, hipMalloc((void**)&c->d_tests, sizeof(unsigned long long) * EZO_NUM_PHASES));
+        HIP_TRY(c, hipMemsetAsync(c->d_tests, 0, sizeof(unsigned long long) * EZO_NUM_PHASES, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
     c->timing = enable != 0;
     for (double& m : c->phase_ms) m = 0.0;
@@ -699,10 +773,19 @@ ezo_status ezo_set_phase_timing(ezo_ctx* c, int32_t enable) {
     return EZO_OK;
 }
 
-ezo_status ezo_get_phase_timing(const ezo_ctx* c, double* ms_out, int64_t* iterations_out) {
+ezo_status ezo_get_phase_timing(ezo_ctx* c, double* ms_out, int64_t* iterations_out, int64_t* tests_out) {
     if (!c || !ms_out) return EZO_E_INVALID;
     for (int i = 0; i < EZO_NUM_PHASES; ++i) ms_out[i] = c->phase_ms[i];
     if (iterations_out) *iterations_out = c->timed_iters;
+    if (tests_out) {
+        unsigned long long h[EZO_NUM_PHASES] = {};
+        if (c->d_tests) {
+            HIP_TRY(c, hipSetDevice(c->device));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            HIP_TRY(c, hipMemcpy(h, c->d_tests, sizeof(h), hipMemcpyDeviceToHost));
+        }
+        for (int i = 0; i < EZO_NUM_PHASES; ++i) tests_out[i] = (int64_t)h[i];
+    }
     return EZO_OK;
 }
 

@@ -33,10 +33,34 @@ struct RobotView {
     int dof;
     int n_spheres;
     int n_self;
+    int n_blocks;
     const float4* dh;          // [dof] (a, d, cos alpha, sin alpha)
     const int* link_begin;     // [dof + 1] spheres of link i: [link_begin[i], link_begin[i+1])
     const float4* sph;         // [S] local (x, y, z), r -- sorted by link
-    const int2* pairs;         // [P] self pairs, indices into the sorted order
+    const int2* pairs;         // [P] self pairs, indices into the sorted order, grouped by block
+    const float4* lbound;      // [dof] bounding sphere of each link's spheres: local centre, radius
+    const int4* blocks;        // [n_blocks] (link i, link j, first pair, pair count)
+};
+
+// Uniform grid over the obstacle cloud (shifted frame).  Cell k lists every
+// obstacle that a robot sphere centred anywhere in cell k could touch:
+// |o - centre_k| < r_o + r_sphere_max + half cell diagonal + slack.  A sphere
+// centre outside the grid box is farther than r_sphere_max + r_o_max from
+// every obstacle.  count[k] > cap marks an overflowing cell (scan all).
+struct GridGeom {
+    float ox, oy, oz;          // origin (min corner)
+    float hx, hy, hz;          // cell size
+    float ihx, ihy, ihz;       // 1 / cell size
+    float reach;               // r_sphere_max + half cell diagonal + slack
+};
+
+struct GridView {
+    int G;                     // cells per axis
+    int cap;                   // list capacity per cell
+    const GridGeom* geom;
+    const int* count;          // [G^3]
+    const unsigned short* list;  // [G^3][cap] obstacle indices
+    unsigned long long* tests;   // optional counter of sphere-sphere tests performed
 };
 
 // Read-only global memory viewed through the constant address space: loads
@@ -110,6 +134,7 @@ struct TileSmem {
     float* q;          // [T][kMaxDof] configurations of the tile
     float2* trig;      // [kMaxDof][T] (cos, sin) of each joint
     float4* cen;       // [S][T] sphere centres (shifted frame) and radius
+    float4* lb;        // [kMaxDof][T] link bounding spheres (shifted frame)
     int* hit;          // [T] collision flag (flags mode) / validity
     float* red;        // [2][W][T] partial minima (signed-distance mode)
 };
@@ -119,6 +144,7 @@ __host__ __device__ inline size_t tile_smem_bytes(int T, int S, int W) {
     b += sizeof(float) * (size_t)T * kMaxDof;
     b += sizeof(float2) * (size_t)kMaxDof * T;
     b += sizeof(float4) * (size_t)(S > 0 ? S : 1) * T;
+    b += sizeof(float4) * (size_t)kMaxDof * T;
     b += sizeof(int) * (size_t)T;
     b += sizeof(float) * 2 * (size_t)W * T;
     return (b + 15) & ~(size_t)15;
@@ -128,6 +154,7 @@ __device__ inline TileSmem carve_tile(char* base, int T, int S, int W) {
     TileSmem t;
     char* p = base;
     t.cen = reinterpret_cast<float4*>(p);   p += sizeof(float4) * (size_t)(S > 0 ? S : 1) * T;
+    t.lb = reinterpret_cast<float4*>(p);    p += sizeof(float4) * (size_t)kMaxDof * T;
     t.trig = reinterpret_cast<float2*>(p);  p += sizeof(float2) * (size_t)kMaxDof * T;
     t.q = reinterpret_cast<float*>(p);      p += sizeof(float) * (size_t)T * kMaxDof;
     t.red = reinterpret_cast<float*>(p);    p += sizeof(float) * 2 * (size_t)W * T;
@@ -155,6 +182,15 @@ __device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const Til
             const float2 cs = t.trig[l * T + c];
             dh_compose(R, p, cs.x, cs.y, rb.dh[l]);
         }
+        {
+            const float4 lc = rb.lbound[link];
+            float4 o;
+            o.x = fmaf(R[0], lc.x, fmaf(R[1], lc.y, fmaf(R[2], lc.z, p[0])));
+            o.y = fmaf(R[3], lc.x, fmaf(R[4], lc.y, fmaf(R[5], lc.z, p[1])));
+            o.z = fmaf(R[6], lc.x, fmaf(R[7], lc.y, fmaf(R[8], lc.z, p[2])));
+            o.w = lc.w;
+            t.lb[link * T + c] = o;
+        }
         const int s1 = rb.link_begin[link + 1];
         for (int s = rb.link_begin[link]; s < s1; ++s) {
             const float4 ps = rb.sph[s];
@@ -175,75 +211,6 @@ __device__ __forceinline__ int wave_id() {
 
 __device__ __forceinline__ bool wave_all(bool p) {
     return __ballot(p) == __ballot(true);
-}
-
-// Flags-mode pair sweep.  Result: t.hit[c] = 1 iff configuration c collides
-// (invalid configurations c >= n_valid are reported as 1).  Barrier at exit.
-__device__ inline void tile_pairs_flags(const RobotView& rb, const ObsView& ob, const TileSmem& t, int T,
-                                        int n_valid) {
-    const int tid = threadIdx.x;
-    const int W = blockDim.x >> 6;
-    const int w = wave_id();
-    const int lane = tid & 63;
-    const int c = lane % T;
-    const int nsub = 64 / T;
-    const int j = lane / T;
-    volatile int* hit = t.hit;
-    const int S = rb.n_spheres;
-
-    // ---- self pairs (cheap; many configurations self-collide) ----
-    {
-        const int P = rb.n_self;
-        const int step = W * nsub;
-        for (int p0 = w * nsub; p0 < P; p0 += step) {
-            if (wave_all(hit[c] != 0)) break;
-            const int p = p0 + j;
-            if (p < P) {
-                const int2 pr = rb.pairs[p];
-                const float4 a = t.cen[pr.x * T + c];
-                const float4 b = t.cen[pr.y * T + c];
-                const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
-                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                const float R = a.w + b.w;
-                if (d2 < R * R) hit[c] = 1;
-            }
-        }
-    }
-    // ---- robot/obstacle pairs: this wave's obstacle slice ----
-    const int o0 = (int)(((long)ob.n * w) / W);
-    const int o1 = (int)(((long)ob.n * (w + 1)) / W);
-    if (o1 > o0) {
-        for (int s0 = 0; s0 < S; s0 += 2 * nsub) {
-            if (wave_all(hit[c] != 0)) break;
-            const int sa = s0 + j, sb = s0 + nsub + j;
-            float4 A = sa < S ? t.cen[sa * T + c] : make_float4(0.f, 0.f, 0.f, 0.f);
-            float4 B = sb < S ? t.cen[sb * T + c] : make_float4(0.f, 0.f, 0.f, 0.f);
-            const float alA = sa < S ? fmaf(A.x, A.x, fmaf(A.y, A.y, fmaf(A.z, A.z, -A.w * A.w))) : kHuge;
-            const float alB = sb < S ? fmaf(B.x, B.x, fmaf(B.y, B.y, fmaf(B.z, B.z, -B.w * B.w))) : kHuge;
-            const float mA = -2.f * A.w, mB = -2.f * B.w;
-            float accA = kHuge, accB = kHuge;
-            const cfloat* rec = (const cfloat*)ob.rec;
-#pragma unroll 4
-            for (int o = o0; o < o1; ++o) {
-                const float4 P0 = cload4(rec + 8 * o);       // (ox, oy, oz, ro)
-                const float4 P1 = cload4(rec + 8 * o + 4);   // (-2ox, -2oy, -2oz, beta)
-                float vA = alA + P1.w;
-                float vB = alB + P1.w;
-                vA = fmaf(A.x, P1.x, vA);
-                vB = fmaf(B.x, P1.x, vB);
-                vA = fmaf(A.y, P1.y, vA);
-                vB = fmaf(B.y, P1.y, vB);
-                vA = fmaf(A.z, P1.z, vA);
-                vB = fmaf(B.z, P1.z, vB);
-                vA = fmaf(mA, P0.w, vA);
-                vB = fmaf(mB, P0.w, vB);
-                accA = fminf(accA, vA);
-                accB = fminf(accB, vB);
-            }
-            if (fminf(accA, accB) < 0.f) hit[c] = 1;
-        }
-    }
-    __syncthreads();
 }
 
 // Signed-distance pair sweep.  Results: t.red[0][0][c] = overall minimum,
@@ -316,15 +283,89 @@ __device__ inline void tile_pairs_sd(const RobotView& rb, const ObsView& ob, con
     __syncthreads();
 }
 
+// Flags-mode sweep with broad phase.  Work items are (configuration,
+// self-pair block) and (configuration, sphere), spread over the whole
+// workgroup.  A self-pair block (all listed pairs between two links) is
+// skipped when the two links' bounding spheres are apart; a sphere tests only
+// the obstacles listed in its grid cell.  Every skipped pair is provably
+// separated, so the flag equals that of the all-pairs test.  The pair test is
+// |c - o|^2 < (r_c + r_o)^2 (difference form).  Barrier at exit.
+// `tests` (optional) accumulates the number of sphere-sphere tests performed
+// (bound tests included), one atomic per wave.
+__device__ inline void tile_pairs_grid(const RobotView& rb, const ObsView& ob, const GridView& gv, const TileSmem& t,
+                                       int T, unsigned long long* tests) {
+    volatile int* hit = t.hit;
+    const int nt = blockDim.x;
+    unsigned int ntest = 0;
+    for (int it = threadIdx.x; it < T * rb.n_blocks; it += nt) {
+        const int c = it % T, bk = it / T;
+        if (hit[c]) continue;
+        const int4 blk = rb.blocks[bk];
+        const float4 A = t.lb[blk.x * T + c], B = t.lb[blk.y * T + c];
+        const float dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;
+        const float R = A.w + B.w;
+        ++ntest;
+        if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) >= R * R) continue;
+        for (int p = blk.z; p < blk.z + blk.w; ++p) {
+            ++ntest;
+            const int2 pr = rb.pairs[p];
+            const float4 a = t.cen[pr.x * T + c];
+            const float4 b = t.cen[pr.y * T + c];
+            const float ex = a.x - b.x, ey = a.y - b.y, ez = a.z - b.z;
+            const float Rr = a.w + b.w;
+            if (fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < Rr * Rr) {
+                hit[c] = 1;
+                break;
+            }
+        }
+    }
+    if (ob.n > 0) {
+        const GridGeom g = *gv.geom;
+        const int G = gv.G;
+        const int S = rb.n_spheres;
+        for (int it = threadIdx.x; it < T * S; it += nt) {
+            const int c = it % T, s = it / T;
+            if (hit[c]) continue;
+            const float4 C = t.cen[s * T + c];
+            const float fx = (C.x - g.ox) * g.ihx, fy = (C.y - g.oy) * g.ihy, fz = (C.z - g.oz) * g.ihz;
+            if (!(fx >= 0.f && fy >= 0.f && fz >= 0.f && fx < (float)G && fy < (float)G && fz < (float)G)) continue;
+            const int cx = min((int)fx, G - 1), cy = min((int)fy, G - 1), cz = min((int)fz, G - 1);
+            const int cell = (cz * G + cy) * G + cx;
+            const int cnt = gv.count[cell];
+            const bool full = cnt > gv.cap;
+            const int n = full ? ob.n : cnt;
+            const unsigned short* lst = gv.list + (size_t)cell * gv.cap;
+            for (int k = 0; k < n; ++k) {
+                ++ntest;
+                const int o = full ? k : (int)lst[k];
+                const float4 O = ob.rec[2 * o];
+                const float ex = C.x - O.x, ey = C.y - O.y, ez = C.z - O.z;
+                const float Rr = C.w + O.w;
+                if (fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < Rr * Rr) {
+                    hit[c] = 1;
+                    break;
+                }
+            }
+        }
+    }
+    if (tests) {
+        unsigned long long v = ntest;
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if ((threadIdx.x & 63) == 0) atomicAdd(tests, v);
+    }
+    __syncthreads();
+}
+
 // Whole tile check on t.q[0..n_valid).  Flags mode fills t.hit; signed-
 // distance mode also fills t.red[c] (overall) and t.red[W*T + c] (self).
 template <bool SD>
-__device__ inline void tile_check(const RobotView& rb, const ObsView& ob, const TileSmem& t, int T, int n_valid) {
+__device__ inline void tile_check(const RobotView& rb, const ObsView& ob, const GridView& gv, const TileSmem& t,
+                                  int T, int n_valid) {
     tile_fk(rb, ob, t, T, n_valid);
     if (threadIdx.x < (unsigned)T) t.hit[threadIdx.x] = (threadIdx.x < (unsigned)n_valid) ? 0 : 1;
     __syncthreads();
     if (SD) tile_pairs_sd(rb, ob, t, T, n_valid);
-    else tile_pairs_flags(rb, ob, t, T, n_valid);
+    else tile_pairs_grid(rb, ob, gv, t, T, gv.tests);
 }
 
 }  // namespace ezo

@@ -38,44 +38,98 @@ __device__ __forceinline__ bool edge_running(const int* status, int e) {
 }
 
 // ---------------------------------------------------------------------------
-// Obstacle preparation: centre of the bounding box of the obstacle centres,
-// then records (o', r), (-2 o', |o'|^2 - r^2) with o' = o - centre.
-// One workgroup.
+// Obstacle preparation (one workgroup): bounding box of the obstacle centres
+// and largest obstacle radius; records (o', r), (-2 o', |o'|^2 - r^2) with
+// o' = o - centre of the box; geometry of a G^3 grid over the box grown by
+// r_sphere_max + r_obstacle_max + slack.
 // ---------------------------------------------------------------------------
+constexpr float kGridSlack = 1e-4f;
+
 __global__ void __launch_bounds__(256) k_prep_obstacles(const float* __restrict__ obs, int n, float4* __restrict__ rec,
-                                                        float4* __restrict__ centre) {
-    __shared__ float red[6][256];
+                                                        float4* __restrict__ centre, GridGeom* __restrict__ geom,
+                                                        int G, float r_sphere_max) {
+    __shared__ float red[7][256];
     const int tid = threadIdx.x;
-    float mn[3] = {kHuge, kHuge, kHuge}, mx[3] = {-kHuge, -kHuge, -kHuge};
-    for (int o = tid; o < n; o += blockDim.x)
+    float mn[3] = {kHuge, kHuge, kHuge}, mx[3] = {-kHuge, -kHuge, -kHuge}, rmax = 0.f;
+    for (int o = tid; o < n; o += blockDim.x) {
         for (int k = 0; k < 3; ++k) {
             const float v = obs[4 * (size_t)o + k];
             mn[k] = fminf(mn[k], v);
             mx[k] = fmaxf(mx[k], v);
         }
+        rmax = fmaxf(rmax, obs[4 * (size_t)o + 3]);
+    }
     for (int k = 0; k < 3; ++k) { red[k][tid] = mn[k]; red[3 + k][tid] = mx[k]; }
+    red[6][tid] = rmax;
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (tid < s)
+        if (tid < s) {
             for (int k = 0; k < 3; ++k) {
                 red[k][tid] = fminf(red[k][tid], red[k][tid + s]);
                 red[3 + k][tid] = fmaxf(red[3 + k][tid], red[3 + k][tid + s]);
             }
+            red[6][tid] = fmaxf(red[6][tid], red[6][tid + s]);
+        }
         __syncthreads();
     }
-    float cx = 0.f, cy = 0.f, cz = 0.f;
-    if (n > 0) {
-        cx = 0.5f * (red[0][0] + red[3][0]);
-        cy = 0.5f * (red[1][0] + red[4][0]);
-        cz = 0.5f * (red[2][0] + red[5][0]);
+    float c[3] = {0.f, 0.f, 0.f}, half[3] = {0.f, 0.f, 0.f};
+    if (n > 0)
+        for (int k = 0; k < 3; ++k) {
+            c[k] = 0.5f * (red[k][0] + red[3 + k][0]);
+            half[k] = 0.5f * (red[3 + k][0] - red[k][0]);
+        }
+    if (tid == 0) {
+        centre[0] = make_float4(c[0], c[1], c[2], 0.f);
+        const float margin = r_sphere_max + red[6][0] + kGridSlack;
+        GridGeom g;
+        float h[3];
+        for (int k = 0; k < 3; ++k) h[k] = 2.f * (half[k] + margin) / (float)G;
+        g.ox = -half[0] - margin; g.oy = -half[1] - margin; g.oz = -half[2] - margin;
+        g.hx = h[0]; g.hy = h[1]; g.hz = h[2];
+        g.ihx = 1.f / h[0]; g.ihy = 1.f / h[1]; g.ihz = 1.f / h[2];
+        g.reach = r_sphere_max + 0.5f * sqrtf(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]) + kGridSlack;
+        geom[0] = g;
     }
-    if (tid == 0) centre[0] = make_float4(cx, cy, cz, 0.f);
     for (int o = tid; o < n; o += blockDim.x) {
-        const float x = obs[4 * (size_t)o + 0] - cx, y = obs[4 * (size_t)o + 1] - cy, z = obs[4 * (size_t)o + 2] - cz;
+        const float x = obs[4 * (size_t)o + 0] - c[0], y = obs[4 * (size_t)o + 1] - c[1], z = obs[4 * (size_t)o + 2] - c[2];
         const float r = obs[4 * (size_t)o + 3];
         rec[2 * (size_t)o] = make_float4(x, y, z, r);
         rec[2 * (size_t)o + 1] = make_float4(-2.f * x, -2.f * y, -2.f * z, fmaf(x, x, fmaf(y, y, fmaf(z, z, -r * r))));
     }
+}
+
+// Grid lists: one wave per cell; 64 obstacles per step tested against the
+// cell's reach, survivors appended in index order by ballot prefix.
+__global__ void __launch_bounds__(256) k_build_grid(const float4* __restrict__ rec, int n, const GridGeom* __restrict__ geom,
+                                                    int G, int cap, int* __restrict__ count,
+                                                    unsigned short* __restrict__ list) {
+    const int cell = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (cell >= G * G * G) return;
+    if (n > 65535) {                       // indices do not fit the list type: every cell scans all
+        if (lane == 0) count[cell] = cap + 1;
+        return;
+    }
+    const GridGeom g = *geom;
+    const int cx = cell % G, cy = (cell / G) % G, cz = cell / (G * G);
+    const float px = g.ox + (cx + 0.5f) * g.hx, py = g.oy + (cy + 0.5f) * g.hy, pz = g.oz + (cz + 0.5f) * g.hz;
+    int total = 0;
+    unsigned short* lst = list + (size_t)cell * cap;
+    for (int o0 = 0; o0 < n; o0 += 64) {
+        const int o = o0 + lane;
+        bool in = false;
+        if (o < n) {
+            const float4 O = rec[2 * (size_t)o];
+            const float dx = O.x - px, dy = O.y - py, dz = O.z - pz;
+            const float R = O.w + g.reach;
+            in = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < R * R;
+        }
+        const unsigned long long m = __ballot(in);
+        const int pos = total + __popcll(m & ((1ull << lane) - 1ull));
+        if (in && pos < cap) lst[pos] = (unsigned short)o;
+        total += __popcll(m);
+    }
+    if (lane == 0) count[cell] = total;
 }
 
 // ---------------------------------------------------------------------------
@@ -84,7 +138,7 @@ __global__ void __launch_bounds__(256) k_prep_obstacles(const float* __restrict_
 // n = iteration's |S| when it.k_dev is set, else n_arg.
 // ---------------------------------------------------------------------------
 template <int T, bool SD>
-__global__ void __launch_bounds__(1024) k_check(RobotView rb, ObsView ob, const float* __restrict__ q, int64_t n_arg,
+__global__ void __launch_bounds__(1024) k_check(RobotView rb, ObsView ob, GridView gv, const float* __restrict__ q, int64_t n_arg,
                                                 int64_t stride_n, int64_t stride_d, int64_t q_batch,
                                                 uint8_t* __restrict__ flags, float* __restrict__ min_sd,
                                                 float* __restrict__ min_sd_self, int64_t out_batch,
@@ -105,7 +159,7 @@ __global__ void __launch_bounds__(1024) k_check(RobotView rb, ObsView ob, const 
         if (c < nv) t.q[c * kMaxDof + j] = qb[(base + c) * stride_n + j * stride_d];
     }
     __syncthreads();
-    tile_check<SD>(rb, ob, t, T, nv);
+    tile_check<SD>(rb, ob, gv, t, T, nv);
     if (threadIdx.x < (unsigned)nv) {
         const int64_t g = b * out_batch + base + threadIdx.x;
         flags[g] = (uint8_t)t.hit[threadIdx.x];
@@ -236,7 +290,7 @@ __global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict
                 den = fmaf(a, u[j], den);
                 ax = fmaf(a, x[j], ax);
             }
-            const float tt = (rowb[f] - ax) / den;
+            const float tt = (rowb[f] - ax) * __builtin_amdgcn_rcpf(den);
             if (den > 0.f) thi = fminf(thi, tt);
             else if (den < 0.f) tlo = fmaxf(tlo, tt);
         }
@@ -336,7 +390,7 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
 // c < T of wave 0; every check is a whole-workgroup tile check.
 // ---------------------------------------------------------------------------
 template <int T>
-__global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView ob, const float* __restrict__ edges,
+__global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView ob, GridView gv, const float* __restrict__ edges,
                                                          const float* __restrict__ S, int64_t stride,
                                                          const int* __restrict__ cand_idx,
                                                          const int* __restrict__ n_cands, int cand_cap, int n_b,
@@ -387,7 +441,7 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView o
         }
     }
     __syncthreads();
-    tile_check<false>(rb, ob, t, T, nv);
+    tile_check<false>(rb, ob, gv, t, T, nv);
     if (own) {
         const int h = t.hit[tid];
         proj_collides[(size_t)e * cand_cap + base + tid] = (uint8_t)h;
@@ -398,7 +452,7 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView o
         if (own)
             for (int j = 0; j < dof; ++j) t.q[tid * kMaxDof + j] = 0.5f * (lo[j] + hi[j]);
         __syncthreads();
-        tile_check<false>(rb, ob, t, T, nv);
+        tile_check<false>(rb, ob, gv, t, T, nv);
         if (own) {
             const bool h = t.hit[tid] != 0;
 #pragma unroll
