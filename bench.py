@@ -61,12 +61,70 @@ def cpu_baseline(name, data, desc, seed, edges_idx):
             "edges_per_s": len(edges_idx) / dt}
 
 
+def sweep(args):
+    """Raw checker throughput: N uniform configurations x n_obs obstacles,
+    flags + minimum signed distance (all pairs) and flags only (broad phase).
+    Inputs resident in HBM; hipEvent-free wall timing around synchronised
+    repetitions (the checker runs on torch's current stream)."""
+    import numpy as np
+    import torch
+
+    import paper_2504_10783_amd as ezo
+    import workloads
+    from workloads import draw
+
+    data = workloads.load("sweep")
+    desc = workloads.robot(data)
+    ctx = ezo.Context(0)
+    rob = ezo.Robot(ctx, desc)
+    dev = torch.device("cuda", 0)
+    points = []
+    sizes = [int(x) for x in args.sweep_sizes.split(",")]
+    qmax = torch.from_numpy(draw.uniform_q_fast(303, max(sizes), data["q_lo"], data["q_hi"])).to(dev)
+    for n_obs in (256, 1024, 4096):
+        obs = torch.from_numpy(data[f"obstacles_{n_obs}"]).to(dev)
+        for n in sizes:
+            q = qmax[:n]
+            flags = torch.empty(n, dtype=torch.uint8, device=dev)
+            msd = torch.empty(n, dtype=torch.float32, device=dev)
+            row = {"n": n, "n_obs": n_obs}
+            for mode in ("sd", "flags"):
+                def run():
+                    ezo.check_collisions(ctx, rob, obs, q, flags, msd if mode == "sd" else None)
+                run()
+                torch.cuda.synchronize()
+                reps = max(1, min(args.steps, int(2e8 // n)))
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    run()
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / reps
+                row[f"{mode}_configs_per_s"] = n / dt
+                row[f"{mode}_ms"] = dt * 1e3
+                if mode == "sd":
+                    fpc = flop_per_check(rob.n_spheres, n_obs, rob.n_self)
+                    row["sd_tflops"] = fpc * n / dt / 1e12
+                    row["sd_frac"] = row["sd_tflops"] / PEAK_FP32_TFLOPS
+                    row["collision_fraction"] = float(flags.float().mean().item())
+            points.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+    best = max(points, key=lambda r: r["n"] * (r["n_obs"] == 4096))
+    line = {"metric": "collision-checked configs/sec (raw checker sweep, 7-DOF, 70 spheres, 1500 self pairs)",
+            "value": best["sd_configs_per_s"], "unit": "configs/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic", "config": {"workload": "sweep: uniform q in joint limits, obstacles in "
+                                            "[0.3,1.3]x[-0.5,0.5]x[0,1] m, r U[0.02,0.08]"},
+            "points": points}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="dof7", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="dof7", choices=sorted(WORKLOADS) + ["sweep"])
+    ap.add_argument("--sweep-sizes", default="1048576,4194304,16777216")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -76,6 +134,10 @@ def main():
               "(edges shard across GPUs with no exchange; multi-GPU runs are not part of this build)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "sweep":
+        sweep(args)
+        return
 
     import numpy as np
     import torch

@@ -255,9 +255,10 @@ enum {
 
 /* Enables (1) or disables (0) per-phase GPU timing of ezo_inflate_edges on
  * this context.  While enabled, the iteration's kernels are launched directly
- * (not through the replayed hipGraph) with hipEvents recorded between the
- * phases on the stream the kernels run on, and the elapsed times accumulate.
- * Results are identical either way.  Enabling resets the totals. */
+ * (not through the replayed hipGraph), each with a pair of hipEvents that its
+ * dispatch records at kernel start and end on the stream it runs on, and the
+ * kernel durations accumulate per phase.  Results are identical either way.
+ * Enabling resets the totals. */
 ezo_status ezo_set_phase_timing(ezo_ctx *ctx, int32_t enable);
 
 /* Cumulative per-phase kernel time (ms_out[EZO_NUM_PHASES], host), the

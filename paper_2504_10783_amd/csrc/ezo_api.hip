@@ -3,6 +3,7 @@
 // stream; robots are uploaded once and rounded to FP32; the fused inflation
 // captures one iteration of kernels into a hipGraph and replays it, polling a
 // 4-byte active-edge counter after each replay.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,7 +39,8 @@ struct ezo_ctx {
     std::vector<DevBuf> ws;            // named workspace slots
     int* pinned = nullptr;             // host-pinned poll word
     bool timing = false;               // per-phase timing of the fused loop
-    hipEvent_t tev[EZO_NUM_PHASES + 1] = {};
+    hipEvent_t tev[2 * EZO_NUM_PHASES] = {};   // (start, stop) of each phase's kernel
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;   // events for the next kernel launch (timing mode)
     double phase_ms[EZO_NUM_PHASES] = {};
     int64_t timed_iters = 0;
     unsigned long long* d_tests = nullptr;   // [EZO_NUM_PHASES] sphere-sphere tests per phase
@@ -79,6 +81,17 @@ ezo_status fail(ezo_ctx* c, ezo_status code, const char* fmt, ...) {
     do {                                                                                        \
         hipError_t e_ = (call);                                                                 \
         if (e_ != hipSuccess) return fail(ctx, EZO_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// Kernel launch; in timing mode the dispatch itself records c->ev_a / c->ev_b
+// at its start and end (hipExtLaunchKernelGGL), so elapsed time is the
+// kernel's own duration.
+#define EZO_KLAUNCH(c, K, grid, block, lds, st, ...)                                              \
+    do {                                                                                          \
+        if ((c)->ev_a)                                                                            \
+            hipExtLaunchKernelGGL(K, grid, block, lds, st, (c)->ev_a, (c)->ev_b, 0, __VA_ARGS__); \
+        else                                                                                      \
+            hipLaunchKernelGGL(K, grid, block, lds, st, __VA_ARGS__);                              \
     } while (0)
 
 ezo_status ws_get(ezo_ctx* c, int slot, size_t bytes, void** out) {
@@ -180,7 +193,7 @@ ezo_status launch_check(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const
     if (tiles <= 0) return EZO_OK;
     dim3 grid((unsigned)tiles, (unsigned)n_batch), block(64 * W);
 #define EZO_LAUNCH_CHECK(TT)                                                                          \
-    hipLaunchKernelGGL((k_check<TT, SD>), grid, block, lds, st, r->view, ov, gv, q, n, sn, sd, q_batch, flags, \
+    EZO_KLAUNCH(c, (k_check<TT, SD>), grid, block, lds, st, r->view, ov, gv, q, n, sn, sd, q_batch, flags, \
                        min_sd, min_sd_self, out_batch, status, it)
     switch (T) {
         case 64: EZO_LAUNCH_CHECK(64); break;
@@ -209,7 +222,7 @@ ezo_status launch_sample(ezo_ctx* c, int dof, const float* A, const float* b, co
     dim3 grid((unsigned)((threads + 255) / 256), (unsigned)E), block(256);
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 #define EZO_LAUNCH_SAMPLE(DD, LL)                                                                                 \
-    hipLaunchKernelGGL((k_sample<DD, LL>), grid, block, lds, st, dof, A, b, n_faces, cap, edges, k0, k1, eid0, n_mix, \
+    EZO_KLAUNCH(c, (k_sample<DD, LL>), grid, block, lds, st, dof, A, b, n_faces, cap, edges, k0, k1, eid0, n_mix, \
                        S, stride, status, it)
     if (D == 4 && L == 8) EZO_LAUNCH_SAMPLE(4, 8);
     else if (D == 4) EZO_LAUNCH_SAMPLE(4, 4);
@@ -231,7 +244,7 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
     const size_t lds = tile_smem_bytes(T, r->S, W);
     dim3 grid((unsigned)((cand_cap + T - 1) / T), (unsigned)E), block(64 * W);
 #define EZO_LAUNCH_PB(TT)                                                                                    \
-    hipLaunchKernelGGL(k_project_bisect<TT>, grid, block, lds, st, r->view, ov, gv, edges, S, stride, cand_idx, \
+    EZO_KLAUNCH(c, (k_project_bisect<TT>), grid, block, lds, st, r->view, ov, gv, edges, S, stride, cand_idx, \
                        n_cands, cand_cap, n_b, c_star, a_dir, t_star, pcol, pany, status)
     switch (T) {
         case 64: EZO_LAUNCH_PB(64); break;
@@ -655,16 +668,20 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
     // records inside a captured graph do not time the kernels).
     auto launch_iteration = [&](bool marks) -> ezo_status {
         ezo_status ls = EZO_OK;
-        auto mark = [&](int i) {
-            if (marks && ls == EZO_OK) {
-                hipError_t me = hipEventRecord(c->tev[i], st);
-                if (me != hipSuccess) ls = fail(c, EZO_E_HIP, "event record failed: %s", hipGetErrorString(me));
+        auto mark = [&](int i) {          // the next launch belongs to phase i
+            if (marks && i < EZO_NUM_PHASES) {
+                c->ev_a = c->tev[2 * i];
+                c->ev_b = c->tev[2 * i + 1];
+            } else {
+                c->ev_a = c->ev_b = nullptr;
             }
         };
         mark(EZO_PHASE_SAMPLE);
         if ((ls = launch_sample(c, dof, A, b, n_faces, cap, edges, E, S_cap, p->n_mix, p->seed, p->edge_id_base,
-                                (float*)w_s, stride, edge_status, it, st)))
+                                (float*)w_s, stride, edge_status, it, st))) {
+            mark(EZO_NUM_PHASES);
             return ls;
+        }
         mark(EZO_PHASE_CHECK);
         GridView gvc = gv, gvb = gv;
         if (marks && c->d_tests) {
@@ -672,23 +689,27 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
             gvb.tests = c->d_tests + EZO_PHASE_BISECT;
         }
         if ((ls = launch_check<false>(c, r, ov, gvc, (const float*)w_s, S_cap, 1, stride, (int64_t)dof * stride,
-                                      (uint8_t*)w_f, nullptr, nullptr, stride, E, edge_status, it, st)))
+                                      (uint8_t*)w_f, nullptr, nullptr, stride, E, edge_status, it, st))) {
+            mark(EZO_NUM_PHASES);
             return ls;
+        }
         mark(EZO_PHASE_TEST);
-        hipLaunchKernelGGL(k_test_select, dim3(E), dim3(1024), 0, st, (const uint8_t*)w_f, stride, p->n_p, p->n_b,
+        EZO_KLAUNCH(c, k_test_select, dim3(E), dim3(1024), 0, st, (const uint8_t*)w_f, stride, p->n_p, p->n_b,
                            (int*)w_ci, cand_cap, (int*)w_nc, nullptr, nullptr, edge_status, (EdgeStatsDev*)w_st, it);
         mark(EZO_PHASE_BISECT);
         if ((ls = launch_project_bisect(c, r, ov, gvb, edges, E, (const float*)w_s, stride, (const int*)w_ci,
                                         (const int*)w_nc, cand_cap, p->n_b, (float*)w_cs, (float*)w_ad,
-                                        (float*)w_ts, (uint8_t*)w_pc, (uint8_t*)w_pa, edge_status, st)))
+                                        (float*)w_ts, (uint8_t*)w_pc, (uint8_t*)w_pa, edge_status, st))) {
+            mark(EZO_NUM_PHASES);
             return ls;
+        }
         mark(EZO_PHASE_PLACE);
-        hipLaunchKernelGGL(k_place, dim3(E), dim3(1024), (size_t)std::max(cand_cap, 16), st, dof, edges,
+        EZO_KLAUNCH(c, k_place, dim3(E), dim3(1024), (size_t)std::max(cand_cap, 16), st, dof, edges,
                            (const float*)w_cs, (const float*)w_ad, (const float*)w_ts, (const int*)w_nc, cand_cap,
                            p->n_f, (float)p->step_back_max, (float)p->t_col, A, b, n_faces, cap, edge_status,
                            nullptr, nullptr, (const uint8_t*)w_pa, (EdgeStatsDev*)w_st);
         mark(EZO_PHASE_ADVANCE);
-        hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, st, (int*)w_k, p->max_iters, edge_status, E, (int*)w_ac);
+        EZO_KLAUNCH(c, k_advance, dim3(1), dim3(256), 0, st, (int*)w_k, p->max_iters, edge_status, E, (int*)w_ac);
         mark(EZO_NUM_PHASES);
         if (ls == EZO_OK) {
             hipError_t le = hipGetLastError();
@@ -730,7 +751,7 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
         if (!exec) {
             for (int ph = 0; ph < EZO_NUM_PHASES; ++ph) {
                 float ms = 0.f;
-                if (hipEventElapsedTime(&ms, c->tev[ph], c->tev[ph + 1]) == hipSuccess) c->phase_ms[ph] += ms;
+                if (hipEventElapsedTime(&ms, c->tev[2 * ph], c->tev[2 * ph + 1]) == hipSuccess) c->phase_ms[ph] += ms;
             }
             c->timed_iters++;
         }

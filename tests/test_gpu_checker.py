@@ -149,3 +149,46 @@ def test_checker_full_size_sweep_sampled(ezo, ctx):
     assert np.abs(msd[idx] - sdo).max() <= SD_TOL
     ff, _, _ = gpu_check(ezo, ctx, rob, obs, q, sd=False)
     assert np.array_equal(ff[idx][out], fo[out])
+
+
+def broad_phase_scenes():
+    rng = np.random.default_rng(77)
+    def cloud(n, lo, hi, rlo, rhi):
+        c = rng.uniform(lo, hi, size=(n, 3))
+        return np.concatenate([c, rng.uniform(rlo, rhi, size=(n, 1))], 1).astype(np.float32)
+    return {
+        # 4096 obstacles packed in a 0.25 m cube: most grid cells overflow their lists
+        "overflow": cloud(4096, [0.4, -0.1, 0.3], [0.65, 0.15, 0.55], 0.01, 0.03),
+        # a cloud far from the arm: every sphere falls outside the grid
+        "far": cloud(1000, [20.0, 20.0, 20.0], [21.0, 21.0, 21.0], 0.02, 0.08),
+        # grid-size thresholds and large obstacles
+        "n31": cloud(31, [-1.0, -1.0, -0.5], [1.0, 1.0, 1.0], 0.05, 0.5),
+        "n32": cloud(32, [-1.0, -1.0, -0.5], [1.0, 1.0, 1.0], 0.05, 0.5),
+        "n255": cloud(255, [-1.0, -1.0, -0.5], [1.0, 1.0, 1.0], 0.02, 0.2),
+        "n256": cloud(256, [-1.0, -1.0, -0.5], [1.0, 1.0, 1.0], 0.02, 0.2),
+        "single": cloud(1, [0.5, 0.0, 0.5], [0.5, 0.0, 0.5], 0.3, 0.3),
+    }
+
+
+@pytest.mark.parametrize("scene", ["overflow", "far", "n31", "n32", "n255", "n256", "single"])
+def test_broad_phase_flags_equal_all_pairs(ezo, ctx, scene):
+    """Flags-only checks use the grid broad phase and link-bound culling of
+    self pairs; flags must equal the plain definition's (oracle) outside the
+    band, and the signed-distance mode's flags (all pairs) everywhere the two
+    modes' own arithmetic agrees."""
+    data, desc = load("dof7")
+    obs = broad_phase_scenes()[scene]
+    print_case("broad phase", scene, len(obs))
+    rob = ezo.Robot(ctx, desc)
+    q = draw.uniform_q(500, 3001, data["q_lo"], data["q_hi"])
+    f_fl, _, _ = gpu_check(ezo, ctx, rob, obs, q, sd=False)
+    f_sd, msd, _ = gpu_check(ezo, ctx, rob, obs, q, sd=True)
+    fo, sdo, seo, sso = oracle.check(oracle.Robot(desc), f32_up(obs), f32_up(q))
+    out = np.abs(sdo) >= BAND
+    print(f"collision fraction {fo.mean():.3f} (env {np.mean(seo < 0):.3f}), band {np.sum(~out)}")
+    assert np.array_equal(f_fl[out], fo[out])
+    assert np.array_equal(f_sd[out], fo[out])
+    if scene == "far":
+        assert np.all(seo > 10.0)
+    if scene == "overflow":
+        assert np.mean(seo < 0) > 0.05
