@@ -118,6 +118,75 @@ def sweep(args):
     print(json.dumps(line), flush=True)
 
 
+def screen_compare(args):
+    """Learned screen: train on exact self-collision labels, calibrate, then
+    time the inflation with and without the screen at identical
+    eps/delta/tau/seed."""
+    import numpy as np
+    import torch
+
+    import paper_2504_10783_amd as ezo
+    import workloads
+    from workloads import draw
+
+    name = args.workload
+    data = workloads.load(name)
+    desc = workloads.robot(data)
+    ctx = ezo.Context(0)
+    rob = ezo.Robot(ctx, desc)
+    dev = torch.device("cuda", 0)
+    n_tr, n_cal, n_te = 3_600_000 // 4096 * 4096, 200_000, 200_000
+    t0 = time.perf_counter()
+    q = torch.from_numpy(draw.uniform_q_fast(404, n_tr + n_cal + n_te, data["q_lo"], data["q_hi"])).to(dev)
+    n = q.shape[0]
+    flags = torch.empty(n, dtype=torch.uint8, device=dev)
+    msd = torch.empty(n, dtype=torch.float32, device=dev)
+    lab = torch.empty(n, dtype=torch.float32, device=dev)
+    ezo.check_collisions(ctx, rob, torch.zeros((0, 4), dtype=torch.float32, device=dev), q, flags, msd, lab)
+    torch.cuda.synchronize()
+    t_lab = time.perf_counter() - t0
+    sur = ezo.Surrogate(ctx, rob.dof, 256, seed=args.seed)
+    tp = ezo.make_train_params(epochs=args.screen_epochs, batch=4096, lr=1e-3, seed=args.seed)
+    t0 = time.perf_counter()
+    losses = sur.train(q[:n_tr], lab[:n_tr], tp)
+    t_train = time.perf_counter() - t0
+    margin = sur.calibrate(q[n_tr:n_tr + n_cal], lab[n_tr:n_tr + n_cal], 1e-3)
+    miss, frac = sur.miss_rate(q[n_tr + n_cal:], lab[n_tr + n_cal:])
+    obs = torch.from_numpy(data["obstacles"]).to(dev)
+    edges = torch.from_numpy(data["edges"]).to(dev)
+    E = edges.shape[0]
+    res = {}
+    for mode in ("exact", "screened"):
+        prm = ezo.make_params(dof=rob.dof, seed=args.seed, surrogate=sur if mode == "screened" else None,
+                              **workloads.PARAMS[name])
+        for _ in range(args.warmup):
+            ezo.inflate_edges(ctx, rob, obs, edges, prm)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        checks = screened = 0
+        for _ in range(args.steps):
+            r = ezo.inflate_edges(ctx, rob, obs, edges, prm)
+            checks += sum(x["exact_checks"] for x in r.stats)
+            screened += sum(x["screened_checks"] for x in r.stats)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / args.steps
+        st = r.status.cpu().numpy()
+        res[mode] = {"ms_per_step": dt * 1e3, "edges_per_s": E / dt, "configs_per_s": checks / args.steps / dt,
+                     "screened_fraction_of_checks": screened / max(checks, 1),
+                     "certified": int(np.sum(st == 0)), "iterations_mean": float(np.mean([x["iterations"] for x in r.stats])),
+                     "planes_mean": float(np.mean([x["planes"] for x in r.stats]))}
+    line = {"metric": "edges inflated/sec, learned self-collision screen vs exact (7-DOF)",
+            "value": res["screened"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32 checks, bf16 MFMA screen", "data": "synthetic",
+            "config": {"workload": f"{name}: {WORKLOADS[name]}", "labels": n, "train": n_tr, "calibration": n_cal,
+                       "test": n_te, "alpha": 1e-3, "epochs": args.screen_epochs},
+            "speedup_vs_exact": res["screened"]["edges_per_s"] / res["exact"]["edges_per_s"],
+            "miss_rate_test": miss, "screened_fraction_test": frac, "margin": margin,
+            "label_seconds": t_lab, "train_seconds": t_train, "epoch_losses": losses, **res}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +196,8 @@ def main():
     ap.add_argument("--sweep-sizes", default="1048576,4194304,16777216")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--screen", action="store_true", help="learned screen vs exact comparison")
+    ap.add_argument("--screen-epochs", type=int, default=10)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -137,6 +208,9 @@ def main():
 
     if args.workload == "sweep":
         sweep(args)
+        return
+    if args.screen:
+        screen_compare(args)
         return
 
     import numpy as np

@@ -45,6 +45,7 @@ extern "C" {
 
 typedef struct ezo_ctx ezo_ctx;
 typedef struct ezo_robot ezo_robot;
+typedef struct ezo_surrogate ezo_surrogate;
 typedef int32_t ezo_status;
 
 enum {
@@ -102,6 +103,11 @@ typedef struct {
     uint64_t seed;           /* Philox key                                          */
     int64_t edge_id_base;    /* edge e of this call draws the random stream of
                                 edge id (edge_id_base + e)                           */
+    const ezo_surrogate *surrogate;  /* NULL = exact checks only.  Otherwise the
+                                learned screen skips the exact self-collision
+                                pairs of samples after the first M_k (never of
+                                the test samples) whose predicted self distance
+                                is >= the screen's calibrated margin           */
 } ezo_params;
 
 typedef struct {
@@ -111,6 +117,7 @@ typedef struct {
     int64_t test_collisions; /* collisions among the first M_k samples, last test   */
     int64_t samples;         /* samples drawn (sum of |S| over iterations)          */
     int64_t exact_checks;    /* configurations collision-checked                    */
+    int64_t screened_checks; /* of those, checks whose self pairs the screen skipped */
 } ezo_edge_stats;
 
 /* ---- context and robot ------------------------------------------------- */
@@ -239,6 +246,57 @@ ezo_status ezo_inflate_edges(ezo_ctx *ctx, const ezo_robot *robot, const float *
                              const float *edges, int32_t n_edges, const ezo_params *params, float *A,
                              float *b, int32_t *n_faces, int32_t *edge_status, ezo_edge_stats *stats,
                              void *stream);
+
+/* ---- learned self-collision screen ------------------------------------ */
+/* A multilayer perceptron dof -> H -> H -> H -> 1 with SiLU activations
+ * predicting a configuration's minimum self-collision signed distance from
+ * x = q / pi (BF16 MFMA layers, FP32 accumulation and master weights).
+ * Trained with this library's own forward/backward kernels and Adam on
+ * labels produced by the exact checker; used by ezo_inflate_edges only to
+ * skip exact self pairs of optimizer samples (never of the unadaptive test's
+ * samples), so certification never depends on it.  Callers: anyone wanting
+ * to trade exact self-pair work for a network evaluation.
+ * Parameters are one flat FP32 vector W1[H][dof] b1[H] W2[H][H] b2[H]
+ * W3[H][H] b3[H] W4[H] b4[1] (z = W a + b). */
+typedef struct {
+    int32_t epochs;          /* passes over the training rows                       */
+    int32_t batch;           /* rows per Adam step, a multiple of 64                */
+    double lr;               /* peak learning rate, cosine decay to 0               */
+    double beta1, beta2, adam_eps;
+    double huber_delta;      /* Huber loss threshold                                */
+    double clip_lo, clip_hi; /* targets are clipped to [clip_lo, clip_hi]           */
+    uint64_t seed;           /* batch order                                         */
+} ezo_train_params;
+
+int64_t ezo_surrogate_num_params(int32_t dof, int32_t hidden);
+/* hidden: multiple of 64 in [64, 4096].  Weights ~ U(+-1/sqrt(fan_in)) from seed;
+ * margin = +inf (screens nothing) until calibrated. */
+ezo_status ezo_surrogate_create(ezo_ctx *ctx, int32_t dof, int32_t hidden, uint64_t seed, ezo_surrogate **out);
+void ezo_surrogate_destroy(ezo_surrogate *s);
+/* host [n] parameter copies (n = ezo_surrogate_num_params); set resets Adam. */
+ezo_status ezo_surrogate_set_params(ezo_surrogate *s, const float *params, int64_t n);
+ezo_status ezo_surrogate_get_params(const ezo_surrogate *s, float *params, int64_t n);
+/* Adam training on rows q dev f32 [n][dof] with targets dev f32 [n];
+ * epoch_loss host [epochs] (mean Huber loss per epoch) may be NULL.  Blocks. */
+ezo_status ezo_surrogate_train(ezo_ctx *ctx, ezo_surrogate *s, const float *q, const float *target, int64_t n,
+                               const ezo_train_params *tp, float *epoch_loss, void *stream);
+/* Mean loss (host) and its gradient (host f32 [num_params]) over n rows
+ * (n a multiple of 64, <= 2^20) without updating the weights.  Blocks. */
+ezo_status ezo_surrogate_loss_grad(ezo_ctx *ctx, ezo_surrogate *s, const float *q, const float *target, int64_t n,
+                                   const ezo_train_params *tp, float *grad, double *loss, void *stream);
+/* Predictions pred dev f32 [n] for q dev f32 [n][dof]. */
+ezo_status ezo_surrogate_predict(ezo_ctx *ctx, const ezo_surrogate *s, const float *q, int64_t n, float *pred,
+                                 void *stream);
+/* Margin m = smallest value with #{pred >= m and target < 0} <= alpha
+ * #{target < 0} on the given rows (conformal-style calibration); stored in
+ * the screen and returned.  Blocks. */
+ezo_status ezo_surrogate_calibrate(ezo_ctx *ctx, ezo_surrogate *s, const float *q, const float *target, int64_t n,
+                                   double alpha, double *margin_out, void *stream);
+ezo_status ezo_surrogate_set_margin(ezo_surrogate *s, double margin);
+/* On held-out rows: miss rate = #{pred >= m and target < 0} / #{target < 0};
+ * screened fraction = #{pred >= m} / n.  Blocks. */
+ezo_status ezo_surrogate_miss_rate(ezo_ctx *ctx, const ezo_surrogate *s, const float *q, const float *target,
+                                   int64_t n, double *miss_rate, double *screened_fraction, void *stream);
 
 /* ---- instrumentation ------------------------------------------------- */
 

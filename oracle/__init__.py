@@ -14,7 +14,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "ezo_oracle.c")
+_SRC = [os.path.join(_HERE, "ezo_oracle.c"), os.path.join(_HERE, "mlp_oracle.c")]
 _SO = os.path.join(_HERE, "libezo_oracle.so")
 
 CERTIFIED, MAX_ITERS, IN_COLLISION, INVALID = 0, 1, 2, 3
@@ -25,7 +25,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
-                               "-Wall", "-Wno-unknown-pragmas", "-o", tmp, _SRC, "-lm"])
+                               "-Wall", "-Wno-unknown-pragmas", "-o", tmp, *_SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -101,6 +101,15 @@ def _declare(L):
     L.orc_eizo_balls.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, C.c_int32, _dp, _dp,
                                  C.POINTER(Params), _dp, _dp, C.c_int32, _ip, C.POINTER(Stats)]
     L.orc_eizo_balls.restype = C.c_int
+    L.orc_mlp_num_params.argtypes = [C.c_int32, C.c_int32]
+    L.orc_mlp_num_params.restype = C.c_int64
+    L.orc_mlp_forward.argtypes = [C.c_int32, C.c_int32, _dp, _dp, C.c_int64, _dp]
+    L.orc_mlp_loss_grad.argtypes = [C.c_int32, C.c_int32, _dp, _dp, _dp, C.c_int64, C.c_double, C.c_double,
+                                    C.c_double, _dp]
+    L.orc_mlp_loss_grad.restype = C.c_double
+    L.orc_mlp_loss.argtypes = [C.c_int32, C.c_int32, _dp, _dp, _dp, C.c_int64, C.c_double, C.c_double,
+                               C.c_double]
+    L.orc_mlp_loss.restype = C.c_double
     L.orc_set_threads.argtypes = [C.c_int32]
     L.orc_max_threads.restype = C.c_int32
 
@@ -309,3 +318,31 @@ def eizo_balls(centres, radii, A_D, b_D, v1, v2, prm: Params, cap=None):
                                     _ptr(b_D), len(b_D), _ptr(v1), _ptr(v2), C.byref(prm),
                                     _ptr(A), _ptr(b), cap, C.byref(nf), C.byref(st))
     return _eizo_common(call, dim, A_D, b_D, v1, v2, prm, cap)
+
+
+# ---------------------------------------------------------------------------
+# Learned self-collision screen: FP64 multilayer perceptron
+# ---------------------------------------------------------------------------
+
+def mlp_num_params(D: int, H: int) -> int:
+    return int(lib().orc_mlp_num_params(D, H))
+
+
+def mlp_forward(D, H, params, x):
+    params, x = _d(params), _d(x).reshape(-1, D)
+    y = np.empty(len(x))
+    lib().orc_mlp_forward(D, H, _ptr(params), _ptr(x), len(x), _ptr(y))
+    return y
+
+
+def mlp_loss_grad(D, H, params, x, t, huber_delta=0.05, clip_lo=-0.3, clip_hi=0.5):
+    params, x, t = _d(params), _d(x).reshape(-1, D), _d(t)
+    g = np.empty_like(params)
+    loss = lib().orc_mlp_loss_grad(D, H, _ptr(params), _ptr(x), _ptr(t), len(x), huber_delta, clip_lo, clip_hi,
+                                   _ptr(g))
+    return float(loss), g
+
+
+def mlp_loss(D, H, params, x, t, huber_delta=0.05, clip_lo=-0.3, clip_hi=0.5):
+    params, x, t = _d(params), _d(x).reshape(-1, D), _d(t)
+    return float(lib().orc_mlp_loss(D, H, _ptr(params), _ptr(x), _ptr(t), len(x), huber_delta, clip_lo, clip_hi))

@@ -26,6 +26,9 @@ EXPORTS = (
     "ezo_check_collisions", "ezo_sphere_centres", "ezo_test_constants", "ezo_sample_polytopes",
     "ezo_test_and_select", "ezo_project_bisect", "ezo_place_hyperplanes", "ezo_inflate_edges",
     "ezo_set_phase_timing", "ezo_get_phase_timing",
+    "ezo_surrogate_num_params", "ezo_surrogate_create", "ezo_surrogate_destroy", "ezo_surrogate_set_params",
+    "ezo_surrogate_get_params", "ezo_surrogate_train", "ezo_surrogate_loss_grad", "ezo_surrogate_predict",
+    "ezo_surrogate_calibrate", "ezo_surrogate_set_margin", "ezo_surrogate_miss_rate",
 )
 PHASES = ("sample", "check", "test", "bisect", "place", "advance")
 
@@ -48,12 +51,20 @@ class Params(C.Structure):
     _fields_ = [("eps", C.c_double), ("delta", C.c_double), ("tau", C.c_double),
                 ("step_back_max", C.c_double), ("t_col", C.c_double), ("n_p", C.c_int32),
                 ("n_f", C.c_int32), ("n_b", C.c_int32), ("n_mix", C.c_int32), ("max_iters", C.c_int32),
-                ("face_capacity", C.c_int32), ("seed", C.c_uint64), ("edge_id_base", C.c_int64)]
+                ("face_capacity", C.c_int32), ("seed", C.c_uint64), ("edge_id_base", C.c_int64),
+                ("surrogate", C.c_void_p)]
+
+
+class TrainParams(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("adam_eps", C.c_double), ("huber_delta", C.c_double),
+                ("clip_lo", C.c_double), ("clip_hi", C.c_double), ("seed", C.c_uint64)]
 
 
 class EdgeStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("planes", C.c_int32), ("final_m", C.c_int64),
-                ("test_collisions", C.c_int64), ("samples", C.c_int64), ("exact_checks", C.c_int64)]
+                ("test_collisions", C.c_int64), ("samples", C.c_int64), ("exact_checks", C.c_int64),
+                ("screened_checks", C.c_int64)]
 
 
 _lib = None
@@ -87,6 +98,20 @@ def lib():
                                         C.POINTER(EdgeStats), vp]
         L.ezo_set_phase_timing.argtypes = [vp, i32]
         L.ezo_get_phase_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(i64)]
+        tp = C.POINTER(TrainParams)
+        L.ezo_surrogate_num_params.argtypes = [i32, i32]
+        L.ezo_surrogate_num_params.restype = i64
+        L.ezo_surrogate_create.argtypes = [vp, i32, i32, u64, C.POINTER(vp)]
+        L.ezo_surrogate_destroy.argtypes = [vp]
+        L.ezo_surrogate_destroy.restype = None
+        L.ezo_surrogate_set_params.argtypes = [vp, C.POINTER(C.c_float), i64]
+        L.ezo_surrogate_get_params.argtypes = [vp, C.POINTER(C.c_float), i64]
+        L.ezo_surrogate_train.argtypes = [vp, vp, vp, vp, i64, tp, C.POINTER(C.c_float), vp]
+        L.ezo_surrogate_loss_grad.argtypes = [vp, vp, vp, vp, i64, tp, C.POINTER(C.c_float), C.POINTER(dbl), vp]
+        L.ezo_surrogate_predict.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.ezo_surrogate_calibrate.argtypes = [vp, vp, vp, vp, i64, dbl, C.POINTER(dbl), vp]
+        L.ezo_surrogate_set_margin.argtypes = [vp, dbl]
+        L.ezo_surrogate_miss_rate.argtypes = [vp, vp, vp, vp, i64, C.POINTER(dbl), C.POINTER(dbl), vp]
         for name in EXPORTS:
             fn = getattr(L, name)
             if fn.restype is C.c_int:
@@ -309,11 +334,96 @@ class InflateResult:
 
 
 def make_params(eps, delta, tau=0.5, step_back_max=0.01, t_col=1e-4, n_p=1000, n_f=10, n_b=11, n_mix=30,
-                max_iters=50, face_capacity=None, seed=0, edge_id_base=0, dof=None) -> Params:
+                max_iters=50, face_capacity=None, seed=0, edge_id_base=0, dof=None, surrogate=None) -> Params:
     if face_capacity is None:
         face_capacity = 2 * (dof or MAX_DOF) + n_f * max_iters
     return Params(eps, delta, tau, step_back_max, t_col, n_p, n_f, n_b, n_mix, max_iters, face_capacity, seed,
-                  edge_id_base)
+                  edge_id_base, surrogate.h.value if surrogate is not None else None)
+
+
+def make_train_params(epochs=10, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, huber_delta=0.05,
+                      clip_lo=-0.3, clip_hi=0.5, seed=0) -> TrainParams:
+    return TrainParams(epochs, batch, lr, beta1, beta2, adam_eps, huber_delta, clip_lo, clip_hi, seed)
+
+
+def surrogate_num_params(dof: int, hidden: int) -> int:
+    return int(lib().ezo_surrogate_num_params(dof, hidden))
+
+
+class Surrogate:
+    """Learned self-collision screen (MLP dof -> H -> H -> H -> 1, SiLU,
+    BF16 MFMA layers) owned by a context."""
+
+    def __init__(self, ctx: Context, dof: int, hidden: int = 256, seed: int = 0):
+        self.ctx = ctx
+        self.dof, self.hidden = int(dof), int(hidden)
+        h = C.c_void_p()
+        ctx._check(lib().ezo_surrogate_create(ctx.h, self.dof, self.hidden, int(seed), C.byref(h)))
+        self.h = h
+        self.n_params = surrogate_num_params(self.dof, self.hidden)
+        self.margin = float("inf")
+
+    def close(self):
+        if self.h:
+            lib().ezo_surrogate_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.empty(self.n_params, np.float32)
+        self.ctx._check(lib().ezo_surrogate_get_params(self.h, out.ctypes.data_as(C.POINTER(C.c_float)),
+                                                       self.n_params))
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self.ctx._check(lib().ezo_surrogate_set_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float)), len(p)))
+
+    def train(self, q, target, tp: TrainParams, stream=None):
+        torch = _torch()
+        _need(q, torch.float32, "q")
+        _need(target, torch.float32, "target", q.shape[0])
+        losses = (C.c_float * max(tp.epochs, 1))()
+        self.ctx._check(lib().ezo_surrogate_train(self.ctx.h, self.h, _ptr(q), _ptr(target), q.shape[0],
+                                                  C.byref(tp), losses, _stream(stream)))
+        return [losses[i] for i in range(tp.epochs)]
+
+    def loss_grad(self, q, target, tp: TrainParams, stream=None):
+        grad = np.empty(self.n_params, np.float32)
+        loss = C.c_double()
+        self.ctx._check(lib().ezo_surrogate_loss_grad(self.ctx.h, self.h, _ptr(q), _ptr(target), q.shape[0],
+                                                      C.byref(tp), grad.ctypes.data_as(C.POINTER(C.c_float)),
+                                                      C.byref(loss), _stream(stream)))
+        return loss.value, grad
+
+    def predict(self, q, out, stream=None):
+        torch = _torch()
+        _need(q, torch.float32, "q")
+        _need(out, torch.float32, "out", q.shape[0])
+        self.ctx._check(lib().ezo_surrogate_predict(self.ctx.h, self.h, _ptr(q), q.shape[0], _ptr(out),
+                                                    _stream(stream)))
+
+    def calibrate(self, q, target, alpha, stream=None):
+        m = C.c_double()
+        self.ctx._check(lib().ezo_surrogate_calibrate(self.ctx.h, self.h, _ptr(q), _ptr(target), q.shape[0],
+                                                      float(alpha), C.byref(m), _stream(stream)))
+        self.margin = m.value
+        return m.value
+
+    def set_margin(self, m):
+        self.ctx._check(lib().ezo_surrogate_set_margin(self.h, float(m)))
+        self.margin = float(m)
+
+    def miss_rate(self, q, target, stream=None):
+        miss, frac = C.c_double(), C.c_double()
+        self.ctx._check(lib().ezo_surrogate_miss_rate(self.ctx.h, self.h, _ptr(q), _ptr(target), q.shape[0],
+                                                      C.byref(miss), C.byref(frac), _stream(stream)))
+        return miss.value, frac.value
 
 
 def inflate_edges(ctx: Context, robot: Robot, obs, edges, params: Params, out=None, stream=None) -> InflateResult:

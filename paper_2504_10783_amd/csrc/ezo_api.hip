@@ -3,70 +3,14 @@
 // stream; robots are uploaded once and rounded to FP32; the fused inflation
 // captures one iteration of kernels into a hipGraph and replays it, polling a
 // 4-byte active-edge counter after each replay.
-#include <hip/hip_ext.h>
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cmath>
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
-#include <string>
-#include <vector>
-
-#include "ezo.h"
+#include "ezo_internal.hpp"
 #include "ezo_kernels.hpp"
 
 using namespace ezo;
 
-namespace {
+std::string g_create_err;
 
-constexpr int kNumCU = 256;
-
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-};
-
-}  // namespace
-
-struct ezo_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;      // internal stream (default priority)
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    size_t lds_cap = 65536;
-    std::string err;
-    std::vector<DevBuf> ws;            // named workspace slots
-    int* pinned = nullptr;             // host-pinned poll word
-    bool timing = false;               // per-phase timing of the fused loop
-    hipEvent_t tev[2 * EZO_NUM_PHASES] = {};   // (start, stop) of each phase's kernel
-    hipEvent_t ev_a = nullptr, ev_b = nullptr;   // events for the next kernel launch (timing mode)
-    double phase_ms[EZO_NUM_PHASES] = {};
-    int64_t timed_iters = 0;
-    unsigned long long* d_tests = nullptr;   // [EZO_NUM_PHASES] sphere-sphere tests per phase
-};
-
-struct ezo_robot {
-    ezo_ctx* ctx = nullptr;
-    int dof = 0, S = 0, P = 0;
-    float r_max = 0.f;                 // largest sphere radius
-    void* buf = nullptr;               // one device allocation holding everything below
-    RobotView view{};
-    const int* sorted_to_orig = nullptr;
-    const float* q_lo = nullptr;
-    const float* q_hi = nullptr;
-};
-
-static std::string g_create_err;
-
-namespace {
-
-enum Slot {
-    W_OBS_REC, W_OBS_CENTRE, W_GRID_GEOM, W_GRID_COUNT, W_GRID_LIST, W_SAMPLES, W_FLAGS, W_CAND, W_NCAND, W_CSTAR, W_ADIR, W_TSTAR, W_PCOL,
-    W_PANY, W_STATS, W_TABLE, W_KDEV, W_ACTIVE, W_NSLOTS
-};
-
-ezo_status fail(ezo_ctx* c, ezo_status code, const char* fmt, ...) {
+ezo_status ezo_fail(ezo_ctx* c, ezo_status code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -77,24 +21,7 @@ ezo_status fail(ezo_ctx* c, ezo_status code, const char* fmt, ...) {
     return code;
 }
 
-#define HIP_TRY(ctx, call)                                                                      \
-    do {                                                                                        \
-        hipError_t e_ = (call);                                                                 \
-        if (e_ != hipSuccess) return fail(ctx, EZO_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
-
-// Kernel launch; in timing mode the dispatch itself records c->ev_a / c->ev_b
-// at its start and end (hipExtLaunchKernelGGL), so elapsed time is the
-// kernel's own duration.
-#define EZO_KLAUNCH(c, K, grid, block, lds, st, ...)                                              \
-    do {                                                                                          \
-        if ((c)->ev_a)                                                                            \
-            hipExtLaunchKernelGGL(K, grid, block, lds, st, (c)->ev_a, (c)->ev_b, 0, __VA_ARGS__); \
-        else                                                                                      \
-            hipLaunchKernelGGL(K, grid, block, lds, st, __VA_ARGS__);                              \
-    } while (0)
-
-ezo_status ws_get(ezo_ctx* c, int slot, size_t bytes, void** out) {
+ezo_status ezo_ws_get(ezo_ctx* c, int slot, size_t bytes, void** out) {
     DevBuf& b = c->ws[slot];
     if (bytes == 0) bytes = 16;
     if (b.bytes < bytes) {
@@ -107,7 +34,7 @@ ezo_status ws_get(ezo_ctx* c, int slot, size_t bytes, void** out) {
         size_t nb = bytes + bytes / 4 + 256;
         if (hipMalloc(&b.p, nb) != hipSuccess) {
             b.p = nullptr;
-            return fail(c, EZO_E_NOMEM, "device allocation of %zu bytes failed", nb);
+            return ezo_fail(c, EZO_E_NOMEM, "device allocation of %zu bytes failed", nb);
         }
         b.bytes = nb;
     }
@@ -115,7 +42,8 @@ ezo_status ws_get(ezo_ctx* c, int slot, size_t bytes, void** out) {
     return EZO_OK;
 }
 
-hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+namespace {
+
 
 // Tile size for a tile check: largest T whose LDS fits and that still gives
 // at least ~4 workgroups per CU; W waves split the obstacles.
@@ -157,11 +85,11 @@ ezo_status prep_obstacles(ezo_ctx* c, const ezo_robot* r, const float* obs, int 
     void *rec, *centre, *geom, *count, *list;
     const int G = grid_dim(n_obs);
     const size_t cells = (size_t)G * G * G;
-    if ((s = ws_get(c, W_OBS_REC, sizeof(float4) * 2 * (size_t)std::max(n_obs, 1), &rec)) != EZO_OK) return s;
-    if ((s = ws_get(c, W_OBS_CENTRE, sizeof(float4), &centre)) != EZO_OK) return s;
-    if ((s = ws_get(c, W_GRID_GEOM, sizeof(GridGeom), &geom)) != EZO_OK) return s;
-    if ((s = ws_get(c, W_GRID_COUNT, sizeof(int) * cells, &count)) != EZO_OK) return s;
-    if ((s = ws_get(c, W_GRID_LIST, sizeof(unsigned short) * cells * kGridCap, &list)) != EZO_OK) return s;
+    if ((s = ezo_ws_get(c, W_OBS_REC, sizeof(float4) * 2 * (size_t)std::max(n_obs, 1), &rec)) != EZO_OK) return s;
+    if ((s = ezo_ws_get(c, W_OBS_CENTRE, sizeof(float4), &centre)) != EZO_OK) return s;
+    if ((s = ezo_ws_get(c, W_GRID_GEOM, sizeof(GridGeom), &geom)) != EZO_OK) return s;
+    if ((s = ezo_ws_get(c, W_GRID_COUNT, sizeof(int) * cells, &count)) != EZO_OK) return s;
+    if ((s = ezo_ws_get(c, W_GRID_LIST, sizeof(unsigned short) * cells * kGridCap, &list)) != EZO_OK) return s;
     hipLaunchKernelGGL(k_prep_obstacles, dim3(1), dim3(256), 0, st, obs, n_obs, (float4*)rec, (float4*)centre,
                        (GridGeom*)geom, G, r ? r->r_max : 0.f);
     hipLaunchKernelGGL(k_build_grid, dim3((unsigned)((cells * 64 + 255) / 256)), dim3(256), 0, st,
@@ -184,17 +112,18 @@ template <bool SD>
 ezo_status launch_check(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const GridView& gv, const float* q, int64_t n,
                         int64_t sn, int64_t sd, int64_t q_batch, uint8_t* flags, float* min_sd,
                         float* min_sd_self, int64_t out_batch, int n_batch, const int* status,
-                        const IterArgs& it, hipStream_t st) {
+                        const IterArgs& it, hipStream_t st, const float* pred = nullptr, float margin = 0.f,
+                        EdgeStatsDev* stats = nullptr) {
     const int W = SD ? pick_W(ov.n) : 4;
     const int T = pick_T(c, n * n_batch, r->S, W);
-    if (T == 0) return fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
+    if (T == 0) return ezo_fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
     const size_t lds = tile_smem_bytes(T, r->S, W);
     const int64_t tiles = (n + T - 1) / T;
     if (tiles <= 0) return EZO_OK;
     dim3 grid((unsigned)tiles, (unsigned)n_batch), block(64 * W);
 #define EZO_LAUNCH_CHECK(TT)                                                                          \
     EZO_KLAUNCH(c, (k_check<TT, SD>), grid, block, lds, st, r->view, ov, gv, q, n, sn, sd, q_batch, flags, \
-                       min_sd, min_sd_self, out_batch, status, it)
+                       min_sd, min_sd_self, out_batch, status, it, pred, margin, stats)
     switch (T) {
         case 64: EZO_LAUNCH_CHECK(64); break;
         case 32: EZO_LAUNCH_CHECK(32); break;
@@ -214,7 +143,7 @@ ezo_status launch_sample(ezo_ctx* c, int dof, const float* A, const float* b, co
                          float* S, int64_t stride, const int* status, const IterArgs& it, hipStream_t st) {
     const int D = dof <= 4 ? 4 : 8;
     const size_t lds = sizeof(float) * (size_t)cap * (D + 1);
-    if (lds > c->lds_cap) return fail(c, EZO_E_UNSUPPORTED, "face capacity %d too large for the sampler", cap);
+    if (lds > c->lds_cap) return ezo_fail(c, EZO_E_UNSUPPORTED, "face capacity %d too large for the sampler", cap);
     if (max_samples <= 0 || E <= 0) return EZO_OK;
     // lanes per walk: 8 when walks are few (fill the chip), else 4
     const int L = ((int64_t)max_samples * E * 8 <= 64LL * 4 * 4 * kNumCU * 64) ? 8 : 4;
@@ -240,7 +169,7 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
                                  uint8_t* pcol, uint8_t* pany, const int* status, hipStream_t st) {
     const int W = 4;
     const int T = std::min(pick_T(c, (int64_t)cand_cap * E, r->S, W), 64);
-    if (T == 0) return fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
+    if (T == 0) return ezo_fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
     const size_t lds = tile_smem_bytes(T, r->S, W);
     dim3 grid((unsigned)((cand_cap + T - 1) / T), (unsigned)E), block(64 * W);
 #define EZO_LAUNCH_PB(TT)                                                                                    \
@@ -270,12 +199,12 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 extern "C" {
 
 ezo_status ezo_ctx_create(int32_t device, ezo_ctx** out) {
-    if (!out) return fail(nullptr, EZO_E_INVALID, "out is NULL");
+    if (!out) return ezo_fail(nullptr, EZO_E_INVALID, "out is NULL");
     *out = nullptr;
     int n = 0;
-    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(nullptr, EZO_E_HIP, "no HIP device");
-    if (device < 0 || device >= n) return fail(nullptr, EZO_E_INVALID, "device %d out of range", device);
-    if (hipSetDevice(device) != hipSuccess) return fail(nullptr, EZO_E_HIP, "hipSetDevice failed");
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return ezo_fail(nullptr, EZO_E_HIP, "no HIP device");
+    if (device < 0 || device >= n) return ezo_fail(nullptr, EZO_E_INVALID, "device %d out of range", device);
+    if (hipSetDevice(device) != hipSuccess) return ezo_fail(nullptr, EZO_E_HIP, "hipSetDevice failed");
     ezo_ctx* c = new ezo_ctx();
     c->device = device;
     c->ws.resize(W_NSLOTS);
@@ -287,7 +216,7 @@ ezo_status ezo_ctx_create(int32_t device, ezo_ctx** out) {
         hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
         hipHostMalloc((void**)&c->pinned, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
         ezo_ctx_destroy(c);
-        return fail(nullptr, EZO_E_HIP, "stream/event/pinned allocation failed");
+        return ezo_fail(nullptr, EZO_E_HIP, "stream/event/pinned allocation failed");
     }
     *out = c;
     return EZO_OK;
@@ -314,28 +243,28 @@ void ezo_ctx_destroy(ezo_ctx* c) {
 const char* ezo_last_error(const ezo_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
 ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out) {
-    if (!c || !d || !out) return fail(c, EZO_E_INVALID, "NULL argument");
+    if (!c || !d || !out) return ezo_fail(c, EZO_E_INVALID, "NULL argument");
     *out = nullptr;
-    if (d->dof < 1 || d->dof > EZO_MAX_DOF) return fail(c, EZO_E_UNSUPPORTED, "dof %d not in [1, %d]", d->dof, EZO_MAX_DOF);
+    if (d->dof < 1 || d->dof > EZO_MAX_DOF) return ezo_fail(c, EZO_E_UNSUPPORTED, "dof %d not in [1, %d]", d->dof, EZO_MAX_DOF);
     if (d->n_spheres < 0 || d->n_spheres > EZO_MAX_SPHERES)
-        return fail(c, EZO_E_UNSUPPORTED, "n_spheres %d not in [0, %d]", d->n_spheres, EZO_MAX_SPHERES);
-    if (d->n_self_pairs < 0) return fail(c, EZO_E_INVALID, "n_self_pairs < 0");
+        return ezo_fail(c, EZO_E_UNSUPPORTED, "n_spheres %d not in [0, %d]", d->n_spheres, EZO_MAX_SPHERES);
+    if (d->n_self_pairs < 0) return ezo_fail(c, EZO_E_INVALID, "n_self_pairs < 0");
     if (!d->dh_a || !d->dh_alpha || !d->dh_d || !d->q_lo || !d->q_hi)
-        return fail(c, EZO_E_INVALID, "NULL DH or limit array");
+        return ezo_fail(c, EZO_E_INVALID, "NULL DH or limit array");
     if (d->n_spheres > 0 && (!d->sphere_link || !d->sphere_xyz || !d->sphere_r))
-        return fail(c, EZO_E_INVALID, "NULL sphere array");
-    if (d->n_self_pairs > 0 && !d->self_pairs) return fail(c, EZO_E_INVALID, "NULL self_pairs");
+        return ezo_fail(c, EZO_E_INVALID, "NULL sphere array");
+    if (d->n_self_pairs > 0 && !d->self_pairs) return ezo_fail(c, EZO_E_INVALID, "NULL self_pairs");
     const int dof = d->dof, S = d->n_spheres, P = d->n_self_pairs;
     for (int j = 0; j < dof; ++j)
-        if (!(d->q_lo[j] <= d->q_hi[j])) return fail(c, EZO_E_INVALID, "q_lo[%d] > q_hi[%d]", j, j);
+        if (!(d->q_lo[j] <= d->q_hi[j])) return ezo_fail(c, EZO_E_INVALID, "q_lo[%d] > q_hi[%d]", j, j);
     for (int s = 0; s < S; ++s) {
         if (d->sphere_link[s] < 0 || d->sphere_link[s] >= dof)
-            return fail(c, EZO_E_INVALID, "sphere %d has link %d", s, d->sphere_link[s]);
-        if (!(d->sphere_r[s] >= 0.0)) return fail(c, EZO_E_INVALID, "sphere %d has a negative radius", s);
+            return ezo_fail(c, EZO_E_INVALID, "sphere %d has link %d", s, d->sphere_link[s]);
+        if (!(d->sphere_r[s] >= 0.0)) return ezo_fail(c, EZO_E_INVALID, "sphere %d has a negative radius", s);
     }
     for (int p = 0; p < 2 * P; ++p)
         if (d->self_pairs[p] < 0 || d->self_pairs[p] >= S)
-            return fail(c, EZO_E_INVALID, "self pair entry %d = %d out of range", p, d->self_pairs[p]);
+            return ezo_fail(c, EZO_E_INVALID, "self pair entry %d = %d out of range", p, d->self_pairs[p]);
     // sort spheres by link (stable), remember the original order
     std::vector<int> order(S);
     for (int s = 0; s < S; ++s) order[s] = s;
@@ -421,11 +350,11 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     memcpy(host.data() + off_lim, lim.data(), sizeof(float) * lim.size());
     HIP_TRY(c, hipSetDevice(c->device));
     void* buf = nullptr;
-    if (hipMalloc(&buf, total) != hipSuccess) return fail(c, EZO_E_NOMEM, "robot allocation failed");
+    if (hipMalloc(&buf, total) != hipSuccess) return ezo_fail(c, EZO_E_NOMEM, "robot allocation failed");
     if (hipMemcpy(buf, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
         hipError_t e = hipFree(buf);
         (void)e;
-        return fail(c, EZO_E_HIP, "robot upload failed");
+        return ezo_fail(c, EZO_E_HIP, "robot upload failed");
     }
     ezo_robot* r = new ezo_robot();
     r->ctx = c;
@@ -475,10 +404,10 @@ ezo_status ezo_check_collisions(ezo_ctx* c, const ezo_robot* r, const float* obs
                                 int64_t n, int64_t stride_n, int64_t stride_d, uint8_t* flags, float* min_sd,
                                 float* min_sd_self, void* stream) {
     if (!c) return EZO_E_INVALID;
-    if (!r) return fail(c, EZO_E_INVALID, "robot is NULL");
-    if (n < 0 || n_obs < 0) return fail(c, EZO_E_INVALID, "negative size");
+    if (!r) return ezo_fail(c, EZO_E_INVALID, "robot is NULL");
+    if (n < 0 || n_obs < 0) return ezo_fail(c, EZO_E_INVALID, "negative size");
     if (n == 0) return EZO_OK;
-    if (!q || !flags || (n_obs > 0 && !obs)) return fail(c, EZO_E_INVALID, "NULL buffer");
+    if (!q || !flags || (n_obs > 0 && !obs)) return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
     HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t st = as_stream(stream);
     ObsView ov;
@@ -496,9 +425,9 @@ ezo_status ezo_check_collisions(ezo_ctx* c, const ezo_robot* r, const float* obs
 ezo_status ezo_sphere_centres(ezo_ctx* c, const ezo_robot* r, const float* q, int64_t n, int64_t stride_n,
                               int64_t stride_d, float* centres, void* stream) {
     if (!c) return EZO_E_INVALID;
-    if (!r || n < 0) return fail(c, EZO_E_INVALID, "bad argument");
+    if (!r || n < 0) return ezo_fail(c, EZO_E_INVALID, "bad argument");
     if (n == 0 || r->S == 0) return EZO_OK;
-    if (!q || !centres) return fail(c, EZO_E_INVALID, "NULL buffer");
+    if (!q || !centres) return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
     HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t st = as_stream(stream);
     ObsView ov;
@@ -527,9 +456,9 @@ ezo_status ezo_sample_polytopes(ezo_ctx* c, int32_t dof, const float* A, const f
     if (!c) return EZO_E_INVALID;
     if (dof < 1 || dof > EZO_MAX_DOF || n_edges < 0 || n_samples < 0 || n_mix < 0 || iteration < 0 ||
         face_capacity < 1 || sample_stride < n_samples)
-        return fail(c, EZO_E_INVALID, "bad sizes");
+        return ezo_fail(c, EZO_E_INVALID, "bad sizes");
     if (n_edges == 0 || n_samples == 0) return EZO_OK;
-    if (!A || !b || !n_faces || !edges || !samples) return fail(c, EZO_E_INVALID, "NULL buffer");
+    if (!A || !b || !n_faces || !edges || !samples) return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
     HIP_TRY(c, hipSetDevice(c->device));
     IterArgs it{nullptr, nullptr, iteration, 0, 0, n_samples};
     return launch_sample(c, dof, A, b, n_faces, face_capacity, edges, n_edges, n_samples, n_mix, seed, edge_id_base,
@@ -543,9 +472,9 @@ ezo_status ezo_test_and_select(ezo_ctx* c, const uint8_t* flags, int32_t n_edges
     if (!c) return EZO_E_INVALID;
     if (n_edges < 0 || n_samples < 0 || M < 0 || M > n_samples || n_p < 1 || n_p > cand_capacity ||
         sample_stride < n_samples || M > 0x7fffffff)
-        return fail(c, EZO_E_INVALID, "bad sizes");
+        return ezo_fail(c, EZO_E_INVALID, "bad sizes");
     if (n_edges == 0) return EZO_OK;
-    if (!flags || !cand_idx || !n_cands) return fail(c, EZO_E_INVALID, "NULL buffer");
+    if (!flags || !cand_idx || !n_cands) return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
     HIP_TRY(c, hipSetDevice(c->device));
     IterArgs it{nullptr, nullptr, 0, (int)M, (int)std::min<int64_t>(T, 0x7fffffff), n_samples};
     hipLaunchKernelGGL(k_test_select, dim3(n_edges), dim3(1024), 0, as_stream(stream), flags, sample_stride, n_p, 0,
@@ -559,11 +488,11 @@ ezo_status ezo_project_bisect(ezo_ctx* c, const ezo_robot* r, const float* obs, 
                               const int32_t* n_cands, int32_t cand_capacity, int32_t n_b, float* c_star,
                               float* a_dir, float* t_star, uint8_t* proj_collides, void* stream) {
     if (!c) return EZO_E_INVALID;
-    if (!r || n_edges < 0 || n_obs < 0 || cand_capacity < 0 || n_b < 0) return fail(c, EZO_E_INVALID, "bad argument");
+    if (!r || n_edges < 0 || n_obs < 0 || cand_capacity < 0 || n_b < 0) return ezo_fail(c, EZO_E_INVALID, "bad argument");
     if (n_edges == 0 || cand_capacity == 0) return EZO_OK;
     if (!edges || !samples || !cand_idx || !n_cands || !c_star || !a_dir || !t_star || !proj_collides ||
         (n_obs > 0 && !obs))
-        return fail(c, EZO_E_INVALID, "NULL buffer");
+        return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
     HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t st = as_stream(stream);
     ObsView ov;
@@ -582,11 +511,11 @@ ezo_status ezo_place_hyperplanes(ezo_ctx* c, int32_t dof, const float* edges, in
     if (!c) return EZO_E_INVALID;
     if (dof < 1 || dof > EZO_MAX_DOF || n_edges < 0 || cand_capacity < 0 || n_f < 0 || face_capacity < 1 ||
         !finite_pos(step_back_max) || !std::isfinite(t_col))
-        return fail(c, EZO_E_INVALID, "bad argument");
+        return ezo_fail(c, EZO_E_INVALID, "bad argument");
     if (n_edges == 0) return EZO_OK;
     if (!edges || !c_star || !a_dir || !t_star || !n_cands || !A || !b || !n_faces || !edge_status)
-        return fail(c, EZO_E_INVALID, "NULL buffer");
-    if ((size_t)cand_capacity > c->lds_cap - 1024) return fail(c, EZO_E_UNSUPPORTED, "cand_capacity too large");
+        return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
+    if ((size_t)cand_capacity > c->lds_cap - 1024) return ezo_fail(c, EZO_E_UNSUPPORTED, "cand_capacity too large");
     HIP_TRY(c, hipSetDevice(c->device));
     hipLaunchKernelGGL(k_place, dim3(n_edges), dim3(1024), (size_t)std::max(cand_capacity, 16), as_stream(stream), dof,
                        edges, c_star, a_dir, t_star, n_cands, cand_capacity, n_f, (float)step_back_max, (float)t_col, A,
@@ -599,30 +528,30 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
                              int32_t n_edges, const ezo_params* p, float* A, float* b, int32_t* n_faces,
                              int32_t* edge_status, ezo_edge_stats* stats, void* stream) {
     if (!c) return EZO_E_INVALID;
-    if (!r || !p) return fail(c, EZO_E_INVALID, "NULL robot or params");
-    if (n_edges < 0 || n_obs < 0) return fail(c, EZO_E_INVALID, "negative size");
+    if (!r || !p) return ezo_fail(c, EZO_E_INVALID, "NULL robot or params");
+    if (n_edges < 0 || n_obs < 0) return ezo_fail(c, EZO_E_INVALID, "negative size");
     if (!(p->eps > 0 && p->eps < 1) || !(p->delta > 0 && p->delta < 1) || !(p->tau > 0 && p->tau < 1) ||
         !finite_pos(p->step_back_max) || !std::isfinite(p->t_col) || p->n_p < 1 || p->n_f < 1 || p->n_b < 0 ||
         p->n_mix < 0 || p->max_iters < 1)
-        return fail(c, EZO_E_INVALID, "parameter out of range");
+        return ezo_fail(c, EZO_E_INVALID, "parameter out of range");
     const int dof = r->dof;
     if ((int64_t)p->face_capacity < 2LL * dof + (int64_t)p->n_f * p->max_iters)
-        return fail(c, EZO_E_CAPACITY, "face_capacity %d < 2 dof + n_f max_iters = %lld", p->face_capacity,
+        return ezo_fail(c, EZO_E_CAPACITY, "face_capacity %d < 2 dof + n_f max_iters = %lld", p->face_capacity,
                     (long long)(2LL * dof + (int64_t)p->n_f * p->max_iters));
     if (n_edges == 0) return EZO_OK;
     if (!edges || !A || !b || !n_faces || !edge_status || (n_obs > 0 && !obs))
-        return fail(c, EZO_E_INVALID, "NULL buffer");
+        return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
     const int cap = p->face_capacity;
     if (sizeof(float) * (size_t)cap * ((dof <= 4 ? 4 : 8) + 1) > c->lds_cap)
-        return fail(c, EZO_E_UNSUPPORTED, "face_capacity %d too large", cap);
-    if ((size_t)p->n_p > c->lds_cap - 1024) return fail(c, EZO_E_UNSUPPORTED, "n_p %d too large", p->n_p);
+        return ezo_fail(c, EZO_E_UNSUPPORTED, "face_capacity %d too large", cap);
+    if ((size_t)p->n_p > c->lds_cap - 1024) return ezo_fail(c, EZO_E_UNSUPPORTED, "n_p %d too large", p->n_p);
     // per-iteration constants, FP64 on the host
     std::vector<int4> table(p->max_iters + 2, make_int4(0, 0, 0, 0));
     int S_cap = 0;
     for (int k = 1; k <= p->max_iters; ++k) {
         int64_t M, T;
         ezo_test_constants(p->eps, p->delta, p->tau, k, &M, &T);
-        if (M > (1 << 28)) return fail(c, EZO_E_UNSUPPORTED, "M_%d = %lld samples is too many", k, (long long)M);
+        if (M > (1 << 28)) return ezo_fail(c, EZO_E_UNSUPPORTED, "M_%d = %lld samples is too many", k, (long long)M);
         const int nS = (int)std::max<int64_t>(p->n_p, M);
         table[k] = make_int4((int)M, (int)std::min<int64_t>(T, 1 << 30), nS, 0);
         S_cap = std::max(S_cap, nS);
@@ -632,20 +561,24 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
     const int E = n_edges;
     const int64_t stride = ((int64_t)S_cap + 63) / 64 * 64;
     const int cand_cap = p->n_p;
-    void *w_s, *w_f, *w_ci, *w_nc, *w_cs, *w_ad, *w_ts, *w_pc, *w_pa, *w_st, *w_tb, *w_k, *w_ac;
+    void *w_s, *w_f, *w_ci, *w_nc, *w_cs, *w_ad, *w_ts, *w_pc, *w_pa, *w_st, *w_tb, *w_k, *w_ac, *w_pred = nullptr;
     ezo_status s;
-    if ((s = ws_get(c, W_SAMPLES, sizeof(float) * (size_t)E * dof * stride, &w_s)) ||
-        (s = ws_get(c, W_FLAGS, (size_t)E * stride, &w_f)) ||
-        (s = ws_get(c, W_CAND, sizeof(int) * (size_t)E * cand_cap, &w_ci)) ||
-        (s = ws_get(c, W_NCAND, sizeof(int) * (size_t)E, &w_nc)) ||
-        (s = ws_get(c, W_CSTAR, sizeof(float) * (size_t)E * dof * cand_cap, &w_cs)) ||
-        (s = ws_get(c, W_ADIR, sizeof(float) * (size_t)E * dof * cand_cap, &w_ad)) ||
-        (s = ws_get(c, W_TSTAR, sizeof(float) * (size_t)E * cand_cap, &w_ts)) ||
-        (s = ws_get(c, W_PCOL, (size_t)E * cand_cap, &w_pc)) || (s = ws_get(c, W_PANY, (size_t)E, &w_pa)) ||
-        (s = ws_get(c, W_STATS, sizeof(EdgeStatsDev) * (size_t)E, &w_st)) ||
-        (s = ws_get(c, W_TABLE, sizeof(int4) * table.size(), &w_tb)) || (s = ws_get(c, W_KDEV, sizeof(int), &w_k)) ||
-        (s = ws_get(c, W_ACTIVE, sizeof(int), &w_ac)))
+    if ((s = ezo_ws_get(c, W_SAMPLES, sizeof(float) * (size_t)E * dof * stride, &w_s)) ||
+        (s = ezo_ws_get(c, W_FLAGS, (size_t)E * stride, &w_f)) ||
+        (s = ezo_ws_get(c, W_CAND, sizeof(int) * (size_t)E * cand_cap, &w_ci)) ||
+        (s = ezo_ws_get(c, W_NCAND, sizeof(int) * (size_t)E, &w_nc)) ||
+        (s = ezo_ws_get(c, W_CSTAR, sizeof(float) * (size_t)E * dof * cand_cap, &w_cs)) ||
+        (s = ezo_ws_get(c, W_ADIR, sizeof(float) * (size_t)E * dof * cand_cap, &w_ad)) ||
+        (s = ezo_ws_get(c, W_TSTAR, sizeof(float) * (size_t)E * cand_cap, &w_ts)) ||
+        (s = ezo_ws_get(c, W_PCOL, (size_t)E * cand_cap, &w_pc)) || (s = ezo_ws_get(c, W_PANY, (size_t)E, &w_pa)) ||
+        (s = ezo_ws_get(c, W_STATS, sizeof(EdgeStatsDev) * (size_t)E, &w_st)) ||
+        (s = ezo_ws_get(c, W_TABLE, sizeof(int4) * table.size(), &w_tb)) || (s = ezo_ws_get(c, W_KDEV, sizeof(int), &w_k)) ||
+        (s = ezo_ws_get(c, W_ACTIVE, sizeof(int), &w_ac)))
         return s;
+    if (p->surrogate) {
+        if (p->surrogate->D != dof) return ezo_fail(c, EZO_E_INVALID, "screen dof %d != robot dof %d", p->surrogate->D, dof);
+        if ((s = ezo_ws_get(c, W_PRED, sizeof(float) * (size_t)E * stride, &w_pred))) return s;
+    }
     hipStream_t st = c->stream;
     HIP_TRY(c, hipEventRecord(c->ev_in, as_stream(stream)));
     HIP_TRY(c, hipStreamWaitEvent(st, c->ev_in, 0));
@@ -682,6 +615,19 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
             mark(EZO_NUM_PHASES);
             return ls;
         }
+        if (p->surrogate) {
+            RowSource src{};
+            src.q = (const float*)w_s;
+            src.sn = 1;
+            src.sd = stride;
+            src.rows_per_batch = stride;
+            src.qb = (int64_t)dof * stride;
+            src.rows = (int64_t)E * stride;
+            if ((ls = ezo_surrogate_forward_rows(c, p->surrogate, src, (float*)w_pred, edge_status, st))) {
+                mark(EZO_NUM_PHASES);
+                return ls;
+            }
+        }
         mark(EZO_PHASE_CHECK);
         GridView gvc = gv, gvb = gv;
         if (marks && c->d_tests) {
@@ -689,7 +635,9 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
             gvb.tests = c->d_tests + EZO_PHASE_BISECT;
         }
         if ((ls = launch_check<false>(c, r, ov, gvc, (const float*)w_s, S_cap, 1, stride, (int64_t)dof * stride,
-                                      (uint8_t*)w_f, nullptr, nullptr, stride, E, edge_status, it, st))) {
+                                      (uint8_t*)w_f, nullptr, nullptr, stride, E, edge_status, it, st,
+                                      p->surrogate ? (const float*)w_pred : nullptr,
+                                      p->surrogate ? p->surrogate->margin : 0.f, (EdgeStatsDev*)w_st))) {
             mark(EZO_NUM_PHASES);
             return ls;
         }
@@ -713,7 +661,7 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
         mark(EZO_NUM_PHASES);
         if (ls == EZO_OK) {
             hipError_t le = hipGetLastError();
-            if (le != hipSuccess) ls = fail(c, EZO_E_HIP, "kernel launch failed: %s", hipGetErrorString(le));
+            if (le != hipSuccess) ls = ezo_fail(c, EZO_E_HIP, "kernel launch failed: %s", hipGetErrorString(le));
         }
         return ls;
     };
@@ -727,10 +675,10 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
             if (graph) (void)hipGraphDestroy(graph);
             return cs;
         }
-        if (ce != hipSuccess) return fail(c, EZO_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+        if (ce != hipSuccess) return ezo_fail(c, EZO_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
         if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
             (void)hipGraphDestroy(graph);
-            return fail(c, EZO_E_HIP, "graph instantiation failed");
+            return ezo_fail(c, EZO_E_HIP, "graph instantiation failed");
         }
     }
     ezo_status result = EZO_OK;
@@ -744,7 +692,7 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
         hipError_t e2 = hipMemcpyAsync(c->pinned, w_ac, sizeof(int), hipMemcpyDeviceToHost, st);
         hipError_t e3 = hipStreamSynchronize(st);
         if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-            result = fail(c, EZO_E_HIP, "iteration %d failed: %s", k,
+            result = ezo_fail(c, EZO_E_HIP, "iteration %d failed: %s", k,
                           hipGetErrorString(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3)));
             break;
         }
@@ -771,6 +719,7 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
             stats[e].test_collisions = hs[e].test_collisions;
             stats[e].samples = hs[e].samples;
             stats[e].exact_checks = hs[e].exact_checks;
+            stats[e].screened_checks = hs[e].screened;
         }
     }
     HIP_TRY(c, hipEventRecord(c->ev_out, st));

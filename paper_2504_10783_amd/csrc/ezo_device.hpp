@@ -136,6 +136,7 @@ struct TileSmem {
     float4* cen;       // [S][T] sphere centres (shifted frame) and radius
     float4* lb;        // [kMaxDof][T] link bounding spheres (shifted frame)
     int* hit;          // [T] collision flag (flags mode) / validity
+    int* scr;          // [T] 1 = the learned screen cleared this configuration's self pairs
     float* red;        // [2][W][T] partial minima (signed-distance mode)
 };
 
@@ -145,7 +146,7 @@ __host__ __device__ inline size_t tile_smem_bytes(int T, int S, int W) {
     b += sizeof(float2) * (size_t)kMaxDof * T;
     b += sizeof(float4) * (size_t)(S > 0 ? S : 1) * T;
     b += sizeof(float4) * (size_t)kMaxDof * T;
-    b += sizeof(int) * (size_t)T;
+    b += sizeof(int) * 2 * (size_t)T;
     b += sizeof(float) * 2 * (size_t)W * T;
     return (b + 15) & ~(size_t)15;
 }
@@ -158,7 +159,8 @@ __device__ inline TileSmem carve_tile(char* base, int T, int S, int W) {
     t.trig = reinterpret_cast<float2*>(p);  p += sizeof(float2) * (size_t)kMaxDof * T;
     t.q = reinterpret_cast<float*>(p);      p += sizeof(float) * (size_t)T * kMaxDof;
     t.red = reinterpret_cast<float*>(p);    p += sizeof(float) * 2 * (size_t)W * T;
-    t.hit = reinterpret_cast<int*>(p);
+    t.hit = reinterpret_cast<int*>(p);      p += sizeof(int) * (size_t)T;
+    t.scr = reinterpret_cast<int*>(p);
     return t;
 }
 
@@ -299,7 +301,7 @@ __device__ inline void tile_pairs_grid(const RobotView& rb, const ObsView& ob, c
     unsigned int ntest = 0;
     for (int it = threadIdx.x; it < T * rb.n_blocks; it += nt) {
         const int c = it % T, bk = it / T;
-        if (hit[c]) continue;
+        if (hit[c] || t.scr[c]) continue;
         const int4 blk = rb.blocks[bk];
         const float4 A = t.lb[blk.x * T + c], B = t.lb[blk.y * T + c];
         const float dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;

@@ -1,0 +1,117 @@
+// ezo_internal.hpp -- host-side definitions shared by the library's
+// translation units (ezo_api.hip: collision checking and inflation;
+// ezo_surrogate.hip: the learned self-collision screen).  Not installed.
+#pragma once
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ezo.h"
+#include "ezo_device.hpp"
+
+constexpr int kNumCU = 256;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+// Workspace slots of a context (grown on demand, reused across calls).
+enum Slot {
+    W_OBS_REC, W_OBS_CENTRE, W_GRID_GEOM, W_GRID_COUNT, W_GRID_LIST, W_SAMPLES, W_FLAGS, W_CAND, W_NCAND, W_CSTAR,
+    W_ADIR, W_TSTAR, W_PCOL, W_PANY, W_STATS, W_TABLE, W_KDEV, W_ACTIVE, W_PRED, W_SCREENED, W_MLP_H1, W_MLP_H2,
+    W_MLP_CNT, W_NSLOTS
+};
+
+struct ezo_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;      // internal stream (default priority)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    size_t lds_cap = 65536;
+    std::string err;
+    std::vector<DevBuf> ws;            // named workspace slots
+    int* pinned = nullptr;             // host-pinned poll word
+    bool timing = false;               // per-phase timing of the fused loop
+    hipEvent_t tev[2 * EZO_NUM_PHASES] = {};   // (start, stop) of each phase's kernel
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;   // events for the next kernel launch (timing mode)
+    double phase_ms[EZO_NUM_PHASES] = {};
+    int64_t timed_iters = 0;
+    unsigned long long* d_tests = nullptr;   // [EZO_NUM_PHASES] sphere-sphere tests per phase
+};
+
+struct ezo_robot {
+    ezo_ctx* ctx = nullptr;
+    int dof = 0, S = 0, P = 0;
+    float r_max = 0.f;                 // largest sphere radius
+    void* buf = nullptr;               // one device allocation holding everything below
+    ezo::RobotView view{};
+    const int* sorted_to_orig = nullptr;
+    const float* q_lo = nullptr;
+    const float* q_hi = nullptr;
+};
+
+// Rows of the screen's input.  Row r (after adding rbase) reads configuration
+// idx ? idx[r] : r, coordinate j at q[cfg * sn + j * sd]; with
+// rows_per_batch > 0, row r belongs to batch r / rows_per_batch whose
+// configurations start at q + batch * qb.
+struct RowSource {
+    const float* q;
+    int64_t sn, sd;
+    const int* idx;
+    int64_t rows_per_batch;
+    int64_t qb;
+    int64_t rbase;
+    int64_t rows;               // valid rows (after rbase)
+};
+
+struct ezo_surrogate {
+    ezo_ctx* ctx = nullptr;
+    int D = 0, H = 0;
+    int64_t n_params = 0;
+    float margin = INFINITY;            // screen threshold (calibrated); +inf screens nothing
+    float* P = nullptr;                 // FP32 master parameters
+    float* G = nullptr;                 // gradient
+    float* m = nullptr;                 // Adam moments
+    float* v = nullptr;
+    __bf16* W2b = nullptr;              // BF16 copies for the MFMA layers
+    __bf16* W3b = nullptr;
+    int64_t adam_steps = 0;
+    // training batch buffers
+    int batch = 0;
+    void* tb = nullptr;
+};
+
+extern std::string g_create_err;
+ezo_status ezo_fail(ezo_ctx* c, ezo_status code, const char* fmt, ...);
+ezo_status ezo_ws_get(ezo_ctx* c, int slot, size_t bytes, void** out);
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Screen predictions for `src.rows` rows into pred[0..rows) (chunked MLP
+// forward).  Rows of batches whose status is final (status != NULL) are
+// skipped.  Launches only; no synchronisation.
+ezo_status ezo_surrogate_forward_rows(ezo_ctx* c, const ezo_surrogate* s, const RowSource& src, float* pred,
+                                      const int* status, hipStream_t st);
+
+#define HIP_TRY(ctx, call)                                                                                 \
+    do {                                                                                                   \
+        hipError_t e_ = (call);                                                                            \
+        if (e_ != hipSuccess) return ezo_fail(ctx, EZO_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// Kernel launch; in timing mode the dispatch itself records c->ev_a / c->ev_b
+// at its start and end (hipExtLaunchKernelGGL), so elapsed time is the
+// kernel's own duration.
+#define EZO_KLAUNCH(c, K, grid, block, lds, st, ...)                                              \
+    do {                                                                                          \
+        if ((c)->ev_a)                                                                            \
+            hipExtLaunchKernelGGL(K, grid, block, lds, st, (c)->ev_a, (c)->ev_b, 0, __VA_ARGS__); \
+        else                                                                                      \
+            hipLaunchKernelGGL(K, grid, block, lds, st, __VA_ARGS__);                              \
+    } while (0)

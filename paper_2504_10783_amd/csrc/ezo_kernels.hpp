@@ -32,6 +32,10 @@ __device__ __forceinline__ IterVals resolve(const IterArgs& a) {
     return v;
 }
 
+struct EdgeStatsDev {
+    long long iterations, planes, final_m, test_collisions, samples, exact_checks, screened;
+};
+
 // Edge is still running (fused mode) -- or always, when no status array.
 __device__ __forceinline__ bool edge_running(const int* status, int e) {
     return status == nullptr || status[e] < 0;
@@ -142,12 +146,18 @@ __global__ void __launch_bounds__(1024) k_check(RobotView rb, ObsView ob, GridVi
                                                 int64_t stride_n, int64_t stride_d, int64_t q_batch,
                                                 uint8_t* __restrict__ flags, float* __restrict__ min_sd,
                                                 float* __restrict__ min_sd_self, int64_t out_batch,
-                                                const int* __restrict__ status, IterArgs it) {
+                                                const int* __restrict__ status, IterArgs it,
+                                                const float* __restrict__ pred, float margin,
+                                                EdgeStatsDev* __restrict__ stats) {
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.y;
     if (!edge_running(status, b)) return;
-    int64_t n = n_arg;
-    if (it.k_dev) n = resolve(it).nS;
+    int64_t n = n_arg, screen_from = n_arg;
+    if (it.k_dev) {
+        const IterVals iv = resolve(it);
+        n = iv.nS;
+        screen_from = iv.M;               // the unadaptive test's samples are never screened
+    }
     const int64_t base = (int64_t)blockIdx.x * T;
     if (base >= n) return;
     const int nv = (int)((n - base) < T ? (n - base) : T);
@@ -157,6 +167,12 @@ __global__ void __launch_bounds__(1024) k_check(RobotView rb, ObsView ob, GridVi
     for (int i = threadIdx.x; i < T * rb.dof; i += blockDim.x) {
         const int c = i % T, j = i / T;
         if (c < nv) t.q[c * kMaxDof + j] = qb[(base + c) * stride_n + j * stride_d];
+    }
+    if (threadIdx.x < (unsigned)T) {
+        const int64_t g = base + threadIdx.x;
+        const bool s = !SD && pred && threadIdx.x < (unsigned)nv && g >= screen_from && pred[b * out_batch + g] >= margin;
+        t.scr[threadIdx.x] = s ? 1 : 0;
+        if (s && stats) atomicAdd((unsigned long long*)&stats[b].screened, 1ull);
     }
     __syncthreads();
     tile_check<SD>(rb, ob, gv, t, T, nv);
@@ -315,9 +331,7 @@ __global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict
 // Unadaptive test + selection of the first N_p colliding samples.
 // One workgroup (1024 threads) per edge.
 // ---------------------------------------------------------------------------
-struct EdgeStatsDev {
-    long long iterations, planes, final_m, test_collisions, samples, exact_checks;
-};
+
 
 __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict__ flags, int64_t stride, int n_p,
                                                       int n_b, int* __restrict__ cand_idx, int cand_cap,
@@ -411,6 +425,7 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView o
     TileSmem t = carve_tile(smem, T, rb.n_spheres, W);
     const int tid = threadIdx.x;
     const bool own = tid < nv;
+    if (tid < T) t.scr[tid] = 0;          // bisection midpoints are always checked exactly
     float lo[kMaxDof], hi[kMaxDof], cp[kMaxDof];
     const float* v = edges + (size_t)e * 2 * dof;
     if (own) {
@@ -606,7 +621,7 @@ __global__ void k_init_edges(int dof, const float* __restrict__ q_lo, const floa
         if (!(x == x) || isinf(x) || x < q_lo[jj] || x > q_hi[jj]) ok = false;
     }
     status[e] = ok ? -1 : 3;
-    stats[e] = EdgeStatsDev{0, 0, 0, 0, 0, 0};
+    stats[e] = EdgeStatsDev{0, 0, 0, 0, 0, 0, 0};
     proj_any[e] = 0;
 }
 
