@@ -32,9 +32,10 @@ ezo_status ezo_ws_get(ezo_ctx* c, int slot, size_t bytes, void** out) {
             b.bytes = 0;
         }
         size_t nb = bytes + bytes / 4 + 256;
-        if (hipMalloc(&b.p, nb) != hipSuccess) {
+        const hipError_t me = hipMalloc(&b.p, nb);
+        if (me != hipSuccess) {
             b.p = nullptr;
-            return ezo_fail(c, EZO_E_NOMEM, "device allocation of %zu bytes failed", nb);
+            return ezo_fail(c, EZO_E_NOMEM, "device allocation of %zu bytes failed: %s", nb, hipGetErrorString(me));
         }
         b.bytes = nb;
     }
@@ -578,6 +579,8 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
     if (p->surrogate) {
         if (p->surrogate->D != dof) return ezo_fail(c, EZO_E_INVALID, "screen dof %d != robot dof %d", p->surrogate->D, dof);
         if ((s = ezo_ws_get(c, W_PRED, sizeof(float) * (size_t)E * stride, &w_pred))) return s;
+        // the screen's activation buffers must exist before the graph capture
+        if ((s = ezo_surrogate_reserve(c, p->surrogate, (int64_t)E * stride))) return s;
     }
     hipStream_t st = c->stream;
     HIP_TRY(c, hipEventRecord(c->ev_in, as_stream(stream)));

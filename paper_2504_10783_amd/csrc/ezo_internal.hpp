@@ -98,6 +98,9 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // skipped.  Launches only; no synchronisation.
 ezo_status ezo_surrogate_forward_rows(ezo_ctx* c, const ezo_surrogate* s, const RowSource& src, float* pred,
                                       const int* status, hipStream_t st);
+// Grows the forward pass's workspace for `rows` rows (no allocation happens
+// in ezo_surrogate_forward_rows afterwards for at most that many rows).
+ezo_status ezo_surrogate_reserve(ezo_ctx* c, const ezo_surrogate* s, int64_t rows);
 
 #define HIP_TRY(ctx, call)                                                                                 \
     do {                                                                                                   \

@@ -146,6 +146,16 @@ ezo_status ensure_train_bufs(ezo_ctx* c, ezo_surrogate* s, int B) {
 
 }  // namespace
 
+ezo_status ezo_surrogate_reserve(ezo_ctx* c, const ezo_surrogate* s, int64_t rows) {
+    void *h1, *h2;
+    const int64_t R = std::min<int64_t>(kChunkRows, round64(std::max<int64_t>(rows, 1)));
+    ezo_status e;
+    if ((e = ezo_ws_get(c, W_MLP_H1, sizeof(__bf16) * (size_t)R * s->H, &h1)) ||
+        (e = ezo_ws_get(c, W_MLP_H2, sizeof(__bf16) * (size_t)R * s->H, &h2)))
+        return e;
+    return EZO_OK;
+}
+
 ezo_status ezo_surrogate_forward_rows(ezo_ctx* c, const ezo_surrogate* s, const RowSource& src, float* pred,
                                       const int* status, hipStream_t st) {
     const int D = s->D, H = s->H;

@@ -154,3 +154,21 @@ def test_screened_inflation_safety(ezo, ctx):
     b1 = r1.b[0, :F1].cpu().numpy().astype(np.float64)
     for v in data["edges"][0].astype(np.float64):
         assert np.all(A1 @ v <= b1 + 1e-5)
+
+
+def test_screened_inflation_in_fresh_context(ezo):
+    """The first call on a new context is a screened 96-edge inflation: every
+    workspace buffer (the screen's included) must exist before the iteration
+    is captured into a graph."""
+    c2 = ezo.Context(0)
+    data, desc = load("batched")
+    rob = ezo.Robot(c2, desc)
+    s = ezo.Surrogate(c2, 7, 256, seed=2)
+    s.set_margin(0.0)
+    p = dict(workloads.PARAMS["batched"], max_iters=2)
+    r = ezo.inflate_edges(c2, rob, torch.from_numpy(data["obstacles"]).cuda(),
+                          torch.from_numpy(data["edges"]).cuda(), ezo.make_params(dof=7, seed=1, surrogate=s, **p))
+    torch.cuda.synchronize()
+    st = r.status.cpu().numpy()
+    assert np.all((st == ezo.CERTIFIED) | (st == ezo.MAX_ITERS))
+    assert sum(x["screened_checks"] for x in r.stats) > 0
