@@ -114,7 +114,8 @@ def sweep(args):
             "warmup": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic", "config": {"workload": "sweep: uniform q in joint limits, obstacles in "
                                             "[0.3,1.3]x[-0.5,0.5]x[0,1] m, r U[0.02,0.08]"},
-            "points": points}
+            "points": points,
+            "launch_shapes": ezo.tune_cache_entries()}
     print(json.dumps(line), flush=True)
 
 
@@ -198,6 +199,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--screen", action="store_true", help="learned screen vs exact comparison")
     ap.add_argument("--screen-epochs", type=int, default=10)
+    ap.add_argument("--no-autotune", action="store_true", help="size-heuristic launch shapes (no tuning)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -238,9 +240,16 @@ def main():
         ezo.inflate_edges(ctx, rob, obs, edges, prm, out=out)
         return out.stats
 
-    for _ in range(args.warmup):
+    # the first call times launch shapes for this workload (autotuner) when
+    # they are not cached yet; it is part of the warm-up, never of the timed steps
+    ctx.set_autotune(not args.no_autotune)
+    t_first = time.perf_counter()
+    for _ in range(max(args.warmup, 1)):
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        if t_first is not None:
+            first_call_ms = (time.perf_counter() - t_first) * 1e3
+            t_first = None
     # timed region: the product path (one replayed hipGraph per iteration)
     checks = samples = 0
     t0 = time.perf_counter()
@@ -285,7 +294,7 @@ def main():
         "unit": "configs/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": args.warmup,
+        "warmup": max(args.warmup, 1),
         "ms_per_step": dt / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -302,6 +311,11 @@ def main():
         "phase_ms_per_step": {k: v / args.steps for k, v in phase_ms.items()},
         "ms_per_step_phase_pass": dt_phase / args.steps * 1e3,
         "roofline": roofline,
+        "autotune": not args.no_autotune,
+        "first_call_ms": first_call_ms,
+        "launch_shapes": [{k: e[k] for k in ("kernel", "log2_items", "T", "W", "stage", "us")}
+                          for e in ezo.tune_cache_entries()
+                          if e["obstacles"] == int(obs.shape[0]) or e["kernel"] == "sample"],
     }
     if not args.no_cpu_baseline:
         idx = [0] if E == 1 else sorted({int(np.nonzero(data["path_id"] == p)[0][0]) for p in np.unique(data["path_id"])})

@@ -327,6 +327,51 @@ ezo_status ezo_set_phase_timing(ezo_ctx *ctx, int32_t enable);
  * enabled.  Synchronises the context's stream when tests_out is given. */
 ezo_status ezo_get_phase_timing(ezo_ctx *ctx, double *ms_out, int64_t *iterations_out, int64_t *tests_out);
 
+/* ---------------------------------------------------------------------------
+ * Launch-shape autotuning
+ *
+ * The tile kernels (collision check in flags and signed-distance mode;
+ * projection + bisection) run with a launch shape: configurations per
+ * workgroup, waves per workgroup, and whether obstacle records are staged in
+ * LDS; the sampler runs with a number of lanes per walk.  The shape never
+ * changes a result (every flag, distance and bisection is computed from the
+ * same pair tests whatever the split, and the sampler's split of the faces
+ * is reduced with exact min/max), only the time.
+ * With autotuning on (the default), the first call whose tuning key is new
+ * times each candidate shape on the device and caches the fastest for the
+ * process; the key is (device architecture, kernel, dof, spheres, self pairs,
+ * obstacles, floor(log2(work items))).  That first call synchronises with
+ * `stream` (it reads timing events), so it must not run under stream
+ * capture: disable tuning or import a cache first.  ezo_check_collisions and
+ * ezo_project_bisect time on the call's own inputs (launches that only write
+ * the call's outputs); ezo_inflate_edges times on configurations uniform in
+ * the joint box, before its first iteration.  With autotuning off, a cached
+ * shape is still used; otherwise a size heuristic picks one.
+ * ------------------------------------------------------------------------- */
+
+/* Turn timing of new tuning keys on (enable != 0, default) or off. */
+ezo_status ezo_set_autotune(ezo_ctx *ctx, int32_t enable);
+
+/* The process-wide cache as text, one JSON object per line with keys arch,
+ * kernel ("check_flags" | "check_sd" | "bisect" | "sample"), dof, spheres,
+ * self_pairs, obstacles, log2_items, T, W, stage and us (measured time per
+ * launch).  For "sample", T is the number of lanes per walk, W the waves per
+ * workgroup, and spheres = self_pairs = obstacles = 0.
+ * buf (host, may be NULL) receives at most capacity - 1 bytes and a NUL;
+ * *length (host, may be NULL) receives the full text length.  Returns
+ * EZO_E_CAPACITY when the text was truncated. */
+ezo_status ezo_tune_cache_export(char *buf, int64_t capacity, int64_t *length);
+
+/* Adds (or replaces) cache entries from text in the export format.  Returns
+ * EZO_E_INVALID, importing nothing, when a line with '{' lacks a key or has
+ * an invalid shape; *n_imported (host, may be NULL) receives the number of
+ * entries added.  Entries whose shape does not fit a device's LDS are
+ * ignored when looked up. */
+ezo_status ezo_tune_cache_import(const char *text, int32_t *n_imported);
+
+/* Empties the process-wide cache. */
+void ezo_tune_cache_clear(void);
+
 #ifdef __cplusplus
 }
 #endif

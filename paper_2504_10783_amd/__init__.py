@@ -29,6 +29,7 @@ EXPORTS = (
     "ezo_surrogate_num_params", "ezo_surrogate_create", "ezo_surrogate_destroy", "ezo_surrogate_set_params",
     "ezo_surrogate_get_params", "ezo_surrogate_train", "ezo_surrogate_loss_grad", "ezo_surrogate_predict",
     "ezo_surrogate_calibrate", "ezo_surrogate_set_margin", "ezo_surrogate_miss_rate",
+    "ezo_set_autotune", "ezo_tune_cache_export", "ezo_tune_cache_import", "ezo_tune_cache_clear",
 )
 PHASES = ("sample", "check", "test", "bisect", "place", "advance")
 
@@ -112,6 +113,11 @@ def lib():
         L.ezo_surrogate_calibrate.argtypes = [vp, vp, vp, vp, i64, dbl, C.POINTER(dbl), vp]
         L.ezo_surrogate_set_margin.argtypes = [vp, dbl]
         L.ezo_surrogate_miss_rate.argtypes = [vp, vp, vp, vp, i64, C.POINTER(dbl), C.POINTER(dbl), vp]
+        L.ezo_set_autotune.argtypes = [vp, i32]
+        L.ezo_tune_cache_export.argtypes = [C.c_char_p, i64, C.POINTER(i64)]
+        L.ezo_tune_cache_import.argtypes = [C.c_char_p, C.POINTER(i32)]
+        L.ezo_tune_cache_clear.argtypes = []
+        L.ezo_tune_cache_clear.restype = None
         for name in EXPORTS:
             fn = getattr(L, name)
             if fn.restype is C.c_int:
@@ -156,6 +162,38 @@ def test_constants(eps: float, delta: float, tau: float, k: int):
     return M.value, T.value
 
 
+def tune_cache_export() -> str:
+    """The process-wide launch-shape cache as JSON lines."""
+    n = C.c_int64()
+    rc = lib().ezo_tune_cache_export(None, 0, C.byref(n))
+    if rc:
+        raise EzoError(rc, "tuning cache export failed")
+    buf = C.create_string_buffer(n.value + 1)
+    rc = lib().ezo_tune_cache_export(buf, n.value + 1, C.byref(n))
+    if rc:
+        raise EzoError(rc, "tuning cache export failed")
+    return buf.value.decode()
+
+
+def tune_cache_entries():
+    """The cache as a list of dicts."""
+    import json
+    return [json.loads(line) for line in tune_cache_export().splitlines() if line.strip()]
+
+
+def tune_cache_import(text: str) -> int:
+    """Adds entries in the export format; returns how many."""
+    n = C.c_int32()
+    rc = lib().ezo_tune_cache_import(text.encode(), C.byref(n))
+    if rc:
+        raise EzoError(rc, "malformed tuning cache text")
+    return n.value
+
+
+def tune_cache_clear():
+    lib().ezo_tune_cache_clear()
+
+
 class Context:
     """An ezo context on one HIP device."""
 
@@ -177,6 +215,10 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_autotune(self, enable: bool):
+        """Time launch shapes on the first call with a new tuning key (default on)."""
+        self._check(lib().ezo_set_autotune(self.h, 1 if enable else 0))
 
     def set_phase_timing(self, enable: bool):
         """Per-phase GPU timing of inflate_edges (hipEvents on the kernels' stream)."""

@@ -14,7 +14,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = [os.path.join(PKG, "csrc", "ezo_api.hip"), os.path.join(PKG, "csrc", "ezo_surrogate.hip")]
+SRC = [os.path.join(PKG, "csrc", f) for f in ("ezo_api.hip", "ezo_surrogate.hip", "ezo_tune.hip")]
 OUT = os.path.join(PKG, "libezo.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -48,24 +48,32 @@ namespace {
 
 // Tile size for a tile check: largest T whose LDS fits and that still gives
 // at least ~4 workgroups per CU; W waves split the obstacles.
-int pick_T(const ezo_ctx* c, int64_t items, int S, int W) {
+constexpr size_t kObsStageBytes = 32768;   // obstacle records staged in LDS up to this size
+
+int pick_T(const ezo_ctx* c, int64_t items, int S, int W, size_t extra = 0) {
     const int cand[4] = {64, 32, 16, 8};
     int fit = 0;
     for (int T : cand) {
-        if (tile_smem_bytes(T, S, W) > c->lds_cap) continue;
+        if (tile_smem_bytes(T, S, W) + extra > c->lds_cap) continue;
         if (!fit) fit = T;
         if (items / T >= 4 * kNumCU) return T;
     }
     if (!fit) {
         for (int T : {4, 2, 1})
-            if (tile_smem_bytes(T, S, W) <= c->lds_cap) return T;
+            if (tile_smem_bytes(T, S, W) + extra <= c->lds_cap) return T;
         return 0;
     }
     // few items: smallest fitting tile gives the most workgroups
     int best = fit;
     for (int T : cand)
-        if (tile_smem_bytes(T, S, W) <= c->lds_cap) best = T;
+        if (tile_smem_bytes(T, S, W) + extra <= c->lds_cap) best = T;
     return best;
+}
+
+// Obstacle records go to LDS when they fit beside a tile of T.
+bool stage_fits(const ezo_ctx* c, int T, int S, int W, int n_obs) {
+    const size_t b = 16 * (size_t)n_obs;
+    return T > 0 && n_obs > 0 && b <= kObsStageBytes && tile_smem_bytes(T, S, W) + b <= c->lds_cap;
 }
 
 int pick_W(int n_obs) {
@@ -98,6 +106,7 @@ ezo_status prep_obstacles(ezo_ctx* c, const ezo_robot* r, const float* obs, int 
                        (unsigned short*)list);
     HIP_TRY(c, hipGetLastError());
     ov->n = n_obs;
+    ov->lds_n = 0;
     ov->rec = (const float4*)rec;
     ov->centre = (const float4*)centre;
     gv->G = G;
@@ -109,21 +118,89 @@ ezo_status prep_obstacles(ezo_ctx* c, const ezo_robot* r, const float* obs, int 
     return EZO_OK;
 }
 
+bool pow2_tile(int T) { return T == 1 || T == 2 || T == 4 || T == 8 || T == 16 || T == 32 || T == 64; }
+
+// A shape is usable when its LDS fits and staging is possible where asked.
+bool cfg_valid(const ezo_ctx* c, const TileCfg& g, int S, int n_obs, bool sd) {
+    if (!pow2_tile(g.T) || g.W < 1 || g.W > 16) return false;
+    if (g.stage && (sd || !stage_fits(c, g.T, S, g.W, n_obs))) return false;
+    return tile_smem_bytes(g.T, S, g.W) + (g.stage ? 16 * (size_t)n_obs : 0) <= c->lds_cap;
+}
+
+TuneKey tune_key(const ezo_ctx* c, const ezo_robot* r, TuneKind kind, int n_obs, int64_t items) {
+    TuneKey k;
+    k.arch = c->arch;
+    k.kind = kind;
+    k.dof = r->dof;
+    k.S = r->S;
+    k.P = r->P;
+    k.n_obs = n_obs;
+    k.bucket = ezo_tune_bucket(items);
+    return k;
+}
+
+// Heuristic shapes, used when tuning is off and nothing is cached.
+TileCfg heuristic_check(const ezo_ctx* c, const ezo_robot* r, int n_obs, int64_t items, bool sd) {
+    TileCfg g;
+    g.W = sd ? pick_W(n_obs) : 4;
+    g.T = pick_T(c, items, r->S, g.W);
+    g.stage = (!sd && stage_fits(c, g.T, r->S, g.W, n_obs)) ? 1 : 0;
+    return g;
+}
+
+TileCfg heuristic_bisect(const ezo_ctx* c, const ezo_robot* r, int n_obs, int64_t items) {
+    TileCfg g;
+    g.W = 4;
+    g.T = std::min(pick_T(c, items, r->S, g.W), 64);
+    g.stage = stage_fits(c, g.T, r->S, g.W, n_obs) ? 1 : 0;
+    return g;
+}
+
+TileCfg resolve_cfg(const ezo_ctx* c, const TuneKey& k, const TileCfg& fallback, int S, int n_obs, bool sd) {
+    TileCfg g;
+    if (ezo_tune_lookup(k, &g) && cfg_valid(c, g, S, n_obs, sd)) return g;
+    return fallback;
+}
+
+// Candidate shapes: every fitting T in {4..64} x W x staging.
+std::vector<TileCfg> tile_candidates(const ezo_ctx* c, int S, int n_obs, bool sd, std::initializer_list<int> Ws,
+                                     int64_t items) {
+    std::vector<TileCfg> v;
+    for (int T : {64, 32, 16, 8, 4}) {
+        if (T > 4 && items < 4LL * T) continue;          // a handful of items: small tiles only
+        for (int W : Ws)
+            for (int st = 0; st <= (sd ? 0 : 1); ++st) {
+                TileCfg g{T, W, st};
+                if (cfg_valid(c, g, S, n_obs, sd)) v.push_back(g);
+            }
+    }
+    return v;
+}
+
 template <bool SD>
 ezo_status launch_check(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const GridView& gv, const float* q, int64_t n,
                         int64_t sn, int64_t sd, int64_t q_batch, uint8_t* flags, float* min_sd,
                         float* min_sd_self, int64_t out_batch, int n_batch, const int* status,
                         const IterArgs& it, hipStream_t st, const float* pred = nullptr, float margin = 0.f,
-                        EdgeStatsDev* stats = nullptr) {
-    const int W = SD ? pick_W(ov.n) : 4;
-    const int T = pick_T(c, n * n_batch, r->S, W);
+                        EdgeStatsDev* stats = nullptr, const TileCfg* shape = nullptr) {
+    TileCfg g;
+    if (shape) {
+        g = *shape;
+    } else {
+        const int64_t items = n * n_batch;
+        g = resolve_cfg(c, tune_key(c, r, SD ? TUNE_CHECK_SD : TUNE_CHECK_FLAGS, ov.n, items),
+                        heuristic_check(c, r, ov.n, items, SD), r->S, ov.n, SD);
+    }
+    const int T = g.T, W = g.W;
     if (T == 0) return ezo_fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
-    const size_t lds = tile_smem_bytes(T, r->S, W);
+    ObsView ovs = ov;
+    ovs.lds_n = g.stage ? ov.n : 0;
+    const size_t lds = tile_smem_bytes(T, r->S, W) + 16 * (size_t)ovs.lds_n;
     const int64_t tiles = (n + T - 1) / T;
     if (tiles <= 0) return EZO_OK;
     dim3 grid((unsigned)tiles, (unsigned)n_batch), block(64 * W);
 #define EZO_LAUNCH_CHECK(TT)                                                                          \
-    EZO_KLAUNCH(c, (k_check<TT, SD>), grid, block, lds, st, r->view, ov, gv, q, n, sn, sd, q_batch, flags, \
+    EZO_KLAUNCH(c, (k_check<TT, SD>), grid, block, lds, st, r->view, ovs, gv, q, n, sn, sd, q_batch, flags, \
                        min_sd, min_sd_self, out_batch, status, it, pred, margin, stats)
     switch (T) {
         case 64: EZO_LAUNCH_CHECK(64); break;
@@ -139,25 +216,64 @@ ezo_status launch_check(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const
     return EZO_OK;
 }
 
+TuneKey sample_key(const ezo_ctx* c, int dof, int64_t walks) {
+    TuneKey k;
+    k.arch = c->arch;
+    k.kind = TUNE_SAMPLE;
+    k.dof = dof;
+    k.bucket = ezo_tune_bucket(walks);
+    return k;
+}
+
+// Lanes per walk: 8 when walks are few (fill the chip), else 4.
+TileCfg heuristic_sample(int64_t walks) {
+    TileCfg g;
+    g.T = (walks * 8 <= 64LL * 4 * 4 * kNumCU * 64) ? 8 : 4;
+    g.W = 4;
+    return g;
+}
+
+bool sample_cfg_valid(const TileCfg& g) { return (g.T == 1 || g.T == 2 || g.T == 4 || g.T == 8) && g.W == 4; }
+
 ezo_status launch_sample(ezo_ctx* c, int dof, const float* A, const float* b, const int* n_faces, int cap,
                          const float* edges, int E, int max_samples, int n_mix, uint64_t seed, int64_t eid0,
-                         float* S, int64_t stride, const int* status, const IterArgs& it, hipStream_t st) {
+                         float* S, int64_t stride, const int* status, const IterArgs& it, hipStream_t st,
+                         const TileCfg* shape = nullptr) {
     const int D = dof <= 4 ? 4 : 8;
     const size_t lds = sizeof(float) * (size_t)cap * (D + 1);
     if (lds > c->lds_cap) return ezo_fail(c, EZO_E_UNSUPPORTED, "face capacity %d too large for the sampler", cap);
     if (max_samples <= 0 || E <= 0) return EZO_OK;
-    // lanes per walk: 8 when walks are few (fill the chip), else 4
-    const int L = ((int64_t)max_samples * E * 8 <= 64LL * 4 * 4 * kNumCU * 64) ? 8 : 4;
+    const int64_t walks = (int64_t)max_samples * E;
+    TileCfg g;
+    if (shape) {
+        g = *shape;
+    } else {
+        const TileCfg h = heuristic_sample(walks);
+        g = (ezo_tune_lookup(sample_key(c, dof, walks), &g) && sample_cfg_valid(g)) ? g : h;
+    }
+    if (!sample_cfg_valid(g)) return ezo_fail(c, EZO_E_INVALID, "sampler shape T=%d W=%d", g.T, g.W);
+    const int L = g.T;
     const int64_t threads = (int64_t)max_samples * L;
     dim3 grid((unsigned)((threads + 255) / 256), (unsigned)E), block(256);
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 #define EZO_LAUNCH_SAMPLE(DD, LL)                                                                                 \
     EZO_KLAUNCH(c, (k_sample<DD, LL>), grid, block, lds, st, dof, A, b, n_faces, cap, edges, k0, k1, eid0, n_mix, \
                        S, stride, status, it)
-    if (D == 4 && L == 8) EZO_LAUNCH_SAMPLE(4, 8);
-    else if (D == 4) EZO_LAUNCH_SAMPLE(4, 4);
-    else if (L == 8) EZO_LAUNCH_SAMPLE(8, 8);
-    else EZO_LAUNCH_SAMPLE(8, 4);
+    if (D == 4) {
+        switch (L) {
+            case 1: EZO_LAUNCH_SAMPLE(4, 1); break;
+            case 2: EZO_LAUNCH_SAMPLE(4, 2); break;
+            case 4: EZO_LAUNCH_SAMPLE(4, 4); break;
+            default: EZO_LAUNCH_SAMPLE(4, 8); break;
+        }
+    } else {
+        switch (L) {
+            case 1: EZO_LAUNCH_SAMPLE(8, 1); break;
+            case 2: EZO_LAUNCH_SAMPLE(8, 2); break;
+            case 4: EZO_LAUNCH_SAMPLE(8, 4); break;
+            default: EZO_LAUNCH_SAMPLE(8, 8); break;
+        }
+    }
 #undef EZO_LAUNCH_SAMPLE
     HIP_TRY(c, hipGetLastError());
     return EZO_OK;
@@ -167,14 +283,24 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
                                  const float* edges, int E,
                                  const float* S, int64_t stride, const int* cand_idx, const int* n_cands,
                                  int cand_cap, int n_b, float* c_star, float* a_dir, float* t_star,
-                                 uint8_t* pcol, uint8_t* pany, const int* status, hipStream_t st) {
-    const int W = 4;
-    const int T = std::min(pick_T(c, (int64_t)cand_cap * E, r->S, W), 64);
+                                 uint8_t* pcol, uint8_t* pany, const int* status, hipStream_t st,
+                                 const TileCfg* shape = nullptr) {
+    TileCfg g;
+    if (shape) {
+        g = *shape;
+    } else {
+        const int64_t items = (int64_t)cand_cap * E;
+        g = resolve_cfg(c, tune_key(c, r, TUNE_BISECT, ov.n, items), heuristic_bisect(c, r, ov.n, items), r->S,
+                        ov.n, false);
+    }
+    const int T = g.T, W = g.W;
     if (T == 0) return ezo_fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
-    const size_t lds = tile_smem_bytes(T, r->S, W);
+    ObsView ovs = ov;
+    ovs.lds_n = g.stage ? ov.n : 0;
+    const size_t lds = tile_smem_bytes(T, r->S, W) + 16 * (size_t)ovs.lds_n;
     dim3 grid((unsigned)((cand_cap + T - 1) / T), (unsigned)E), block(64 * W);
 #define EZO_LAUNCH_PB(TT)                                                                                    \
-    EZO_KLAUNCH(c, (k_project_bisect<TT>), grid, block, lds, st, r->view, ov, gv, edges, S, stride, cand_idx, \
+    EZO_KLAUNCH(c, (k_project_bisect<TT>), grid, block, lds, st, r->view, ovs, gv, edges, S, stride, cand_idx, \
                        n_cands, cand_cap, n_b, c_star, a_dir, t_star, pcol, pany, status)
     switch (T) {
         case 64: EZO_LAUNCH_PB(64); break;
@@ -188,6 +314,114 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
 #undef EZO_LAUNCH_PB
     HIP_TRY(c, hipGetLastError());
     return EZO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning (first use of a key, when enabled)
+// ---------------------------------------------------------------------------
+
+// Raw checker: time the candidate shapes on a prefix of the call's own
+// configurations (the kernel only writes outputs, so repeated launches are
+// harmless).  The prefix keeps one timing launch to a few milliseconds
+// while leaving far more workgroups than CUs.
+template <bool SD>
+ezo_status tune_check_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const GridView& gv, const float* q,
+                              int64_t n, int64_t sn, int64_t sd, uint8_t* flags, float* min_sd, float* min_sd_self,
+                              hipStream_t st) {
+    const TuneKey k = tune_key(c, r, SD ? TUNE_CHECK_SD : TUNE_CHECK_FLAGS, ov.n, n);
+    TileCfg g;
+    if (!c->autotune || ezo_tune_lookup(k, &g)) return EZO_OK;
+    const int64_t n_t = SD ? std::min<int64_t>(n, std::max<int64_t>(65536, (1LL << 28) / std::max(ov.n, 256)))
+                           : std::min<int64_t>(n, 1LL << 19);
+    const auto cands = SD ? tile_candidates(c, r->S, ov.n, true, {1, 2, 4, 8, 16}, n_t)
+                          : tile_candidates(c, r->S, ov.n, false, {1, 2, 4, 8}, n_t);
+    if (cands.empty()) return EZO_OK;
+    IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
+    auto run = [&](const TileCfg& cfg) {
+        return launch_check<SD>(c, r, ov, gv, q, n_t, sn, sd, 0, flags, min_sd, min_sd_self, 0, 1, nullptr, it, st,
+                                nullptr, 0.f, nullptr, &cfg);
+    };
+    return ezo_tune_search(c, k, cands, st, run, &g);
+}
+
+// Driven projection + bisection: the call's own candidates (outputs only).
+ezo_status tune_bisect_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const GridView& gv,
+                               const float* edges, int E, const float* S, int64_t stride, const int* cand_idx,
+                               const int* n_cands, int cand_cap, int n_b, float* c_star, float* a_dir, float* t_star,
+                               uint8_t* pcol, hipStream_t st) {
+    const TuneKey k = tune_key(c, r, TUNE_BISECT, ov.n, (int64_t)cand_cap * E);
+    TileCfg g;
+    if (!c->autotune || ezo_tune_lookup(k, &g)) return EZO_OK;
+    const auto cands = tile_candidates(c, r->S, ov.n, false, {1, 2, 4, 8}, (int64_t)cand_cap * E);
+    if (cands.empty()) return EZO_OK;
+    auto run = [&](const TileCfg& cfg) {
+        return launch_project_bisect(c, r, ov, gv, edges, E, S, stride, cand_idx, n_cands, cand_cap, n_b, c_star,
+                                     a_dir, t_star, pcol, nullptr, nullptr, st, &cfg);
+    };
+    return ezo_tune_search(c, k, cands, st, run, &g);
+}
+
+// Fused inflation: the loop's workspace (and the caller's A, b, n_faces) are
+// free until the edges are initialised, so the shapes of the loop's sampler,
+// check and bisection launches are timed there on a stand-in for a typical
+// iteration: the joint box written as 2 dof + 2 n_f rows (box rows repeated),
+// |S| hit-and-run samples per edge from it, and as candidates the first n_p
+// of them in collision.  At most kTuneEdges edges take part (already far more
+// workgroups than CUs).
+constexpr int kTuneEdges = 16;
+
+ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const GridView& gv, const float* edges,
+                          int E, const ezo_params* p, int S_cap, int64_t stride, float* A, float* b, int* n_faces,
+                          float* w_s, uint8_t* w_f, int* w_ci, int* w_nc, float* w_cs, float* w_ad, float* w_ts,
+                          uint8_t* w_pc, hipStream_t st) {
+    if (!c->autotune) return EZO_OK;
+    const int dof = r->dof, cap = p->face_capacity, cand_cap = p->n_p;
+    const TuneKey ks = sample_key(c, dof, (int64_t)S_cap * E);
+    const TuneKey kc = tune_key(c, r, TUNE_CHECK_FLAGS, ov.n, (int64_t)S_cap * E);
+    const TuneKey kb = tune_key(c, r, TUNE_BISECT, ov.n, (int64_t)cand_cap * E);
+    TileCfg g;
+    const bool need_s = !ezo_tune_lookup(ks, &g), need_c = !ezo_tune_lookup(kc, &g), need_b = !ezo_tune_lookup(kb, &g);
+    if (!need_s && !need_c && !need_b) return EZO_OK;
+    E = std::min(E, kTuneEdges);
+    const int F = std::min(cap, 2 * dof + 2 * p->n_f);
+    hipLaunchKernelGGL(k_tune_polytope, dim3((E + 63) / 64), dim3(64), 0, st, dof, r->q_lo, r->q_hi, E, cap, F, A, b,
+                       n_faces);
+    HIP_TRY(c, hipGetLastError());
+    IterArgs its{nullptr, nullptr, 1, 0, 0, S_cap};
+    auto run_s = [&](const TileCfg& cfg) {
+        return launch_sample(c, dof, A, b, n_faces, cap, edges, E, S_cap, p->n_mix, p->seed, p->edge_id_base, w_s,
+                             stride, nullptr, its, st, &cfg);
+    };
+    ezo_status s;
+    if (need_s) {
+        const std::vector<TileCfg> cands = {{1, 4, 0}, {2, 4, 0}, {4, 4, 0}, {8, 4, 0}};
+        if ((s = ezo_tune_search(c, ks, cands, st, run_s, &g))) return s;
+    } else if ((s = launch_sample(c, dof, A, b, n_faces, cap, edges, E, S_cap, p->n_mix, p->seed, p->edge_id_base,
+                                  w_s, stride, nullptr, its, st))) {
+        return s;
+    }
+    IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
+    auto run_c = [&](const TileCfg& cfg) {
+        return launch_check<false>(c, r, ov, gv, w_s, S_cap, 1, stride, (int64_t)dof * stride, w_f, nullptr, nullptr,
+                                   stride, E, nullptr, it, st, nullptr, 0.f, nullptr, &cfg);
+    };
+    if (need_c) {
+        const auto cands = tile_candidates(c, r->S, ov.n, false, {1, 2, 4, 8}, (int64_t)S_cap * E);
+        if (!cands.empty() && (s = ezo_tune_search(c, kc, cands, st, run_c, &g))) return s;
+    }
+    if (!need_b) return EZO_OK;
+    if ((s = run_c(heuristic_check(c, r, ov.n, (int64_t)S_cap * E, false)))) return s;
+    IterArgs sel{nullptr, nullptr, 0, S_cap, -1, S_cap};     // T = -1: never accept, always select
+    hipLaunchKernelGGL(k_test_select, dim3(E), dim3(1024), 0, st, w_f, stride, p->n_p, p->n_b, w_ci, cand_cap, w_nc,
+                       nullptr, nullptr, nullptr, nullptr, sel);
+    HIP_TRY(c, hipGetLastError());
+    const auto cands = tile_candidates(c, r->S, ov.n, false, {1, 2, 4, 8}, (int64_t)cand_cap * E);
+    if (cands.empty()) return EZO_OK;
+    auto run_b = [&](const TileCfg& cfg) {
+        return launch_project_bisect(c, r, ov, gv, edges, E, w_s, stride, w_ci, w_nc, cand_cap, p->n_b, w_cs, w_ad,
+                                     w_ts, w_pc, nullptr, nullptr, st, &cfg);
+    };
+    return ezo_tune_search(c, kb, cands, st, run_b, &g);
 }
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
@@ -209,6 +443,13 @@ ezo_status ezo_ctx_create(int32_t device, ezo_ctx** out) {
     ezo_ctx* c = new ezo_ctx();
     c->device = device;
     c->ws.resize(W_NSLOTS);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        c->arch = prop.gcnArchName;
+        const size_t colon = c->arch.find(':');
+        if (colon != std::string::npos) c->arch.resize(colon);
+    }
+    if (c->arch.empty()) c->arch = "unknown";
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
         c->lds_cap = std::min<size_t>((size_t)lds, 65536);
@@ -234,6 +475,8 @@ void ezo_ctx_destroy(ezo_ctx* c) {
     if (c->ev_in) e = hipEventDestroy(c->ev_in);
     if (c->ev_out) e = hipEventDestroy(c->ev_out);
     for (auto& ev : c->tev)
+        if (ev) e = hipEventDestroy(ev);
+    for (auto& ev : c->tune_ev)
         if (ev) e = hipEventDestroy(ev);
     if (c->d_tests) e = hipFree(c->d_tests);
     if (c->stream) e = hipStreamDestroy(c->stream);
@@ -299,11 +542,15 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     }
     std::stable_sort(keyed.begin(), keyed.end(),
                      [](const auto& x, const auto& y) { return x.first < y.first; });
+    // A block holds at most kPairChunk consecutive pairs of one link pair, so
+    // that one thread's pair loads issue together; w = count | 256 on the
+    // first block of each link pair (the one that counts its bound test).
     std::vector<int4> blocks;
     for (int p = 0; p < P; ++p) {
         pairs[p] = keyed[p].second;
-        if (p == 0 || keyed[p].first != keyed[p - 1].first)
-            blocks.push_back(make_int4(keyed[p].first.first, keyed[p].first.second, p, 0));
+        const bool lead = p == 0 || keyed[p].first != keyed[p - 1].first;
+        if (lead || (blocks.back().w & 255) == ezo::kPairChunk)
+            blocks.push_back(make_int4(keyed[p].first.first, keyed[p].first.second, p, lead ? 256 : 0));
         blocks.back().w++;
     }
     if (blocks.empty()) blocks.push_back(make_int4(0, 0, 0, 0));
@@ -416,9 +663,13 @@ ezo_status ezo_check_collisions(ezo_ctx* c, const ezo_robot* r, const float* obs
     ezo_status s = prep_obstacles(c, r, obs, n_obs, st, &ov, &gv);
     if (s) return s;
     IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
-    if (min_sd || min_sd_self)
+    if (min_sd || min_sd_self) {
+        if ((s = tune_check_inplace<true>(c, r, ov, gv, q, n, stride_n, stride_d, flags, min_sd, min_sd_self, st)))
+            return s;
         return launch_check<true>(c, r, ov, gv, q, n, stride_n, stride_d, 0, flags, min_sd, min_sd_self, 0, 1,
                                   nullptr, it, st);
+    }
+    if ((s = tune_check_inplace<false>(c, r, ov, gv, q, n, stride_n, stride_d, flags, nullptr, nullptr, st))) return s;
     return launch_check<false>(c, r, ov, gv, q, n, stride_n, stride_d, 0, flags, nullptr, nullptr, 0, 1, nullptr, it,
                                st);
 }
@@ -462,8 +713,20 @@ ezo_status ezo_sample_polytopes(ezo_ctx* c, int32_t dof, const float* A, const f
     if (!A || !b || !n_faces || !edges || !samples) return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
     HIP_TRY(c, hipSetDevice(c->device));
     IterArgs it{nullptr, nullptr, iteration, 0, 0, n_samples};
+    hipStream_t st = as_stream(stream);
+    const TuneKey k = sample_key(c, dof, (int64_t)n_samples * n_edges);
+    TileCfg g;
+    if (c->autotune && !ezo_tune_lookup(k, &g)) {       // time the lane counts on this call (writes samples only)
+        const std::vector<TileCfg> cands = {{1, 4, 0}, {2, 4, 0}, {4, 4, 0}, {8, 4, 0}};
+        auto run = [&](const TileCfg& cfg) {
+            return launch_sample(c, dof, A, b, n_faces, face_capacity, edges, n_edges, n_samples, n_mix, seed,
+                                 edge_id_base, samples, sample_stride, nullptr, it, st, &cfg);
+        };
+        ezo_status s = ezo_tune_search(c, k, cands, st, run, &g);
+        if (s) return s;
+    }
     return launch_sample(c, dof, A, b, n_faces, face_capacity, edges, n_edges, n_samples, n_mix, seed, edge_id_base,
-                         samples, sample_stride, nullptr, it, as_stream(stream));
+                         samples, sample_stride, nullptr, it, st);
 }
 
 ezo_status ezo_test_and_select(ezo_ctx* c, const uint8_t* flags, int32_t n_edges, int64_t sample_stride,
@@ -500,6 +763,9 @@ ezo_status ezo_project_bisect(ezo_ctx* c, const ezo_robot* r, const float* obs, 
     GridView gv;
     ezo_status s = prep_obstacles(c, r, obs, n_obs, st, &ov, &gv);
     if (s) return s;
+    if ((s = tune_bisect_inplace(c, r, ov, gv, edges, n_edges, samples, sample_stride, cand_idx, n_cands,
+                                 cand_capacity, n_b, c_star, a_dir, t_star, proj_collides, st)))
+        return s;
     return launch_project_bisect(c, r, ov, gv, edges, n_edges, samples, sample_stride, cand_idx, n_cands, cand_capacity,
                                  n_b, c_star, a_dir, t_star, proj_collides, nullptr, nullptr, st);
 }
@@ -591,6 +857,9 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
     ObsView ov;
     GridView gv;
     if ((s = prep_obstacles(c, r, obs, n_obs, st, &ov, &gv))) return s;
+    if ((s = tune_inflation(c, r, ov, gv, edges, E, p, S_cap, stride, A, b, n_faces, (float*)w_s, (uint8_t*)w_f,
+                            (int*)w_ci, (int*)w_nc, (float*)w_cs, (float*)w_ad, (float*)w_ts, (uint8_t*)w_pc, st)))
+        return s;
     hipLaunchKernelGGL(k_init_edges, dim3((E + 63) / 64), dim3(64), 0, st, dof, r->q_lo, r->q_hi, edges, E, A, b,
                        n_faces, cap, edge_status, (EdgeStatsDev*)w_st, (uint8_t*)w_pa);
     HIP_TRY(c, hipGetLastError());
@@ -634,8 +903,8 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
         mark(EZO_PHASE_CHECK);
         GridView gvc = gv, gvb = gv;
         if (marks && c->d_tests) {
-            gvc.tests = c->d_tests + EZO_PHASE_CHECK;
-            gvb.tests = c->d_tests + EZO_PHASE_BISECT;
+            gvc.tests = c->d_tests + (size_t)EZO_PHASE_CHECK * kTestSlots;
+            gvb.tests = c->d_tests + (size_t)EZO_PHASE_BISECT * kTestSlots;
         }
         if ((ls = launch_check<false>(c, r, ov, gvc, (const float*)w_s, S_cap, 1, stride, (int64_t)dof * stride,
                                       (uint8_t*)w_f, nullptr, nullptr, stride, E, edge_status, it, st,
@@ -736,8 +1005,9 @@ ezo_status ezo_set_phase_timing(ezo_ctx* c, int32_t enable) {
     if (enable) {
         for (auto& ev : c->tev)
             if (!ev) HIP_TRY(c, hipEventCreate(&ev));
-        if (!c->d_tests) HIP_TRY(c, hipMalloc((void**)&c->d_tests, sizeof(unsigned long long) * EZO_NUM_PHASES));
-        HIP_TRY(c, hipMemsetAsync(c->d_tests, 0, sizeof(unsigned long long) * EZO_NUM_PHASES, c->stream));
+        const size_t tb = sizeof(unsigned long long) * EZO_NUM_PHASES * kTestSlots;
+        if (!c->d_tests) HIP_TRY(c, hipMalloc((void**)&c->d_tests, tb));
+        HIP_TRY(c, hipMemsetAsync(c->d_tests, 0, tb, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
     c->timing = enable != 0;
@@ -751,13 +1021,17 @@ ezo_status ezo_get_phase_timing(ezo_ctx* c, double* ms_out, int64_t* iterations_
     for (int i = 0; i < EZO_NUM_PHASES; ++i) ms_out[i] = c->phase_ms[i];
     if (iterations_out) *iterations_out = c->timed_iters;
     if (tests_out) {
-        unsigned long long h[EZO_NUM_PHASES] = {};
+        std::vector<unsigned long long> h((size_t)EZO_NUM_PHASES * kTestSlots, 0ull);
         if (c->d_tests) {
             HIP_TRY(c, hipSetDevice(c->device));
             HIP_TRY(c, hipStreamSynchronize(c->stream));
-            HIP_TRY(c, hipMemcpy(h, c->d_tests, sizeof(h), hipMemcpyDeviceToHost));
+            HIP_TRY(c, hipMemcpy(h.data(), c->d_tests, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
         }
-        for (int i = 0; i < EZO_NUM_PHASES; ++i) tests_out[i] = (int64_t)h[i];
+        for (int i = 0; i < EZO_NUM_PHASES; ++i) {
+            unsigned long long t = 0;
+            for (int k = 0; k < kTestSlots; ++k) t += h[(size_t)i * kTestSlots + k];
+            tests_out[i] = (int64_t)t;
+        }
     }
     return EZO_OK;
 }

@@ -39,8 +39,10 @@ struct RobotView {
     const float4* sph;         // [S] local (x, y, z), r -- sorted by link
     const int2* pairs;         // [P] self pairs, indices into the sorted order, grouped by block
     const float4* lbound;      // [dof] bounding sphere of each link's spheres: local centre, radius
-    const int4* blocks;        // [n_blocks] (link i, link j, first pair, pair count)
+    const int4* blocks;        // [n_blocks] (link i, link j, first pair, pair count | 256 if first of the link pair)
 };
+
+constexpr int kPairChunk = 8;  // self pairs per block
 
 // Uniform grid over the obstacle cloud (shifted frame).  Cell k lists every
 // obstacle that a robot sphere centred anywhere in cell k could touch:
@@ -60,7 +62,7 @@ struct GridView {
     const GridGeom* geom;
     const int* count;          // [G^3]
     const unsigned short* list;  // [G^3][cap] obstacle indices
-    unsigned long long* tests;   // optional counter of sphere-sphere tests performed
+    unsigned long long* tests;   // optional [kTestSlots] counters of sphere-sphere tests performed
 };
 
 // Read-only global memory viewed through the constant address space: loads
@@ -71,6 +73,7 @@ __device__ __forceinline__ float4 cload4(const cfloat* p) { return make_float4(p
 
 struct ObsView {
     int n;
+    int lds_n;                 // > 0: the workgroup stages the n records (x, y, z, r) in LDS
     const float4* rec;         // [n][2]: (ox, oy, oz, ro), (-2ox, -2oy, -2oz, |o|^2 - ro^2), shifted frame
     const float4* centre;      // [1] shift applied to world coordinates (x' = x - centre)
 };
@@ -83,8 +86,10 @@ struct U4 { uint32_t x, y, z, w; };
 __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        // one 32 x 32 -> 64-bit multiply (v_mad_u64_u32) gives both halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         U4 n;
         n.x = hi1 ^ c.y ^ k0;
         n.y = lo1;
@@ -138,6 +143,7 @@ struct TileSmem {
     int* hit;          // [T] collision flag (flags mode) / validity
     int* scr;          // [T] 1 = the learned screen cleared this configuration's self pairs
     float* red;        // [2][W][T] partial minima (signed-distance mode)
+    float4* obs;       // [lds_n] staged obstacle records (x, y, z, r), or NULL
 };
 
 __host__ __device__ inline size_t tile_smem_bytes(int T, int S, int W) {
@@ -151,8 +157,10 @@ __host__ __device__ inline size_t tile_smem_bytes(int T, int S, int W) {
     return (b + 15) & ~(size_t)15;
 }
 
-__device__ inline TileSmem carve_tile(char* base, int T, int S, int W) {
+// Obstacle staging follows the tile region: tile_smem_bytes(T, S, W) + 16 lds_n.
+__device__ inline TileSmem carve_tile(char* base, int T, int S, int W, int lds_n = 0) {
     TileSmem t;
+    t.obs = lds_n > 0 ? reinterpret_cast<float4*>(base + tile_smem_bytes(T, S, W)) : nullptr;
     char* p = base;
     t.cen = reinterpret_cast<float4*>(p);   p += sizeof(float4) * (size_t)(S > 0 ? S : 1) * T;
     t.lb = reinterpret_cast<float4*>(p);    p += sizeof(float4) * (size_t)kMaxDof * T;
@@ -204,6 +212,14 @@ __device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const Til
             t.cen[s * T + c] = o;
         }
     }
+    __syncthreads();
+}
+
+// Copy the obstacle records (x, y, z, r) into the workgroup's LDS copy.
+// Ends with a barrier.
+__device__ inline void stage_obstacles(const ObsView& ob, const TileSmem& t) {
+    if (t.obs)
+        for (int o = threadIdx.x; o < ob.lds_n; o += blockDim.x) t.obs[o] = ob.rec[2 * o];
     __syncthreads();
 }
 
@@ -292,10 +308,10 @@ __device__ inline void tile_pairs_sd(const RobotView& rb, const ObsView& ob, con
 // the obstacles listed in its grid cell.  Every skipped pair is provably
 // separated, so the flag equals that of the all-pairs test.  The pair test is
 // |c - o|^2 < (r_c + r_o)^2 (difference form).  Barrier at exit.
-// `tests` (optional) accumulates the number of sphere-sphere tests performed
-// (bound tests included), one atomic per wave.
-__device__ inline void tile_pairs_grid(const RobotView& rb, const ObsView& ob, const GridView& gv, const TileSmem& t,
-                                       int T, unsigned long long* tests) {
+// Returns the number of sphere-sphere tests this thread performed (bound
+// tests included).
+__device__ inline unsigned tile_pairs_grid(const RobotView& rb, const ObsView& ob, const GridView& gv,
+                                           const TileSmem& t, int T) {
     volatile int* hit = t.hit;
     const int nt = blockDim.x;
     unsigned int ntest = 0;
@@ -306,20 +322,24 @@ __device__ inline void tile_pairs_grid(const RobotView& rb, const ObsView& ob, c
         const float4 A = t.lb[blk.x * T + c], B = t.lb[blk.y * T + c];
         const float dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;
         const float R = A.w + B.w;
-        ++ntest;
+        ntest += blk.w >> 8;               // the link pair's bound test, counted once
         if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) >= R * R) continue;
-        for (int p = blk.z; p < blk.z + blk.w; ++p) {
-            ++ntest;
-            const int2 pr = rb.pairs[p];
-            const float4 a = t.cen[pr.x * T + c];
-            const float4 b = t.cen[pr.y * T + c];
+        const int np = blk.w & 255;
+        int2 pr[kPairChunk];
+#pragma unroll
+        for (int k = 0; k < kPairChunk; ++k) pr[k] = rb.pairs[blk.z + (k < np ? k : 0)];
+        bool found = false;
+#pragma unroll
+        for (int k = 0; k < kPairChunk; ++k) {
+            if (k >= np) break;
+            const float4 a = t.cen[pr[k].x * T + c];
+            const float4 b = t.cen[pr[k].y * T + c];
             const float ex = a.x - b.x, ey = a.y - b.y, ez = a.z - b.z;
             const float Rr = a.w + b.w;
-            if (fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < Rr * Rr) {
-                hit[c] = 1;
-                break;
-            }
+            found |= fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < Rr * Rr;
         }
+        ntest += np;
+        if (found) hit[c] = 1;
     }
     if (ob.n > 0) {
         const GridGeom g = *gv.geom;
@@ -336,38 +356,65 @@ __device__ inline void tile_pairs_grid(const RobotView& rb, const ObsView& ob, c
             const int cnt = gv.count[cell];
             const bool full = cnt > gv.cap;
             const int n = full ? ob.n : cnt;
-            const unsigned short* lst = gv.list + (size_t)cell * gv.cap;
-            for (int k = 0; k < n; ++k) {
-                ++ntest;
-                const int o = full ? k : (int)lst[k];
-                const float4 O = ob.rec[2 * o];
-                const float ex = C.x - O.x, ey = C.y - O.y, ez = C.z - O.z;
-                const float Rr = C.w + O.w;
-                if (fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < Rr * Rr) {
-                    hit[c] = 1;
-                    break;
+            // list entries four at a time (cell lists are 8-byte aligned), the
+            // four record reads issued together
+            const ushort4* lst4 = reinterpret_cast<const ushort4*>(gv.list + (size_t)cell * gv.cap);
+            bool found = false;
+            for (int k0 = 0; k0 < n && !found; k0 += 4) {
+                int oi[4];
+                if (full) {
+                    oi[0] = k0; oi[1] = k0 + 1; oi[2] = k0 + 2; oi[3] = k0 + 3;
+                } else {
+                    const ushort4 v = lst4[k0 >> 2];
+                    oi[0] = v.x; oi[1] = v.y; oi[2] = v.z; oi[3] = v.w;
+                }
+                float4 O[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int o = (k0 + e < n) ? oi[e] : oi[0];
+                    O[e] = t.obs ? t.obs[o] : ob.rec[2 * o];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (k0 + e >= n) break;
+                    ++ntest;
+                    const float ex = C.x - O[e].x, ey = C.y - O[e].y, ez = C.z - O[e].z;
+                    const float Rr = C.w + O[e].w;
+                    if (fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < Rr * Rr) found = true;
                 }
             }
+            if (found) hit[c] = 1;
         }
     }
-    if (tests) {
-        unsigned long long v = ntest;
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if ((threadIdx.x & 63) == 0) atomicAdd(tests, v);
-    }
     __syncthreads();
+    return ntest;
+}
+
+// Adds the wave's test counts to one of kTestSlots counters (spread by
+// workgroup, so that the atomics of many small workgroups do not queue on
+// one address).  Every lane of the wave must call it.
+constexpr int kTestSlots = 256;
+
+__device__ inline void flush_tests(unsigned long long* tests, unsigned n) {
+    unsigned long long v = n;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) atomicAdd(tests + (blockIdx.x + 97u * blockIdx.y) % kTestSlots, v);
 }
 
 // Whole tile check on t.q[0..n_valid).  Flags mode fills t.hit; signed-
 // distance mode also fills t.red[c] (overall) and t.red[W*T + c] (self).
+// Returns the thread's count of pair tests (flags mode; 0 otherwise).
 template <bool SD>
-__device__ inline void tile_check(const RobotView& rb, const ObsView& ob, const GridView& gv, const TileSmem& t,
-                                  int T, int n_valid) {
+__device__ inline unsigned tile_check(const RobotView& rb, const ObsView& ob, const GridView& gv, const TileSmem& t,
+                                      int T, int n_valid) {
     tile_fk(rb, ob, t, T, n_valid);
     if (threadIdx.x < (unsigned)T) t.hit[threadIdx.x] = (threadIdx.x < (unsigned)n_valid) ? 0 : 1;
     __syncthreads();
-    if (SD) tile_pairs_sd(rb, ob, t, T, n_valid);
-    else tile_pairs_grid(rb, ob, gv, t, T, gv.tests);
+    if (SD) {
+        tile_pairs_sd(rb, ob, t, T, n_valid);
+        return 0;
+    }
+    return tile_pairs_grid(rb, ob, gv, t, T);
 }
 
 }  // namespace ezo

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -44,6 +45,9 @@ struct ezo_ctx {
     double phase_ms[EZO_NUM_PHASES] = {};
     int64_t timed_iters = 0;
     unsigned long long* d_tests = nullptr;   // [EZO_NUM_PHASES] sphere-sphere tests per phase
+    std::string arch;                  // device architecture name (tuning cache key)
+    bool autotune = true;              // time launch shapes on first use of a tuning key
+    hipEvent_t tune_ev[2] = {};
 };
 
 struct ezo_robot {
@@ -87,6 +91,36 @@ struct ezo_surrogate {
     int batch = 0;
     void* tb = nullptr;
 };
+
+// ---------------------------------------------------------------------------
+// Launch shapes of the tile kernels and their tuning cache
+// ---------------------------------------------------------------------------
+// T configurations per workgroup, W waves per workgroup, obstacle records
+// staged in LDS (stage = 1) or read from global memory.  T = 0: not chosen.
+struct TileCfg {
+    int T = 0, W = 0, stage = 0;
+};
+
+// For the sampler, T = lanes per walk and W = waves per workgroup.
+enum TuneKind { TUNE_CHECK_FLAGS = 0, TUNE_CHECK_SD = 1, TUNE_BISECT = 2, TUNE_SAMPLE = 3, TUNE_NKINDS };
+
+// A tuned shape applies to calls with the same device architecture, kernel,
+// robot size (dof, spheres, self pairs), obstacle count and work size
+// (bucket = floor(log2(items))).  Sampler keys hold the dof and the walk
+// count only (spheres = self pairs = obstacles = 0).
+struct TuneKey {
+    std::string arch;
+    int kind = 0, dof = 0, S = 0, P = 0, n_obs = 0, bucket = 0;
+    bool operator<(const TuneKey& o) const;
+};
+
+int ezo_tune_bucket(int64_t items);
+bool ezo_tune_lookup(const TuneKey& k, TileCfg* out);
+// Times every candidate (one warm-up and kTuneReps timed launches of `run`
+// on stream st, host-synchronising) and caches the fastest under k.
+// Candidates whose launch fails are skipped.  Needs at least one candidate.
+ezo_status ezo_tune_search(ezo_ctx* c, const TuneKey& k, const std::vector<TileCfg>& cands, hipStream_t st,
+                           const std::function<ezo_status(const TileCfg&)>& run, TileCfg* best);
 
 extern std::string g_create_err;
 ezo_status ezo_fail(ezo_ctx* c, ezo_status code, const char* fmt, ...);

@@ -162,7 +162,8 @@ __global__ void __launch_bounds__(1024) k_check(RobotView rb, ObsView ob, GridVi
     if (base >= n) return;
     const int nv = (int)((n - base) < T ? (n - base) : T);
     const int W = blockDim.x >> 6;
-    TileSmem t = carve_tile(smem, T, rb.n_spheres, W);
+    TileSmem t = carve_tile(smem, T, rb.n_spheres, W, SD ? 0 : ob.lds_n);
+    if (!SD) stage_obstacles(ob, t);
     const float* qb = q + b * q_batch;
     for (int i = threadIdx.x; i < T * rb.dof; i += blockDim.x) {
         const int c = i % T, j = i / T;
@@ -175,7 +176,8 @@ __global__ void __launch_bounds__(1024) k_check(RobotView rb, ObsView ob, GridVi
         if (s && stats) atomicAdd((unsigned long long*)&stats[b].screened, 1ull);
     }
     __syncthreads();
-    tile_check<SD>(rb, ob, gv, t, T, nv);
+    const unsigned ntest = tile_check<SD>(rb, ob, gv, t, T, nv);
+    if (gv.tests) flush_tests(gv.tests, ntest);
     if (threadIdx.x < (unsigned)nv) {
         const int64_t g = b * out_batch + base + threadIdx.x;
         flags[g] = (uint8_t)t.hit[threadIdx.x];
@@ -215,12 +217,14 @@ __global__ void __launch_bounds__(256) k_centres(RobotView rb, ObsView ob, const
 }
 
 // ---------------------------------------------------------------------------
-// Hit-and-run sampler.  A walk is carried by a group of L lanes (L in {4, 8})
-// that all hold its position x and direction u; per step, lane m < #calls
-// computes Philox call m, lane m < #pairs computes Box-Muller pair m, and the
-// words and normals are exchanged by shuffles; the polytope rows (LDS, shared
-// by the workgroup's walks, all from one edge = blockIdx.y) are split over
-// the L lanes and the chord ends are reduced with shuffle min/max.
+// Hit-and-run sampler.  A walk is carried by a group of L lanes (L in {1, 2,
+// 4, 8}) that all hold its position x and direction u.  The step's random
+// words (Philox calls) and normals (Box-Muller pairs) are drawn either by
+// every lane itself (L <= 2) or split over the group -- lane m computes call
+// m and pair m -- and exchanged by shuffles (L >= 4).  The polytope rows
+// (LDS, shared by the workgroup's walks, all from one edge = blockIdx.y) are
+// split over the L lanes and the chord ends are reduced with shuffle min/max,
+// which is exact, so the samples do not depend on L.
 // Rows stored as [F][D] normals plus b[F].
 // ---------------------------------------------------------------------------
 template <int D, int L>
@@ -229,7 +233,7 @@ __global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict
                                                 const float* __restrict__ edges, uint32_t key0, uint32_t key1,
                                                 int64_t edge_id_base, int n_mix, float* __restrict__ S,
                                                 int64_t stride, const int* __restrict__ status, IterArgs it) {
-    static_assert(L == 4 || L == 8, "lanes per walk");
+    static_assert(L == 1 || L == 2 || L == 4 || L == 8, "lanes per walk");
     extern __shared__ __align__(16) char smem[];
     const int e = blockIdx.y;
     if (!edge_running(status, e)) return;
@@ -261,42 +265,68 @@ __global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict
 #pragma unroll
         for (int j = 0; j < D; ++j) x[j] = j < dof ? fmaf(w0, v[dof + j] - v[j], v[j]) : 0.f;
     }
-    const int npair = (dof + 1) >> 1;                     // Box-Muller pairs (<= 4 <= L)
+    const int npair = (dof + 1) >> 1;                     // Box-Muller pairs (<= 4)
     const int tword = 2 * npair;                          // word holding the chord position
-    const int ncall = (tword + 4) >> 2;                   // Philox calls per step (<= 3 <= L)
+    const int ncall = (tword + 4) >> 2;                   // Philox calls per step (<= 3)
     for (int s = 1; s <= n_mix; ++s) {
-        // Philox call `sub` of this step (lanes sub >= ncall compute a spare call)
-        const U4 r = philox4x32_10(U4{ii, eid, kk, 16u * (uint32_t)s + (uint32_t)(sub < ncall ? sub : 0)}, key0, key1);
-        // Box-Muller pair m = sub uses words 2m, 2m+1 = call m/2, components 2(m%2), 2(m%2)+1
-        const int src = g0 + (sub >> 1);
-        const uint32_t wx = __shfl((int)r.x, src), wy = __shfl((int)r.y, src);
-        const uint32_t wz = __shfl((int)r.z, src), ww = __shfl((int)r.w, src);
-        const bool hi = (sub & 1) != 0;
-        const float ua = u01(hi ? wz : wx);
-        const float ub = u01(hi ? ww : wy);
-        const float rad = sqrtf(-2.f * logf(ua));
-        float sn, cs;
-        sincospif(2.f * ub, &sn, &cs);
-        const float g_even = rad * cs, g_odd = rad * sn;
-        float nrm = 0.f;
+        float wt;
+        if constexpr (L <= 2) {
+            U4 r[3] = {};
 #pragma unroll
-        for (int m = 0; m < (D + 1) / 2; ++m) {
-            const float ge = __shfl(g_even, g0 + m);
-            const float go = __shfl(g_odd, g0 + m);
-            if (2 * m < D) u[2 * m] = (2 * m < dof) ? ge : 0.f;
-            if (2 * m + 1 < D) u[2 * m + 1] = (2 * m + 1 < dof) ? go : 0.f;
+            for (int c = 0; c < 3; ++c)
+                if (c < ncall) r[c] = philox4x32_10(U4{ii, eid, kk, 16u * (uint32_t)s + (uint32_t)c}, key0, key1);
+#pragma unroll
+            for (int m = 0; m < (D + 1) / 2; ++m) {
+                float ge = 0.f, go = 0.f;
+                if (m < npair) {
+                    const U4& rm = r[m >> 1];
+                    const bool hi = (m & 1) != 0;
+                    const float ua = u01(hi ? rm.z : rm.x);
+                    const float ub = u01(hi ? rm.w : rm.y);
+                    const float rad = sqrtf(-2.f * logf(ua));
+                    float sn, cs;
+                    sincospif(2.f * ub, &sn, &cs);
+                    ge = rad * cs;
+                    go = rad * sn;
+                }
+                if (2 * m < D) u[2 * m] = (2 * m < dof) ? ge : 0.f;
+                if (2 * m + 1 < D) u[2 * m + 1] = (2 * m + 1 < dof) ? go : 0.f;
+            }
+            wt = u01(word_of(r[tword >> 2], tword & 3));
+        } else {
+            // Philox call `sub` of this step (lanes sub >= ncall compute a spare call)
+            const U4 r = philox4x32_10(U4{ii, eid, kk, 16u * (uint32_t)s + (uint32_t)(sub < ncall ? sub : 0)}, key0, key1);
+            // Box-Muller pair m = sub uses words 2m, 2m+1 = call m/2, components 2(m%2), 2(m%2)+1
+            const int src = g0 + (sub >> 1);
+            const uint32_t wx = __shfl((int)r.x, src), wy = __shfl((int)r.y, src);
+            const uint32_t wz = __shfl((int)r.z, src), ww = __shfl((int)r.w, src);
+            const bool hi = (sub & 1) != 0;
+            const float ua = u01(hi ? wz : wx);
+            const float ub = u01(hi ? ww : wy);
+            const float rad = sqrtf(-2.f * logf(ua));
+            float sn, cs;
+            sincospif(2.f * ub, &sn, &cs);
+            const float g_even = rad * cs, g_odd = rad * sn;
+#pragma unroll
+            for (int m = 0; m < (D + 1) / 2; ++m) {
+                const float ge = __shfl(g_even, g0 + m);
+                const float go = __shfl(g_odd, g0 + m);
+                if (2 * m < D) u[2 * m] = (2 * m < dof) ? ge : 0.f;
+                if (2 * m + 1 < D) u[2 * m + 1] = (2 * m + 1 < dof) ? go : 0.f;
+            }
+            // chord position word: call tword/4, component tword%4
+            const int tsrc = g0 + (tword >> 2);
+            const uint32_t t0 = __shfl((int)r.x, tsrc), t1 = __shfl((int)r.y, tsrc);
+            const uint32_t t2 = __shfl((int)r.z, tsrc), t3 = __shfl((int)r.w, tsrc);
+            const int tc = tword & 3;
+            wt = u01(tc == 0 ? t0 : (tc == 1 ? t1 : (tc == 2 ? t2 : t3)));
         }
+        float nrm = 0.f;
 #pragma unroll
         for (int j = 0; j < D; ++j) nrm = fmaf(u[j], u[j], nrm);
         const float inv = 1.0f / sqrtf(nrm);
 #pragma unroll
         for (int j = 0; j < D; ++j) u[j] *= inv;
-        // chord position word: call tword/4, component tword%4
-        const int tsrc = g0 + (tword >> 2);
-        const uint32_t t0 = __shfl((int)r.x, tsrc), t1 = __shfl((int)r.y, tsrc);
-        const uint32_t t2 = __shfl((int)r.z, tsrc), t3 = __shfl((int)r.w, tsrc);
-        const int tc = tword & 3;
-        const float wt = u01(tc == 0 ? t0 : (tc == 1 ? t1 : (tc == 2 ? t2 : t3)));
         float tlo = -INFINITY, thi = INFINITY;
         for (int f = sub; f < F; f += L) {
             float den = 0.f, ax = 0.f;
@@ -422,7 +452,8 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView o
     const int nv = (nc - base) < T ? (nc - base) : T;
     const int dof = rb.dof;
     const int W = blockDim.x >> 6;
-    TileSmem t = carve_tile(smem, T, rb.n_spheres, W);
+    TileSmem t = carve_tile(smem, T, rb.n_spheres, W, ob.lds_n);
+    stage_obstacles(ob, t);
     const int tid = threadIdx.x;
     const bool own = tid < nv;
     if (tid < T) t.scr[tid] = 0;          // bisection midpoints are always checked exactly
@@ -456,7 +487,7 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView o
         }
     }
     __syncthreads();
-    tile_check<false>(rb, ob, gv, t, T, nv);
+    unsigned ntest = tile_check<false>(rb, ob, gv, t, T, nv);
     if (own) {
         const int h = t.hit[tid];
         proj_collides[(size_t)e * cand_cap + base + tid] = (uint8_t)h;
@@ -467,7 +498,7 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView o
         if (own)
             for (int j = 0; j < dof; ++j) t.q[tid * kMaxDof + j] = 0.5f * (lo[j] + hi[j]);
         __syncthreads();
-        tile_check<false>(rb, ob, gv, t, T, nv);
+        ntest += tile_check<false>(rb, ob, gv, t, T, nv);
         if (own) {
             const bool h = t.hit[tid] != 0;
 #pragma unroll
@@ -488,6 +519,7 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView o
         }
         t_star[(size_t)e * cand_cap + base + tid] = sqrtf(ts);
     }
+    if (gv.tests) flush_tests(gv.tests, ntest);
 }
 
 // ---------------------------------------------------------------------------
@@ -594,6 +626,22 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
 // ---------------------------------------------------------------------------
 // P_e = D (box rows: +e_j <= hi_j, then -e_j <= -lo_j); status -1 (running) or
 // INVALID (3) when a vertex is outside D or not finite.
+// The autotuner's stand-in polytope: the joint box, its 2 dof rows repeated
+// up to F rows (a typical face count of the loop; repeated rows leave the
+// polytope unchanged).  One thread per edge.
+__global__ void k_tune_polytope(int dof, const float* __restrict__ q_lo, const float* __restrict__ q_hi, int n_edges,
+                                int cap, int F, float* __restrict__ A, float* __restrict__ bvec,
+                                int* __restrict__ n_faces) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_edges) return;
+    for (int f = 0; f < F; ++f) {
+        const int g = f % (2 * dof), j0 = g % dof;
+        for (int j = 0; j < dof; ++j) A[((size_t)e * cap + f) * dof + j] = j == j0 ? (g < dof ? 1.f : -1.f) : 0.f;
+        bvec[(size_t)e * cap + f] = g < dof ? q_hi[j0] : -q_lo[j0];
+    }
+    n_faces[e] = F;
+}
+
 __global__ void k_init_edges(int dof, const float* __restrict__ q_lo, const float* __restrict__ q_hi,
                              const float* __restrict__ edges, int n_edges, float* __restrict__ A,
                              float* __restrict__ bvec, int* __restrict__ n_faces, int cap, int* __restrict__ status,

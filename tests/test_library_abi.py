@@ -60,3 +60,39 @@ def test_test_constants_reject_bad_arguments(ezo):
         ezo.test_constants(0.0, 0.05, 0.5, 1)
     with pytest.raises(ezo.EzoError):
         ezo.test_constants(0.1, 0.05, 0.5, 0)
+
+
+TUNE_LINE = ('{"arch":"gfx950","kernel":"bisect","dof":7,"spheres":70,"self_pairs":1500,"obstacles":512,'
+             '"log2_items":13,"T":16,"W":4,"stage":1,"us":93.5}')
+
+
+def test_tuning_cache_roundtrip_on_host(ezo):
+    """The launch-shape cache is host state: import, export, clear."""
+    ezo.tune_cache_clear()
+    assert ezo.tune_cache_export() == ""
+    extra = TUNE_LINE.replace('"bisect"', '"check_sd"').replace('"T":16', '"T":64')
+    assert ezo.tune_cache_import(TUNE_LINE + "\n" + extra + "\n") == 2
+    ents = ezo.tune_cache_entries()
+    assert len(ents) == 2
+    by_kernel = {e["kernel"]: e for e in ents}
+    assert by_kernel["bisect"]["T"] == 16 and by_kernel["bisect"]["stage"] == 1
+    assert by_kernel["check_sd"]["T"] == 64 and by_kernel["bisect"]["obstacles"] == 512
+    # re-import of an exported text is the identity
+    text = ezo.tune_cache_export()
+    ezo.tune_cache_clear()
+    assert ezo.tune_cache_import(text) == 2 and ezo.tune_cache_export() == text
+    ezo.tune_cache_clear()
+    assert ezo.tune_cache_entries() == []
+
+
+@pytest.mark.parametrize("bad", [
+    TUNE_LINE.replace('"T":16', '"T":12'),              # tile size not a power of two
+    TUNE_LINE.replace('"W":4', '"W":17'),               # more than 16 waves
+    TUNE_LINE.replace('"bisect"', '"gemm"'),            # unknown kernel
+    TUNE_LINE.replace('"stage":1,', ''),                # missing key
+])
+def test_tuning_cache_rejects_malformed_lines(ezo, bad):
+    ezo.tune_cache_clear()
+    with pytest.raises(ezo.EzoError):
+        ezo.tune_cache_import(TUNE_LINE + "\n" + bad)
+    assert ezo.tune_cache_entries() == []               # nothing imported from a rejected text
