@@ -369,6 +369,7 @@ ezo_status tune_bisect_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov
 // of them in collision.  At most kTuneEdges edges take part (already far more
 // workgroups than CUs).
 constexpr int kTuneEdges = 16;
+constexpr int kItersPerGraph = 2;        // iterations captured per replayed graph
 
 ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const GridView& gv, const float* edges,
                           int E, const ezo_params* p, int S_cap, int64_t stride, float* A, float* b, int* n_faces,
@@ -478,6 +479,7 @@ void ezo_ctx_destroy(ezo_ctx* c) {
         if (ev) e = hipEventDestroy(ev);
     for (auto& ev : c->tune_ev)
         if (ev) e = hipEventDestroy(ev);
+    if (c->loop_exec) e = hipGraphExecDestroy(c->loop_exec);
     if (c->d_tests) e = hipFree(c->d_tests);
     if (c->stream) e = hipStreamDestroy(c->stream);
     (void)e;
@@ -937,24 +939,44 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
         }
         return ls;
     };
-    hipGraph_t graph = nullptr;
+    // Normal mode: kItersPerGraph iterations per graph (extra iterations after
+    // every edge is final are no-ops: each kernel skips final edges), one
+    // 4-byte poll per replay.  The executable graph is kept by the context and
+    // updated in place with the next call's capture (same topology, new
+    // arguments); instantiation happens only when the topology changes.
     hipGraphExec_t exec = nullptr;
+    int per = 1;
     if (!c->timing) {
+        per = kItersPerGraph;
+        hipGraph_t graph = nullptr;
         HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        ezo_status cs = launch_iteration(false);
+        ezo_status cs = EZO_OK;
+        for (int i = 0; i < per && cs == EZO_OK; ++i) cs = launch_iteration(false);
         hipError_t ce = hipStreamEndCapture(st, &graph);
         if (cs) {
             if (graph) (void)hipGraphDestroy(graph);
             return cs;
         }
         if (ce != hipSuccess) return ezo_fail(c, EZO_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
-        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        if (c->loop_exec) {
+            hipGraphNode_t bad = nullptr;
+            hipGraphExecUpdateResult ur = hipGraphExecUpdateError;
+            if (hipGraphExecUpdate(c->loop_exec, graph, &bad, &ur) != hipSuccess || ur != hipGraphExecUpdateSuccess) {
+                (void)hipGetLastError();
+                (void)hipGraphExecDestroy(c->loop_exec);
+                c->loop_exec = nullptr;
+            }
+        }
+        if (!c->loop_exec && hipGraphInstantiate(&c->loop_exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            c->loop_exec = nullptr;
             (void)hipGraphDestroy(graph);
             return ezo_fail(c, EZO_E_HIP, "graph instantiation failed");
         }
+        (void)hipGraphDestroy(graph);
+        exec = c->loop_exec;
     }
     ezo_status result = EZO_OK;
-    for (int k = 1; k <= p->max_iters; ++k) {
+    for (int k = 1; k <= p->max_iters; k += per) {
         hipError_t e1 = hipSuccess;
         if (exec) {
             e1 = hipGraphLaunch(exec, st);
@@ -977,8 +999,6 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
         }
         if (c->pinned[0] == 0) break;
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
     if (result) return result;
     if (stats) {
         std::vector<EdgeStatsDev> hs(E);

@@ -48,6 +48,7 @@ struct ezo_ctx {
     std::string arch;                  // device architecture name (tuning cache key)
     bool autotune = true;              // time launch shapes on first use of a tuning key
     hipEvent_t tune_ev[2] = {};
+    hipGraphExec_t loop_exec = nullptr;   // the inflation loop's graph, updated in place by later calls
 };
 
 struct ezo_robot {
