@@ -240,8 +240,8 @@ ezo_status launch_sample(ezo_ctx* c, int dof, const float* A, const float* b, co
                          float* S, int64_t stride, const int* status, const IterArgs& it, hipStream_t st,
                          const TileCfg* shape = nullptr) {
     const int D = dof <= 4 ? 4 : 8;
-    const size_t lds = sizeof(float) * (size_t)cap * (D + 1);
-    if (lds > c->lds_cap) return ezo_fail(c, EZO_E_UNSUPPORTED, "face capacity %d too large for the sampler", cap);
+    if (sample_smem_bytes(D, 8, cap, 256) > c->lds_cap)
+        return ezo_fail(c, EZO_E_UNSUPPORTED, "face capacity %d too large for the sampler", cap);
     if (max_samples <= 0 || E <= 0) return EZO_OK;
     const int64_t walks = (int64_t)max_samples * E;
     TileCfg g;
@@ -253,6 +253,7 @@ ezo_status launch_sample(ezo_ctx* c, int dof, const float* A, const float* b, co
     }
     if (!sample_cfg_valid(g)) return ezo_fail(c, EZO_E_INVALID, "sampler shape T=%d W=%d", g.T, g.W);
     const int L = g.T;
+    const size_t lds = sample_smem_bytes(D, L, cap, 256);
     const int64_t threads = (int64_t)max_samples * L;
     dim3 grid((unsigned)((threads + 255) / 256), (unsigned)E), block(256);
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
@@ -811,7 +812,7 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
     if (!edges || !A || !b || !n_faces || !edge_status || (n_obs > 0 && !obs))
         return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
     const int cap = p->face_capacity;
-    if (sizeof(float) * (size_t)cap * ((dof <= 4 ? 4 : 8) + 1) > c->lds_cap)
+    if (sample_smem_bytes(dof <= 4 ? 4 : 8, 8, cap, 256) > c->lds_cap)
         return ezo_fail(c, EZO_E_UNSUPPORTED, "face_capacity %d too large", cap);
     if ((size_t)p->n_p > c->lds_cap - 1024) return ezo_fail(c, EZO_E_UNSUPPORTED, "n_p %d too large", p->n_p);
     // per-iteration constants, FP64 on the host

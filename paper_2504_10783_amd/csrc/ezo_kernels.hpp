@@ -217,16 +217,125 @@ __global__ void __launch_bounds__(256) k_centres(RobotView rb, ObsView ob, const
 }
 
 // ---------------------------------------------------------------------------
-// Hit-and-run sampler.  A walk is carried by a group of L lanes (L in {1, 2,
-// 4, 8}) that all hold its position x and direction u.  The step's random
-// words (Philox calls) and normals (Box-Muller pairs) are drawn either by
-// every lane itself (L <= 2) or split over the group -- lane m computes call
-// m and pair m -- and exchanged by shuffles (L >= 4).  The polytope rows
-// (LDS, shared by the workgroup's walks, all from one edge = blockIdx.y) are
-// split over the L lanes and the chord ends are reduced with shuffle min/max,
-// which is exact, so the samples do not depend on L.
+// Hit-and-run sampler.
+//
+// Step s of walk i (edge e, iteration k) draws Philox calls (i, e, k, 16 s + c),
+// c < 3: words 2m, 2m+1 feed Box-Muller pair m (normals 2m, 2m+1 of the
+// direction g ~ N(0, I)), word 2 ceil(dof/2) gives the chord position; u =
+// g / |g|.  The chord through x along u is cut by every row of P.
+//
+// A walk is carried by a group of L lanes (L in {1, 2, 4, 8}) that all hold
+// x; the rows of P (LDS, all walks of a workgroup belong to one edge =
+// blockIdx.y) are split over the L lanes and the chord ends are combined with
+// DPP min/max, which is exact, so the samples do not depend on L.
+//   L <= 2: every lane draws each step's direction itself.
+//   L >= 4: the directions of 2 L steps are drawn ahead, lane m of the group
+//   drawing steps m and m + L, into LDS; the walk then reads them, so the
+//   random draws are off the walk's step-to-step dependency chain.
 // Rows stored as [F][D] normals plus b[F].
 // ---------------------------------------------------------------------------
+__host__ __device__ constexpr int sample_chunk(int L) { return 2 * L; }        // steps drawn ahead (L >= 4)
+__host__ __device__ constexpr int sample_dir_stride(int D) { return D + 4; }   // u[D], chord word, pad
+
+// LDS bytes of k_sample: rows, then (L >= 4) the drawn directions (the same
+// size for every L >= 4).
+__host__ __device__ inline size_t sample_smem_bytes(int D, int L, int cap, int threads) {
+    const size_t rows = (sizeof(float) * (size_t)cap * (D + 1) + 15) & ~(size_t)15;
+    return rows + (L >= 4 ? sizeof(float) * (size_t)(threads / L) * sample_chunk(L) * sample_dir_stride(D) : 0);
+}
+
+// Normalised direction u (zero beyond dof) and chord word of one step.
+template <int D>
+__device__ inline float draw_direction(int dof, uint32_t ii, uint32_t eid, uint32_t kk, uint32_t s, uint32_t key0,
+                                       uint32_t key1, float (&u)[D]) {
+    const int npair = (dof + 1) >> 1;
+    const int tword = 2 * npair;
+    const int ncall = (tword + 4) >> 2;
+    U4 r[3] = {};
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        if (c < ncall) r[c] = philox4x32_10(U4{ii, eid, kk, 16u * s + (uint32_t)c}, key0, key1);
+#pragma unroll
+    for (int m = 0; m < (D + 1) / 2; ++m) {
+        float ge = 0.f, go = 0.f;
+        if (m < npair) {
+            const U4& rm = r[m >> 1];
+            const bool hi = (m & 1) != 0;
+            const float ua = u01(hi ? rm.z : rm.x);
+            const float ub = u01(hi ? rm.w : rm.y);
+            const float rad = sqrtf(-2.f * logf(ua));
+            float sn, cs;
+            sincospif(2.f * ub, &sn, &cs);
+            ge = rad * cs;
+            go = rad * sn;
+        }
+        if (2 * m < D) u[2 * m] = (2 * m < dof) ? ge : 0.f;
+        if (2 * m + 1 < D) u[2 * m + 1] = (2 * m + 1 < dof) ? go : 0.f;
+    }
+    float nrm = 0.f;
+#pragma unroll
+    for (int j = 0; j < D; ++j) nrm = fmaf(u[j], u[j], nrm);
+    const float inv = 1.0f / sqrtf(nrm);
+#pragma unroll
+    for (int j = 0; j < D; ++j) u[j] *= inv;
+    return u01(word_of(r[tword >> 2], tword & 3));
+}
+
+// min / max over the L lanes of a group (groups aligned to L lanes): DPP
+// quad permutations for lane distances 1 and 2, the half-row mirror (lane i
+// with 7 - i) to join the two quads of an 8-lane group.
+template <int L>
+__device__ __forceinline__ void group_minmax(float& lo_max, float& hi_min) {
+    auto dpp = [](float v, int ctrl) -> float {
+        const int b = __builtin_bit_cast(int, v);
+        int r;
+        switch (ctrl) {
+            case 0: r = __builtin_amdgcn_mov_dpp(b, 0xB1, 0xF, 0xF, true); break;    // quad_perm [1,0,3,2]
+            case 1: r = __builtin_amdgcn_mov_dpp(b, 0x4E, 0xF, 0xF, true); break;    // quad_perm [2,3,0,1]
+            default: r = __builtin_amdgcn_mov_dpp(b, 0x141, 0xF, 0xF, true); break;  // row_half_mirror
+        }
+        return __builtin_bit_cast(float, r);
+    };
+    if constexpr (L >= 2) {
+        hi_min = fminf(hi_min, dpp(hi_min, 0));
+        lo_max = fmaxf(lo_max, dpp(lo_max, 0));
+    }
+    if constexpr (L >= 4) {
+        hi_min = fminf(hi_min, dpp(hi_min, 1));
+        lo_max = fmaxf(lo_max, dpp(lo_max, 1));
+    }
+    if constexpr (L >= 8) {
+        hi_min = fminf(hi_min, dpp(hi_min, 2));
+        lo_max = fmaxf(lo_max, dpp(lo_max, 2));
+    }
+}
+
+// One hit-and-run step of the group's walk: chord of x along u through P
+// (rows f = sub, sub + L, ... on this lane), x += t u with t = tlo + w (thi -
+// tlo); t = 0 when rounding empties the chord.
+template <int D, int L>
+__device__ __forceinline__ void walk_step(const float* rowA, const float* rowb, int F, int sub, const float (&u)[D],
+                                          float wt, float (&x)[D]) {
+    float tlo = -INFINITY, thi = INFINITY;
+    for (int f = sub; f < F; f += L) {
+        float den = 0.f, ax = 0.f;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const float a = rowA[f * D + j];
+            den = fmaf(a, u[j], den);
+            ax = fmaf(a, x[j], ax);
+        }
+        const float tt = (rowb[f] - ax) * __builtin_amdgcn_rcpf(den);
+        if (den > 0.f) thi = fminf(thi, tt);
+        else if (den < 0.f) tlo = fmaxf(tlo, tt);
+    }
+    group_minmax<L>(tlo, thi);
+    float tm = 0.f;
+    if (thi >= tlo && tlo > -INFINITY && thi < INFINITY) tm = fmaf(wt, thi - tlo, tlo);
+#pragma unroll
+    for (int j = 0; j < D; ++j) x[j] = fmaf(tm, u[j], x[j]);
+}
+
 template <int D, int L>
 __global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict__ A, const float* __restrict__ bvec,
                                                 const int* __restrict__ n_faces, int cap,
@@ -250,10 +359,9 @@ __global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int sub = lane & (L - 1);                       // position in the walk's lane group
-    const int g0 = lane - sub;                            // first lane of the group
     const int i = (blockIdx.x * blockDim.x + threadIdx.x) / L;
-    // A group past the end still runs (its lanes feed no shuffles of others)
-    // but stores nothing; groups never straddle walks.
+    // A group past the end still runs (it takes part in the workgroup's
+    // barriers) but stores nothing; groups never straddle walks.
     const bool live = i < iv.nS;
     const float* v = edges + (size_t)e * 2 * dof;
     const uint32_t eid = (uint32_t)(edge_id_base + e);
@@ -265,90 +373,31 @@ __global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict
 #pragma unroll
         for (int j = 0; j < D; ++j) x[j] = j < dof ? fmaf(w0, v[dof + j] - v[j], v[j]) : 0.f;
     }
-    const int npair = (dof + 1) >> 1;                     // Box-Muller pairs (<= 4)
-    const int tword = 2 * npair;                          // word holding the chord position
-    const int ncall = (tword + 4) >> 2;                   // Philox calls per step (<= 3)
-    for (int s = 1; s <= n_mix; ++s) {
-        float wt;
-        if constexpr (L <= 2) {
-            U4 r[3] = {};
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                if (c < ncall) r[c] = philox4x32_10(U4{ii, eid, kk, 16u * (uint32_t)s + (uint32_t)c}, key0, key1);
-#pragma unroll
-            for (int m = 0; m < (D + 1) / 2; ++m) {
-                float ge = 0.f, go = 0.f;
-                if (m < npair) {
-                    const U4& rm = r[m >> 1];
-                    const bool hi = (m & 1) != 0;
-                    const float ua = u01(hi ? rm.z : rm.x);
-                    const float ub = u01(hi ? rm.w : rm.y);
-                    const float rad = sqrtf(-2.f * logf(ua));
-                    float sn, cs;
-                    sincospif(2.f * ub, &sn, &cs);
-                    ge = rad * cs;
-                    go = rad * sn;
-                }
-                if (2 * m < D) u[2 * m] = (2 * m < dof) ? ge : 0.f;
-                if (2 * m + 1 < D) u[2 * m + 1] = (2 * m + 1 < dof) ? go : 0.f;
-            }
-            wt = u01(word_of(r[tword >> 2], tword & 3));
-        } else {
-            // Philox call `sub` of this step (lanes sub >= ncall compute a spare call)
-            const U4 r = philox4x32_10(U4{ii, eid, kk, 16u * (uint32_t)s + (uint32_t)(sub < ncall ? sub : 0)}, key0, key1);
-            // Box-Muller pair m = sub uses words 2m, 2m+1 = call m/2, components 2(m%2), 2(m%2)+1
-            const int src = g0 + (sub >> 1);
-            const uint32_t wx = __shfl((int)r.x, src), wy = __shfl((int)r.y, src);
-            const uint32_t wz = __shfl((int)r.z, src), ww = __shfl((int)r.w, src);
-            const bool hi = (sub & 1) != 0;
-            const float ua = u01(hi ? wz : wx);
-            const float ub = u01(hi ? ww : wy);
-            const float rad = sqrtf(-2.f * logf(ua));
-            float sn, cs;
-            sincospif(2.f * ub, &sn, &cs);
-            const float g_even = rad * cs, g_odd = rad * sn;
-#pragma unroll
-            for (int m = 0; m < (D + 1) / 2; ++m) {
-                const float ge = __shfl(g_even, g0 + m);
-                const float go = __shfl(g_odd, g0 + m);
-                if (2 * m < D) u[2 * m] = (2 * m < dof) ? ge : 0.f;
-                if (2 * m + 1 < D) u[2 * m + 1] = (2 * m + 1 < dof) ? go : 0.f;
-            }
-            // chord position word: call tword/4, component tword%4
-            const int tsrc = g0 + (tword >> 2);
-            const uint32_t t0 = __shfl((int)r.x, tsrc), t1 = __shfl((int)r.y, tsrc);
-            const uint32_t t2 = __shfl((int)r.z, tsrc), t3 = __shfl((int)r.w, tsrc);
-            const int tc = tword & 3;
-            wt = u01(tc == 0 ? t0 : (tc == 1 ? t1 : (tc == 2 ? t2 : t3)));
+    if constexpr (L <= 2) {
+        for (int s = 1; s <= n_mix; ++s) {
+            const float wt = draw_direction<D>(dof, ii, eid, kk, (uint32_t)s, key0, key1, u);
+            walk_step<D, L>(rowA, rowb, F, sub, u, wt, x);
         }
-        float nrm = 0.f;
+    } else {
+        constexpr int SD = sample_dir_stride(D), CH = sample_chunk(L);
+        float* dirs = reinterpret_cast<float*>(smem + sample_smem_bytes(D, 1, cap, 0)) +
+                      (size_t)(threadIdx.x / L) * CH * SD;
+        for (int s0 = 1; s0 <= n_mix; s0 += CH) {
+            const int ns = min(CH, n_mix - s0 + 1);
+            for (int c = sub; c < ns; c += L) {
+                const float wt = draw_direction<D>(dof, ii, eid, kk, (uint32_t)(s0 + c), key0, key1, u);
 #pragma unroll
-        for (int j = 0; j < D; ++j) nrm = fmaf(u[j], u[j], nrm);
-        const float inv = 1.0f / sqrtf(nrm);
-#pragma unroll
-        for (int j = 0; j < D; ++j) u[j] *= inv;
-        float tlo = -INFINITY, thi = INFINITY;
-        for (int f = sub; f < F; f += L) {
-            float den = 0.f, ax = 0.f;
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                const float a = rowA[f * D + j];
-                den = fmaf(a, u[j], den);
-                ax = fmaf(a, x[j], ax);
+                for (int j = 0; j < D; ++j) dirs[c * SD + j] = u[j];
+                dirs[c * SD + D] = wt;
             }
-            const float tt = (rowb[f] - ax) * __builtin_amdgcn_rcpf(den);
-            if (den > 0.f) thi = fminf(thi, tt);
-            else if (den < 0.f) tlo = fmaxf(tlo, tt);
-        }
+            __syncthreads();
+            for (int c = 0; c < ns; ++c) {
 #pragma unroll
-        for (int off = 1; off < L; off <<= 1) {
-            thi = fminf(thi, __shfl_xor(thi, off));
-            tlo = fmaxf(tlo, __shfl_xor(tlo, off));
+                for (int j = 0; j < D; ++j) u[j] = dirs[c * SD + j];
+                walk_step<D, L>(rowA, rowb, F, sub, u, dirs[c * SD + D], x);
+            }
+            __syncthreads();
         }
-        float tm = 0.f;
-        if (thi >= tlo && tlo > -INFINITY && thi < INFINITY) tm = fmaf(wt, thi - tlo, tlo);
-#pragma unroll
-        for (int j = 0; j < D; ++j) x[j] = fmaf(tm, u[j], x[j]);
     }
     if (live) {
 #pragma unroll
