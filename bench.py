@@ -119,6 +119,20 @@ def sweep(args):
     print(json.dumps(line), flush=True)
 
 
+def copy_calibration(args):
+    """A plain device-to-device copy of 1 GiB (read 1 GiB, write 1 GiB) per
+    step: the reference dispatch that scales rocprofv3's FETCH_SIZE and
+    WRITE_SIZE counters to bytes."""
+    import torch
+    n = 1 << 28                                   # float32 elements = 1 GiB
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(max(args.steps, 1)):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_dispatch": 4 * n, "dispatches": max(args.steps, 1)}), flush=True)
+
+
 def screen_compare(args):
     """Learned screen: train on exact self-collision labels, calibrate, then
     time the inflation with and without the screen at identical
@@ -200,6 +214,8 @@ def main():
     ap.add_argument("--screen", action="store_true", help="learned screen vs exact comparison")
     ap.add_argument("--screen-epochs", type=int, default=10)
     ap.add_argument("--no-autotune", action="store_true", help="size-heuristic launch shapes (no tuning)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -208,6 +224,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        copy_calibration(args)
+        return
     if args.workload == "sweep":
         sweep(args)
         return
@@ -313,7 +332,7 @@ def main():
         "roofline": roofline,
         "autotune": not args.no_autotune,
         "first_call_ms": first_call_ms,
-        "launch_shapes": [{k: e[k] for k in ("kernel", "log2_items", "T", "W", "stage", "us")}
+        "launch_shapes": [{k: e[k] for k in ("kernel", "log2_items", "T", "W", "stage", "depth", "us")}
                           for e in ezo.tune_cache_entries()
                           if e["obstacles"] == int(obs.shape[0]) or e["kernel"] == "sample"],
     }

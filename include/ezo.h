@@ -338,8 +338,8 @@ ezo_status ezo_get_phase_timing(ezo_ctx *ctx, double *ms_out, int64_t *iteration
  * same pair tests whatever the split, and the sampler's split of the faces
  * is reduced with exact min/max), only the time.
  * With autotuning on (the default), the first call whose tuning key is new
- * times each candidate shape on the device and caches the fastest for the
- * process; the key is (device architecture, kernel, dof, spheres, self pairs,
+ * times every candidate shape once on the device, times the four fastest
+ * again over three launches each, and caches the fastest for the process; the key is (device architecture, kernel, dof, spheres, self pairs,
  * obstacles, floor(log2(work items))).  That first call synchronises with
  * `stream` (it reads timing events), so it must not run under stream
  * capture: disable tuning or import a cache first.  ezo_check_collisions and
@@ -354,9 +354,13 @@ ezo_status ezo_set_autotune(ezo_ctx *ctx, int32_t enable);
 
 /* The process-wide cache as text, one JSON object per line with keys arch,
  * kernel ("check_flags" | "check_sd" | "bisect" | "sample"), dof, spheres,
- * self_pairs, obstacles, log2_items, T, W, stage and us (measured time per
- * launch).  For "sample", T is the number of lanes per walk, W the waves per
- * workgroup, and spheres = self_pairs = obstacles = 0.
+ * self_pairs, obstacles, log2_items, T, W, stage, depth and us (measured
+ * time per launch).  For "bisect", T counts candidates per workgroup and
+ * depth (1..3, optional on import, default 1) the bisection levels checked
+ * per round, so a tile check holds T (2^depth - 1) configurations.  For
+ * "sample", T is
+ * the number of lanes per walk, W the waves per workgroup, and spheres =
+ * self_pairs = obstacles = 0.
  * buf (host, may be NULL) receives at most capacity - 1 bytes and a NUL;
  * *length (host, may be NULL) receives the full text length.  Returns
  * EZO_E_CAPACITY when the text was truncated. */

@@ -120,11 +120,22 @@ ezo_status prep_obstacles(ezo_ctx* c, const ezo_robot* r, const float* obs, int 
 
 bool pow2_tile(int T) { return T == 1 || T == 2 || T == 4 || T == 8 || T == 16 || T == 32 || T == 64; }
 
+// Configurations per tile check: T for a check; T candidates x (2^depth - 1)
+// bisection points for the bisection.
+int tile_configs(const TileCfg& g, bool bisect) { return bisect ? g.T * ((1 << g.depth) - 1) : g.T; }
+
+// Bisection shapes that have a kernel instance.
+bool bisect_shape_built(const TileCfg& g) {
+    return (g.depth == 1 && g.T >= 2 && g.T <= 64) || (g.depth == 2 && g.T <= 16) || (g.depth == 3 && g.T <= 8);
+}
+
 // A shape is usable when its LDS fits and staging is possible where asked.
-bool cfg_valid(const ezo_ctx* c, const TileCfg& g, int S, int n_obs, bool sd) {
-    if (!pow2_tile(g.T) || g.W < 1 || g.W > 16) return false;
-    if (g.stage && (sd || !stage_fits(c, g.T, S, g.W, n_obs))) return false;
-    return tile_smem_bytes(g.T, S, g.W) + (g.stage ? 16 * (size_t)n_obs : 0) <= c->lds_cap;
+bool cfg_valid(const ezo_ctx* c, const TileCfg& g, int S, int n_obs, bool sd, bool bisect = false) {
+    if (!pow2_tile(g.T) || g.W < 1 || g.W > 16 || g.depth < 1 || g.depth > 3) return false;
+    if (bisect ? !bisect_shape_built(g) : g.depth != 1) return false;
+    const int T = tile_configs(g, bisect);
+    if (g.stage && (sd || !stage_fits(c, T, S, g.W, n_obs))) return false;
+    return tile_smem_bytes(T, S, g.W) + (g.stage ? 16 * (size_t)n_obs : 0) <= c->lds_cap;
 }
 
 TuneKey tune_key(const ezo_ctx* c, const ezo_robot* r, TuneKind kind, int n_obs, int64_t items) {
@@ -148,32 +159,38 @@ TileCfg heuristic_check(const ezo_ctx* c, const ezo_robot* r, int n_obs, int64_t
     return g;
 }
 
+// items = candidate slots; one bisection level per round.
 TileCfg heuristic_bisect(const ezo_ctx* c, const ezo_robot* r, int n_obs, int64_t items) {
     TileCfg g;
     g.W = 4;
-    g.T = std::min(pick_T(c, items, r->S, g.W), 64);
+    g.depth = 1;
+    g.T = std::max(std::min(pick_T(c, items, r->S, g.W), 64), 2);
     g.stage = stage_fits(c, g.T, r->S, g.W, n_obs) ? 1 : 0;
     return g;
 }
 
-TileCfg resolve_cfg(const ezo_ctx* c, const TuneKey& k, const TileCfg& fallback, int S, int n_obs, bool sd) {
+TileCfg resolve_cfg(const ezo_ctx* c, const TuneKey& k, const TileCfg& fallback, int S, int n_obs, bool sd,
+                    bool bisect = false) {
     TileCfg g;
-    if (ezo_tune_lookup(k, &g) && cfg_valid(c, g, S, n_obs, sd)) return g;
+    if (ezo_tune_lookup(k, &g) && cfg_valid(c, g, S, n_obs, sd, bisect)) return g;
     return fallback;
 }
 
-// Candidate shapes: every fitting T in {4..64} x W x staging.
+// Candidate shapes: every fitting T x W x staging (x bisection depth 1..3);
+// T = configurations (check, 4..64) or candidates (bisection, 1..64) per
+// workgroup; items = configurations or candidate slots.
 std::vector<TileCfg> tile_candidates(const ezo_ctx* c, int S, int n_obs, bool sd, std::initializer_list<int> Ws,
-                                     int64_t items) {
+                                     int64_t items, bool bisect = false) {
     std::vector<TileCfg> v;
-    for (int T : {64, 32, 16, 8, 4}) {
-        if (T > 4 && items < 4LL * T) continue;          // a handful of items: small tiles only
-        for (int W : Ws)
-            for (int st = 0; st <= (sd ? 0 : 1); ++st) {
-                TileCfg g{T, W, st};
-                if (cfg_valid(c, g, S, n_obs, sd)) v.push_back(g);
-            }
-    }
+    for (int dp = 1; dp <= (bisect ? 3 : 1); ++dp)
+        for (int T : {64, 32, 16, 8, 4, 2, 1}) {
+            if ((!bisect && T < 4) || (T > 4 && items < 4LL * T)) continue;   // a handful of items: small tiles
+            for (int W : Ws)
+                for (int st = 0; st <= (sd ? 0 : 1); ++st) {
+                    TileCfg g{T, W, st, dp};
+                    if (cfg_valid(c, g, S, n_obs, sd, bisect)) v.push_back(g);
+                }
+        }
     return v;
 }
 
@@ -235,14 +252,35 @@ TileCfg heuristic_sample(int64_t walks) {
 
 bool sample_cfg_valid(const TileCfg& g) { return (g.T == 1 || g.T == 2 || g.T == 4 || g.T == 8) && g.W == 4; }
 
+// Walks of all running edges up to which the fused loop's sampler splits a
+// walk over 8 lanes (above: one lane per walk).  Measured on MI355X for the
+// 7-DOF sampler at 14-144 rows: 8 lanes win at 10 k and 160 k walks (up to
+// 4x at 10 k), one lane wins at 960 k (by 5-25 %).
+constexpr int64_t kSampleWideWalks = 400000;
+
+// `active` (device, may be NULL): number of running edges; when given, the
+// adaptive kernel chooses the lanes per walk on the device each launch.
 ezo_status launch_sample(ezo_ctx* c, int dof, const float* A, const float* b, const int* n_faces, int cap,
                          const float* edges, int E, int max_samples, int n_mix, uint64_t seed, int64_t eid0,
                          float* S, int64_t stride, const int* status, const IterArgs& it, hipStream_t st,
-                         const TileCfg* shape = nullptr) {
+                         const TileCfg* shape = nullptr, const int* active = nullptr) {
     const int D = dof <= 4 ? 4 : 8;
     if (sample_smem_bytes(D, 8, cap, 256) > c->lds_cap)
         return ezo_fail(c, EZO_E_UNSUPPORTED, "face capacity %d too large for the sampler", cap);
     if (max_samples <= 0 || E <= 0) return EZO_OK;
+    const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+    if (active) {
+        const size_t lds = sample_smem_bytes(D, 8, cap, 256);
+        dim3 grid((unsigned)(((int64_t)max_samples * 8 + 255) / 256), (unsigned)E), block(256);
+        if (D == 4)
+            EZO_KLAUNCH(c, k_sample_auto<4>, grid, block, lds, st, dof, A, b, n_faces, cap, edges, key0, key1, eid0,
+                        n_mix, S, stride, status, it, active, kSampleWideWalks);
+        else
+            EZO_KLAUNCH(c, k_sample_auto<8>, grid, block, lds, st, dof, A, b, n_faces, cap, edges, key0, key1, eid0,
+                        n_mix, S, stride, status, it, active, kSampleWideWalks);
+        HIP_TRY(c, hipGetLastError());
+        return EZO_OK;
+    }
     const int64_t walks = (int64_t)max_samples * E;
     TileCfg g;
     if (shape) {
@@ -292,25 +330,43 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
     } else {
         const int64_t items = (int64_t)cand_cap * E;
         g = resolve_cfg(c, tune_key(c, r, TUNE_BISECT, ov.n, items), heuristic_bisect(c, r, ov.n, items), r->S,
-                        ov.n, false);
+                        ov.n, false, true);
     }
-    const int T = g.T, W = g.W;
-    if (T == 0) return ezo_fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
+    const int TC = g.T, W = g.W, dp = g.depth;
+    if (!bisect_shape_built(g) || W < 1 || W > 16)
+        return ezo_fail(c, EZO_E_INVALID, "bisection shape T=%d W=%d depth=%d", TC, W, dp);
     ObsView ovs = ov;
     ovs.lds_n = g.stage ? ov.n : 0;
-    const size_t lds = tile_smem_bytes(T, r->S, W) + 16 * (size_t)ovs.lds_n;
-    dim3 grid((unsigned)((cand_cap + T - 1) / T), (unsigned)E), block(64 * W);
-#define EZO_LAUNCH_PB(TT)                                                                                    \
-    EZO_KLAUNCH(c, (k_project_bisect<TT>), grid, block, lds, st, r->view, ovs, gv, edges, S, stride, cand_idx, \
+    const size_t lds = tile_smem_bytes(tile_configs(g, true), r->S, W) + 16 * (size_t)ovs.lds_n;
+    if (lds > c->lds_cap) return ezo_fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
+    dim3 grid((unsigned)((cand_cap + TC - 1) / TC), (unsigned)E), block(64 * W);
+#define EZO_LAUNCH_PB(TT, DD)                                                                                    \
+    EZO_KLAUNCH(c, (k_project_bisect<TT, DD>), grid, block, lds, st, r->view, ovs, gv, edges, S, stride, cand_idx, \
                        n_cands, cand_cap, n_b, c_star, a_dir, t_star, pcol, pany, status)
-    switch (T) {
-        case 64: EZO_LAUNCH_PB(64); break;
-        case 32: EZO_LAUNCH_PB(32); break;
-        case 16: EZO_LAUNCH_PB(16); break;
-        case 8: EZO_LAUNCH_PB(8); break;
-        case 4: EZO_LAUNCH_PB(4); break;
-        case 2: EZO_LAUNCH_PB(2); break;
-        default: EZO_LAUNCH_PB(1); break;
+    if (dp == 1) {
+        switch (TC) {
+            case 64: EZO_LAUNCH_PB(64, 1); break;
+            case 32: EZO_LAUNCH_PB(32, 1); break;
+            case 16: EZO_LAUNCH_PB(16, 1); break;
+            case 8: EZO_LAUNCH_PB(8, 1); break;
+            case 4: EZO_LAUNCH_PB(4, 1); break;
+            default: EZO_LAUNCH_PB(2, 1); break;
+        }
+    } else if (dp == 2) {
+        switch (TC) {
+            case 16: EZO_LAUNCH_PB(16, 2); break;
+            case 8: EZO_LAUNCH_PB(8, 2); break;
+            case 4: EZO_LAUNCH_PB(4, 2); break;
+            case 2: EZO_LAUNCH_PB(2, 2); break;
+            default: EZO_LAUNCH_PB(1, 2); break;
+        }
+    } else {
+        switch (TC) {
+            case 8: EZO_LAUNCH_PB(8, 3); break;
+            case 4: EZO_LAUNCH_PB(4, 3); break;
+            case 2: EZO_LAUNCH_PB(2, 3); break;
+            default: EZO_LAUNCH_PB(1, 3); break;
+        }
     }
 #undef EZO_LAUNCH_PB
     HIP_TRY(c, hipGetLastError());
@@ -353,7 +409,7 @@ ezo_status tune_bisect_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov
     const TuneKey k = tune_key(c, r, TUNE_BISECT, ov.n, (int64_t)cand_cap * E);
     TileCfg g;
     if (!c->autotune || ezo_tune_lookup(k, &g)) return EZO_OK;
-    const auto cands = tile_candidates(c, r->S, ov.n, false, {1, 2, 4, 8}, (int64_t)cand_cap * E);
+    const auto cands = tile_candidates(c, r->S, ov.n, false, {1, 2, 4, 8}, (int64_t)cand_cap * E, true);
     if (cands.empty()) return EZO_OK;
     auto run = [&](const TileCfg& cfg) {
         return launch_project_bisect(c, r, ov, gv, edges, E, S, stride, cand_idx, n_cands, cand_cap, n_b, c_star,
@@ -363,45 +419,33 @@ ezo_status tune_bisect_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov
 }
 
 // Fused inflation: the loop's workspace (and the caller's A, b, n_faces) are
-// free until the edges are initialised, so the shapes of the loop's sampler,
-// check and bisection launches are timed there on a stand-in for a typical
-// iteration: the joint box written as 2 dof + 2 n_f rows (box rows repeated),
+// free until the edges are initialised, so the shapes of the loop's check
+// and bisection launches are timed there on a stand-in for a typical
+// iteration (the loop's sampler picks its lanes per walk on the device): the joint box written as 2 dof + 2 n_f rows (box rows repeated),
 // |S| hit-and-run samples per edge from it, and as candidates the first n_p
-// of them in collision.  At most kTuneEdges edges take part (already far more
-// workgroups than CUs).
-constexpr int kTuneEdges = 16;
+// of them in collision.
 constexpr int kItersPerGraph = 2;        // iterations captured per replayed graph
 
 ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const GridView& gv, const float* edges,
                           int E, const ezo_params* p, int S_cap, int64_t stride, float* A, float* b, int* n_faces,
                           float* w_s, uint8_t* w_f, int* w_ci, int* w_nc, float* w_cs, float* w_ad, float* w_ts,
-                          uint8_t* w_pc, hipStream_t st) {
+                          uint8_t* w_pc, const int* w_active, hipStream_t st) {
     if (!c->autotune) return EZO_OK;
     const int dof = r->dof, cap = p->face_capacity, cand_cap = p->n_p;
-    const TuneKey ks = sample_key(c, dof, (int64_t)S_cap * E);
     const TuneKey kc = tune_key(c, r, TUNE_CHECK_FLAGS, ov.n, (int64_t)S_cap * E);
     const TuneKey kb = tune_key(c, r, TUNE_BISECT, ov.n, (int64_t)cand_cap * E);
     TileCfg g;
-    const bool need_s = !ezo_tune_lookup(ks, &g), need_c = !ezo_tune_lookup(kc, &g), need_b = !ezo_tune_lookup(kb, &g);
-    if (!need_s && !need_c && !need_b) return EZO_OK;
-    E = std::min(E, kTuneEdges);
+    const bool need_c = !ezo_tune_lookup(kc, &g), need_b = !ezo_tune_lookup(kb, &g);
+    if (!need_c && !need_b) return EZO_OK;
     const int F = std::min(cap, 2 * dof + 2 * p->n_f);
     hipLaunchKernelGGL(k_tune_polytope, dim3((E + 63) / 64), dim3(64), 0, st, dof, r->q_lo, r->q_hi, E, cap, F, A, b,
                        n_faces);
     HIP_TRY(c, hipGetLastError());
     IterArgs its{nullptr, nullptr, 1, 0, 0, S_cap};
-    auto run_s = [&](const TileCfg& cfg) {
-        return launch_sample(c, dof, A, b, n_faces, cap, edges, E, S_cap, p->n_mix, p->seed, p->edge_id_base, w_s,
-                             stride, nullptr, its, st, &cfg);
-    };
     ezo_status s;
-    if (need_s) {
-        const std::vector<TileCfg> cands = {{1, 4, 0}, {2, 4, 0}, {4, 4, 0}, {8, 4, 0}};
-        if ((s = ezo_tune_search(c, ks, cands, st, run_s, &g))) return s;
-    } else if ((s = launch_sample(c, dof, A, b, n_faces, cap, edges, E, S_cap, p->n_mix, p->seed, p->edge_id_base,
-                                  w_s, stride, nullptr, its, st))) {
+    if ((s = launch_sample(c, dof, A, b, n_faces, cap, edges, E, S_cap, p->n_mix, p->seed, p->edge_id_base, w_s,
+                           stride, nullptr, its, st, nullptr, w_active)))
         return s;
-    }
     IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
     auto run_c = [&](const TileCfg& cfg) {
         return launch_check<false>(c, r, ov, gv, w_s, S_cap, 1, stride, (int64_t)dof * stride, w_f, nullptr, nullptr,
@@ -417,7 +461,7 @@ ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, con
     hipLaunchKernelGGL(k_test_select, dim3(E), dim3(1024), 0, st, w_f, stride, p->n_p, p->n_b, w_ci, cand_cap, w_nc,
                        nullptr, nullptr, nullptr, nullptr, sel);
     HIP_TRY(c, hipGetLastError());
-    const auto cands = tile_candidates(c, r->S, ov.n, false, {1, 2, 4, 8}, (int64_t)cand_cap * E);
+    const auto cands = tile_candidates(c, r->S, ov.n, false, {1, 2, 4, 8}, (int64_t)cand_cap * E, true);
     if (cands.empty()) return EZO_OK;
     auto run_b = [&](const TileCfg& cfg) {
         return launch_project_bisect(c, r, ov, gv, edges, E, w_s, stride, w_ci, w_nc, cand_cap, p->n_b, w_cs, w_ad,
@@ -855,13 +899,15 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
     HIP_TRY(c, hipEventRecord(c->ev_in, as_stream(stream)));
     HIP_TRY(c, hipStreamWaitEvent(st, c->ev_in, 0));
     HIP_TRY(c, hipMemcpyAsync(w_tb, table.data(), sizeof(int4) * table.size(), hipMemcpyHostToDevice, st));
-    const int one = 1;
+    const int one = 1, n_edges_init = E;
     HIP_TRY(c, hipMemcpyAsync(w_k, &one, sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipMemcpyAsync(w_ac, &n_edges_init, sizeof(int), hipMemcpyHostToDevice, st));
     ObsView ov;
     GridView gv;
     if ((s = prep_obstacles(c, r, obs, n_obs, st, &ov, &gv))) return s;
     if ((s = tune_inflation(c, r, ov, gv, edges, E, p, S_cap, stride, A, b, n_faces, (float*)w_s, (uint8_t*)w_f,
-                            (int*)w_ci, (int*)w_nc, (float*)w_cs, (float*)w_ad, (float*)w_ts, (uint8_t*)w_pc, st)))
+                            (int*)w_ci, (int*)w_nc, (float*)w_cs, (float*)w_ad, (float*)w_ts, (uint8_t*)w_pc,
+                            (const int*)w_ac, st)))
         return s;
     hipLaunchKernelGGL(k_init_edges, dim3((E + 63) / 64), dim3(64), 0, st, dof, r->q_lo, r->q_hi, edges, E, A, b,
                        n_faces, cap, edge_status, (EdgeStatsDev*)w_st, (uint8_t*)w_pa);
@@ -886,7 +932,7 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
         };
         mark(EZO_PHASE_SAMPLE);
         if ((ls = launch_sample(c, dof, A, b, n_faces, cap, edges, E, S_cap, p->n_mix, p->seed, p->edge_id_base,
-                                (float*)w_s, stride, edge_status, it, st))) {
+                                (float*)w_s, stride, edge_status, it, st, nullptr, (const int*)w_ac))) {
             mark(EZO_NUM_PHASES);
             return ls;
         }

@@ -172,20 +172,47 @@ __device__ inline TileSmem carve_tile(char* base, int T, int S, int W, int lds_n
     return t;
 }
 
+// Work items (c, k), c < n, k < K, item index k n + c, spread over the
+// workgroup's threads: one division per loop instead of one per item.
+struct ItemWalk {
+    int c, k, dc, dk;
+    __device__ ItemWalk(int n) {
+        const int nt = blockDim.x, tid = threadIdx.x;
+        if ((n & (n - 1)) == 0) {                  // a power of two: shifts
+            const int sh = __builtin_ctz(n);
+            k = tid >> sh;
+            dk = nt >> sh;
+        } else {
+            k = tid / n;
+            dk = nt / n;
+        }
+        c = tid - k * n;
+        dc = nt - dk * n;
+    }
+    __device__ void next(int n) {
+        c += dc;
+        k += dk;
+        if (c >= n) {
+            c -= n;
+            ++k;
+        }
+    }
+};
+
 // FK phase: t.q[c][j] (c < n_valid) -> t.cen[s][c].  Ends with a barrier.
+// Only the n_valid >= 1 configurations of the tile are computed.
 __device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const TileSmem& t, int T, int n_valid) {
-    const int tid = threadIdx.x, nt = blockDim.x;
     const int dof = rb.dof;
-    for (int i = tid; i < T * dof; i += nt) {
-        const int c = i % T, j = i / T;
-        float s = 0.f, co = 1.f;
-        if (c < n_valid) sincosf(t.q[c * kMaxDof + j], &s, &co);
+    for (ItemWalk w(n_valid); w.k < dof; w.next(n_valid)) {
+        const int c = w.c, j = w.k;
+        float s, co;
+        sincosf(t.q[c * kMaxDof + j], &s, &co);
         t.trig[j * T + c] = make_float2(co, s);
     }
     __syncthreads();
     const float4 sh = ob.centre[0];
-    for (int i = tid; i < T * dof; i += nt) {
-        const int c = i % T, link = i / T;
+    for (ItemWalk w(n_valid); w.k < dof; w.next(n_valid)) {
+        const int c = w.c, link = w.k;
         float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
         float p[3] = {-sh.x, -sh.y, -sh.z};
         for (int l = 0; l <= link; ++l) {
@@ -311,12 +338,11 @@ __device__ inline void tile_pairs_sd(const RobotView& rb, const ObsView& ob, con
 // Returns the number of sphere-sphere tests this thread performed (bound
 // tests included).
 __device__ inline unsigned tile_pairs_grid(const RobotView& rb, const ObsView& ob, const GridView& gv,
-                                           const TileSmem& t, int T) {
+                                           const TileSmem& t, int T, int n_valid) {
     volatile int* hit = t.hit;
-    const int nt = blockDim.x;
     unsigned int ntest = 0;
-    for (int it = threadIdx.x; it < T * rb.n_blocks; it += nt) {
-        const int c = it % T, bk = it / T;
+    for (ItemWalk w(n_valid); w.k < rb.n_blocks; w.next(n_valid)) {
+        const int c = w.c, bk = w.k;
         if (hit[c] || t.scr[c]) continue;
         const int4 blk = rb.blocks[bk];
         const float4 A = t.lb[blk.x * T + c], B = t.lb[blk.y * T + c];
@@ -345,8 +371,8 @@ __device__ inline unsigned tile_pairs_grid(const RobotView& rb, const ObsView& o
         const GridGeom g = *gv.geom;
         const int G = gv.G;
         const int S = rb.n_spheres;
-        for (int it = threadIdx.x; it < T * S; it += nt) {
-            const int c = it % T, s = it / T;
+        for (ItemWalk w(n_valid); w.k < S; w.next(n_valid)) {
+            const int c = w.c, s = w.k;
             if (hit[c]) continue;
             const float4 C = t.cen[s * T + c];
             const float fx = (C.x - g.ox) * g.ihx, fy = (C.y - g.oy) * g.ihy, fz = (C.z - g.oz) * g.ihz;
@@ -414,7 +440,7 @@ __device__ inline unsigned tile_check(const RobotView& rb, const ObsView& ob, co
         tile_pairs_sd(rb, ob, t, T, n_valid);
         return 0;
     }
-    return tile_pairs_grid(rb, ob, gv, t, T);
+    return tile_pairs_grid(rb, ob, gv, t, T, n_valid);
 }
 
 }  // namespace ezo

@@ -97,9 +97,11 @@ struct ezo_surrogate {
 // Launch shapes of the tile kernels and their tuning cache
 // ---------------------------------------------------------------------------
 // T configurations per workgroup, W waves per workgroup, obstacle records
-// staged in LDS (stage = 1) or read from global memory.  T = 0: not chosen.
+// staged in LDS (stage = 1) or read from global memory; for the bisection,
+// depth = bisection levels per round (T >> depth candidates per workgroup).
+// T = 0: not chosen.
 struct TileCfg {
-    int T = 0, W = 0, stage = 0;
+    int T = 0, W = 0, stage = 0, depth = 1;
 };
 
 // For the sampler, T = lanes per walk and W = waves per workgroup.
@@ -117,9 +119,10 @@ struct TuneKey {
 
 int ezo_tune_bucket(int64_t items);
 bool ezo_tune_lookup(const TuneKey& k, TileCfg* out);
-// Times every candidate (one warm-up and kTuneReps timed launches of `run`
-// on stream st, host-synchronising) and caches the fastest under k.
-// Candidates whose launch fails are skipped.  Needs at least one candidate.
+// Times every candidate once, then the fastest few over several launches
+// (launches of `run` on stream st, host-synchronising), and caches the
+// fastest under k.  Candidates whose launch fails are skipped.  Needs at
+// least one candidate.
 ezo_status ezo_tune_search(ezo_ctx* c, const TuneKey& k, const std::vector<TileCfg>& cands, hipStream_t st,
                            const std::function<ezo_status(const TileCfg&)>& run, TileCfg* best);
 

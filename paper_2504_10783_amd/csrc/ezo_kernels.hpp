@@ -336,17 +336,15 @@ __device__ __forceinline__ void walk_step(const float* rowA, const float* rowb, 
     for (int j = 0; j < D; ++j) x[j] = fmaf(tm, u[j], x[j]);
 }
 
+// The sampler's work for one workgroup with L lanes per walk; walk i =
+// (blockIdx.x blockDim.x + threadIdx.x) / L of edge blockIdx.y.
 template <int D, int L>
-__global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict__ A, const float* __restrict__ bvec,
-                                                const int* __restrict__ n_faces, int cap,
-                                                const float* __restrict__ edges, uint32_t key0, uint32_t key1,
-                                                int64_t edge_id_base, int n_mix, float* __restrict__ S,
-                                                int64_t stride, const int* __restrict__ status, IterArgs it) {
+__device__ inline void sample_block(char* smem, int dof, const float* __restrict__ A, const float* __restrict__ bvec,
+                                    const int* __restrict__ n_faces, int cap, const float* __restrict__ edges,
+                                    uint32_t key0, uint32_t key1, int64_t edge_id_base, int n_mix,
+                                    float* __restrict__ S, int64_t stride, const IterVals& iv) {
     static_assert(L == 1 || L == 2 || L == 4 || L == 8, "lanes per walk");
-    extern __shared__ __align__(16) char smem[];
     const int e = blockIdx.y;
-    if (!edge_running(status, e)) return;
-    const IterVals iv = resolve(it);
     const int F = min(max(n_faces[e], 0), cap);
     float* rowA = reinterpret_cast<float*>(smem);        // [F][D]
     float* rowb = rowA + (size_t)F * D;                   // [F]
@@ -403,6 +401,43 @@ __global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict
 #pragma unroll
         for (int j = 0; j < D; ++j)
             if (j < dof && (j % L) == sub) S[((size_t)e * dof + j) * stride + i] = x[j];
+    }
+}
+
+template <int D, int L>
+__global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict__ A, const float* __restrict__ bvec,
+                                                const int* __restrict__ n_faces, int cap,
+                                                const float* __restrict__ edges, uint32_t key0, uint32_t key1,
+                                                int64_t edge_id_base, int n_mix, float* __restrict__ S,
+                                                int64_t stride, const int* __restrict__ status, IterArgs it) {
+    extern __shared__ __align__(16) char smem[];
+    if (!edge_running(status, blockIdx.y)) return;
+    const IterVals iv = resolve(it);
+    sample_block<D, L>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv);
+}
+
+// The fused loop's sampler: launched with the grid of 8 lanes per walk, it
+// runs 8 lanes per walk while the walks of all running edges (*active x
+// |S|) are at most wide_walks, else one lane per walk (the first 1/8 of the
+// workgroups; the rest exit).  Few walks are latency-bound and gain from
+// splitting the rows; many walks fill the chip either way and one lane per
+// walk does the least work.  Samples are identical in both modes.
+template <int D>
+__global__ void __launch_bounds__(256) k_sample_auto(int dof, const float* __restrict__ A,
+                                                     const float* __restrict__ bvec, const int* __restrict__ n_faces,
+                                                     int cap, const float* __restrict__ edges, uint32_t key0,
+                                                     uint32_t key1, int64_t edge_id_base, int n_mix,
+                                                     float* __restrict__ S, int64_t stride,
+                                                     const int* __restrict__ status, IterArgs it,
+                                                     const int* __restrict__ active, int64_t wide_walks) {
+    extern __shared__ __align__(16) char smem[];
+    if (!edge_running(status, blockIdx.y)) return;
+    const IterVals iv = resolve(it);
+    if ((int64_t)max(*active, 1) * iv.nS <= wide_walks) {
+        sample_block<D, 8>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv);
+    } else {
+        if ((int64_t)blockIdx.x * blockDim.x >= iv.nS) return;     // whole workgroup past the walks
+        sample_block<D, 1>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv);
     }
 }
 
@@ -479,10 +514,20 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
 
 // ---------------------------------------------------------------------------
 // Projection + fail-fast check + N_b bisection steps.  blockIdx.y = edge,
-// blockIdx.x = tile of T candidates.  Candidate state lives with the threads
-// c < T of wave 0; every check is a whole-workgroup tile check.
+// blockIdx.x = a group of TC candidates; every check is a whole-workgroup
+// tile check of up to TC (2^DEPTH - 1) configurations.
+//
+// The first check is the projections c_proj (fail-fast).  The bisection then
+// runs DEPTH levels per round: a round checks, for every candidate, the
+// 2^lev - 1 points of the next lev <= DEPTH levels of its bisection tree
+// (heap order: node 1 = midpoint of [lo, hi]; the children of node i are the
+// midpoints of its two halves), then walks the tree with the flags.  These
+// are exactly the points, computed by the same FP32 operations, and the
+// decisions of one-midpoint-at-a-time bisection, in ceil(N_b / DEPTH)
+// dependent rounds instead of N_b.  Candidate state lives with the threads
+// c < TC; configuration c (2^lev - 1) + i - 1 holds node i of candidate c.
 // ---------------------------------------------------------------------------
-template <int T>
+template <int TC, int DEPTH>
 __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView ob, GridView gv, const float* __restrict__ edges,
                                                          const float* __restrict__ S, int64_t stride,
                                                          const int* __restrict__ cand_idx,
@@ -492,20 +537,23 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView o
                                                          uint8_t* __restrict__ proj_collides,
                                                          uint8_t* __restrict__ proj_any,
                                                          const int* __restrict__ status) {
+    static_assert(DEPTH >= 1 && DEPTH <= 3 && TC >= 1, "bisection depth per round");
+    constexpr int NODES = (1 << DEPTH) - 1;
+    constexpr int T = TC * NODES;                   // configurations per tile check
     extern __shared__ __align__(16) char smem[];
     const int e = blockIdx.y;
     if (!edge_running(status, e)) return;
     const int nc = min(max(n_cands[e], 0), cand_cap);
-    const int base = blockIdx.x * T;
+    const int base = blockIdx.x * TC;
     if (base >= nc) return;
-    const int nv = (nc - base) < T ? (nc - base) : T;
+    const int nv = (nc - base) < TC ? (nc - base) : TC;
     const int dof = rb.dof;
     const int W = blockDim.x >> 6;
     TileSmem t = carve_tile(smem, T, rb.n_spheres, W, ob.lds_n);
     stage_obstacles(ob, t);
     const int tid = threadIdx.x;
     const bool own = tid < nv;
-    if (tid < T) t.scr[tid] = 0;          // bisection midpoints are always checked exactly
+    if (tid < T) t.scr[tid] = 0;          // bisection points are always checked exactly
     float lo[kMaxDof], hi[kMaxDof], cp[kMaxDof];
     const float* v = edges + (size_t)e * 2 * dof;
     if (own) {
@@ -542,23 +590,50 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView o
         proj_collides[(size_t)e * cand_cap + base + tid] = (uint8_t)h;
         if (h && proj_any) proj_any[e] = 1;
     }
-    for (int step = 0; step < n_b; ++step) {
-        __syncthreads();
-        if (own)
-            for (int j = 0; j < dof; ++j) t.q[tid * kMaxDof + j] = 0.5f * (lo[j] + hi[j]);
-        __syncthreads();
-        ntest += tile_check<false>(rb, ob, gv, t, T, nv);
+    for (int done = 0; done < n_b;) {
+        const int lev = min(DEPTH, n_b - done);
+        const int npt = (1 << lev) - 1;
+        __syncthreads();                  // the previous check's reads of t.q are done
         if (own) {
-            const bool h = t.hit[tid] != 0;
+            float* q0 = t.q + (size_t)tid * npt * kMaxDof;
 #pragma unroll
             for (int j = 0; j < kMaxDof; ++j) {
-                const float m = 0.5f * (lo[j] + hi[j]);
-                if (j < dof) {
-                    if (h) hi[j] = m;
-                    else lo[j] = m;
+                if (j >= dof) break;
+                // node i's interval [L_i, H_i]; L_2i = L_i, H_2i = p_i, L_2i+1 = p_i, H_2i+1 = H_i
+                float Lv[NODES + 1], Hv[NODES + 1], pv[NODES + 1];
+                Lv[1] = lo[j];
+                Hv[1] = hi[j];
+#pragma unroll
+                for (int i = 1; i <= NODES; ++i) {
+                    if (i > 1) {
+                        Lv[i] = (i & 1) ? pv[i >> 1] : Lv[i >> 1];
+                        Hv[i] = (i & 1) ? Hv[i >> 1] : pv[i >> 1];
+                    }
+                    pv[i] = 0.5f * (Lv[i] + Hv[i]);
+                    if (i <= npt) q0[(i - 1) * kMaxDof + j] = pv[i];
                 }
             }
         }
+        __syncthreads();
+        ntest += tile_check<false>(rb, ob, gv, t, T, nv * npt);
+        if (own) {
+            const int* h = t.hit + tid * npt;
+            const float* q0 = t.q + (size_t)tid * npt * kMaxDof;
+            int node = 1;
+            for (int d = 0; d < lev; ++d) {
+                const bool hc = h[node - 1] != 0;
+#pragma unroll
+                for (int j = 0; j < kMaxDof; ++j) {
+                    if (j < dof) {
+                        const float m = q0[(node - 1) * kMaxDof + j];
+                        if (hc) hi[j] = m;
+                        else lo[j] = m;
+                    }
+                }
+                node = 2 * node + (hc ? 0 : 1);
+            }
+        }
+        done += lev;
     }
     if (own) {
         float ts = 0.f;
@@ -608,14 +683,14 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
     int nf = min(max(n_faces[e], 0), cap);
     int placed = 0;
     if (tid == 0) s_stop = 0;
-    __syncthreads();
+    // smallest (t*, index) key among this thread's alive candidates; after a
+    // plane is placed the discard pass and the next round's scan are one pass
+    unsigned long long best = ~0ull;
+    for (int j = tid; j < n; j += blockDim.x) {
+        const unsigned long long key = ((unsigned long long)__float_as_uint(ts[j]) << 32) | (unsigned)j;
+        best = key < best ? key : best;
+    }
     for (int round = 0; round < n_f; ++round) {
-        unsigned long long best = ~0ull;
-        for (int j = tid; j < n; j += blockDim.x)
-            if (alive[j]) {
-                const unsigned long long key = ((unsigned long long)__float_as_uint(ts[j]) << 32) | (unsigned)j;
-                best = key < best ? key : best;
-            }
         for (int off = 32; off > 0; off >>= 1) {
             const unsigned long long o = __shfl_xor(best, off);
             best = o < best ? o : best;
@@ -655,13 +730,18 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
         ++nf;
         ++placed;
         const float rhs = row[kMaxDof];
+        best = ~0ull;
         for (int j = tid; j < n; j += blockDim.x)
             if (alive[j]) {
                 float ac = 0.f;
                 for (int k = 0; k < dof; ++k) ac = fmaf(row[k], cs[(size_t)k * cand_cap + j], ac);
-                if (ac > rhs) alive[j] = 0;
+                if (ac > rhs) {
+                    alive[j] = 0;
+                } else {
+                    const unsigned long long key = ((unsigned long long)__float_as_uint(ts[j]) << 32) | (unsigned)j;
+                    best = key < best ? key : best;
+                }
             }
-        __syncthreads();
     }
     if (tid == 0) {
         n_faces[e] = nf;

@@ -10,6 +10,7 @@
 // shape on the call's own (or representative) input and keeps the fastest in
 // a process-wide cache; later calls with that key use it without timing.
 // The cache can be exported as text and imported in another process.
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -19,6 +20,7 @@
 namespace {
 
 constexpr int kTuneReps = 3;
+constexpr int kTuneFinalists = 4;
 
 const char* kKindNames[TUNE_NKINDS] = {"check_flags", "check_sd", "bisect", "sample"};
 
@@ -30,12 +32,25 @@ struct Entry {
 std::mutex g_mu;
 std::map<TuneKey, Entry> g_cache;
 
+// Position just after `"key"` and the ':' that follows it (blanks allowed
+// around the colon), or npos.
+size_t value_pos(const std::string& line, const char* key) {
+    const std::string pat = std::string("\"") + key + "\"";
+    size_t p = line.find(pat);
+    if (p == std::string::npos) return p;
+    p += pat.size();
+    while (p < line.size() && (line[p] == ' ' || line[p] == '\t')) ++p;
+    if (p >= line.size() || line[p] != ':') return std::string::npos;
+    ++p;
+    while (p < line.size() && (line[p] == ' ' || line[p] == '\t')) ++p;
+    return p;
+}
+
 bool find_num(const std::string& line, const char* key, double* out) {
-    const std::string pat = std::string("\"") + key + "\":";
-    const size_t p = line.find(pat);
+    const size_t p = value_pos(line, key);
     if (p == std::string::npos) return false;
     char* end = nullptr;
-    const char* s = line.c_str() + p + pat.size();
+    const char* s = line.c_str() + p;
     const double v = std::strtod(s, &end);
     if (end == s) return false;
     *out = v;
@@ -43,12 +58,11 @@ bool find_num(const std::string& line, const char* key, double* out) {
 }
 
 bool find_str(const std::string& line, const char* key, std::string* out) {
-    const std::string pat = std::string("\"") + key + "\":\"";
-    const size_t p = line.find(pat);
-    if (p == std::string::npos) return false;
-    const size_t q = line.find('"', p + pat.size());
+    const size_t p = value_pos(line, key);
+    if (p == std::string::npos || line[p] != '"') return false;
+    const size_t q = line.find('"', p + 1);
     if (q == std::string::npos) return false;
-    *out = line.substr(p + pat.size(), q - p - pat.size());
+    *out = line.substr(p + 1, q - p - 1);
     return true;
 }
 
@@ -80,39 +94,57 @@ bool ezo_tune_lookup(const TuneKey& k, TileCfg* out) {
     return true;
 }
 
+// Mean time of `reps` launches of one shape (ms), +inf if a launch fails.
+static ezo_status time_shape(ezo_ctx* c, hipStream_t st, const std::function<ezo_status(const TileCfg&)>& run,
+                             const TileCfg& cfg, int reps, double* ms_out) {
+    *ms_out = INFINITY;
+    HIP_TRY(c, hipEventRecord(c->tune_ev[0], st));
+    ezo_status s = EZO_OK;
+    for (int r = 0; r < reps && s == EZO_OK; ++r) s = run(cfg);
+    HIP_TRY(c, hipEventRecord(c->tune_ev[1], st));
+    HIP_TRY(c, hipEventSynchronize(c->tune_ev[1]));
+    if (s != EZO_OK) {                   // e.g. a shape the device cannot launch
+        (void)hipGetLastError();
+        return EZO_OK;
+    }
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->tune_ev[0], c->tune_ev[1]));
+    *ms_out = ms / reps;
+    return EZO_OK;
+}
+
 ezo_status ezo_tune_search(ezo_ctx* c, const TuneKey& k, const std::vector<TileCfg>& cands, hipStream_t st,
                            const std::function<ezo_status(const TileCfg&)>& run, TileCfg* best) {
     if (cands.empty()) return ezo_fail(c, EZO_E_INVALID, "no launch shape to tune");
     for (auto& ev : c->tune_ev)
         if (!ev) HIP_TRY(c, hipEventCreate(&ev));
+    // screening: one launch of every shape (after one warm-up launch of the
+    // first), then the kTuneFinalists fastest again with kTuneReps launches
+    ezo_status s;
+    if (run(cands[0]) != EZO_OK) (void)hipGetLastError();
+    std::vector<std::pair<double, int>> order;
+    for (int i = 0; i < (int)cands.size(); ++i) {
+        double ms;
+        if ((s = time_shape(c, st, run, cands[i], 1, &ms))) return s;
+        if (std::isfinite(ms)) order.push_back({ms, i});
+    }
+    if (order.empty()) return ezo_fail(c, EZO_E_HIP, "no launch shape ran during tuning");
+    std::sort(order.begin(), order.end());
     double best_ms = INFINITY;
-    TileCfg pick = cands[0];
-    for (const TileCfg& cfg : cands) {
-        if (run(cfg) != EZO_OK) {        // e.g. a shape the device cannot launch
-            (void)hipGetLastError();
-            continue;
-        }
-        HIP_TRY(c, hipEventRecord(c->tune_ev[0], st));
-        ezo_status s = EZO_OK;
-        for (int r = 0; r < kTuneReps && s == EZO_OK; ++r) s = run(cfg);
-        HIP_TRY(c, hipEventRecord(c->tune_ev[1], st));
-        HIP_TRY(c, hipEventSynchronize(c->tune_ev[1]));
-        if (s != EZO_OK) {
-            (void)hipGetLastError();
-            continue;
-        }
-        float ms = 0.f;
-        HIP_TRY(c, hipEventElapsedTime(&ms, c->tune_ev[0], c->tune_ev[1]));
+    TileCfg pick = cands[order[0].second];
+    for (int f = 0; f < std::min<int>(kTuneFinalists, (int)order.size()); ++f) {
+        double ms;
+        if ((s = time_shape(c, st, run, cands[order[f].second], kTuneReps, &ms))) return s;
         if (ms < best_ms) {
             best_ms = ms;
-            pick = cfg;
+            pick = cands[order[f].second];
         }
     }
     if (!std::isfinite(best_ms)) return ezo_fail(c, EZO_E_HIP, "no launch shape ran during tuning");
     c->err.clear();
     {
         std::lock_guard<std::mutex> lock(g_mu);
-        g_cache[k] = Entry{pick, 1e3 * best_ms / kTuneReps};
+        g_cache[k] = Entry{pick, 1e3 * best_ms};
     }
     *best = pick;
     return EZO_OK;
@@ -136,9 +168,10 @@ ezo_status ezo_tune_cache_export(char* buf, int64_t capacity, int64_t* length) {
             char line[512];
             std::snprintf(line, sizeof(line),
                           "{\"arch\":\"%s\",\"kernel\":\"%s\",\"dof\":%d,\"spheres\":%d,\"self_pairs\":%d,"
-                          "\"obstacles\":%d,\"log2_items\":%d,\"T\":%d,\"W\":%d,\"stage\":%d,\"us\":%.3f}\n",
+                          "\"obstacles\":%d,\"log2_items\":%d,\"T\":%d,\"W\":%d,\"stage\":%d,\"depth\":%d,"
+                          "\"us\":%.3f}\n",
                           k.arch.c_str(), kKindNames[k.kind], k.dof, k.S, k.P, k.n_obs, k.bucket, e.cfg.T, e.cfg.W,
-                          e.cfg.stage, e.us);
+                          e.cfg.stage, e.cfg.depth, e.us);
             os << line;
         }
     }
@@ -171,8 +204,10 @@ ezo_status ezo_tune_cache_import(const char* text, int32_t* n_imported) {
         for (int i = 0; i < TUNE_NKINDS && ok; ++i)
             if (kern == kKindNames[i]) kind = i;
         const int T = ok ? (int)v[5] : 0, W = ok ? (int)v[6] : 0;
+        double depth = 1.0;                          // optional key (bisection only)
+        if (ok) find_num(line, "depth", &depth);
         const bool shape_ok = (T == 1 || T == 2 || T == 4 || T == 8 || T == 16 || T == 32 || T == 64) && W >= 1 &&
-                              W <= 16 && (v[7] == 0 || v[7] == 1);
+                              W <= 16 && (v[7] == 0 || v[7] == 1) && (depth == 1 || depth == 2 || depth == 3);
         if (!ok || kind < 0 || !shape_ok) return EZO_E_INVALID;
         k.kind = kind;
         k.dof = (int)v[0];
@@ -184,6 +219,7 @@ ezo_status ezo_tune_cache_import(const char* text, int32_t* n_imported) {
         e.cfg.T = T;
         e.cfg.W = W;
         e.cfg.stage = (int)v[7];
+        e.cfg.depth = (int)depth;
         e.us = v[8];
         add[k] = e;
         ++n;

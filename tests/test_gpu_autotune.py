@@ -38,11 +38,11 @@ def arch():
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 
 
-def entry(kernel, desc, n_obs, items, T, W, stage):
+def entry(kernel, desc, n_obs, items, T, W, stage, depth=1):
     return json.dumps({"arch": arch(), "kernel": kernel, "dof": int(desc["dof"]),
                        "spheres": int(len(desc["sphere_r"])), "self_pairs": int(len(desc["self_pairs"])),
                        "obstacles": int(n_obs), "log2_items": int(items).bit_length() - 1,
-                       "T": T, "W": W, "stage": stage, "us": 0.0}, separators=(",", ":"))
+                       "T": T, "W": W, "stage": stage, "depth": depth, "us": 0.0}, separators=(",", ":"))
 
 
 def run_check(ezo, ctx, rob, obs, q, sd):
@@ -83,6 +83,9 @@ def test_check_shapes_give_identical_results(ezo, ctx):
 
 
 def test_bisect_shapes_give_identical_results(ezo, ctx):
+    """Candidates per workgroup, waves, staging and bisection levels per
+    round (the same midpoints and decisions in fewer dependent rounds) must
+    not change any output."""
     data, desc = load("dof7")
     rob = ezo.Robot(ctx, desc)
     dof = 7
@@ -112,12 +115,13 @@ def test_bisect_shapes_give_identical_results(ezo, ctx):
     try:
         ezo.tune_cache_clear()
         ref = run()
-        for T, W, st in SHAPES:
-            ezo.tune_cache_clear()
-            ezo.tune_cache_import(entry("bisect", desc, len(obs), cap, T, W, st))
-            got = run()
-            for a, b in zip(got, ref):
-                assert torch.equal(a, b), (T, W, st)
+        for dp, Ts in ((1, (2, 4, 8, 16, 32)), (2, (1, 2, 4, 8, 16)), (3, (1, 2, 4, 8))):
+            for T, W, st in ((T, W, st) for T in Ts for W in (1, 2, 4, 8) for st in (0, 1)):
+                ezo.tune_cache_clear()
+                ezo.tune_cache_import(entry("bisect", desc, len(obs), cap, T, W, st, dp))
+                got = run()
+                for a, b in zip(got, ref):
+                    assert torch.equal(a, b), (T, W, st, dp)
     finally:
         ezo.tune_cache_clear()
         ctx.set_autotune(True)
@@ -208,7 +212,7 @@ def test_autotuned_inflation_equals_heuristic(ezo, ctx, name, max_iters):
     for e, F in enumerate(r0.n_faces.tolist()):           # rows past n_faces are not written
         assert torch.equal(r0.A[e, :F], r1.A[e, :F]) and torch.equal(r0.b[e, :F], r1.b[e, :F])
     assert r0.stats == r1.stats
-    kinds = {e["kernel"] for e in ezo.tune_cache_entries() if e["obstacles"] in (len(obs), 0)}
-    assert {"check_flags", "bisect", "sample"} <= kinds
+    kinds = {e["kernel"] for e in ezo.tune_cache_entries() if e["obstacles"] == len(obs)}
+    assert {"check_flags", "bisect"} <= kinds
     st = r1.status.cpu().numpy()
     assert np.all(st == ezo.CERTIFIED) or max_iters < 50

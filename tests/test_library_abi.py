@@ -77,6 +77,9 @@ def test_tuning_cache_roundtrip_on_host(ezo):
     by_kernel = {e["kernel"]: e for e in ents}
     assert by_kernel["bisect"]["T"] == 16 and by_kernel["bisect"]["stage"] == 1
     assert by_kernel["check_sd"]["T"] == 64 and by_kernel["bisect"]["obstacles"] == 512
+    assert by_kernel["bisect"]["depth"] == 1                # optional on import, default 1
+    assert ezo.tune_cache_import(TUNE_LINE.replace('"us"', '"depth":2,"us"')) == 1
+    assert {e["kernel"]: e for e in ezo.tune_cache_entries()}["bisect"]["depth"] == 2
     # re-import of an exported text is the identity
     text = ezo.tune_cache_export()
     ezo.tune_cache_clear()
@@ -90,6 +93,8 @@ def test_tuning_cache_roundtrip_on_host(ezo):
     TUNE_LINE.replace('"W":4', '"W":17'),               # more than 16 waves
     TUNE_LINE.replace('"bisect"', '"gemm"'),            # unknown kernel
     TUNE_LINE.replace('"stage":1,', ''),                # missing key
+    TUNE_LINE.replace('"us"', '"depth":0,"us"'),        # depth below 1
+    TUNE_LINE.replace('"us"', '"depth":4,"us"'),        # depth beyond 3
 ])
 def test_tuning_cache_rejects_malformed_lines(ezo, bad):
     ezo.tune_cache_clear()
