@@ -589,15 +589,11 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     }
     std::stable_sort(keyed.begin(), keyed.end(),
                      [](const auto& x, const auto& y) { return x.first < y.first; });
-    // A block holds at most kPairChunk consecutive pairs of one link pair, so
-    // that one thread's pair loads issue together; w = count | 256 on the
-    // first block of each link pair (the one that counts its bound test).
     std::vector<int4> blocks;
     for (int p = 0; p < P; ++p) {
         pairs[p] = keyed[p].second;
-        const bool lead = p == 0 || keyed[p].first != keyed[p - 1].first;
-        if (lead || (blocks.back().w & 255) == ezo::kPairChunk)
-            blocks.push_back(make_int4(keyed[p].first.first, keyed[p].first.second, p, lead ? 256 : 0));
+        if (p == 0 || keyed[p].first != keyed[p - 1].first)
+            blocks.push_back(make_int4(keyed[p].first.first, keyed[p].first.second, p, 0));
         blocks.back().w++;
     }
     if (blocks.empty()) blocks.push_back(make_int4(0, 0, 0, 0));

@@ -39,10 +39,10 @@ struct RobotView {
     const float4* sph;         // [S] local (x, y, z), r -- sorted by link
     const int2* pairs;         // [P] self pairs, indices into the sorted order, grouped by block
     const float4* lbound;      // [dof] bounding sphere of each link's spheres: local centre, radius
-    const int4* blocks;        // [n_blocks] (link i, link j, first pair, pair count | 256 if first of the link pair)
+    const int4* blocks;        // [n_blocks] per link pair: (link i, link j, first pair, pair count)
 };
 
-constexpr int kPairChunk = 8;  // self pairs per block
+constexpr int kMaxLinkPairs = kMaxDof * (kMaxDof + 1) / 2;   // link pairs, same-link pairs included
 
 // Uniform grid over the obstacle cloud (shifted frame).  Cell k lists every
 // obstacle that a robot sphere centred anywhere in cell k could touch:
@@ -143,6 +143,8 @@ struct TileSmem {
     int* hit;          // [T] collision flag (flags mode) / validity
     int* scr;          // [T] 1 = the learned screen cleared this configuration's self pairs
     float* red;        // [2][W][T] partial minima (signed-distance mode)
+    int* wl;           // [T][kMaxLinkPairs] work list: (configuration, link pair) whose bounds overlap
+    int* wl_n;         // [1] work list length
     float4* obs;       // [lds_n] staged obstacle records (x, y, z, r), or NULL
 };
 
@@ -154,6 +156,7 @@ __host__ __device__ inline size_t tile_smem_bytes(int T, int S, int W) {
     b += sizeof(float4) * (size_t)kMaxDof * T;
     b += sizeof(int) * 2 * (size_t)T;
     b += sizeof(float) * 2 * (size_t)W * T;
+    b += sizeof(int) * ((size_t)T * kMaxLinkPairs + 1);
     return (b + 15) & ~(size_t)15;
 }
 
@@ -168,7 +171,9 @@ __device__ inline TileSmem carve_tile(char* base, int T, int S, int W, int lds_n
     t.q = reinterpret_cast<float*>(p);      p += sizeof(float) * (size_t)T * kMaxDof;
     t.red = reinterpret_cast<float*>(p);    p += sizeof(float) * 2 * (size_t)W * T;
     t.hit = reinterpret_cast<int*>(p);      p += sizeof(int) * (size_t)T;
-    t.scr = reinterpret_cast<int*>(p);
+    t.scr = reinterpret_cast<int*>(p);      p += sizeof(int) * (size_t)T;
+    t.wl = reinterpret_cast<int*>(p);       p += sizeof(int) * (size_t)T * kMaxLinkPairs;
+    t.wl_n = reinterpret_cast<int*>(p);
     return t;
 }
 
@@ -328,44 +333,52 @@ __device__ inline void tile_pairs_sd(const RobotView& rb, const ObsView& ob, con
     __syncthreads();
 }
 
-// Flags-mode sweep with broad phase.  Work items are (configuration,
-// self-pair block) and (configuration, sphere), spread over the whole
-// workgroup.  A self-pair block (all listed pairs between two links) is
-// skipped when the two links' bounding spheres are apart; a sphere tests only
-// the obstacles listed in its grid cell.  Every skipped pair is provably
-// separated, so the flag equals that of the all-pairs test.  The pair test is
-// |c - o|^2 < (r_c + r_o)^2 (difference form).  Barrier at exit.
+// Flags-mode sweep with broad phase.  Self pairs: the bounding spheres of
+// the two links of every (configuration, link pair) are tested first; the
+// overlapping ones go to an LDS work list, and each wave then takes a work
+// item and tests its link pair's sphere pairs one per lane (coalesced pair
+// loads, no divergence).  Obstacles: a work item (configuration, sphere)
+// tests only the obstacles listed in the sphere's grid cell.  Every skipped
+// pair is provably separated, so the flag equals that of the all-pairs
+// test.  The pair test is |c - o|^2 < (r_c + r_o)^2 (difference form).
+// Needs *t.wl_n == 0 on entry.  Barrier at exit.
 // Returns the number of sphere-sphere tests this thread performed (bound
 // tests included).
 __device__ inline unsigned tile_pairs_grid(const RobotView& rb, const ObsView& ob, const GridView& gv,
                                            const TileSmem& t, int T, int n_valid) {
     volatile int* hit = t.hit;
     unsigned int ntest = 0;
-    for (ItemWalk w(n_valid); w.k < rb.n_blocks; w.next(n_valid)) {
-        const int c = w.c, bk = w.k;
-        if (hit[c] || t.scr[c]) continue;
-        const int4 blk = rb.blocks[bk];
-        const float4 A = t.lb[blk.x * T + c], B = t.lb[blk.y * T + c];
-        const float dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;
-        const float R = A.w + B.w;
-        ntest += blk.w >> 8;               // the link pair's bound test, counted once
-        if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) >= R * R) continue;
-        const int np = blk.w & 255;
-        int2 pr[kPairChunk];
-#pragma unroll
-        for (int k = 0; k < kPairChunk; ++k) pr[k] = rb.pairs[blk.z + (k < np ? k : 0)];
-        bool found = false;
-#pragma unroll
-        for (int k = 0; k < kPairChunk; ++k) {
-            if (k >= np) break;
-            const float4 a = t.cen[pr[k].x * T + c];
-            const float4 b = t.cen[pr[k].y * T + c];
-            const float ex = a.x - b.x, ey = a.y - b.y, ez = a.z - b.z;
-            const float Rr = a.w + b.w;
-            found |= fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < Rr * Rr;
+    if (rb.n_blocks > 0) {
+        for (ItemWalk w(n_valid); w.k < rb.n_blocks; w.next(n_valid)) {
+            const int c = w.c, bk = w.k;
+            if (hit[c] || t.scr[c]) continue;
+            const int4 blk = rb.blocks[bk];
+            const float4 A = t.lb[blk.x * T + c], B = t.lb[blk.y * T + c];
+            const float dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;
+            const float R = A.w + B.w;
+            ++ntest;
+            if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < R * R) t.wl[atomicAdd(t.wl_n, 1)] = (bk << 8) | c;
         }
-        ntest += np;
-        if (found) hit[c] = 1;
+        __syncthreads();
+        const int n_items = *t.wl_n;
+        const int lane = threadIdx.x & 63;
+        for (int it = wave_id(); it < n_items; it += blockDim.x >> 6) {
+            const int item = t.wl[it];
+            const int c = item & 255;
+            if (hit[c]) continue;                          // wave-uniform
+            const int4 blk = rb.blocks[item >> 8];
+            bool found = false;
+            for (int p = lane; p < blk.w; p += 64) {
+                const int2 pr = rb.pairs[blk.z + p];
+                const float4 a = t.cen[pr.x * T + c];
+                const float4 b = t.cen[pr.y * T + c];
+                const float ex = a.x - b.x, ey = a.y - b.y, ez = a.z - b.z;
+                const float Rr = a.w + b.w;
+                ++ntest;
+                found |= fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < Rr * Rr;
+            }
+            if (found) hit[c] = 1;
+        }
     }
     if (ob.n > 0) {
         const GridGeom g = *gv.geom;
@@ -435,6 +448,7 @@ __device__ inline unsigned tile_check(const RobotView& rb, const ObsView& ob, co
                                       int T, int n_valid) {
     tile_fk(rb, ob, t, T, n_valid);
     if (threadIdx.x < (unsigned)T) t.hit[threadIdx.x] = (threadIdx.x < (unsigned)n_valid) ? 0 : 1;
+    if (threadIdx.x == 0) *t.wl_n = 0;
     __syncthreads();
     if (SD) {
         tile_pairs_sd(rb, ob, t, T, n_valid);
