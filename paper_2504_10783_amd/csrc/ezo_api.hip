@@ -250,13 +250,17 @@ TileCfg heuristic_sample(int64_t walks) {
     return g;
 }
 
-bool sample_cfg_valid(const TileCfg& g) { return (g.T == 1 || g.T == 2 || g.T == 4 || g.T == 8) && g.W == 4; }
+bool sample_cfg_valid(const TileCfg& g) {
+    return (g.T == 1 || g.T == 2 || g.T == 4 || g.T == 8 || g.T == 16) && g.W == 4;
+}
 
 // Walks of all running edges up to which the fused loop's sampler splits a
-// walk over 8 lanes (above: one lane per walk).  Measured on MI355X for the
-// 7-DOF sampler at 14-144 rows: 8 lanes win at 10 k and 160 k walks (up to
-// 4x at 10 k), one lane wins at 960 k (by 5-25 %).
-constexpr int64_t kSampleWideWalks = 400000;
+// walk over 16 / 4 lanes (above: one lane per walk).  Measured on MI355X for
+// the 7-DOF sampler at 14-144 rows: 16 lanes win at 10 k walks (up to 9x
+// over one lane), 4 lanes at 160 k (by up to 1.4x), one lane at 960 k rows
+// <= 74 (by 5-25 %).
+constexpr int64_t kSampleWalks16 = 40000;
+constexpr int64_t kSampleWalks4 = 400000;
 
 // `active` (device, may be NULL): number of running edges; when given, the
 // adaptive kernel chooses the lanes per walk on the device each launch.
@@ -265,19 +269,19 @@ ezo_status launch_sample(ezo_ctx* c, int dof, const float* A, const float* b, co
                          float* S, int64_t stride, const int* status, const IterArgs& it, hipStream_t st,
                          const TileCfg* shape = nullptr, const int* active = nullptr) {
     const int D = dof <= 4 ? 4 : 8;
-    if (sample_smem_bytes(D, 8, cap, 256) > c->lds_cap)
+    if (sample_smem_bytes(D, 16, cap, 256) > c->lds_cap)
         return ezo_fail(c, EZO_E_UNSUPPORTED, "face capacity %d too large for the sampler", cap);
     if (max_samples <= 0 || E <= 0) return EZO_OK;
     const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
     if (active) {
-        const size_t lds = sample_smem_bytes(D, 8, cap, 256);
-        dim3 grid((unsigned)(((int64_t)max_samples * 8 + 255) / 256), (unsigned)E), block(256);
+        const size_t lds = sample_smem_bytes(D, 16, cap, 256);
+        dim3 grid((unsigned)(((int64_t)max_samples * 16 + 255) / 256), (unsigned)E), block(256);
         if (D == 4)
             EZO_KLAUNCH(c, k_sample_auto<4>, grid, block, lds, st, dof, A, b, n_faces, cap, edges, key0, key1, eid0,
-                        n_mix, S, stride, status, it, active, kSampleWideWalks);
+                        n_mix, S, stride, status, it, active, kSampleWalks16, kSampleWalks4);
         else
             EZO_KLAUNCH(c, k_sample_auto<8>, grid, block, lds, st, dof, A, b, n_faces, cap, edges, key0, key1, eid0,
-                        n_mix, S, stride, status, it, active, kSampleWideWalks);
+                        n_mix, S, stride, status, it, active, kSampleWalks16, kSampleWalks4);
         HIP_TRY(c, hipGetLastError());
         return EZO_OK;
     }
@@ -303,14 +307,16 @@ ezo_status launch_sample(ezo_ctx* c, int dof, const float* A, const float* b, co
             case 1: EZO_LAUNCH_SAMPLE(4, 1); break;
             case 2: EZO_LAUNCH_SAMPLE(4, 2); break;
             case 4: EZO_LAUNCH_SAMPLE(4, 4); break;
-            default: EZO_LAUNCH_SAMPLE(4, 8); break;
+            case 8: EZO_LAUNCH_SAMPLE(4, 8); break;
+            default: EZO_LAUNCH_SAMPLE(4, 16); break;
         }
     } else {
         switch (L) {
             case 1: EZO_LAUNCH_SAMPLE(8, 1); break;
             case 2: EZO_LAUNCH_SAMPLE(8, 2); break;
             case 4: EZO_LAUNCH_SAMPLE(8, 4); break;
-            default: EZO_LAUNCH_SAMPLE(8, 8); break;
+            case 8: EZO_LAUNCH_SAMPLE(8, 8); break;
+            default: EZO_LAUNCH_SAMPLE(8, 16); break;
         }
     }
 #undef EZO_LAUNCH_SAMPLE
@@ -424,7 +430,7 @@ ezo_status tune_bisect_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov
 // iteration (the loop's sampler picks its lanes per walk on the device): the joint box written as 2 dof + 2 n_f rows (box rows repeated),
 // |S| hit-and-run samples per edge from it, and as candidates the first n_p
 // of them in collision.
-constexpr int kItersPerGraph = 2;        // iterations captured per replayed graph
+constexpr int kItersPerGraph = 4;        // iterations captured per replayed graph
 
 ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const GridView& gv, const float* edges,
                           int E, const ezo_params* p, int S_cap, int64_t stride, float* A, float* b, int* n_faces,
@@ -760,7 +766,7 @@ ezo_status ezo_sample_polytopes(ezo_ctx* c, int32_t dof, const float* A, const f
     const TuneKey k = sample_key(c, dof, (int64_t)n_samples * n_edges);
     TileCfg g;
     if (c->autotune && !ezo_tune_lookup(k, &g)) {       // time the lane counts on this call (writes samples only)
-        const std::vector<TileCfg> cands = {{1, 4, 0}, {2, 4, 0}, {4, 4, 0}, {8, 4, 0}};
+        const std::vector<TileCfg> cands = {{1, 4, 0}, {2, 4, 0}, {4, 4, 0}, {8, 4, 0}, {16, 4, 0}};
         auto run = [&](const TileCfg& cfg) {
             return launch_sample(c, dof, A, b, n_faces, face_capacity, edges, n_edges, n_samples, n_mix, seed,
                                  edge_id_base, samples, sample_stride, nullptr, it, st, &cfg);
@@ -852,7 +858,7 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
     if (!edges || !A || !b || !n_faces || !edge_status || (n_obs > 0 && !obs))
         return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
     const int cap = p->face_capacity;
-    if (sample_smem_bytes(dof <= 4 ? 4 : 8, 8, cap, 256) > c->lds_cap)
+    if (sample_smem_bytes(dof <= 4 ? 4 : 8, 16, cap, 256) > c->lds_cap)
         return ezo_fail(c, EZO_E_UNSUPPORTED, "face_capacity %d too large", cap);
     if ((size_t)p->n_p > c->lds_cap - 1024) return ezo_fail(c, EZO_E_UNSUPPORTED, "n_p %d too large", p->n_p);
     // per-iteration constants, FP64 on the host

@@ -246,20 +246,22 @@ __host__ __device__ inline size_t sample_smem_bytes(int D, int L, int cap, int t
 
 // Normalised direction u (zero beyond dof) and chord word of one step.
 template <int D>
-__device__ inline float draw_direction(int dof, uint32_t ii, uint32_t eid, uint32_t kk, uint32_t s, uint32_t key0,
+__device__ __forceinline__ float draw_direction(int dof, uint32_t ii, uint32_t eid, uint32_t kk, uint32_t s, uint32_t key0,
                                        uint32_t key1, float (&u)[D]) {
     const int npair = (dof + 1) >> 1;
     const int tword = 2 * npair;
     const int ncall = (tword + 4) >> 2;
-    U4 r[3] = {};
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-        if (c < ncall) r[c] = philox4x32_10(U4{ii, eid, kk, 16u * s + (uint32_t)c}, key0, key1);
+    // calls as separate values (an array indexed through a reference would
+    // be kept in scratch memory)
+    const U4 r0 = philox4x32_10(U4{ii, eid, kk, 16u * s}, key0, key1);
+    U4 r1{0, 0, 0, 0}, r2{0, 0, 0, 0};
+    if (ncall > 1) r1 = philox4x32_10(U4{ii, eid, kk, 16u * s + 1u}, key0, key1);
+    if (ncall > 2) r2 = philox4x32_10(U4{ii, eid, kk, 16u * s + 2u}, key0, key1);
 #pragma unroll
     for (int m = 0; m < (D + 1) / 2; ++m) {
         float ge = 0.f, go = 0.f;
         if (m < npair) {
-            const U4& rm = r[m >> 1];
+            const U4 rm = (m >> 1) == 0 ? r0 : r1;
             const bool hi = (m & 1) != 0;
             const float ua = u01(hi ? rm.z : rm.x);
             const float ub = u01(hi ? rm.w : rm.y);
@@ -278,12 +280,15 @@ __device__ inline float draw_direction(int dof, uint32_t ii, uint32_t eid, uint3
     const float inv = 1.0f / sqrtf(nrm);
 #pragma unroll
     for (int j = 0; j < D; ++j) u[j] *= inv;
-    return u01(word_of(r[tword >> 2], tword & 3));
+    const int tc = tword >> 2;
+    const U4 rt = tc == 0 ? r0 : (tc == 1 ? r1 : r2);
+    return u01(word_of(rt, tword & 3));
 }
 
 // min / max over the L lanes of a group (groups aligned to L lanes): DPP
 // quad permutations for lane distances 1 and 2, the half-row mirror (lane i
-// with 7 - i) to join the two quads of an 8-lane group.
+// with 7 - i) to join the two quads of an 8-lane group, the row mirror (lane
+// i with 15 - i) to join the two halves of a 16-lane row.
 template <int L>
 __device__ __forceinline__ void group_minmax(float& lo_max, float& hi_min) {
     auto dpp = [](float v, int ctrl) -> float {
@@ -292,7 +297,8 @@ __device__ __forceinline__ void group_minmax(float& lo_max, float& hi_min) {
         switch (ctrl) {
             case 0: r = __builtin_amdgcn_mov_dpp(b, 0xB1, 0xF, 0xF, true); break;    // quad_perm [1,0,3,2]
             case 1: r = __builtin_amdgcn_mov_dpp(b, 0x4E, 0xF, 0xF, true); break;    // quad_perm [2,3,0,1]
-            default: r = __builtin_amdgcn_mov_dpp(b, 0x141, 0xF, 0xF, true); break;  // row_half_mirror
+            case 2: r = __builtin_amdgcn_mov_dpp(b, 0x141, 0xF, 0xF, true); break;   // row_half_mirror
+            default: r = __builtin_amdgcn_mov_dpp(b, 0x140, 0xF, 0xF, true); break;  // row_mirror
         }
         return __builtin_bit_cast(float, r);
     };
@@ -307,6 +313,10 @@ __device__ __forceinline__ void group_minmax(float& lo_max, float& hi_min) {
     if constexpr (L >= 8) {
         hi_min = fminf(hi_min, dpp(hi_min, 2));
         lo_max = fmaxf(lo_max, dpp(lo_max, 2));
+    }
+    if constexpr (L >= 16) {
+        hi_min = fminf(hi_min, dpp(hi_min, 3));
+        lo_max = fmaxf(lo_max, dpp(lo_max, 3));
     }
 }
 
@@ -339,11 +349,11 @@ __device__ __forceinline__ void walk_step(const float* rowA, const float* rowb, 
 // The sampler's work for one workgroup with L lanes per walk; walk i =
 // (blockIdx.x blockDim.x + threadIdx.x) / L of edge blockIdx.y.
 template <int D, int L>
-__device__ inline void sample_block(char* smem, int dof, const float* __restrict__ A, const float* __restrict__ bvec,
+__device__ __forceinline__ void sample_block(char* smem, int dof, const float* __restrict__ A, const float* __restrict__ bvec,
                                     const int* __restrict__ n_faces, int cap, const float* __restrict__ edges,
                                     uint32_t key0, uint32_t key1, int64_t edge_id_base, int n_mix,
                                     float* __restrict__ S, int64_t stride, const IterVals& iv) {
-    static_assert(L == 1 || L == 2 || L == 4 || L == 8, "lanes per walk");
+    static_assert(L == 1 || L == 2 || L == 4 || L == 8 || L == 16, "lanes per walk");
     const int e = blockIdx.y;
     const int F = min(max(n_faces[e], 0), cap);
     float* rowA = reinterpret_cast<float*>(smem);        // [F][D]
@@ -416,12 +426,12 @@ __global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict
     sample_block<D, L>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv);
 }
 
-// The fused loop's sampler: launched with the grid of 8 lanes per walk, it
-// runs 8 lanes per walk while the walks of all running edges (*active x
-// |S|) are at most wide_walks, else one lane per walk (the first 1/8 of the
-// workgroups; the rest exit).  Few walks are latency-bound and gain from
-// splitting the rows; many walks fill the chip either way and one lane per
-// walk does the least work.  Samples are identical in both modes.
+// The fused loop's sampler: launched with the grid of 16 lanes per walk, it
+// picks the lanes per walk from the walks of all running edges (*active x
+// |S|): 16 up to walks16, 4 up to walks4, else 1 (workgroups past the walks
+// exit).  Few walks are latency-bound and gain from splitting the rows; many
+// walks fill the chip either way and one lane per walk does the least work.
+// Samples are identical in every mode.
 template <int D>
 __global__ void __launch_bounds__(256) k_sample_auto(int dof, const float* __restrict__ A,
                                                      const float* __restrict__ bvec, const int* __restrict__ n_faces,
@@ -429,14 +439,19 @@ __global__ void __launch_bounds__(256) k_sample_auto(int dof, const float* __res
                                                      uint32_t key1, int64_t edge_id_base, int n_mix,
                                                      float* __restrict__ S, int64_t stride,
                                                      const int* __restrict__ status, IterArgs it,
-                                                     const int* __restrict__ active, int64_t wide_walks) {
+                                                     const int* __restrict__ active, int64_t walks16, int64_t walks4) {
     extern __shared__ __align__(16) char smem[];
     if (!edge_running(status, blockIdx.y)) return;
     const IterVals iv = resolve(it);
-    if ((int64_t)max(*active, 1) * iv.nS <= wide_walks) {
-        sample_block<D, 8>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv);
+    const int64_t walks = (int64_t)max(*active, 1) * iv.nS;
+    const int64_t wg_first = (int64_t)blockIdx.x * blockDim.x;     // first thread of this workgroup
+    if (walks <= walks16) {
+        sample_block<D, 16>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv);
+    } else if (walks <= walks4) {
+        if (wg_first >= 4 * (int64_t)iv.nS) return;
+        sample_block<D, 4>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv);
     } else {
-        if ((int64_t)blockIdx.x * blockDim.x >= iv.nS) return;     // whole workgroup past the walks
+        if (wg_first >= iv.nS) return;
         sample_block<D, 1>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv);
     }
 }
@@ -649,47 +664,52 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView o
 // ---------------------------------------------------------------------------
 // Ordering and placing hyperplanes: one workgroup (1024 threads) per edge,
 // n_f rounds of (argmin over alive candidates by (t*, index), broadcast row,
-// discard).  Alive flags in LDS.
+// discard).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict__ edges, const float* __restrict__ c_star,
-                                                const float* __restrict__ a_dir, const float* __restrict__ t_star,
-                                                const int* __restrict__ n_cands, int cand_cap, int n_f,
-                                                float step_back_max, float t_col, float* __restrict__ A,
-                                                float* __restrict__ bvec, int* __restrict__ n_faces, int cap,
-                                                int* __restrict__ status, int* __restrict__ placed_idx,
-                                                int* __restrict__ n_placed, const uint8_t* __restrict__ proj_any,
-                                                EdgeStatsDev* __restrict__ stats) {
-    extern __shared__ __align__(16) char smem[];
-    uint8_t* alive = reinterpret_cast<uint8_t*>(smem);                // [cand_cap]
-    __shared__ unsigned long long wmin[16];
-    __shared__ float row[kMaxDof + 1];
-    __shared__ int s_stop;
-    const int e = blockIdx.x;
-    if (status[e] >= 0) return;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
-    if (proj_any && proj_any[e]) {
-        if (tid == 0) {
-            status[e] = 2;   // EZO_EDGE_IN_COLLISION
-            if (n_placed) n_placed[e] = 0;
-        }
-        return;
-    }
-    const int n = min(max(n_cands[e], 0), cand_cap);
-    for (int j = tid; j < n; j += blockDim.x) alive[j] = 1;
-    const float* v = edges + (size_t)e * 2 * dof;
-    const float* cs = c_star + (size_t)e * dof * cand_cap;
-    const float* ad = a_dir + (size_t)e * dof * cand_cap;
-    const float* ts = t_star + (size_t)e * cand_cap;
+// Placement rounds of one edge.  REG: the thread's candidates j = tid +
+// q blockDim (q < kPlaceReg) keep c* and their (t*, index) keys in registers
+// (needs n <= kPlaceReg blockDim); otherwise both are read from global memory
+// every round and the alive flags live in LDS.
+constexpr int kPlaceReg = 4;
+
+template <bool REG>
+__device__ inline void place_rounds(int e, int dof, const float* __restrict__ v, const float* __restrict__ cs,
+                                    const float* __restrict__ ad, const float* __restrict__ ts, int n, int cand_cap,
+                                    int n_f, float step_back_max, float t_col, float* __restrict__ A,
+                                    float* __restrict__ bvec, int* __restrict__ n_faces, int cap,
+                                    int* __restrict__ status, int* __restrict__ placed_idx,
+                                    int* __restrict__ n_placed, EdgeStatsDev* __restrict__ stats, uint8_t* alive,
+                                    unsigned long long* wmin, float* row, int* s_stop) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6, nt = blockDim.x;
     int nf = min(max(n_faces[e], 0), cap);
     int placed = 0;
-    if (tid == 0) s_stop = 0;
+    float cx[REG ? kPlaceReg : 1][kMaxDof];
+    unsigned long long key[REG ? kPlaceReg : 1];
+    bool al[REG ? kPlaceReg : 1];
     // smallest (t*, index) key among this thread's alive candidates; after a
     // plane is placed the discard pass and the next round's scan are one pass
     unsigned long long best = ~0ull;
-    for (int j = tid; j < n; j += blockDim.x) {
-        const unsigned long long key = ((unsigned long long)__float_as_uint(ts[j]) << 32) | (unsigned)j;
-        best = key < best ? key : best;
+    if constexpr (REG) {
+#pragma unroll
+        for (int q = 0; q < kPlaceReg; ++q) {
+            const int j = tid + q * nt;
+            al[q] = j < n;
+            key[q] = ~0ull;
+            if (al[q]) {
+                key[q] = ((unsigned long long)__float_as_uint(ts[j]) << 32) | (unsigned)j;
+#pragma unroll
+                for (int k = 0; k < kMaxDof; ++k) cx[q][k] = k < dof ? cs[(size_t)k * cand_cap + j] : 0.f;
+                best = key[q] < best ? key[q] : best;
+            }
+        }
+    } else {
+        for (int j = tid; j < n; j += nt) {
+            alive[j] = 1;
+            const unsigned long long kj = ((unsigned long long)__float_as_uint(ts[j]) << 32) | (unsigned)j;
+            best = kj < best ? kj : best;
+        }
     }
+    if (tid == 0) *s_stop = 0;
     for (int round = 0; round < n_f; ++round) {
         for (int off = 32; off > 0; off >>= 1) {
             const unsigned long long o = __shfl_xor(best, off);
@@ -703,10 +723,10 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
         const int jb = (int)(best & 0xffffffffull);
         if (tid == 0) {
             if (ts[jb] <= t_col) {
-                s_stop = 1;
+                *s_stop = 1;
                 status[e] = 2;                            // EZO_EDGE_IN_COLLISION
             } else if (nf >= cap) {
-                s_stop = 1;
+                *s_stop = 1;
             } else {
                 float bj = 0.f, av1 = 0.f, av2 = 0.f;
                 for (int k = 0; k < dof; ++k) {
@@ -726,28 +746,79 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
             }
         }
         __syncthreads();
-        if (s_stop) break;
+        if (*s_stop) break;
         ++nf;
         ++placed;
         const float rhs = row[kMaxDof];
         best = ~0ull;
-        for (int j = tid; j < n; j += blockDim.x)
-            if (alive[j]) {
+        if constexpr (REG) {
+            float rw[kMaxDof];
+#pragma unroll
+            for (int k = 0; k < kMaxDof; ++k) rw[k] = row[k];
+#pragma unroll
+            for (int q = 0; q < kPlaceReg; ++q) {
+                if (!al[q]) continue;
                 float ac = 0.f;
-                for (int k = 0; k < dof; ++k) ac = fmaf(row[k], cs[(size_t)k * cand_cap + j], ac);
-                if (ac > rhs) {
-                    alive[j] = 0;
-                } else {
-                    const unsigned long long key = ((unsigned long long)__float_as_uint(ts[j]) << 32) | (unsigned)j;
-                    best = key < best ? key : best;
-                }
+#pragma unroll
+                for (int k = 0; k < kMaxDof; ++k)
+                    if (k < dof) ac = fmaf(rw[k], cx[q][k], ac);
+                if (ac > rhs) al[q] = false;
+                else best = key[q] < best ? key[q] : best;
             }
+        } else {
+            for (int j = tid; j < n; j += nt)
+                if (alive[j]) {
+                    float ac = 0.f;
+                    for (int k = 0; k < dof; ++k) ac = fmaf(row[k], cs[(size_t)k * cand_cap + j], ac);
+                    if (ac > rhs) {
+                        alive[j] = 0;
+                    } else {
+                        const unsigned long long kj = ((unsigned long long)__float_as_uint(ts[j]) << 32) | (unsigned)j;
+                        best = kj < best ? kj : best;
+                    }
+                }
+        }
     }
     if (tid == 0) {
         n_faces[e] = nf;
         if (n_placed) n_placed[e] = placed;
         if (stats) stats[e].planes += placed;
     }
+}
+
+__global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict__ edges, const float* __restrict__ c_star,
+                                                const float* __restrict__ a_dir, const float* __restrict__ t_star,
+                                                const int* __restrict__ n_cands, int cand_cap, int n_f,
+                                                float step_back_max, float t_col, float* __restrict__ A,
+                                                float* __restrict__ bvec, int* __restrict__ n_faces, int cap,
+                                                int* __restrict__ status, int* __restrict__ placed_idx,
+                                                int* __restrict__ n_placed, const uint8_t* __restrict__ proj_any,
+                                                EdgeStatsDev* __restrict__ stats) {
+    extern __shared__ __align__(16) char smem[];
+    uint8_t* alive = reinterpret_cast<uint8_t*>(smem);                // [cand_cap]
+    __shared__ unsigned long long wmin[16];
+    __shared__ float row[kMaxDof + 1];
+    __shared__ int s_stop;
+    const int e = blockIdx.x;
+    if (status[e] >= 0) return;
+    if (proj_any && proj_any[e]) {
+        if (threadIdx.x == 0) {
+            status[e] = 2;   // EZO_EDGE_IN_COLLISION
+            if (n_placed) n_placed[e] = 0;
+        }
+        return;
+    }
+    const int n = min(max(n_cands[e], 0), cand_cap);
+    const float* v = edges + (size_t)e * 2 * dof;
+    const float* cs = c_star + (size_t)e * dof * cand_cap;
+    const float* ad = a_dir + (size_t)e * dof * cand_cap;
+    const float* ts = t_star + (size_t)e * cand_cap;
+    if (n <= kPlaceReg * (int)blockDim.x)
+        place_rounds<true>(e, dof, v, cs, ad, ts, n, cand_cap, n_f, step_back_max, t_col, A, bvec, n_faces, cap,
+                           status, placed_idx, n_placed, stats, alive, wmin, row, &s_stop);
+    else
+        place_rounds<false>(e, dof, v, cs, ad, ts, n, cand_cap, n_f, step_back_max, t_col, A, bvec, n_faces, cap,
+                            status, placed_idx, n_placed, stats, alive, wmin, row, &s_stop);
 }
 
 // ---------------------------------------------------------------------------

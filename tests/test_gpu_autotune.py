@@ -152,7 +152,7 @@ def test_sampler_lane_counts_give_identical_samples(ezo, ctx, name, n_mix):
     out = {}
     ctx.set_autotune(False)
     try:
-        for L in (1, 2, 4, 8):
+        for L in (1, 2, 4, 8, 16):
             ezo.tune_cache_clear()
             ezo.tune_cache_import(json.dumps({"arch": arch(), "kernel": "sample", "dof": dof, "spheres": 0,
                                               "self_pairs": 0, "obstacles": 0,
@@ -162,7 +162,7 @@ def test_sampler_lane_counts_give_identical_samples(ezo, ctx, name, n_mix):
             ezo.sample_polytopes(ctx, dof, At, bt, nf, edges, n, n_mix, seed=11, iteration=2, samples=S)
             torch.cuda.synchronize()
             out[L] = S
-        for L in (1, 2, 4):
+        for L in (1, 2, 4, 16):
             assert torch.equal(out[L], out[8]), L
         x = out[8][0, :, :n].cpu().numpy().T.astype(np.float64)
         assert np.all(x @ A.T.astype(np.float64) <= b + 1e-4)
