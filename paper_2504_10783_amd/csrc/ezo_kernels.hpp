@@ -477,9 +477,12 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
     const IterVals iv = resolve(it);
     const uint8_t* fe = flags + (size_t)e * stride;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
-    // count over the first M samples
+    // count over the first M samples (four consecutive flags per thread)
+    const int nt4 = 4 * (int)blockDim.x;
     int cnt = 0;
-    for (int i = tid; i < iv.M; i += blockDim.x) cnt += fe[i] ? 1 : 0;
+    for (int i0 = 4 * tid; i0 < iv.M; i0 += nt4)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cnt += (i0 + q < iv.M && fe[i0 + q]) ? 1 : 0;
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
     if (lane == 0) wsum[w] = cnt;
     __syncthreads();
@@ -491,19 +494,33 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
     if (!accept) {
         if (tid == 0) s_base = 0;
         __syncthreads();
-        for (int c0 = 0; c0 < iv.nS; c0 += blockDim.x) {
-            const int i = c0 + tid;
-            const bool f = (i < iv.nS) && fe[i];
-            const unsigned long long m = __ballot(f);
-            const int before = __popcll(m & ((1ull << lane) - 1ull));
-            if (lane == 0) wsum[w] = __popcll(m);
+        const unsigned long long lt = (1ull << lane) - 1ull;
+        for (int c0 = 0; c0 < iv.nS; c0 += nt4) {
+            // flags i0 .. i0 + 3 of this thread; the wave's exclusive prefix of
+            // the per-thread counts (0..4) from one ballot per count bit
+            const int i0 = c0 + 4 * tid;
+            bool f[4];
+            int lc = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                f[q] = (i0 + q < iv.nS) && fe[i0 + q];
+                lc += f[q] ? 1 : 0;
+            }
+            const unsigned long long b0 = __ballot(lc & 1), b1 = __ballot(lc & 2), b2 = __ballot(lc & 4);
+            const int before = __popcll(b0 & lt) + 2 * __popcll(b1 & lt) + 4 * __popcll(b2 & lt);
+            if (lane == 0) wsum[w] = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
             __syncthreads();
             int off = s_base;
             for (int k = 0; k < w; ++k) off += wsum[k];
             int chunk = 0;
             for (int k = 0; k < nw; ++k) chunk += wsum[k];
-            const int pos = off + before;
-            if (f && pos < n_p) cand_idx[(size_t)e * cand_cap + pos] = i;
+            int pos = off + before;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (f[q]) {
+                    if (pos < n_p) cand_idx[(size_t)e * cand_cap + pos] = i0 + q;
+                    ++pos;
+                }
             __syncthreads();
             if (tid == 0) s_base += chunk;
             __syncthreads();
@@ -684,6 +701,7 @@ __device__ inline void place_rounds(int e, int dof, const float* __restrict__ v,
     int nf = min(max(n_faces[e], 0), cap);
     int placed = 0;
     float cx[REG ? kPlaceReg : 1][kMaxDof];
+    float ax[REG ? kPlaceReg : 1][kMaxDof];
     unsigned long long key[REG ? kPlaceReg : 1];
     bool al[REG ? kPlaceReg : 1];
     // smallest (t*, index) key among this thread's alive candidates; after a
@@ -698,7 +716,10 @@ __device__ inline void place_rounds(int e, int dof, const float* __restrict__ v,
             if (al[q]) {
                 key[q] = ((unsigned long long)__float_as_uint(ts[j]) << 32) | (unsigned)j;
 #pragma unroll
-                for (int k = 0; k < kMaxDof; ++k) cx[q][k] = k < dof ? cs[(size_t)k * cand_cap + j] : 0.f;
+                for (int k = 0; k < kMaxDof; ++k) {
+                    cx[q][k] = k < dof ? cs[(size_t)k * cand_cap + j] : 0.f;
+                    ax[q][k] = k < dof ? ad[(size_t)k * cand_cap + j] : 0.f;
+                }
                 best = key[q] < best ? key[q] : best;
             }
         }
@@ -721,18 +742,38 @@ __device__ inline void place_rounds(int e, int dof, const float* __restrict__ v,
         for (int k = 0; k < nw; ++k) best = wmin[k] < best ? wmin[k] : best;
         if (best == ~0ull) break;                         // no candidate left (uniform)
         const int jb = (int)(best & 0xffffffffull);
-        if (tid == 0) {
-            if (ts[jb] <= t_col) {
+        // the row is built by the thread that holds candidate jb (REG) or by
+        // thread 0 from global memory
+        const bool builder = REG ? (jb % nt == tid) : (tid == 0);
+        if (builder) {
+            const float tsb = __uint_as_float((unsigned)(best >> 32));
+            if (tsb <= t_col) {
                 *s_stop = 1;
                 status[e] = 2;                            // EZO_EDGE_IN_COLLISION
             } else if (nf >= cap) {
                 *s_stop = 1;
             } else {
                 float bj = 0.f, av1 = 0.f, av2 = 0.f;
-                for (int k = 0; k < dof; ++k) {
-                    const float a = ad[(size_t)k * cand_cap + jb];
+                const int qb = jb / nt;
+#pragma unroll
+                for (int k = 0; k < kMaxDof; ++k) {
+                    if (k >= dof) break;
+                    float a, c;
+                    if constexpr (REG) {
+                        a = ax[0][k];
+                        c = cx[0][k];
+#pragma unroll
+                        for (int q = 1; q < kPlaceReg; ++q)
+                            if (q == qb) {
+                                a = ax[q][k];
+                                c = cx[q][k];
+                            }
+                    } else {
+                        a = ad[(size_t)k * cand_cap + jb];
+                        c = cs[(size_t)k * cand_cap + jb];
+                    }
                     row[k] = a;
-                    bj = fmaf(a, cs[(size_t)k * cand_cap + jb], bj);
+                    bj = fmaf(a, c, bj);
                     av1 = fmaf(a, v[k], av1);
                     av2 = fmaf(a, v[dof + k], av2);
                 }
