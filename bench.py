@@ -37,6 +37,36 @@ WORKLOADS = {
 }
 
 
+KERNEL_SOURCES = ("paper_2504_10783_amd/csrc/ezo_device.hpp", "paper_2504_10783_amd/csrc/ezo_kernels.hpp")
+
+
+def kernel_source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel_instance):
+    """HBM bytes per launch of `kernel_instance` from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload (each counter
+    scaled by its reading for a plain 1 GiB copy), or None when there is no
+    summary, the instance was not measured, or the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic__{workload}_inflate.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic-json: "):
+            rec = json.loads(line[len("traffic-json: "):])
+            if rec.get("source_sha256") != kernel_source_sha256():
+                return None
+            return rec.get("bytes_per_launch", {}).get(kernel_instance)
+    return None
+
+
 def flop_per_check(n_spheres, n_obs, n_self):
     return PAIR_FLOP * (n_spheres * n_obs + n_self) + FK_FLOP
 
@@ -299,9 +329,18 @@ def main():
     work = PAIR_FLOP * tests[dom] + FK_FLOP * n_checks[dom]      # both summed over the K steps
     achieved = work / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0
     all_pairs = flop_per_check(rob.n_spheres, obs.shape[0], rob.n_self) * n_checks[dom]
+    shapes = {e["kernel"]: e for e in ezo.tune_cache_entries() if e["obstacles"] == int(obs.shape[0])}
+    if dom == "bisect":
+        sb = shapes.get("bisect")
+        instance = f"ezo::k_project_bisect<{sb['T']}, {sb['depth']}>" if sb else None
+    else:
+        sc = shapes.get("check_flags")
+        instance = f"ezo::k_check<{sc['T']}, false>" if sc else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                "kernel": "k_project_bisect" if dom == "bisect" else "k_check",
+                "frac": achieved / PEAK_FP32_TFLOPS,
+                "traffic": measured_traffic(name, instance) if instance else None,
+                "traffic_unit": "bytes per launch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "kernel": "k_project_bisect" if dom == "bisect" else "k_check", "kernel_instance": instance,
                 "avg_launch_ms": dom_ms / max(iters, 1), "launches": iters,
                 "pair_tests_per_check": tests[dom] / max(n_checks[dom], 1),
                 "all_pairs_per_check": rob.n_spheres * int(obs.shape[0]) + rob.n_self,
