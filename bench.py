@@ -50,11 +50,12 @@ def kernel_source_sha256():
 
 
 def measured_traffic(workload, kernel_instance):
-    """HBM bytes per launch of `kernel_instance` from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload (each counter
-    scaled by its reading for a plain 1 GiB copy), or None when there is no
-    summary, the instance was not measured, or the kernel sources changed
-    since the counters were taken."""
+    """HBM bytes per launch of the kernel of `kernel_instance` (its counters
+    pooled over launch shapes) from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary of this workload (each counter scaled by its reading
+    for a plain 1 GiB copy), or None when there is no summary, the kernel was
+    not measured, or the kernel sources changed since the counters were
+    taken."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic__{workload}_inflate.md")
     if not os.path.exists(path):
         return None
@@ -63,7 +64,7 @@ def measured_traffic(workload, kernel_instance):
             rec = json.loads(line[len("traffic-json: "):])
             if rec.get("source_sha256") != kernel_source_sha256():
                 return None
-            return rec.get("bytes_per_launch", {}).get(kernel_instance)
+            return rec.get("bytes_per_launch", {}).get(kernel_instance.split("<")[0])
     return None
 
 
