@@ -443,6 +443,9 @@ ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, con
     TileCfg g;
     const bool need_c = !ezo_tune_lookup(kc, &g), need_b = !ezo_tune_lookup(kb, &g);
     if (!need_c && !need_b) return EZO_OK;
+    const int n_run = E;                      // the sampler's running-edge count during tuning
+    HIP_TRY(c, hipMemcpyAsync((void*)w_active, &n_run, sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
     const int F = std::min(cap, 2 * dof + 2 * p->n_f);
     hipLaunchKernelGGL(k_tune_polytope, dim3((E + 63) / 64), dim3(64), 0, st, dof, r->q_lo, r->q_hi, E, cap, F, A, b,
                        n_faces);
@@ -900,10 +903,15 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
     hipStream_t st = c->stream;
     HIP_TRY(c, hipEventRecord(c->ev_in, as_stream(stream)));
     HIP_TRY(c, hipStreamWaitEvent(st, c->ev_in, 0));
-    HIP_TRY(c, hipMemcpyAsync(w_tb, table.data(), sizeof(int4) * table.size(), hipMemcpyHostToDevice, st));
-    const int one = 1, n_edges_init = E;
-    HIP_TRY(c, hipMemcpyAsync(w_k, &one, sizeof(int), hipMemcpyHostToDevice, st));
-    HIP_TRY(c, hipMemcpyAsync(w_ac, &n_edges_init, sizeof(int), hipMemcpyHostToDevice, st));
+    // the per-iteration table is copied only when it differs from the one the
+    // slot already holds
+    if (c->table_dev != w_tb || c->table_host.size() != table.size() ||
+        std::memcmp(c->table_host.data(), table.data(), sizeof(int4) * table.size()) != 0) {
+        HIP_TRY(c, hipMemcpyAsync(w_tb, table.data(), sizeof(int4) * table.size(), hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipStreamSynchronize(st));       // the host vector is reused below
+        c->table_host = table;
+        c->table_dev = w_tb;
+    }
     ObsView ov;
     GridView gv;
     if ((s = prep_obstacles(c, r, obs, n_obs, st, &ov, &gv))) return s;
@@ -912,7 +920,7 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
                             (const int*)w_ac, st)))
         return s;
     hipLaunchKernelGGL(k_init_edges, dim3((E + 63) / 64), dim3(64), 0, st, dof, r->q_lo, r->q_hi, edges, E, A, b,
-                       n_faces, cap, edge_status, (EdgeStatsDev*)w_st, (uint8_t*)w_pa);
+                       n_faces, cap, edge_status, (EdgeStatsDev*)w_st, (uint8_t*)w_pa, (int*)w_k, (int*)w_ac);
     HIP_TRY(c, hipGetLastError());
     IterArgs it{(const int*)w_k, (const int4*)w_tb, 0, 0, 0, 0};
     const uint32_t k0 = (uint32_t)p->seed, k1 = (uint32_t)(p->seed >> 32);
@@ -995,7 +1003,56 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
     // arguments); instantiation happens only when the topology changes.
     hipGraphExec_t exec = nullptr;
     int per = 1;
+    // Everything the captured launches depend on: when a call repeats the
+    // previous one's key, the kept executable graph is replayed as it is.
+    std::vector<uintptr_t> key;
     if (!c->timing) {
+        auto push = [&](const void* ptr) { key.push_back(reinterpret_cast<uintptr_t>(ptr)); };
+        push(r);
+        push(r->buf);
+        push(obs);
+        push(edges);
+        push(A);
+        push(b);
+        push(n_faces);
+        push(edge_status);
+        push(st);
+        key.push_back((uintptr_t)(uint32_t)n_obs);
+        key.push_back((uintptr_t)(uint32_t)E);
+        key.push_back((uintptr_t)S_cap);
+        key.push_back((uintptr_t)stride);
+        const unsigned char* pb = reinterpret_cast<const unsigned char*>(p);
+        for (size_t i = 0; i < sizeof(ezo_params); i += sizeof(uint32_t)) {
+            uint32_t wv = 0;
+            std::memcpy(&wv, pb + i, std::min(sizeof(uint32_t), sizeof(ezo_params) - i));
+            key.push_back(wv);
+        }
+        if (p->surrogate) {
+            uint32_t mb;
+            std::memcpy(&mb, &p->surrogate->margin, sizeof(mb));
+            key.push_back(mb);
+            push(p->surrogate->P);
+            push(p->surrogate->W2b);
+            push(p->surrogate->W3b);
+            key.push_back((uintptr_t)p->surrogate->D);
+            key.push_back((uintptr_t)p->surrogate->H);
+        }
+        for (const DevBuf& wb : c->ws) push(wb.p);
+        const TileCfg gc = resolve_cfg(c, tune_key(c, r, TUNE_CHECK_FLAGS, ov.n, (int64_t)S_cap * E),
+                                       heuristic_check(c, r, ov.n, (int64_t)S_cap * E, false), r->S, ov.n, false);
+        const TileCfg gb = resolve_cfg(c, tune_key(c, r, TUNE_BISECT, ov.n, (int64_t)cand_cap * E),
+                                       heuristic_bisect(c, r, ov.n, (int64_t)cand_cap * E), r->S, ov.n, false, true);
+        for (const TileCfg& g : {gc, gb}) {
+            key.push_back((uintptr_t)g.T);
+            key.push_back((uintptr_t)g.W);
+            key.push_back((uintptr_t)g.stage);
+            key.push_back((uintptr_t)g.depth);
+        }
+    }
+    if (!c->timing && c->loop_exec && key == c->loop_key) {
+        per = kItersPerGraph;
+        exec = c->loop_exec;
+    } else if (!c->timing) {
         per = kItersPerGraph;
         hipGraph_t graph = nullptr;
         HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -1023,6 +1080,7 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
         }
         (void)hipGraphDestroy(graph);
         exec = c->loop_exec;
+        c->loop_key = key;
     }
     ezo_status result = EZO_OK;
     for (int k = 1; k <= p->max_iters; k += per) {

@@ -49,6 +49,9 @@ struct ezo_ctx {
     bool autotune = true;              // time launch shapes on first use of a tuning key
     hipEvent_t tune_ev[2] = {};
     hipGraphExec_t loop_exec = nullptr;   // the inflation loop's graph, updated in place by later calls
+    std::vector<uintptr_t> loop_key;      // everything the captured loop's launches depend on
+    std::vector<int4> table_host;         // per-iteration table last copied to table_dev
+    const void* table_dev = nullptr;
 };
 
 struct ezo_robot {

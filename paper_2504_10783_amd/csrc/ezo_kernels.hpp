@@ -392,11 +392,23 @@ __device__ __forceinline__ void sample_block(char* smem, int dof, const float* _
                       (size_t)(threadIdx.x / L) * CH * SD;
         for (int s0 = 1; s0 <= n_mix; s0 += CH) {
             const int ns = min(CH, n_mix - s0 + 1);
-            for (int c = sub; c < ns; c += L) {
-                const float wt = draw_direction<D>(dof, ii, eid, kk, (uint32_t)(s0 + c), key0, key1, u);
+            // this lane's two steps of the chunk, drawn side by side (independent
+            // chains the scheduler interleaves)
+            {
+                float u2[D];
+                const int c0 = sub, c1 = sub + L;
+                const float w0 = draw_direction<D>(dof, ii, eid, kk, (uint32_t)(s0 + c0), key0, key1, u);
+                const float w1 = draw_direction<D>(dof, ii, eid, kk, (uint32_t)(s0 + c1), key0, key1, u2);
+                if (c0 < ns) {
 #pragma unroll
-                for (int j = 0; j < D; ++j) dirs[c * SD + j] = u[j];
-                dirs[c * SD + D] = wt;
+                    for (int j = 0; j < D; ++j) dirs[c0 * SD + j] = u[j];
+                    dirs[c0 * SD + D] = w0;
+                }
+                if (c1 < ns) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) dirs[c1 * SD + j] = u2[j];
+                    dirs[c1 * SD + D] = w1;
+                }
             }
             __syncthreads();
             for (int c = 0; c < ns; ++c) {
@@ -883,11 +895,18 @@ __global__ void k_tune_polytope(int dof, const float* __restrict__ q_lo, const f
     n_faces[e] = F;
 }
 
+// Per edge: P = D (box rows), status RUNNING or INVALID, stats cleared; and
+// the loop's iteration counter k = 1 and running-edge count = n_edges.
 __global__ void k_init_edges(int dof, const float* __restrict__ q_lo, const float* __restrict__ q_hi,
                              const float* __restrict__ edges, int n_edges, float* __restrict__ A,
                              float* __restrict__ bvec, int* __restrict__ n_faces, int cap, int* __restrict__ status,
-                             EdgeStatsDev* __restrict__ stats, uint8_t* __restrict__ proj_any) {
+                             EdgeStatsDev* __restrict__ stats, uint8_t* __restrict__ proj_any,
+                             int* __restrict__ k_dev, int* __restrict__ active) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) {
+        *k_dev = 1;
+        *active = n_edges;
+    }
     if (e >= n_edges) return;
     float* Ae = A + (size_t)e * cap * dof;
     float* be = bvec + (size_t)e * cap;
