@@ -45,15 +45,16 @@ struct RobotView {
 constexpr int kMaxLinkPairs = kMaxDof * (kMaxDof + 1) / 2;   // link pairs, same-link pairs included
 
 // Uniform grid over the obstacle cloud (shifted frame).  Cell k lists every
-// obstacle that a robot sphere centred anywhere in cell k could touch:
-// |o - centre_k| < r_o + r_sphere_max + half cell diagonal + slack.  A sphere
-// centre outside the grid box is farther than r_sphere_max + r_o_max from
-// every obstacle.  count[k] > cap marks an overflowing cell (scan all).
+// obstacle that a robot sphere centred anywhere in cell k could touch: the
+// distance from o to the cell's box is below r_o + r_sphere_max + slack (a
+// sphere centre c in the box has |c - o| >= that distance).  A sphere centre
+// outside the grid box is farther than r_sphere_max + r_o_max from every
+// obstacle.  count[k] > cap marks an overflowing cell (scan all).
 struct GridGeom {
     float ox, oy, oz;          // origin (min corner)
     float hx, hy, hz;          // cell size
     float ihx, ihy, ihz;       // 1 / cell size
-    float reach;               // r_sphere_max + half cell diagonal + slack
+    float reach;               // r_sphere_max + slack
 };
 
 struct GridView {

@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(256) k_prep_obstacles(const float* __restrict_
         g.ox = -half[0] - margin; g.oy = -half[1] - margin; g.oz = -half[2] - margin;
         g.hx = h[0]; g.hy = h[1]; g.hz = h[2];
         g.ihx = 1.f / h[0]; g.ihy = 1.f / h[1]; g.ihz = 1.f / h[2];
-        g.reach = r_sphere_max + 0.5f * sqrtf(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]) + kGridSlack;
+        g.reach = r_sphere_max + kGridSlack;
         geom[0] = g;
     }
     for (int o = tid; o < n; o += blockDim.x) {
@@ -102,8 +102,9 @@ __global__ void __launch_bounds__(256) k_prep_obstacles(const float* __restrict_
     }
 }
 
-// Grid lists: one wave per cell; 64 obstacles per step tested against the
-// cell's reach, survivors appended in index order by ballot prefix.
+// Grid lists: one wave per cell; 64 obstacles per step tested by their
+// distance to the cell's box, survivors appended in index order by ballot
+// prefix.
 __global__ void __launch_bounds__(256) k_build_grid(const float4* __restrict__ rec, int n, const GridGeom* __restrict__ geom,
                                                     int G, int cap, int* __restrict__ count,
                                                     unsigned short* __restrict__ list) {
@@ -116,7 +117,8 @@ __global__ void __launch_bounds__(256) k_build_grid(const float4* __restrict__ r
     }
     const GridGeom g = *geom;
     const int cx = cell % G, cy = (cell / G) % G, cz = cell / (G * G);
-    const float px = g.ox + (cx + 0.5f) * g.hx, py = g.oy + (cy + 0.5f) * g.hy, pz = g.oz + (cz + 0.5f) * g.hz;
+    const float lx = g.ox + cx * g.hx, ly = g.oy + cy * g.hy, lz = g.oz + cz * g.hz;
+    const float ux = lx + g.hx, uy = ly + g.hy, uz = lz + g.hz;
     int total = 0;
     unsigned short* lst = list + (size_t)cell * cap;
     for (int o0 = 0; o0 < n; o0 += 64) {
@@ -124,7 +126,9 @@ __global__ void __launch_bounds__(256) k_build_grid(const float4* __restrict__ r
         bool in = false;
         if (o < n) {
             const float4 O = rec[2 * (size_t)o];
-            const float dx = O.x - px, dy = O.y - py, dz = O.z - pz;
+            const float dx = fmaxf(fmaxf(lx - O.x, O.x - ux), 0.f);
+            const float dy = fmaxf(fmaxf(ly - O.y, O.y - uy), 0.f);
+            const float dz = fmaxf(fmaxf(lz - O.z, O.z - uz), 0.f);
             const float R = O.w + g.reach;
             in = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < R * R;
         }

@@ -273,3 +273,46 @@ def test_full_runs_agree_with_oracle_statistically(ezo, ctx):
             assert np.abs(A[0, :nf[0]] - o["A"]).max() < 1e-3
     print(f"same iterations {same_iters}/{n}, same faces {same_faces}/{n}")
     assert same_iters >= 0.75 * n and same_faces >= 0.75 * n
+
+
+def test_kept_graph_follows_every_change_between_calls(ezo, ctx):
+    """Calls on one context reuse its executable loop graph when nothing
+    changed, else update it.  Same output buffers, then a different seed, new
+    obstacle contents at the same address, and fewer edges: every result must
+    equal that of a fresh context."""
+    data, desc = load("batched")
+    rob = ezo.Robot(ctx, desc)
+    dof = desc["dof"]
+    edges = torch.from_numpy(data["edges"][:12]).cuda()
+    obs = torch.from_numpy(data["obstacles"]).cuda()
+    cap = params(ezo, "batched", dof, seed=1).face_capacity
+    out = ezo.InflateResult(torch.empty((12, cap, dof), dtype=torch.float32, device="cuda"),
+                            torch.empty((12, cap), dtype=torch.float32, device="cuda"),
+                            torch.empty(12, dtype=torch.int32, device="cuda"),
+                            torch.empty(12, dtype=torch.int32, device="cuda"), [])
+
+    def fresh(seed, obs_t, e_t):
+        c2 = ezo.Context(0)
+        r = ezo.inflate_edges(c2, ezo.Robot(c2, desc), obs_t.clone(), e_t.clone(), params(ezo, "batched", dof, seed=seed))
+        torch.cuda.synchronize()
+        return r
+
+    def same(r, ref, n):
+        assert torch.equal(r.status[:n], ref.status) and torch.equal(r.n_faces[:n], ref.n_faces)
+        for e, F in enumerate(ref.n_faces.tolist()):
+            assert torch.equal(r.A[e, :F], ref.A[e, :F]) and torch.equal(r.b[e, :F], ref.b[e, :F])
+
+    print_case("kept graph", 12)
+    for seed in (1, 1, 2, 1):
+        ezo.inflate_edges(ctx, rob, obs, edges, params(ezo, "batched", dof, seed=seed), out=out)
+        torch.cuda.synchronize()
+        same(out, fresh(seed, obs, edges), 12)
+    # new obstacle contents at the same address (the grid is rebuilt per call)
+    obs[:, 3] *= 0.5
+    ezo.inflate_edges(ctx, rob, obs, edges, params(ezo, "batched", dof, seed=1), out=out)
+    torch.cuda.synchronize()
+    same(out, fresh(1, obs, edges), 12)
+    # fewer edges, same buffers
+    ezo.inflate_edges(ctx, rob, obs, edges[:5], params(ezo, "batched", dof, seed=1), out=out)
+    torch.cuda.synchronize()
+    same(out, fresh(1, obs, edges[:5]), 5)
