@@ -328,6 +328,56 @@ ezo_status ezo_set_phase_timing(ezo_ctx *ctx, int32_t enable);
 ezo_status ezo_get_phase_timing(ezo_ctx *ctx, double *ms_out, int64_t *iterations_out, int64_t *tests_out);
 
 /* ---------------------------------------------------------------------------
+ * Recovery from collisions found on a trajectory (Sec. V-B)
+ *
+ * A trajectory through the sets is checked by fine discretisation; the
+ * collisions found inside a set are excluded by repeating the last three
+ * steps of Alg. 1 on them; then every path segment must still lie in some
+ * set (a segment lies in a convex polytope iff both its ends do), else it is
+ * inflated again (ezo_inflate_edges).
+ * ------------------------------------------------------------------------- */
+
+/* Discretises the piecewise-linear path through waypoints (dev [K][dof],
+ * row-major, K >= 1) so that consecutive points differ by at most max_step
+ * in every coordinate -- segment i is cut into m_i = max(1, ceil(max_j
+ * |w_{i+1,j} - w_{i,j}| / max_step)) equal pieces (computed in FP64), points
+ * w_i + (j / m_i)(w_{i+1} - w_i) in FP32, each shared vertex once -- and
+ * checks every point (flags mode).  points_out (dev [point_capacity][dof],
+ * may be NULL when point_capacity = 0) receives the first point_capacity
+ * colliding points in path order; *n_points (host, may be NULL) the number
+ * of path points and *n_colliding (host, may be NULL) the number of
+ * colliding ones.  Synchronises `stream` (the point count sizes the check).
+ * At most 2^28 path points. */
+ezo_status ezo_check_path(ezo_ctx *ctx, const ezo_robot *robot, const float *obs_xyzr, int32_t n_obs,
+                          const float *waypoints, int32_t n_waypoints, double max_step, float *points_out,
+                          int32_t point_capacity, int64_t *n_points, int64_t *n_colliding, void *stream);
+
+/* Edits sets after collisions were found (Sec. V-B).  points (dev
+ * [n_points][dof], row-major) are the found collisions; they are expected to
+ * collide and are not checked again.  For every edge whose status is
+ * CERTIFIED or MAX_ITERS, the points inside its polytope (A x <= b over its
+ * n_faces rows, FP32) are, in point order, the candidates of the last three
+ * steps of Alg. 1: projection onto L with the fail-fast check, n_b bisection
+ * steps, then ordering and placing up to n_f hyperplanes appended to
+ * (A, b, n_faces) (layouts as in ezo_inflate_edges, face_capacity rows per
+ * edge).  An edge whose chosen candidate lies within t_col of L, or whose
+ * candidate's projection collides, becomes EZO_EDGE_IN_COLLISION; every other
+ * status is left as it is.  planes_added (dev [n_edges] or NULL) receives the
+ * planes placed per edge.  n_points <= 64512 per call. */
+ezo_status ezo_update_polytopes(ezo_ctx *ctx, const ezo_robot *robot, const float *obs_xyzr, int32_t n_obs,
+                                const float *edges, int32_t n_edges, const float *points, int32_t n_points,
+                                int32_t n_b, int32_t n_f, double step_back_max, double t_col, float *A, float *b,
+                                int32_t *n_faces, int32_t face_capacity, int32_t *edge_status,
+                                int32_t *planes_added, void *stream);
+
+/* covered[k] (dev [n_segments]) = the smallest set index whose polytope
+ * contains both ends of segment k (segments dev [n_segments][2][dof]):
+ * A v <= b + tol over its n_faces rows (FP32), -1 if no set does. */
+ezo_status ezo_segments_contained(ezo_ctx *ctx, int32_t dof, const float *A, const float *b, const int32_t *n_faces,
+                                  int32_t face_capacity, int32_t n_sets, const float *segments, int32_t n_segments,
+                                  double tol, int32_t *covered, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Launch-shape autotuning
  *
  * The tile kernels (collision check in flags and signed-distance mode;

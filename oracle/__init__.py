@@ -346,3 +346,74 @@ def mlp_loss_grad(D, H, params, x, t, huber_delta=0.05, clip_lo=-0.3, clip_hi=0.
 def mlp_loss(D, H, params, x, t, huber_delta=0.05, clip_lo=-0.3, clip_hi=0.5):
     params, x, t = _d(params), _d(x).reshape(-1, D), _d(t)
     return float(lib().orc_mlp_loss(D, H, _ptr(params), _ptr(x), _ptr(t), len(x), huber_delta, clip_lo, clip_hi))
+
+
+# ---------------------------------------------------------------------------
+# Recovery from collisions found on a trajectory (Sec. V-B)
+# ---------------------------------------------------------------------------
+
+def discretize_path(waypoints, step):
+    """Points along the piecewise-linear path through waypoints [K][d] with
+    consecutive points at most `step` apart in every coordinate (the fine
+    discretisation of a trajectory check, Sec. V-B; step 0.1 rad in Sec. VI):
+    segment i is cut into m_i = max(1, ceil(max_j |w_{i+1,j} - w_{i,j}| / step))
+    equal pieces, points w_i + (j / m_i)(w_{i+1} - w_i), j = 0..m_i, each
+    shared vertex listed once."""
+    w = _d(waypoints).reshape(len(waypoints), -1)
+    pts = [w[0].copy()]
+    for i in range(len(w) - 1):
+        dlt = w[i + 1] - w[i]
+        m = max(1, int(np.ceil(np.max(np.abs(dlt)) / step)))
+        for j in range(1, m + 1):
+            pts.append(w[i] + (j / m) * dlt)
+    return np.array(pts)
+
+
+def check_path(robot: Robot, obs, waypoints, step):
+    """(points, collision flags, min signed distances) of the discretised path."""
+    pts = discretize_path(waypoints, step)
+    flags, sd, *_ = check(robot, obs, pts)
+    return pts, flags, sd
+
+
+def points_in_polytope(A, b, X):
+    """Rows x of X with A x <= b (every row of the polytope)."""
+    A, b, X = _d(A), _d(b), _d(X)
+    if len(b) == 0:
+        return np.ones(len(X), bool)
+    return np.all(X @ A.reshape(len(b), -1).T <= b, axis=1)
+
+
+def covering_set(As, bs, v1, v2, tol=0.0):
+    """Index of the first polytope (A_i, b_i) containing the segment [v1, v2],
+    or -1.  A convex polytope contains a segment iff it contains both ends."""
+    v = np.stack([_d(v1), _d(v2)])
+    for i, (A, b) in enumerate(zip(As, bs)):
+        A, b = _d(A), _d(b)
+        if len(b) == 0 or np.all(v @ A.reshape(len(b), -1).T <= b + tol):
+            return i
+    return -1
+
+
+def recover_set(bisect, v1, v2, A, b, points, n_b, n_f, step_back_max, t_col):
+    """Edit one set after collisions were found on a trajectory (Sec. V-B):
+    the found collisions inside P become the candidates of the last three
+    steps of Alg. 1 -- projection onto L with the fail-fast check, bisection,
+    then ordering and placing up to n_f hyperplanes.  `bisect(v1, v2, c, n_b)`
+    is bisect_arm or bisect_balls bound to a scene.  Returns (A_new, b_new,
+    status, per-candidate bisection results, candidate indices into points)."""
+    A, b = _d(A), _d(b)
+    d = len(_d(v1))
+    A = A.reshape(len(b), d)
+    pts = _d(points).reshape(-1, d)
+    idx = np.nonzero(points_in_polytope(A, b, pts))[0]
+    res = [bisect(v1, v2, pts[i], n_b) for i in idx]
+    if any(r["proj_collides"] for r in res):
+        return A, b, IN_COLLISION, res, idx
+    if len(res) == 0:
+        return A, b, CERTIFIED, res, idx
+    cs = np.array([r["c_star"] for r in res])
+    ad = np.array([r["a"] for r in res])
+    ts = np.array([r["t_star"] for r in res])
+    A2, b2, st, _ = place(v1, v2, cs, ad, ts, n_f, step_back_max, t_col, A, b)
+    return A2, b2, st, res, idx

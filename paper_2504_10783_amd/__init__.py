@@ -30,6 +30,7 @@ EXPORTS = (
     "ezo_surrogate_get_params", "ezo_surrogate_train", "ezo_surrogate_loss_grad", "ezo_surrogate_predict",
     "ezo_surrogate_calibrate", "ezo_surrogate_set_margin", "ezo_surrogate_miss_rate",
     "ezo_set_autotune", "ezo_tune_cache_export", "ezo_tune_cache_import", "ezo_tune_cache_clear",
+    "ezo_check_path", "ezo_update_polytopes", "ezo_segments_contained",
 )
 PHASES = ("sample", "check", "test", "bisect", "place", "advance")
 
@@ -113,6 +114,10 @@ def lib():
         L.ezo_surrogate_calibrate.argtypes = [vp, vp, vp, vp, i64, dbl, C.POINTER(dbl), vp]
         L.ezo_surrogate_set_margin.argtypes = [vp, dbl]
         L.ezo_surrogate_miss_rate.argtypes = [vp, vp, vp, vp, i64, C.POINTER(dbl), C.POINTER(dbl), vp]
+        L.ezo_check_path.argtypes = [vp, vp, vp, i32, vp, i32, dbl, vp, i32, C.POINTER(i64), C.POINTER(i64), vp]
+        L.ezo_update_polytopes.argtypes = [vp, vp, vp, i32, vp, i32, vp, i32, i32, i32, dbl, dbl, vp, vp, vp, i32,
+                                           vp, vp, vp]
+        L.ezo_segments_contained.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp, i32, dbl, vp, vp]
         L.ezo_set_autotune.argtypes = [vp, i32]
         L.ezo_tune_cache_export.argtypes = [C.c_char_p, i64, C.POINTER(i64)]
         L.ezo_tune_cache_import.argtypes = [C.c_char_p, C.POINTER(i32)]
@@ -488,3 +493,53 @@ def inflate_edges(ctx: Context, robot: Robot, obs, edges, params: Params, out=No
                                        _ptr(out.status), st, _stream(stream)))
     out.stats = [{k: getattr(st[e], k) for k, _ in EdgeStats._fields_} for e in range(E)]
     return out
+
+
+# ---------------------------------------------------------------------------
+# Recovery from collisions found on a trajectory (Sec. V-B)
+# ---------------------------------------------------------------------------
+
+def check_path(ctx: Context, robot: Robot, obs, waypoints, max_step, point_capacity=4096, stream=None):
+    """Discretise the path through waypoints [K][dof] (float32 CUDA) at
+    max_step per coordinate and check every point.  Returns (colliding points
+    [min(n, capacity)][dof] in path order, number of colliding points, number
+    of path points)."""
+    torch = _torch()
+    _need(waypoints, torch.float32, "waypoints")
+    _need(obs, torch.float32, "obs")
+    pts = torch.empty((max(point_capacity, 1), robot.dof), dtype=torch.float32, device=waypoints.device)
+    n_pts, n_col = C.c_int64(), C.c_int64()
+    ctx._check(lib().ezo_check_path(ctx.h, robot.h, _ptr(obs), obs.numel() // 4, _ptr(waypoints),
+                                    int(waypoints.shape[0]), float(max_step), _ptr(pts), int(point_capacity),
+                                    C.byref(n_pts), C.byref(n_col), _stream(stream)))
+    return pts[:min(n_col.value, point_capacity)], n_col.value, n_pts.value
+
+
+def update_polytopes(ctx: Context, robot: Robot, obs, edges, points, result, n_b=11, n_f=10, step_back_max=0.01,
+                     t_col=1e-4, stream=None):
+    """Exclude the found collisions `points` [n][dof] from the sets of
+    `result` (an InflateResult for `edges`, edited in place).  Returns the
+    planes added per edge (int32 CUDA tensor)."""
+    torch = _torch()
+    _need(points, torch.float32, "points")
+    _need(edges, torch.float32, "edges")
+    E = edges.shape[0]
+    added = torch.zeros(E, dtype=torch.int32, device=edges.device)
+    ctx._check(lib().ezo_update_polytopes(ctx.h, robot.h, _ptr(obs), obs.numel() // 4, _ptr(edges), int(E),
+                                          _ptr(points), int(points.shape[0]), int(n_b), int(n_f),
+                                          float(step_back_max), float(t_col), _ptr(result.A), _ptr(result.b),
+                                          _ptr(result.n_faces), int(result.b.shape[1]), _ptr(result.status),
+                                          _ptr(added), _stream(stream)))
+    return added
+
+
+def segments_contained(ctx: Context, A, b, n_faces, segments, tol=0.0, stream=None):
+    """covered[k] = smallest set index containing segment k ([K][2][dof]), -1 if none."""
+    torch = _torch()
+    _need(segments, torch.float32, "segments")
+    K, _, dof = segments.shape
+    covered = torch.empty(K, dtype=torch.int32, device=segments.device)
+    ctx._check(lib().ezo_segments_contained(ctx.h, int(dof), _ptr(A), _ptr(b), _ptr(n_faces), int(b.shape[1]),
+                                            int(b.shape[0]), _ptr(segments), int(K), float(tol), _ptr(covered),
+                                            _stream(stream)))
+    return covered

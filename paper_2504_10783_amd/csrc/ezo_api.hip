@@ -329,7 +329,8 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
                                  const float* S, int64_t stride, const int* cand_idx, const int* n_cands,
                                  int cand_cap, int n_b, float* c_star, float* a_dir, float* t_star,
                                  uint8_t* pcol, uint8_t* pany, const int* status, hipStream_t st,
-                                 const TileCfg* shape = nullptr) {
+                                 const TileCfg* shape = nullptr, int64_t s_edge = -1) {
+    if (s_edge < 0) s_edge = (int64_t)r->dof * stride;   // samples [E][dof][stride]
     TileCfg g;
     if (shape) {
         g = *shape;
@@ -347,7 +348,7 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
     if (lds > c->lds_cap) return ezo_fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
     dim3 grid((unsigned)((cand_cap + TC - 1) / TC), (unsigned)E), block(64 * W);
 #define EZO_LAUNCH_PB(TT, DD)                                                                                    \
-    EZO_KLAUNCH(c, (k_project_bisect<TT, DD>), grid, block, lds, st, r->view, ovs, gv, edges, S, stride, cand_idx, \
+    EZO_KLAUNCH(c, (k_project_bisect<TT, DD>), grid, block, lds, st, r->view, ovs, gv, edges, S, stride, s_edge, cand_idx, \
                        n_cands, cand_cap, n_b, c_star, a_dir, t_star, pcol, pany, status)
     if (dp == 1) {
         switch (TC) {
@@ -1123,6 +1124,155 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
     }
     HIP_TRY(c, hipEventRecord(c->ev_out, st));
     HIP_TRY(c, hipStreamWaitEvent(as_stream(stream), c->ev_out, 0));
+    return EZO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Recovery from collisions found on a trajectory (Sec. V-B)
+// ---------------------------------------------------------------------------
+
+ezo_status ezo_check_path(ezo_ctx* c, const ezo_robot* r, const float* obs, int32_t n_obs, const float* waypoints,
+                          int32_t n_waypoints, double max_step, float* points_out, int32_t point_capacity,
+                          int64_t* n_points, int64_t* n_colliding, void* stream) {
+    if (!c) return EZO_E_INVALID;
+    if (!r || n_waypoints < 1 || n_obs < 0 || point_capacity < 0 || !(max_step > 0.0) || !std::isfinite(max_step))
+        return ezo_fail(c, EZO_E_INVALID, "bad argument");
+    if (!waypoints || (n_obs > 0 && !obs) || (point_capacity > 0 && !points_out))
+        return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = as_stream(stream);
+    const int dof = r->dof, K = n_waypoints, nseg = std::max(K - 1, 1);
+    ezo_status s;
+    void *wm, *woff, *wpts, *widx, *wcnt, *wflags;
+    if ((s = ezo_ws_get(c, W_PATH_M, sizeof(int) * nseg, &wm)) ||
+        (s = ezo_ws_get(c, W_PATH_OFF, sizeof(int64_t) * nseg, &woff)))
+        return s;
+    // pieces per segment (device, FP64), offsets on the host
+    std::vector<int> m(nseg, 0);
+    std::vector<int64_t> off(nseg, 0);
+    int64_t N = 1;
+    if (K > 1) {
+        hipLaunchKernelGGL(k_path_pieces, dim3((K - 1 + 255) / 256), dim3(256), 0, st, dof, waypoints, K, max_step,
+                           (int*)wm);
+        HIP_TRY(c, hipGetLastError());
+        HIP_TRY(c, hipMemcpyAsync(m.data(), wm, sizeof(int) * (K - 1), hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+        N = 0;
+        for (int i = 0; i < K - 1; ++i) {
+            off[i] = N;
+            N += (int64_t)m[i] + (i == 0 ? 1 : 0);
+        }
+    }
+    if (N > (1LL << 28)) return ezo_fail(c, EZO_E_UNSUPPORTED, "%lld path points: step too fine", (long long)N);
+    if ((s = ezo_ws_get(c, W_PATH_PTS, sizeof(float) * (size_t)N * dof, &wpts)) ||
+        (s = ezo_ws_get(c, W_PATH_IDX, sizeof(int) * (size_t)std::max(point_capacity, 1), &widx)) ||
+        (s = ezo_ws_get(c, W_PATH_CNT, sizeof(int) * 2, &wcnt)) ||
+        (s = ezo_ws_get(c, W_FLAGS, (size_t)N, &wflags)))
+        return s;
+    if (K > 1) {
+        HIP_TRY(c, hipMemcpyAsync(woff, off.data(), sizeof(int64_t) * (K - 1), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_path_points, dim3(K - 1), dim3(256), 0, st, dof, waypoints, (const int*)wm,
+                           (const int64_t*)woff, (float*)wpts);
+    } else {
+        HIP_TRY(c, hipMemcpyAsync(wpts, waypoints, sizeof(float) * dof, hipMemcpyDeviceToDevice, st));
+    }
+    HIP_TRY(c, hipGetLastError());
+    ObsView ov;
+    GridView gv;
+    if ((s = prep_obstacles(c, r, obs, n_obs, st, &ov, &gv))) return s;
+    IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
+    if ((s = launch_check<false>(c, r, ov, gv, (const float*)wpts, N, dof, 1, 0, (uint8_t*)wflags, nullptr, nullptr,
+                                 0, 1, nullptr, it, st)))
+        return s;
+    // colliding points in path order: the first point_capacity of them, and their count
+    IterArgs sel{nullptr, nullptr, 0, (int)std::min<int64_t>(N, 0x7fffffff), -1, (int)N};
+    int* cnt = (int*)wcnt;
+    hipLaunchKernelGGL(k_test_select, dim3(1), dim3(1024), 0, st, (const uint8_t*)wflags, N,
+                       std::max(point_capacity, 1), 0, (int*)widx, std::max(point_capacity, 1), cnt, nullptr, cnt + 1,
+                       nullptr, nullptr, sel);
+    if (point_capacity > 0)
+        hipLaunchKernelGGL(k_gather_rows, dim3((point_capacity + 255) / 256), dim3(256), 0, st, dof,
+                           (const float*)wpts, (const int*)widx, (const int*)cnt, point_capacity, points_out);
+    HIP_TRY(c, hipGetLastError());
+    int h[2] = {0, 0};
+    HIP_TRY(c, hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (n_points) *n_points = N;
+    if (n_colliding) *n_colliding = h[1];
+    return EZO_OK;
+}
+
+ezo_status ezo_update_polytopes(ezo_ctx* c, const ezo_robot* r, const float* obs, int32_t n_obs, const float* edges,
+                                int32_t n_edges, const float* points, int32_t n_points, int32_t n_b, int32_t n_f,
+                                double step_back_max, double t_col, float* A, float* b, int32_t* n_faces,
+                                int32_t face_capacity, int32_t* edge_status, int32_t* planes_added, void* stream) {
+    if (!c) return EZO_E_INVALID;
+    if (!r || n_edges < 0 || n_points < 0 || n_obs < 0 || n_b < 0 || n_f < 0 || face_capacity < 1 ||
+        !finite_pos(step_back_max) || !std::isfinite(t_col))
+        return ezo_fail(c, EZO_E_INVALID, "bad argument");
+    if (n_edges == 0 || n_points == 0) return EZO_OK;
+    if (!edges || !points || !A || !b || !n_faces || !edge_status || (n_obs > 0 && !obs))
+        return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
+    if ((size_t)n_points > c->lds_cap - 1024)
+        return ezo_fail(c, EZO_E_UNSUPPORTED, "%d points: at most %zu per call", n_points, c->lds_cap - 1024);
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = as_stream(stream);
+    const int dof = r->dof, E = n_edges, N = n_points;
+    ezo_status s;
+    void *w_s, *w_f, *w_ci, *w_nc, *w_cs, *w_ad, *w_ts, *w_pc, *w_pa, *w_run, *w_np;
+    if ((s = ezo_ws_get(c, W_SAMPLES, sizeof(float) * (size_t)dof * N, &w_s)) ||
+        (s = ezo_ws_get(c, W_FLAGS, (size_t)E * N, &w_f)) ||
+        (s = ezo_ws_get(c, W_CAND, sizeof(int) * (size_t)E * N, &w_ci)) ||
+        (s = ezo_ws_get(c, W_NCAND, sizeof(int) * (size_t)E, &w_nc)) ||
+        (s = ezo_ws_get(c, W_CSTAR, sizeof(float) * (size_t)E * dof * N, &w_cs)) ||
+        (s = ezo_ws_get(c, W_ADIR, sizeof(float) * (size_t)E * dof * N, &w_ad)) ||
+        (s = ezo_ws_get(c, W_TSTAR, sizeof(float) * (size_t)E * N, &w_ts)) ||
+        (s = ezo_ws_get(c, W_PCOL, (size_t)E * N, &w_pc)) || (s = ezo_ws_get(c, W_PANY, (size_t)E, &w_pa)) ||
+        (s = ezo_ws_get(c, W_RUN, sizeof(int) * (size_t)E, &w_run)) ||
+        (s = ezo_ws_get(c, W_NPLACED, sizeof(int) * (size_t)E, &w_np)))
+        return s;
+    // found collisions inside each editable set, in point order, become the candidates
+    hipLaunchKernelGGL(k_rows_to_coords, dim3((N + 255) / 256), dim3(256), 0, st, dof, points, (int64_t)N,
+                       (float*)w_s);
+    hipLaunchKernelGGL(k_points_in_sets, dim3((N + 255) / 256, E), dim3(256), 0, st, dof, A, b, n_faces,
+                       face_capacity, edge_status, (const float*)w_s, (int64_t)N, (uint8_t*)w_f);
+    IterArgs sel{nullptr, nullptr, 0, 0, -1, N};
+    hipLaunchKernelGGL(k_test_select, dim3(E), dim3(1024), 0, st, (const uint8_t*)w_f, (int64_t)N, N, n_b,
+                       (int*)w_ci, N, (int*)w_nc, nullptr, nullptr, nullptr, nullptr, sel);
+    hipLaunchKernelGGL(k_recover_begin, dim3((E + 255) / 256), dim3(256), 0, st, E, (const int*)w_nc, (int*)w_run,
+                       (int*)w_np);
+    HIP_TRY(c, hipMemsetAsync(w_pa, 0, (size_t)E, st));
+    HIP_TRY(c, hipGetLastError());
+    ObsView ov;
+    GridView gv;
+    if ((s = prep_obstacles(c, r, obs, n_obs, st, &ov, &gv))) return s;
+    // the last three steps of Alg. 1 on those candidates
+    if ((s = launch_project_bisect(c, r, ov, gv, edges, E, (const float*)w_s, N, (const int*)w_ci, (const int*)w_nc,
+                                   N, n_b, (float*)w_cs, (float*)w_ad, (float*)w_ts, (uint8_t*)w_pc,
+                                   (uint8_t*)w_pa, (const int*)w_run, st, nullptr, 0)))
+        return s;
+    hipLaunchKernelGGL(k_place, dim3(E), dim3(1024), (size_t)std::max(N, 16), st, dof, edges, (const float*)w_cs,
+                       (const float*)w_ad, (const float*)w_ts, (const int*)w_nc, N, n_f, (float)step_back_max,
+                       (float)t_col, A, b, n_faces, face_capacity, (int*)w_run, nullptr, (int*)w_np,
+                       (const uint8_t*)w_pa, nullptr);
+    hipLaunchKernelGGL(k_recover_end, dim3((E + 255) / 256), dim3(256), 0, st, E, (const int*)w_run,
+                       (const int*)w_np, edge_status, planes_added);
+    HIP_TRY(c, hipGetLastError());
+    return EZO_OK;
+}
+
+ezo_status ezo_segments_contained(ezo_ctx* c, int32_t dof, const float* A, const float* b, const int32_t* n_faces,
+                                  int32_t face_capacity, int32_t n_sets, const float* segments, int32_t n_segments,
+                                  double tol, int32_t* covered, void* stream) {
+    if (!c) return EZO_E_INVALID;
+    if (dof < 1 || dof > EZO_MAX_DOF || face_capacity < 1 || n_sets < 0 || n_segments < 0 || !std::isfinite(tol))
+        return ezo_fail(c, EZO_E_INVALID, "bad argument");
+    if (n_segments == 0) return EZO_OK;
+    if (!segments || !covered || (n_sets > 0 && (!A || !b || !n_faces))) return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_segments_contained, dim3(n_segments), dim3(256), 0, as_stream(stream), dof, A, b, n_faces,
+                       face_capacity, n_sets, segments, (float)tol, covered);
+    HIP_TRY(c, hipGetLastError());
     return EZO_OK;
 }
 

@@ -563,7 +563,8 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
 // ---------------------------------------------------------------------------
 // Projection + fail-fast check + N_b bisection steps.  blockIdx.y = edge,
 // blockIdx.x = a group of TC candidates; every check is a whole-workgroup
-// tile check of up to TC (2^DEPTH - 1) configurations.
+// tile check of up to TC (2^DEPTH - 1) configurations.  Candidate j of edge e
+// is sample cand_idx[e][j], coordinate k at S[e s_edge + k stride + idx].
 //
 // The first check is the projections c_proj (fail-fast).  The bisection then
 // runs DEPTH levels per round: a round checks, for every candidate, the
@@ -577,7 +578,7 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
 // ---------------------------------------------------------------------------
 template <int TC, int DEPTH>
 __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView ob, GridView gv, const float* __restrict__ edges,
-                                                         const float* __restrict__ S, int64_t stride,
+                                                         const float* __restrict__ S, int64_t stride, int64_t s_edge,
                                                          const int* __restrict__ cand_idx,
                                                          const int* __restrict__ n_cands, int cand_cap, int n_b,
                                                          float* __restrict__ c_star, float* __restrict__ a_dir,
@@ -606,7 +607,7 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView o
     const float* v = edges + (size_t)e * 2 * dof;
     if (own) {
         const int idx = min(max(cand_idx[(size_t)e * cand_cap + base + tid], 0), (int)(stride - 1));
-        const float* Se = S + (size_t)e * dof * stride;
+        const float* Se = S + (size_t)e * s_edge;
         float num = 0.f, den = 0.f;
 #pragma unroll
         for (int j = 0; j < kMaxDof; ++j) {
@@ -958,6 +959,132 @@ __global__ void __launch_bounds__(256) k_advance(int* __restrict__ k_dev, int ma
         *active_count = cnt;
         *k_dev = k + 1;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Recovery from collisions found on a trajectory (Sec. V-B)
+// ---------------------------------------------------------------------------
+
+// Pieces of segment i of a path through waypoints w [K][dof]:
+// m_i = max(1, ceil(max_j |w_{i+1,j} - w_{i,j}| / step)), in FP64 from the
+// FP32 waypoints (capped at 2^30).
+__global__ void k_path_pieces(int dof, const float* __restrict__ w, int K, double step, int* __restrict__ m) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= K - 1) return;
+    double mx = 0.0;
+    for (int j = 0; j < dof; ++j)
+        mx = fmax(mx, fabs((double)w[(size_t)(i + 1) * dof + j] - (double)w[(size_t)i * dof + j]));
+    const double q = ceil(mx / step);
+    m[i] = q < 1.0 ? 1 : (q > 1073741824.0 ? 1073741824 : (int)q);
+}
+
+// Points of the discretised path, row-major [n][dof]: segment i = blockIdx.x
+// writes points j = 1..m_i (and j = 0 for i = 0), w_i + (j / m_i)(w_{i+1} -
+// w_i) in FP32, from row off[i].
+__global__ void __launch_bounds__(256) k_path_points(int dof, const float* __restrict__ w, const int* __restrict__ m,
+                                                     const int64_t* __restrict__ off, float* __restrict__ pts) {
+    const int i = blockIdx.x;
+    const int mi = m[i];
+    const int j0 = i == 0 ? 0 : 1;
+    const float* a = w + (size_t)i * dof;
+    const float* c = w + (size_t)(i + 1) * dof;
+    for (int jj = threadIdx.x; jj <= mi - j0; jj += blockDim.x) {
+        const int j = j0 + jj;
+        const float t = (float)j / (float)mi;
+        float* out = pts + (size_t)(off[i] + jj) * dof;
+        for (int k = 0; k < dof; ++k) out[k] = fmaf(t, c[k] - a[k], a[k]);
+    }
+}
+
+// out[r] = rows[idx[r]] for r < *n (rows of dof floats).
+__global__ void k_gather_rows(int dof, const float* __restrict__ rows, const int* __restrict__ idx,
+                              const int* __restrict__ n, int cap, float* __restrict__ out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= cap || r >= *n) return;
+    for (int k = 0; k < dof; ++k) out[(size_t)r * dof + k] = rows[(size_t)idx[r] * dof + k];
+}
+
+// Row-major [n][dof] -> coordinate-major [dof][n].
+__global__ void k_rows_to_coords(int dof, const float* __restrict__ rows, int64_t n, float* __restrict__ coords) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < dof; ++k) coords[(size_t)k * n + i] = rows[(size_t)i * dof + k];
+}
+
+// flags[e][i] = 1 iff point i (coordinate-major pts [dof][n]) satisfies every
+// row of polytope e and edge e's status is CERTIFIED or MAX_ITERS (a set
+// that can be edited); blockIdx.y = e.
+__global__ void __launch_bounds__(256) k_points_in_sets(int dof, const float* __restrict__ A,
+                                                        const float* __restrict__ bvec,
+                                                        const int* __restrict__ n_faces, int cap,
+                                                        const int* __restrict__ status, const float* __restrict__ pts,
+                                                        int64_t n, uint8_t* __restrict__ flags) {
+    const int e = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool inside = status[e] == 0 || status[e] == 1;
+    const int F = min(max(n_faces[e], 0), cap);
+    float x[kMaxDof];
+#pragma unroll
+    for (int k = 0; k < kMaxDof; ++k) x[k] = k < dof ? pts[(size_t)k * n + i] : 0.f;
+    const float* Ae = A + (size_t)e * cap * dof;
+    for (int f = 0; f < F && inside; ++f) {
+        float ax = 0.f;
+        for (int k = 0; k < dof; ++k) ax = fmaf(Ae[(size_t)f * dof + k], x[k], ax);
+        inside = ax <= bvec[(size_t)e * cap + f];
+    }
+    flags[(size_t)e * n + i] = inside ? 1 : 0;
+}
+
+// Edges with candidates run the placement (status -1), the rest are skipped.
+__global__ void k_recover_begin(int n_edges, const int* __restrict__ n_cands, int* __restrict__ run,
+                                int* __restrict__ n_placed) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_edges) return;
+    run[e] = n_cands[e] > 0 ? -1 : 0;
+    n_placed[e] = 0;
+}
+
+// A candidate within t_col of L or a colliding projection puts the edge in
+// collision; planes_added[e] = planes placed.
+__global__ void k_recover_end(int n_edges, const int* __restrict__ run, const int* __restrict__ n_placed,
+                              int* __restrict__ status, int* __restrict__ planes_added) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_edges) return;
+    if (run[e] == 2) status[e] = 2;   // EZO_EDGE_IN_COLLISION
+    if (planes_added) planes_added[e] = n_placed[e];
+}
+
+// covered[k] = smallest set index whose polytope contains both ends of
+// segment k (A v <= b + tol), -1 if none; blockIdx.x = k.
+__global__ void __launch_bounds__(256) k_segments_contained(int dof, const float* __restrict__ A,
+                                                            const float* __restrict__ bvec,
+                                                            const int* __restrict__ n_faces, int cap, int n_sets,
+                                                            const float* __restrict__ segs, float tol,
+                                                            int* __restrict__ covered) {
+    __shared__ int best;
+    const int k = blockIdx.x;
+    if (threadIdx.x == 0) best = 0x7fffffff;
+    __syncthreads();
+    const float* v = segs + (size_t)k * 2 * dof;
+    for (int e = threadIdx.x; e < n_sets; e += blockDim.x) {
+        const int F = min(max(n_faces[e], 0), cap);
+        const float* Ae = A + (size_t)e * cap * dof;
+        bool in = true;
+        for (int f = 0; f < F && in; ++f) {
+            float a1 = 0.f, a2 = 0.f;
+            for (int j = 0; j < dof; ++j) {
+                const float a = Ae[(size_t)f * dof + j];
+                a1 = fmaf(a, v[j], a1);
+                a2 = fmaf(a, v[dof + j], a2);
+            }
+            const float bb = bvec[(size_t)e * cap + f] + tol;
+            in = a1 <= bb && a2 <= bb;
+        }
+        if (in) atomicMin(&best, e);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) covered[k] = best == 0x7fffffff ? -1 : best;
 }
 
 }  // namespace ezo

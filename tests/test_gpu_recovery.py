@@ -1,0 +1,213 @@
+"""GPU parity of the recovery calls (Sec. V-B) against the oracle:
+
+* ezo_check_path: the same discretisation (point count exact, points within
+  FP32 rounding) and collision flags identical outside the 1e-5 m band;
+* ezo_update_polytopes: on found collisions whose bisection is decided outside
+  the band, the same candidates, the same placed rows in the same order
+  (a, b within 1e-5) and the same status, with L kept inside every set;
+* ezo_segments_contained: exact against the plain definition.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from workloads import draw
+
+from gpu_common import BAND, f32_up, load, print_case
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ezo():
+    import paper_2504_10783_amd as ezo
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return ezo
+
+
+@pytest.fixture(scope="module")
+def ctx(ezo):
+    return ezo.Context(0)
+
+
+def match_rows(got, ref):
+    """Index into ref of each row of got: rows of got come in path order, so
+    each matches (within 1e-5) the first row of ref after the previous match
+    (a zero-length segment repeats a point)."""
+    idx, j0 = [], 0
+    for g in got:
+        d = np.max(np.abs(ref[j0:] - g), axis=1)
+        hits = np.nonzero(d <= 1e-5)[0]
+        assert len(hits) > 0, d.min()
+        idx.append(j0 + int(hits[0]))
+        j0 = idx[-1] + 1
+    return np.array(idx, int)
+
+
+@pytest.mark.parametrize("name,step,K", [("tiny", 0.02, 7), ("dof7", 0.05, 6)])
+def test_check_path_parity(ezo, ctx, name, step, K):
+    data, desc = load(name)
+    rob = ezo.Robot(ctx, desc)
+    dof = desc["dof"]
+    w = draw.uniform_q(71, K, data["q_lo"], data["q_hi"])
+    w[2] = w[1]                                               # a zero-length segment
+    print_case("check_path", name, K, step)
+    obs = torch.from_numpy(data["obstacles"]).cuda()
+    pts, n_col, n_pts = ezo.check_path(ctx, rob, obs, torch.from_numpy(w).cuda(), step, point_capacity=100000)
+    torch.cuda.synchronize()
+    ref_pts = oracle.discretize_path(f32_up(w), step)
+    fo, sdo, *_ = oracle.check(oracle.Robot(desc), f32_up(data["obstacles"]), ref_pts)
+    print(f"{n_pts} points, {n_col} colliding (oracle {int(fo.sum())})")
+    assert n_pts == len(ref_pts)
+    assert len(pts) == n_col
+    got = pts.cpu().numpy().astype(np.float64)
+    idx = match_rows(got, ref_pts)
+    gflag = np.zeros(len(ref_pts), bool)
+    gflag[idx] = True
+    decided = np.abs(sdo) >= BAND
+    assert np.array_equal(gflag[decided], fo.astype(bool)[decided])
+    assert 0 < n_col < n_pts
+    # a smaller capacity returns the first colliding points and the full count
+    cap = max(1, n_col // 3)
+    pts2, n_col2, _ = ezo.check_path(ctx, rob, obs, torch.from_numpy(w).cuda(), step, point_capacity=cap)
+    torch.cuda.synchronize()
+    assert n_col2 == n_col and len(pts2) == cap
+    assert torch.equal(pts2, pts[:cap])
+
+
+def decided_collisions(desc, data, A, b, v1, v2, n, seed, n_b=11):
+    """Colliding configurations inside P (hit-and-run samples of P) whose
+    membership, projection check and every bisection decision lie outside the
+    band (so FP32 and FP64 agree)."""
+    orob = oracle.Robot(desc)
+    obs = f32_up(data["obstacles"])
+    q = oracle.hit_and_run(A, b, v1, v2, 30, seed, 0, 1, 4000).astype(np.float32)
+    qd = f32_up(q)
+    f, sd, *_ = oracle.check(orob, obs, qd)
+    slack = qd @ A.T - b
+    keep = (f.astype(bool)) & (sd <= -BAND) & np.all(slack <= -1e-4, axis=1)
+    out = []
+    for x in q[keep]:
+        r = oracle.bisect_arm(orob, obs, v1, v2, f32_up(x), n_b)
+        if np.all(np.abs(r["sd_trace"]) >= BAND) and not r["proj_collides"]:
+            out.append(x)
+        if len(out) == n:
+            break
+    return np.array(out, np.float32)
+
+
+@pytest.mark.parametrize("name,n", [("tiny", 40), ("dof7", 120)])
+def test_update_polytopes_parity(ezo, ctx, name, n):
+    data, desc = load(name)
+    rob = ezo.Robot(ctx, desc)
+    dof = desc["dof"]
+    obs = torch.from_numpy(data["obstacles"]).cuda()
+    edges = torch.from_numpy(data["edges"][:1]).cuda()
+    # room for the edited set's new rows beyond those of the inflation
+    prm = ezo.make_params(dof=dof, seed=2, face_capacity=2 * dof + 40, **dict(workloads.PARAMS[name], max_iters=1))
+    res = ezo.inflate_edges(ctx, rob, obs, edges, prm)
+    torch.cuda.synchronize()
+    F0 = int(res.n_faces[0].item())
+    A0 = res.A[0, :F0].cpu().numpy().astype(np.float64)
+    b0 = res.b[0, :F0].cpu().numpy().astype(np.float64)
+    v1, v2 = f32_up(data["edges"][0])
+    pts = decided_collisions(desc, data, A0, b0, v1, v2, n, seed=81)
+    print_case("update_polytopes", name, len(pts))
+    assert len(pts) >= 5
+    # plus points outside the set, which must be ignored
+    far = np.tile(np.asarray(data["q_hi"], np.float32) * 2.0, (3, 1))
+    allp = np.concatenate([pts, far]).astype(np.float32)
+    before_A = res.A.clone()
+    status0 = int(res.status[0].item())
+    added = ezo.update_polytopes(ctx, rob, obs, edges, torch.from_numpy(allp).cuda(), res, n_b=11, n_f=10,
+                                 step_back_max=workloads.PARAMS[name]["step_back_max"],
+                                 t_col=workloads.PARAMS[name]["t_col"])
+    torch.cuda.synchronize()
+    F1 = int(res.n_faces[0].item())
+    assert F1 == F0 + int(added[0].item()) and F1 > F0
+    assert torch.equal(res.A[0, :F0], before_A[0, :F0])               # existing rows untouched
+    bis = lambda a, b_, c, nb: oracle.bisect_arm(oracle.Robot(desc), f32_up(data["obstacles"]), a, b_, c, nb)
+    A2, b2, st, _, idx = oracle.recover_set(bis, v1, v2, A0, b0, f32_up(allp), 11, 10,
+                                            workloads.PARAMS[name]["step_back_max"], workloads.PARAMS[name]["t_col"])
+    assert len(idx) == len(pts)
+    assert int(res.status[0].item()) == (ezo.IN_COLLISION if st == oracle.IN_COLLISION else status0)
+    assert F1 == len(b2)
+    gA = res.A[0, F0:F1].cpu().numpy().astype(np.float64)
+    gb = res.b[0, F0:F1].cpu().numpy().astype(np.float64)
+    assert np.abs(gA - A2[F0:]).max() <= 1e-5 and np.abs(gb - b2[F0:]).max() <= 1e-5
+    A1 = res.A[0, :F1].cpu().numpy().astype(np.float64)
+    b1 = res.b[0, :F1].cpu().numpy().astype(np.float64)
+    for v in (v1, v2):
+        assert np.all(A1 @ v <= b1 + 1e-5)                            # L stays inside
+
+
+def test_segments_contained_exact(ezo, ctx):
+    rng = np.random.default_rng(5)
+    dof, n_sets, cap, K = 4, 9, 12, 300
+    A = np.zeros((n_sets, cap, dof), np.float32)
+    b = np.zeros((n_sets, cap), np.float32)
+    nf = np.zeros(n_sets, np.int32)
+    for e in range(n_sets):
+        F = int(rng.integers(2 * dof, cap + 1))
+        a = rng.normal(size=(F, dof))
+        a /= np.linalg.norm(a, axis=1, keepdims=True)
+        A[e, :F] = a
+        b[e, :F] = rng.uniform(0.3, 1.0, size=F)
+        nf[e] = F
+    seg = (rng.normal(size=(K, 2, dof)) * 0.35).astype(np.float32)
+    print_case("segments_contained", K)
+    cov = ezo.segments_contained(ctx, torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda(),
+                                 torch.from_numpy(nf).cuda(), torch.from_numpy(seg).cuda())
+    torch.cuda.synchronize()
+    cov = cov.cpu().numpy()
+    ref = np.array([oracle.covering_set([f32_up(A[e, :nf[e]]) for e in range(n_sets)],
+                                        [f32_up(b[e, :nf[e]]) for e in range(n_sets)],
+                                        f32_up(seg[k, 0]), f32_up(seg[k, 1])) for k in range(K)])
+    # exact wherever no endpoint lies within 1e-5 of a face of a set
+    near = np.zeros(K, bool)
+    for e in range(n_sets):
+        s = np.abs(f32_up(seg).reshape(-1, dof) @ f32_up(A[e, :nf[e]]).T - f32_up(b[e, :nf[e]])).reshape(K, 2, -1)
+        near |= (s < 1e-5).any(axis=(1, 2))
+    print(f"covered {np.mean(ref >= 0):.2f} of segments; {near.sum()} near a face")
+    assert np.array_equal(cov[~near], ref[~near])
+    assert 0.1 < np.mean(ref >= 0) < 0.95
+
+
+def test_recovery_round_trip(ezo, ctx):
+    """Inflate, route a trajectory through collisions inside the set, find
+    them by the path check, edit the set: the found points leave the set, L
+    stays inside and the segment is still covered."""
+    data, desc = load("dof7")
+    rob = ezo.Robot(ctx, desc)
+    dof = desc["dof"]
+    obs = torch.from_numpy(data["obstacles"]).cuda()
+    edges = torch.from_numpy(data["edges"][:1]).cuda()
+    p = dict(workloads.PARAMS["dof7"], max_iters=1)            # an early, loose set
+    res = ezo.inflate_edges(ctx, rob, obs, edges, ezo.make_params(dof=dof, seed=3, face_capacity=400, **p))
+    torch.cuda.synchronize()
+    F0 = int(res.n_faces[0].item())
+    A0 = res.A[0, :F0].cpu().numpy().astype(np.float64)
+    b0 = res.b[0, :F0].cpu().numpy().astype(np.float64)
+    v1, v2 = f32_up(data["edges"][0])
+    cols = decided_collisions(desc, data, A0, b0, v1, v2, 2, seed=91)
+    assert len(cols) == 2
+    way = np.stack([data["edges"][0][0], cols[0], cols[1], data["edges"][0][1]]).astype(np.float32)
+    print_case("recovery round trip")
+    found, n_col, n_pts = ezo.check_path(ctx, rob, obs, torch.from_numpy(way).cuda(), 0.05, point_capacity=4096)
+    assert n_col > 0
+    added = ezo.update_polytopes(ctx, rob, obs, edges, found, res, n_b=11, n_f=200)
+    torch.cuda.synchronize()
+    assert int(added[0].item()) > 0
+    F1 = int(res.n_faces[0].item())
+    A1 = res.A[0, :F1].cpu().numpy().astype(np.float64)
+    b1 = res.b[0, :F1].cpu().numpy().astype(np.float64)
+    for v in (v1, v2):
+        assert np.all(A1 @ v <= b1 + 1e-5)
+    inside = oracle.points_in_polytope(A1, b1, found.cpu().numpy().astype(np.float64))
+    print(f"{n_col} found collisions, {int(added[0].item())} planes, {int(inside.sum())} still inside")
+    assert inside.mean() <= 0.5
+    cov = ezo.segments_contained(ctx, res.A, res.b, res.n_faces, edges)
+    torch.cuda.synchronize()
+    assert int(cov[0].item()) == 0
