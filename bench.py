@@ -233,6 +233,113 @@ def screen_compare(args):
     print(json.dumps(line), flush=True)
 
 
+def recovery(args):
+    """Recovery from collisions found on a trajectory (Sec. V-B) on the
+    batched workload: the 96 edges inflated for two iterations (loose sets
+    that still hold collisions), a trajectory through 8 hit-and-run samples
+    of each set in path order, then the three recovery calls timed apart:
+    the fine path check (0.01 rad per coordinate), the set update from the
+    found collisions, and the containment of the trajectory's segments."""
+    import numpy as np
+    import torch
+
+    import paper_2504_10783_amd as ezo
+    import workloads
+
+    name = "batched"
+    data = workloads.load(name)
+    desc = workloads.robot(data)
+    ctx = ezo.Context(0)
+    rob = ezo.Robot(ctx, desc)
+    dev = torch.device("cuda", 0)
+    obs = torch.from_numpy(data["obstacles"]).to(dev)
+    edges = torch.from_numpy(data["edges"]).to(dev)
+    E, dof = edges.shape[0], rob.dof
+    p = dict(workloads.PARAMS[name], max_iters=2)
+    n_f_rec, n_b, per_edge, step = 10, 11, 8, 0.01
+    cap = 2 * dof + p["n_f"] * p["max_iters"] + 256
+    res0 = ezo.inflate_edges(ctx, rob, obs, edges, ezo.make_params(dof=dof, seed=args.seed, face_capacity=cap, **p))
+    smp = torch.empty((E, dof, per_edge), dtype=torch.float32, device=dev)
+    ezo.sample_polytopes(ctx, dof, res0.A, res0.b, res0.n_faces, edges, per_edge, p["n_mix"], args.seed + 7, 0, smp)
+    way = torch.cat([edges[:, :1, :], smp.transpose(1, 2), edges[:, 1:, :]], dim=1).reshape(-1, dof).contiguous()
+    segs = torch.stack([way[:-1], way[1:]], dim=1).contiguous()
+    keep = torch.ones(segs.shape[0], dtype=torch.bool, device=dev)
+    keep[per_edge + 1::per_edge + 2] = False          # the jumps from one edge's v2 to the next edge's v1
+    segs = segs[keep].contiguous()
+    work = ezo.InflateResult(res0.A.clone(), res0.b.clone(), res0.n_faces.clone(), res0.status.clone(), [])
+    torch.cuda.synchronize()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    found = {}
+
+    def run_check():
+        found["pts"], found["n_col"], found["n_pts"] = ezo.check_path(ctx, rob, obs, way, step,
+                                                                      point_capacity=1 << 16)
+
+    dt_check = timed(run_check, args.steps)
+    pts = found["pts"]
+
+    def restore():
+        work.A.copy_(res0.A)
+        work.b.copy_(res0.b)
+        work.n_faces.copy_(res0.n_faces)
+        work.status.copy_(res0.status)
+
+    # the update edits the sets in place: restore them before every call and
+    # time the update alone with events on the stream it runs on
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    upd_ms = []
+    for r in range(args.steps + 1):
+        restore()
+        ev[0].record()
+        added = ezo.update_polytopes(ctx, rob, obs, edges, pts, work, n_b=n_b, n_f=n_f_rec,
+                                     step_back_max=p["step_back_max"], t_col=p["t_col"])
+        ev[1].record()
+        torch.cuda.synchronize()
+        if r:
+            upd_ms.append(ev[0].elapsed_time(ev[1]))
+    cov_before = ezo.segments_contained(ctx, res0.A, res0.b, res0.n_faces, segs)
+    dt_cont = timed(lambda: ezo.segments_contained(ctx, work.A, work.b, work.n_faces, segs), args.steps)
+    cov_after = ezo.segments_contained(ctx, work.A, work.b, work.n_faces, segs)
+    # found collisions still inside some edited set (should be few: the new
+    # rows exclude each found point from the set that held it)
+    n_keep = pts.shape[0]
+    inside = 0
+    if n_keep:
+        A, b, nf = work.A.cpu().numpy(), work.b.cpu().numpy(), work.n_faces.cpu().numpy()
+        P = pts.cpu().numpy()
+        for e in range(E):
+            s_ = P @ A[e, :nf[e]].T - b[e, :nf[e]]
+            inside += int(np.sum(np.all(s_ <= 0.0, axis=1)))
+    st = work.status.cpu().numpy()
+    line = {"metric": "recovery (Sec. V-B): trajectory configurations checked/sec",
+            "value": found["n_pts"] / dt_check, "unit": "configs/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"recovery on {name}: {E} sets after {p['max_iters']} iterations, trajectory "
+                                   f"through {per_edge} hit-and-run samples per set, step {step} rad; "
+                                   f"update N_b={n_b}, N_f={n_f_rec}", "waypoints": int(way.shape[0]),
+                       "segments": int(segs.shape[0]), "n_obstacles": int(obs.shape[0])},
+            "path_points": found["n_pts"], "path_check_ms": dt_check * 1e3, "found_collisions": found["n_col"],
+            "update_ms": float(np.mean(upd_ms)), "update_ms_min": float(np.min(upd_ms)),
+            "planes_added": int(added.sum().item()),
+            "edges_edited": int((added > 0).sum().item()),
+            "edges_in_collision_after": int(np.sum(st == 2)),
+            "found_still_inside_a_set": inside,
+            "containment_ms": dt_cont * 1e3, "segments_per_s": segs.shape[0] / dt_cont,
+            "segments_covered_before": int((cov_before >= 0).sum().item()),
+            "segments_covered_after": int((cov_after >= 0).sum().item())}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +351,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--screen", action="store_true", help="learned screen vs exact comparison")
     ap.add_argument("--screen-epochs", type=int, default=10)
+    ap.add_argument("--recovery", action="store_true", help="trajectory check + set update + containment timings")
     ap.add_argument("--no-autotune", action="store_true", help="size-heuristic launch shapes (no tuning)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
@@ -263,6 +371,9 @@ def main():
         return
     if args.screen:
         screen_compare(args)
+        return
+    if args.recovery:
+        recovery(args)
         return
 
     import numpy as np
