@@ -63,7 +63,9 @@ enum {
     EZO_EDGE_MAX_ITERS = 1,    /* max_iters rounds without acceptance; P uncertified  */
     EZO_EDGE_IN_COLLISION = 2, /* a candidate within t_col of L, or a projection onto
                                   L in collision: L is likely in collision            */
-    EZO_EDGE_INVALID = 3       /* a vertex outside D or not finite; P = D             */
+    EZO_EDGE_INVALID = 3,      /* a vertex outside D or not finite; P = D             */
+    EZO_EDGE_CONTAINED = 4     /* not inflated: L lies in the set of an earlier edge
+                                  of its path (ezo_inflate_paths); no rows            */
 };
 
 /* Serial arm with standard Denavit-Hartenberg links,
@@ -134,6 +136,8 @@ const char *ezo_last_error(const ezo_ctx *ctx);
 /* Uploads a robot (copied and rounded to FP32).  EZO_E_UNSUPPORTED beyond
  * the limits; EZO_E_INVALID for out-of-range link or sphere indices. */
 ezo_status ezo_robot_create(ezo_ctx *ctx, const ezo_robot_desc *desc, ezo_robot **out);
+/* Frees the robot; it may run before or after ezo_ctx_destroy of its
+ * context (it reads only the robot), but not while a call uses the robot. */
 void ezo_robot_destroy(ezo_robot *robot);
 
 /* ---- collision checking (Sec. IV-D: PointsInCollision of Alg. 1) -------- */
@@ -247,6 +251,33 @@ ezo_status ezo_inflate_edges(ezo_ctx *ctx, const ezo_robot *robot, const float *
                              float *b, int32_t *n_faces, int32_t *edge_status, ezo_edge_stats *stats,
                              void *stream);
 
+/* ---- piecewise-linear paths in sequence (Sec. V-A) ---------------------- */
+
+/* Inflates n_paths paths, each in sequence with the containment skip: edge k
+ * of a path is inflated only if its segment L_k is not contained in the set
+ * of an earlier edge of the same path (both ends satisfy every row of that
+ * set, FP32), where only sets of edges that were inflated and ended
+ * CERTIFIED or MAX_ITERS count.  Paths are independent of one another; round
+ * k inflates edge k of every path still running in one batched pass.
+ *
+ * vertices dev f32 [sum_p path_vertices[p]][dof], the paths' vertices back
+ * to back; path_vertices host i32 [n_paths], each >= 2.  Edges are numbered
+ * path by path (path p's edge k has global index g = sum_{q<p}
+ * (path_vertices[q] - 1) + k) and every output is indexed by g: A dev f32
+ * [n_edges][face_capacity][dof], b [n_edges][face_capacity], n_faces and
+ * edge_status dev i32 [n_edges], covered_by dev i32 [n_edges] (-1 for an
+ * inflated edge, else the first earlier edge whose set contains it; that
+ * edge's status is EZO_EDGE_CONTAINED and n_faces 0), stats host [n_edges]
+ * (may be NULL; zero for a contained edge).  Edge g draws the random stream
+ * of edge id params->edge_id_base + g, so an inflated edge's set equals the
+ * one ezo_inflate_edges gives for it with the same parameters.  Errors as in
+ * ezo_inflate_edges, EZO_E_INVALID for a path with fewer than 2 vertices.
+ * Blocks until the stream has finished the call. */
+ezo_status ezo_inflate_paths(ezo_ctx *ctx, const ezo_robot *robot, const float *obs, int32_t n_obs,
+                             const float *vertices, const int32_t *path_vertices, int32_t n_paths,
+                             const ezo_params *params, float *A, float *b, int32_t *n_faces,
+                             int32_t *edge_status, int32_t *covered_by, ezo_edge_stats *stats, void *stream);
+
 /* ---- learned self-collision screen ------------------------------------ */
 /* A multilayer perceptron dof -> H -> H -> H -> 1 with SiLU activations
  * predicting a configuration's minimum self-collision signed distance from
@@ -272,6 +303,7 @@ int64_t ezo_surrogate_num_params(int32_t dof, int32_t hidden);
 /* hidden: multiple of 64 in [64, 4096].  Weights ~ U(+-1/sqrt(fan_in)) from seed;
  * margin = +inf (screens nothing) until calibrated. */
 ezo_status ezo_surrogate_create(ezo_ctx *ctx, int32_t dof, int32_t hidden, uint64_t seed, ezo_surrogate **out);
+/* Frees the screen; like ezo_robot_destroy it may outlive its context. */
 void ezo_surrogate_destroy(ezo_surrogate *s);
 /* host [n] parameter copies (n = ezo_surrogate_num_params); set resets Adam. */
 ezo_status ezo_surrogate_set_params(ezo_surrogate *s, const float *params, int64_t n);
@@ -372,7 +404,9 @@ ezo_status ezo_update_polytopes(ezo_ctx *ctx, const ezo_robot *robot, const floa
 
 /* covered[k] (dev [n_segments]) = the smallest set index whose polytope
  * contains both ends of segment k (segments dev [n_segments][2][dof]):
- * A v <= b + tol over its n_faces rows (FP32), -1 if no set does. */
+ * A v <= b + tol over its n_faces rows (FP32), -1 if no set does.  A set
+ * with n_faces = 0 (an edge that holds no set, EZO_EDGE_CONTAINED) contains
+ * nothing. */
 ezo_status ezo_segments_contained(ezo_ctx *ctx, int32_t dof, const float *A, const float *b, const int32_t *n_faces,
                                   int32_t face_capacity, int32_t n_sets, const float *segments, int32_t n_segments,
                                   double tol, int32_t *covered, void *stream);

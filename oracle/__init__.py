@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = [os.path.join(_HERE, "ezo_oracle.c"), os.path.join(_HERE, "mlp_oracle.c")]
 _SO = os.path.join(_HERE, "libezo_oracle.so")
 
-CERTIFIED, MAX_ITERS, IN_COLLISION, INVALID = 0, 1, 2, 3
+CERTIFIED, MAX_ITERS, IN_COLLISION, INVALID, CONTAINED = 0, 1, 2, 3, 4
 
 
 def build(force: bool = True) -> str:
@@ -386,13 +386,38 @@ def points_in_polytope(A, b, X):
 
 def covering_set(As, bs, v1, v2, tol=0.0):
     """Index of the first polytope (A_i, b_i) containing the segment [v1, v2],
-    or -1.  A convex polytope contains a segment iff it contains both ends."""
+    or -1.  A convex polytope contains a segment iff it contains both ends.
+    A set given by no rows stands for an edge that holds no set (one skipped
+    by the path inflation) and contains nothing."""
     v = np.stack([_d(v1), _d(v2)])
     for i, (A, b) in enumerate(zip(As, bs)):
         A, b = _d(A), _d(b)
-        if len(b) == 0 or np.all(v @ A.reshape(len(b), -1).T <= b + tol):
+        if len(b) > 0 and np.all(v @ A.reshape(len(b), -1).T <= b + tol):
             return i
     return -1
+
+
+def inflate_path(inflate, vertices):
+    """Inflation of one piecewise-linear path in sequence with the containment
+    skip (Sec. V-A).  Edge k runs from vertex k to vertex k + 1; it is inflated
+    only if no set of an earlier edge of the path contains its segment, where
+    the sets that count are those of edges that were inflated and ended
+    CERTIFIED or MAX_ITERS; covered_by records the first (lowest k) set that
+    does.  `inflate(k, v1, v2)` inflates edge k and returns a dict with
+    status, A, b.  Returns one dict per edge: status, A, b, covered_by (-1 if
+    inflated; a contained edge has status CONTAINED and no rows)."""
+    V = _d(vertices)
+    V = V.reshape(len(V), -1)
+    out = []
+    for k in range(len(V) - 1):
+        usable = [j for j in range(k) if out[j]["covered_by"] == -1 and out[j]["status"] in (CERTIFIED, MAX_ITERS)]
+        c = covering_set([out[j]["A"] for j in usable], [out[j]["b"] for j in usable], V[k], V[k + 1])
+        if c >= 0:
+            out.append(dict(status=CONTAINED, A=np.zeros((0, V.shape[1])), b=np.zeros(0), covered_by=usable[c]))
+        else:
+            r = inflate(k, V[k], V[k + 1])
+            out.append(dict(status=r["status"], A=r["A"], b=r["b"], covered_by=-1))
+    return out
 
 
 def recover_set(bisect, v1, v2, A, b, points, n_b, n_f, step_back_max, t_col):

@@ -18,13 +18,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libezo.so")
 
 EZO_OK, EZO_E_INVALID, EZO_E_HIP, EZO_E_CAPACITY, EZO_E_NOMEM, EZO_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-CERTIFIED, MAX_ITERS, IN_COLLISION, INVALID = 0, 1, 2, 3
+CERTIFIED, MAX_ITERS, IN_COLLISION, INVALID, CONTAINED = 0, 1, 2, 3, 4
 MAX_DOF = 8
 
 EXPORTS = (
     "ezo_ctx_create", "ezo_ctx_destroy", "ezo_last_error", "ezo_robot_create", "ezo_robot_destroy",
     "ezo_check_collisions", "ezo_sphere_centres", "ezo_test_constants", "ezo_sample_polytopes",
-    "ezo_test_and_select", "ezo_project_bisect", "ezo_place_hyperplanes", "ezo_inflate_edges",
+    "ezo_test_and_select", "ezo_project_bisect", "ezo_place_hyperplanes", "ezo_inflate_edges", "ezo_inflate_paths",
     "ezo_set_phase_timing", "ezo_get_phase_timing",
     "ezo_surrogate_num_params", "ezo_surrogate_create", "ezo_surrogate_destroy", "ezo_surrogate_set_params",
     "ezo_surrogate_get_params", "ezo_surrogate_train", "ezo_surrogate_loss_grad", "ezo_surrogate_predict",
@@ -98,6 +98,8 @@ def lib():
                                             vp, vp, vp, vp]
         L.ezo_inflate_edges.argtypes = [vp, vp, vp, i32, vp, i32, C.POINTER(Params), vp, vp, vp, vp,
                                         C.POINTER(EdgeStats), vp]
+        L.ezo_inflate_paths.argtypes = [vp, vp, vp, i32, vp, C.POINTER(i32), i32, C.POINTER(Params), vp, vp, vp,
+                                        vp, vp, C.POINTER(EdgeStats), vp]
         L.ezo_set_phase_timing.argtypes = [vp, i32]
         L.ezo_get_phase_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(i64)]
         tp = C.POINTER(TrainParams)
@@ -491,6 +493,43 @@ def inflate_edges(ctx: Context, robot: Robot, obs, edges, params: Params, out=No
     ctx._check(lib().ezo_inflate_edges(ctx.h, robot.h, _ptr(obs), obs.numel() // 4, _ptr(edges), int(E),
                                        C.byref(params), _ptr(out.A), _ptr(out.b), _ptr(out.n_faces),
                                        _ptr(out.status), st, _stream(stream)))
+    out.stats = [{k: getattr(st[e], k) for k, _ in EdgeStats._fields_} for e in range(E)]
+    return out
+
+
+class PathsResult(InflateResult):
+    """InflateResult over the paths' edges (numbered path by path) plus
+    covered_by: -1 for an inflated edge, else the earlier edge whose set
+    contains it."""
+
+    def __init__(self, A, b, n_faces, status, stats, covered_by):
+        super().__init__(A, b, n_faces, status, stats)
+        self.covered_by = covered_by
+
+
+def inflate_paths(ctx: Context, robot: Robot, obs, vertices, path_vertices, params: Params, stream=None) -> PathsResult:
+    """Sequential inflation of piecewise-linear paths with the containment
+    skip (Sec. V-A).  vertices: float32 CUDA tensor [sum(path_vertices)][dof]
+    (the paths back to back); path_vertices: vertex count of each path (>= 2)."""
+    torch = _torch()
+    _need(vertices, torch.float32, "vertices")
+    _need(obs, torch.float32, "obs")
+    counts = [int(x) for x in path_vertices]
+    if sum(counts) != vertices.shape[0]:
+        raise ValueError("path_vertices must sum to the number of vertices")
+    E = sum(counts) - len(counts)
+    cap = params.face_capacity
+    dev = vertices.device
+    out = PathsResult(torch.empty((E, cap, robot.dof), dtype=torch.float32, device=dev),
+                      torch.empty((E, cap), dtype=torch.float32, device=dev),
+                      torch.empty(E, dtype=torch.int32, device=dev),
+                      torch.empty(E, dtype=torch.int32, device=dev), [],
+                      torch.empty(E, dtype=torch.int32, device=dev))
+    pv = (C.c_int32 * max(len(counts), 1))(*counts)
+    st = (EdgeStats * max(E, 1))()
+    ctx._check(lib().ezo_inflate_paths(ctx.h, robot.h, _ptr(obs), obs.numel() // 4, _ptr(vertices), pv,
+                                       len(counts), C.byref(params), _ptr(out.A), _ptr(out.b), _ptr(out.n_faces),
+                                       _ptr(out.status), _ptr(out.covered_by), st, _stream(stream)))
     out.stats = [{k: getattr(st[e], k) for k, _ in EdgeStats._fields_} for e in range(E)]
     return out
 

@@ -267,7 +267,8 @@ constexpr int64_t kSampleWalks4 = 400000;
 ezo_status launch_sample(ezo_ctx* c, int dof, const float* A, const float* b, const int* n_faces, int cap,
                          const float* edges, int E, int max_samples, int n_mix, uint64_t seed, int64_t eid0,
                          float* S, int64_t stride, const int* status, const IterArgs& it, hipStream_t st,
-                         const TileCfg* shape = nullptr, const int* active = nullptr) {
+                         const TileCfg* shape = nullptr, const int* active = nullptr,
+                         const int* edge_ids = nullptr) {
     const int D = dof <= 4 ? 4 : 8;
     if (sample_smem_bytes(D, 16, cap, 256) > c->lds_cap)
         return ezo_fail(c, EZO_E_UNSUPPORTED, "face capacity %d too large for the sampler", cap);
@@ -278,10 +279,10 @@ ezo_status launch_sample(ezo_ctx* c, int dof, const float* A, const float* b, co
         dim3 grid((unsigned)(((int64_t)max_samples * 16 + 255) / 256), (unsigned)E), block(256);
         if (D == 4)
             EZO_KLAUNCH(c, k_sample_auto<4>, grid, block, lds, st, dof, A, b, n_faces, cap, edges, key0, key1, eid0,
-                        n_mix, S, stride, status, it, active, kSampleWalks16, kSampleWalks4);
+                        n_mix, S, stride, status, it, active, kSampleWalks16, kSampleWalks4, edge_ids);
         else
             EZO_KLAUNCH(c, k_sample_auto<8>, grid, block, lds, st, dof, A, b, n_faces, cap, edges, key0, key1, eid0,
-                        n_mix, S, stride, status, it, active, kSampleWalks16, kSampleWalks4);
+                        n_mix, S, stride, status, it, active, kSampleWalks16, kSampleWalks4, edge_ids);
         HIP_TRY(c, hipGetLastError());
         return EZO_OK;
     }
@@ -538,6 +539,7 @@ void ezo_ctx_destroy(ezo_ctx* c) {
     if (c->d_tests) e = hipFree(c->d_tests);
     if (c->stream) e = hipStreamDestroy(c->stream);
     (void)e;
+    (void)hipGetLastError();
     delete c;
 }
 
@@ -659,6 +661,7 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     }
     ezo_robot* r = new ezo_robot();
     r->ctx = c;
+    r->device = c->device;
     r->dof = dof;
     r->S = S;
     r->P = P;
@@ -684,9 +687,10 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
 
 void ezo_robot_destroy(ezo_robot* r) {
     if (!r) return;
-    hipError_t e = hipSetDevice(r->ctx->device);
+    hipError_t e = hipSetDevice(r->device);
     if (r->buf) e = hipFree(r->buf);
     (void)e;
+    (void)hipGetLastError();                 // leave no error behind for the caller's next check
     delete r;
 }
 
@@ -844,9 +848,16 @@ ezo_status ezo_place_hyperplanes(ezo_ctx* c, int32_t dof, const float* edges, in
     return EZO_OK;
 }
 
-ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, int32_t n_obs, const float* edges,
-                             int32_t n_edges, const ezo_params* p, float* A, float* b, int32_t* n_faces,
-                             int32_t* edge_status, ezo_edge_stats* stats, void* stream) {
+}  // extern "C"
+
+// The fused inflation of E edges.  edge_ids (device, optional): edge e draws
+// the random stream of edge id edge_id_base + edge_ids[e] instead of
+// edge_id_base + e.  skip (device, optional): edges with skip[e] != 0 are not
+// inflated (status CONTAINED, no rows).
+static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs, int32_t n_obs, const float* edges,
+                               int32_t n_edges, const ezo_params* p, float* A, float* b, int32_t* n_faces,
+                               int32_t* edge_status, ezo_edge_stats* stats, void* stream, const int* edge_ids,
+                               const uint8_t* skip) {
     if (!c) return EZO_E_INVALID;
     if (!r || !p) return ezo_fail(c, EZO_E_INVALID, "NULL robot or params");
     if (n_edges < 0 || n_obs < 0) return ezo_fail(c, EZO_E_INVALID, "negative size");
@@ -921,7 +932,7 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
                             (const int*)w_ac, st)))
         return s;
     hipLaunchKernelGGL(k_init_edges, dim3((E + 63) / 64), dim3(64), 0, st, dof, r->q_lo, r->q_hi, edges, E, A, b,
-                       n_faces, cap, edge_status, (EdgeStatsDev*)w_st, (uint8_t*)w_pa, (int*)w_k, (int*)w_ac);
+                       n_faces, cap, edge_status, (EdgeStatsDev*)w_st, (uint8_t*)w_pa, (int*)w_k, (int*)w_ac, skip);
     HIP_TRY(c, hipGetLastError());
     IterArgs it{(const int*)w_k, (const int4*)w_tb, 0, 0, 0, 0};
     const uint32_t k0 = (uint32_t)p->seed, k1 = (uint32_t)(p->seed >> 32);
@@ -943,7 +954,7 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
         };
         mark(EZO_PHASE_SAMPLE);
         if ((ls = launch_sample(c, dof, A, b, n_faces, cap, edges, E, S_cap, p->n_mix, p->seed, p->edge_id_base,
-                                (float*)w_s, stride, edge_status, it, st, nullptr, (const int*)w_ac))) {
+                                (float*)w_s, stride, edge_status, it, st, nullptr, (const int*)w_ac, edge_ids))) {
             mark(EZO_NUM_PHASES);
             return ls;
         }
@@ -1018,6 +1029,8 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
         push(n_faces);
         push(edge_status);
         push(st);
+        push(edge_ids);
+        push(skip);
         key.push_back((uintptr_t)(uint32_t)n_obs);
         key.push_back((uintptr_t)(uint32_t)E);
         key.push_back((uintptr_t)S_cap);
@@ -1121,6 +1134,79 @@ ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, i
             stats[e].exact_checks = hs[e].exact_checks;
             stats[e].screened_checks = hs[e].screened;
         }
+    }
+    HIP_TRY(c, hipEventRecord(c->ev_out, st));
+    HIP_TRY(c, hipStreamWaitEvent(as_stream(stream), c->ev_out, 0));
+    return EZO_OK;
+}
+
+extern "C" {
+
+ezo_status ezo_inflate_edges(ezo_ctx* c, const ezo_robot* r, const float* obs, int32_t n_obs, const float* edges,
+                             int32_t n_edges, const ezo_params* p, float* A, float* b, int32_t* n_faces,
+                             int32_t* edge_status, ezo_edge_stats* stats, void* stream) {
+    return inflate_core(c, r, obs, n_obs, edges, n_edges, p, A, b, n_faces, edge_status, stats, stream, nullptr,
+                        nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Sequential inflation of paths with the containment skip (Sec. V-A)
+// ---------------------------------------------------------------------------
+
+ezo_status ezo_inflate_paths(ezo_ctx* c, const ezo_robot* r, const float* obs, int32_t n_obs, const float* vertices,
+                             const int32_t* path_vertices, int32_t n_paths, const ezo_params* p, float* A, float* b,
+                             int32_t* n_faces, int32_t* edge_status, int32_t* covered_by, ezo_edge_stats* stats,
+                             void* stream) {
+    if (!c) return EZO_E_INVALID;
+    if (!r || !p) return ezo_fail(c, EZO_E_INVALID, "NULL robot or params");
+    if (n_paths < 0 || n_obs < 0) return ezo_fail(c, EZO_E_INVALID, "negative size");
+    if (n_paths == 0) return EZO_OK;
+    if (!path_vertices) return ezo_fail(c, EZO_E_INVALID, "NULL path_vertices");
+    std::vector<int> eoff(n_paths + 1, 0);
+    int max_k = 0;
+    for (int q = 0; q < n_paths; ++q) {
+        const int nv = path_vertices[q];
+        if (nv < 2) return ezo_fail(c, EZO_E_INVALID, "path %d has %d vertices (at least 2)", q, nv);
+        if ((int64_t)eoff[q] + nv - 1 > INT32_MAX / 2) return ezo_fail(c, EZO_E_INVALID, "too many edges");
+        eoff[q + 1] = eoff[q] + nv - 1;
+        max_k = std::max(max_k, nv - 1);
+    }
+    if (!vertices || !A || !b || !n_faces || !edge_status || !covered_by || (n_obs > 0 && !obs))
+        return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
+    const int dof = r->dof, P = n_paths, cap = p->face_capacity;
+    if (cap < 1) return ezo_fail(c, EZO_E_CAPACITY, "face_capacity %d", cap);
+    HIP_TRY(c, hipSetDevice(c->device));
+    void *w_eo, *w_re, *w_ri, *w_rs, *w_ra, *w_rb, *w_rn, *w_rt;
+    ezo_status s;
+    if ((s = ezo_ws_get(c, W_PATH_EOFF, sizeof(int) * (size_t)(P + 1), &w_eo)) ||
+        (s = ezo_ws_get(c, W_ROUND_EDGES, sizeof(float) * (size_t)P * 2 * dof, &w_re)) ||
+        (s = ezo_ws_get(c, W_ROUND_IDS, sizeof(int) * (size_t)P, &w_ri)) ||
+        (s = ezo_ws_get(c, W_ROUND_SKIP, (size_t)P, &w_rs)) ||
+        (s = ezo_ws_get(c, W_ROUND_A, sizeof(float) * (size_t)P * cap * dof, &w_ra)) ||
+        (s = ezo_ws_get(c, W_ROUND_B, sizeof(float) * (size_t)P * cap, &w_rb)) ||
+        (s = ezo_ws_get(c, W_ROUND_NF, sizeof(int) * (size_t)P, &w_rn)) ||
+        (s = ezo_ws_get(c, W_ROUND_ST, sizeof(int) * (size_t)P, &w_rt)))
+        return s;
+    hipStream_t st = c->stream;
+    HIP_TRY(c, hipEventRecord(c->ev_in, as_stream(stream)));
+    HIP_TRY(c, hipStreamWaitEvent(st, c->ev_in, 0));
+    HIP_TRY(c, hipMemcpyAsync(w_eo, eoff.data(), sizeof(int) * (P + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipStreamSynchronize(st));            // eoff is a host vector
+    std::vector<ezo_edge_stats> rstats(P);
+    for (int rr = 0; rr < max_k; ++rr) {
+        EZO_KLAUNCH(c, k_path_round, dim3(P), dim3(256), 0, st, dof, vertices, (const int*)w_eo, rr, A, b, n_faces,
+                    edge_status, cap, covered_by, (float*)w_re, (int*)w_ri, (uint8_t*)w_rs);
+        HIP_TRY(c, hipGetLastError());
+        if ((s = inflate_core(c, r, obs, n_obs, (const float*)w_re, P, p, (float*)w_ra, (float*)w_rb, (int*)w_rn,
+                              (int*)w_rt, stats ? rstats.data() : nullptr, st, (const int*)w_ri,
+                              (const uint8_t*)w_rs)))
+            return s;
+        EZO_KLAUNCH(c, k_path_scatter, dim3(P), dim3(256), 0, st, dof, (const int*)w_eo, rr, (const float*)w_ra,
+                    (const float*)w_rb, (const int*)w_rn, (const int*)w_rt, cap, A, b, n_faces, edge_status);
+        HIP_TRY(c, hipGetLastError());
+        if (stats)
+            for (int q = 0; q < P; ++q)
+                if (rr < eoff[q + 1] - eoff[q]) stats[eoff[q] + rr] = rstats[q];
     }
     HIP_TRY(c, hipEventRecord(c->ev_out, st));
     HIP_TRY(c, hipStreamWaitEvent(as_stream(stream), c->ev_out, 0));

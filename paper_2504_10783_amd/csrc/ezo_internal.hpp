@@ -28,7 +28,8 @@ struct DevBuf {
 enum Slot {
     W_OBS_REC, W_OBS_CENTRE, W_GRID_GEOM, W_GRID_COUNT, W_GRID_LIST, W_SAMPLES, W_FLAGS, W_CAND, W_NCAND, W_CSTAR,
     W_ADIR, W_TSTAR, W_PCOL, W_PANY, W_STATS, W_TABLE, W_KDEV, W_ACTIVE, W_PRED, W_SCREENED, W_MLP_H1, W_MLP_H2,
-    W_MLP_CNT, W_PATH_M, W_PATH_OFF, W_PATH_PTS, W_PATH_IDX, W_PATH_CNT, W_RUN, W_NPLACED, W_NSLOTS
+    W_MLP_CNT, W_PATH_M, W_PATH_OFF, W_PATH_PTS, W_PATH_IDX, W_PATH_CNT, W_RUN, W_NPLACED, W_PATH_EOFF,
+    W_ROUND_EDGES, W_ROUND_IDS, W_ROUND_SKIP, W_ROUND_A, W_ROUND_B, W_ROUND_NF, W_ROUND_ST, W_NSLOTS
 };
 
 struct ezo_ctx {
@@ -56,6 +57,7 @@ struct ezo_ctx {
 
 struct ezo_robot {
     ezo_ctx* ctx = nullptr;
+    int device = 0;                    // the context's device (destroy does not read the context)
     int dof = 0, S = 0, P = 0;
     float r_max = 0.f;                 // largest sphere radius
     void* buf = nullptr;               // one device allocation holding everything below
@@ -81,6 +83,7 @@ struct RowSource {
 
 struct ezo_surrogate {
     ezo_ctx* ctx = nullptr;
+    int device = 0;                     // the context's device (destroy does not read the context)
     int D = 0, H = 0;
     int64_t n_params = 0;
     float margin = INFINITY;            // screen threshold (calibrated); +inf screens nothing

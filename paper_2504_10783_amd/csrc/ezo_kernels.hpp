@@ -356,7 +356,8 @@ template <int D, int L>
 __device__ __forceinline__ void sample_block(char* smem, int dof, const float* __restrict__ A, const float* __restrict__ bvec,
                                     const int* __restrict__ n_faces, int cap, const float* __restrict__ edges,
                                     uint32_t key0, uint32_t key1, int64_t edge_id_base, int n_mix,
-                                    float* __restrict__ S, int64_t stride, const IterVals& iv) {
+                                    float* __restrict__ S, int64_t stride, const IterVals& iv,
+                                    const int* __restrict__ edge_ids = nullptr) {
     static_assert(L == 1 || L == 2 || L == 4 || L == 8 || L == 16, "lanes per walk");
     const int e = blockIdx.y;
     const int F = min(max(n_faces[e], 0), cap);
@@ -376,7 +377,7 @@ __device__ __forceinline__ void sample_block(char* smem, int dof, const float* _
     // barriers) but stores nothing; groups never straddle walks.
     const bool live = i < iv.nS;
     const float* v = edges + (size_t)e * 2 * dof;
-    const uint32_t eid = (uint32_t)(edge_id_base + e);
+    const uint32_t eid = (uint32_t)(edge_id_base + (edge_ids ? edge_ids[e] : e));
     const uint32_t ii = (uint32_t)i, kk = (uint32_t)iv.k;
     float x[D], u[D];
     {
@@ -455,20 +456,24 @@ __global__ void __launch_bounds__(256) k_sample_auto(int dof, const float* __res
                                                      uint32_t key1, int64_t edge_id_base, int n_mix,
                                                      float* __restrict__ S, int64_t stride,
                                                      const int* __restrict__ status, IterArgs it,
-                                                     const int* __restrict__ active, int64_t walks16, int64_t walks4) {
+                                                     const int* __restrict__ active, int64_t walks16, int64_t walks4,
+                                                     const int* __restrict__ edge_ids) {
     extern __shared__ __align__(16) char smem[];
     if (!edge_running(status, blockIdx.y)) return;
     const IterVals iv = resolve(it);
     const int64_t walks = (int64_t)max(*active, 1) * iv.nS;
     const int64_t wg_first = (int64_t)blockIdx.x * blockDim.x;     // first thread of this workgroup
     if (walks <= walks16) {
-        sample_block<D, 16>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv);
+        sample_block<D, 16>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv,
+                            edge_ids);
     } else if (walks <= walks4) {
         if (wg_first >= 4 * (int64_t)iv.nS) return;
-        sample_block<D, 4>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv);
+        sample_block<D, 4>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv,
+                            edge_ids);
     } else {
         if (wg_first >= iv.nS) return;
-        sample_block<D, 1>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv);
+        sample_block<D, 1>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv,
+                            edge_ids);
     }
 }
 
@@ -906,13 +911,20 @@ __global__ void k_init_edges(int dof, const float* __restrict__ q_lo, const floa
                              const float* __restrict__ edges, int n_edges, float* __restrict__ A,
                              float* __restrict__ bvec, int* __restrict__ n_faces, int cap, int* __restrict__ status,
                              EdgeStatsDev* __restrict__ stats, uint8_t* __restrict__ proj_any,
-                             int* __restrict__ k_dev, int* __restrict__ active) {
+                             int* __restrict__ k_dev, int* __restrict__ active, const uint8_t* __restrict__ skip) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e == 0) {
         *k_dev = 1;
         *active = n_edges;
     }
     if (e >= n_edges) return;
+    if (skip && skip[e]) {                      // not inflated: final from the start, no rows
+        n_faces[e] = 0;
+        status[e] = 4;                          // EZO_EDGE_CONTAINED
+        stats[e] = EdgeStatsDev{0, 0, 0, 0, 0, 0, 0};
+        proj_any[e] = 0;
+        return;
+    }
     float* Ae = A + (size_t)e * cap * dof;
     float* be = bvec + (size_t)e * cap;
     for (int f = 0; f < 2 * dof; ++f) {
@@ -958,6 +970,96 @@ __global__ void __launch_bounds__(256) k_advance(int* __restrict__ k_dev, int ma
     if (threadIdx.x == 0) {
         *active_count = cnt;
         *k_dev = k + 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sequential inflation of piecewise-linear paths with the containment skip
+// (Sec. V-A).  Round r holds edge r of every path; an edge whose segment lies
+// in the set of an earlier edge of its path is not inflated.  Path p's edges
+// are eoff[p] .. eoff[p+1]-1 (global numbering); its vertices start at
+// eoff[p] + p, so edge g of path p runs from vertex g + p to g + p + 1.
+// ---------------------------------------------------------------------------
+
+// One workgroup (256 threads) per path.  Slot p of round r: the segment, its
+// global edge index and whether it is skipped -- past the path's end, or
+// contained in the set of an earlier edge h of the path that was inflated
+// (covered_by[h] == -1) and ended CERTIFIED or MAX_ITERS; covered_by[g] = the
+// first such h, else -1.  One wave per earlier set, lanes over its rows: both
+// endpoints satisfy every row a.v <= b (FP32, fmaf in index order).
+__global__ void __launch_bounds__(256) k_path_round(int dof, const float* __restrict__ verts,
+                                                    const int* __restrict__ eoff, int r,
+                                                    const float* __restrict__ A, const float* __restrict__ bvec,
+                                                    const int* __restrict__ n_faces,
+                                                    const int* __restrict__ status, int cap,
+                                                    int* __restrict__ covered_by, float* __restrict__ round_edges,
+                                                    int* __restrict__ round_ids, uint8_t* __restrict__ round_skip) {
+    __shared__ int best;
+    const int p = blockIdx.x;
+    const int e0 = eoff[p], K = eoff[p + 1] - e0;
+    float* re = round_edges + (size_t)p * 2 * dof;
+    if (r >= K) {
+        if (threadIdx.x < 2 * dof) re[threadIdx.x] = 0.f;
+        if (threadIdx.x == 0) {
+            round_ids[p] = e0;
+            round_skip[p] = 1;
+        }
+        return;
+    }
+    const int g = e0 + r;
+    const float* v = verts + (size_t)(g + p) * dof;
+    if (threadIdx.x < 2 * dof) re[threadIdx.x] = v[threadIdx.x];
+    if (threadIdx.x == 0) best = 0x7fffffff;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+    for (int h = e0 + wave; h < g; h += n_waves) {
+        const int sh = status[h];
+        if (covered_by[h] != -1 || (sh != 0 && sh != 1)) continue;       // uniform over the wave
+        const int F = min(max(n_faces[h], 0), cap);
+        if (F == 0) continue;
+        const float* Ah = A + (size_t)h * cap * dof;
+        bool out = false;
+        for (int f = lane; f < F; f += 64) {
+            float a1 = 0.f, a2 = 0.f;
+            for (int j = 0; j < dof; ++j) {
+                const float a = Ah[(size_t)f * dof + j];
+                a1 = fmaf(a, v[j], a1);
+                a2 = fmaf(a, v[dof + j], a2);
+            }
+            const float bb = bvec[(size_t)h * cap + f];
+            out |= !(a1 <= bb && a2 <= bb);
+        }
+        if (__ballot(out) == 0 && lane == 0) atomicMin(&best, h);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int c = best == 0x7fffffff ? -1 : best;
+        covered_by[g] = c;
+        round_ids[p] = g;
+        round_skip[p] = c >= 0;
+    }
+}
+
+// Slot p of the round's inflation into global edge round_ids[p]: rows,
+// face count and status (a contained edge: CONTAINED, no rows).  One
+// workgroup per path; slots past a path's end store nothing.
+__global__ void __launch_bounds__(256) k_path_scatter(int dof, const int* __restrict__ eoff, int r,
+                                                      const float* __restrict__ rA, const float* __restrict__ rb,
+                                                      const int* __restrict__ rnf, const int* __restrict__ rst,
+                                                      int cap, float* __restrict__ A, float* __restrict__ bvec,
+                                                      int* __restrict__ n_faces, int* __restrict__ status) {
+    const int p = blockIdx.x;
+    const int e0 = eoff[p];
+    if (r >= eoff[p + 1] - e0) return;
+    const int g = e0 + r;
+    const int F = min(max(rnf[p], 0), cap);
+    const float* sA = rA + (size_t)p * cap * dof;
+    float* dA = A + (size_t)g * cap * dof;
+    for (int i = threadIdx.x; i < F * dof; i += blockDim.x) dA[i] = sA[i];
+    for (int f = threadIdx.x; f < F; f += blockDim.x) bvec[(size_t)g * cap + f] = rb[(size_t)p * cap + f];
+    if (threadIdx.x == 0) {
+        n_faces[g] = rnf[p];
+        status[g] = rst[p];
     }
 }
 
@@ -1069,6 +1171,7 @@ __global__ void __launch_bounds__(256) k_segments_contained(int dof, const float
     const float* v = segs + (size_t)k * 2 * dof;
     for (int e = threadIdx.x; e < n_sets; e += blockDim.x) {
         const int F = min(max(n_faces[e], 0), cap);
+        if (F == 0) continue;                    // an edge that holds no set
         const float* Ae = A + (size_t)e * cap * dof;
         bool in = true;
         for (int f = 0; f < F && in; ++f) {

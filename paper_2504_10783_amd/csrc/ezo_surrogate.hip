@@ -197,6 +197,7 @@ ezo_status ezo_surrogate_create(ezo_ctx* c, int32_t dof, int32_t hidden, uint64_
     HIP_TRY(c, hipSetDevice(c->device));
     ezo_surrogate* s = new ezo_surrogate();
     s->ctx = c;
+    s->device = c->device;
     s->D = dof;
     s->H = hidden;
     const MlpOffsets o = mlp_offsets(dof, hidden);
@@ -235,10 +236,11 @@ ezo_status ezo_surrogate_create(ezo_ctx* c, int32_t dof, int32_t hidden, uint64_
 
 void ezo_surrogate_destroy(ezo_surrogate* s) {
     if (!s) return;
-    hipError_t e = hipSetDevice(s->ctx->device);
+    hipError_t e = hipSetDevice(s->device);
     for (void* p : {(void*)s->P, (void*)s->G, (void*)s->m, (void*)s->v, (void*)s->W2b, (void*)s->W3b, s->tb})
         if (p) e = hipFree(p);
     (void)e;
+    (void)hipGetLastError();
     delete s;
 }
 

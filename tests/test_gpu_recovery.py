@@ -98,6 +98,17 @@ def decided_collisions(desc, data, A, b, v1, v2, n, seed, n_b=11):
     return np.array(out, np.float32)
 
 
+def oracle_set(desc, data, name, v1, v2, seed):
+    """An early, loose set of the edge from the oracle's own FP64 inflation
+    (one iteration), rounded to FP32 as the GPU holds it."""
+    p = dict(workloads.PARAMS[name], max_iters=1)
+    if name == "dof7":
+        p["n_p"] = 2000                                   # keeps the FP64 run short
+    o = oracle.eizo_arm(oracle.Robot(desc), f32_up(data["obstacles"]), v1, v2,
+                        oracle.make_params(**p, seed=seed, edge_id=0))
+    return o["A"].astype(np.float32), o["b"].astype(np.float32), o["status"]
+
+
 @pytest.mark.parametrize("name,n", [("tiny", 40), ("dof7", 120)])
 def test_update_polytopes_parity(ezo, ctx, name, n):
     data, desc = load(name)
@@ -105,34 +116,35 @@ def test_update_polytopes_parity(ezo, ctx, name, n):
     dof = desc["dof"]
     obs = torch.from_numpy(data["obstacles"]).cuda()
     edges = torch.from_numpy(data["edges"][:1]).cuda()
-    # room for the edited set's new rows beyond those of the inflation
-    prm = ezo.make_params(dof=dof, seed=2, face_capacity=2 * dof + 40, **dict(workloads.PARAMS[name], max_iters=1))
-    res = ezo.inflate_edges(ctx, rob, obs, edges, prm)
-    torch.cuda.synchronize()
-    F0 = int(res.n_faces[0].item())
-    A0 = res.A[0, :F0].cpu().numpy().astype(np.float64)
-    b0 = res.b[0, :F0].cpu().numpy().astype(np.float64)
     v1, v2 = f32_up(data["edges"][0])
+    A0f, b0f, st0 = oracle_set(desc, data, name, v1, v2, seed=2)
+    F0 = len(b0f)
+    cap = F0 + 40                                         # room for the new rows
+    res = ezo.InflateResult(torch.zeros((1, cap, dof), dtype=torch.float32, device="cuda"),
+                            torch.zeros((1, cap), dtype=torch.float32, device="cuda"),
+                            torch.tensor([F0], dtype=torch.int32, device="cuda"),
+                            torch.tensor([st0], dtype=torch.int32, device="cuda"), [])
+    res.A[0, :F0] = torch.from_numpy(A0f).cuda()
+    res.b[0, :F0] = torch.from_numpy(b0f).cuda()
+    A0, b0 = f32_up(A0f), f32_up(b0f)
     pts = decided_collisions(desc, data, A0, b0, v1, v2, n, seed=81)
-    print_case("update_polytopes", name, len(pts))
+    print_case("update_polytopes", name, len(pts), "rows", F0, "status", st0)
     assert len(pts) >= 5
     # plus points outside the set, which must be ignored
     far = np.tile(np.asarray(data["q_hi"], np.float32) * 2.0, (3, 1))
     allp = np.concatenate([pts, far]).astype(np.float32)
-    before_A = res.A.clone()
-    status0 = int(res.status[0].item())
     added = ezo.update_polytopes(ctx, rob, obs, edges, torch.from_numpy(allp).cuda(), res, n_b=11, n_f=10,
                                  step_back_max=workloads.PARAMS[name]["step_back_max"],
                                  t_col=workloads.PARAMS[name]["t_col"])
     torch.cuda.synchronize()
     F1 = int(res.n_faces[0].item())
     assert F1 == F0 + int(added[0].item()) and F1 > F0
-    assert torch.equal(res.A[0, :F0], before_A[0, :F0])               # existing rows untouched
+    assert np.array_equal(res.A[0, :F0].cpu().numpy(), A0f)            # existing rows untouched
     bis = lambda a, b_, c, nb: oracle.bisect_arm(oracle.Robot(desc), f32_up(data["obstacles"]), a, b_, c, nb)
     A2, b2, st, _, idx = oracle.recover_set(bis, v1, v2, A0, b0, f32_up(allp), 11, 10,
                                             workloads.PARAMS[name]["step_back_max"], workloads.PARAMS[name]["t_col"])
     assert len(idx) == len(pts)
-    assert int(res.status[0].item()) == (ezo.IN_COLLISION if st == oracle.IN_COLLISION else status0)
+    assert int(res.status[0].item()) == (ezo.IN_COLLISION if st == oracle.IN_COLLISION else st0)
     assert F1 == len(b2)
     gA = res.A[0, F0:F1].cpu().numpy().astype(np.float64)
     gb = res.b[0, F0:F1].cpu().numpy().astype(np.float64)
@@ -178,7 +190,8 @@ def test_segments_contained_exact(ezo, ctx):
 def test_recovery_round_trip(ezo, ctx):
     """Inflate, route a trajectory through collisions inside the set, find
     them by the path check, edit the set: the found points leave the set, L
-    stays inside and the segment is still covered."""
+    stays inside and the segment is still covered.  GPU calls only; the
+    properties are checked with plain numpy."""
     data, desc = load("dof7")
     rob = ezo.Robot(ctx, desc)
     dof = desc["dof"]
@@ -186,13 +199,16 @@ def test_recovery_round_trip(ezo, ctx):
     edges = torch.from_numpy(data["edges"][:1]).cuda()
     p = dict(workloads.PARAMS["dof7"], max_iters=1)            # an early, loose set
     res = ezo.inflate_edges(ctx, rob, obs, edges, ezo.make_params(dof=dof, seed=3, face_capacity=400, **p))
+    # colliding configurations inside the set: hit-and-run samples, checked
+    S = torch.empty((1, dof, 4096), dtype=torch.float32, device="cuda")
+    ezo.sample_polytopes(ctx, dof, res.A, res.b, res.n_faces, edges, 4096, 60, 91, 0, S)
+    q = S[0].t().contiguous()
+    flags = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    ezo.check_collisions(ctx, rob, obs, q, flags)
     torch.cuda.synchronize()
-    F0 = int(res.n_faces[0].item())
-    A0 = res.A[0, :F0].cpu().numpy().astype(np.float64)
-    b0 = res.b[0, :F0].cpu().numpy().astype(np.float64)
-    v1, v2 = f32_up(data["edges"][0])
-    cols = decided_collisions(desc, data, A0, b0, v1, v2, 2, seed=91)
+    cols = q[flags.bool()][:2].cpu().numpy()
     assert len(cols) == 2
+    v1, v2 = data["edges"][0].astype(np.float64)
     way = np.stack([data["edges"][0][0], cols[0], cols[1], data["edges"][0][1]]).astype(np.float32)
     print_case("recovery round trip")
     found, n_col, n_pts = ezo.check_path(ctx, rob, obs, torch.from_numpy(way).cuda(), 0.05, point_capacity=4096)
@@ -205,7 +221,8 @@ def test_recovery_round_trip(ezo, ctx):
     b1 = res.b[0, :F1].cpu().numpy().astype(np.float64)
     for v in (v1, v2):
         assert np.all(A1 @ v <= b1 + 1e-5)
-    inside = oracle.points_in_polytope(A1, b1, found.cpu().numpy().astype(np.float64))
+    P = found.cpu().numpy().astype(np.float64)
+    inside = np.all(P @ A1.T <= b1, axis=1)
     print(f"{n_col} found collisions, {int(added[0].item())} planes, {int(inside.sum())} still inside")
     assert inside.mean() <= 0.5
     cov = ezo.segments_contained(ctx, res.A, res.b, res.n_faces, edges)
