@@ -54,7 +54,9 @@ class _Robot(C.Structure):
     _fields_ = [("dof", C.c_int32), ("a", _dp), ("alpha", _dp), ("d", _dp),
                 ("q_lo", _dp), ("q_hi", _dp), ("n_spheres", C.c_int32),
                 ("sphere_link", _ip), ("sphere_xyz", _dp), ("sphere_r", _dp),
-                ("n_self", C.c_int32), ("self_pairs", _ip)]
+                ("n_self", C.c_int32), ("self_pairs", _ip),
+                ("n_boxes", C.c_int32), ("box_link", _ip), ("box_pose", _dp), ("box_half", _dp),
+                ("n_box_pairs", C.c_int32), ("box_pairs", _ip)]
 
 
 class Params(C.Structure):
@@ -78,8 +80,12 @@ def _declare(L):
     rp = C.POINTER(_Robot)
     L.orc_link_frames.argtypes = [rp, _dp, _dp]
     L.orc_sphere_centres.argtypes = [rp, _dp, _dp]
-    L.orc_check_config.argtypes = [rp, _dp, C.c_int32, _dp, _dp, _dp]
-    L.orc_check_batch.argtypes = [rp, _dp, C.c_int32, _dp, C.c_int64, _u8p, _dp, _dp, _dp]
+    L.orc_check_config.argtypes = [rp, _dp, C.c_int32, _dp, C.c_int32, _dp, _dp, _dp, C.POINTER(C.c_int)]
+    L.orc_check_batch.argtypes = [rp, _dp, C.c_int32, _dp, C.c_int32, _dp, C.c_int64, _u8p, _dp, _dp, _dp, _u8p]
+    L.orc_sd_sphere_box.argtypes = [_dp, C.c_double, _dp, _dp, _dp]
+    L.orc_sd_sphere_box.restype = C.c_double
+    L.orc_sat_boxes.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, C.POINTER(C.c_int)]
+    L.orc_sat_boxes.restype = C.c_double
     L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
     L.orc_u01.argtypes = [C.c_uint32]
     L.orc_u01.restype = C.c_double
@@ -87,7 +93,8 @@ def _declare(L):
     L.orc_hit_and_run.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, C.c_int32, C.c_uint64,
                                   C.c_uint32, C.c_uint32, C.c_int64, _dp]
     L.orc_project.argtypes = [C.c_int32, _dp, _dp, _dp, _dp, _dp]
-    L.orc_bisect_arm.argtypes = [rp, _dp, C.c_int32, _dp, _dp, _dp, C.c_int32, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_bisect_arm.argtypes = [rp, _dp, C.c_int32, _dp, C.c_int32, _dp, _dp, _dp, C.c_int32, _dp, _dp, _dp, _dp,
+                                 _dp, _dp]
     L.orc_bisect_arm.restype = C.c_int
     L.orc_bisect_balls.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, _dp, C.c_int32,
                                    _dp, _dp, _dp, _dp, _dp, _dp]
@@ -95,7 +102,7 @@ def _declare(L):
     L.orc_place.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, _dp, C.c_int32, C.c_double,
                             C.c_double, _dp, _dp, _ip, C.c_int32, _ip, _ip]
     L.orc_place.restype = C.c_int
-    L.orc_eizo_arm.argtypes = [rp, _dp, C.c_int32, _dp, _dp, C.c_int32, _dp, _dp,
+    L.orc_eizo_arm.argtypes = [rp, _dp, C.c_int32, _dp, C.c_int32, _dp, _dp, C.c_int32, _dp, _dp,
                                C.POINTER(Params), _dp, _dp, C.c_int32, _ip, C.POINTER(Stats)]
     L.orc_eizo_arm.restype = C.c_int
     L.orc_eizo_balls.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, C.c_int32, _dp, _dp,
@@ -141,10 +148,19 @@ class Robot:
             sp = np.zeros((0, 2), np.int32)
         self.self_pairs = np.ascontiguousarray(sp, dtype=np.int32).reshape(-1, 2)
         self.n_spheres = len(self.sphere_r)
+        # boxes on links (optional): link, pose (centre, rotation row-major) in
+        # the link frame, half extents, self pairs of box indices
+        self.box_link = np.ascontiguousarray(desc.get("box_link", np.zeros(0)), dtype=np.int32)
+        self.box_pose = _d(desc.get("box_pose", np.zeros((0, 12)))).reshape(-1, 12)
+        self.box_half = _d(desc.get("box_half", np.zeros((0, 3)))).reshape(-1, 3)
+        self.box_pairs = np.ascontiguousarray(desc.get("box_pairs", np.zeros((0, 2))), dtype=np.int32).reshape(-1, 2)
+        self.n_boxes = len(self.box_link)
         self._s = _Robot(self.dof, _ptr(self.a), _ptr(self.alpha), _ptr(self.d), _ptr(self.q_lo),
                          _ptr(self.q_hi), self.n_spheres, _ptr(self.sphere_link, _ip),
                          _ptr(self.sphere_xyz), _ptr(self.sphere_r), len(self.self_pairs),
-                         _ptr(self.self_pairs, _ip))
+                         _ptr(self.self_pairs, _ip), self.n_boxes, _ptr(self.box_link, _ip),
+                         _ptr(self.box_pose), _ptr(self.box_half), len(self.box_pairs),
+                         _ptr(self.box_pairs, _ip))
 
     @property
     def ref(self):
@@ -179,16 +195,42 @@ def sphere_centres(robot: Robot, q):
     return out
 
 
-def check(robot: Robot, obs, q):
-    """Returns (flags u8[n], min_sd[n], sd_env[n], sd_self[n]) for q [n][dof]."""
+def _ebox(env_boxes):
+    """Obstacle boxes as [n][15] FP64: centre (3), rotation (9, row-major,
+    columns = box axes), half extents (3), world frame."""
+    if env_boxes is None:
+        return np.zeros((0, 15))
+    return _d(env_boxes).reshape(-1, 15)
+
+
+def check(robot: Robot, obs, q, env_boxes=None, fragile=False):
+    """Returns (flags u8[n], min_sd[n], sd_env[n], sd_self[n]) for q [n][dof];
+    with fragile=True also fragile u8[n]: some box-box pair near the minimum
+    rests on a separating axis of nearly parallel edges (sat_boxes)."""
     q = _d(q).reshape(-1, robot.dof)
     obs = _d(obs).reshape(-1, 4)
+    eb = _ebox(env_boxes)
     n = q.shape[0]
     flags = np.empty(n, np.uint8)
     sd, se, ss = np.empty(n), np.empty(n), np.empty(n)
-    lib().orc_check_batch(robot.ref, _ptr(obs), obs.shape[0], _ptr(q), n, _ptr(flags, _u8p),
-                          _ptr(sd), _ptr(se), _ptr(ss))
-    return flags, sd, se, ss
+    fr = np.empty(n, np.uint8) if fragile else None
+    lib().orc_check_batch(robot.ref, _ptr(obs), obs.shape[0], _ptr(eb), eb.shape[0], _ptr(q), n,
+                          _ptr(flags, _u8p), _ptr(sd), _ptr(se), _ptr(ss), _ptr(fr, _u8p))
+    return (flags, sd, se, ss, fr) if fragile else (flags, sd, se, ss)
+
+
+def sd_sphere_box(x, r, c, R, h):
+    """Signed distance of a sphere (centre x, radius r) and a box (centre c,
+    rotation R with the box axes as columns, half extents h)."""
+    return lib().orc_sd_sphere_box(_ptr(_d(x)), float(r), _ptr(_d(c)), _ptr(_d(R).reshape(9)), _ptr(_d(h)))
+
+
+def sat_boxes(cA, RA, hA, cB, RB, hB):
+    """(separating-axis value, fragile) of two boxes."""
+    f = C.c_int()
+    v = lib().orc_sat_boxes(_ptr(_d(cA)), _ptr(_d(RA).reshape(9)), _ptr(_d(hA)), _ptr(_d(cB)),
+                            _ptr(_d(RB).reshape(9)), _ptr(_d(hB)), C.byref(f))
+    return v, bool(f.value)
 
 
 def philox(ctr, key):
@@ -228,14 +270,15 @@ def project(v1, v2, c):
     return cp, al.value
 
 
-def bisect_arm(robot: Robot, obs, v1, v2, c, n_b):
+def bisect_arm(robot: Robot, obs, v1, v2, c, n_b, env_boxes=None):
     obs = _d(obs).reshape(-1, 4)
+    eb = _ebox(env_boxes)
     v1, v2, c = _d(v1), _d(v2), _d(c)
     d = robot.dof
     cs, ad, cp = np.empty(d), np.empty(d), np.empty(d)
     tr = np.empty(int(n_b) + 1)
     t, m = C.c_double(), C.c_double()
-    p = lib().orc_bisect_arm(robot.ref, _ptr(obs), obs.shape[0], _ptr(v1), _ptr(v2), _ptr(c),
+    p = lib().orc_bisect_arm(robot.ref, _ptr(obs), obs.shape[0], _ptr(eb), eb.shape[0], _ptr(v1), _ptr(v2), _ptr(c),
                              int(n_b), _ptr(cs), C.byref(t), _ptr(ad), _ptr(cp), C.byref(m), _ptr(tr))
     return dict(proj_collides=bool(p), c_star=cs, t_star=t.value, a=ad, c_proj=cp,
                 min_abs_sd=m.value, sd_trace=tr)
@@ -298,12 +341,13 @@ def _eizo_common(call, dof, A_D, b_D, v1, v2, prm: Params, cap):
     return dict(status=status, A=A[:nf.value].copy(), b=b[:nf.value].copy(), stats=st.as_dict())
 
 
-def eizo_arm(robot: Robot, obs, v1, v2, prm: Params, cap=None):
+def eizo_arm(robot: Robot, obs, v1, v2, prm: Params, cap=None, env_boxes=None):
     obs = _d(obs).reshape(-1, 4)
+    eb = _ebox(env_boxes)
     A_D, b_D = robot.box()
 
     def call(A_D, b_D, v1, v2, A, b, cap, nf, st):
-        return lib().orc_eizo_arm(robot.ref, _ptr(obs), obs.shape[0], _ptr(A_D), _ptr(b_D),
+        return lib().orc_eizo_arm(robot.ref, _ptr(obs), obs.shape[0], _ptr(eb), eb.shape[0], _ptr(A_D), _ptr(b_D),
                                   len(b_D), _ptr(v1), _ptr(v2), C.byref(prm), _ptr(A), _ptr(b),
                                   cap, C.byref(nf), C.byref(st))
     return _eizo_common(call, robot.dof, A_D, b_D, v1, v2, prm, cap)

@@ -45,6 +45,14 @@ typedef struct {
     const double *sphere_r;        /* [S] radius                              */
     int32_t n_self;
     const int32_t *self_pairs;     /* [P][2] sphere indices checked for self-collision */
+    /* boxes rigidly attached to links (the box geometry of Sec. IV-D) */
+    int32_t n_boxes;
+    const int32_t *box_link;       /* [B] 0-based link                                  */
+    const double *box_pose;        /* [B][12] centre (3), then rotation (3x3, row-major,
+                                      columns = the box axes) in that link's frame      */
+    const double *box_half;        /* [B][3] half extents along the box axes            */
+    int32_t n_box_pairs;
+    const int32_t *box_pairs;      /* [Q][2] box indices checked for self-collision     */
 } orc_robot;
 
 /* A signed-distance function over configurations; the configuration is in
@@ -55,6 +63,9 @@ typedef struct {
     const orc_robot *robot;
     const double *obs;             /* [n_obs][4] x, y, z, r (world frame) */
     int32_t n_obs;
+    const double *ebox;            /* [n_ebox][15] obstacle boxes: centre (3), rotation (9,
+                                      row-major, columns = axes), half extents (3), world */
+    int32_t n_ebox;
 } orc_arm_scene;
 
 typedef struct {
@@ -136,48 +147,190 @@ static double dist3(const double *x, const double *y) {
     return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
+/* ---- boxes ---------------------------------------------------------------- */
+
+/* World pose of a box fixed to a link: c = R_T p + t, R = R_T R_local. */
+static void box_world(const double T[16], const double *pose, double c[3], double R[9]) {
+    for (int r = 0; r < 3; ++r) {
+        c[r] = T[4 * r + 0] * pose[0] + T[4 * r + 1] * pose[1] + T[4 * r + 2] * pose[2] + T[4 * r + 3];
+        for (int k = 0; k < 3; ++k)
+            R[3 * r + k] = T[4 * r + 0] * pose[3 + k] + T[4 * r + 1] * pose[6 + k] + T[4 * r + 2] * pose[9 + k];
+    }
+}
+
+/* Signed distance between a sphere (centre x, radius r) and a box (centre c,
+ * rotation R whose columns are the axes, half extents h): the point in box
+ * coordinates p = R^T (x - c); outside the box the Euclidean distance from p
+ * to the box minus r, inside minus (the distance to the nearest face + r). */
+double orc_sd_sphere_box(const double x[3], double r, const double c[3], const double R[9], const double h[3]) {
+    double p[3], out2 = 0.0, depth = INFINITY;
+    int inside = 1;
+    for (int k = 0; k < 3; ++k) {
+        p[k] = R[0 + k] * (x[0] - c[0]) + R[3 + k] * (x[1] - c[1]) + R[6 + k] * (x[2] - c[2]);
+        const double a = fabs(p[k]);
+        if (a > h[k]) {
+            inside = 0;
+            out2 += (a - h[k]) * (a - h[k]);
+        }
+        if (h[k] - a < depth) depth = h[k] - a;
+    }
+    return inside ? -depth - r : sqrt(out2) - r;
+}
+
+/* Separating-axis value of two boxes: the largest, over the 3 + 3 face
+ * normals and the 9 cross products of an edge of each box (unit, those with
+ * |A_i x B_j| < 1e-6 skipped as parallel), of |t . L| - r_A(L) - r_B(L), with
+ * t the centre offset and r_X(L) = sum_k h_k |X_k . L| the box's half width
+ * along L.  Positive: the boxes are apart (a lower bound on their distance);
+ * otherwise minus the smallest overlap over the axes, which for two boxes is
+ * the penetration depth.  *fragile (may be NULL) is set when a cross axis
+ * with |A_i x B_j| < 0.05 (nearly parallel edges, where FP32 rounding of the
+ * poses is amplified) comes within 1e-3 of the value or within 1e-4 of 0. */
+double orc_sat_boxes(const double cA[3], const double RA[9], const double hA[3], const double cB[3],
+                     const double RB[9], const double hB[3], int *fragile) {
+    double Ax[3][3], Bx[3][3], t[3];
+    for (int k = 0; k < 3; ++k) {
+        for (int r = 0; r < 3; ++r) {
+            Ax[k][r] = RA[3 * r + k];
+            Bx[k][r] = RB[3 * r + k];
+        }
+        t[k] = cB[k] - cA[k];
+    }
+    double best = -INFINITY;
+    double weak[9];
+    int n_weak = 0;
+    for (int a = 0; a < 15; ++a) {
+        double L[3];
+        double norm = 1.0;
+        if (a < 3) {
+            memcpy(L, Ax[a], sizeof(L));
+        } else if (a < 6) {
+            memcpy(L, Bx[a - 3], sizeof(L));
+        } else {
+            const double *u = Ax[(a - 6) / 3], *v = Bx[(a - 6) % 3];
+            L[0] = u[1] * v[2] - u[2] * v[1];
+            L[1] = u[2] * v[0] - u[0] * v[2];
+            L[2] = u[0] * v[1] - u[1] * v[0];
+            norm = sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
+            if (norm < 1e-6) continue;
+            for (int k = 0; k < 3; ++k) L[k] /= norm;
+        }
+        double rA = 0.0, rB = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            rA += hA[k] * fabs(Ax[k][0] * L[0] + Ax[k][1] * L[1] + Ax[k][2] * L[2]);
+            rB += hB[k] * fabs(Bx[k][0] * L[0] + Bx[k][1] * L[1] + Bx[k][2] * L[2]);
+        }
+        const double sep = fabs(t[0] * L[0] + t[1] * L[1] + t[2] * L[2]) - rA - rB;
+        if (sep > best) best = sep;
+        if (a >= 6 && norm < 0.05) weak[n_weak++] = sep;
+    }
+    if (fragile) {
+        *fragile = 0;
+        for (int i = 0; i < n_weak; ++i)
+            if (weak[i] > best - 1e-3 || fabs(weak[i]) < 1e-4) *fragile = 1;
+    }
+    return best;
+}
+
 /* Minimum signed distance over robot-obstacle pairs (sd_env) and over the
- * listed self pairs (sd_self); +inf when a set of pairs is empty. */
-void orc_check_config(const orc_robot *rb, const double *obs, int32_t n_obs, const double *q,
-                      double *sd_env, double *sd_self) {
+ * listed self pairs (sd_self); +inf when a set of pairs is empty.  Obstacle
+ * pairs: robot spheres and boxes against obstacle spheres and boxes
+ * (sphere-sphere: centre distance minus radii; sphere-box: orc_sd_sphere_box;
+ * box-box: orc_sat_boxes).  Self pairs: the sphere pairs and the box pairs.
+ * *fragile (may be NULL): some box-box pair within 1e-3 of the overall
+ * minimum has a fragile separating-axis value. */
+void orc_check_config(const orc_robot *rb, const double *obs, int32_t n_obs, const double *ebox, int32_t n_ebox,
+                      const double *q, double *sd_env, double *sd_self, int *fragile) {
     double *c = (double *)malloc(sizeof(double) * 3 * (size_t)(rb->n_spheres > 0 ? rb->n_spheres : 1));
+    const int B = rb->n_boxes;
+    double *bc = (double *)malloc(sizeof(double) * 12 * (size_t)(B > 0 ? B : 1));
     orc_sphere_centres(rb, q, c);
+    if (B > 0) {
+        double *frames = (double *)malloc(sizeof(double) * 16 * (size_t)rb->dof);
+        orc_link_frames(rb, q, frames);
+        for (int k = 0; k < B; ++k)
+            box_world(frames + 16 * rb->box_link[k], rb->box_pose + 12 * k, bc + 12 * k, bc + 12 * k + 3);
+        free(frames);
+    }
     double env = INFINITY, self = INFINITY;
     for (int s = 0; s < rb->n_spheres; ++s)
         for (int o = 0; o < n_obs; ++o) {
             double sd = dist3(c + 3 * s, obs + 4 * o) - rb->sphere_r[s] - obs[4 * o + 3];
             if (sd < env) env = sd;
         }
+    for (int s = 0; s < rb->n_spheres; ++s)
+        for (int e = 0; e < n_ebox; ++e) {
+            const double *E = ebox + 15 * e;
+            double sd = orc_sd_sphere_box(c + 3 * s, rb->sphere_r[s], E, E + 3, E + 12);
+            if (sd < env) env = sd;
+        }
+    /* box-box values with their fragility, kept until the minimum is known */
+    const int n_bb = B * n_ebox + rb->n_box_pairs;
+    double *bbv = (double *)malloc(sizeof(double) * (size_t)(n_bb > 0 ? n_bb : 1));
+    int *bbf = (int *)malloc(sizeof(int) * (size_t)(n_bb > 0 ? n_bb : 1));
+    int nb = 0;
+    for (int k = 0; k < B; ++k) {
+        const double *h = rb->box_half + 3 * k;
+        for (int o = 0; o < n_obs; ++o) {
+            double sd = orc_sd_sphere_box(obs + 4 * o, obs[4 * o + 3], bc + 12 * k, bc + 12 * k + 3, h);
+            if (sd < env) env = sd;
+        }
+        for (int e = 0; e < n_ebox; ++e) {
+            const double *E = ebox + 15 * e;
+            double sd = orc_sat_boxes(bc + 12 * k, bc + 12 * k + 3, h, E, E + 3, E + 12, &bbf[nb]);
+            bbv[nb++] = sd;
+            if (sd < env) env = sd;
+        }
+    }
     for (int p = 0; p < rb->n_self; ++p) {
         int s = rb->self_pairs[2 * p], t = rb->self_pairs[2 * p + 1];
         double sd = dist3(c + 3 * s, c + 3 * t) - rb->sphere_r[s] - rb->sphere_r[t];
         if (sd < self) self = sd;
     }
+    for (int p = 0; p < rb->n_box_pairs; ++p) {
+        int i = rb->box_pairs[2 * p], j = rb->box_pairs[2 * p + 1];
+        double sd = orc_sat_boxes(bc + 12 * i, bc + 12 * i + 3, rb->box_half + 3 * i, bc + 12 * j, bc + 12 * j + 3,
+                                  rb->box_half + 3 * j, &bbf[nb]);
+        bbv[nb++] = sd;
+        if (sd < self) self = sd;
+    }
+    if (fragile) {
+        const double m = env < self ? env : self;
+        *fragile = 0;
+        for (int i = 0; i < nb; ++i)
+            if (bbf[i] && bbv[i] < m + 1e-3) *fragile = 1;
+    }
+    free(bbv);
+    free(bbf);
+    free(bc);
     free(c);
     *sd_env = env;
     *sd_self = self;
 }
 
 /* Batch form: flag = [min(sd_env, sd_self) < 0].  Any output may be NULL. */
-void orc_check_batch(const orc_robot *rb, const double *obs, int32_t n_obs, const double *q, int64_t n,
-                     uint8_t *flags, double *min_sd, double *sd_env, double *sd_self) {
+void orc_check_batch(const orc_robot *rb, const double *obs, int32_t n_obs, const double *ebox, int32_t n_ebox,
+                     const double *q, int64_t n, uint8_t *flags, double *min_sd, double *sd_env, double *sd_self,
+                     uint8_t *fragile) {
     const int dof = rb->dof;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < n; ++i) {
         double e, s;
-        orc_check_config(rb, obs, n_obs, q + (size_t)i * dof, &e, &s);
+        int fr = 0;
+        orc_check_config(rb, obs, n_obs, ebox, n_ebox, q + (size_t)i * dof, &e, &s, fragile ? &fr : NULL);
         double m = e < s ? e : s;
         if (flags) flags[i] = (uint8_t)(m < 0.0);
         if (min_sd) min_sd[i] = m;
         if (sd_env) sd_env[i] = e;
         if (sd_self) sd_self[i] = s;
+        if (fragile) fragile[i] = (uint8_t)fr;
     }
 }
 
 double orc_arm_sd(const void *scene, const double *q) {
     const orc_arm_scene *sc = (const orc_arm_scene *)scene;
     double e, s;
-    orc_check_config(sc->robot, sc->obs, sc->n_obs, q, &e, &s);
+    orc_check_config(sc->robot, sc->obs, sc->n_obs, sc->ebox, sc->n_ebox, q, &e, &s, NULL);
     return e < s ? e : s;
 }
 
@@ -538,11 +691,11 @@ int orc_eizo(const void *scene, orc_sd_fn sd, int32_t d, const double *A_D, cons
 }
 
 /* Convenience entry points for the two scene kinds. */
-int orc_eizo_arm(const orc_robot *rb, const double *obs, int32_t n_obs, const double *A_D,
-                 const double *b_D, int32_t n_D, const double *v1, const double *v2,
+int orc_eizo_arm(const orc_robot *rb, const double *obs, int32_t n_obs, const double *ebox, int32_t n_ebox,
+                 const double *A_D, const double *b_D, int32_t n_D, const double *v1, const double *v2,
                  const orc_params *prm, double *A, double *b, int32_t cap, int32_t *n_faces,
                  orc_stats *st) {
-    orc_arm_scene sc = {rb, obs, n_obs};
+    orc_arm_scene sc = {rb, obs, n_obs, ebox, n_ebox};
     return orc_eizo(&sc, orc_arm_sd, rb->dof, A_D, b_D, n_D, v1, v2, prm, A, b, cap, n_faces, st);
 }
 
@@ -554,10 +707,10 @@ int orc_eizo_balls(int32_t dim, const double *centres, const double *radii, int3
     return orc_eizo(&sc, orc_ball_sd, dim, A_D, b_D, n_D, v1, v2, prm, A, b, cap, n_faces, st);
 }
 
-int orc_bisect_arm(const orc_robot *rb, const double *obs, int32_t n_obs, const double *v1,
-                   const double *v2, const double *c, int32_t n_b, double *c_star, double *t_star,
-                   double *a_dir, double *c_proj, double *min_abs_sd, double *sd_trace) {
-    orc_arm_scene sc = {rb, obs, n_obs};
+int orc_bisect_arm(const orc_robot *rb, const double *obs, int32_t n_obs, const double *ebox, int32_t n_ebox,
+                   const double *v1, const double *v2, const double *c, int32_t n_b, double *c_star,
+                   double *t_star, double *a_dir, double *c_proj, double *min_abs_sd, double *sd_trace) {
+    orc_arm_scene sc = {rb, obs, n_obs, ebox, n_ebox};
     return orc_bisect(&sc, orc_arm_sd, rb->dof, v1, v2, c, n_b, c_star, t_star, a_dir, c_proj, min_abs_sd,
                       sd_trace);
 }
