@@ -25,6 +25,12 @@ and data are not public in this form):
            the same box rejected against all 96 swept segments.
   sweep    seed 3: arm of dof7; 256 / 1024 / 4096 obstacles in the box, no
            rejection (configurations are drawn at run time, uniform).
+  boxes    seed 4: the dof7 arm's links covered by 11 boxes (no spheres);
+           box self pairs = links at least two apart, minus pairs touching at
+           q = 0; voxel obstacles (side 0.08 m, circumscribing spheres)
+           filling 6 random boxes in the obstacle box, plus a table box whose
+           top is 20 cm below the base; one segment of length U[0.3, 1.0] rad
+           free of self-collision, voxels and table along its length.
 
 "Along the segment" is checked on a discretisation fine enough that no
 sphere moves more than MARGIN/2 between neighbouring points, so keeping a
@@ -212,7 +218,56 @@ def make_sweep():
     return out
 
 
-MAKERS = dict(tiny=make_tiny, dof7=make_dof7, batched=make_batched, sweep=make_sweep)
+TABLE = np.concatenate([[0.4, 0.0, -0.45], np.eye(3).ravel(), [1.2, 1.2, 0.25]])   # top at z = -0.2
+
+
+def box_reach_sum(desc, half) -> float:
+    """As robot_reach_sum, with the largest box half-diagonal as the radius."""
+    L = np.abs(desc["a"]).astype(np.float64) + np.abs(desc["d"]).astype(np.float64)
+    tail = np.cumsum(L[::-1])[::-1]
+    return float(np.sum(tail + float(np.max(np.linalg.norm(half, axis=1)))))
+
+
+def make_boxes():
+    _, arm, _, _, _ = make_arm7()
+    rng = draw.rng_for(4)
+    bl, bp, bh = draw.arm_boxes(rng, arm)
+    desc = dict(arm, sphere_link=np.zeros(0, np.int32), sphere_xyz=np.zeros((0, 3), np.float32),
+                sphere_r=np.zeros(0, np.float32), box_link=bl, box_pose=bp, box_half=bh)
+    i, j = np.triu_indices(len(bl), 1)
+    cand = np.stack([i, j], axis=1)[np.abs(bl[i] - bl[j]) >= 2].astype(np.int32)
+    keep = []
+    for pr in cand:
+        _, _, _, ss = oracle.check(oracle.Robot(dict(desc, box_pairs=pr[None])), np.zeros((0, 4)),
+                                   np.zeros((1, arm["dof"])))
+        keep.append(ss[0] >= 0.0)
+    bpairs = cand[np.array(keep, bool)]
+    desc["box_pairs"] = bpairs
+    rob = oracle.Robot(desc, np.zeros((0, 2), np.int32))
+    qs = draw.uniform_q(12346, 10_000, arm["q_lo"], arm["q_hi"])
+    _, _, _, ss = oracle.check(rob, np.zeros((0, 4)), qs)
+    frac = float(np.mean(ss < 0))
+    lo, hi = OBS_BOX
+    vox = draw.voxel_obstacles(rng, lo, hi)
+    table = draw._f32(TABLE)[None]
+    reach = box_reach_sum(arm, bh)
+    for _ in range(100_000):
+        e = draw.segment_candidate(rng, arm["q_lo"], arm["q_hi"], rng.uniform(0.3, 1.0))
+        if e is None:
+            continue
+        qd = discretise(e[0], e[1], reach)
+        _, sd, _, _ = oracle.check(rob, vox, qd, env_boxes=table)
+        if np.all(sd >= MARGIN):
+            break
+    else:
+        raise RuntimeError("no free segment found")
+    out = dict(robot_arrays(desc, np.zeros((0, 2), np.int32)), box_link=bl, box_pose=bp, box_half=bh,
+               box_pairs=bpairs, obstacles=vox, env_boxes=table, edges=e[None], path_id=np.zeros(1, np.int32),
+               self_collision_fraction=np.float64(frac))
+    return out
+
+
+MAKERS = dict(tiny=make_tiny, dof7=make_dof7, batched=make_batched, sweep=make_sweep, boxes=make_boxes)
 
 
 def main():

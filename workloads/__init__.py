@@ -30,6 +30,8 @@ PARAMS = {
                  n_f=10, n_b=11, n_mix=60, max_iters=50),
     "batched": dict(eps=0.05, delta=0.05, tau=0.5, step_back_max=0.01, t_col=1e-4, n_p=10000,
                     n_f=10, n_b=11, n_mix=60, max_iters=50),
+    "boxes": dict(eps=0.05, delta=0.05, tau=0.5, step_back_max=0.01, t_col=1e-4, n_p=10000,
+                  n_f=20, n_b=11, n_mix=60, max_iters=50),
 }
 
 
@@ -40,5 +42,10 @@ def load(name: str) -> dict:
     return data
 
 
+BOX_KEYS = ("box_link", "box_pose", "box_half", "box_pairs")
+
+
 def robot(data: dict) -> dict:
-    return {k: data[k] for k in ROBOT_KEYS}
+    out = {k: data[k] for k in ROBOT_KEYS}
+    out.update({k: data[k] for k in BOX_KEYS if k in data})
+    return out

@@ -17,7 +17,16 @@ standing in for):
 * 7-DOF arm: standard DH, a_i, d_i ~ U[0, 0.4] m, alpha_i uniform on
   {0, +pi/2, -pi/2}, 10 spheres per link evenly spaced on the segment from
   the previous frame origin to the link's own origin, radii U[0.03, 0.06] m;
-* joint limits [-pi, pi] on every joint.
+* joint limits [-pi, pi] on every joint;
+* box arm (the iiwa's 11-box model): the 7-DOF arm's links, each covered by
+  a box aligned with the segment from the previous frame origin to the link's
+  own origin (x axis along it), the four longest segments split in two boxes;
+  half widths U[0.04, 0.07] m, lengths covering the segment plus the width at
+  each end; a link whose segment has zero length gets a cube of half width
+  0.05 m at its origin;
+* perceived obstacles: voxels of side 0.08 m filling a few random boxes,
+  each voxel represented by its circumscribing sphere (radius sqrt(3)/2 s),
+  as in the paper's perception pipeline; a table as one box.
 """
 from __future__ import annotations
 
@@ -149,3 +158,55 @@ def uniform_q_fast(seed: int, n: int, q_lo, q_hi) -> np.ndarray:
 
 
 PATH_SEGMENTS = (2, 5, 8, 11, 14, 17, 19, 20)
+
+
+def arm_boxes(rng: np.random.Generator, desc: dict, n_boxes: int = 11):
+    """Boxes on the links of a DH arm (see the module docstring): returns
+    box_link [B], box_pose [B][12] (centre, rotation row-major with the box
+    axes as columns, link frame), box_half [B][3]."""
+    dof = int(desc["dof"])
+    a, d, al = (np.asarray(desc[k], np.float64) for k in ("a", "d", "alpha"))
+    prev = np.stack([-a, -d * np.sin(al), -d * np.cos(al)], axis=1)      # previous origin in frame i
+    length = np.linalg.norm(prev, axis=1)
+    split = set(np.argsort(-length)[:max(0, n_boxes - dof)].tolist())
+    link, pose, half = [], [], []
+    for i in range(dof):
+        w = rng.uniform(0.04, 0.07)
+        if length[i] < 1e-9:
+            link.append(i)
+            pose.append(np.concatenate([np.zeros(3), np.eye(3).ravel()]))
+            half.append([0.05, 0.05, 0.05])
+            continue
+        u = -prev[i] / length[i]                      # from the previous origin towards this one
+        t = np.array([0.0, 0.0, 1.0]) if abs(u[2]) < 0.9 else np.array([1.0, 0.0, 0.0])
+        y = np.cross(t, u)
+        y /= np.linalg.norm(y)
+        z = np.cross(u, y)
+        R = np.stack([u, y, z], axis=1)               # columns = box axes
+        parts = 2 if i in split else 1
+        for k in range(parts):
+            c = prev[i] + (k + 0.5) / parts * (-prev[i])
+            link.append(i)
+            pose.append(np.concatenate([c, R.ravel()]))
+            half.append([length[i] / (2 * parts) + w, w, w])
+    return (np.asarray(link, np.int32), _f32(pose).reshape(-1, 12), _f32(half).reshape(-1, 3))
+
+
+def voxel_obstacles(rng: np.random.Generator, lo, hi, side: float = 0.08, n_shapes: int = 6,
+                    size_lo: float = 0.1, size_hi: float = 0.4):
+    """Voxel spheres [n][4] (centre, r = sqrt(3)/2 side) of the voxels of a
+    side-`side` grid over [lo, hi] whose centres fall in one of n_shapes
+    random axis-aligned boxes (sizes U[size_lo, size_hi] per axis)."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    n = np.floor((hi - lo) / side).astype(int)
+    g = [lo[k] + side * (np.arange(n[k]) + 0.5) for k in range(3)]
+    X, Y, Z = np.meshgrid(*g, indexing="ij")
+    cen = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    keep = np.zeros(len(cen), bool)
+    for _ in range(n_shapes):
+        sz = rng.uniform(size_lo, size_hi, 3)
+        c0 = rng.uniform(lo + sz / 2, hi - sz / 2)
+        keep |= np.all(np.abs(cen - c0) <= sz / 2, axis=1)
+    v = cen[keep]
+    return _f32(np.concatenate([v, np.full((len(v), 1), np.sqrt(3) / 2 * side)], axis=1))
