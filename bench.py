@@ -507,10 +507,10 @@ def main():
     shapes = {e["kernel"]: e for e in ezo.tune_cache_entries() if e["obstacles"] == int(obs.shape[0])}
     if dom == "bisect":
         sb = shapes.get("bisect")
-        instance = f"ezo::k_project_bisect<{sb['T']}, {sb['depth']}>" if sb else None
+        instance = f"ezo::k_project_bisect<{sb['T']}, {sb['depth']}, false>" if sb else None
     else:
         sc = shapes.get("check_flags")
-        instance = f"ezo::k_check<{sc['T']}, false>" if sc else None
+        instance = f"ezo::k_check<{sc['T']}, false, false>" if sc else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_TFLOPS,
                 "traffic": measured_traffic(name, instance) if instance else None,

@@ -42,6 +42,8 @@ extern "C" {
 
 #define EZO_MAX_DOF 8
 #define EZO_MAX_SPHERES 1024
+#define EZO_MAX_BOXES 64
+#define EZO_MAX_OBSTACLE_BOXES 64
 
 typedef struct ezo_ctx ezo_ctx;
 typedef struct ezo_robot ezo_robot;
@@ -85,6 +87,15 @@ typedef struct {
     const double *sphere_r;      /* [S] radius (>= 0)                                */
     int32_t n_self_pairs;        /* >= 0                                             */
     const int32_t *self_pairs;   /* [P][2] sphere indices tested against each other  */
+    /* boxes rigidly attached to links (Sec. IV-D: box and sphere geometries) */
+    int32_t n_boxes;             /* 0..EZO_MAX_BOXES                                 */
+    const int32_t *box_link;     /* [B] link of each box, 0-based                    */
+    const double *box_pose;      /* [B][12] centre (x, y, z), then the rotation
+                                    (3x3, row-major, columns = the box axes), in
+                                    the link frame                                  */
+    const double *box_half;      /* [B][3] half extents along the box axes, >= 0     */
+    int32_t n_box_pairs;         /* >= 0                                             */
+    const int32_t *box_pairs;    /* [Q][2] box indices tested against each other     */
 } ezo_robot_desc;
 
 /* EI-ZO parameters: Alg. 1 Input (delta, eps, tau, Delta_max, N_p, N_f, N_b)
@@ -129,6 +140,14 @@ typedef struct {
 ezo_status ezo_ctx_create(int32_t device, ezo_ctx **out);
 void ezo_ctx_destroy(ezo_ctx *ctx);
 
+/* Obstacle boxes of the context (e.g. a table), in addition to the obstacle
+ * spheres each call passes: every check, inflation, bisection and path check
+ * on the context tests them.  boxes host f32 [n][15]: centre (x, y, z),
+ * rotation (3x3, row-major, columns = the box axes), half extents, world
+ * frame; copied.  n = 0 removes them.  EZO_E_UNSUPPORTED above
+ * EZO_MAX_OBSTACLE_BOXES. */
+ezo_status ezo_set_obstacle_boxes(ezo_ctx *ctx, const float *boxes, int32_t n);
+
 /* Text of the last error on ctx (or of the last failed ezo_ctx_create when
  * ctx is NULL).  Valid until the next call on that context. */
 const char *ezo_last_error(const ezo_ctx *ctx);
@@ -147,7 +166,20 @@ void ezo_robot_destroy(ezo_robot *robot);
  *   robot-obstacle pairs  |c_s - o| - r_s - r_o   (obstacles obs[n_obs][4] =
  *                                                 x, y, z, r; dev, FP32)
  *   listed self pairs     |c_s - c_t| - r_s - r_t
- * and flags[i] = 1 iff that minimum is < 0 (dev u8[n]).
+ * and, with boxes (robot boxes, the context's obstacle boxes),
+ *   sphere-box pairs      the exact signed distance: outside the box the
+ *                         distance from the centre to the box minus r, inside
+ *                         minus (the distance to the nearest face + r)
+ *   box-box pairs         the separating-axis value: the largest, over the 6
+ *                         face normals and the 9 edge-edge cross products
+ *                         (unit; those with |A_i x B_j|^2 < 1e-12 skipped), of
+ *                         |t.L| - r_A(L) - r_B(L) (t = centre offset, r_X(L) =
+ *                         sum_k h_k |X_k . L|); the penetration depth when the
+ *                         boxes overlap, a lower bound of their distance when
+ *                         apart
+ * (robot boxes against obstacle spheres and boxes, robot spheres against
+ * obstacle boxes, the listed box self pairs) and flags[i] = 1 iff that
+ * minimum is < 0 (dev u8[n]).
  * If min_sd and min_sd_self are both NULL only flags are computed, and a
  * configuration stops being tested at its first colliding pair.  Otherwise
  * min_sd[i] (dev f32[n], may be NULL) receives the overall minimum and

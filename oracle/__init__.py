@@ -205,8 +205,9 @@ def _ebox(env_boxes):
 
 def check(robot: Robot, obs, q, env_boxes=None, fragile=False):
     """Returns (flags u8[n], min_sd[n], sd_env[n], sd_self[n]) for q [n][dof];
-    with fragile=True also fragile u8[n]: some box-box pair near the minimum
-    rests on a separating axis of nearly parallel edges (sat_boxes)."""
+    with fragile=True also fragile u8[n], bits as in sat_boxes: bit 0, some
+    box-box pair within 1e-3 of the minimum of its kind (obstacle or self)
+    has a fragile value; bit 1, some box-box pair has a fragile sign."""
     q = _d(q).reshape(-1, robot.dof)
     obs = _d(obs).reshape(-1, 4)
     eb = _ebox(env_boxes)
@@ -226,11 +227,13 @@ def sd_sphere_box(x, r, c, R, h):
 
 
 def sat_boxes(cA, RA, hA, cB, RB, hB):
-    """(separating-axis value, fragile) of two boxes."""
+    """(separating-axis value, fragile bits) of two boxes: bit 0 the value,
+    bit 1 the sign may change under FP32 rounding of the poses (a cross axis
+    of nearly parallel edges decides)."""
     f = C.c_int()
     v = lib().orc_sat_boxes(_ptr(_d(cA)), _ptr(_d(RA).reshape(9)), _ptr(_d(hA)), _ptr(_d(cB)),
                             _ptr(_d(RB).reshape(9)), _ptr(_d(hB)), C.byref(f))
-    return v, bool(f.value)
+    return v, int(f.value)
 
 
 def philox(ctr, key):

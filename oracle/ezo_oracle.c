@@ -183,9 +183,12 @@ double orc_sd_sphere_box(const double x[3], double r, const double c[3], const d
  * t the centre offset and r_X(L) = sum_k h_k |X_k . L| the box's half width
  * along L.  Positive: the boxes are apart (a lower bound on their distance);
  * otherwise minus the smallest overlap over the axes, which for two boxes is
- * the penetration depth.  *fragile (may be NULL) is set when a cross axis
- * with |A_i x B_j| < 0.05 (nearly parallel edges, where FP32 rounding of the
- * poses is amplified) comes within 1e-3 of the value or within 1e-4 of 0. */
+ * the penetration depth.  *fragile (may be NULL) flags where FP32 rounding
+ * of the poses, amplified on a cross axis of nearly parallel edges
+ * (|A_i x B_j| < 0.05, a "weak" axis), can change the result: bit 0 (the
+ * value) when a weak axis comes within 1e-3 of the value or within 1e-4 of
+ * 0; bit 1 (the sign) when the value is set by a weak axis, is above -5e-5,
+ * and the other axes alone give less than 5e-5. */
 double orc_sat_boxes(const double cA[3], const double RA[9], const double hA[3], const double cB[3],
                      const double RB[9], const double hB[3], int *fragile) {
     double Ax[3][3], Bx[3][3], t[3];
@@ -196,7 +199,7 @@ double orc_sat_boxes(const double cA[3], const double RA[9], const double hA[3],
         }
         t[k] = cB[k] - cA[k];
     }
-    double best = -INFINITY;
+    double best = -INFINITY, best_good = -INFINITY;
     double weak[9];
     int n_weak = 0;
     for (int a = 0; a < 15; ++a) {
@@ -222,12 +225,16 @@ double orc_sat_boxes(const double cA[3], const double RA[9], const double hA[3],
         }
         const double sep = fabs(t[0] * L[0] + t[1] * L[1] + t[2] * L[2]) - rA - rB;
         if (sep > best) best = sep;
-        if (a >= 6 && norm < 0.05) weak[n_weak++] = sep;
+        if (a >= 6 && norm < 0.05)
+            weak[n_weak++] = sep;
+        else if (sep > best_good)
+            best_good = sep;
     }
     if (fragile) {
         *fragile = 0;
         for (int i = 0; i < n_weak; ++i)
-            if (weak[i] > best - 1e-3 || fabs(weak[i]) < 1e-4) *fragile = 1;
+            if (weak[i] > best - 1e-3 || fabs(weak[i]) < 1e-4) *fragile |= 1;
+        if (best > best_good && best > -5e-5 && best_good < 5e-5) *fragile |= 2;
     }
     return best;
 }
@@ -237,8 +244,10 @@ double orc_sat_boxes(const double cA[3], const double RA[9], const double hA[3],
  * pairs: robot spheres and boxes against obstacle spheres and boxes
  * (sphere-sphere: centre distance minus radii; sphere-box: orc_sd_sphere_box;
  * box-box: orc_sat_boxes).  Self pairs: the sphere pairs and the box pairs.
- * *fragile (may be NULL): some box-box pair within 1e-3 of the overall
- * minimum has a fragile separating-axis value. */
+ * *fragile (may be NULL): bit 0 when some box-box pair within 1e-3 of the
+ * minimum of its own kind (sd_env for obstacle boxes, sd_self for box self
+ * pairs) has a fragile value, bit 1 when some box-box pair has a fragile
+ * sign (orc_sat_boxes). */
 void orc_check_config(const orc_robot *rb, const double *obs, int32_t n_obs, const double *ebox, int32_t n_ebox,
                       const double *q, double *sd_env, double *sd_self, int *fragile) {
     double *c = (double *)malloc(sizeof(double) * 3 * (size_t)(rb->n_spheres > 0 ? rb->n_spheres : 1));
@@ -264,11 +273,13 @@ void orc_check_config(const orc_robot *rb, const double *obs, int32_t n_obs, con
             double sd = orc_sd_sphere_box(c + 3 * s, rb->sphere_r[s], E, E + 3, E + 12);
             if (sd < env) env = sd;
         }
-    /* box-box values with their fragility, kept until the minimum is known */
+    /* box-box values with their fragility, kept until the minima are known;
+       the first n_eb are obstacle-box pairs */
     const int n_bb = B * n_ebox + rb->n_box_pairs;
     double *bbv = (double *)malloc(sizeof(double) * (size_t)(n_bb > 0 ? n_bb : 1));
     int *bbf = (int *)malloc(sizeof(int) * (size_t)(n_bb > 0 ? n_bb : 1));
     int nb = 0;
+    const int n_eb = B * n_ebox;
     for (int k = 0; k < B; ++k) {
         const double *h = rb->box_half + 3 * k;
         for (int o = 0; o < n_obs; ++o) {
@@ -295,10 +306,11 @@ void orc_check_config(const orc_robot *rb, const double *obs, int32_t n_obs, con
         if (sd < self) self = sd;
     }
     if (fragile) {
-        const double m = env < self ? env : self;
         *fragile = 0;
-        for (int i = 0; i < nb; ++i)
-            if (bbf[i] && bbv[i] < m + 1e-3) *fragile = 1;
+        for (int i = 0; i < nb; ++i) {
+            if ((bbf[i] & 1) && bbv[i] < (i < n_eb ? env : self) + 1e-3) *fragile |= 1;
+            *fragile |= bbf[i] & 2;
+        }
     }
     free(bbv);
     free(bbf);

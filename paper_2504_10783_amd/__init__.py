@@ -22,7 +22,8 @@ CERTIFIED, MAX_ITERS, IN_COLLISION, INVALID, CONTAINED = 0, 1, 2, 3, 4
 MAX_DOF = 8
 
 EXPORTS = (
-    "ezo_ctx_create", "ezo_ctx_destroy", "ezo_last_error", "ezo_robot_create", "ezo_robot_destroy",
+    "ezo_ctx_create", "ezo_ctx_destroy", "ezo_last_error", "ezo_set_obstacle_boxes", "ezo_robot_create",
+    "ezo_robot_destroy",
     "ezo_check_collisions", "ezo_sphere_centres", "ezo_test_constants", "ezo_sample_polytopes",
     "ezo_test_and_select", "ezo_project_bisect", "ezo_place_hyperplanes", "ezo_inflate_edges", "ezo_inflate_paths",
     "ezo_set_phase_timing", "ezo_get_phase_timing",
@@ -46,7 +47,10 @@ class RobotDesc(C.Structure):
                 ("dh_d", C.POINTER(C.c_double)), ("q_lo", C.POINTER(C.c_double)), ("q_hi", C.POINTER(C.c_double)),
                 ("n_spheres", C.c_int32), ("sphere_link", C.POINTER(C.c_int32)),
                 ("sphere_xyz", C.POINTER(C.c_double)), ("sphere_r", C.POINTER(C.c_double)),
-                ("n_self_pairs", C.c_int32), ("self_pairs", C.POINTER(C.c_int32))]
+                ("n_self_pairs", C.c_int32), ("self_pairs", C.POINTER(C.c_int32)),
+                ("n_boxes", C.c_int32), ("box_link", C.POINTER(C.c_int32)), ("box_pose", C.POINTER(C.c_double)),
+                ("box_half", C.POINTER(C.c_double)), ("n_box_pairs", C.c_int32),
+                ("box_pairs", C.POINTER(C.c_int32))]
 
 
 class Params(C.Structure):
@@ -85,6 +89,7 @@ def lib():
         L.ezo_ctx_destroy.restype = None
         L.ezo_last_error.argtypes = [vp]
         L.ezo_last_error.restype = C.c_char_p
+        L.ezo_set_obstacle_boxes.argtypes = [vp, C.POINTER(C.c_float), i32]
         L.ezo_robot_create.argtypes = [vp, C.POINTER(RobotDesc), C.POINTER(vp)]
         L.ezo_robot_destroy.argtypes = [vp]
         L.ezo_robot_destroy.restype = None
@@ -223,6 +228,13 @@ class Context:
         except Exception:
             pass
 
+    def set_obstacle_boxes(self, boxes):
+        """Obstacle boxes tested by every call on this context: [n][15] =
+        centre (3), rotation (9, row-major, columns = box axes), half
+        extents (3), world frame.  None or an empty array removes them."""
+        b = np.ascontiguousarray(np.zeros((0, 15)) if boxes is None else boxes, dtype=np.float32).reshape(-1, 15)
+        self._check(lib().ezo_set_obstacle_boxes(self.h, b.ctypes.data_as(C.POINTER(C.c_float)), len(b)))
+
     def set_autotune(self, enable: bool):
         """Time launch shapes on the first call with a new tuning key (default on)."""
         self._check(lib().ezo_set_autotune(self.h, 1 if enable else 0))
@@ -259,15 +271,26 @@ class Robot:
                           xyz=np.ascontiguousarray(desc["sphere_xyz"], dtype=np.float64).reshape(-1, 3),
                           r=f64("sphere_r"),
                           pairs=np.ascontiguousarray(desc.get("self_pairs", np.zeros((0, 2))),
-                                                     dtype=np.int32).reshape(-1, 2))
+                                                     dtype=np.int32).reshape(-1, 2),
+                          box_link=np.ascontiguousarray(desc.get("box_link", np.zeros(0)), dtype=np.int32),
+                          box_pose=np.ascontiguousarray(desc.get("box_pose", np.zeros((0, 12))),
+                                                        dtype=np.float64).reshape(-1, 12),
+                          box_half=np.ascontiguousarray(desc.get("box_half", np.zeros((0, 3))),
+                                                        dtype=np.float64).reshape(-1, 3),
+                          box_pairs=np.ascontiguousarray(desc.get("box_pairs", np.zeros((0, 2))),
+                                                         dtype=np.int32).reshape(-1, 2))
         k = self._keep
         dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
         ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
         self.dof = int(desc["dof"])
         self.n_spheres = len(k["r"])
         self.n_self = len(k["pairs"])
+        self.n_boxes = len(k["box_link"])
+        self.n_box_pairs = len(k["box_pairs"])
         d = RobotDesc(self.dof, dp(k["a"]), dp(k["alpha"]), dp(k["d"]), dp(k["q_lo"]), dp(k["q_hi"]),
-                      self.n_spheres, ip(k["link"]), dp(k["xyz"]), dp(k["r"]), self.n_self, ip(k["pairs"]))
+                      self.n_spheres, ip(k["link"]), dp(k["xyz"]), dp(k["r"]), self.n_self, ip(k["pairs"]),
+                      self.n_boxes, ip(k["box_link"]), dp(k["box_pose"]), dp(k["box_half"]), self.n_box_pairs,
+                      ip(k["box_pairs"]))
         h = C.c_void_p()
         ctx._check(lib().ezo_robot_create(ctx.h, C.byref(d), C.byref(h)))
         self.h = h

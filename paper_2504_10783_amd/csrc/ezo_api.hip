@@ -109,6 +109,8 @@ ezo_status prep_obstacles(ezo_ctx* c, const ezo_robot* r, const float* obs, int 
     ov->lds_n = 0;
     ov->rec = (const float4*)rec;
     ov->centre = (const float4*)centre;
+    ov->n_ebox = c->n_ebox;
+    ov->ebox = c->ebox;
     gv->G = G;
     gv->cap = kGridCap;
     gv->geom = (const GridGeom*)geom;
@@ -145,6 +147,7 @@ TuneKey tune_key(const ezo_ctx* c, const ezo_robot* r, TuneKind kind, int n_obs,
     k.dof = r->dof;
     k.S = r->S;
     k.P = r->P;
+    k.B = r->B;
     k.n_obs = n_obs;
     k.bucket = ezo_tune_bucket(items);
     return k;
@@ -154,8 +157,8 @@ TuneKey tune_key(const ezo_ctx* c, const ezo_robot* r, TuneKind kind, int n_obs,
 TileCfg heuristic_check(const ezo_ctx* c, const ezo_robot* r, int n_obs, int64_t items, bool sd) {
     TileCfg g;
     g.W = sd ? pick_W(n_obs) : 4;
-    g.T = pick_T(c, items, r->S, g.W);
-    g.stage = (!sd && stage_fits(c, g.T, r->S, g.W, n_obs)) ? 1 : 0;
+    g.T = pick_T(c, items, r->slots, g.W);
+    g.stage = (!sd && stage_fits(c, g.T, r->slots, g.W, n_obs)) ? 1 : 0;
     return g;
 }
 
@@ -164,8 +167,8 @@ TileCfg heuristic_bisect(const ezo_ctx* c, const ezo_robot* r, int n_obs, int64_
     TileCfg g;
     g.W = 4;
     g.depth = 1;
-    g.T = std::max(std::min(pick_T(c, items, r->S, g.W), 64), 2);
-    g.stage = stage_fits(c, g.T, r->S, g.W, n_obs) ? 1 : 0;
+    g.T = std::max(std::min(pick_T(c, items, r->slots, g.W), 64), 2);
+    g.stage = stage_fits(c, g.T, r->slots, g.W, n_obs) ? 1 : 0;
     return g;
 }
 
@@ -206,19 +209,26 @@ ezo_status launch_check(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const
     } else {
         const int64_t items = n * n_batch;
         g = resolve_cfg(c, tune_key(c, r, SD ? TUNE_CHECK_SD : TUNE_CHECK_FLAGS, ov.n, items),
-                        heuristic_check(c, r, ov.n, items, SD), r->S, ov.n, SD);
+                        heuristic_check(c, r, ov.n, items, SD), r->slots, ov.n, SD);
     }
     const int T = g.T, W = g.W;
     if (T == 0) return ezo_fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
     ObsView ovs = ov;
     ovs.lds_n = g.stage ? ov.n : 0;
-    const size_t lds = tile_smem_bytes(T, r->S, W) + 16 * (size_t)ovs.lds_n;
+    const size_t lds = tile_smem_bytes(T, r->slots, W) + 16 * (size_t)ovs.lds_n;
     const int64_t tiles = (n + T - 1) / T;
     if (tiles <= 0) return EZO_OK;
     dim3 grid((unsigned)tiles, (unsigned)n_batch), block(64 * W);
-#define EZO_LAUNCH_CHECK(TT)                                                                          \
-    EZO_KLAUNCH(c, (k_check<TT, SD>), grid, block, lds, st, r->view, ovs, gv, q, n, sn, sd, q_batch, flags, \
-                       min_sd, min_sd_self, out_batch, status, it, pred, margin, stats)
+    const bool box = r->B > 0 || ov.n_ebox > 0;
+#define EZO_LAUNCH_CHECK(TT)                                                                                   \
+    do {                                                                                                       \
+        if (box)                                                                                               \
+            EZO_KLAUNCH(c, (k_check<TT, SD, true>), grid, block, lds, st, r->view, ovs, gv, q, n, sn, sd, q_batch, \
+                        flags, min_sd, min_sd_self, out_batch, status, it, pred, margin, stats);               \
+        else                                                                                                   \
+            EZO_KLAUNCH(c, (k_check<TT, SD, false>), grid, block, lds, st, r->view, ovs, gv, q, n, sn, sd,      \
+                        q_batch, flags, min_sd, min_sd_self, out_batch, status, it, pred, margin, stats);      \
+    } while (0)
     switch (T) {
         case 64: EZO_LAUNCH_CHECK(64); break;
         case 32: EZO_LAUNCH_CHECK(32); break;
@@ -337,7 +347,7 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
         g = *shape;
     } else {
         const int64_t items = (int64_t)cand_cap * E;
-        g = resolve_cfg(c, tune_key(c, r, TUNE_BISECT, ov.n, items), heuristic_bisect(c, r, ov.n, items), r->S,
+        g = resolve_cfg(c, tune_key(c, r, TUNE_BISECT, ov.n, items), heuristic_bisect(c, r, ov.n, items), r->slots,
                         ov.n, false, true);
     }
     const int TC = g.T, W = g.W, dp = g.depth;
@@ -345,12 +355,19 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
         return ezo_fail(c, EZO_E_INVALID, "bisection shape T=%d W=%d depth=%d", TC, W, dp);
     ObsView ovs = ov;
     ovs.lds_n = g.stage ? ov.n : 0;
-    const size_t lds = tile_smem_bytes(tile_configs(g, true), r->S, W) + 16 * (size_t)ovs.lds_n;
+    const size_t lds = tile_smem_bytes(tile_configs(g, true), r->slots, W) + 16 * (size_t)ovs.lds_n;
     if (lds > c->lds_cap) return ezo_fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
     dim3 grid((unsigned)((cand_cap + TC - 1) / TC), (unsigned)E), block(64 * W);
-#define EZO_LAUNCH_PB(TT, DD)                                                                                    \
-    EZO_KLAUNCH(c, (k_project_bisect<TT, DD>), grid, block, lds, st, r->view, ovs, gv, edges, S, stride, s_edge, cand_idx, \
-                       n_cands, cand_cap, n_b, c_star, a_dir, t_star, pcol, pany, status)
+    const bool box = r->B > 0 || ov.n_ebox > 0;
+#define EZO_LAUNCH_PB(TT, DD)                                                                                       \
+    do {                                                                                                            \
+        if (box)                                                                                                    \
+            EZO_KLAUNCH(c, (k_project_bisect<TT, DD, true>), grid, block, lds, st, r->view, ovs, gv, edges, S, stride, \
+                        s_edge, cand_idx, n_cands, cand_cap, n_b, c_star, a_dir, t_star, pcol, pany, status);         \
+        else                                                                                                        \
+            EZO_KLAUNCH(c, (k_project_bisect<TT, DD, false>), grid, block, lds, st, r->view, ovs, gv, edges, S,       \
+                        stride, s_edge, cand_idx, n_cands, cand_cap, n_b, c_star, a_dir, t_star, pcol, pany, status); \
+    } while (0)
     if (dp == 1) {
         switch (TC) {
             case 64: EZO_LAUNCH_PB(64, 1); break;
@@ -398,8 +415,8 @@ ezo_status tune_check_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov,
     if (!c->autotune || ezo_tune_lookup(k, &g)) return EZO_OK;
     const int64_t n_t = SD ? std::min<int64_t>(n, std::max<int64_t>(65536, (1LL << 28) / std::max(ov.n, 256)))
                            : std::min<int64_t>(n, 1LL << 19);
-    const auto cands = SD ? tile_candidates(c, r->S, ov.n, true, {1, 2, 4, 8, 16}, n_t)
-                          : tile_candidates(c, r->S, ov.n, false, {1, 2, 4, 8}, n_t);
+    const auto cands = SD ? tile_candidates(c, r->slots, ov.n, true, {1, 2, 4, 8, 16}, n_t)
+                          : tile_candidates(c, r->slots, ov.n, false, {1, 2, 4, 8}, n_t);
     if (cands.empty()) return EZO_OK;
     IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
     auto run = [&](const TileCfg& cfg) {
@@ -417,7 +434,7 @@ ezo_status tune_bisect_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov
     const TuneKey k = tune_key(c, r, TUNE_BISECT, ov.n, (int64_t)cand_cap * E);
     TileCfg g;
     if (!c->autotune || ezo_tune_lookup(k, &g)) return EZO_OK;
-    const auto cands = tile_candidates(c, r->S, ov.n, false, {1, 2, 4, 8}, (int64_t)cand_cap * E, true);
+    const auto cands = tile_candidates(c, r->slots, ov.n, false, {1, 2, 4, 8}, (int64_t)cand_cap * E, true);
     if (cands.empty()) return EZO_OK;
     auto run = [&](const TileCfg& cfg) {
         return launch_project_bisect(c, r, ov, gv, edges, E, S, stride, cand_idx, n_cands, cand_cap, n_b, c_star,
@@ -463,7 +480,7 @@ ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, con
                                    stride, E, nullptr, it, st, nullptr, 0.f, nullptr, &cfg);
     };
     if (need_c) {
-        const auto cands = tile_candidates(c, r->S, ov.n, false, {1, 2, 4, 8}, (int64_t)S_cap * E);
+        const auto cands = tile_candidates(c, r->slots, ov.n, false, {1, 2, 4, 8}, (int64_t)S_cap * E);
         if (!cands.empty() && (s = ezo_tune_search(c, kc, cands, st, run_c, &g))) return s;
     }
     if (!need_b) return EZO_OK;
@@ -472,7 +489,7 @@ ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, con
     hipLaunchKernelGGL(k_test_select, dim3(E), dim3(1024), 0, st, w_f, stride, p->n_p, p->n_b, w_ci, cand_cap, w_nc,
                        nullptr, nullptr, nullptr, nullptr, sel);
     HIP_TRY(c, hipGetLastError());
-    const auto cands = tile_candidates(c, r->S, ov.n, false, {1, 2, 4, 8}, (int64_t)cand_cap * E, true);
+    const auto cands = tile_candidates(c, r->slots, ov.n, false, {1, 2, 4, 8}, (int64_t)cand_cap * E, true);
     if (cands.empty()) return EZO_OK;
     auto run_b = [&](const TileCfg& cfg) {
         return launch_project_bisect(c, r, ov, gv, edges, E, w_s, stride, w_ci, w_nc, cand_cap, p->n_b, w_cs, w_ad,
@@ -537,6 +554,7 @@ void ezo_ctx_destroy(ezo_ctx* c) {
         if (ev) e = hipEventDestroy(ev);
     if (c->loop_exec) e = hipGraphExecDestroy(c->loop_exec);
     if (c->d_tests) e = hipFree(c->d_tests);
+    if (c->ebox) e = hipFree(c->ebox);
     if (c->stream) e = hipStreamDestroy(c->stream);
     (void)e;
     (void)hipGetLastError();
@@ -544,6 +562,38 @@ void ezo_ctx_destroy(ezo_ctx* c) {
 }
 
 const char* ezo_last_error(const ezo_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+ezo_status ezo_set_obstacle_boxes(ezo_ctx* c, const float* boxes, int32_t n) {
+    if (!c) return EZO_E_INVALID;
+    if (n < 0 || (n > 0 && !boxes)) return ezo_fail(c, EZO_E_INVALID, "bad argument");
+    if (n > EZO_MAX_OBSTACLE_BOXES)
+        return ezo_fail(c, EZO_E_UNSUPPORTED, "%d obstacle boxes (at most %d)", n, EZO_MAX_OBSTACLE_BOXES);
+    std::vector<float4> pk(4 * (size_t)std::max(n, 1));
+    for (int e = 0; e < n; ++e) {
+        const float* x = boxes + 15 * (size_t)e;
+        for (int i = 0; i < 15; ++i)
+            if (!std::isfinite(x[i])) return ezo_fail(c, EZO_E_INVALID, "obstacle box %d not finite", e);
+        if (x[12] < 0.f || x[13] < 0.f || x[14] < 0.f)
+            return ezo_fail(c, EZO_E_INVALID, "obstacle box %d has a negative half extent", e);
+        const double rad = std::sqrt((double)x[12] * x[12] + (double)x[13] * x[13] + (double)x[14] * x[14]);
+        pk[4 * e] = make_float4(x[0], x[1], x[2], x[12]);
+        pk[4 * e + 1] = make_float4(x[3], x[4], x[5], x[13]);
+        pk[4 * e + 2] = make_float4(x[6], x[7], x[8], x[14]);
+        pk[4 * e + 3] = make_float4(x[9], x[10], x[11], (float)(rad * (1.0 + 1e-5) + 1e-5));
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));        // no call in flight still reads the old boxes
+    if (!c->ebox) {
+        // allocated once at the maximum size, so the address never changes
+        if (hipMalloc((void**)&c->ebox, sizeof(float4) * 4 * EZO_MAX_OBSTACLE_BOXES) != hipSuccess) {
+            c->ebox = nullptr;
+            return ezo_fail(c, EZO_E_NOMEM, "obstacle box allocation failed");
+        }
+    }
+    if (n > 0) HIP_TRY(c, hipMemcpy(c->ebox, pk.data(), sizeof(float4) * 4 * (size_t)n, hipMemcpyHostToDevice));
+    c->n_ebox = n;
+    return EZO_OK;
+}
 
 ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out) {
     if (!c || !d || !out) return ezo_fail(c, EZO_E_INVALID, "NULL argument");
@@ -568,6 +618,24 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     for (int p = 0; p < 2 * P; ++p)
         if (d->self_pairs[p] < 0 || d->self_pairs[p] >= S)
             return ezo_fail(c, EZO_E_INVALID, "self pair entry %d = %d out of range", p, d->self_pairs[p]);
+    if (d->n_boxes < 0 || d->n_boxes > EZO_MAX_BOXES)
+        return ezo_fail(c, EZO_E_UNSUPPORTED, "n_boxes %d not in [0, %d]", d->n_boxes, EZO_MAX_BOXES);
+    if (d->n_box_pairs < 0) return ezo_fail(c, EZO_E_INVALID, "n_box_pairs < 0");
+    if (d->n_boxes > 0 && (!d->box_link || !d->box_pose || !d->box_half))
+        return ezo_fail(c, EZO_E_INVALID, "NULL box array");
+    if (d->n_box_pairs > 0 && !d->box_pairs) return ezo_fail(c, EZO_E_INVALID, "NULL box_pairs");
+    for (int k = 0; k < d->n_boxes; ++k) {
+        if (d->box_link[k] < 0 || d->box_link[k] >= dof)
+            return ezo_fail(c, EZO_E_INVALID, "box %d has link %d", k, d->box_link[k]);
+        for (int i = 0; i < 12; ++i)
+            if (!std::isfinite(d->box_pose[12 * k + i])) return ezo_fail(c, EZO_E_INVALID, "box %d pose not finite", k);
+        for (int i = 0; i < 3; ++i)
+            if (!(d->box_half[3 * k + i] >= 0.0) || !std::isfinite(d->box_half[3 * k + i]))
+                return ezo_fail(c, EZO_E_INVALID, "box %d has a bad half extent", k);
+    }
+    for (int p = 0; p < 2 * d->n_box_pairs; ++p)
+        if (d->box_pairs[p] < 0 || d->box_pairs[p] >= d->n_boxes)
+            return ezo_fail(c, EZO_E_INVALID, "box pair entry %d = %d out of range", p, d->box_pairs[p]);
     // sort spheres by link (stable), remember the original order
     std::vector<int> order(S);
     for (int s = 0; s < S; ++s) order[s] = s;
@@ -632,7 +700,31 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
         lbound[j] = make_float4((float)cc[0], (float)cc[1], (float)cc[2], (float)(R * (1.0 + 1e-5) + 1e-5));
     }
     for (int s2 = 0; s2 < S; ++s2) r_max = std::max(r_max, sph[s2].w);
-    // one allocation: [dh][sph][pairs][lbound][blocks][link_begin][s2o][limits]
+    // boxes sorted by link (stable); four float4 each: (centre, h_x), (rotation
+    // row 0, h_y), (row 1, h_z), (row 2, bounding radius |h| padded for FP32)
+    const int B = d->n_boxes, Q = d->n_box_pairs;
+    std::vector<int> border(B);
+    for (int k = 0; k < B; ++k) border[k] = k;
+    std::stable_sort(border.begin(), border.end(), [&](int x, int y) { return d->box_link[x] < d->box_link[y]; });
+    std::vector<int> box_o2s(std::max(B, 1));
+    std::vector<float4> boxv(4 * (size_t)std::max(B, 1), make_float4(0.f, 0.f, 0.f, 0.f));
+    std::vector<int> box_begin(dof + 1, 0);
+    std::vector<int2> bpairs(std::max(Q, 1), make_int2(0, 0));
+    for (int k = 0; k < B; ++k) {
+        const int o = border[k];
+        box_o2s[o] = k;
+        const double* ps = d->box_pose + 12 * (size_t)o;
+        const double* h = d->box_half + 3 * (size_t)o;
+        const double rad = std::sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+        boxv[4 * k] = make_float4((float)ps[0], (float)ps[1], (float)ps[2], (float)h[0]);
+        boxv[4 * k + 1] = make_float4((float)ps[3], (float)ps[4], (float)ps[5], (float)h[1]);
+        boxv[4 * k + 2] = make_float4((float)ps[6], (float)ps[7], (float)ps[8], (float)h[2]);
+        boxv[4 * k + 3] = make_float4((float)ps[9], (float)ps[10], (float)ps[11], (float)(rad * (1.0 + 1e-5) + 1e-5));
+        box_begin[d->box_link[o] + 1]++;
+    }
+    for (int j = 0; j < dof; ++j) box_begin[j + 1] += box_begin[j];
+    for (int p = 0; p < Q; ++p) bpairs[p] = make_int2(box_o2s[d->box_pairs[2 * p]], box_o2s[d->box_pairs[2 * p + 1]]);
+    // one allocation: [dh][sph][pairs][lbound][blocks][link_begin][s2o][limits][boxes][box_begin][box pairs]
     size_t off_dh = 0;
     size_t off_sph = off_dh + sizeof(float4) * dof;
     size_t off_pairs = off_sph + sizeof(float4) * sph.size();
@@ -641,7 +733,10 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     size_t off_lb = off_blk + sizeof(int4) * blocks.size();
     size_t off_s2o = off_lb + sizeof(int) * link_begin.size();
     size_t off_lim = off_s2o + sizeof(int) * s2o.size();
-    size_t total = off_lim + sizeof(float) * lim.size();
+    size_t off_box = (off_lim + sizeof(float) * lim.size() + 15) & ~(size_t)15;
+    size_t off_bb = off_box + sizeof(float4) * boxv.size();
+    size_t off_bp = off_bb + sizeof(int) * box_begin.size();
+    size_t total = off_bp + sizeof(int2) * bpairs.size();
     std::vector<char> host(total);
     memcpy(host.data() + off_dh, dh.data(), sizeof(float4) * dof);
     memcpy(host.data() + off_sph, sph.data(), sizeof(float4) * sph.size());
@@ -651,6 +746,9 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     memcpy(host.data() + off_lb, link_begin.data(), sizeof(int) * link_begin.size());
     memcpy(host.data() + off_s2o, s2o.data(), sizeof(int) * s2o.size());
     memcpy(host.data() + off_lim, lim.data(), sizeof(float) * lim.size());
+    memcpy(host.data() + off_box, boxv.data(), sizeof(float4) * boxv.size());
+    memcpy(host.data() + off_bb, box_begin.data(), sizeof(int) * box_begin.size());
+    memcpy(host.data() + off_bp, bpairs.data(), sizeof(int2) * bpairs.size());
     HIP_TRY(c, hipSetDevice(c->device));
     void* buf = nullptr;
     if (hipMalloc(&buf, total) != hipSuccess) return ezo_fail(c, EZO_E_NOMEM, "robot allocation failed");
@@ -665,6 +763,9 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     r->dof = dof;
     r->S = S;
     r->P = P;
+    r->B = B;
+    r->Q = Q;
+    r->slots = tile_slots(S, B);
     r->buf = buf;
     char* b = reinterpret_cast<char*>(buf);
     r->r_max = r_max;
@@ -678,6 +779,11 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     r->view.sph = reinterpret_cast<const float4*>(b + off_sph);
     r->view.pairs = reinterpret_cast<const int2*>(b + off_pairs);
     r->view.link_begin = reinterpret_cast<const int*>(b + off_lb);
+    r->view.n_boxes = B;
+    r->view.n_box_pairs = Q;
+    r->view.box = reinterpret_cast<const float4*>(b + off_box);
+    r->view.box_begin = reinterpret_cast<const int*>(b + off_bb);
+    r->view.box_pairs = reinterpret_cast<const int2*>(b + off_bp);
     r->sorted_to_orig = reinterpret_cast<const int*>(b + off_s2o);
     r->q_lo = reinterpret_cast<const float*>(b + off_lim);
     r->q_hi = r->q_lo + dof;
@@ -744,8 +850,8 @@ ezo_status ezo_sphere_centres(ezo_ctx* c, const ezo_robot* r, const float* q, in
     ezo_status s = prep_obstacles(c, r, nullptr, 0, st, &ov, &gv);   // zero shift
     if (s) return s;
     int T = 16;
-    while (T > 1 && tile_smem_bytes(T, r->S, 4) > c->lds_cap) T >>= 1;
-    const size_t lds = tile_smem_bytes(T, r->S, 4);
+    while (T > 1 && tile_smem_bytes(T, r->slots, 4) > c->lds_cap) T >>= 1;
+    const size_t lds = tile_smem_bytes(T, r->slots, 4);
     dim3 grid((unsigned)((n + T - 1) / T)), block(256);
     switch (T) {
         case 16: hipLaunchKernelGGL(k_centres<16>, grid, block, lds, st, r->view, ov, r->sorted_to_orig, q, n, stride_n, stride_d, centres); break;
@@ -1031,6 +1137,8 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         push(st);
         push(edge_ids);
         push(skip);
+        push(c->ebox);
+        key.push_back((uintptr_t)(uint32_t)c->n_ebox);
         key.push_back((uintptr_t)(uint32_t)n_obs);
         key.push_back((uintptr_t)(uint32_t)E);
         key.push_back((uintptr_t)S_cap);
@@ -1053,9 +1161,9 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         }
         for (const DevBuf& wb : c->ws) push(wb.p);
         const TileCfg gc = resolve_cfg(c, tune_key(c, r, TUNE_CHECK_FLAGS, ov.n, (int64_t)S_cap * E),
-                                       heuristic_check(c, r, ov.n, (int64_t)S_cap * E, false), r->S, ov.n, false);
+                                       heuristic_check(c, r, ov.n, (int64_t)S_cap * E, false), r->slots, ov.n, false);
         const TileCfg gb = resolve_cfg(c, tune_key(c, r, TUNE_BISECT, ov.n, (int64_t)cand_cap * E),
-                                       heuristic_bisect(c, r, ov.n, (int64_t)cand_cap * E), r->S, ov.n, false, true);
+                                       heuristic_bisect(c, r, ov.n, (int64_t)cand_cap * E), r->slots, ov.n, false, true);
         for (const TileCfg& g : {gc, gb}) {
             key.push_back((uintptr_t)g.T);
             key.push_back((uintptr_t)g.W);

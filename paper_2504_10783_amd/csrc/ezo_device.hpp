@@ -40,7 +40,18 @@ struct RobotView {
     const int2* pairs;         // [P] self pairs, indices into the sorted order, grouped by block
     const float4* lbound;      // [dof] bounding sphere of each link's spheres: local centre, radius
     const int4* blocks;        // [n_blocks] per link pair: (link i, link j, first pair, pair count)
+    // boxes on links, sorted by link: box k = four float4 in the link frame,
+    // (centre, h_x), (rotation row 0, h_y), (row 1, h_z), (row 2, bounding
+    // radius |h|); the rotation's columns are the box axes
+    int n_boxes;
+    int n_box_pairs;
+    const float4* box;         // [B][4]
+    const int* box_begin;      // [dof + 1] boxes of link i: [box_begin[i], box_begin[i+1])
+    const int2* box_pairs;     // [Q] box self pairs (sorted indices)
 };
+
+// LDS rows of a tile's pose array: one per sphere, four per box.
+__host__ __device__ inline int tile_slots(int n_spheres, int n_boxes) { return n_spheres + 4 * n_boxes; }
 
 constexpr int kMaxLinkPairs = kMaxDof * (kMaxDof + 1) / 2;   // link pairs, same-link pairs included
 
@@ -77,6 +88,8 @@ struct ObsView {
     int lds_n;                 // > 0: the workgroup stages the n records (x, y, z, r) in LDS
     const float4* rec;         // [n][2]: (ox, oy, oz, ro), (-2ox, -2oy, -2oz, |o|^2 - ro^2), shifted frame
     const float4* centre;      // [1] shift applied to world coordinates (x' = x - centre)
+    int n_ebox;                // obstacle boxes (world frame, packed like robot boxes)
+    const float4* ebox;        // [n_ebox][4]
 };
 
 // ---------------------------------------------------------------------------
@@ -139,7 +152,8 @@ __device__ __forceinline__ void dh_compose(float R[9], float p[3], float ct, flo
 struct TileSmem {
     float* q;          // [T][kMaxDof] configurations of the tile
     float2* trig;      // [kMaxDof][T] (cos, sin) of each joint
-    float4* cen;       // [S][T] sphere centres (shifted frame) and radius
+    float4* cen;       // [S + 4B][T] sphere centres (shifted frame) and radius, then each
+                       // box's world pose as four rows (packed like RobotView::box)
     float4* lb;        // [kMaxDof][T] link bounding spheres (shifted frame)
     int* hit;          // [T] collision flag (flags mode) / validity
     int* scr;          // [T] 1 = the learned screen cleared this configuration's self pairs
@@ -207,6 +221,9 @@ struct ItemWalk {
 
 // FK phase: t.q[c][j] (c < n_valid) -> t.cen[s][c].  Ends with a barrier.
 // Only the n_valid >= 1 configurations of the tile are computed.
+// BOX = false compiles the sphere-only path (no box code, fewer registers);
+// BOX = true adds the boxes of RobotView and ObsView.
+template <bool BOX>
 __device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const TileSmem& t, int T, int n_valid) {
     const int dof = rb.dof;
     for (ItemWalk w(n_valid); w.k < dof; w.next(n_valid)) {
@@ -244,8 +261,149 @@ __device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const Til
             o.w = ps.w;
             t.cen[s * T + c] = o;
         }
+        if (BOX && rb.n_boxes > 0) {
+            const int S = rb.n_spheres;
+            const int k1 = rb.box_begin[link + 1];
+            for (int k = rb.box_begin[link]; k < k1; ++k) {
+                const float4 b0 = rb.box[4 * k], b1 = rb.box[4 * k + 1], b2 = rb.box[4 * k + 2], b3 = rb.box[4 * k + 3];
+                const float L[9] = {b1.x, b1.y, b1.z, b2.x, b2.y, b2.z, b3.x, b3.y, b3.z};
+                float4* dst = t.cen + (size_t)(S + 4 * k) * T + c;
+                float W[9];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        W[3 * i + j] = fmaf(R[3 * i], L[j], fmaf(R[3 * i + 1], L[3 + j], R[3 * i + 2] * L[6 + j]));
+                dst[0] = make_float4(fmaf(R[0], b0.x, fmaf(R[1], b0.y, fmaf(R[2], b0.z, p[0]))),
+                                     fmaf(R[3], b0.x, fmaf(R[4], b0.y, fmaf(R[5], b0.z, p[1]))),
+                                     fmaf(R[6], b0.x, fmaf(R[7], b0.y, fmaf(R[8], b0.z, p[2]))), b0.w);
+                dst[T] = make_float4(W[0], W[1], W[2], b1.w);
+                dst[2 * T] = make_float4(W[3], W[4], W[5], b2.w);
+                dst[3 * T] = make_float4(W[6], W[7], W[8], b3.w);
+            }
+        }
     }
     __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Box geometry (FP32).  A box: centre c, rotation R (row-major, columns = the
+// box axes), half extents h, bounding radius |h|.
+// ---------------------------------------------------------------------------
+struct DBox {
+    float c[3];
+    float R[9];
+    float h[3];
+    float rb;
+};
+
+// Row i of a box's four packed float4 (c, h_x), (R row 0, h_y), (R row 1, h_z),
+// (R row 2, bounding radius); the centre shifted by -sh.
+__device__ __forceinline__ DBox unpack_box(float4 b0, float4 b1, float4 b2, float4 b3, float3 sh) {
+    DBox x;
+    x.c[0] = b0.x - sh.x;
+    x.c[1] = b0.y - sh.y;
+    x.c[2] = b0.z - sh.z;
+    x.R[0] = b1.x; x.R[1] = b1.y; x.R[2] = b1.z;
+    x.R[3] = b2.x; x.R[4] = b2.y; x.R[5] = b2.z;
+    x.R[6] = b3.x; x.R[7] = b3.y; x.R[8] = b3.z;
+    x.h[0] = b0.w;
+    x.h[1] = b1.w;
+    x.h[2] = b2.w;
+    x.rb = b3.w;
+    return x;
+}
+
+__device__ __forceinline__ DBox tile_box(const TileSmem& t, int S, int T, int k, int c) {
+    const float4* p = t.cen + (size_t)(S + 4 * k) * T + c;
+    return unpack_box(p[0], p[T], p[2 * T], p[3 * T], make_float3(0.f, 0.f, 0.f));
+}
+
+// Per-axis excess of a point over the box, e_k = |p_k| - h_k with p the
+// point in box coordinates; returns max_k e_k and sum_k max(e_k, 0)^2.
+__device__ __forceinline__ void box_excess(const DBox& B, float x, float y, float z, float* emax, float* out2) {
+    const float dx = x - B.c[0], dy = y - B.c[1], dz = z - B.c[2];
+    float m = -INFINITY, o = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float pk = fmaf(B.R[k], dx, fmaf(B.R[3 + k], dy, B.R[6 + k] * dz));
+        const float e = fabsf(pk) - B.h[k];
+        m = fmaxf(m, e);
+        const float ep = fmaxf(e, 0.f);
+        o = fmaf(ep, ep, o);
+    }
+    *emax = m;
+    *out2 = o;
+}
+
+// Signed distance sphere (x, r) - box: outside sqrt(sum max(e,0)^2) - r, inside
+// max_k e_k - r (minus the distance to the nearest face, minus r).
+__device__ __forceinline__ float sd_sphere_box(const DBox& B, float x, float y, float z, float r) {
+    float m, o;
+    box_excess(B, x, y, z, &m, &o);
+    return (m <= 0.f ? m : sqrtf(o)) - r;
+}
+
+// Collision test of the same pair: signed distance < 0.
+__device__ __forceinline__ bool hit_sphere_box(const DBox& B, float x, float y, float z, float r) {
+    float m, o;
+    box_excess(B, x, y, z, &m, &o);
+    return m <= 0.f ? (m < r) : (o < r * r);
+}
+
+// Separating-axis value of two boxes: with C_ij = A_i . B_j and t_i = A_i . t
+// (t = c_B - c_A, A_i and B_j the box axes), the face axes give
+// |t_i| - h_Ai - sum_j h_Bj |C_ij| and |sum_i C_ij t_i| - sum_i h_Ai |C_ij| - h_Bj,
+// the cross axis A_i x B_j (length sqrt(1 - C_ij^2), skipped below 1e-6) the
+// unnormalised value |t_{i+2} C_{i+1,j} - t_{i+1} C_{i+2,j}| - h_A(i+1) |C_{i+2,j}|
+// - h_A(i+2) |C_{i+1,j}| - h_B(j+1) |C_{i,j+2}| - h_B(j+2) |C_{i,j+1}| (indices
+// mod 3), divided by that length.  Returns the largest (exact: all axes).
+// With early = true it returns as soon as an axis has a value >= 0 (the
+// boxes do not collide) and the result is then only that value.
+template <bool EARLY>
+__device__ inline float sat_value(const DBox& A, const DBox& B) {
+    const float tx = B.c[0] - A.c[0], ty = B.c[1] - A.c[1], tz = B.c[2] - A.c[2];
+    float C[3][3], aC[3][3], t[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        t[i] = fmaf(A.R[i], tx, fmaf(A.R[3 + i], ty, A.R[6 + i] * tz));
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            C[i][j] = fmaf(A.R[i], B.R[j], fmaf(A.R[3 + i], B.R[3 + j], A.R[6 + i] * B.R[6 + j]));
+            aC[i][j] = fabsf(C[i][j]);
+        }
+    }
+    float best = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float v = fabsf(t[i]) - A.h[i] - fmaf(B.h[0], aC[i][0], fmaf(B.h[1], aC[i][1], B.h[2] * aC[i][2]));
+        best = fmaxf(best, v);
+        if (EARLY && v >= 0.f) return v;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const float tb = fmaf(C[0][j], t[0], fmaf(C[1][j], t[1], C[2][j] * t[2]));
+        const float v = fabsf(tb) - fmaf(A.h[0], aC[0][j], fmaf(A.h[1], aC[1][j], A.h[2] * aC[2][j])) - B.h[j];
+        best = fmaxf(best, v);
+        if (EARLY && v >= 0.f) return v;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            const float n2 = fmaf(-C[i][j], C[i][j], 1.f);
+            if (n2 < 1e-12f) continue;
+            const float u = fabsf(fmaf(t[i2], C[i1][j], -t[i1] * C[i2][j])) -
+                            fmaf(A.h[i1], aC[i2][j], fmaf(A.h[i2], aC[i1][j],
+                                 fmaf(B.h[j1], aC[i][j2], B.h[j2] * aC[i][j1])));
+            const float v = u * rsqrtf(n2);
+            best = fmaxf(best, v);
+            if (EARLY && u >= 0.f) return v;
+        }
+    }
+    return best;
 }
 
 // Copy the obstacle records (x, y, z, r) into the workgroup's LDS copy.
@@ -266,6 +424,7 @@ __device__ __forceinline__ bool wave_all(bool p) {
 
 // Signed-distance pair sweep.  Results: t.red[0][0][c] = overall minimum,
 // t.red[1][0][c] = self minimum; t.hit[c] = (overall < 0).  Barrier at exit.
+template <bool BOX>
 __device__ inline void tile_pairs_sd(const RobotView& rb, const ObsView& ob, const TileSmem& t, int T,
                                      int n_valid) {
     const int tid = threadIdx.x;
@@ -311,6 +470,32 @@ __device__ inline void tile_pairs_sd(const RobotView& rb, const ObsView& ob, con
             if (sb < S) env = fminf(env, bestB - B.w);
         }
     }
+    if (BOX && (rb.n_boxes > 0 || ob.n_ebox > 0)) {
+        const float4 shv = ob.centre[0];
+        const float3 sh = make_float3(shv.x, shv.y, shv.z);
+        const int B = rb.n_boxes;
+        const bool ok = c < n_valid;
+        for (int p = w * nsub + j; ok && p < rb.n_box_pairs; p += W * nsub) {
+            const int2 pr = rb.box_pairs[p];
+            self = fminf(self, sat_value<false>(tile_box(t, S, T, pr.x, c), tile_box(t, S, T, pr.y, c)));
+        }
+        for (int k = w * nsub + j; ok && k < B; k += W * nsub) {
+            const DBox X = tile_box(t, S, T, k, c);
+            for (int o = 0; o < ob.n; ++o) {
+                const float4 O = ob.rec[2 * o];
+                env = fminf(env, sd_sphere_box(X, O.x, O.y, O.z, O.w));
+            }
+            for (int e = 0; e < ob.n_ebox; ++e)
+                env = fminf(env, sat_value<false>(X, unpack_box(ob.ebox[4 * e], ob.ebox[4 * e + 1], ob.ebox[4 * e + 2],
+                                                                ob.ebox[4 * e + 3], sh)));
+        }
+        for (int s2 = w * nsub + j; ok && ob.n_ebox > 0 && s2 < S; s2 += W * nsub) {
+            const float4 C = t.cen[s2 * T + c];
+            for (int e = 0; e < ob.n_ebox; ++e)
+                env = fminf(env, sd_sphere_box(unpack_box(ob.ebox[4 * e], ob.ebox[4 * e + 1], ob.ebox[4 * e + 2],
+                                                          ob.ebox[4 * e + 3], sh), C.x, C.y, C.z, C.w));
+        }
+    }
     // reduce over the lanes of one configuration, then over waves
     for (int off = T; off < 64; off <<= 1) {
         env = fminf(env, __shfl_xor(env, off));
@@ -345,6 +530,64 @@ __device__ inline void tile_pairs_sd(const RobotView& rb, const ObsView& ob, con
 // Needs *t.wl_n == 0 on entry.  Barrier at exit.
 // Returns the number of sphere-sphere tests this thread performed (bound
 // tests included).
+// Box pairs of a tile, flags mode (after the sphere passes; configurations
+// already hit are skipped): the box self pairs, every robot box against every
+// obstacle sphere and obstacle box, every robot sphere against every obstacle
+// box.  Each pair is first bounded by the two bounding spheres (a pair they
+// prove apart cannot collide), then tested exactly.
+__device__ inline void tile_boxes_flags(const RobotView& rb, const ObsView& ob, const TileSmem& t, int T,
+                                        int n_valid) {
+    volatile int* hit = t.hit;
+    const int S = rb.n_spheres, B = rb.n_boxes;
+    const float4 shv = ob.centre[0];
+    const float3 sh = make_float3(shv.x, shv.y, shv.z);
+    for (ItemWalk w(n_valid); w.k < rb.n_box_pairs; w.next(n_valid)) {
+        const int c = w.c;
+        if (hit[c]) continue;
+        const int2 pr = rb.box_pairs[w.k];
+        const DBox X = tile_box(t, S, T, pr.x, c), Y = tile_box(t, S, T, pr.y, c);
+        const float dx = X.c[0] - Y.c[0], dy = X.c[1] - Y.c[1], dz = X.c[2] - Y.c[2];
+        const float Rr = X.rb + Y.rb;
+        if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) >= Rr * Rr) continue;
+        if (sat_value<true>(X, Y) < 0.f) hit[c] = 1;
+    }
+    for (ItemWalk w(n_valid); w.k < B; w.next(n_valid)) {
+        const int c = w.c;
+        if (hit[c]) continue;
+        const DBox X = tile_box(t, S, T, w.k, c);
+        bool found = false;
+        for (int o = 0; o < ob.n && !found; ++o) {
+            const float4 O = t.obs ? t.obs[o] : ob.rec[2 * o];
+            const float dx = O.x - X.c[0], dy = O.y - X.c[1], dz = O.z - X.c[2];
+            const float Rr = X.rb + O.w;
+            if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < Rr * Rr && hit_sphere_box(X, O.x, O.y, O.z, O.w)) found = true;
+        }
+        for (int e = 0; e < ob.n_ebox && !found; ++e) {
+            const DBox E = unpack_box(ob.ebox[4 * e], ob.ebox[4 * e + 1], ob.ebox[4 * e + 2], ob.ebox[4 * e + 3], sh);
+            const float dx = E.c[0] - X.c[0], dy = E.c[1] - X.c[1], dz = E.c[2] - X.c[2];
+            const float Rr = X.rb + E.rb;
+            if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < Rr * Rr && sat_value<true>(X, E) < 0.f) found = true;
+        }
+        if (found) hit[c] = 1;
+    }
+    if (ob.n_ebox > 0) {
+        for (ItemWalk w(n_valid); w.k < S; w.next(n_valid)) {
+            const int c = w.c;
+            if (hit[c]) continue;
+            const float4 C = t.cen[w.k * T + c];
+            bool found = false;
+            for (int e = 0; e < ob.n_ebox && !found; ++e) {
+                const DBox E = unpack_box(ob.ebox[4 * e], ob.ebox[4 * e + 1], ob.ebox[4 * e + 2], ob.ebox[4 * e + 3], sh);
+                const float dx = E.c[0] - C.x, dy = E.c[1] - C.y, dz = E.c[2] - C.z;
+                const float Rr = E.rb + C.w;
+                if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < Rr * Rr && hit_sphere_box(E, C.x, C.y, C.z, C.w)) found = true;
+            }
+            if (found) hit[c] = 1;
+        }
+    }
+}
+
+template <bool BOX>
 __device__ inline unsigned tile_pairs_grid(const RobotView& rb, const ObsView& ob, const GridView& gv,
                                            const TileSmem& t, int T, int n_valid) {
     volatile int* hit = t.hit;
@@ -426,6 +669,7 @@ __device__ inline unsigned tile_pairs_grid(const RobotView& rb, const ObsView& o
             if (found) hit[c] = 1;
         }
     }
+    if (BOX && (rb.n_boxes > 0 || ob.n_ebox > 0)) tile_boxes_flags(rb, ob, t, T, n_valid);
     __syncthreads();
     return ntest;
 }
@@ -444,18 +688,18 @@ __device__ inline void flush_tests(unsigned long long* tests, unsigned n) {
 // Whole tile check on t.q[0..n_valid).  Flags mode fills t.hit; signed-
 // distance mode also fills t.red[c] (overall) and t.red[W*T + c] (self).
 // Returns the thread's count of pair tests (flags mode; 0 otherwise).
-template <bool SD>
+template <bool SD, bool BOX>
 __device__ inline unsigned tile_check(const RobotView& rb, const ObsView& ob, const GridView& gv, const TileSmem& t,
                                       int T, int n_valid) {
-    tile_fk(rb, ob, t, T, n_valid);
+    tile_fk<BOX>(rb, ob, t, T, n_valid);
     if (threadIdx.x < (unsigned)T) t.hit[threadIdx.x] = (threadIdx.x < (unsigned)n_valid) ? 0 : 1;
     if (threadIdx.x == 0) *t.wl_n = 0;
     __syncthreads();
     if (SD) {
-        tile_pairs_sd(rb, ob, t, T, n_valid);
+        tile_pairs_sd<BOX>(rb, ob, t, T, n_valid);
         return 0;
     }
-    return tile_pairs_grid(rb, ob, gv, t, T, n_valid);
+    return tile_pairs_grid<BOX>(rb, ob, gv, t, T, n_valid);
 }
 
 }  // namespace ezo

@@ -53,12 +53,16 @@ struct ezo_ctx {
     std::vector<uintptr_t> loop_key;      // everything the captured loop's launches depend on
     std::vector<int4> table_host;         // per-iteration table last copied to table_dev
     const void* table_dev = nullptr;
+    float4* ebox = nullptr;               // obstacle boxes [n_ebox][4] (packed like robot boxes), world frame
+    int n_ebox = 0;
 };
 
 struct ezo_robot {
     ezo_ctx* ctx = nullptr;
     int device = 0;                    // the context's device (destroy does not read the context)
     int dof = 0, S = 0, P = 0;
+    int B = 0, Q = 0;                  // boxes, box self pairs
+    int slots = 0;                     // LDS pose rows per configuration: S + 4 B
     float r_max = 0.f;                 // largest sphere radius
     void* buf = nullptr;               // one device allocation holding everything below
     ezo::RobotView view{};
@@ -119,7 +123,7 @@ enum TuneKind { TUNE_CHECK_FLAGS = 0, TUNE_CHECK_SD = 1, TUNE_BISECT = 2, TUNE_S
 // count only (spheres = self pairs = obstacles = 0).
 struct TuneKey {
     std::string arch;
-    int kind = 0, dof = 0, S = 0, P = 0, n_obs = 0, bucket = 0;
+    int kind = 0, dof = 0, S = 0, P = 0, n_obs = 0, bucket = 0, B = 0;
     bool operator<(const TuneKey& o) const;
 };
 

@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(256) k_build_grid(const float4* __restrict__ r
 // blockIdx.x = tile.  q_b = q + b * q_batch; flags_b = flags + b * out_batch.
 // n = iteration's |S| when it.k_dev is set, else n_arg.
 // ---------------------------------------------------------------------------
-template <int T, bool SD>
+template <int T, bool SD, bool BOX>
 __global__ void __launch_bounds__(1024) k_check(RobotView rb, ObsView ob, GridView gv, const float* __restrict__ q, int64_t n_arg,
                                                 int64_t stride_n, int64_t stride_d, int64_t q_batch,
                                                 uint8_t* __restrict__ flags, float* __restrict__ min_sd,
@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(1024) k_check(RobotView rb, ObsView ob, GridVi
     if (base >= n) return;
     const int nv = (int)((n - base) < T ? (n - base) : T);
     const int W = blockDim.x >> 6;
-    TileSmem t = carve_tile(smem, T, rb.n_spheres, W, SD ? 0 : ob.lds_n);
+    TileSmem t = carve_tile(smem, T, tile_slots(rb.n_spheres, rb.n_boxes), W, SD ? 0 : ob.lds_n);
     if (!SD) stage_obstacles(ob, t);
     const float* qb = q + b * q_batch;
     for (int i = threadIdx.x; i < T * rb.dof; i += blockDim.x) {
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(1024) k_check(RobotView rb, ObsView ob, GridVi
         if (s && stats) atomicAdd((unsigned long long*)&stats[b].screened, 1ull);
     }
     __syncthreads();
-    const unsigned ntest = tile_check<SD>(rb, ob, gv, t, T, nv);
+    const unsigned ntest = tile_check<SD, BOX>(rb, ob, gv, t, T, nv);
     if (gv.tests) flush_tests(gv.tests, ntest);
     if (threadIdx.x < (unsigned)nv) {
         const int64_t g = b * out_batch + base + threadIdx.x;
@@ -201,13 +201,13 @@ __global__ void __launch_bounds__(256) k_centres(RobotView rb, ObsView ob, const
     const int64_t base = (int64_t)blockIdx.x * T;
     if (base >= n) return;
     const int nv = (int)((n - base) < T ? (n - base) : T);
-    TileSmem t = carve_tile(smem, T, rb.n_spheres, blockDim.x >> 6);
+    TileSmem t = carve_tile(smem, T, tile_slots(rb.n_spheres, rb.n_boxes), blockDim.x >> 6);
     for (int i = threadIdx.x; i < T * rb.dof; i += blockDim.x) {
         const int c = i % T, j = i / T;
         if (c < nv) t.q[c * kMaxDof + j] = q[(base + c) * stride_n + j * stride_d];
     }
     __syncthreads();
-    tile_fk(rb, ob, t, T, nv);
+    tile_fk<false>(rb, ob, t, T, nv);
     const float4 sh = ob.centre[0];
     const int S = rb.n_spheres;
     for (int i = threadIdx.x; i < nv * S; i += blockDim.x) {
@@ -581,7 +581,7 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
 // dependent rounds instead of N_b.  Candidate state lives with the threads
 // c < TC; configuration c (2^lev - 1) + i - 1 holds node i of candidate c.
 // ---------------------------------------------------------------------------
-template <int TC, int DEPTH>
+template <int TC, int DEPTH, bool BOX>
 __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView ob, GridView gv, const float* __restrict__ edges,
                                                          const float* __restrict__ S, int64_t stride, int64_t s_edge,
                                                          const int* __restrict__ cand_idx,
@@ -603,7 +603,7 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView o
     const int nv = (nc - base) < TC ? (nc - base) : TC;
     const int dof = rb.dof;
     const int W = blockDim.x >> 6;
-    TileSmem t = carve_tile(smem, T, rb.n_spheres, W, ob.lds_n);
+    TileSmem t = carve_tile(smem, T, tile_slots(rb.n_spheres, rb.n_boxes), W, ob.lds_n);
     stage_obstacles(ob, t);
     const int tid = threadIdx.x;
     const bool own = tid < nv;
@@ -638,7 +638,7 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView o
         }
     }
     __syncthreads();
-    unsigned ntest = tile_check<false>(rb, ob, gv, t, T, nv);
+    unsigned ntest = tile_check<false, BOX>(rb, ob, gv, t, T, nv);
     if (own) {
         const int h = t.hit[tid];
         proj_collides[(size_t)e * cand_cap + base + tid] = (uint8_t)h;
@@ -669,7 +669,7 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView o
             }
         }
         __syncthreads();
-        ntest += tile_check<false>(rb, ob, gv, t, T, nv * npt);
+        ntest += tile_check<false, BOX>(rb, ob, gv, t, T, nv * npt);
         if (own) {
             const int* h = t.hit + tid * npt;
             const float* q0 = t.q + (size_t)tid * npt * kMaxDof;

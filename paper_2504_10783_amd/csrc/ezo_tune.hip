@@ -70,9 +70,9 @@ bool find_str(const std::string& line, const char* key, std::string* out) {
 
 bool TuneKey::operator<(const TuneKey& o) const {
     if (arch != o.arch) return arch < o.arch;
-    const int a[6] = {kind, dof, S, P, n_obs, bucket};
-    const int b[6] = {o.kind, o.dof, o.S, o.P, o.n_obs, o.bucket};
-    for (int i = 0; i < 6; ++i)
+    const int a[7] = {kind, dof, S, P, n_obs, bucket, B};
+    const int b[7] = {o.kind, o.dof, o.S, o.P, o.n_obs, o.bucket, o.B};
+    for (int i = 0; i < 7; ++i)
         if (a[i] != b[i]) return a[i] < b[i];
     return false;
 }
@@ -168,10 +168,10 @@ ezo_status ezo_tune_cache_export(char* buf, int64_t capacity, int64_t* length) {
             char line[512];
             std::snprintf(line, sizeof(line),
                           "{\"arch\":\"%s\",\"kernel\":\"%s\",\"dof\":%d,\"spheres\":%d,\"self_pairs\":%d,"
-                          "\"obstacles\":%d,\"log2_items\":%d,\"T\":%d,\"W\":%d,\"stage\":%d,\"depth\":%d,"
-                          "\"us\":%.3f}\n",
-                          k.arch.c_str(), kKindNames[k.kind], k.dof, k.S, k.P, k.n_obs, k.bucket, e.cfg.T, e.cfg.W,
-                          e.cfg.stage, e.cfg.depth, e.us);
+                          "\"boxes\":%d,\"obstacles\":%d,\"log2_items\":%d,\"T\":%d,\"W\":%d,\"stage\":%d,"
+                          "\"depth\":%d,\"us\":%.3f}\n",
+                          k.arch.c_str(), kKindNames[k.kind], k.dof, k.S, k.P, k.B, k.n_obs, k.bucket, e.cfg.T,
+                          e.cfg.W, e.cfg.stage, e.cfg.depth, e.us);
             os << line;
         }
     }
@@ -206,6 +206,8 @@ ezo_status ezo_tune_cache_import(const char* text, int32_t* n_imported) {
         const int T = ok ? (int)v[5] : 0, W = ok ? (int)v[6] : 0;
         double depth = 1.0;                          // optional key (bisection only)
         if (ok) find_num(line, "depth", &depth);
+        double boxes = 0.0;                          // optional key (robots with boxes)
+        if (ok) find_num(line, "boxes", &boxes);
         const bool shape_ok = (T == 1 || T == 2 || T == 4 || T == 8 || T == 16 || T == 32 || T == 64) && W >= 1 &&
                               W <= 16 && (v[7] == 0 || v[7] == 1) && (depth == 1 || depth == 2 || depth == 3);
         if (!ok || kind < 0 || !shape_ok) return EZO_E_INVALID;
@@ -215,6 +217,7 @@ ezo_status ezo_tune_cache_import(const char* text, int32_t* n_imported) {
         k.P = (int)v[2];
         k.n_obs = (int)v[3];
         k.bucket = (int)v[4];
+        k.B = (int)boxes;
         Entry e;
         e.cfg.T = T;
         e.cfg.W = W;

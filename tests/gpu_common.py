@@ -41,7 +41,7 @@ def sampler_agreement(got, ref, A, b, label=""):
     return q
 
 
-def bisection_agreement(c_star_gpu, t_star_gpu, proj_gpu, o, c):
+def bisection_agreement(c_star_gpu, t_star_gpu, proj_gpu, o, c, band=BAND):
     """Until the first evaluated point whose exact signed distance lies in the
     band, FP32 and FP64 take the same bisection decisions; the bisection is
     meant to converge onto the boundary, so later midpoints often do lie in
@@ -49,10 +49,10 @@ def bisection_agreement(c_star_gpu, t_star_gpu, proj_gpu, o, c):
     step, whose length is |c - c_proj| 2^-(s) for a first band midpoint at
     step s.  Returns the number of decided steps."""
     tr = o["sd_trace"]
-    if abs(tr[0]) >= BAND:
+    if abs(tr[0]) >= band:
         assert bool(proj_gpu) == o["proj_collides"]
     n_b = len(tr) - 1
-    first = next((i for i in range(1, n_b + 1) if abs(tr[i]) < BAND), n_b + 1)
+    first = next((i for i in range(1, n_b + 1) if abs(tr[i]) < band), n_b + 1)
     steps_equal = first - 1                  # decisions 0 .. first-2 are certain
     L = float(np.linalg.norm(c - o["c_proj"]))
     tol = L * 2.0 ** (-steps_equal) + 1e-5 if first <= n_b else 1e-5

@@ -1,0 +1,238 @@
+"""GPU parity of the box collision geometry (Sec. IV-D: box and sphere
+geometries) against the oracle:
+
+* raw check of the 11-box arm among voxel spheres and a table box, flags and
+  signed distances, with and without the table;
+* a sphere arm against an obstacle box;
+* projection + bisection of the box arm's colliding samples;
+* the obstacle-box call's errors, removal, and the inflation graph following
+  a change of the obstacle boxes.
+
+Box-box values: the FK rotations carry FP32 rounding of about 1e-6, which a
+cross axis of edges at |A_i x B_j| >= 0.05 amplifies to at most about
+1e-6 x 2.5 m / 0.05 = 5e-5 m.  So flags must agree wherever the oracle's
+minimum lies outside +-5e-5 m and no box pair's sign rests on such a cross
+axis (fragile bit 1), and signed distances agree to 5e-5 m wherever no box
+pair near the minimum of its kind has such a value (fragile bit 0).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from workloads import draw
+
+from gpu_common import bisection_agreement, f32_up, load, print_case
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+BOX_BAND = 5e-5
+
+
+@pytest.fixture(scope="module")
+def ezo():
+    import paper_2504_10783_amd as ezo
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return ezo
+
+
+@pytest.fixture(scope="module")
+def ctx(ezo):
+    return ezo.Context(0)
+
+
+def compare(ezo, ctx, desc, obs_np, ebox, q, label):
+    rob = ezo.Robot(ctx, desc)
+    ctx.set_obstacle_boxes(ebox)
+    try:
+        obs = torch.from_numpy(np.ascontiguousarray(obs_np, np.float32)).cuda()
+        qt = torch.from_numpy(q).cuda()
+        n = len(q)
+        flags = torch.empty(n, dtype=torch.uint8, device="cuda")
+        flags_sd = torch.empty(n, dtype=torch.uint8, device="cuda")
+        msd = torch.empty(n, dtype=torch.float32, device="cuda")
+        mss = torch.empty(n, dtype=torch.float32, device="cuda")
+        ezo.check_collisions(ctx, rob, obs, qt, flags)
+        ezo.check_collisions(ctx, rob, obs, qt, flags_sd, msd, mss)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_obstacle_boxes(None)
+    f, sd, se, ss, fr = oracle.check(oracle.Robot(desc), f32_up(obs_np), f32_up(q),
+                                     env_boxes=None if ebox is None else f32_up(ebox), fragile=True)
+    g, gs, gsd, gss = (x.cpu().numpy() for x in (flags, flags_sd, msd, mss))
+    ok = (np.abs(sd) >= BOX_BAND) & ((fr & 2) == 0)
+    vok = (fr & 1) == 0
+    print(f"{label}: {n} configs, collision {f.mean():.3f}, in band {np.mean(np.abs(sd) < BOX_BAND):.4f}, "
+          f"fragile value {np.mean(fr & 1):.4f} sign {np.mean((fr & 2) > 0):.4f}, "
+          f"max |sd err| {np.abs(gsd - sd)[vok].max():.2e}")
+    assert np.array_equal(g[ok], f[ok]) and np.array_equal(gs[ok], f[ok])
+    assert np.abs(gsd - sd)[vok].max() <= BOX_BAND
+    fin = np.isfinite(ss)
+    assert np.abs(gss[fin] - ss[fin])[vok[fin]].max() <= BOX_BAND
+    assert np.all(np.isinf(gss[~fin]))
+    return f
+
+
+@pytest.mark.parametrize("table", [True, False])
+def test_box_arm_check_parity(ezo, ctx, table):
+    data, desc = load("boxes")
+    q = draw.uniform_q(21, 20001, data["q_lo"], data["q_hi"])          # ragged tail
+    print_case("box check", "table" if table else "no table", len(q))
+    f = compare(ezo, ctx, desc, data["obstacles"], data["env_boxes"] if table else None, q, "boxes")
+    assert 0.2 < f.mean() < 0.95
+
+
+def test_sphere_arm_against_obstacle_box(ezo, ctx):
+    data, desc = load("dof7")
+    box = load("boxes")[0]["env_boxes"]
+    q = draw.uniform_q(22, 8000, data["q_lo"], data["q_hi"])
+    print_case("sphere arm vs box", len(q))
+    f = compare(ezo, ctx, desc, data["obstacles"], box, q, "spheres+table")
+    assert f.mean() > 0.3
+
+
+def test_box_arm_bisection_parity(ezo, ctx):
+    data, desc = load("boxes")
+    dof = desc["dof"]
+    rob = ezo.Robot(ctx, desc)
+    orob = oracle.Robot(desc)
+    obs_np, eb = f32_up(data["obstacles"]), f32_up(data["env_boxes"])
+    v1, v2 = f32_up(data["edges"][0])
+    A, b = orob.box()
+    S = oracle.hit_and_run(A, b, v1, v2, 10, 5, 0, 1, 800).astype(np.float32)
+    fo, *_ = oracle.check(orob, obs_np, f32_up(S), env_boxes=eb)
+    cand = S[fo.astype(bool)][:150]
+    n = len(cand)
+    print_case("box bisection", n)
+    St = torch.zeros((1, dof, n + 5), dtype=torch.float32, device="cuda")
+    St[0, :, :n] = torch.from_numpy(np.ascontiguousarray(cand.T)).cuda()
+    ci = torch.arange(n, dtype=torch.int32, device="cuda")[None]
+    nc = torch.tensor([n], dtype=torch.int32, device="cuda")
+    cs = torch.empty((1, dof, n), dtype=torch.float32, device="cuda")
+    ad = torch.empty((1, dof, n), dtype=torch.float32, device="cuda")
+    ts = torch.empty((1, n), dtype=torch.float32, device="cuda")
+    pc = torch.empty((1, n), dtype=torch.uint8, device="cuda")
+    ctx.set_obstacle_boxes(data["env_boxes"])
+    try:
+        ezo.project_bisect(ctx, rob, torch.from_numpy(data["obstacles"]).cuda(),
+                           torch.from_numpy(data["edges"][:1]).cuda(), St, ci, nc, 11, cs, ad, ts, pc)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_obstacle_boxes(None)
+    cs, ad, ts, pc = (x.cpu().numpy() for x in (cs, ad, ts, pc))
+    steps, skipped = [], 0
+    t = np.arange(2049) / 2048.0
+    for j in range(n):
+        o = oracle.bisect_arm(orob, obs_np, v1, v2, f32_up(cand[j]), 11, env_boxes=eb)
+        assert np.abs(ad[0, :, j] - o["a"]).max() <= 1e-5
+        # every midpoint lies at a dyadic fraction of [c_proj, c]; skip the
+        # candidate if the flag of any of them may change (fragile sign)
+        pts = o["c_proj"][None] + t[:, None] * (f32_up(cand[j]) - o["c_proj"])[None]
+        *_, fr = oracle.check(orob, obs_np, pts, env_boxes=eb, fragile=True)
+        if (fr & 2).any():
+            skipped += 1
+            continue
+        steps.append(bisection_agreement(cs[0, :, j], ts[0, j], pc[0, j], o, f32_up(cand[j]), band=BOX_BAND))
+    steps = np.array(steps)
+    print(f"{len(steps)} candidates compared ({skipped} with a fragile midpoint skipped); "
+          f"decided steps mean {steps.mean():.2f} of 11")
+    assert skipped <= 0.2 * n and np.mean(steps >= 8) >= 0.9
+
+
+def test_obstacle_box_errors_and_removal(ezo, ctx):
+    data, desc = load("boxes")
+    bad = np.array(data["env_boxes"], np.float32)
+    with pytest.raises(ezo.EzoError) as ei:
+        ctx.set_obstacle_boxes(np.repeat(bad, 65, axis=0))
+    assert ei.value.code == ezo.EZO_E_UNSUPPORTED
+    nan = bad.copy()
+    nan[0, 4] = np.nan
+    with pytest.raises(ezo.EzoError) as ei:
+        ctx.set_obstacle_boxes(nan)
+    assert ei.value.code == ezo.EZO_E_INVALID
+    neg = bad.copy()
+    neg[0, 13] = -0.1
+    with pytest.raises(ezo.EzoError):
+        ctx.set_obstacle_boxes(neg)
+    # set, then remove: flags equal those of a context that never had boxes
+    rob = ezo.Robot(ctx, desc)
+    q = torch.from_numpy(draw.uniform_q(23, 4096, data["q_lo"], data["q_hi"])).cuda()
+    obs = torch.from_numpy(data["obstacles"]).cuda()
+    f1 = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    f2 = torch.empty_like(f1)
+    f3 = torch.empty_like(f1)
+    ezo.check_collisions(ctx, rob, obs, q, f1)
+    ctx.set_obstacle_boxes(bad)
+    ezo.check_collisions(ctx, rob, obs, q, f2)
+    ctx.set_obstacle_boxes(None)
+    ezo.check_collisions(ctx, rob, obs, q, f3)
+    torch.cuda.synchronize()
+    assert torch.equal(f1, f3) and int(f2.sum()) > int(f1.sum())
+    assert bool(((f2 == 1) | (f1 == 0)).all())                 # the table only adds collisions
+
+
+def test_box_arm_inflation_and_graph_follows_box_change(ezo, ctx):
+    """The box arm's edge inflates (L in P in D, certified); an inflation
+    on a context whose obstacle boxes were changed between calls equals one
+    on a fresh context."""
+    data, desc = load("boxes")
+    dof = desc["dof"]
+    rob = ezo.Robot(ctx, desc)
+    obs = torch.from_numpy(data["obstacles"]).cuda()
+    edges = torch.from_numpy(data["edges"]).cuda()
+    prm = ezo.make_params(dof=dof, seed=4, **workloads.PARAMS["boxes"])
+    print_case("box inflation")
+    ctx.set_obstacle_boxes(data["env_boxes"])
+    r1 = ezo.inflate_edges(ctx, rob, obs, edges, prm)
+    ctx.set_obstacle_boxes(None)
+    r2 = ezo.inflate_edges(ctx, rob, obs, edges, prm)
+    torch.cuda.synchronize()
+    st = int(r1.status[0].item())
+    F = int(r1.n_faces[0].item())
+    print("status", st, "faces", F, "iterations", r1.stats[0]["iterations"], "without table", int(r2.n_faces[0].item()))
+    assert st == ezo.CERTIFIED
+    A = r1.A[0, :F].cpu().numpy().astype(np.float64)
+    b = r1.b[0, :F].cpu().numpy().astype(np.float64)
+    for v in data["edges"][0].astype(np.float64):
+        assert np.all(A @ v <= b + 1e-5)
+    for with_table, r in ((True, r1), (False, r2)):
+        c2 = ezo.Context(0)
+        if with_table:
+            c2.set_obstacle_boxes(data["env_boxes"])
+        ref = ezo.inflate_edges(c2, ezo.Robot(c2, desc), obs.clone(), edges.clone(), prm)
+        torch.cuda.synchronize()
+        assert torch.equal(ref.status, r.status) and torch.equal(ref.n_faces, r.n_faces)
+        Fr = int(ref.n_faces[0].item())
+        assert torch.equal(ref.A[0, :Fr], r.A[0, :Fr]) and torch.equal(ref.b[0, :Fr], r.b[0, :Fr])
+
+
+def test_box_arm_full_runs_agree_with_oracle(ezo, ctx):
+    """Whole inflations of the box arm's edge (reduced N_p) against the
+    oracle's own: statuses equal, iterations and face counts equal on most
+    seeds, as for the single-edge sphere runs."""
+    data, desc = load("boxes")
+    dof = desc["dof"]
+    rob = ezo.Robot(ctx, desc)
+    orob = oracle.Robot(desc)
+    p = dict(workloads.PARAMS["boxes"], n_p=1000, eps=0.1)
+    v1, v2 = f32_up(data["edges"][0])
+    ctx.set_obstacle_boxes(data["env_boxes"])
+    same_it = same_f = 0
+    n = 4
+    try:
+        for seed in range(n):
+            r = ezo.inflate_edges(ctx, rob, torch.from_numpy(data["obstacles"]).cuda(),
+                                  torch.from_numpy(data["edges"]).cuda(), ezo.make_params(dof=dof, seed=seed, **p))
+            torch.cuda.synchronize()
+            o = oracle.eizo_arm(orob, f32_up(data["obstacles"]), v1, v2, oracle.make_params(**p, seed=seed),
+                                env_boxes=f32_up(data["env_boxes"]))
+            st = int(r.status[0].item())
+            print(seed, st, o["status"], r.stats[0]["iterations"], o["stats"]["iterations"],
+                  int(r.n_faces[0].item()), len(o["b"]))
+            assert st == o["status"]
+            same_it += r.stats[0]["iterations"] == o["stats"]["iterations"]
+            same_f += int(r.n_faces[0].item()) == len(o["b"])
+    finally:
+        ctx.set_obstacle_boxes(None)
+    assert same_it >= n // 2 and same_f >= n // 2

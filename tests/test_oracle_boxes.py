@@ -55,7 +55,7 @@ def test_sphere_box_rigid_invariance_and_sampled_surface():
 def test_sat_axis_aligned_closed_forms():
     hA, hB = np.array([1.0, 1.0, 1.0]), np.array([0.5, 2.0, 0.25])
     v, fr = oracle.sat_boxes(np.zeros(3), I3, hA, [2.0, 0.3, 0.1], I3, hB)
-    assert v == pytest.approx(0.5) and not fr                    # face-face gap along x
+    assert v == pytest.approx(0.5) and fr == 0                   # face-face gap along x
     v, _ = oracle.sat_boxes(np.zeros(3), I3, hA, [1.2, 0.5, 1.1], I3, hB)
     assert v == pytest.approx(-0.15)                              # overlaps 0.3, 2.5, 0.15 -> -min
     v, _ = oracle.sat_boxes(np.zeros(3), I3, hA, [1.5, 0.0, 0.0], I3, hB)
