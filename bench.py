@@ -34,6 +34,8 @@ WORKLOADS = {
     "batched": "7-DOF DH arm, 2048 obstacle spheres, 96 edges of 8 uneven paths in one call; "
                "N_p=10000, eps=0.05, delta=0.05, N_mix=60",
     "tiny": "3-DOF planar arm (12 spheres), 20 obstacle discs, one edge; N_p=1000, eps=0.1, delta=0.05",
+    "boxes": "7-DOF DH arm as 11 link boxes (36 box self pairs), 194 voxel spheres (8 cm voxels) and a table "
+             "box, one edge; N_p=10000, eps=0.05, delta=0.05, N_f=20, N_b=11, N_mix=60",
 }
 
 
@@ -83,7 +85,7 @@ def cpu_baseline(name, data, desc, seed, edges_idx):
     for e in edges_idx:
         v1, v2 = data["edges"][e].astype(np.float64)
         prm = oracle.make_params(**workloads.PARAMS[name], seed=seed, edge_id=int(e))
-        out = oracle.eizo_arm(orob, obs, v1, v2, prm)
+        out = oracle.eizo_arm(orob, obs, v1, v2, prm, env_boxes=data.get("env_boxes"))
         checks += out["stats"]["checks"]
     dt = time.perf_counter() - t0
     return {"value": checks / dt, "unit": "configs/s", "cores": oracle.max_threads(), "kind": "oracle",
@@ -399,6 +401,64 @@ def paths_compare(args):
     print(json.dumps(line), flush=True)
 
 
+def box_sweep(args):
+    """Raw checker throughput of the box arm (11 link boxes, 36 box self
+    pairs) among 194 voxel spheres and a table box: N uniform configurations,
+    flags only and flags + minimum signed distance.  The paper quotes about
+    6.9 M configurations/s for its 11-box arm at a batch of 2 M on its own
+    GPU (Sec. VI-B, hardware); that scene is not available, so the figure is
+    context, not a baseline."""
+    import torch
+
+    import paper_2504_10783_amd as ezo
+    import workloads
+    from workloads import draw
+
+    data = workloads.load("boxes")
+    desc = workloads.robot(data)
+    ctx = ezo.Context(0)
+    rob = ezo.Robot(ctx, desc)
+    ctx.set_obstacle_boxes(data["env_boxes"])
+    dev = torch.device("cuda", 0)
+    obs = torch.from_numpy(data["obstacles"]).to(dev)
+    sizes = [int(x) for x in args.sweep_sizes.split(",")]
+    qmax = torch.from_numpy(draw.uniform_q_fast(304, max(sizes), data["q_lo"], data["q_hi"])).to(dev)
+    points = []
+    for n in sizes:
+        q = qmax[:n]
+        flags = torch.empty(n, dtype=torch.uint8, device=dev)
+        msd = torch.empty(n, dtype=torch.float32, device=dev)
+        row = {"n": n}
+        for mode in ("flags", "sd"):
+            def run():
+                ezo.check_collisions(ctx, rob, obs, q, flags, msd if mode == "sd" else None)
+            run()
+            torch.cuda.synchronize()
+            reps = max(1, min(args.steps, int(4e8 // n)))
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                run()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            row[f"{mode}_configs_per_s"] = n / dt
+            row[f"{mode}_ms"] = dt * 1e3
+        row["collision_fraction"] = float(flags.float().mean().item())
+        points.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    at2m = min(points, key=lambda r: abs(r["n"] - 2_000_000))
+    line = {"metric": "collision-checked configs/sec, box arm (11 boxes) among voxel spheres and a table box",
+            "value": at2m["flags_configs_per_s"], "unit": "configs/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"boxes raw check: uniform q in joint limits, batch {at2m['n']}; "
+                                   f"{WORKLOADS['boxes']}"},
+            "paper_context": {"configs_per_s": 6.9e6, "batch": 2_000_000,
+                              "hardware": "GeForce RTX 2080 Ti (paper, Sec. VI-B), its own 11-box arm and scene"},
+            "points": points,
+            "launch_shapes": [e for e in ezo.tune_cache_entries() if e.get("boxes", 0) > 0]}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -412,6 +472,7 @@ def main():
     ap.add_argument("--screen-epochs", type=int, default=10)
     ap.add_argument("--recovery", action="store_true", help="trajectory check + set update + containment timings")
     ap.add_argument("--paths", action="store_true", help="sequential path inflation vs independent edges")
+    ap.add_argument("--box-sweep", action="store_true", help="raw checker throughput of the box arm")
     ap.add_argument("--no-autotune", action="store_true", help="size-heuristic launch shapes (no tuning)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
@@ -438,6 +499,9 @@ def main():
     if args.paths:
         paths_compare(args)
         return
+    if args.box_sweep:
+        box_sweep(args)
+        return
 
     import numpy as np
     import torch
@@ -450,6 +514,8 @@ def main():
     desc = workloads.robot(data)
     ctx = ezo.Context(0)
     rob = ezo.Robot(ctx, desc)
+    if "env_boxes" in data:
+        ctx.set_obstacle_boxes(data["env_boxes"])
     dev = torch.device("cuda", 0)
     obs = torch.from_numpy(data["obstacles"]).to(dev)
     edges = torch.from_numpy(data["edges"]).to(dev)
@@ -505,12 +571,13 @@ def main():
     achieved = work / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0
     all_pairs = flop_per_check(rob.n_spheres, obs.shape[0], rob.n_self) * n_checks[dom]
     shapes = {e["kernel"]: e for e in ezo.tune_cache_entries() if e["obstacles"] == int(obs.shape[0])}
+    box = "true" if (rob.n_boxes > 0 or "env_boxes" in data) else "false"
     if dom == "bisect":
         sb = shapes.get("bisect")
-        instance = f"ezo::k_project_bisect<{sb['T']}, {sb['depth']}, false>" if sb else None
+        instance = f"ezo::k_project_bisect<{sb['T']}, {sb['depth']}, {box}>" if sb else None
     else:
         sc = shapes.get("check_flags")
-        instance = f"ezo::k_check<{sc['T']}, false, false>" if sc else None
+        instance = f"ezo::k_check<{sc['T']}, false, {box}>" if sc else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_TFLOPS,
                 "traffic": measured_traffic(name, instance) if instance else None,
@@ -519,6 +586,7 @@ def main():
                 "avg_launch_ms": dom_ms / max(iters, 1), "launches": iters,
                 "pair_tests_per_check": tests[dom] / max(n_checks[dom], 1),
                 "all_pairs_per_check": rob.n_spheres * int(obs.shape[0]) + rob.n_self,
+                "box_pair_tests_counted": False if rob.n_boxes > 0 or "env_boxes" in data else None,
                 "all_pairs_equivalent_tflops": all_pairs / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0}
 
     line = {
