@@ -82,6 +82,7 @@ def _declare(L):
     L.orc_sphere_centres.argtypes = [rp, _dp, _dp]
     L.orc_check_config.argtypes = [rp, _dp, C.c_int32, _dp, C.c_int32, _dp, _dp, _dp, C.POINTER(C.c_int)]
     L.orc_check_batch.argtypes = [rp, _dp, C.c_int32, _dp, C.c_int32, _dp, C.c_int64, _u8p, _dp, _dp, _dp, _u8p]
+    L.orc_collision_map.argtypes = [rp, _dp, C.c_int64, _dp, C.c_double, _ip, _i64p, C.c_int64, _dp]
     L.orc_sd_sphere_box.argtypes = [_dp, C.c_double, _dp, _dp, _dp]
     L.orc_sd_sphere_box.restype = C.c_double
     L.orc_sat_boxes.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, C.POINTER(C.c_int)]
@@ -218,6 +219,22 @@ def check(robot: Robot, obs, q, env_boxes=None, fragile=False):
     lib().orc_check_batch(robot.ref, _ptr(obs), obs.shape[0], _ptr(eb), eb.shape[0], _ptr(q), n,
                           _ptr(flags, _u8p), _ptr(sd), _ptr(se), _ptr(ss), _ptr(fr, _u8p))
     return (flags, sd, se, ss, fr) if fragile else (flags, sd, se, ss)
+
+
+def collision_map(robot: Robot, q, lo, side, dims, voxels=None):
+    """Collision map of a dynamic roadmap (appendix, DRM construction) on the
+    listed voxels (all of the grid if None): returns (hits bool [M][N],
+    sd [M][N]) with sd the minimum signed distance between voxel m's
+    circumscribing sphere and node n's robot spheres and boxes."""
+    q = _d(q).reshape(-1, robot.dof)
+    dims = np.ascontiguousarray(dims, dtype=np.int32).reshape(3)
+    if voxels is None:
+        voxels = np.arange(int(np.prod(dims.astype(np.int64))))
+    vox = np.ascontiguousarray(voxels, dtype=np.int64)
+    sd = np.empty((len(vox), len(q)))
+    lib().orc_collision_map(robot.ref, _ptr(q), len(q), _ptr(_d(lo).reshape(3)), float(side), _ptr(dims, _ip),
+                            _ptr(vox, _i64p), len(vox), _ptr(sd))
+    return sd < 0.0, sd
 
 
 def sd_sphere_box(x, r, c, R, h):

@@ -339,6 +339,52 @@ void orc_check_batch(const orc_robot *rb, const double *obs, int32_t n_obs, cons
     }
 }
 
+/* ---- collision map of a dynamic roadmap (appendix, DRM construction) ------- */
+
+/* The task space is cut into voxels of side s: voxel (i, j, k) of a grid of
+ * dims[0] x dims[1] x dims[2] cells from corner lo has index v = (k dims[1] +
+ * j) dims[0] + i and is represented by its circumscribing sphere, centre
+ * lo + s (i + 1/2, j + 1/2, k + 1/2), radius sqrt(3)/2 s.  For each listed
+ * voxel vox[m] and each node q_n, sd[m][n] = the minimum signed distance
+ * between that sphere and the robot's spheres and boxes (self pairs play no
+ * part); the node collides with the voxel iff sd < 0. */
+void orc_collision_map(const orc_robot *rb, const double *q, int64_t n_nodes, const double lo[3], double side,
+                       const int32_t dims[3], const int64_t *vox, int64_t n_vox, double *sd) {
+    const double rv = 0.5 * sqrt(3.0) * side;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t n = 0; n < n_nodes; ++n) {
+        const double *qn = q + (size_t)n * rb->dof;
+        double *c = (double *)malloc(sizeof(double) * 3 * (size_t)(rb->n_spheres > 0 ? rb->n_spheres : 1));
+        double *bc = (double *)malloc(sizeof(double) * 12 * (size_t)(rb->n_boxes > 0 ? rb->n_boxes : 1));
+        orc_sphere_centres(rb, qn, c);
+        if (rb->n_boxes > 0) {
+            double *frames = (double *)malloc(sizeof(double) * 16 * (size_t)rb->dof);
+            orc_link_frames(rb, qn, frames);
+            for (int k = 0; k < rb->n_boxes; ++k)
+                box_world(frames + 16 * rb->box_link[k], rb->box_pose + 12 * k, bc + 12 * k, bc + 12 * k + 3);
+            free(frames);
+        }
+        for (int64_t m = 0; m < n_vox; ++m) {
+            const int64_t v = vox[m];
+            const int64_t i = v % dims[0], j = (v / dims[0]) % dims[1], k = v / ((int64_t)dims[0] * dims[1]);
+            const double x[3] = {lo[0] + side * ((double)i + 0.5), lo[1] + side * ((double)j + 0.5),
+                                 lo[2] + side * ((double)k + 0.5)};
+            double best = INFINITY;
+            for (int s = 0; s < rb->n_spheres; ++s) {
+                const double d = dist3(c + 3 * s, x) - rb->sphere_r[s] - rv;
+                if (d < best) best = d;
+            }
+            for (int b = 0; b < rb->n_boxes; ++b) {
+                const double d = orc_sd_sphere_box(x, rv, bc + 12 * b, bc + 12 * b + 3, rb->box_half + 3 * b);
+                if (d < best) best = d;
+            }
+            sd[(size_t)m * n_nodes + n] = best;
+        }
+        free(bc);
+        free(c);
+    }
+}
+
 double orc_arm_sd(const void *scene, const double *q) {
     const orc_arm_scene *sc = (const orc_arm_scene *)scene;
     double e, s;
