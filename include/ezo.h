@@ -392,6 +392,37 @@ ezo_status ezo_set_phase_timing(ezo_ctx *ctx, int32_t enable);
 ezo_status ezo_get_phase_timing(ezo_ctx *ctx, double *ms_out, int64_t *iterations_out, int64_t *tests_out);
 
 /* ---------------------------------------------------------------------------
+ * Collision map of a dynamic roadmap (appendix, DRM construction)
+ *
+ * The task space is cut into voxels of side `side`: voxel (i, j, k) of a
+ * dims[0] x dims[1] x dims[2] grid from corner lo (host f32 [3]) has index
+ * v = (k dims[1] + j) dims[0] + i and is represented by its circumscribing
+ * sphere, centre lo + side (i + 1/2, j + 1/2, k + 1/2), radius sqrt(3)/2 side.
+ * Every voxel is checked against every roadmap node.
+ * ------------------------------------------------------------------------- */
+
+/* map (dev u32 [V][row_words], V = dims[0] dims[1] dims[2], row_words >=
+ * ceil(n_nodes / 32)): bit n of row v (word n / 32, bit n % 32) is set iff the
+ * robot at node q_n (dev f32 [n_nodes][dof], row-major) collides with voxel
+ * v: some robot sphere or box at signed distance < 0 from the voxel's sphere
+ * (FP32; self pairs, obstacles and obstacle boxes play no part).  The call
+ * clears the map first.  A dense bitset instead of id lists: 35 000 nodes x
+ * 12 000 voxels is 52 MB, the online lookup is an OR of rows, and the result
+ * does not depend on thread timing.  Does not synchronise. */
+ezo_status ezo_collision_map(ezo_ctx *ctx, const ezo_robot *robot, const float *q, int64_t n_nodes,
+                             const float *lo, float side, const int32_t *dims, uint32_t *map, int64_t row_words,
+                             void *stream);
+
+/* The map as id lists: offsets (dev i64 [n_rows + 1]) = exclusive prefix of
+ * the rows' bit counts, ids (dev i32 [capacity]) = the set bits of each row
+ * as node ids in increasing order, row v at ids[offsets[v] .. offsets[v+1]).
+ * *total (host, may be NULL) = offsets[n_rows]; EZO_E_CAPACITY (ids not
+ * written) if it exceeds capacity.  Synchronises `stream`. */
+ezo_status ezo_collision_map_lists(ezo_ctx *ctx, const uint32_t *map, int64_t n_rows, int64_t row_words,
+                                   int64_t n_nodes, int64_t *offsets, int32_t *ids, int64_t capacity,
+                                   int64_t *total, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Recovery from collisions found on a trajectory (Sec. V-B)
  *
  * A trajectory through the sets is checked by fine discretisation; the

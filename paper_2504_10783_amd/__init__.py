@@ -32,6 +32,7 @@ EXPORTS = (
     "ezo_surrogate_calibrate", "ezo_surrogate_set_margin", "ezo_surrogate_miss_rate",
     "ezo_set_autotune", "ezo_tune_cache_export", "ezo_tune_cache_import", "ezo_tune_cache_clear",
     "ezo_check_path", "ezo_update_polytopes", "ezo_segments_contained",
+    "ezo_collision_map", "ezo_collision_map_lists",
 )
 PHASES = ("sample", "check", "test", "bisect", "place", "advance")
 
@@ -125,6 +126,8 @@ def lib():
         L.ezo_update_polytopes.argtypes = [vp, vp, vp, i32, vp, i32, vp, i32, i32, i32, dbl, dbl, vp, vp, vp, i32,
                                            vp, vp, vp]
         L.ezo_segments_contained.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp, i32, dbl, vp, vp]
+        L.ezo_collision_map.argtypes = [vp, vp, vp, i64, C.POINTER(C.c_float), C.c_float, C.POINTER(i32), vp, i64, vp]
+        L.ezo_collision_map_lists.argtypes = [vp, vp, i64, i64, i64, vp, vp, i64, C.POINTER(i64), vp]
         L.ezo_set_autotune.argtypes = [vp, i32]
         L.ezo_tune_cache_export.argtypes = [C.c_char_p, i64, C.POINTER(i64)]
         L.ezo_tune_cache_import.argtypes = [C.c_char_p, C.POINTER(i32)]
@@ -605,3 +608,43 @@ def segments_contained(ctx: Context, A, b, n_faces, segments, tol=0.0, stream=No
                                             int(b.shape[0]), _ptr(segments), int(K), float(tol), _ptr(covered),
                                             _stream(stream)))
     return covered
+
+
+# ---------------------------------------------------------------------------
+# Collision map of a dynamic roadmap (appendix, DRM construction)
+# ---------------------------------------------------------------------------
+
+def collision_map(ctx: Context, robot: Robot, q, lo, side, dims, out=None, stream=None):
+    """Bitset map [V][ceil(N/32)] int32 (read as uint32): bit n of row v set
+    iff node q[n] ([N][dof] float32 CUDA) collides with voxel v's sphere."""
+    torch = _torch()
+    _need(q, torch.float32, "q")
+    n = q.shape[0]
+    dims = [int(x) for x in dims]
+    V = dims[0] * dims[1] * dims[2]
+    words = max((n + 31) // 32, 1)
+    if out is None:
+        out = torch.empty((V, words), dtype=torch.int32, device=q.device)
+    lo_c = (C.c_float * 3)(*[float(x) for x in lo])
+    dims_c = (C.c_int32 * 3)(*dims)
+    ctx._check(lib().ezo_collision_map(ctx.h, robot.h, _ptr(q), n, lo_c, float(side), dims_c, _ptr(out),
+                                       out.shape[1], _stream(stream)))
+    return out
+
+
+def collision_map_lists(ctx: Context, cmap, n_nodes, stream=None):
+    """(offsets int64 [V+1], ids int32 [total]) of a bitset map: row v's node
+    ids, increasing, at ids[offsets[v]:offsets[v+1]]."""
+    torch = _torch()
+    V, words = cmap.shape
+    offsets = torch.empty(V + 1, dtype=torch.int64, device=cmap.device)
+    total = C.c_int64()
+    rc = lib().ezo_collision_map_lists(ctx.h, _ptr(cmap), V, words, int(n_nodes), _ptr(offsets), None, 0,
+                                       C.byref(total), _stream(stream))
+    if rc not in (EZO_OK, EZO_E_CAPACITY):
+        ctx._check(rc)
+    ids = torch.empty(max(total.value, 1), dtype=torch.int32, device=cmap.device)
+    if total.value:
+        ctx._check(lib().ezo_collision_map_lists(ctx.h, _ptr(cmap), V, words, int(n_nodes), _ptr(offsets),
+                                                 _ptr(ids), total.value, C.byref(total), _stream(stream)))
+    return offsets, ids[:total.value]

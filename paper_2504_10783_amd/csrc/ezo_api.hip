@@ -1322,6 +1322,95 @@ ezo_status ezo_inflate_paths(ezo_ctx* c, const ezo_robot* r, const float* obs, i
 }
 
 // ---------------------------------------------------------------------------
+// Collision map of a dynamic roadmap (appendix, DRM construction)
+// ---------------------------------------------------------------------------
+
+ezo_status ezo_collision_map(ezo_ctx* c, const ezo_robot* r, const float* q, int64_t n_nodes, const float* lo,
+                             float side, const int32_t* dims, uint32_t* map, int64_t row_words, void* stream) {
+    if (!c) return EZO_E_INVALID;
+    if (!r || n_nodes < 0 || !lo || !dims || !(side > 0.f) || !std::isfinite(side))
+        return ezo_fail(c, EZO_E_INVALID, "bad argument");
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 1 || !std::isfinite(lo[a])) return ezo_fail(c, EZO_E_INVALID, "bad voxel grid");
+    const int64_t V = (int64_t)dims[0] * dims[1] * dims[2];
+    if (row_words < (n_nodes + 31) / 32) return ezo_fail(c, EZO_E_INVALID, "row_words < ceil(n_nodes / 32)");
+    if (n_nodes > 0 && (!q || !map)) return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
+    if (V > ((int64_t)1 << 40) / std::max<int64_t>(row_words, 1)) return ezo_fail(c, EZO_E_UNSUPPORTED, "map too large");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = as_stream(stream);
+    if (map && row_words > 0) {
+        const int64_t words = V * row_words;
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 65535)), dim3(256), 0,
+                           st, map, words, 0u);
+        HIP_TRY(c, hipGetLastError());
+    }
+    if (n_nodes == 0) return EZO_OK;
+    ObsView ov;
+    GridView gv;
+    ezo_status s = prep_obstacles(c, r, nullptr, 0, st, &ov, &gv);   // zero shift: world frame
+    if (s) return s;
+    ov.n_ebox = 0;                                                    // the map holds the robot only
+    int T = 16;
+    while (T > 1 && tile_smem_bytes(T, r->slots, 4) > c->lds_cap) T >>= 1;
+    const size_t lds = tile_smem_bytes(T, r->slots, 4);
+    dim3 grid((unsigned)((n_nodes + T - 1) / T)), block(256);
+    const float3 lo3 = make_float3(lo[0], lo[1], lo[2]);
+    const int3 d3 = make_int3(dims[0], dims[1], dims[2]);
+#define EZO_LAUNCH_MAP(TT)                                                                                    \
+    do {                                                                                                      \
+        if (r->B > 0)                                                                                         \
+            hipLaunchKernelGGL((k_collision_map<TT, true>), grid, block, lds, st, r->view, ov, q, n_nodes, lo3, \
+                               side, d3, map, row_words);                                                     \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_collision_map<TT, false>), grid, block, lds, st, r->view, ov, q, n_nodes,     \
+                               lo3, side, d3, map, row_words);                                                \
+    } while (0)
+    switch (T) {
+        case 16: EZO_LAUNCH_MAP(16); break;
+        case 8: EZO_LAUNCH_MAP(8); break;
+        case 4: EZO_LAUNCH_MAP(4); break;
+        case 2: EZO_LAUNCH_MAP(2); break;
+        default: EZO_LAUNCH_MAP(1); break;
+    }
+#undef EZO_LAUNCH_MAP
+    HIP_TRY(c, hipGetLastError());
+    return EZO_OK;
+}
+
+ezo_status ezo_collision_map_lists(ezo_ctx* c, const uint32_t* map, int64_t n_rows, int64_t row_words,
+                                   int64_t n_nodes, int64_t* offsets, int32_t* ids, int64_t capacity, int64_t* total,
+                                   void* stream) {
+    if (!c) return EZO_E_INVALID;
+    if (n_rows < 0 || n_nodes < 0 || capacity < 0 || row_words < (n_nodes + 31) / 32)
+        return ezo_fail(c, EZO_E_INVALID, "bad sizes");
+    if (!offsets || (n_rows > 0 && row_words > 0 && !map) || (capacity > 0 && !ids))
+        return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = as_stream(stream);
+    void* w_cnt;
+    ezo_status s;
+    if ((s = ezo_ws_get(c, W_MAP_COUNTS, sizeof(int64_t) * (size_t)std::max<int64_t>(n_rows, 1), &w_cnt))) return s;
+    if (n_rows > 0) {
+        hipLaunchKernelGGL(k_row_popcount, dim3((unsigned)((n_rows * 64 + 255) / 256)), dim3(256), 0, st, map, n_rows,
+                           row_words, (int64_t*)w_cnt);
+        HIP_TRY(c, hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, (const int64_t*)w_cnt, n_rows, offsets);
+    HIP_TRY(c, hipGetLastError());
+    int64_t tot = 0;
+    HIP_TRY(c, hipMemcpyAsync(&tot, offsets + n_rows, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (total) *total = tot;
+    if (tot > capacity) return ezo_fail(c, EZO_E_CAPACITY, "%lld ids > capacity %lld", (long long)tot, (long long)capacity);
+    if (n_rows > 0 && tot > 0) {
+        hipLaunchKernelGGL(k_map_lists, dim3((unsigned)((n_rows * 64 + 255) / 256)), dim3(256), 0, st, map, n_rows,
+                           row_words, n_nodes, (const int64_t*)offsets, ids);
+        HIP_TRY(c, hipGetLastError());
+    }
+    return EZO_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Recovery from collisions found on a trajectory (Sec. V-B)
 // ---------------------------------------------------------------------------
 

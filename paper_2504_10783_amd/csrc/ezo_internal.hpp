@@ -29,7 +29,7 @@ enum Slot {
     W_OBS_REC, W_OBS_CENTRE, W_GRID_GEOM, W_GRID_COUNT, W_GRID_LIST, W_SAMPLES, W_FLAGS, W_CAND, W_NCAND, W_CSTAR,
     W_ADIR, W_TSTAR, W_PCOL, W_PANY, W_STATS, W_TABLE, W_KDEV, W_ACTIVE, W_PRED, W_SCREENED, W_MLP_H1, W_MLP_H2,
     W_MLP_CNT, W_PATH_M, W_PATH_OFF, W_PATH_PTS, W_PATH_IDX, W_PATH_CNT, W_RUN, W_NPLACED, W_PATH_EOFF,
-    W_ROUND_EDGES, W_ROUND_IDS, W_ROUND_SKIP, W_ROUND_A, W_ROUND_B, W_ROUND_NF, W_ROUND_ST, W_NSLOTS
+    W_ROUND_EDGES, W_ROUND_IDS, W_ROUND_SKIP, W_ROUND_A, W_ROUND_B, W_ROUND_NF, W_ROUND_ST, W_MAP_COUNTS, W_NSLOTS
 };
 
 struct ezo_ctx {

@@ -1064,6 +1064,171 @@ __global__ void __launch_bounds__(256) k_path_scatter(int dof, const int* __rest
 }
 
 // ---------------------------------------------------------------------------
+// Collision map of a dynamic roadmap (appendix, DRM construction).  Voxel
+// (i, j, k) of a dims.x x dims.y x dims.z grid of side `side` from corner lo
+// has index v = (k dims.y + j) dims.x + i and stands for its circumscribing
+// sphere (centre lo + side (i + 1/2, j + 1/2, k + 1/2), radius sqrt(3)/2 side).
+// Bit n of row v of the map is set iff node n's robot collides with it.
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Voxel index range [i0, i1] along one axis whose centres lie within R of x
+// (a superset: the exact test decides), clamped to the grid; empty if i0 > i1.
+__device__ __forceinline__ void voxel_range(float x, float R, float lo, float inv, int n, int* i0, int* i1) {
+    const float a = (x - R - lo) * inv - 0.5f, b = (x + R - lo) * inv - 0.5f;
+    *i0 = (int)fmaxf(floorf(a), 0.f);
+    *i1 = (int)fminf(ceilf(b), (float)(n - 1));
+}
+
+// One workgroup per tile of T nodes: FK into LDS, then every (node, sphere)
+// and (node, box) item tests the voxels within reach and sets the node's bit
+// in each hit voxel's row.
+template <int T, bool BOX>
+__global__ void __launch_bounds__(256) k_collision_map(RobotView rb, ObsView ob, const float* __restrict__ q,
+                                                       int64_t n, float3 lo, float side, int3 dims,
+                                                       uint32_t* __restrict__ map, int64_t row_words) {
+    extern __shared__ __align__(16) char smem[];
+    const int64_t base = (int64_t)blockIdx.x * T;
+    if (base >= n) return;
+    const int nv = (int)((n - base) < T ? (n - base) : T);
+    TileSmem t = carve_tile(smem, T, tile_slots(rb.n_spheres, rb.n_boxes), blockDim.x >> 6);
+    for (int i = threadIdx.x; i < T * rb.dof; i += blockDim.x) {
+        const int c = i % T, j = i / T;
+        if (c < nv) t.q[c * kMaxDof + j] = q[(base + c) * rb.dof + j];
+    }
+    __syncthreads();
+    tile_fk<BOX>(rb, ob, t, T, nv);
+    const float rv = 0.866025403784438647f * side, inv = 1.f / side;
+    const int S = rb.n_spheres;
+    for (ItemWalk w(nv); w.k < S; w.next(nv)) {
+        const int c = w.c;
+        const float4 C = t.cen[w.k * T + c];
+        if (!(isfinite(C.x) && isfinite(C.y) && isfinite(C.z))) continue;
+        const float R = C.w + rv;
+        int i0, i1, j0, j1, k0, k1;
+        voxel_range(C.x, R, lo.x, inv, dims.x, &i0, &i1);
+        voxel_range(C.y, R, lo.y, inv, dims.y, &j0, &j1);
+        voxel_range(C.z, R, lo.z, inv, dims.z, &k0, &k1);
+        const int64_t node = base + c;
+        const uint32_t bit = 1u << (node & 31);
+        for (int k = k0; k <= k1; ++k) {
+            const float dz = C.z - fmaf(side, (float)k + 0.5f, lo.z);
+            for (int j = j0; j <= j1; ++j) {
+                const float dy = C.y - fmaf(side, (float)j + 0.5f, lo.y);
+                const float dyz = fmaf(dy, dy, dz * dz);
+                for (int i = i0; i <= i1; ++i) {
+                    const float dx = C.x - fmaf(side, (float)i + 0.5f, lo.x);
+                    if (fmaf(dx, dx, dyz) < R * R) {
+                        const int64_t v = ((int64_t)k * dims.y + j) * dims.x + i;
+                        atomicOr(map + v * row_words + (node >> 5), bit);
+                    }
+                }
+            }
+        }
+    }
+    if (BOX) {
+        for (ItemWalk w(nv); w.k < rb.n_boxes; w.next(nv)) {
+            const int c = w.c;
+            const DBox X = tile_box(t, S, T, w.k, c);
+            if (!(isfinite(X.c[0]) && isfinite(X.c[1]) && isfinite(X.c[2]))) continue;
+            float e[3];                        // half widths of the box's world AABB
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                e[a] = fmaf(X.h[0], fabsf(X.R[3 * a]), fmaf(X.h[1], fabsf(X.R[3 * a + 1]), X.h[2] * fabsf(X.R[3 * a + 2])));
+            int i0, i1, j0, j1, k0, k1;
+            voxel_range(X.c[0], e[0] + rv, lo.x, inv, dims.x, &i0, &i1);
+            voxel_range(X.c[1], e[1] + rv, lo.y, inv, dims.y, &j0, &j1);
+            voxel_range(X.c[2], e[2] + rv, lo.z, inv, dims.z, &k0, &k1);
+            const int64_t node = base + c;
+            const uint32_t bit = 1u << (node & 31);
+            for (int k = k0; k <= k1; ++k)
+                for (int j = j0; j <= j1; ++j)
+                    for (int i = i0; i <= i1; ++i) {
+                        const float x = fmaf(side, (float)i + 0.5f, lo.x), y = fmaf(side, (float)j + 0.5f, lo.y),
+                                    z = fmaf(side, (float)k + 0.5f, lo.z);
+                        if (hit_sphere_box(X, x, y, z, rv)) {
+                            const int64_t v = ((int64_t)k * dims.y + j) * dims.x + i;
+                            atomicOr(map + v * row_words + (node >> 5), bit);
+                        }
+                    }
+        }
+    }
+}
+
+// Colliding nodes per voxel: popcount of each row.  One wave per row.
+__global__ void __launch_bounds__(256) k_row_popcount(const uint32_t* __restrict__ map, int64_t rows,
+                                                      int64_t row_words, int64_t* __restrict__ counts) {
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (row >= rows) return;
+    int64_t c = 0;
+    for (int64_t w = lane; w < row_words; w += 64) c += __popc(map[row * row_words + w]);
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if (lane == 0) counts[row] = c;
+}
+
+// Exclusive prefix sum of counts[0..n) into offsets[0..n] (offsets[n] = total).
+// One workgroup of 1024 threads, each summing a contiguous chunk.
+__global__ void __launch_bounds__(1024) k_scan_counts(const int64_t* __restrict__ counts, int64_t n,
+                                                      int64_t* __restrict__ offsets) {
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t a = min(n, tid * chunk), b = min(n, a + chunk);
+    int64_t sum = 0;
+    for (int64_t i = a; i < b; ++i) sum += counts[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {             // inclusive scan (Hillis-Steele)
+        const int64_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = part[tid] - sum;
+    for (int64_t i = a; i < b; ++i) {
+        offsets[i] = run;
+        run += counts[i];
+    }
+    if (tid == 1023) offsets[n] = part[1023];
+}
+
+// Node ids of each row in increasing order at offsets[row]: one wave per row,
+// each lane one word at a time, the wave's exclusive prefix of the popcounts
+// placing the lanes' ids.
+__global__ void __launch_bounds__(256) k_map_lists(const uint32_t* __restrict__ map, int64_t rows, int64_t row_words,
+                                                   int64_t n_nodes, const int64_t* __restrict__ offsets,
+                                                   int32_t* __restrict__ ids) {
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (row >= rows) return;
+    int64_t pos = offsets[row];
+    for (int64_t w0 = 0; w0 < row_words; w0 += 64) {
+        const int64_t w = w0 + lane;
+        uint32_t bits = w < row_words ? map[row * row_words + w] : 0u;
+        const int cnt = __popc(bits);
+        int incl = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off);
+            if (lane >= off) incl += v;
+        }
+        int64_t p = pos + incl - cnt;
+        while (bits) {
+            const int b = __builtin_ctz(bits);
+            bits &= bits - 1u;
+            const int64_t node = w * 32 + b;
+            if (node < n_nodes) ids[p] = (int32_t)node;
+            ++p;
+        }
+        pos += __shfl(incl, 63);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Recovery from collisions found on a trajectory (Sec. V-B)
 // ---------------------------------------------------------------------------
 
