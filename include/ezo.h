@@ -72,8 +72,11 @@ enum {
 
 /* Serial arm with standard Denavit-Hartenberg links,
  *   T_i = T_{i-1} Rz(q_i) Tz(d_i) Tx(a_i) Rx(alpha_i),  T_0 = identity,
- * and collision spheres rigidly attached to links (Sec. IV-D: sphere
- * geometries; Sec. II: kinematics and collision geometry are given).
+ * (a prismatic joint: Rz(0) Tz(d_i + q_i)), and collision spheres and boxes
+ * rigidly attached to links (Sec. IV-D: sphere and box geometries; Sec. II:
+ * kinematics and collision geometry are given).  A point robot in a plane
+ * (the Forest scene, Sec. VI-A) is two prismatic joints and one sphere of
+ * radius 0.
  * All arrays are host memory and are copied at ezo_robot_create. */
 typedef struct {
     int32_t dof;                 /* 1..EZO_MAX_DOF                                   */
@@ -96,6 +99,8 @@ typedef struct {
     const double *box_half;      /* [B][3] half extents along the box axes, >= 0     */
     int32_t n_box_pairs;         /* >= 0                                             */
     const int32_t *box_pairs;    /* [Q][2] box indices tested against each other     */
+    const int32_t *joint_type;   /* [dof] 0 revolute (theta = q), 1 prismatic (theta
+                                    = 0, offset d + q); NULL = all revolute          */
 } ezo_robot_desc;
 
 /* EI-ZO parameters: Alg. 1 Input (delta, eps, tau, Delta_max, N_p, N_f, N_b)

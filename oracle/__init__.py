@@ -56,7 +56,7 @@ class _Robot(C.Structure):
                 ("sphere_link", _ip), ("sphere_xyz", _dp), ("sphere_r", _dp),
                 ("n_self", C.c_int32), ("self_pairs", _ip),
                 ("n_boxes", C.c_int32), ("box_link", _ip), ("box_pose", _dp), ("box_half", _dp),
-                ("n_box_pairs", C.c_int32), ("box_pairs", _ip)]
+                ("n_box_pairs", C.c_int32), ("box_pairs", _ip), ("joint_type", _ip)]
 
 
 class Params(C.Structure):
@@ -156,12 +156,14 @@ class Robot:
         self.box_half = _d(desc.get("box_half", np.zeros((0, 3)))).reshape(-1, 3)
         self.box_pairs = np.ascontiguousarray(desc.get("box_pairs", np.zeros((0, 2))), dtype=np.int32).reshape(-1, 2)
         self.n_boxes = len(self.box_link)
+        jt = desc.get("joint_type")
+        self.joint_type = None if jt is None else np.ascontiguousarray(jt, dtype=np.int32)
         self._s = _Robot(self.dof, _ptr(self.a), _ptr(self.alpha), _ptr(self.d), _ptr(self.q_lo),
                          _ptr(self.q_hi), self.n_spheres, _ptr(self.sphere_link, _ip),
                          _ptr(self.sphere_xyz), _ptr(self.sphere_r), len(self.self_pairs),
                          _ptr(self.self_pairs, _ip), self.n_boxes, _ptr(self.box_link, _ip),
                          _ptr(self.box_pose), _ptr(self.box_half), len(self.box_pairs),
-                         _ptr(self.box_pairs, _ip))
+                         _ptr(self.box_pairs, _ip), _ptr(self.joint_type, _ip))
 
     @property
     def ref(self):

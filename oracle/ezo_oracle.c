@@ -53,6 +53,8 @@ typedef struct {
     const double *box_half;        /* [B][3] half extents along the box axes            */
     int32_t n_box_pairs;
     const int32_t *box_pairs;      /* [Q][2] box indices checked for self-collision     */
+    const int32_t *joint_type;     /* [dof] 0 revolute (theta = q), 1 prismatic (theta = 0,
+                                      offset d + q); NULL = all revolute              */
 } orc_robot;
 
 /* A signed-distance function over configurations; the configuration is in
@@ -112,13 +114,15 @@ static void trans(double x, double y, double z, double M[16]) {
     M[3] = x; M[7] = y; M[11] = z;
 }
 
-/* Link frames T_1..T_dof (world <- link i), each a row-major 4x4. */
+/* Link frames T_1..T_dof (world <- link i), each a row-major 4x4.  A
+ * prismatic joint keeps theta = 0 and slides along its z axis: d_i + q_i. */
 void orc_link_frames(const orc_robot *rb, const double *q, double *frames /* [dof][16] */) {
     double T[16], E[16];
     mat4_identity(T);
     for (int i = 0; i < rb->dof; ++i) {
-        rot_z(q[i], E);               mat4_mul(T, E, T);
-        trans(0, 0, rb->d[i], E);     mat4_mul(T, E, T);
+        const int prismatic = rb->joint_type && rb->joint_type[i] == 1;
+        rot_z(prismatic ? 0.0 : q[i], E);                       mat4_mul(T, E, T);
+        trans(0, 0, rb->d[i] + (prismatic ? q[i] : 0.0), E);   mat4_mul(T, E, T);
         trans(rb->a[i], 0, 0, E);     mat4_mul(T, E, T);
         rot_x(rb->alpha[i], E);       mat4_mul(T, E, T);
         memcpy(frames + 16 * i, T, sizeof(T));

@@ -31,6 +31,11 @@ and data are not public in this form):
            filling 6 random boxes in the obstacle box, plus a table box whose
            top is 20 cm below the base; one segment of length U[0.3, 1.0] rad
            free of self-collision, voxels and table along its length.
+  forest   seed 5: the Forest scene: a point robot in [0, 10]^2 (two
+           prismatic joints), 15 discs of radius 0.35 with centres uniform in
+           the central [1.5, 8.5]^2; a piecewise-linear path from (0.5, 0.5)
+           to (9.5, 9.5) found by breadth-first search on a 0.1 grid keeping
+           0.1 clearance, thinned to straight pieces that stay free.
 
 "Along the segment" is checked on a discretisation fine enough that no
 sphere moves more than MARGIN/2 between neighbouring points, so keeping a
@@ -267,7 +272,57 @@ def make_boxes():
     return out
 
 
-MAKERS = dict(tiny=make_tiny, dof7=make_dof7, batched=make_batched, sweep=make_sweep, boxes=make_boxes)
+def make_forest():
+    from collections import deque
+    rng = draw.rng_for(5)
+    desc = draw.point_robot_plane(10.0)
+    discs = draw.forest_discs(rng)
+    # world spheres: the point sits at (0, q_2, q_1)
+    obs = draw._f32(np.stack([np.zeros(len(discs)), discs[:, 1], discs[:, 0], discs[:, 2]], axis=1))
+    rob = oracle.Robot(desc)
+    h = 0.1
+    g = np.arange(0.05, 10.0, h)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    clear = np.min(np.hypot(X[..., None] - discs[:, 0], Y[..., None] - discs[:, 1]) - discs[:, 2], axis=2)
+    free = clear >= 0.1
+    start, goal = (4, 4), (94, 94)
+    prev = {start: None}
+    dq = deque([start])
+    while dq:
+        c = dq.popleft()
+        if c == goal:
+            break
+        for di, dj in ((1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, -1), (1, -1), (-1, 1)):
+            n = (c[0] + di, c[1] + dj)
+            if 0 <= n[0] < len(g) and 0 <= n[1] < len(g) and free[n] and n not in prev:
+                prev[n] = c
+                dq.append(n)
+    cells = [goal]
+    while prev[cells[-1]] is not None:
+        cells.append(prev[cells[-1]])
+    pts = np.array([[g[i], g[j]] for i, j in cells[::-1]])
+
+    def seg_free(a, b):
+        n = int(np.ceil(np.max(np.abs(b - a)) / 1e-3)) + 1
+        w = np.linspace(0.0, 1.0, n)[:, None]
+        _, sd, _, _ = oracle.check(rob, obs, (1 - w) * a + w * b)
+        return bool(np.all(sd >= MARGIN))
+
+    verts, i = [pts[0]], 0
+    while i < len(pts) - 1:                 # greedy: the farthest grid point reachable in a straight free line
+        j = len(pts) - 1
+        while j > i + 1 and not seg_free(pts[i], pts[j]):
+            j -= 1
+        verts.append(pts[j])
+        i = j
+    V = draw._f32(verts)
+    edges = np.stack([V[:-1], V[1:]], axis=1)
+    return dict(robot_arrays(desc, np.zeros((0, 2), np.int32)), joint_type=desc["joint_type"], obstacles=obs,
+                discs=discs, edges=edges, path_id=np.zeros(len(edges), np.int32))
+
+
+MAKERS = dict(tiny=make_tiny, dof7=make_dof7, batched=make_batched, sweep=make_sweep, boxes=make_boxes,
+              forest=make_forest)
 
 
 def main():

@@ -51,7 +51,7 @@ class RobotDesc(C.Structure):
                 ("n_self_pairs", C.c_int32), ("self_pairs", C.POINTER(C.c_int32)),
                 ("n_boxes", C.c_int32), ("box_link", C.POINTER(C.c_int32)), ("box_pose", C.POINTER(C.c_double)),
                 ("box_half", C.POINTER(C.c_double)), ("n_box_pairs", C.c_int32),
-                ("box_pairs", C.POINTER(C.c_int32))]
+                ("box_pairs", C.POINTER(C.c_int32)), ("joint_type", C.POINTER(C.c_int32))]
 
 
 class Params(C.Structure):
@@ -289,11 +289,13 @@ class Robot:
         self.n_spheres = len(k["r"])
         self.n_self = len(k["pairs"])
         self.n_boxes = len(k["box_link"])
+        jt = desc.get("joint_type")
+        k["joint_type"] = None if jt is None else np.ascontiguousarray(jt, dtype=np.int32)
         self.n_box_pairs = len(k["box_pairs"])
         d = RobotDesc(self.dof, dp(k["a"]), dp(k["alpha"]), dp(k["d"]), dp(k["q_lo"]), dp(k["q_hi"]),
                       self.n_spheres, ip(k["link"]), dp(k["xyz"]), dp(k["r"]), self.n_self, ip(k["pairs"]),
                       self.n_boxes, ip(k["box_link"]), dp(k["box_pose"]), dp(k["box_half"]), self.n_box_pairs,
-                      ip(k["box_pairs"]))
+                      ip(k["box_pairs"]), ip(k["joint_type"]) if k["joint_type"] is not None else None)
         h = C.c_void_p()
         ctx._check(lib().ezo_robot_create(ctx.h, C.byref(d), C.byref(h)))
         self.h = h

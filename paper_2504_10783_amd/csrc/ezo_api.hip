@@ -618,6 +618,13 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     for (int p = 0; p < 2 * P; ++p)
         if (d->self_pairs[p] < 0 || d->self_pairs[p] >= S)
             return ezo_fail(c, EZO_E_INVALID, "self pair entry %d = %d out of range", p, d->self_pairs[p]);
+    unsigned prismatic = 0;
+    if (d->joint_type)
+        for (int j = 0; j < dof; ++j) {
+            if (d->joint_type[j] != 0 && d->joint_type[j] != 1)
+                return ezo_fail(c, EZO_E_INVALID, "joint %d has type %d (0 revolute, 1 prismatic)", j, d->joint_type[j]);
+            if (d->joint_type[j] == 1) prismatic |= 1u << j;
+        }
     if (d->n_boxes < 0 || d->n_boxes > EZO_MAX_BOXES)
         return ezo_fail(c, EZO_E_UNSUPPORTED, "n_boxes %d not in [0, %d]", d->n_boxes, EZO_MAX_BOXES);
     if (d->n_box_pairs < 0) return ezo_fail(c, EZO_E_INVALID, "n_box_pairs < 0");
@@ -770,6 +777,7 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     char* b = reinterpret_cast<char*>(buf);
     r->r_max = r_max;
     r->view.dof = dof;
+    r->view.prismatic = prismatic;
     r->view.n_spheres = S;
     r->view.n_self = P;
     r->view.n_blocks = NB;

@@ -31,6 +31,7 @@ constexpr float kHuge = 3.0e38f;
 // ---------------------------------------------------------------------------
 struct RobotView {
     int dof;
+    unsigned prismatic;        // bit j: joint j is prismatic (theta = 0, offset d_j + q_j)
     int n_spheres;
     int n_self;
     int n_blocks;
@@ -228,8 +229,8 @@ __device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const Til
     const int dof = rb.dof;
     for (ItemWalk w(n_valid); w.k < dof; w.next(n_valid)) {
         const int c = w.c, j = w.k;
-        float s, co;
-        sincosf(t.q[c * kMaxDof + j], &s, &co);
+        float s = 0.f, co = 1.f;
+        if (!((rb.prismatic >> j) & 1u)) sincosf(t.q[c * kMaxDof + j], &s, &co);
         t.trig[j * T + c] = make_float2(co, s);
     }
     __syncthreads();
@@ -240,7 +241,9 @@ __device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const Til
         float p[3] = {-sh.x, -sh.y, -sh.z};
         for (int l = 0; l <= link; ++l) {
             const float2 cs = t.trig[l * T + c];
-            dh_compose(R, p, cs.x, cs.y, rb.dh[l]);
+            float4 dh = rb.dh[l];
+            if ((rb.prismatic >> l) & 1u) dh.y += t.q[c * kMaxDof + l];
+            dh_compose(R, p, cs.x, cs.y, dh);
         }
         {
             const float4 lc = rb.lbound[link];

@@ -32,6 +32,9 @@ PARAMS = {
                     n_f=10, n_b=11, n_mix=60, max_iters=50),
     "boxes": dict(eps=0.05, delta=0.05, tau=0.5, step_back_max=0.01, t_col=1e-4, n_p=10000,
                   n_f=20, n_b=11, n_mix=60, max_iters=50),
+    # the paper's Forest table: delta 0.05, eps 0.01, N_p 1000, N_f 10, N_ms 30, Delta 0.01
+    "forest": dict(eps=0.01, delta=0.05, tau=0.5, step_back_max=0.01, t_col=1e-4, n_p=1000,
+                   n_f=10, n_b=11, n_mix=30, max_iters=50),
 }
 
 
@@ -42,7 +45,7 @@ def load(name: str) -> dict:
     return data
 
 
-BOX_KEYS = ("box_link", "box_pose", "box_half", "box_pairs")
+BOX_KEYS = ("box_link", "box_pose", "box_half", "box_pairs", "joint_type")
 
 
 def robot(data: dict) -> dict:

@@ -210,3 +210,24 @@ def voxel_obstacles(rng: np.random.Generator, lo, hi, side: float = 0.08, n_shap
         keep |= np.all(np.abs(cen - c0) <= sz / 2, axis=1)
     v = cen[keep]
     return _f32(np.concatenate([v, np.full((len(v), 1), np.sqrt(3) / 2 * side)], axis=1))
+
+
+def point_robot_plane(extent: float = 10.0):
+    """A point robot in a plane as a 2-DOF arm of two prismatic joints
+    (theta = 0, offset d + q): joint 1 slides along world z, alpha_1 = -pi/2
+    turns the next axis onto world y, joint 2 slides along it; the point
+    (one sphere of radius 0 on link 2) sits at world (0, q_2, q_1).  Limits
+    [0, extent] on both joints."""
+    return dict(
+        dof=2, a=np.zeros(2, F32), alpha=_f32([-PI / 2, 0.0]), d=np.zeros(2, F32),
+        q_lo=np.zeros(2, F32), q_hi=_f32([extent, extent]),
+        sphere_link=np.array([1], np.int32), sphere_xyz=np.zeros((1, 3), F32), sphere_r=np.zeros(1, F32),
+        joint_type=np.array([1, 1], np.int32),
+    )
+
+
+def forest_discs(rng: np.random.Generator, n: int = 15, lo: float = 1.5, hi: float = 8.5, r: float = 0.35):
+    """The Forest scene's discs in configuration coordinates (q_1, q_2, r):
+    centres uniform in the central [lo, hi]^2 of the domain, radius r."""
+    c = rng.uniform(lo, hi, size=(n, 2))
+    return _f32(np.concatenate([c, np.full((n, 1), r)], axis=1))
