@@ -72,6 +72,23 @@ def measured_traffic(workload, kernel_instance):
     return None
 
 
+def measured_valu(workload, kernel_instance):
+    """Counted FP32 VALU flop per launch (64 lanes x (ADD + MUL + TRANS +
+    2 FMA) wave instructions, rocprofv3 SQ_INSTS_VALU_*_F32) of the kernel's
+    family from the committed summary of this workload, or None (no summary,
+    kernel not measured, or kernel sources changed since)."""
+    path = os.path.join(ROOT, "profiles", f"valu_fp32__{workload}_inflate.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("valu-json: "):
+            rec = json.loads(line[len("valu-json: "):])
+            if rec.get("source_sha256") != kernel_source_sha256():
+                return None
+            return rec.get("fp32_flop_per_launch", {}).get(kernel_instance.split("<")[0])
+    return None
+
+
 def flop_per_check(n_spheres, n_obs, n_self):
     return PAIR_FLOP * (n_spheres * n_obs + n_self) + FK_FLOP
 
@@ -715,6 +732,13 @@ def main():
                 "all_pairs_per_check": rob.n_spheres * int(obs.shape[0]) + rob.n_self,
                 "box_pair_tests_counted": False if rob.n_boxes > 0 or "env_boxes" in data else None,
                 "all_pairs_equivalent_tflops": all_pairs / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0}
+    counted = measured_valu(name, instance) if instance else None
+    if counted is not None and dom_ms > 0:
+        # the second form of the FP32 fraction: counted FP32 VALU flop of a
+        # launch (committed rocprofv3 summary) over the live average launch time
+        ct = counted / (roofline["avg_launch_ms"] * 1e-3) / 1e12
+        roofline["counted_fp32"] = {"flop_per_launch": counted, "tflops": ct, "frac": ct / PEAK_FP32_TFLOPS,
+                                    "source": f"profiles/valu_fp32__{name}_inflate.md"}
 
     line = {
         "metric": "collision-checked configs/sec and edges inflated/sec (7-DOF), % FP32 VALU peak",
