@@ -1230,7 +1230,10 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         if (!exec) {
             for (int ph = 0; ph < EZO_NUM_PHASES; ++ph) {
                 float ms = 0.f;
-                if (hipEventElapsedTime(&ms, c->tev[2 * ph], c->tev[2 * ph + 1]) == hipSuccess) c->phase_ms[ph] += ms;
+                if (hipEventElapsedTime(&ms, c->tev[2 * ph], c->tev[2 * ph + 1]) == hipSuccess)
+                    c->phase_ms[ph] += ms;
+                else
+                    (void)hipGetLastError();               // leave no error for the next check
             }
             c->timed_iters++;
         }

@@ -829,17 +829,41 @@ __device__ inline void place_rounds(int e, int dof, const float* __restrict__ v,
                 else best = key[q] < best ? key[q] : best;
             }
         } else {
-            for (int j = tid; j < n; j += nt)
-                if (alive[j]) {
+            // four candidates per thread at a time: their c* and t* loads are
+            // issued together, then tested (the same dot products, in the
+            // same order, as one candidate at a time)
+            constexpr int U = 4;
+            float rw[kMaxDof];
+#pragma unroll
+            for (int k = 0; k < kMaxDof; ++k) rw[k] = row[k];
+            for (int j0 = tid; j0 < n; j0 += U * nt) {
+                float cu[U][kMaxDof], tu[U];
+                bool live[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 + u * nt;
+                    live[u] = j < n && alive[j];
+#pragma unroll
+                    for (int k = 0; k < kMaxDof; ++k)
+                        cu[u][k] = (live[u] && k < dof) ? cs[(size_t)k * cand_cap + j] : 0.f;
+                    tu[u] = live[u] ? ts[j] : 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (!live[u]) continue;
+                    const int j = j0 + u * nt;
                     float ac = 0.f;
-                    for (int k = 0; k < dof; ++k) ac = fmaf(row[k], cs[(size_t)k * cand_cap + j], ac);
+#pragma unroll
+                    for (int k = 0; k < kMaxDof; ++k)
+                        if (k < dof) ac = fmaf(rw[k], cu[u][k], ac);
                     if (ac > rhs) {
                         alive[j] = 0;
                     } else {
-                        const unsigned long long kj = ((unsigned long long)__float_as_uint(ts[j]) << 32) | (unsigned)j;
+                        const unsigned long long kj = ((unsigned long long)__float_as_uint(tu[u]) << 32) | (unsigned)j;
                         best = kj < best ? kj : best;
                     }
                 }
+            }
         }
     }
     if (tid == 0) {
