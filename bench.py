@@ -414,7 +414,7 @@ def paths_compare(args):
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"{name}: {WORKLOADS[name]}", "paths": len(counts),
                        "edges_per_path": [c - 1 for c in counts]},
-            "rounds": max(counts) - 1,
+            "longest_path_edges": max(counts) - 1,
             "speedup_vs_independent": res["independent"]["ms_per_call"] / res["sequential"]["ms_per_call"],
             **res}
     print(json.dumps(line), flush=True)

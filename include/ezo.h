@@ -294,8 +294,13 @@ ezo_status ezo_inflate_edges(ezo_ctx *ctx, const ezo_robot *robot, const float *
  * of a path is inflated only if its segment L_k is not contained in the set
  * of an earlier edge of the same path (both ends satisfy every row of that
  * set, FP32), where only sets of edges that were inflated and ended
- * CERTIFIED or MAX_ITERS count.  Paths are independent of one another; round
- * k inflates edge k of every path still running in one batched pass.
+ * CERTIFIED or MAX_ITERS count.  Paths are independent of one another.
+ * Since an edge's set does not depend on any other edge, the call works in
+ * rounds over windows of s consecutive edges of every path (s chosen so that
+ * a round holds about 128 edges): window edges inside a set of an earlier
+ * round are skipped, the others are inflated in one batched pass, and then
+ * resolved in path order (an edge inside the set of an earlier edge of its
+ * window is dropped).  The result is that of the sequential process.
  *
  * vertices dev f32 [sum_p path_vertices[p]][dof], the paths' vertices back
  * to back; path_vertices host i32 [n_paths], each >= 2.  Edges are numbered

@@ -450,6 +450,8 @@ ezo_status tune_bisect_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov
 // |S| hit-and-run samples per edge from it, and as candidates the first n_p
 // of them in collision.
 constexpr int kItersPerGraph = 4;        // iterations captured per replayed graph
+// Edges per round of ezo_inflate_paths (a path window of s = kPathBatch / paths edges).
+constexpr int kPathBatch = 128;
 
 ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const GridView& gv, const float* edges,
                           int E, const ezo_params* p, int S_cap, int64_t stride, float* A, float* b, int* n_faces,
@@ -1294,38 +1296,53 @@ ezo_status ezo_inflate_paths(ezo_ctx* c, const ezo_robot* r, const float* obs, i
         return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
     const int dof = r->dof, P = n_paths, cap = p->face_capacity;
     if (cap < 1) return ezo_fail(c, EZO_E_CAPACITY, "face_capacity %d", cap);
+    // window of s edges per path and round: enough edges per round to keep
+    // the chip busy (kPathBatch), at most the longest path (one round)
+    const int s_win = std::max(1, std::min({max_k, (kPathBatch + P - 1) / P, kPathWindowMax}));
+    const int slots = P * s_win, rounds = (max_k + s_win - 1) / s_win;
     HIP_TRY(c, hipSetDevice(c->device));
     void *w_eo, *w_re, *w_ri, *w_rs, *w_ra, *w_rb, *w_rn, *w_rt;
     ezo_status s;
     if ((s = ezo_ws_get(c, W_PATH_EOFF, sizeof(int) * (size_t)(P + 1), &w_eo)) ||
-        (s = ezo_ws_get(c, W_ROUND_EDGES, sizeof(float) * (size_t)P * 2 * dof, &w_re)) ||
-        (s = ezo_ws_get(c, W_ROUND_IDS, sizeof(int) * (size_t)P, &w_ri)) ||
-        (s = ezo_ws_get(c, W_ROUND_SKIP, (size_t)P, &w_rs)) ||
-        (s = ezo_ws_get(c, W_ROUND_A, sizeof(float) * (size_t)P * cap * dof, &w_ra)) ||
-        (s = ezo_ws_get(c, W_ROUND_B, sizeof(float) * (size_t)P * cap, &w_rb)) ||
-        (s = ezo_ws_get(c, W_ROUND_NF, sizeof(int) * (size_t)P, &w_rn)) ||
-        (s = ezo_ws_get(c, W_ROUND_ST, sizeof(int) * (size_t)P, &w_rt)))
+        (s = ezo_ws_get(c, W_ROUND_EDGES, sizeof(float) * (size_t)slots * 2 * dof, &w_re)) ||
+        (s = ezo_ws_get(c, W_ROUND_IDS, sizeof(int) * (size_t)slots, &w_ri)) ||
+        (s = ezo_ws_get(c, W_ROUND_SKIP, (size_t)slots, &w_rs)) ||
+        (s = ezo_ws_get(c, W_ROUND_A, sizeof(float) * (size_t)slots * cap * dof, &w_ra)) ||
+        (s = ezo_ws_get(c, W_ROUND_B, sizeof(float) * (size_t)slots * cap, &w_rb)) ||
+        (s = ezo_ws_get(c, W_ROUND_NF, sizeof(int) * (size_t)slots, &w_rn)) ||
+        (s = ezo_ws_get(c, W_ROUND_ST, sizeof(int) * (size_t)slots, &w_rt)))
         return s;
     hipStream_t st = c->stream;
     HIP_TRY(c, hipEventRecord(c->ev_in, as_stream(stream)));
     HIP_TRY(c, hipStreamWaitEvent(st, c->ev_in, 0));
     HIP_TRY(c, hipMemcpyAsync(w_eo, eoff.data(), sizeof(int) * (P + 1), hipMemcpyHostToDevice, st));
     HIP_TRY(c, hipStreamSynchronize(st));            // eoff is a host vector
-    std::vector<ezo_edge_stats> rstats(P);
-    for (int rr = 0; rr < max_k; ++rr) {
-        EZO_KLAUNCH(c, k_path_round, dim3(P), dim3(256), 0, st, dof, vertices, (const int*)w_eo, rr, A, b, n_faces,
-                    edge_status, cap, covered_by, (float*)w_re, (int*)w_ri, (uint8_t*)w_rs);
+    std::vector<ezo_edge_stats> rstats(slots);
+    for (int rr = 0; rr < rounds; ++rr) {
+        EZO_KLAUNCH(c, k_path_round, dim3(P), dim3(256), 0, st, dof, vertices, (const int*)w_eo, rr, s_win, A, b,
+                    n_faces, edge_status, cap, covered_by, (float*)w_re, (int*)w_ri, (uint8_t*)w_rs);
         HIP_TRY(c, hipGetLastError());
-        if ((s = inflate_core(c, r, obs, n_obs, (const float*)w_re, P, p, (float*)w_ra, (float*)w_rb, (int*)w_rn,
-                              (int*)w_rt, stats ? rstats.data() : nullptr, st, (const int*)w_ri,
+        if ((s = inflate_core(c, r, obs, n_obs, (const float*)w_re, slots, p, (float*)w_ra, (float*)w_rb,
+                              (int*)w_rn, (int*)w_rt, stats ? rstats.data() : nullptr, st, (const int*)w_ri,
                               (const uint8_t*)w_rs)))
             return s;
-        EZO_KLAUNCH(c, k_path_scatter, dim3(P), dim3(256), 0, st, dof, (const int*)w_eo, rr, (const float*)w_ra,
-                    (const float*)w_rb, (const int*)w_rn, (const int*)w_rt, cap, A, b, n_faces, edge_status);
+        EZO_KLAUNCH(c, k_path_resolve, dim3(P), dim3(256), 0, st, dof, vertices, (const int*)w_eo, rr, s_win,
+                    (const float*)w_ra, (const float*)w_rb, (const int*)w_rn, (const int*)w_rt, cap, A, b, n_faces,
+                    edge_status, covered_by);
         HIP_TRY(c, hipGetLastError());
         if (stats)
             for (int q = 0; q < P; ++q)
-                if (rr < eoff[q + 1] - eoff[q]) stats[eoff[q] + rr] = rstats[q];
+                for (int i = 0; i < s_win; ++i)
+                    if (rr * s_win + i < eoff[q + 1] - eoff[q]) stats[eoff[q] + rr * s_win + i] = rstats[q * s_win + i];
+    }
+    if (stats) {
+        // an edge inflated in its window but then found inside an earlier
+        // edge's set of the same window holds no set: no statistics
+        std::vector<int32_t> cov(eoff[P]);
+        HIP_TRY(c, hipMemcpyAsync(cov.data(), covered_by, sizeof(int32_t) * cov.size(), hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+        for (size_t g = 0; g < cov.size(); ++g)
+            if (cov[g] >= 0) stats[g] = ezo_edge_stats{};
     }
     HIP_TRY(c, hipEventRecord(c->ev_out, st));
     HIP_TRY(c, hipStreamWaitEvent(as_stream(stream), c->ev_out, 0));

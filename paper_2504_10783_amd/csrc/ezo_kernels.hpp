@@ -997,51 +997,32 @@ __global__ void __launch_bounds__(256) k_advance(int* __restrict__ k_dev, int ma
     }
 }
 
+// Largest window of ezo_inflate_paths (edges of one path per round).
+constexpr int kPathWindowMax = 1024;
+
 // ---------------------------------------------------------------------------
-// Sequential inflation of piecewise-linear paths with the containment skip
-// (Sec. V-A).  Round r holds edge r of every path; an edge whose segment lies
-// in the set of an earlier edge of its path is not inflated.  Path p's edges
-// are eoff[p] .. eoff[p+1]-1 (global numbering); its vertices start at
-// eoff[p] + p, so edge g of path p runs from vertex g + p to g + p + 1.
+// Inflation of piecewise-linear paths with the containment skip (Sec. V-A).
+// Path p's edges are eoff[p] .. eoff[p+1]-1 (global numbering); its vertices
+// start at eoff[p] + p, so edge g of path p runs from vertex g + p to g + p + 1.
+// Round r takes the window of s edges at positions r s .. r s + s - 1 of every
+// path; slot p s + i of the round holds position r s + i of path p.
 // ---------------------------------------------------------------------------
 
-// One workgroup (256 threads) per path.  Slot p of round r: the segment, its
-// global edge index and whether it is skipped -- past the path's end, or
-// contained in the set of an earlier edge h of the path that was inflated
-// (covered_by[h] == -1) and ended CERTIFIED or MAX_ITERS; covered_by[g] = the
-// first such h, else -1.  One wave per earlier set, lanes over its rows: both
-// endpoints satisfy every row a.v <= b (FP32, fmaf in index order).
-__global__ void __launch_bounds__(256) k_path_round(int dof, const float* __restrict__ verts,
-                                                    const int* __restrict__ eoff, int r,
-                                                    const float* __restrict__ A, const float* __restrict__ bvec,
-                                                    const int* __restrict__ n_faces,
-                                                    const int* __restrict__ status, int cap,
-                                                    int* __restrict__ covered_by, float* __restrict__ round_edges,
-                                                    int* __restrict__ round_ids, uint8_t* __restrict__ round_skip) {
-    __shared__ int best;
-    const int p = blockIdx.x;
-    const int e0 = eoff[p], K = eoff[p + 1] - e0;
-    float* re = round_edges + (size_t)p * 2 * dof;
-    if (r >= K) {
-        if (threadIdx.x < 2 * dof) re[threadIdx.x] = 0.f;
-        if (threadIdx.x == 0) {
-            round_ids[p] = e0;
-            round_skip[p] = 1;
-        }
-        return;
-    }
-    const int g = e0 + r;
-    const float* v = verts + (size_t)(g + p) * dof;
-    if (threadIdx.x < 2 * dof) re[threadIdx.x] = v[threadIdx.x];
-    if (threadIdx.x == 0) best = 0x7fffffff;
+// Smallest h in [h0, h1) whose set contains the segment v[0 .. 2 dof), or
+// 0x7fffffff; set(h, &A_h, &b_h, &F) gives set h's rows and whether it counts
+// (an inflated edge that ended CERTIFIED or MAX_ITERS).  Both ends satisfy
+// every row a.v <= b (FP32, fmaf in index order).  One wave per candidate
+// set, lanes over its rows; the whole workgroup calls it (it has barriers).
+template <class SetFn>
+__device__ inline int first_containing_set(int dof, const float* v, int h0, int h1, SetFn set, int* best) {
+    if (threadIdx.x == 0) *best = 0x7fffffff;
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
-    for (int h = e0 + wave; h < g; h += n_waves) {
-        const int sh = status[h];
-        if (covered_by[h] != -1 || (sh != 0 && sh != 1)) continue;       // uniform over the wave
-        const int F = min(max(n_faces[h], 0), cap);
-        if (F == 0) continue;
-        const float* Ah = A + (size_t)h * cap * dof;
+    for (int h = h0 + wave; h < h1; h += n_waves) {
+        const float* Ah;
+        const float* bh;
+        int F;
+        if (!set(h, &Ah, &bh, &F) || F == 0) continue;        // uniform over the wave
         bool out = false;
         for (int f = lane; f < F; f += 64) {
             float a1 = 0.f, a2 = 0.f;
@@ -1050,40 +1031,113 @@ __global__ void __launch_bounds__(256) k_path_round(int dof, const float* __rest
                 a1 = fmaf(a, v[j], a1);
                 a2 = fmaf(a, v[dof + j], a2);
             }
-            const float bb = bvec[(size_t)h * cap + f];
-            out |= !(a1 <= bb && a2 <= bb);
+            out |= !(a1 <= bh[f] && a2 <= bh[f]);
         }
-        if (__ballot(out) == 0 && lane == 0) atomicMin(&best, h);
+        if (__ballot(out) == 0 && lane == 0) atomicMin(best, h);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const int c = best == 0x7fffffff ? -1 : best;
-        covered_by[g] = c;
-        round_ids[p] = g;
-        round_skip[p] = c >= 0;
+    return *best;
+}
+
+// One workgroup (256 threads) per path: the s slots of round r.  A slot past
+// the path's end is skipped; an edge whose segment lies in a set of an
+// earlier round is skipped too (covered_by = that set's edge); the others are
+// inflated (covered_by = -1 for now).
+__global__ void __launch_bounds__(256) k_path_round(int dof, const float* __restrict__ verts,
+                                                    const int* __restrict__ eoff, int r, int s,
+                                                    const float* __restrict__ A, const float* __restrict__ bvec,
+                                                    const int* __restrict__ n_faces,
+                                                    const int* __restrict__ status, int cap,
+                                                    int* __restrict__ covered_by, float* __restrict__ round_edges,
+                                                    int* __restrict__ round_ids, uint8_t* __restrict__ round_skip) {
+    __shared__ int best;
+    const int p = blockIdx.x;
+    const int e0 = eoff[p], K = eoff[p + 1] - e0;
+    for (int i = 0; i < s; ++i) {
+        const int slot = p * s + i, k = r * s + i;
+        float* re = round_edges + (size_t)slot * 2 * dof;
+        if (k >= K) {
+            if (threadIdx.x < 2 * dof) re[threadIdx.x] = 0.f;
+            if (threadIdx.x == 0) {
+                round_ids[slot] = e0;
+                round_skip[slot] = 1;
+            }
+            continue;                                            // uniform over the workgroup
+        }
+        const int g = e0 + k;
+        const float* v = verts + (size_t)(g + p) * dof;
+        if (threadIdx.x < 2 * dof) re[threadIdx.x] = v[threadIdx.x];
+        // sets of earlier rounds: final arrays, written by earlier kernels
+        auto set = [&](int h, const float** Ah, const float** bh, int* F) {
+            const int sh = status[h];
+            *Ah = A + (size_t)h * cap * dof;
+            *bh = bvec + (size_t)h * cap;
+            *F = min(max(n_faces[h], 0), cap);
+            return covered_by[h] == -1 && (sh == 0 || sh == 1);
+        };
+        const int h = first_containing_set(dof, v, e0, e0 + r * s, set, &best);
+        if (threadIdx.x == 0) {
+            const int c = h == 0x7fffffff ? -1 : h;
+            covered_by[g] = c;
+            round_ids[slot] = g;
+            round_skip[slot] = c >= 0;
+        }
     }
 }
 
-// Slot p of the round's inflation into global edge round_ids[p]: rows,
-// face count and status (a contained edge: CONTAINED, no rows).  One
-// workgroup per path; slots past a path's end store nothing.
-__global__ void __launch_bounds__(256) k_path_scatter(int dof, const int* __restrict__ eoff, int r,
+// One workgroup per path, the window's edges in path order: an inflated edge
+// whose segment lies in the set of an earlier inflated edge of the same
+// window is contained after all (covered_by = the first such edge, status
+// CONTAINED, no rows); every other slot's rows, face count and status go to
+// its global edge.  (Sets of earlier rounds were checked before inflation.)
+__global__ void __launch_bounds__(256) k_path_resolve(int dof, const float* __restrict__ verts,
+                                                      const int* __restrict__ eoff, int r, int s,
                                                       const float* __restrict__ rA, const float* __restrict__ rb,
                                                       const int* __restrict__ rnf, const int* __restrict__ rst,
                                                       int cap, float* __restrict__ A, float* __restrict__ bvec,
-                                                      int* __restrict__ n_faces, int* __restrict__ status) {
+                                                      int* __restrict__ n_faces, int* __restrict__ status,
+                                                      int* __restrict__ covered_by) {
+    __shared__ int best;
+    __shared__ uint8_t kept[kPathWindowMax];                     // window edge i holds its set
     const int p = blockIdx.x;
-    const int e0 = eoff[p];
-    if (r >= eoff[p + 1] - e0) return;
-    const int g = e0 + r;
-    const int F = min(max(rnf[p], 0), cap);
-    const float* sA = rA + (size_t)p * cap * dof;
-    float* dA = A + (size_t)g * cap * dof;
-    for (int i = threadIdx.x; i < F * dof; i += blockDim.x) dA[i] = sA[i];
-    for (int f = threadIdx.x; f < F; f += blockDim.x) bvec[(size_t)g * cap + f] = rb[(size_t)p * cap + f];
-    if (threadIdx.x == 0) {
-        n_faces[g] = rnf[p];
-        status[g] = rst[p];
+    const int e0 = eoff[p], K = eoff[p + 1] - e0;
+    const int w0 = e0 + r * s;                                   // first edge of the window
+    // the window's sets come from the round buffers (written by the inflation
+    // kernels) and the decisions taken so far from LDS: this workgroup's own
+    // global writes of this kernel are never read back
+    auto set = [&](int h, const float** Ah, const float** bh, int* F) {
+        const int sl = p * s + (h - w0);
+        const int sh = rst[sl];
+        *Ah = rA + (size_t)sl * cap * dof;
+        *bh = rb + (size_t)sl * cap;
+        *F = min(max(rnf[sl], 0), cap);
+        return kept[h - w0] != 0 && (sh == 0 || sh == 1);
+    };
+    for (int i = 0; i < s && r * s + i < K; ++i) {
+        const int slot = p * s + i, g = w0 + i;
+        const float* v = verts + (size_t)(g + p) * dof;
+        int h = 0x7fffffff;
+        const bool inflated = covered_by[g] == -1;               // uniform over the workgroup
+        if (inflated) h = first_containing_set(dof, v, w0, g, set, &best);
+        if (threadIdx.x == 0) kept[i] = inflated && h == 0x7fffffff;
+        if (inflated && h != 0x7fffffff) {
+            if (threadIdx.x == 0) {
+                covered_by[g] = h;
+                n_faces[g] = 0;
+                status[g] = 4;                                   // EZO_EDGE_CONTAINED
+            }
+        } else {
+            const int F = min(max(rnf[slot], 0), cap);
+            const float* sA = rA + (size_t)slot * cap * dof;
+            float* dA = A + (size_t)g * cap * dof;
+            for (int t = threadIdx.x; t < F * dof; t += blockDim.x) dA[t] = sA[t];
+            for (int f = threadIdx.x; f < F; f += blockDim.x) bvec[(size_t)g * cap + f] = rb[(size_t)slot * cap + f];
+            if (threadIdx.x == 0) {
+                n_faces[g] = rnf[slot];
+                status[g] = rst[slot];
+            }
+        }
+        __syncthreads();                                         // kept[i] visible to the next edge
     }
 }
 
