@@ -604,6 +604,7 @@ def main():
     ap.add_argument("--sweep-sizes", default="1048576,4194304,16777216")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-call-per-edge comparison (E > 1)")
     ap.add_argument("--screen", action="store_true", help="learned screen vs exact comparison")
     ap.add_argument("--screen-epochs", type=int, default=10)
     ap.add_argument("--recovery", action="store_true", help="trajectory check + set update + containment timings")
@@ -769,6 +770,29 @@ def main():
                           for e in ezo.tune_cache_entries()
                           if e["obstacles"] == int(obs.shape[0]) or e["kernel"] == "sample"],
     }
+    if E > 1 and not args.no_plain:
+        # the plain GPU form: the same edges, one call per edge (edge e draws
+        # the stream of edge id e in both forms, so the sets are identical),
+        # after the timed region
+        prm1 = [ezo.make_params(dof=desc["dof"], seed=args.seed, edge_id_base=e, **workloads.PARAMS[name])
+                for e in range(E)]
+        outs = [ezo.inflate_edges(ctx, rob, obs, edges[e:e + 1], prm1[e]) for e in range(E)]   # warm-up
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 3))
+        t2 = time.perf_counter()
+        checks1 = 0
+        for _ in range(reps):
+            for e in range(E):
+                outs[e] = ezo.inflate_edges(ctx, rob, obs, edges[e:e + 1], prm1[e])
+                checks1 += outs[e].stats[0]["exact_checks"]
+        torch.cuda.synchronize()
+        dt1 = (time.perf_counter() - t2) / reps
+        same = all(torch.equal(outs[e].n_faces[0], out.n_faces[e]) and torch.equal(outs[e].status[0], out.status[e])
+                   and torch.equal(outs[e].A[0, :int(out.n_faces[e])], out.A[e, :int(out.n_faces[e])])
+                   for e in range(E))
+        line["plain"] = {"ms_per_step": dt1 * 1e3, "edges_per_s": E / dt1, "configs_per_s": checks1 / reps / dt1,
+                         "calls_per_step": E, "equal_to_batched": bool(same)}
+        line["batched_speedup_vs_plain"] = (E / (dt / args.steps)) / (E / dt1)
     if not args.no_cpu_baseline:
         idx = [0] if E == 1 else sorted({int(np.nonzero(data["path_id"] == p)[0][0]) for p in np.unique(data["path_id"])})
         line["cpu_baseline"] = cpu_baseline(name, data, desc, args.seed, idx)
