@@ -32,7 +32,7 @@ WORKLOADS = {
     "dof7": "7-DOF DH arm (7x10 spheres, 1500 self pairs), 512 obstacle spheres, one edge; "
             "N_p=10000, eps=0.05, delta=0.05, tau=0.5, N_f=10, N_b=11, N_mix=60",
     "batched": "7-DOF DH arm, 2048 obstacle spheres, 96 edges of 8 uneven paths in one call; "
-               "N_p=10000, eps=0.05, delta=0.05, N_mix=60",
+               "eps=0.05, delta=0.05, N_mix=60 (N_p in config.n_p)",
     "tiny": "3-DOF planar arm (12 spheres), 20 obstacle discs, one edge; N_p=1000, eps=0.1, delta=0.05",
     "forest": "Forest scene: point robot in [0,10]^2 (two prismatic joints), 15 discs r=0.35, a 4-edge path; "
               "N_p=1000, eps=0.01, delta=0.05, N_f=10, N_b=11, N_mix=30",
@@ -53,37 +53,37 @@ def kernel_source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(workload, kernel_instance):
+def measured_traffic(workload, kernel_instance, n_p):
     """HBM bytes per launch of the kernel of `kernel_instance` (its counters
     pooled over launch shapes) from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary of this workload (each counter scaled by its reading
     for a plain 1 GiB copy), or None when there is no summary, the kernel was
-    not measured, or the kernel sources changed since the counters were
-    taken."""
+    not measured, the kernel sources changed since the counters were taken,
+    or the counters were taken at another N_p (samples per iteration)."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic__{workload}_inflate.md")
     if not os.path.exists(path):
         return None
     for line in open(path):
         if line.startswith("traffic-json: "):
             rec = json.loads(line[len("traffic-json: "):])
-            if rec.get("source_sha256") != kernel_source_sha256():
+            if rec.get("source_sha256") != kernel_source_sha256() or rec.get("n_p") != n_p:
                 return None
             return rec.get("bytes_per_launch", {}).get(kernel_instance.split("<")[0])
     return None
 
 
-def measured_valu(workload, kernel_instance):
+def measured_valu(workload, kernel_instance, n_p):
     """Counted FP32 VALU flop per launch (64 lanes x (ADD + MUL + TRANS +
     2 FMA) wave instructions, rocprofv3 SQ_INSTS_VALU_*_F32) of the kernel's
     family from the committed summary of this workload, or None (no summary,
-    kernel not measured, or kernel sources changed since)."""
+    kernel not measured, kernel sources changed since, or another N_p)."""
     path = os.path.join(ROOT, "profiles", f"valu_fp32__{workload}_inflate.md")
     if not os.path.exists(path):
         return None
     for line in open(path):
         if line.startswith("valu-json: "):
             rec = json.loads(line[len("valu-json: "):])
-            if rec.get("source_sha256") != kernel_source_sha256():
+            if rec.get("source_sha256") != kernel_source_sha256() or rec.get("n_p") != n_p:
                 return None
             return rec.get("fp32_flop_per_launch", {}).get(kernel_instance.split("<")[0])
     return None
@@ -93,7 +93,43 @@ def flop_per_check(n_spheres, n_obs, n_self):
     return PAIR_FLOP * (n_spheres * n_obs + n_self) + FK_FLOP
 
 
-def cpu_baseline(name, data, desc, seed, edges_idx):
+def samples_arg(v):
+    if v in ("paper", "tuned"):
+        return v
+    if not v.isdigit() or int(v) < 1:
+        raise argparse.ArgumentTypeError("--samples takes 'paper', 'tuned' or a positive count")
+    return int(v)
+
+
+def sample_mode(args, name):
+    """N_p source: the batched workload's configuration leaves the sample
+    count to the tuner; the single-edge workloads use the paper's table."""
+    return args.samples or ("tuned" if name == "batched" else "paper")
+
+
+def sample_params(args, name):
+    """Workload parameters with N_p set as --samples asks (n_p = 0: tuned)."""
+    import workloads
+    wp = dict(workloads.PARAMS[name])
+    m = sample_mode(args, name)
+    if m == "tuned":
+        wp["n_p"] = 0
+    elif m != "paper":
+        wp["n_p"] = m
+    return wp
+
+
+def tuned_sample_count(ezo, rob, n_obs):
+    """N_p the sample-count tuner picked for this robot and obstacle count."""
+    hits = [x["T"] for x in ezo.tune_cache_entries()
+            if x["kernel"] == "samples" and x["dof"] == rob.dof and x["spheres"] == rob.n_spheres
+            and x["obstacles"] == n_obs]
+    if len(set(hits)) != 1:
+        raise RuntimeError(f"expected one tuned sample count for this workload, cache holds {hits}")
+    return hits[0]
+
+
+def cpu_baseline(name, data, desc, seed, edges_idx, n_p=None):
     import numpy as np
     import oracle
     import workloads
@@ -103,13 +139,15 @@ def cpu_baseline(name, data, desc, seed, edges_idx):
     t0 = time.perf_counter()
     for e in edges_idx:
         v1, v2 = data["edges"][e].astype(np.float64)
-        prm = oracle.make_params(**workloads.PARAMS[name], seed=seed, edge_id=int(e))
+        wp = dict(workloads.PARAMS[name], **({"n_p": n_p} if n_p else {}))
+        prm = oracle.make_params(**wp, seed=seed, edge_id=int(e))
         out = oracle.eizo_arm(orob, obs, v1, v2, prm, env_boxes=data.get("env_boxes"))
         checks += out["stats"]["checks"]
     dt = time.perf_counter() - t0
     return {"value": checks / dt, "unit": "configs/s", "cores": oracle.max_threads(), "kind": "oracle",
             "sample": f"FP64 reference EI-ZO on {len(edges_idx)} edge(s) of the '{name}' workload "
-                      f"(seed {seed}): {checks} exact checks in {dt:.2f} s",
+                      f"(seed {seed}, N_p {n_p or workloads.PARAMS[name]['n_p']}): {checks} exact checks "
+                      f"in {dt:.2f} s",
             "edges_per_s": len(edges_idx) / dt}
 
 
@@ -222,10 +260,14 @@ def screen_compare(args):
     obs = torch.from_numpy(data["obstacles"]).to(dev)
     edges = torch.from_numpy(data["edges"]).to(dev)
     E = edges.shape[0]
+    wp = sample_params(args, name)
+    if wp["n_p"] == 0:
+        # both forms run with the N_p the tuner picks for the exact form
+        ezo.inflate_edges(ctx, rob, obs, edges, ezo.make_params(dof=rob.dof, seed=args.seed, **wp))
+        wp["n_p"] = tuned_sample_count(ezo, rob, int(obs.shape[0]))
     res = {}
     for mode in ("exact", "screened"):
-        prm = ezo.make_params(dof=rob.dof, seed=args.seed, surrogate=sur if mode == "screened" else None,
-                              **workloads.PARAMS[name])
+        prm = ezo.make_params(dof=rob.dof, seed=args.seed, surrogate=sur if mode == "screened" else None, **wp)
         for _ in range(args.warmup):
             ezo.inflate_edges(ctx, rob, obs, edges, prm)
         torch.cuda.synchronize()
@@ -247,7 +289,7 @@ def screen_compare(args):
             "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32 checks, bf16 MFMA screen", "data": "synthetic",
             "config": {"workload": f"{name}: {WORKLOADS[name]}", "labels": n, "train": n_tr, "calibration": n_cal,
-                       "test": n_te, "alpha": 1e-3, "epochs": args.screen_epochs},
+                       "test": n_te, "alpha": 1e-3, "epochs": args.screen_epochs, "n_p": wp["n_p"]},
             "speedup_vs_exact": res["screened"]["edges_per_s"] / res["exact"]["edges_per_s"],
             "miss_rate_test": miss, "screened_fraction_test": frac, "margin": margin,
             "label_seconds": t_lab, "train_seconds": t_train, "epoch_losses": losses, **res}
@@ -348,7 +390,7 @@ def recovery(args):
             "config": {"workload": f"recovery on {name}: {E} sets after {p['max_iters']} iterations, trajectory "
                                    f"through {per_edge} hit-and-run samples per set, step {step} rad; "
                                    f"update N_b={n_b}, N_f={n_f_rec}", "waypoints": int(way.shape[0]),
-                       "segments": int(segs.shape[0]), "n_obstacles": int(obs.shape[0])},
+                       "segments": int(segs.shape[0]), "n_obstacles": int(obs.shape[0]), "n_p": p["n_p"]},
             "path_points": found["n_pts"], "path_check_ms": dt_check * 1e3, "found_collisions": found["n_col"],
             "update_ms": float(np.mean(upd_ms)), "update_ms_min": float(np.min(upd_ms)),
             "planes_added": int(added.sum().item()),
@@ -413,7 +455,7 @@ def paths_compare(args):
             "steps": args.steps, "warmup": max(args.warmup, 1), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"{name}: {WORKLOADS[name]}", "paths": len(counts),
-                       "edges_per_path": [c - 1 for c in counts]},
+                       "edges_per_path": [c - 1 for c in counts], "n_p": prm.n_p},
             "longest_path_edges": max(counts) - 1,
             "speedup_vs_independent": res["independent"]["ms_per_call"] / res["sequential"]["ms_per_call"],
             **res}
@@ -604,7 +646,12 @@ def main():
     ap.add_argument("--sweep-sizes", default="1048576,4194304,16777216")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true", help="skip the one-call-per-edge comparison (E > 1)")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the comparison runs after the timed region (one call per edge; the paper's N_p)")
+    ap.add_argument("--samples", type=samples_arg, default=None,
+                    help="N_p of the inflation: 'paper' (the paper's table value), 'tuned' (chosen by the "
+                         "sample-count tuner, n_p = 0) or a count; default tuned for the batched workload, "
+                         "paper otherwise")
     ap.add_argument("--screen", action="store_true", help="learned screen vs exact comparison")
     ap.add_argument("--screen-epochs", type=int, default=10)
     ap.add_argument("--recovery", action="store_true", help="trajectory check + set update + containment timings")
@@ -665,7 +712,10 @@ def main():
     obs = torch.from_numpy(data["obstacles"]).to(dev)
     edges = torch.from_numpy(data["edges"]).to(dev)
     E = edges.shape[0]
-    prm = ezo.make_params(dof=desc["dof"], seed=args.seed, **workloads.PARAMS[name])
+    samples_mode = sample_mode(args, name)
+    wp = sample_params(args, name)
+    ctx.set_autotune(not args.no_autotune)
+    prm = ezo.make_params(dof=desc["dof"], seed=args.seed, **wp)
     out = ezo.InflateResult(torch.empty((E, prm.face_capacity, rob.dof), dtype=torch.float32, device=dev),
                             torch.empty((E, prm.face_capacity), dtype=torch.float32, device=dev),
                             torch.empty(E, dtype=torch.int32, device=dev),
@@ -675,9 +725,9 @@ def main():
         ezo.inflate_edges(ctx, rob, obs, edges, prm, out=out)
         return out.stats
 
-    # the first call times launch shapes for this workload (autotuner) when
-    # they are not cached yet; it is part of the warm-up, never of the timed steps
-    ctx.set_autotune(not args.no_autotune)
+    # the first call times launch shapes (and, for n_p = 0, the sample count)
+    # for this workload when they are not cached yet; it is part of the
+    # warm-up, never of the timed steps
     t_first = time.perf_counter()
     for _ in range(max(args.warmup, 1)):
         step()
@@ -695,6 +745,8 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     status = out.status.cpu().numpy()
+    n_p_used = wp["n_p"] or tuned_sample_count(ezo, rob, int(obs.shape[0]))
+    planes_mean = float(np.mean([s["planes"] for s in out.stats]))
     # phase pass: the same steps with hipEvents between the kernel phases on
     # the library's stream (identical results; kernels launched directly)
     ctx.set_phase_timing(True)
@@ -725,7 +777,7 @@ def main():
         instance = f"ezo::k_check<{sc['T']}, false, {box}>" if sc else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_TFLOPS,
-                "traffic": measured_traffic(name, instance) if instance else None,
+                "traffic": measured_traffic(name, instance, n_p_used) if instance else None,
                 "traffic_unit": "bytes per launch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": "k_project_bisect" if dom == "bisect" else "k_check", "kernel_instance": instance,
                 "avg_launch_ms": dom_ms / max(iters, 1), "launches": iters,
@@ -733,7 +785,7 @@ def main():
                 "all_pairs_per_check": rob.n_spheres * int(obs.shape[0]) + rob.n_self,
                 "box_pair_tests_counted": False if rob.n_boxes > 0 or "env_boxes" in data else None,
                 "all_pairs_equivalent_tflops": all_pairs / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0}
-    counted = measured_valu(name, instance) if instance else None
+    counted = measured_valu(name, instance, n_p_used) if instance else None
     if counted is not None and dom_ms > 0:
         # the second form of the FP32 fraction: counted FP32 VALU flop of a
         # launch (committed rocprofv3 summary) over the live average launch time
@@ -755,7 +807,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{name}: {WORKLOADS[name]}", "edges": E, "n_obstacles": int(obs.shape[0]),
-                   "robot_spheres": rob.n_spheres, "self_pairs": rob.n_self},
+                   "robot_spheres": rob.n_spheres, "self_pairs": rob.n_self, "n_p": n_p_used},
         "edges_per_s": E * args.steps / dt,
         "checks_per_step": checks // args.steps,
         "iterations_per_step": iters / args.steps,
@@ -765,6 +817,9 @@ def main():
         "ms_per_step_phase_pass": dt_phase / args.steps * 1e3,
         "roofline": roofline,
         "autotune": not args.no_autotune,
+        "n_p": n_p_used,
+        "n_p_source": {"tuned": "sample-count tuner (n_p = 0)", "paper": "paper table"}.get(samples_mode, "--samples"),
+        "planes_mean": planes_mean,
         "first_call_ms": first_call_ms,
         "launch_shapes": [{k: e[k] for k in ("kernel", "log2_items", "T", "W", "stage", "depth", "us")}
                           for e in ezo.tune_cache_entries()
@@ -774,7 +829,9 @@ def main():
         # the plain GPU form: the same edges, one call per edge (edge e draws
         # the stream of edge id e in both forms, so the sets are identical),
         # after the timed region
-        prm1 = [ezo.make_params(dof=desc["dof"], seed=args.seed, edge_id_base=e, **workloads.PARAMS[name])
+        # the plain form uses the N_p the batched call used (the tuner's pick
+        # for n_p = 0), so that both forms compute the same sets
+        prm1 = [ezo.make_params(dof=desc["dof"], seed=args.seed, edge_id_base=e, **dict(wp, n_p=n_p_used))
                 for e in range(E)]
         outs = [ezo.inflate_edges(ctx, rob, obs, edges[e:e + 1], prm1[e]) for e in range(E)]   # warm-up
         torch.cuda.synchronize()
@@ -793,9 +850,27 @@ def main():
         line["plain"] = {"ms_per_step": dt1 * 1e3, "edges_per_s": E / dt1, "configs_per_s": checks1 / reps / dt1,
                          "calls_per_step": E, "equal_to_batched": bool(same)}
         line["batched_speedup_vs_plain"] = (E / (dt / args.steps)) / (E / dt1)
+    if samples_mode == "tuned" and n_p_used != workloads.PARAMS[name]["n_p"] and not args.no_plain:
+        # the same batched call with the paper's N_p (same eps, delta, tau):
+        # what the tuned sample count gains; the sets differ, the certificate
+        # does not
+        prm_p = ezo.make_params(dof=desc["dof"], seed=args.seed, **workloads.PARAMS[name])
+        r = ezo.inflate_edges(ctx, rob, obs, edges, prm_p)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for _ in range(args.steps):
+            r = ezo.inflate_edges(ctx, rob, obs, edges, prm_p)
+        torch.cuda.synchronize()
+        dt3 = (time.perf_counter() - t3) / args.steps
+        st3 = r.status.cpu().numpy()
+        line["paper_n_p"] = {"n_p": workloads.PARAMS[name]["n_p"], "ms_per_step": dt3 * 1e3, "edges_per_s": E / dt3,
+                             "certified": int(np.sum(st3 == 0)),
+                             "iterations_mean": float(np.mean([x["iterations"] for x in r.stats])),
+                             "planes_mean": float(np.mean([x["planes"] for x in r.stats]))}
+        line["tuned_speedup_vs_paper_n_p"] = dt3 / (dt / args.steps)
     if not args.no_cpu_baseline:
         idx = [0] if E == 1 else sorted({int(np.nonzero(data["path_id"] == p)[0][0]) for p in np.unique(data["path_id"])})
-        line["cpu_baseline"] = cpu_baseline(name, data, desc, args.seed, idx)
+        line["cpu_baseline"] = cpu_baseline(name, data, desc, args.seed, idx, n_p_used)
     print(json.dumps(line), flush=True)
 
 

@@ -112,7 +112,8 @@ typedef struct {
     double tau;              /* test decision threshold, (0, 1); typically 0.5      */
     double step_back_max;    /* Delta_max > 0                                       */
     double t_col;            /* candidates with dist <= t_col abort the edge        */
-    int32_t n_p;             /* N_p >= 1: samples updated per iteration             */
+    int32_t n_p;             /* N_p >= 1: samples updated per iteration; 0: chosen
+                                by the autotuner (ezo_inflate_edges)                 */
     int32_t n_f;             /* N_f >= 1: faces placed per iteration                */
     int32_t n_b;             /* N_b >= 0: bisection steps                           */
     int32_t n_mix;           /* hit-and-run steps per sample, >= 0                  */
@@ -282,7 +283,14 @@ ezo_status ezo_place_hyperplanes(ezo_ctx *ctx, int32_t dof, const float *edges, 
  * skipped.  Outputs: A dev f32 [E][face_capacity][dof], b dev f32
  * [E][face_capacity], n_faces dev i32 [E], edge_status dev i32 [E] (EZO_EDGE_*),
  * stats host [E] (may be NULL).  Returns EZO_E_CAPACITY if face_capacity <
- * 2 dof + n_f max_iters.  Blocks until the stream has finished the call. */
+ * 2 dof + n_f max_iters.  Blocks until the stream has finished the call.
+ * params->n_p = 0: N_p is chosen by the autotuner (tuning kind "samples",
+ * key: architecture, robot size, obstacle count, floor(log2 E)): the first
+ * call with a new key inflates its own edges with N_p = 10000, 5000, 2000 and
+ * 1000 (each once, then all again three times) and keeps the largest N_p
+ * whose time is within 5 % of the fastest; with tuning off and nothing
+ * cached N_p = 10000.  The certification does not depend on
+ * N_p (the test uses the first M_k samples); the sets do. */
 ezo_status ezo_inflate_edges(ezo_ctx *ctx, const ezo_robot *robot, const float *obs, int32_t n_obs,
                              const float *edges, int32_t n_edges, const ezo_params *params, float *A,
                              float *b, int32_t *n_faces, int32_t *edge_status, ezo_edge_stats *stats,

@@ -450,6 +450,13 @@ ezo_status tune_bisect_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov
 // |S| hit-and-run samples per edge from it, and as candidates the first n_p
 // of them in collision.
 constexpr int kItersPerGraph = 4;        // iterations captured per replayed graph
+// Candidate sample counts N_p of the sample-count tuner, largest first (its
+// order of preference: more samples give more hyperplanes per iteration), the
+// margin by which a smaller count must be faster to be picked, and the count
+// used when tuning is off and nothing is cached.
+constexpr int kSampleCounts[] = {10000, 5000, 2000, 1000};
+constexpr double kSampleCountSlack = 0.05;
+constexpr int kDefaultSampleCount = 10000;
 // Edges per round of ezo_inflate_paths (a path window of s = kPathBatch / paths edges).
 constexpr int kPathBatch = 128;
 
@@ -978,7 +985,7 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
     if (!r || !p) return ezo_fail(c, EZO_E_INVALID, "NULL robot or params");
     if (n_edges < 0 || n_obs < 0) return ezo_fail(c, EZO_E_INVALID, "negative size");
     if (!(p->eps > 0 && p->eps < 1) || !(p->delta > 0 && p->delta < 1) || !(p->tau > 0 && p->tau < 1) ||
-        !finite_pos(p->step_back_max) || !std::isfinite(p->t_col) || p->n_p < 1 || p->n_f < 1 || p->n_b < 0 ||
+        !finite_pos(p->step_back_max) || !std::isfinite(p->t_col) || p->n_p < 0 || p->n_f < 1 || p->n_b < 0 ||
         p->n_mix < 0 || p->max_iters < 1)
         return ezo_fail(c, EZO_E_INVALID, "parameter out of range");
     const int dof = r->dof;
@@ -988,6 +995,42 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
     if (n_edges == 0) return EZO_OK;
     if (!edges || !A || !b || !n_faces || !edge_status || (n_obs > 0 && !obs))
         return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
+    if (p->n_p == 0) {
+        // N_p chosen by measurement: whole inflations of this call's own
+        // edges with each candidate count (results go to the call's outputs
+        // and are overwritten below); kept per key is the largest count
+        // within kSampleCountSlack of the fastest.  Certification does not
+        // depend on N_p: the test always uses the first M_k samples.
+        const TuneKey k = tune_key(c, r, TUNE_SAMPLE_COUNT, n_obs, n_edges);
+        TileCfg g;
+        if (!ezo_tune_lookup(k, &g)) {
+            if (!c->autotune) {
+                g.T = kDefaultSampleCount;
+            } else {
+                HIP_TRY(c, hipEventRecord(c->ev_in, as_stream(stream)));
+                HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_in, 0));
+                std::vector<TileCfg> cands;
+                for (int np : kSampleCounts) {
+                    TileCfg t;
+                    t.T = np;
+                    t.W = 1;
+                    cands.push_back(t);
+                }
+                auto run = [&](const TileCfg& t) -> ezo_status {
+                    ezo_params q = *p;
+                    q.n_p = t.T;
+                    return inflate_core(c, r, obs, n_obs, edges, n_edges, &q, A, b, n_faces, edge_status, nullptr,
+                                        c->stream, edge_ids, skip);
+                };
+                ezo_status ts = ezo_tune_search(c, k, cands, c->stream, run, &g, kSampleCountSlack);
+                if (ts) return ts;
+            }
+        }
+        ezo_params q = *p;
+        q.n_p = g.T;
+        return inflate_core(c, r, obs, n_obs, edges, n_edges, &q, A, b, n_faces, edge_status, stats, stream, edge_ids,
+                            skip);
+    }
     const int cap = p->face_capacity;
     if (sample_smem_bytes(dof <= 4 ? 4 : 8, 16, cap, 256) > c->lds_cap)
         return ezo_fail(c, EZO_E_UNSUPPORTED, "face_capacity %d too large", cap);

@@ -115,7 +115,9 @@ struct TileCfg {
 };
 
 // For the sampler, T = lanes per walk and W = waves per workgroup.
-enum TuneKind { TUNE_CHECK_FLAGS = 0, TUNE_CHECK_SD = 1, TUNE_BISECT = 2, TUNE_SAMPLE = 3, TUNE_NKINDS };
+// TUNE_SAMPLE_COUNT: T = the inflation's N_p (samples per iteration).
+enum TuneKind { TUNE_CHECK_FLAGS = 0, TUNE_CHECK_SD = 1, TUNE_BISECT = 2, TUNE_SAMPLE = 3, TUNE_SAMPLE_COUNT = 4,
+                TUNE_NKINDS };
 
 // A tuned shape applies to calls with the same device architecture, kernel,
 // robot size (dof, spheres, self pairs), obstacle count and work size
@@ -131,10 +133,11 @@ int ezo_tune_bucket(int64_t items);
 bool ezo_tune_lookup(const TuneKey& k, TileCfg* out);
 // Times every candidate once, then the fastest few over several launches
 // (launches of `run` on stream st, host-synchronising), and caches the
-// fastest under k.  Candidates whose launch fails are skipped.  Needs at
-// least one candidate.
+// pick under k: the first candidate in `cands` order whose time is within
+// (1 + slack) of the fastest (slack = 0: the fastest).  Candidates whose
+// launch fails are skipped.  Needs at least one candidate.
 ezo_status ezo_tune_search(ezo_ctx* c, const TuneKey& k, const std::vector<TileCfg>& cands, hipStream_t st,
-                           const std::function<ezo_status(const TileCfg&)>& run, TileCfg* best);
+                           const std::function<ezo_status(const TileCfg&)>& run, TileCfg* best, double slack = 0.0);
 
 extern std::string g_create_err;
 ezo_status ezo_fail(ezo_ctx* c, ezo_status code, const char* fmt, ...);

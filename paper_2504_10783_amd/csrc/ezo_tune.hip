@@ -22,7 +22,7 @@ namespace {
 constexpr int kTuneReps = 3;
 constexpr int kTuneFinalists = 4;
 
-const char* kKindNames[TUNE_NKINDS] = {"check_flags", "check_sd", "bisect", "sample"};
+const char* kKindNames[TUNE_NKINDS] = {"check_flags", "check_sd", "bisect", "sample", "samples"};
 
 struct Entry {
     TileCfg cfg;
@@ -114,7 +114,7 @@ static ezo_status time_shape(ezo_ctx* c, hipStream_t st, const std::function<ezo
 }
 
 ezo_status ezo_tune_search(ezo_ctx* c, const TuneKey& k, const std::vector<TileCfg>& cands, hipStream_t st,
-                           const std::function<ezo_status(const TileCfg&)>& run, TileCfg* best) {
+                           const std::function<ezo_status(const TileCfg&)>& run, TileCfg* best, double slack) {
     if (cands.empty()) return ezo_fail(c, EZO_E_INVALID, "no launch shape to tune");
     for (auto& ev : c->tune_ev)
         if (!ev) HIP_TRY(c, hipEventCreate(&ev));
@@ -131,16 +131,25 @@ ezo_status ezo_tune_search(ezo_ctx* c, const TuneKey& k, const std::vector<TileC
     if (order.empty()) return ezo_fail(c, EZO_E_HIP, "no launch shape ran during tuning");
     std::sort(order.begin(), order.end());
     double best_ms = INFINITY;
-    TileCfg pick = cands[order[0].second];
+    std::vector<std::pair<double, int>> fin;      // (ms, candidate index) of the finalists
     for (int f = 0; f < std::min<int>(kTuneFinalists, (int)order.size()); ++f) {
         double ms;
         if ((s = time_shape(c, st, run, cands[order[f].second], kTuneReps, &ms))) return s;
-        if (ms < best_ms) {
-            best_ms = ms;
-            pick = cands[order[f].second];
-        }
+        fin.push_back({ms, order[f].second});
+        best_ms = std::min(best_ms, ms);
     }
     if (!std::isfinite(best_ms)) return ezo_fail(c, EZO_E_HIP, "no launch shape ran during tuning");
+    // the earliest candidate (in the caller's order of preference) within
+    // (1 + slack) of the fastest
+    int pick_i = -1;
+    double pick_ms = best_ms;
+    for (const auto& f : fin)
+        if (f.first <= best_ms * (1.0 + slack) && (pick_i < 0 || f.second < pick_i)) {
+            pick_i = f.second;
+            pick_ms = f.first;
+        }
+    const TileCfg pick = cands[pick_i];
+    best_ms = pick_ms;
     c->err.clear();
     {
         std::lock_guard<std::mutex> lock(g_mu);
@@ -208,8 +217,10 @@ ezo_status ezo_tune_cache_import(const char* text, int32_t* n_imported) {
         if (ok) find_num(line, "depth", &depth);
         double boxes = 0.0;                          // optional key (robots with boxes)
         if (ok) find_num(line, "boxes", &boxes);
-        const bool shape_ok = (T == 1 || T == 2 || T == 4 || T == 8 || T == 16 || T == 32 || T == 64) && W >= 1 &&
-                              W <= 16 && (v[7] == 0 || v[7] == 1) && (depth == 1 || depth == 2 || depth == 3);
+        const bool count = kind == TUNE_SAMPLE_COUNT;   // T is a sample count, not a tile size
+        const bool shape_ok = (count ? (T >= 1 && T <= (1 << 24))
+                                     : (T == 1 || T == 2 || T == 4 || T == 8 || T == 16 || T == 32 || T == 64)) &&
+                              W >= 1 && W <= 16 && (v[7] == 0 || v[7] == 1) && (depth == 1 || depth == 2 || depth == 3);
         if (!ok || kind < 0 || !shape_ok) return EZO_E_INVALID;
         k.kind = kind;
         k.dof = (int)v[0];

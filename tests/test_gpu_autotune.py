@@ -216,3 +216,46 @@ def test_autotuned_inflation_equals_heuristic(ezo, ctx, name, max_iters):
     assert {"check_flags", "bisect"} <= kinds
     st = r1.status.cpu().numpy()
     assert np.all(st == ezo.CERTIFIED) or max_iters < 50
+
+
+def test_sample_count_tuning(ezo, ctx):
+    """n_p = 0: the first call times whole inflations with each candidate
+    N_p and caches one ("samples" entry: the largest within 5 % of the
+    fastest, a timing-dependent pick); the call's result equals
+    an explicit call with that N_p bit for bit; a second call reuses the
+    entry; with tuning off and no entry N_p = 10000."""
+    import workloads
+    data, desc = load("dof7")
+    rob = ezo.Robot(ctx, desc)
+    obs = torch.from_numpy(data["obstacles"]).cuda()
+    edges = torch.from_numpy(data["edges"]).cuda()
+    p = dict(workloads.PARAMS["dof7"], n_p=0)
+    print_case("sample-count tuning")
+    ezo.tune_cache_clear()
+    ctx.set_autotune(True)
+    try:
+        r = ezo.inflate_edges(ctx, rob, obs, edges, ezo.make_params(dof=7, seed=6, **p))
+        torch.cuda.synchronize()
+        ent = [e for e in ezo.tune_cache_entries() if e["kernel"] == "samples"]
+        print("samples entries", ent)
+        assert len(ent) == 1 and ent[0]["T"] in (1000, 2000, 5000, 10000) and ent[0]["log2_items"] == 0
+        chosen = ent[0]["T"]
+        assert int(r.status[0].item()) == ezo.CERTIFIED
+        ref = ezo.inflate_edges(ctx, rob, obs, edges, ezo.make_params(dof=7, seed=6, **dict(p, n_p=chosen)))
+        again = ezo.inflate_edges(ctx, rob, obs, edges, ezo.make_params(dof=7, seed=6, **p))
+        torch.cuda.synchronize()
+        F = int(r.n_faces[0].item())
+        for x in (ref, again):
+            assert torch.equal(x.status, r.status) and torch.equal(x.n_faces, r.n_faces)
+            assert torch.equal(x.A[0, :F], r.A[0, :F]) and torch.equal(x.b[0, :F], r.b[0, :F])
+        assert len([e for e in ezo.tune_cache_entries() if e["kernel"] == "samples"]) == 1
+        # tuning off, no entry: the default count
+        ezo.tune_cache_clear()
+        ctx.set_autotune(False)
+        d = ezo.inflate_edges(ctx, rob, obs, edges, ezo.make_params(dof=7, seed=6, **p))
+        dref = ezo.inflate_edges(ctx, rob, obs, edges, ezo.make_params(dof=7, seed=6, **dict(p, n_p=10000)))
+        torch.cuda.synchronize()
+        assert torch.equal(d.n_faces, dref.n_faces) and torch.equal(d.status, dref.status)
+        assert not [e for e in ezo.tune_cache_entries() if e["kernel"] == "samples"]
+    finally:
+        ctx.set_autotune(True)

@@ -84,6 +84,13 @@ def test_tuning_cache_roundtrip_on_host(ezo):
     text = ezo.tune_cache_export()
     ezo.tune_cache_clear()
     assert ezo.tune_cache_import(text) == 2 and ezo.tune_cache_export() == text
+    # a sample-count entry keeps any count as T; a box robot's key its boxes
+    cnt = TUNE_LINE.replace('"bisect"', '"samples"').replace('"T":16', '"T":5000').replace('"W":4', '"W":1')
+    box = TUNE_LINE.replace('"self_pairs":1500,', '"self_pairs":0,"boxes":11,')
+    assert ezo.tune_cache_import(cnt + "\n" + box) == 2
+    ents = ezo.tune_cache_entries()
+    assert any(e["kernel"] == "samples" and e["T"] == 5000 for e in ents)
+    assert any(e.get("boxes") == 11 for e in ents) and len(ents) == 4
     ezo.tune_cache_clear()
     assert ezo.tune_cache_entries() == []
 
@@ -95,6 +102,7 @@ def test_tuning_cache_roundtrip_on_host(ezo):
     TUNE_LINE.replace('"stage":1,', ''),                # missing key
     TUNE_LINE.replace('"us"', '"depth":0,"us"'),        # depth below 1
     TUNE_LINE.replace('"us"', '"depth":4,"us"'),        # depth beyond 3
+    TUNE_LINE.replace('"bisect"', '"samples"').replace('"T":16', '"T":0'),   # no samples
 ])
 def test_tuning_cache_rejects_malformed_lines(ezo, bad):
     ezo.tune_cache_clear()
