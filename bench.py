@@ -54,12 +54,13 @@ def kernel_source_sha256():
 
 
 def measured_traffic(workload, kernel_instance, n_p):
-    """HBM bytes per launch of the kernel of `kernel_instance` (its counters
-    pooled over launch shapes) from the committed rocprofv3 FETCH_SIZE /
+    """HBM bytes per launch of `kernel_instance` (that template instance,
+    i.e. that launch shape) from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary of this workload (each counter scaled by its reading
-    for a plain 1 GiB copy), or None when there is no summary, the kernel was
-    not measured, the kernel sources changed since the counters were taken,
-    or the counters were taken at another N_p (samples per iteration)."""
+    for a plain 1 GiB copy), or None when there is no summary, the instance
+    was not measured, the kernel sources changed since the counters were
+    taken, or the counters were taken at another N_p (samples per
+    iteration)."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic__{workload}_inflate.md")
     if not os.path.exists(path):
         return None
@@ -68,15 +69,16 @@ def measured_traffic(workload, kernel_instance, n_p):
             rec = json.loads(line[len("traffic-json: "):])
             if rec.get("source_sha256") != kernel_source_sha256() or rec.get("n_p") != n_p:
                 return None
-            return rec.get("bytes_per_launch", {}).get(kernel_instance.split("<")[0])
+            return rec.get("bytes_per_launch_by_instance", {}).get(kernel_instance)
     return None
 
 
 def measured_valu(workload, kernel_instance, n_p):
     """Counted FP32 VALU flop per launch (64 lanes x (ADD + MUL + TRANS +
-    2 FMA) wave instructions, rocprofv3 SQ_INSTS_VALU_*_F32) of the kernel's
-    family from the committed summary of this workload, or None (no summary,
-    kernel not measured, kernel sources changed since, or another N_p)."""
+    2 FMA) wave instructions, rocprofv3 SQ_INSTS_VALU_*_F32) of
+    `kernel_instance` from the committed summary of this workload, or None
+    (no summary, instance not measured, kernel sources changed since, or
+    another N_p)."""
     path = os.path.join(ROOT, "profiles", f"valu_fp32__{workload}_inflate.md")
     if not os.path.exists(path):
         return None
@@ -85,7 +87,7 @@ def measured_valu(workload, kernel_instance, n_p):
             rec = json.loads(line[len("valu-json: "):])
             if rec.get("source_sha256") != kernel_source_sha256() or rec.get("n_p") != n_p:
                 return None
-            return rec.get("fp32_flop_per_launch", {}).get(kernel_instance.split("<")[0])
+            return rec.get("fp32_flop_per_launch_by_instance", {}).get(kernel_instance)
     return None
 
 
@@ -127,6 +129,21 @@ def tuned_sample_count(ezo, rob, n_obs):
     if len(set(hits)) != 1:
         raise RuntimeError(f"expected one tuned sample count for this workload, cache holds {hits}")
     return hits[0]
+
+
+def timed_shapes(ezo, rob, n_obs, prm, n_p, E):
+    """The cached launch shapes the inflation of E edges with N_p = n_p used:
+    the entries whose key matches the call's work sizes (the check on
+    max_k max(N_p, M_k) samples per edge, the bisection on N_p candidate
+    slots per edge; bucket = floor(log2(items)))."""
+    s_cap = max(max(n_p, ezo.test_constants(prm.eps, prm.delta, prm.tau, k)[0]) for k in range(1, prm.max_iters + 1))
+    want = {"check_flags": (s_cap * E).bit_length() - 1, "bisect": (n_p * E).bit_length() - 1}
+    out = {}
+    for e in ezo.tune_cache_entries():
+        if (e["kernel"] in want and e["log2_items"] == want[e["kernel"]] and e["obstacles"] == n_obs
+                and e["dof"] == rob.dof and e["spheres"] == rob.n_spheres):
+            out[e["kernel"]] = e
+    return out
 
 
 def cpu_baseline(name, data, desc, seed, edges_idx, n_p=None):
@@ -660,6 +677,10 @@ def main():
     ap.add_argument("--drm-map", action="store_true", help="DRM collision map of a 35 000-node roadmap")
     ap.add_argument("--forest", action="store_true", help="Forest scene: raw checker and path inflation")
     ap.add_argument("--no-autotune", action="store_true", help="size-heuristic launch shapes (no tuning)")
+    ap.add_argument("--tune-import", default=None,
+                    help="JSON-lines tuning cache to load before the run (profiled runs replay the shapes and "
+                         "sample count an unprofiled run picked; timing under a profiler distorts the tuner)")
+    ap.add_argument("--tune-export", default=None, help="write the tuning cache after the run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -714,6 +735,8 @@ def main():
     E = edges.shape[0]
     samples_mode = sample_mode(args, name)
     wp = sample_params(args, name)
+    if args.tune_import:
+        ezo.tune_cache_import(open(args.tune_import).read())
     ctx.set_autotune(not args.no_autotune)
     prm = ezo.make_params(dof=desc["dof"], seed=args.seed, **wp)
     out = ezo.InflateResult(torch.empty((E, prm.face_capacity, rob.dof), dtype=torch.float32, device=dev),
@@ -767,7 +790,7 @@ def main():
     work = PAIR_FLOP * tests[dom] + FK_FLOP * n_checks[dom]      # both summed over the K steps
     achieved = work / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0
     all_pairs = flop_per_check(rob.n_spheres, obs.shape[0], rob.n_self) * n_checks[dom]
-    shapes = {e["kernel"]: e for e in ezo.tune_cache_entries() if e["obstacles"] == int(obs.shape[0])}
+    shapes = timed_shapes(ezo, rob, int(obs.shape[0]), prm, n_p_used, E)
     box = "true" if (rob.n_boxes > 0 or "env_boxes" in data) else "false"
     if dom == "bisect":
         sb = shapes.get("bisect")
@@ -822,8 +845,7 @@ def main():
         "planes_mean": planes_mean,
         "first_call_ms": first_call_ms,
         "launch_shapes": [{k: e[k] for k in ("kernel", "log2_items", "T", "W", "stage", "depth", "us")}
-                          for e in ezo.tune_cache_entries()
-                          if e["obstacles"] == int(obs.shape[0]) or e["kernel"] == "sample"],
+                          for e in shapes.values()],
     }
     if E > 1 and not args.no_plain:
         # the plain GPU form: the same edges, one call per edge (edge e draws
@@ -868,6 +890,9 @@ def main():
                              "iterations_mean": float(np.mean([x["iterations"] for x in r.stats])),
                              "planes_mean": float(np.mean([x["planes"] for x in r.stats]))}
         line["tuned_speedup_vs_paper_n_p"] = dt3 / (dt / args.steps)
+    if args.tune_export:
+        with open(args.tune_export, "w") as f:
+            f.write(ezo.tune_cache_export())
     if not args.no_cpu_baseline:
         idx = [0] if E == 1 else sorted({int(np.nonzero(data["path_id"] == p)[0][0]) for p in np.unique(data["path_id"])})
         line["cpu_baseline"] = cpu_baseline(name, data, desc, args.seed, idx, n_p_used)

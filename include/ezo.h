@@ -504,8 +504,11 @@ ezo_status ezo_segments_contained(ezo_ctx *ctx, int32_t dof, const float *A, con
  * is reduced with exact min/max), only the time.
  * With autotuning on (the default), the first call whose tuning key is new
  * times every candidate shape once on the device, times the four fastest
- * again over three launches each, and caches the fastest for the process; the key is (device architecture, kernel, dof, spheres, self pairs,
- * obstacles, floor(log2(work items))).  That first call synchronises with
+ * again over three launches each, and caches for the process the first of
+ * them (in a fixed order: fewer bisection levels per round, larger tiles
+ * first) whose time is within 3 % of the fastest; the key is (device
+ * architecture, kernel, dof, spheres, self pairs, obstacles,
+ * floor(log2(work items))).  That first call synchronises with
  * `stream` (it reads timing events), so it must not run under stream
  * capture: disable tuning or import a cache first.  ezo_check_collisions and
  * ezo_project_bisect time on the call's own inputs (launches that only write

@@ -70,10 +70,11 @@ int pick_T(const ezo_ctx* c, int64_t items, int S, int W, size_t extra = 0) {
     return best;
 }
 
-// Obstacle records go to LDS when they fit beside a tile of T.
-bool stage_fits(const ezo_ctx* c, int T, int S, int W, int n_obs) {
+// Obstacle records go to LDS when they fit beside a tile of T (and `extra`
+// bytes more: the bisection's staged robot tables).
+bool stage_fits(const ezo_ctx* c, int T, int S, int W, int n_obs, size_t extra = 0) {
     const size_t b = 16 * (size_t)n_obs;
-    return T > 0 && n_obs > 0 && b <= kObsStageBytes && tile_smem_bytes(T, S, W) + b <= c->lds_cap;
+    return T > 0 && n_obs > 0 && b <= kObsStageBytes && tile_smem_bytes(T, S, W) + b + extra <= c->lds_cap;
 }
 
 int pick_W(int n_obs) {
@@ -136,8 +137,9 @@ bool cfg_valid(const ezo_ctx* c, const TileCfg& g, int S, int n_obs, bool sd, bo
     if (!pow2_tile(g.T) || g.W < 1 || g.W > 16 || g.depth < 1 || g.depth > 3) return false;
     if (bisect ? !bisect_shape_built(g) : g.depth != 1) return false;
     const int T = tile_configs(g, bisect);
-    if (g.stage && (sd || !stage_fits(c, T, S, g.W, n_obs))) return false;
-    return tile_smem_bytes(T, S, g.W) + (g.stage ? 16 * (size_t)n_obs : 0) <= c->lds_cap;
+    const size_t rs = bisect ? robot_stage_bytes(S) : 0;
+    if (g.stage && (sd || !stage_fits(c, T, S, g.W, n_obs, rs))) return false;
+    return tile_smem_bytes(T, S, g.W) + (g.stage ? 16 * (size_t)n_obs : 0) + rs <= c->lds_cap;
 }
 
 TuneKey tune_key(const ezo_ctx* c, const ezo_robot* r, TuneKind kind, int n_obs, int64_t items) {
@@ -167,8 +169,9 @@ TileCfg heuristic_bisect(const ezo_ctx* c, const ezo_robot* r, int n_obs, int64_
     TileCfg g;
     g.W = 4;
     g.depth = 1;
-    g.T = std::max(std::min(pick_T(c, items, r->slots, g.W), 64), 2);
-    g.stage = stage_fits(c, g.T, r->slots, g.W, n_obs) ? 1 : 0;
+    const size_t rs = robot_stage_bytes(r->slots);
+    g.T = std::max(std::min(pick_T(c, items, r->slots, g.W, rs), 64), 2);
+    g.stage = stage_fits(c, g.T, r->slots, g.W, n_obs, rs) ? 1 : 0;
     return g;
 }
 
@@ -355,7 +358,8 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
         return ezo_fail(c, EZO_E_INVALID, "bisection shape T=%d W=%d depth=%d", TC, W, dp);
     ObsView ovs = ov;
     ovs.lds_n = g.stage ? ov.n : 0;
-    const size_t lds = tile_smem_bytes(tile_configs(g, true), r->slots, W) + 16 * (size_t)ovs.lds_n;
+    const size_t lds = tile_smem_bytes(tile_configs(g, true), r->slots, W) + 16 * (size_t)ovs.lds_n +
+                       robot_stage_bytes(r->slots);
     if (lds > c->lds_cap) return ezo_fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
     dim3 grid((unsigned)((cand_cap + TC - 1) / TC), (unsigned)E), block(64 * W);
     const bool box = r->B > 0 || ov.n_ebox > 0;

@@ -56,6 +56,42 @@ __host__ __device__ inline int tile_slots(int n_spheres, int n_boxes) { return n
 
 constexpr int kMaxLinkPairs = kMaxDof * (kMaxDof + 1) / 2;   // link pairs, same-link pairs included
 
+// Robot tables that a workgroup running many dependent tile checks (the
+// bisection) copies into LDS once: DH rows, link bounding spheres, self-pair
+// blocks, spheres and link sphere ranges; their reads in FK and in the
+// self-pair sweep then cost an LDS access instead of a cache access.  At
+// most this many bytes (slots >= spheres).
+__host__ __device__ inline size_t robot_stage_bytes(int slots) {
+    return 16 * (size_t)(2 * kMaxDof + kMaxLinkPairs + (slots > 0 ? slots : 1)) + 16 * ((kMaxDof + 4) / 4);
+}
+
+// Copies the tables into LDS at `base` (16-byte aligned, robot_stage_bytes
+// long) and returns a view whose table pointers address the copies (box
+// tables and self pairs stay in global memory).  The caller places a
+// barrier before the first use.
+__device__ inline RobotView stage_robot(const RobotView& rb, char* base) {
+    float4* dh = reinterpret_cast<float4*>(base);
+    float4* lb = dh + kMaxDof;
+    int4* blk = reinterpret_cast<int4*>(lb + kMaxDof);
+    float4* sph = reinterpret_cast<float4*>(blk + kMaxLinkPairs);
+    int* lbeg = reinterpret_cast<int*>(sph + (rb.n_spheres > 0 ? rb.n_spheres : 1));
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i < rb.dof; i += nt) {
+        dh[i] = rb.dh[i];
+        lb[i] = rb.lbound[i];
+    }
+    for (int i = tid; i <= rb.dof; i += nt) lbeg[i] = rb.link_begin[i];
+    for (int i = tid; i < rb.n_blocks; i += nt) blk[i] = rb.blocks[i];
+    for (int i = tid; i < rb.n_spheres; i += nt) sph[i] = rb.sph[i];
+    RobotView v = rb;
+    v.dh = dh;
+    v.lbound = lb;
+    v.blocks = blk;
+    v.sph = sph;
+    v.link_begin = lbeg;
+    return v;
+}
+
 // Uniform grid over the obstacle cloud (shifted frame).  Cell k lists every
 // obstacle that a robot sphere centred anywhere in cell k could touch: the
 // distance from o to the cell's box is below r_o + r_sphere_max + slack (a

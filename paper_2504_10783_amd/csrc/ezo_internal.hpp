@@ -134,10 +134,13 @@ bool ezo_tune_lookup(const TuneKey& k, TileCfg* out);
 // Times every candidate once, then the fastest few over several launches
 // (launches of `run` on stream st, host-synchronising), and caches the
 // pick under k: the first candidate in `cands` order whose time is within
-// (1 + slack) of the fastest (slack = 0: the fastest).  Candidates whose
-// launch fails are skipped.  Needs at least one candidate.
+// (1 + slack) of the fastest.  The default slack (3 %, about the spread of
+// repeated timings) lets repeated tunings of near-equal shapes agree.
+// Candidates whose launch fails are skipped.  Needs at least one candidate.
+constexpr double kTuneSlack = 0.03;
 ezo_status ezo_tune_search(ezo_ctx* c, const TuneKey& k, const std::vector<TileCfg>& cands, hipStream_t st,
-                           const std::function<ezo_status(const TileCfg&)>& run, TileCfg* best, double slack = 0.0);
+                           const std::function<ezo_status(const TileCfg&)>& run, TileCfg* best,
+                           double slack = kTuneSlack);
 
 extern std::string g_create_err;
 ezo_status ezo_fail(ezo_ctx* c, ezo_status code, const char* fmt, ...);

@@ -580,9 +580,11 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
 // decisions of one-midpoint-at-a-time bisection, in ceil(N_b / DEPTH)
 // dependent rounds instead of N_b.  Candidate state lives with the threads
 // c < TC; configuration c (2^lev - 1) + i - 1 holds node i of candidate c.
+// LDS: the tile, the staged obstacles (ob.lds_n records), then the robot
+// tables (robot_stage_bytes), read by every one of the dependent checks.
 // ---------------------------------------------------------------------------
 template <int TC, int DEPTH, bool BOX>
-__global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView ob, GridView gv, const float* __restrict__ edges,
+__global__ void __launch_bounds__(1024) k_project_bisect(RobotView rg, ObsView ob, GridView gv, const float* __restrict__ edges,
                                                          const float* __restrict__ S, int64_t stride, int64_t s_edge,
                                                          const int* __restrict__ cand_idx,
                                                          const int* __restrict__ n_cands, int cand_cap, int n_b,
@@ -601,9 +603,11 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rb, ObsView o
     const int base = blockIdx.x * TC;
     if (base >= nc) return;
     const int nv = (nc - base) < TC ? (nc - base) : TC;
-    const int dof = rb.dof;
+    const int dof = rg.dof;
     const int W = blockDim.x >> 6;
-    TileSmem t = carve_tile(smem, T, tile_slots(rb.n_spheres, rb.n_boxes), W, ob.lds_n);
+    const int slots = tile_slots(rg.n_spheres, rg.n_boxes);
+    TileSmem t = carve_tile(smem, T, slots, W, ob.lds_n);
+    const RobotView rb = stage_robot(rg, smem + tile_smem_bytes(T, slots, W) + 16 * (size_t)ob.lds_n);
     stage_obstacles(ob, t);
     const int tid = threadIdx.x;
     const bool own = tid < nv;
