@@ -7,8 +7,12 @@
   margin keeps the miss rate on held-out data near the target;
 * screened inflation never screens the unadaptive test's samples, gives the
   same polytope as the exact method when the margin screens nothing, and
-  keeps every invariant when it does.
+  keeps every invariant when it does;
+* what a trained screen gains: the same certified inflation with fewer
+  exact pair tests per checked configuration (times printed).
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -172,3 +176,48 @@ def test_screened_inflation_in_fresh_context(ezo):
     st = r.status.cpu().numpy()
     assert np.all((st == ezo.CERTIFIED) | (st == ezo.MAX_ITERS))
     assert sum(x["screened_checks"] for x in r.stats) > 0
+
+
+def test_trained_screen_gain(ezo, ctx):
+    """What the trained network gains over the method without it, on the
+    dof7 edge at identical eps / delta / tau / seed: both runs certify; the
+    screened run skips the exact self pairs of the optimizer samples the
+    network clears, so its check phase performs fewer exact pair tests per
+    checked configuration.  Both wall times are printed (the exact self pairs
+    cost ~100 pair tests per configuration after the broad phase, fewer flops
+    than the network, so the time gain can be negative)."""
+    data, desc = load("dof7")
+    rob = ezo.Robot(ctx, desc)
+    n_train, n_cal = 200_704, 32_768
+    print_case("screen gain", n_train)
+    q = torch.from_numpy(draw.uniform_q(43, n_train + n_cal, data["q_lo"], data["q_hi"])).cuda()
+    t = self_labels(ezo, ctx, rob, q)
+    s = ezo.Surrogate(ctx, 7, 256, seed=11)
+    s.train(q[:n_train], t[:n_train], ezo.make_train_params(epochs=3, batch=4096, lr=1e-3, seed=2))
+    margin = s.calibrate(q[n_train:], t[n_train:], 1e-3)
+    obs = torch.from_numpy(data["obstacles"]).cuda()
+    edges = torch.from_numpy(data["edges"]).cuda()
+    p = dict(workloads.PARAMS["dof7"])
+    res = {}
+    for mode in ("exact", "screened"):
+        prm = ezo.make_params(dof=7, seed=5, surrogate=s if mode == "screened" else None, **p)
+        r = ezo.inflate_edges(ctx, rob, obs, edges, prm)            # warm-up (tuning, graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            r = ezo.inflate_edges(ctx, rob, obs, edges, prm)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / 3 * 1e3
+        ctx.set_phase_timing(True)
+        rt = ezo.inflate_edges(ctx, rob, obs, edges, prm)
+        _, _, tests = ctx.phase_timing(with_tests=True)
+        ctx.set_phase_timing(False)
+        st = rt.stats[0]
+        assert torch.equal(rt.n_faces, r.n_faces) and torch.equal(rt.status, r.status)
+        res[mode] = {"ms": ms, "status": int(r.status[0].item()), "samples": st["samples"],
+                     "screened": st["screened_checks"], "tests_per_sample": tests["check"] / st["samples"]}
+    print(f"margin {margin:.4f}; exact {res['exact']}; screened {res['screened']}; "
+          f"time ratio exact/screened {res['exact']['ms'] / res['screened']['ms']:.3f}")
+    assert res["exact"]["status"] == ezo.CERTIFIED and res["screened"]["status"] == ezo.CERTIFIED
+    assert res["exact"]["screened"] == 0 and res["screened"]["screened"] > 0
+    assert res["screened"]["tests_per_sample"] < res["exact"]["tests_per_sample"]
