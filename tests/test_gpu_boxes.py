@@ -236,3 +236,93 @@ def test_box_arm_full_runs_agree_with_oracle(ezo, ctx):
     finally:
         ctx.set_obstacle_boxes(None)
     assert same_it >= n // 2 and same_f >= n // 2
+
+
+def max_robot(seed=77):
+    """The largest robot the library takes (include/ezo.h limits): 8 joints,
+    1024 spheres (128 per link, radii halved), 64 link boxes (8 per link,
+    small cuboids along each link); 6 000 sphere self pairs drawn from the
+    pairs of links at least two apart that are 2 cm clear at q = 0 (spread
+    over the link pairs) and every box pair of links at least three apart;
+    obstacle spheres and the 64 obstacle boxes beside the arm."""
+    rng = draw.rng_for(seed)
+    desc = draw.arm_dh(rng, dof=8, spheres_per_link=128)
+    desc["sphere_r"] = (desc["sphere_r"] * 0.5).astype(np.float32)
+    cand = draw.self_pair_candidates(desc["sphere_link"], 2)
+    x0 = oracle.sphere_centres(oracle.Robot(dict(desc, self_pairs=np.zeros((0, 2), np.int32))), np.zeros(8))
+    r = desc["sphere_r"].astype(np.float64)
+    gap = np.linalg.norm(x0[cand[:, 0]] - x0[cand[:, 1]], axis=1) - r[cand[:, 0]] - r[cand[:, 1]]
+    cand = cand[gap > 0.02]
+    desc["self_pairs"] = cand[np.sort(rng.choice(len(cand), 6000, replace=False))]
+    a, d, al = (np.asarray(desc[k], np.float64) for k in ("a", "d", "alpha"))
+    prev = np.stack([-a, -d * np.sin(al), -d * np.cos(al)], axis=1)
+    link, pose, half = [], [], []
+    for i in range(8):
+        for j in range(8):
+            c = (1.0 - (j + 0.5) / 8) * prev[i]
+            link.append(i)
+            pose.append(np.concatenate([c, np.eye(3).ravel()]))
+            half.append([0.02, 0.03, 0.025])
+    bl = np.asarray(link, np.int32)
+    i, j = np.triu_indices(64, k=1)
+    keep = np.abs(bl[i] - bl[j]) >= 3
+    desc.update(box_link=bl, box_pose=np.asarray(pose, np.float32), box_half=np.asarray(half, np.float32),
+                box_pairs=np.stack([i[keep], j[keep]], axis=1).astype(np.int32))
+    obs = draw.obstacle_candidates(rng, 64, [0.6, -1.0, 0.0], [1.6, 1.0, 1.2], 0.02, 0.06)
+    ebox = np.zeros((64, 15), np.float32)
+    ebox[:, :3] = rng.uniform([-1.6, -1.0, 0.0], [-0.6, 1.0, 1.2], size=(64, 3))
+    ebox[:, 3:12] = np.eye(3).ravel()
+    ebox[:, 12:] = 0.04
+    return desc, obs, ebox
+
+
+def test_max_size_robot_check_and_bisection(ezo, ctx):
+    """Every size at its maximum at once (dof, spheres, link boxes, obstacle
+    boxes): the checker in flags and signed-distance mode on a ragged batch,
+    and the projection + bisection, whose tile then only just fits the
+    workgroup's LDS, against the oracle."""
+    desc, obs_np, ebox = max_robot()
+    assert len(desc["sphere_r"]) == 1024 and len(desc["box_link"]) == 64 and desc["dof"] == 8
+    q = draw.uniform_q(23, 333, desc["q_lo"], desc["q_hi"])
+    print_case("max robot check", len(q))
+    f = compare(ezo, ctx, desc, obs_np, ebox, q, "max robot")
+    assert 0.05 < f.mean() < 0.99
+    # projection + bisection of a few colliding configurations toward an edge
+    orob = oracle.Robot(desc)
+    ob64, eb64 = f32_up(obs_np), f32_up(ebox)
+    v1, v2 = f32_up(np.zeros(8, np.float32)), f32_up(np.full(8, 0.3, np.float32))
+    cand = q[f.astype(bool)][:8]
+    n = len(cand)
+    print_case("max robot bisection", n)
+    rob = ezo.Robot(ctx, desc)
+    St = torch.zeros((1, 8, n + 3), dtype=torch.float32, device="cuda")
+    St[0, :, :n] = torch.from_numpy(np.ascontiguousarray(cand.T)).cuda()
+    ci = torch.arange(n, dtype=torch.int32, device="cuda")[None]
+    nc = torch.tensor([n], dtype=torch.int32, device="cuda")
+    cs = torch.empty((1, 8, n), dtype=torch.float32, device="cuda")
+    ad = torch.empty((1, 8, n), dtype=torch.float32, device="cuda")
+    ts = torch.empty((1, n), dtype=torch.float32, device="cuda")
+    pc = torch.empty((1, n), dtype=torch.uint8, device="cuda")
+    edge = torch.from_numpy(np.stack([v1, v2]).astype(np.float32)[None]).cuda()
+    ctx.set_obstacle_boxes(ebox)
+    try:
+        ezo.project_bisect(ctx, rob, torch.from_numpy(obs_np).cuda(), edge, St, ci, nc, 11, cs, ad, ts, pc)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_obstacle_boxes(None)
+    cs, ad, ts, pc = (x.cpu().numpy() for x in (cs, ad, ts, pc))
+    t = np.arange(2049) / 2048.0
+    steps, skipped = [], 0
+    for j in range(n):
+        o = oracle.bisect_arm(orob, ob64, v1, v2, f32_up(cand[j]), 11, env_boxes=eb64)
+        assert np.abs(ad[0, :, j] - o["a"]).max() <= 1e-5
+        pts = o["c_proj"][None] + t[:, None] * (f32_up(cand[j]) - o["c_proj"])[None]
+        *_, fr = oracle.check(orob, ob64, pts, env_boxes=eb64, fragile=True)
+        if (fr & 2).any():
+            skipped += 1
+            continue
+        steps.append(bisection_agreement(cs[0, :, j], ts[0, j], pc[0, j], o, f32_up(cand[j]), band=BOX_BAND))
+    print(f"max robot bisection: {len(steps)} compared, {skipped} with a fragile midpoint skipped, steps {steps}")
+    # every compared candidate's end point lies in the oracle's bracket (checked
+    # above); a midpoint inside the band may end the decided steps early
+    assert len(steps) >= n // 2 and np.mean(np.array(steps) >= 8) >= 0.5
