@@ -161,11 +161,25 @@ def cpu_baseline(name, data, desc, seed, edges_idx, n_p=None):
         out = oracle.eizo_arm(orob, obs, v1, v2, prm, env_boxes=data.get("env_boxes"))
         checks += out["stats"]["checks"]
     dt = time.perf_counter() - t0
-    return {"value": checks / dt, "unit": "configs/s", "cores": oracle.max_threads(), "kind": "oracle",
+    # the same reference on one host thread, first edge of the sample only
+    e = edges_idx[0]
+    v1, v2 = data["edges"][e].astype(np.float64)
+    wp = dict(workloads.PARAMS[name], **({"n_p": n_p} if n_p else {}))
+    cores = oracle.max_threads()
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        out = oracle.eizo_arm(orob, obs, v1, v2, oracle.make_params(**wp, seed=seed, edge_id=int(e)),
+                              env_boxes=data.get("env_boxes"))
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(cores)
+    return {"value": checks / dt, "unit": "configs/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 reference EI-ZO on {len(edges_idx)} edge(s) of the '{name}' workload "
                       f"(seed {seed}, N_p {n_p or workloads.PARAMS[name]['n_p']}): {checks} exact checks "
-                      f"in {dt:.2f} s",
-            "edges_per_s": len(edges_idx) / dt}
+                      f"in {dt:.2f} s; one thread: edge {e}, {out['stats']['checks']} checks in {dt1:.2f} s",
+            "edges_per_s": len(edges_idx) / dt,
+            "value_1thread": out["stats"]["checks"] / dt1}
 
 
 def sweep(args):
@@ -216,6 +230,29 @@ def sweep(args):
             points.append(row)
             print(json.dumps(row), file=sys.stderr, flush=True)
     best = max(points, key=lambda r: r["n"] * (r["n_obs"] == 4096))
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        orob = oracle.Robot(desc)
+        qc = qmax[:1 << 16].cpu().numpy().astype(np.float64)
+        cpu = {}
+        for n_obs in (256, 1024, 4096):
+            ob = data[f"obstacles_{n_obs}"].astype(np.float64)
+            t0 = time.perf_counter()
+            oracle.check(orob, ob, qc)
+            cpu[n_obs] = len(qc) / (time.perf_counter() - t0)
+        cores = oracle.max_threads()
+        oracle.set_threads(1)
+        try:
+            t0 = time.perf_counter()
+            oracle.check(orob, data["obstacles_4096"].astype(np.float64), qc[:1 << 12])
+            one = (1 << 12) / (time.perf_counter() - t0)
+        finally:
+            oracle.set_threads(cores)
+        cpu = {"value": cpu[4096], "unit": "configs/s", "cores": cores, "kind": "oracle",
+               "sample": "FP64 reference checker (flags and signed distances, all pairs) on the first 65 536 "
+                         "configurations at 256 / 1024 / 4096 obstacles; one thread: 4 096 configurations at 4096",
+               "configs_per_s_by_obstacles": cpu, "value_1thread": one}
     line = {"metric": "collision-checked configs/sec (raw checker sweep, 7-DOF, 70 spheres, 1500 self pairs)",
             "value": best["sd_configs_per_s"], "unit": "configs/s", "n_gpus": 1, "steps": args.steps,
             "warmup": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -223,6 +260,8 @@ def sweep(args):
                                             "[0.3,1.3]x[-0.5,0.5]x[0,1] m, r U[0.02,0.08]"},
             "points": points,
             "launch_shapes": ezo.tune_cache_entries()}
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 
@@ -760,9 +799,12 @@ def main():
             t_first = None
     # timed region: the product path (one replayed hipGraph per iteration)
     checks = samples = 0
+    step_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        st = step()
+        ts_ = time.perf_counter()
+        st = step()                       # returns once the call's stream is done
+        step_ms.append((time.perf_counter() - ts_) * 1e3)
         checks += sum(s["exact_checks"] for s in st)
         samples += sum(s["samples"] for s in st)
     torch.cuda.synchronize()
@@ -808,6 +850,8 @@ def main():
                 "all_pairs_per_check": rob.n_spheres * int(obs.shape[0]) + rob.n_self,
                 "box_pair_tests_counted": False if rob.n_boxes > 0 or "env_boxes" in data else None,
                 "all_pairs_equivalent_tflops": all_pairs / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0}
+    if roofline["traffic"] is not None and roofline["avg_launch_ms"] > 0:
+        roofline["traffic_gbps"] = roofline["traffic"] / (roofline["avg_launch_ms"] * 1e-3) / 1e9
     counted = measured_valu(name, instance, n_p_used) if instance else None
     if counted is not None and dom_ms > 0:
         # the second form of the FP32 fraction: counted FP32 VALU flop of a
@@ -832,6 +876,7 @@ def main():
         "config": {"workload": f"{name}: {WORKLOADS[name]}", "edges": E, "n_obstacles": int(obs.shape[0]),
                    "robot_spheres": rob.n_spheres, "self_pairs": rob.n_self, "n_p": n_p_used},
         "edges_per_s": E * args.steps / dt,
+        "step_ms_p10_p50_p90": [float(np.percentile(step_ms, x)) for x in (10, 50, 90)],
         "checks_per_step": checks // args.steps,
         "iterations_per_step": iters / args.steps,
         "edge_status": {k: int(np.sum(status == v)) for k, v in
