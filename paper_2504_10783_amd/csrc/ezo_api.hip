@@ -95,7 +95,7 @@ ezo_status prep_obstacles(ezo_ctx* c, const ezo_robot* r, const float* obs, int 
     void *rec, *centre, *geom, *count, *list;
     const int G = grid_dim(n_obs);
     const size_t cells = (size_t)G * G * G;
-    if ((s = ezo_ws_get(c, W_OBS_REC, sizeof(float4) * 2 * (size_t)std::max(n_obs, 1), &rec)) != EZO_OK) return s;
+    if ((s = ezo_ws_get(c, W_OBS_REC, sizeof(float4) * (size_t)std::max(n_obs, 1), &rec)) != EZO_OK) return s;
     if ((s = ezo_ws_get(c, W_OBS_CENTRE, sizeof(float4), &centre)) != EZO_OK) return s;
     if ((s = ezo_ws_get(c, W_GRID_GEOM, sizeof(GridGeom), &geom)) != EZO_OK) return s;
     if ((s = ezo_ws_get(c, W_GRID_COUNT, sizeof(int) * cells, &count)) != EZO_OK) return s;

@@ -123,7 +123,7 @@ __device__ __forceinline__ float4 cload4(const cfloat* p) { return make_float4(p
 struct ObsView {
     int n;
     int lds_n;                 // > 0: the workgroup stages the n records (x, y, z, r) in LDS
-    const float4* rec;         // [n][2]: (ox, oy, oz, ro), (-2ox, -2oy, -2oz, |o|^2 - ro^2), shifted frame
+    const float4* rec;         // [n] (ox, oy, oz, ro), shifted frame
     const float4* centre;      // [1] shift applied to world coordinates (x' = x - centre)
     int n_ebox;                // obstacle boxes (world frame, packed like robot boxes)
     const float4* ebox;        // [n_ebox][4]
@@ -449,7 +449,7 @@ __device__ inline float sat_value(const DBox& A, const DBox& B) {
 // Ends with a barrier.
 __device__ inline void stage_obstacles(const ObsView& ob, const TileSmem& t) {
     if (t.obs)
-        for (int o = threadIdx.x; o < ob.lds_n; o += blockDim.x) t.obs[o] = ob.rec[2 * o];
+        for (int o = threadIdx.x; o < ob.lds_n; o += blockDim.x) t.obs[o] = ob.rec[o];
     __syncthreads();
 }
 
@@ -497,7 +497,7 @@ __device__ inline void tile_pairs_sd(const RobotView& rb, const ObsView& ob, con
             const cfloat* rec = (const cfloat*)ob.rec;
 #pragma unroll 4
             for (int o = o0; o < o1; ++o) {
-                const float4 P0 = cload4(rec + 8 * o);
+                const float4 P0 = cload4(rec + 4 * o);
                 const float ax = A.x - P0.x, ay = A.y - P0.y, az = A.z - P0.z;
                 const float bx = B.x - P0.x, by = B.y - P0.y, bz = B.z - P0.z;
                 const float dA = sqrtf(fmaf(ax, ax, fmaf(ay, ay, az * az)));
@@ -521,7 +521,7 @@ __device__ inline void tile_pairs_sd(const RobotView& rb, const ObsView& ob, con
         for (int k = w * nsub + j; ok && k < B; k += W * nsub) {
             const DBox X = tile_box(t, S, T, k, c);
             for (int o = 0; o < ob.n; ++o) {
-                const float4 O = ob.rec[2 * o];
+                const float4 O = ob.rec[o];
                 env = fminf(env, sd_sphere_box(X, O.x, O.y, O.z, O.w));
             }
             for (int e = 0; e < ob.n_ebox; ++e)
@@ -596,7 +596,7 @@ __device__ inline void tile_boxes_flags(const RobotView& rb, const ObsView& ob, 
         const DBox X = tile_box(t, S, T, w.k, c);
         bool found = false;
         for (int o = 0; o < ob.n && !found; ++o) {
-            const float4 O = t.obs ? t.obs[o] : ob.rec[2 * o];
+            const float4 O = t.obs ? t.obs[o] : ob.rec[o];
             const float dx = O.x - X.c[0], dy = O.y - X.c[1], dz = O.z - X.c[2];
             const float Rr = X.rb + O.w;
             if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < Rr * Rr && hit_sphere_box(X, O.x, O.y, O.z, O.w)) found = true;
@@ -694,7 +694,7 @@ __device__ inline unsigned tile_pairs_grid(const RobotView& rb, const ObsView& o
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int o = (k0 + e < n) ? oi[e] : oi[0];
-                    O[e] = t.obs ? t.obs[o] : ob.rec[2 * o];
+                    O[e] = t.obs ? t.obs[o] : ob.rec[o];
                 }
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {

@@ -43,8 +43,8 @@ __device__ __forceinline__ bool edge_running(const int* status, int e) {
 
 // ---------------------------------------------------------------------------
 // Obstacle preparation (one workgroup): bounding box of the obstacle centres
-// and largest obstacle radius; records (o', r), (-2 o', |o'|^2 - r^2) with
-// o' = o - centre of the box; geometry of a G^3 grid over the box grown by
+// and largest obstacle radius; records (o', r) with o' = o - centre of the
+// box; geometry of a G^3 grid over the box grown by
 // r_sphere_max + r_obstacle_max + slack.
 // ---------------------------------------------------------------------------
 constexpr float kGridSlack = 1e-4f;
@@ -97,8 +97,7 @@ __global__ void __launch_bounds__(256) k_prep_obstacles(const float* __restrict_
     for (int o = tid; o < n; o += blockDim.x) {
         const float x = obs[4 * (size_t)o + 0] - c[0], y = obs[4 * (size_t)o + 1] - c[1], z = obs[4 * (size_t)o + 2] - c[2];
         const float r = obs[4 * (size_t)o + 3];
-        rec[2 * (size_t)o] = make_float4(x, y, z, r);
-        rec[2 * (size_t)o + 1] = make_float4(-2.f * x, -2.f * y, -2.f * z, fmaf(x, x, fmaf(y, y, fmaf(z, z, -r * r))));
+        rec[o] = make_float4(x, y, z, r);
     }
 }
 
@@ -125,7 +124,7 @@ __global__ void __launch_bounds__(256) k_build_grid(const float4* __restrict__ r
         const int o = o0 + lane;
         bool in = false;
         if (o < n) {
-            const float4 O = rec[2 * (size_t)o];
+            const float4 O = rec[o];
             const float dx = fmaxf(fmaxf(lx - O.x, O.x - ux), 0.f);
             const float dy = fmaxf(fmaxf(ly - O.y, O.y - uy), 0.f);
             const float dz = fmaxf(fmaxf(lz - O.z, O.z - uz), 0.f);
