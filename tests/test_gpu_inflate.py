@@ -275,6 +275,62 @@ def test_full_runs_agree_with_oracle_statistically(ezo, ctx):
     assert same_iters >= 0.75 * n and same_faces >= 0.75 * n
 
 
+def test_batched_full_size_sampled_edges_agree_with_oracle(ezo, ctx):
+    """The batched workload at full size in the launch configuration the
+    bench times: all 96 edges in one call, N_p chosen by the sample-count
+    tuner.  One edge per path is re-run on its own by the oracle with the
+    same N_p, seed and edge id.  Unique: the status (every edge certifies)
+    and, on most edges, the iteration count.  Not unique: which candidates
+    become planes -- they are taken in order of t*, and FP32 and FP64 break
+    near-ties in t* (and the last bisection decisions, whose midpoints lie in
+    the band) differently -- so the GPU set is checked for validity (it holds
+    its segment, its hyperplane normals are unit vectors) and for how many of
+    its hyperplanes the oracle also placed: normal within 1e-3 and offset
+    within the last two bisection brackets, diam(D) 2^-(N_b - 1)."""
+    data, desc = load("batched")
+    rob = ezo.Robot(ctx, desc)
+    orob = oracle.Robot(desc)
+    dof = desc["dof"]
+    E = len(data["edges"])
+    print_case("batched full size, tuned N_p", E)
+    ctx.set_autotune(True)
+    prm = ezo.make_params(dof=dof, seed=0, **dict(workloads.PARAMS["batched"], n_p=0))
+    r = ezo.inflate_edges(ctx, rob, torch.from_numpy(data["obstacles"]).cuda(),
+                          torch.from_numpy(data["edges"]).cuda(), prm)
+    torch.cuda.synchronize()
+    ent = [x["T"] for x in ezo.tune_cache_entries() if x["kernel"] == "samples" and x["obstacles"] == 2048
+           and x["log2_items"] == E.bit_length() - 1]
+    assert len(ent) == 1
+    n_p = ent[0]
+    st, nf = r.status.cpu().numpy(), r.n_faces.cpu().numpy()
+    A, b = r.A.cpu().numpy().astype(np.float64), r.b.cpu().numpy().astype(np.float64)
+    assert np.all(st == ezo.CERTIFIED)
+    lo, hi = data["q_lo"].astype(np.float64), data["q_hi"].astype(np.float64)
+    tol_b = float(np.linalg.norm(hi - lo)) * 2.0 ** -(workloads.PARAMS["batched"]["n_b"] - 1)
+    obs64 = f32_up(data["obstacles"])
+    idx = sorted({int(np.nonzero(data["path_id"] == q)[0][0]) for q in np.unique(data["path_id"])})
+    same_iters, matched = 0, []
+    for e in idx:
+        v1, v2 = f32_up(data["edges"][e])
+        o = oracle.eizo_arm(orob, obs64, v1, v2,
+                            oracle.make_params(**dict(workloads.PARAMS["batched"], n_p=n_p), seed=0, edge_id=e))
+        assert st[e] == o["status"]
+        same_iters += r.stats[e]["iterations"] == o["stats"]["iterations"]
+        Ae, be = A[e, :nf[e]], b[e, :nf[e]]
+        for v in (v1, v2):
+            assert np.all(Ae @ v <= be + 1e-5)
+        planes = Ae[2 * dof:]
+        assert np.all(np.abs(np.linalg.norm(planes, axis=1) - 1.0) < 1e-4)
+        oA, ob = np.asarray(o["A"])[2 * dof:], np.asarray(o["b"])[2 * dof:]
+        hit = [np.any((np.abs(oA - planes[k]).max(axis=1) < 1e-3) & (np.abs(ob - be[2 * dof + k]) < tol_b))
+               for k in range(len(planes))]
+        matched.append(float(np.mean(hit)) if hit else 1.0)
+    print(f"N_p {n_p}: same iterations {same_iters}/{len(idx)}; hyperplanes also placed by the oracle per edge "
+          f"{np.round(matched, 2).tolist()}")
+    assert same_iters >= 0.75 * len(idx)
+    assert np.mean(matched) >= 0.5
+
+
 def test_kept_graph_follows_every_change_between_calls(ezo, ctx):
     """Calls on one context reuse its executable loop graph when nothing
     changed, else update it.  Same output buffers, then a different seed, new
