@@ -275,6 +275,42 @@ def test_full_runs_agree_with_oracle_statistically(ezo, ctx):
     assert same_iters >= 0.75 * n and same_faces >= 0.75 * n
 
 
+def test_dof7_full_runs_agree_with_oracle(ezo, ctx):
+    """The bench's default workload (the 7-DOF edge, N_p = 10000) run whole
+    on four seeds, each against the oracle's run with the same seed: the same
+    status on all, the same iteration count on most, each GPU set holding its
+    segment with unit normals, and most of its planes also placed by the
+    oracle (normal within 1e-3, offset within two final bisection brackets;
+    which candidates become planes is not unique across FP32 / FP64)."""
+    data, desc = load("dof7")
+    dof = desc["dof"]
+    rob = ezo.Robot(ctx, desc)
+    orob = oracle.Robot(desc)
+    v1, v2 = f32_up(data["edges"][0])
+    lo, hi = data["q_lo"].astype(np.float64), data["q_hi"].astype(np.float64)
+    tol_b = float(np.linalg.norm(hi - lo)) * 2.0 ** -(workloads.PARAMS["dof7"]["n_b"] - 1)
+    same_iters, matched, n = 0, [], 4
+    for seed in range(n):
+        print_case("dof7 full run", seed)
+        prm = params(ezo, "dof7", dof, seed=seed)
+        A, b, nf, st, stats = run_fused(ezo, ctx, rob, data, data["edges"][:1], prm)
+        o = oracle.eizo_arm(orob, f32_up(data["obstacles"]), v1, v2,
+                            oracle.make_params(**workloads.PARAMS["dof7"], seed=seed))
+        assert st[0] == o["status"]
+        same_iters += stats[0]["iterations"] == o["stats"]["iterations"]
+        Ae, be = A[0, :nf[0]].astype(np.float64), b[0, :nf[0]].astype(np.float64)
+        for v in (v1, v2):
+            assert np.all(Ae @ v <= be + 1e-5)
+        planes = Ae[2 * dof:]
+        assert np.all(np.abs(np.linalg.norm(planes, axis=1) - 1.0) < 1e-4)
+        oA, ob = np.asarray(o["A"])[2 * dof:], np.asarray(o["b"])[2 * dof:]
+        hit = [np.any((np.abs(oA - planes[k]).max(axis=1) < 1e-3) & (np.abs(ob - be[2 * dof + k]) < tol_b))
+               for k in range(len(planes))]
+        matched.append(float(np.mean(hit)) if hit else 1.0)
+    print(f"same iterations {same_iters}/{n}; planes also placed by the oracle {np.round(matched, 2).tolist()}")
+    assert same_iters >= 0.75 * n and np.mean(matched) >= 0.5
+
+
 def test_batched_full_size_sampled_edges_agree_with_oracle(ezo, ctx):
     """The batched workload at full size in the launch configuration the
     bench times: all 96 edges in one call, N_p chosen by the sample-count
