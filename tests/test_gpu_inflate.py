@@ -408,3 +408,26 @@ def test_kept_graph_follows_every_change_between_calls(ezo, ctx):
     ezo.inflate_edges(ctx, rob, obs, edges[:5], params(ezo, "batched", dof, seed=1), out=out)
     torch.cuda.synchronize()
     same(out, fresh(1, obs, edges[:5]), 5)
+
+
+def test_first_test_count_does_not_depend_on_n_p(ezo, ctx):
+    """The certificate does not depend on N_p (Sec. IV-B: the test counts
+    collisions among the first M_k samples of |S| = max(N_p, M_k)): one
+    iteration on the 7-DOF edge with N_p from below M_1 = 559 to 10000
+    reports the same test count bit for bit, equal to the oracle's up to a
+    configuration whose flag lies in the FP32 band."""
+    data, desc = load("dof7")
+    rob = ezo.Robot(ctx, desc)
+    print_case("test count vs N_p")
+    counts = []
+    for n_p in (500, 1000, 2000, 10000):
+        prm = params(ezo, "dof7", desc["dof"], seed=2, n_p=n_p, max_iters=1)
+        *_, stats = run_fused(ezo, ctx, rob, data, data["edges"][:1], prm)
+        assert stats[0]["final_m"] == 559 and stats[0]["samples"] == max(n_p, 559)
+        counts.append(stats[0]["test_collisions"])
+    assert len(set(counts)) == 1
+    v1, v2 = f32_up(data["edges"][0])
+    o = oracle.eizo_arm(oracle.Robot(desc), f32_up(data["obstacles"]), v1, v2,
+                        oracle.make_params(**dict(workloads.PARAMS["dof7"], n_p=1000, max_iters=1), seed=2))
+    print("test count", counts[0], "oracle", o["stats"]["test_collisions"])
+    assert abs(counts[0] - o["stats"]["test_collisions"]) <= 1

@@ -208,3 +208,23 @@ def test_stored_workloads_are_valid(orc):
     for i in range(95):
         if b["path_id"][i] == b["path_id"][i + 1]:
             np.testing.assert_array_equal(b["edges"][i, 1], b["edges"][i + 1, 0])
+
+
+def test_first_test_count_does_not_depend_on_n_p(orc):
+    """Sec. IV-B: |S| = max(N_p, M_k) and the unadaptive test counts the
+    collisions among the first M_k samples only.  At k = 1 the polytope is
+    the joint box whatever N_p is, and sample i is drawn from the same
+    counter-based stream, so the test's count (and M_1) is the same for N_p
+    below, near and far above M_1 = 280 -- what lets a tuner pick N_p
+    without touching the certificate; the planes placed from the larger
+    candidate sets may differ."""
+    data = workloads.load("tiny")
+    rob = orc.Robot(workloads.robot(data))
+    v1, v2 = data["edges"][0].astype(np.float64)
+    outs = []
+    for n_p in (100, 300, 1000, 5000):
+        prm = orc.make_params(**dict(workloads.PARAMS["tiny"], n_p=n_p, max_iters=1), seed=3)
+        o = orc.eizo_arm(rob, data["obstacles"], v1, v2, prm)
+        assert o["stats"]["samples"] == max(n_p, 280) and o["stats"]["final_m"] == 280
+        outs.append(o["stats"]["test_collisions"])
+    assert len(set(outs)) == 1 and outs[0] > 14           # the same count; above T_1 = 14 (not yet certified)
