@@ -87,6 +87,8 @@ def _declare(L):
     L.orc_sd_sphere_box.restype = C.c_double
     L.orc_sat_boxes.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, C.POINTER(C.c_int)]
     L.orc_sat_boxes.restype = C.c_double
+    L.orc_set_fragility.argtypes = [C.c_double, C.c_double]
+    L.orc_set_fragility.restype = None
     L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
     L.orc_u01.argtypes = [C.c_uint32]
     L.orc_u01.restype = C.c_double
@@ -243,6 +245,12 @@ def sd_sphere_box(x, r, c, R, h):
     """Signed distance of a sphere (centre x, radius r) and a box (centre c,
     rotation R with the box axes as columns, half extents h)."""
     return lib().orc_sd_sphere_box(_ptr(_d(x)), float(r), _ptr(_d(c)), _ptr(_d(R).reshape(9)), _ptr(_d(h)))
+
+
+def set_fragility(weak_axis_norm=0.05, band=5e-5):
+    """Thresholds of the fragility bits (sat_boxes, check): a cross axis
+    |A_i x B_j| < weak_axis_norm is weak; the sign bit uses +-band."""
+    lib().orc_set_fragility(float(weak_axis_norm), float(band))
 
 
 def sat_boxes(cA, RA, hA, cB, RB, hB):

@@ -189,10 +189,21 @@ double orc_sd_sphere_box(const double x[3], double r, const double c[3], const d
  * otherwise minus the smallest overlap over the axes, which for two boxes is
  * the penetration depth.  *fragile (may be NULL) flags where FP32 rounding
  * of the poses, amplified on a cross axis of nearly parallel edges
- * (|A_i x B_j| < 0.05, a "weak" axis), can change the result: bit 0 (the
- * value) when a weak axis comes within 1e-3 of the value or within 1e-4 of
- * 0; bit 1 (the sign) when the value is set by a weak axis, is above -5e-5,
- * and the other axes alone give less than 5e-5. */
+ * (|A_i x B_j| < weak, a "weak" axis; weak and the band are set by
+ * orc_set_fragility, default 0.05 and 5e-5), can change the result: bit 0
+ * (the value) when a weak axis comes within 1e-3 of the value or within 1e-4
+ * of 0; bit 1 (the sign) when the value is set by a weak axis, is above
+ * -band, and the other axes alone give less than band. */
+static double g_weak_axis = 0.05, g_fragile_band = 5e-5;
+
+/* Thresholds of the fragility bits of orc_sat_boxes (test infrastructure: the
+ * conditioning of a cross axis is about 1/|A_i x B_j|, so a smaller weak norm
+ * needs a wider band).  Not thread-safe: set before checking. */
+void orc_set_fragility(double weak_axis_norm, double band) {
+    g_weak_axis = weak_axis_norm;
+    g_fragile_band = band;
+}
+
 double orc_sat_boxes(const double cA[3], const double RA[9], const double hA[3], const double cB[3],
                      const double RB[9], const double hB[3], int *fragile) {
     double Ax[3][3], Bx[3][3], t[3];
@@ -229,7 +240,7 @@ double orc_sat_boxes(const double cA[3], const double RA[9], const double hA[3],
         }
         const double sep = fabs(t[0] * L[0] + t[1] * L[1] + t[2] * L[2]) - rA - rB;
         if (sep > best) best = sep;
-        if (a >= 6 && norm < 0.05)
+        if (a >= 6 && norm < g_weak_axis)
             weak[n_weak++] = sep;
         else if (sep > best_good)
             best_good = sep;
@@ -238,7 +249,7 @@ double orc_sat_boxes(const double cA[3], const double RA[9], const double hA[3],
         *fragile = 0;
         for (int i = 0; i < n_weak; ++i)
             if (weak[i] > best - 1e-3 || fabs(weak[i]) < 1e-4) *fragile |= 1;
-        if (best > best_good && best > -5e-5 && best_good < 5e-5) *fragile |= 2;
+        if (best > best_good && best > -g_fragile_band && best_good < g_fragile_band) *fragile |= 2;
     }
     return best;
 }

@@ -392,13 +392,19 @@ __device__ __forceinline__ bool hit_sphere_box(const DBox& B, float x, float y, 
 
 // Separating-axis value of two boxes: with C_ij = A_i . B_j and t_i = A_i . t
 // (t = c_B - c_A, A_i and B_j the box axes), the face axes give
-// |t_i| - h_Ai - sum_j h_Bj |C_ij| and |sum_i C_ij t_i| - sum_i h_Ai |C_ij| - h_Bj,
-// the cross axis A_i x B_j (length sqrt(1 - C_ij^2), skipped below 1e-6) the
-// unnormalised value |t_{i+2} C_{i+1,j} - t_{i+1} C_{i+2,j}| - h_A(i+1) |C_{i+2,j}|
-// - h_A(i+2) |C_{i+1,j}| - h_B(j+1) |C_{i,j+2}| - h_B(j+2) |C_{i,j+1}| (indices
-// mod 3), divided by that length.  Returns the largest (exact: all axes).
-// With early = true it returns as soon as an axis has a value >= 0 (the
-// boxes do not collide) and the result is then only that value.
+// |t_i| - h_Ai - sum_j h_Bj |C_ij| and |sum_i C_ij t_i| - sum_i h_Ai |C_ij| - h_Bj.
+// A cross axis n = A_i x B_j is taken in A's frame, where it is
+// (n_i, n_i1, n_i2) = (0, -C_i2,j, C_i1,j) (i1 = i+1, i2 = i+2 mod 3): its
+// length is sqrt(C_i1,j^2 + C_i2,j^2) (a sum of squares, so nearly parallel
+// edges keep their length to full relative precision; skipped below 1e-6),
+// and every term of the unnormalised value
+//   |t . n| - sum_k h_Ak |n_k| - sum_k h_Bk |B_k . n|,
+//   B_k . n = C_i1,j C_i2,k - C_i2,j C_i1,k   (a cofactor of C; 0 for k = j)
+// is a product of n's components, so its rounding error scales with |n| and
+// the normalised value is as accurate as that of a well separated axis.
+// Returns the largest value (exact: all axes).  With early = true it returns
+// as soon as an axis has a value >= 0 (the boxes do not collide) and the
+// result is then only that value.
 template <bool EARLY>
 __device__ inline float sat_value(const DBox& A, const DBox& B) {
     const float tx = B.c[0] - A.c[0], ty = B.c[1] - A.c[1], tz = B.c[2] - A.c[2];
@@ -432,11 +438,13 @@ __device__ inline float sat_value(const DBox& A, const DBox& B) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-            const float n2 = fmaf(-C[i][j], C[i][j], 1.f);
+            const float n2 = fmaf(C[i1][j], C[i1][j], C[i2][j] * C[i2][j]);
             if (n2 < 1e-12f) continue;
+            const float bj1 = fmaf(C[i1][j], C[i2][j1], -C[i2][j] * C[i1][j1]);
+            const float bj2 = fmaf(C[i1][j], C[i2][j2], -C[i2][j] * C[i1][j2]);
             const float u = fabsf(fmaf(t[i2], C[i1][j], -t[i1] * C[i2][j])) -
                             fmaf(A.h[i1], aC[i2][j], fmaf(A.h[i2], aC[i1][j],
-                                 fmaf(B.h[j1], aC[i][j2], B.h[j2] * aC[i][j1])));
+                                 fmaf(B.h[j1], fabsf(bj1), B.h[j2] * fabsf(bj2))));
             const float v = u * rsqrtf(n2);
             best = fmaxf(best, v);
             if (EARLY && u >= 0.f) return v;
