@@ -289,7 +289,11 @@ ezo_status ezo_place_hyperplanes(ezo_ctx *ctx, int32_t dof, const float *edges, 
  * call with a new key inflates its own edges with N_p = 10000, 5000, 2000 and
  * 1000 (each once, then all again three times) and keeps the largest N_p
  * whose time is within 5 % of the fastest; with tuning off and nothing
- * cached N_p = 10000.  The certification does not depend on
+ * cached N_p = 10000.  Those timed inflations draw from an independent
+ * random stream (Philox key seed ^ 0x9E3779B97F4A7C15, recorded as
+ * "tune_seed" in the cache entry) and are discarded; the returned sets are
+ * one inflation with the chosen N_p on the call's own seed, so the choice
+ * never depends on their draws.  The certification does not depend on
  * N_p (the test uses the first M_k samples); the sets do. */
 ezo_status ezo_inflate_edges(ezo_ctx *ctx, const ezo_robot *robot, const float *obs, int32_t n_obs,
                              const float *edges, int32_t n_edges, const ezo_params *params, float *A,
@@ -526,6 +530,8 @@ ezo_status ezo_set_autotune(ezo_ctx *ctx, int32_t enable);
  * time per launch).  For "bisect", T counts candidates per workgroup and
  * depth (1..3, optional on import, default 1) the bisection levels checked
  * per round, so a tile check holds T (2^depth - 1) configurations.  For
+ * "samples" (the sample count N_p of ezo_inflate_edges), T is N_p and
+ * tune_seed (export only) the Philox key of the timed inflations.  For
  * "sample", T is
  * the number of lanes per walk, W the waves per workgroup, and spheres =
  * self_pairs = obstacles = 0.

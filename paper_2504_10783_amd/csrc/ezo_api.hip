@@ -461,6 +461,8 @@ constexpr int kItersPerGraph = 4;        // iterations captured per replayed gra
 constexpr int kSampleCounts[] = {10000, 5000, 2000, 1000};
 constexpr double kSampleCountSlack = 0.05;
 constexpr int kDefaultSampleCount = 10000;
+// The sample-count tuner's inflations draw from key seed ^ kTuneSeedMix.
+constexpr uint64_t kTuneSeedMix = 0x9E3779B97F4A7C15ull;
 // Edges per round of ezo_inflate_paths (a path window of s = kPathBatch / paths edges).
 constexpr int kPathBatch = 128;
 
@@ -1000,11 +1002,15 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
     if (!edges || !A || !b || !n_faces || !edge_status || (n_obs > 0 && !obs))
         return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
     if (p->n_p == 0) {
-        // N_p chosen by measurement: whole inflations of this call's own
-        // edges with each candidate count (results go to the call's outputs
-        // and are overwritten below); kept per key is the largest count
-        // within kSampleCountSlack of the fastest.  Certification does not
-        // depend on N_p: the test always uses the first M_k samples.
+        // N_p chosen by measurement: whole inflations of this call's edges
+        // with each candidate count, drawn from an independent random stream
+        // (key seed ^ kTuneSeedMix) and thrown away (they use the call's
+        // outputs as scratch; the inflation below overwrites them).  Kept per
+        // key is the largest count within kSampleCountSlack of the fastest.
+        // The choice thus never depends on the draws of the returned sets: a
+        // run whose test happened to accept early finishes sooner, and picking
+        // by time on the returned stream would favour it.  Certification does
+        // not depend on N_p: the test always uses the first M_k samples.
         const TuneKey k = tune_key(c, r, TUNE_SAMPLE_COUNT, n_obs, n_edges);
         TileCfg g;
         if (!ezo_tune_lookup(k, &g)) {
@@ -1020,14 +1026,17 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
                     t.W = 1;
                     cands.push_back(t);
                 }
+                const uint64_t tune_seed = p->seed ^ kTuneSeedMix;
                 auto run = [&](const TileCfg& t) -> ezo_status {
                     ezo_params q = *p;
                     q.n_p = t.T;
+                    q.seed = tune_seed;
                     return inflate_core(c, r, obs, n_obs, edges, n_edges, &q, A, b, n_faces, edge_status, nullptr,
                                         c->stream, edge_ids, skip);
                 };
                 ezo_status ts = ezo_tune_search(c, k, cands, c->stream, run, &g, kSampleCountSlack);
                 if (ts) return ts;
+                ezo_tune_note_seed(k, tune_seed);
             }
         }
         ezo_params q = *p;

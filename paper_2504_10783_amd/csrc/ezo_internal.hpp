@@ -142,6 +142,10 @@ ezo_status ezo_tune_search(ezo_ctx* c, const TuneKey& k, const std::vector<TileC
                            const std::function<ezo_status(const TileCfg&)>& run, TileCfg* best,
                            double slack = kTuneSlack);
 
+// Records, for a cached entry, the Philox key that the timed runs drew from
+// (the sample-count tuner's own stream; exported as "tune_seed").
+void ezo_tune_note_seed(const TuneKey& k, uint64_t seed);
+
 extern std::string g_create_err;
 ezo_status ezo_fail(ezo_ctx* c, ezo_status code, const char* fmt, ...);
 ezo_status ezo_ws_get(ezo_ctx* c, int slot, size_t bytes, void** out);

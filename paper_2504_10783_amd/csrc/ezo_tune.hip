@@ -27,6 +27,8 @@ const char* kKindNames[TUNE_NKINDS] = {"check_flags", "check_sd", "bisect", "sam
 struct Entry {
     TileCfg cfg;
     double us = 0.0;
+    bool has_seed = false;      // the timed runs drew from Philox key `seed`
+    uint64_t seed = 0;
 };
 
 std::mutex g_mu;
@@ -159,6 +161,14 @@ ezo_status ezo_tune_search(ezo_ctx* c, const TuneKey& k, const std::vector<TileC
     return EZO_OK;
 }
 
+void ezo_tune_note_seed(const TuneKey& k, uint64_t seed) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_cache.find(k);
+    if (it == g_cache.end()) return;
+    it->second.has_seed = true;
+    it->second.seed = seed;
+}
+
 extern "C" {
 
 ezo_status ezo_set_autotune(ezo_ctx* c, int32_t enable) {
@@ -174,13 +184,14 @@ ezo_status ezo_tune_cache_export(char* buf, int64_t capacity, int64_t* length) {
         for (const auto& kv : g_cache) {
             const TuneKey& k = kv.first;
             const Entry& e = kv.second;
-            char line[512];
+            char line[512], seed[64] = "";
+            if (e.has_seed) std::snprintf(seed, sizeof(seed), ",\"tune_seed\":%llu", (unsigned long long)e.seed);
             std::snprintf(line, sizeof(line),
                           "{\"arch\":\"%s\",\"kernel\":\"%s\",\"dof\":%d,\"spheres\":%d,\"self_pairs\":%d,"
                           "\"boxes\":%d,\"obstacles\":%d,\"log2_items\":%d,\"T\":%d,\"W\":%d,\"stage\":%d,"
-                          "\"depth\":%d,\"us\":%.3f}\n",
+                          "\"depth\":%d,\"us\":%.3f%s}\n",
                           k.arch.c_str(), kKindNames[k.kind], k.dof, k.S, k.P, k.B, k.n_obs, k.bucket, e.cfg.T,
-                          e.cfg.W, e.cfg.stage, e.cfg.depth, e.us);
+                          e.cfg.W, e.cfg.stage, e.cfg.depth, e.us, seed);
             os << line;
         }
     }

@@ -221,9 +221,13 @@ def test_autotuned_inflation_equals_heuristic(ezo, ctx, name, max_iters):
 def test_sample_count_tuning(ezo, ctx):
     """n_p = 0: the first call times whole inflations with each candidate
     N_p and caches one ("samples" entry: the largest within 5 % of the
-    fastest, a timing-dependent pick); the call's result equals
-    an explicit call with that N_p bit for bit; a second call reuses the
-    entry; with tuning off and no entry N_p = 10000."""
+    fastest, a timing-dependent pick); the timed inflations drew from their
+    own Philox key (seed ^ 0x9E3779B97F4A7C15, recorded in the entry), never
+    from the call's, so the pick cannot favour a run whose own draws ended it
+    early (Alg. 1 Output: the delta bound holds for the returned sets); the
+    call's result equals an explicit call with that N_p on the call's seed bit
+    for bit; a second call reuses the entry; with tuning off and no entry
+    N_p = 10000."""
     import workloads
     data, desc = load("dof7")
     rob = ezo.Robot(ctx, desc)
@@ -239,6 +243,7 @@ def test_sample_count_tuning(ezo, ctx):
         ent = [e for e in ezo.tune_cache_entries() if e["kernel"] == "samples"]
         print("samples entries", ent)
         assert len(ent) == 1 and ent[0]["T"] in (1000, 2000, 5000, 10000) and ent[0]["log2_items"] == 0
+        assert ent[0]["tune_seed"] == 6 ^ 0x9E3779B97F4A7C15 and ent[0]["tune_seed"] != 6
         chosen = ent[0]["T"]
         assert int(r.status[0].item()) == ezo.CERTIFIED
         ref = ezo.inflate_edges(ctx, rob, obs, edges, ezo.make_params(dof=7, seed=6, **dict(p, n_p=chosen)))
