@@ -95,6 +95,9 @@ def _declare(L):
     L.orc_test_constants.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, _i64p, _i64p]
     L.orc_hit_and_run.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _dp, _dp, C.c_int32, C.c_uint64,
                                   C.c_uint32, C.c_uint32, C.c_int64, _dp]
+    L.orc_hit_and_run_steps.argtypes = [C.c_int32, _dp, _dp, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32,
+                                        C.c_uint32, C.c_int64, C.c_int64, _dp, _dp]
+    L.orc_hit_and_run_steps.restype = None
     L.orc_project.argtypes = [C.c_int32, _dp, _dp, _dp, _dp, _dp]
     L.orc_bisect_arm.argtypes = [rp, _dp, C.c_int32, _dp, C.c_int32, _dp, _dp, _dp, C.c_int32, _dp, _dp, _dp, _dp,
                                  _dp, _dp]
@@ -290,6 +293,21 @@ def hit_and_run(A, b, v1, v2, n_mix, seed, edge, k, n):
     lib().orc_hit_and_run(d, _ptr(A), _ptr(b), A.shape[0], _ptr(v1), _ptr(v2), int(n_mix),
                           int(seed), int(edge), int(k), int(n), _ptr(S))
     return S
+
+
+def hit_and_run_step(A, b, X, seed, edge, k, s, first=0):
+    """Step s (>= 1) of hit-and-run walks first .. first + n - 1 (Sec. IV-B),
+    each taken from its own point X[i] (rows [n][d]).  Returns the new points
+    and, per walk, a^T u of the rows that bound the chord below and above
+    (0 where no row bounds that end)."""
+    A = _d(A)
+    b = _d(b)
+    X = np.array(X, dtype=np.float64, order="C", copy=True)
+    n, d = X.shape
+    den = np.zeros((n, 2))
+    lib().orc_hit_and_run_steps(d, _ptr(A), _ptr(b), A.shape[0], int(seed), int(edge), int(k), int(s),
+                                int(first), int(n), _ptr(X), _ptr(den))
+    return X, den
 
 
 def project(v1, v2, c):

@@ -485,50 +485,71 @@ void orc_test_constants(double eps, double delta, double tau, int32_t k, int64_t
 /* Hit-and-run inside P = {x : A x <= b} (Sec. IV-B, Lovasz 1999)            */
 /* ------------------------------------------------------------------------ */
 
-/* One walk: start uniform on L = conv{v1, v2}, then n_mix steps.  A step draws
- * a direction u = g/|g|, g ~ N(0, I) (Box-Muller on word pairs), intersects
- * the line x + t u with every row to get the chord [t_lo, t_hi], and moves to
- * t ~ U[t_lo, t_hi].  If rounding leaves t_hi < t_lo the walk stays put. */
+/* Step s (>= 1) of walk i from the point x (updated in place): draws a
+ * direction u = g/|g|, g ~ N(0, I) (Box-Muller on word pairs), intersects the
+ * line x + t u with every row to get the chord [t_lo, t_hi], and moves to
+ * t ~ U[t_lo, t_hi].  If rounding leaves t_hi < t_lo the walk stays put.
+ * den_bind (may be NULL) receives a^T u of the rows that set t_lo and t_hi
+ * (0 where no row bounds that end): how well conditioned the two chord ends
+ * are. */
+void orc_hit_and_run_step(int32_t d, const double *A, const double *b, int32_t F, uint64_t seed,
+                          uint32_t i, uint32_t e, uint32_t k, uint32_t s, double *x, double *den_bind) {
+    const int npair = (d + 1) / 2;
+    double g[64], u[64];
+    for (int m = 0; m < npair; ++m) {
+        double ua = stream_u01(seed, i, e, k, s, 2 * m);
+        double ub = stream_u01(seed, i, e, k, s, 2 * m + 1);
+        double r = sqrt(-2.0 * log(ua));
+        g[2 * m] = r * cos(2.0 * ORC_PI * ub);
+        g[2 * m + 1] = r * sin(2.0 * ORC_PI * ub);
+    }
+    double nrm = 0.0;
+    for (int j = 0; j < d; ++j) nrm += g[j] * g[j];
+    nrm = sqrt(nrm);
+    for (int j = 0; j < d; ++j) u[j] = g[j] / nrm;
+    double t_lo = -INFINITY, t_hi = INFINITY, den_lo = 0.0, den_hi = 0.0;
+    for (int f = 0; f < F; ++f) {
+        double den = 0.0, ax = 0.0;
+        for (int j = 0; j < d; ++j) {
+            den += A[(size_t)f * d + j] * u[j];
+            ax += A[(size_t)f * d + j] * x[j];
+        }
+        double num = b[f] - ax;
+        if (den > 0.0) {
+            double t = num / den;
+            if (t < t_hi) { t_hi = t; den_hi = den; }
+        } else if (den < 0.0) {
+            double t = num / den;
+            if (t > t_lo) { t_lo = t; den_lo = den; }
+        }
+    }
+    double wt = stream_u01(seed, i, e, k, s, 2 * npair);
+    double t = 0.0;
+    if (t_hi >= t_lo && isfinite(t_lo) && isfinite(t_hi)) t = t_lo + wt * (t_hi - t_lo);
+    for (int j = 0; j < d; ++j) x[j] += t * u[j];
+    if (den_bind) {
+        den_bind[0] = den_lo;
+        den_bind[1] = den_hi;
+    }
+}
+
+/* One walk: start uniform on L = conv{v1, v2}, then n_mix steps. */
 void orc_hit_and_run_walk(int32_t d, const double *A, const double *b, int32_t F,
                           const double *v1, const double *v2, int32_t n_mix, uint64_t seed,
                           uint32_t i, uint32_t e, uint32_t k, double *x) {
     double w0 = stream_u01(seed, i, e, k, 0, 0);
     for (int j = 0; j < d; ++j) x[j] = v1[j] + w0 * (v2[j] - v1[j]);
-    const int npair = (d + 1) / 2;
-    double g[64], u[64];
-    for (int s = 1; s <= n_mix; ++s) {
-        for (int m = 0; m < npair; ++m) {
-            double ua = stream_u01(seed, i, e, k, (uint32_t)s, 2 * m);
-            double ub = stream_u01(seed, i, e, k, (uint32_t)s, 2 * m + 1);
-            double r = sqrt(-2.0 * log(ua));
-            g[2 * m] = r * cos(2.0 * ORC_PI * ub);
-            g[2 * m + 1] = r * sin(2.0 * ORC_PI * ub);
-        }
-        double nrm = 0.0;
-        for (int j = 0; j < d; ++j) nrm += g[j] * g[j];
-        nrm = sqrt(nrm);
-        for (int j = 0; j < d; ++j) u[j] = g[j] / nrm;
-        double t_lo = -INFINITY, t_hi = INFINITY;
-        for (int f = 0; f < F; ++f) {
-            double den = 0.0, ax = 0.0;
-            for (int j = 0; j < d; ++j) {
-                den += A[(size_t)f * d + j] * u[j];
-                ax += A[(size_t)f * d + j] * x[j];
-            }
-            double num = b[f] - ax;
-            if (den > 0.0) {
-                double t = num / den;
-                if (t < t_hi) t_hi = t;
-            } else if (den < 0.0) {
-                double t = num / den;
-                if (t > t_lo) t_lo = t;
-            }
-        }
-        double wt = stream_u01(seed, i, e, k, (uint32_t)s, 2 * npair);
-        double t = 0.0;
-        if (t_hi >= t_lo && isfinite(t_lo) && isfinite(t_hi)) t = t_lo + wt * (t_hi - t_lo);
-        for (int j = 0; j < d; ++j) x[j] += t * u[j];
-    }
+    for (int s = 1; s <= n_mix; ++s) orc_hit_and_run_step(d, A, b, F, seed, i, e, k, (uint32_t)s, x, NULL);
+}
+
+/* Step s of walks first .. first + n - 1, each from its own point X[i] (in
+ * place); den_bind [n][2] or NULL. */
+void orc_hit_and_run_steps(int32_t d, const double *A, const double *b, int32_t F, uint64_t seed, uint32_t e,
+                           uint32_t k, uint32_t s, int64_t first, int64_t n, double *X, double *den_bind) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        orc_hit_and_run_step(d, A, b, F, seed, (uint32_t)(first + i), e, k, s, X + (size_t)i * d,
+                             den_bind ? den_bind + 2 * (size_t)i : NULL);
 }
 
 void orc_hit_and_run(int32_t d, const double *A, const double *b, int32_t F, const double *v1,

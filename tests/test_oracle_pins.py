@@ -303,6 +303,57 @@ def test_hit_and_run_streams_are_independent_of_batch(orc):
     assert not np.allclose(S3, S2)
 
 
+def test_hit_and_run_step_one_dimension_closed_form(orc):
+    """In one dimension P = [lo, hi] and u = +-1, so the chord is [lo, hi]
+    whatever the current point is: step s lands at lo + w (hi - lo) (u = +1)
+    or hi - w (hi - lo) (u = -1), w the chord word (word 2 of the step's
+    Philox call, counter (i, e, k, 16 s)).  Both chord ends are bounded by a
+    row with |a^T u| = 1."""
+    lo, hi = -0.7, 1.9
+    A, b = box_rows(np.array([lo]), np.array([hi]))
+    rng = np.random.default_rng(4)
+    n, seed, e, k, s = 500, 12345, 3, 2, 7
+    X = rng.uniform(lo, hi, size=(n, 1))
+    Y, den = orc.hit_and_run_step(A, b, X, seed, e, k, s, first=40)
+    key = np.array([seed & 0xFFFFFFFF, seed >> 32], np.uint32)
+    for i in range(n):
+        w = orc.u01(int(orc.philox([40 + i, e, k, 16 * s], key)[2]))
+        y = Y[i, 0]
+        assert min(abs(y - (lo + w * (hi - lo))), abs(y - (hi - w * (hi - lo)))) <= 1e-12
+    np.testing.assert_array_equal(np.abs(den), 1.0)
+    assert np.all(den[:, 0] < 0) and np.all(den[:, 1] > 0)
+
+
+def test_hit_and_run_step_chord_ends_on_boundary(orc):
+    """A step moves along a line through x and stays in P; the two rows it
+    reports as binding are the rows where that line leaves P on either side
+    of x (brute force over the rows along the line's direction)."""
+    A = np.array([[-1.0, 0.0], [0.0, -1.0], [1.0, 1.0], [1.0, -2.0]])
+    b = np.array([0.0, 0.0, 1.0, 0.5])
+    X = np.tile([[0.2, 0.2]], (300, 1))
+    Y, den = orc.hit_and_run_step(A, b, X, 9, 0, 1, 1)
+    assert np.all(Y @ A.T <= b + 1e-12)
+    for x, y, dd in zip(X, Y, den):
+        u = (y - x) / np.linalg.norm(y - x)
+        au = A @ u
+        t = (b - A @ x) / au
+        fwd = np.where(au > 0, t, np.inf).argmin()
+        bwd = np.where(au < 0, t, -np.inf).argmax()
+        want = sorted([abs(au[fwd]), abs(au[bwd])])
+        np.testing.assert_allclose(sorted(np.abs(dd)), want, atol=1e-9)
+        assert dd[0] < 0 < dd[1]
+
+
+def test_hit_and_run_steps_reproduce_the_walk(orc):
+    A = np.array([[-1.0, 0.0, 0.0], [0.0, -1.0, 0.0], [0.0, 0.0, -1.0], [1.0, 1.0, 1.0]])
+    b = np.array([0.0, 0.0, 0.0, 1.0])
+    v1, v2 = np.array([0.1, 0.1, 0.1]), np.array([0.3, 0.2, 0.1])
+    X = orc.hit_and_run(A, b, v1, v2, 0, 21, 2, 5, 64)
+    for s in range(1, 13):
+        X, _ = orc.hit_and_run_step(A, b, X, 21, 2, 5, s)
+    np.testing.assert_array_equal(X, orc.hit_and_run(A, b, v1, v2, 12, 21, 2, 5, 64))
+
+
 # --------------------------------------------------------------------------
 # Projection, gradient, tangent plane (Sec. IV-A), bisection (Sec. IV-B)
 # --------------------------------------------------------------------------
