@@ -195,6 +195,25 @@ ezo_status ezo_check_collisions(ezo_ctx *ctx, const ezo_robot *robot, const floa
                                 const float *q, int64_t n, int64_t stride_n, int64_t stride_d,
                                 uint8_t *flags, float *min_sd, float *min_sd_self, void *stream);
 
+/* The same check with no allocation: for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, layouts, outputs and errors as in
+ * ezo_check_collisions; the results are bit-identical to it.  Instead of the
+ * context's growable workspace it uses a fixed scratch array in device
+ * memory (obstacle records, frame shift, broad-phase grid counts and lists:
+ * about 8.6 MB), one per device, allocated with the library's code object
+ * and held until the process ends; the call itself allocates nothing and
+ * never runs a launch-shape timing search (it uses the tuning cache, else
+ * the size heuristic).  Limit: n_obs <= EZO_NOALLOC_MAX_OBSTACLES, else
+ * EZO_E_CAPACITY (any n).  Every call on one device shares that device's
+ * scratch, so calls that overlap on one device (two streams, two contexts,
+ * two threads) race; calls in one stream are ordered.  Each call rewrites
+ * every scratch byte it reads. */
+#define EZO_NOALLOC_MAX_OBSTACLES 4096
+ezo_status ezo_check_collisions_noalloc(ezo_ctx *ctx, const ezo_robot *robot, const float *obs, int32_t n_obs,
+                                        const float *q, int64_t n, int64_t stride_n, int64_t stride_d,
+                                        uint8_t *flags, float *min_sd, float *min_sd_self, void *stream);
+
 /* Forward kinematics only: world-frame sphere centres, centres[i][s][0..2]
  * (dev f32 [n][S][3]), for the same q layout as ezo_check_collisions. */
 ezo_status ezo_sphere_centres(ezo_ctx *ctx, const ezo_robot *robot, const float *q, int64_t n,

@@ -20,11 +20,12 @@ LIB_PATH = os.path.join(_HERE, "libezo.so")
 EZO_OK, EZO_E_INVALID, EZO_E_HIP, EZO_E_CAPACITY, EZO_E_NOMEM, EZO_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 CERTIFIED, MAX_ITERS, IN_COLLISION, INVALID, CONTAINED = 0, 1, 2, 3, 4
 MAX_DOF = 8
+NOALLOC_MAX_OBSTACLES = 4096      # EZO_NOALLOC_MAX_OBSTACLES
 
 EXPORTS = (
     "ezo_ctx_create", "ezo_ctx_destroy", "ezo_last_error", "ezo_set_obstacle_boxes", "ezo_robot_create",
     "ezo_robot_destroy",
-    "ezo_check_collisions", "ezo_sphere_centres", "ezo_test_constants", "ezo_sample_polytopes",
+    "ezo_check_collisions", "ezo_check_collisions_noalloc", "ezo_sphere_centres", "ezo_test_constants", "ezo_sample_polytopes",
     "ezo_test_and_select", "ezo_project_bisect", "ezo_place_hyperplanes", "ezo_inflate_edges", "ezo_inflate_paths",
     "ezo_set_phase_timing", "ezo_get_phase_timing",
     "ezo_surrogate_num_params", "ezo_surrogate_create", "ezo_surrogate_destroy", "ezo_surrogate_set_params",
@@ -95,6 +96,7 @@ def lib():
         L.ezo_robot_destroy.argtypes = [vp]
         L.ezo_robot_destroy.restype = None
         L.ezo_check_collisions.argtypes = [vp, vp, vp, i32, vp, i64, i64, i64, vp, vp, vp, vp]
+        L.ezo_check_collisions_noalloc.argtypes = [vp, vp, vp, i32, vp, i64, i64, i64, vp, vp, vp, vp]
         L.ezo_sphere_centres.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp]
         L.ezo_test_constants.argtypes = [dbl, dbl, dbl, i32, C.POINTER(i64), C.POINTER(i64)]
         L.ezo_sample_polytopes.argtypes = [vp, i32, vp, vp, vp, i32, vp, i32, i32, i32, u64, i64, i32, vp, i64, vp]
@@ -315,10 +317,12 @@ class Robot:
 
 
 def check_collisions(ctx: Context, robot: Robot, obs, q, flags, min_sd=None, min_sd_self=None,
-                     stride_n=None, stride_d=None, n=None, stream=None):
+                     stride_n=None, stride_d=None, n=None, stream=None, noalloc=False):
     """q: float32 CUDA tensor; by default [n][dof] (stride_n = dof,
     stride_d = 1).  flags: uint8 [n]; min_sd / min_sd_self: float32 [n] or
-    None (both None = flags only, early exit)."""
+    None (both None = flags only, early exit).  noalloc=True calls
+    ezo_check_collisions_noalloc (fixed device scratch, at most
+    EZO_NOALLOC_MAX_OBSTACLES obstacles)."""
     torch = _torch()
     _need(q, torch.float32, "q")
     if stride_n is None:
@@ -338,8 +342,9 @@ def check_collisions(ctx: Context, robot: Robot, obs, q, flags, min_sd=None, min
         _need(min_sd, torch.float32, "min_sd", n)
     if min_sd_self is not None:
         _need(min_sd_self, torch.float32, "min_sd_self", n)
-    ctx._check(lib().ezo_check_collisions(ctx.h, robot.h, _ptr(obs), n_obs, _ptr(q), n, stride_n, stride_d,
-                                          _ptr(flags), _ptr(min_sd), _ptr(min_sd_self), _stream(stream)))
+    fn = lib().ezo_check_collisions_noalloc if noalloc else lib().ezo_check_collisions
+    ctx._check(fn(ctx.h, robot.h, _ptr(obs), n_obs, _ptr(q), n, stride_n, stride_d,
+                  _ptr(flags), _ptr(min_sd), _ptr(min_sd_self), _stream(stream)))
 
 
 def sphere_centres(ctx: Context, robot: Robot, q, out, stream=None):

@@ -88,18 +88,14 @@ constexpr int kGridCap = 128;
 
 int grid_dim(int n_obs) { return n_obs >= 256 ? 32 : (n_obs >= 32 ? 16 : 8); }
 
-// Obstacle records, the frame shift and the broad-phase grid for one call.
-ezo_status prep_obstacles(ezo_ctx* c, const ezo_robot* r, const float* obs, int n_obs, hipStream_t st,
-                          ObsView* ov, GridView* gv) {
-    ezo_status s;
-    void *rec, *centre, *geom, *count, *list;
+// Obstacle records, the frame shift and the broad-phase grid for one call,
+// written to the given device buffers (every byte the kernels read later is
+// rewritten here: nothing needs to start at zero).
+ezo_status prep_obstacles_into(ezo_ctx* c, const ezo_robot* r, const float* obs, int n_obs, hipStream_t st,
+                               void* rec, void* centre, void* geom, void* count, void* list, ObsView* ov,
+                               GridView* gv) {
     const int G = grid_dim(n_obs);
     const size_t cells = (size_t)G * G * G;
-    if ((s = ezo_ws_get(c, W_OBS_REC, sizeof(float4) * (size_t)std::max(n_obs, 1), &rec)) != EZO_OK) return s;
-    if ((s = ezo_ws_get(c, W_OBS_CENTRE, sizeof(float4), &centre)) != EZO_OK) return s;
-    if ((s = ezo_ws_get(c, W_GRID_GEOM, sizeof(GridGeom), &geom)) != EZO_OK) return s;
-    if ((s = ezo_ws_get(c, W_GRID_COUNT, sizeof(int) * cells, &count)) != EZO_OK) return s;
-    if ((s = ezo_ws_get(c, W_GRID_LIST, sizeof(unsigned short) * cells * kGridCap, &list)) != EZO_OK) return s;
     hipLaunchKernelGGL(k_prep_obstacles, dim3(1), dim3(256), 0, st, obs, n_obs, (float4*)rec, (float4*)centre,
                        (GridGeom*)geom, G, r ? r->r_max : 0.f);
     hipLaunchKernelGGL(k_build_grid, dim3((unsigned)((cells * 64 + 255) / 256)), dim3(256), 0, st,
@@ -119,6 +115,52 @@ ezo_status prep_obstacles(ezo_ctx* c, const ezo_robot* r, const float* obs, int 
     gv->list = (const unsigned short*)list;
     gv->tests = nullptr;
     return EZO_OK;
+}
+
+// The same in the context's workspace.
+ezo_status prep_obstacles(ezo_ctx* c, const ezo_robot* r, const float* obs, int n_obs, hipStream_t st,
+                          ObsView* ov, GridView* gv) {
+    ezo_status s;
+    void *rec, *centre, *geom, *count, *list;
+    const size_t cells = (size_t)grid_dim(n_obs) * grid_dim(n_obs) * grid_dim(n_obs);
+    if ((s = ezo_ws_get(c, W_OBS_REC, sizeof(float4) * (size_t)std::max(n_obs, 1), &rec)) != EZO_OK) return s;
+    if ((s = ezo_ws_get(c, W_OBS_CENTRE, sizeof(float4), &centre)) != EZO_OK) return s;
+    if ((s = ezo_ws_get(c, W_GRID_GEOM, sizeof(GridGeom), &geom)) != EZO_OK) return s;
+    if ((s = ezo_ws_get(c, W_GRID_COUNT, sizeof(int) * cells, &count)) != EZO_OK) return s;
+    if ((s = ezo_ws_get(c, W_GRID_LIST, sizeof(unsigned short) * cells * kGridCap, &list)) != EZO_OK) return s;
+    return prep_obstacles_into(c, r, obs, n_obs, st, rec, centre, geom, count, list, ov, gv);
+}
+
+// ---------------------------------------------------------------------------
+// Fixed scratch of ezo_check_collisions_noalloc: the obstacle records, frame
+// shift, grid geometry, grid cell counts and cell lists of one call with up to
+// EZO_NOALLOC_MAX_OBSTACLES obstacles (grid of 32^3 cells).  A file-scope
+// device array: every device the library runs on holds one copy until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host that name is only a stand-in); it uses the device address taken with
+// hipGetSymbolAddress at context creation.
+// ---------------------------------------------------------------------------
+constexpr size_t kScrRec = 0;
+constexpr size_t kScrCentre = kScrRec + 16 * (size_t)EZO_NOALLOC_MAX_OBSTACLES;
+constexpr size_t kScrGeom = kScrCentre + 256;
+constexpr size_t kScrCount = kScrGeom + 256;
+constexpr size_t kScrCells = 32 * 32 * 32;
+constexpr size_t kScrList = kScrCount + sizeof(int) * kScrCells;
+constexpr size_t kScrBytes = kScrList + sizeof(unsigned short) * kScrCells * kGridCap;
+static_assert(sizeof(GridGeom) <= 256, "grid geometry slot");
+static_assert(kScrList % 256 == 0, "list slot alignment");
+
+static __device__ __align__(256) unsigned char scratch[kScrBytes];
+
+// Device address of this device's `scratch`; the device must be current.
+// Returns nullptr (and leaves no HIP error behind) when it cannot be taken.
+unsigned char* scratch_address() {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return static_cast<unsigned char*>(ptr);
 }
 
 bool pow2_tile(int T) { return T == 1 || T == 2 || T == 4 || T == 8 || T == 16 || T == 32 || T == 64; }
@@ -542,6 +584,9 @@ ezo_status ezo_ctx_create(int32_t device, ezo_ctx** out) {
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
         c->lds_cap = std::min<size_t>((size_t)lds, 65536);
+    // this device's copy of the no-allocation entry point's scratch (device
+    // current); nullptr makes that entry point report an error
+    c->scratch = scratch_address();
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
@@ -856,6 +901,36 @@ ezo_status ezo_check_collisions(ezo_ctx* c, const ezo_robot* r, const float* obs
                                   nullptr, it, st);
     }
     if ((s = tune_check_inplace<false>(c, r, ov, gv, q, n, stride_n, stride_d, flags, nullptr, nullptr, st))) return s;
+    return launch_check<false>(c, r, ov, gv, q, n, stride_n, stride_d, 0, flags, nullptr, nullptr, 0, 1, nullptr, it,
+                               st);
+}
+
+ezo_status ezo_check_collisions_noalloc(ezo_ctx* c, const ezo_robot* r, const float* obs, int32_t n_obs,
+                                        const float* q, int64_t n, int64_t stride_n, int64_t stride_d, uint8_t* flags,
+                                        float* min_sd, float* min_sd_self, void* stream) {
+    if (!c) return EZO_E_INVALID;
+    if (!r) return ezo_fail(c, EZO_E_INVALID, "robot is NULL");
+    if (n < 0 || n_obs < 0) return ezo_fail(c, EZO_E_INVALID, "negative size");
+    if (n_obs > EZO_NOALLOC_MAX_OBSTACLES)
+        return ezo_fail(c, EZO_E_CAPACITY, "%d obstacles exceed the fixed scratch of %d", n_obs,
+                        EZO_NOALLOC_MAX_OBSTACLES);
+    if (n == 0) return EZO_OK;
+    if (!q || !flags || (n_obs > 0 && !obs)) return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
+    if (!c->scratch) return ezo_fail(c, EZO_E_HIP, "the fixed scratch's device address is not available");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = as_stream(stream);
+    ObsView ov;
+    GridView gv;
+    unsigned char* p = c->scratch;
+    ezo_status s = prep_obstacles_into(c, r, obs, n_obs, st, p + kScrRec, p + kScrCentre, p + kScrGeom,
+                                       p + kScrCount, p + kScrList, &ov, &gv);
+    if (s) return s;
+    // launch shapes: the tuning cache or the size heuristic (never a timing
+    // search, which would write the outputs repeatedly)
+    IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
+    if (min_sd || min_sd_self)
+        return launch_check<true>(c, r, ov, gv, q, n, stride_n, stride_d, 0, flags, min_sd, min_sd_self, 0, 1,
+                                  nullptr, it, st);
     return launch_check<false>(c, r, ov, gv, q, n, stride_n, stride_d, 0, flags, nullptr, nullptr, 0, 1, nullptr, it,
                                st);
 }

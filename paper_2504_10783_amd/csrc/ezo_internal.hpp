@@ -55,6 +55,7 @@ struct ezo_ctx {
     const void* table_dev = nullptr;
     float4* ebox = nullptr;               // obstacle boxes [n_ebox][4] (packed like robot boxes), world frame
     int n_ebox = 0;
+    unsigned char* scratch = nullptr;     // device address of this device's fixed scratch (no-allocation calls)
 };
 
 struct ezo_robot {
