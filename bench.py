@@ -14,6 +14,15 @@ step time); `edges_per_s` is the same run's edges inflated per second.
 `roofline` reports the dominant kernel phase timed live with hipEvents on the
 stream it runs on; `cpu_baseline` times the FP64 reference on one full
 inflation of the same workload (rank 0 only).
+
+The default run (the 7-DOF edge) also carries the metric's other
+configurations as sub-objects of the same line (`--no-extras` leaves them
+out): `batched` (the 96 edges of 8 uneven paths in one call, the plain
+one-call-per-edge form at identical certification, its own roofline and CPU
+baseline), `sweep` (the raw checker at 16 M configurations x 256 / 1024 /
+4096 obstacles, flags and signed distances) and `screen` (the learned
+self-collision screen against the exact form on the batched workload).
+Progress lines go to stderr.
 """
 import argparse
 import json
@@ -41,7 +50,8 @@ WORKLOADS = {
 }
 
 
-KERNEL_SOURCES = ("paper_2504_10783_amd/csrc/ezo_device.hpp", "paper_2504_10783_amd/csrc/ezo_kernels.hpp")
+KERNEL_SOURCES = ("paper_2504_10783_amd/csrc/ezo_device.hpp", "paper_2504_10783_amd/csrc/ezo_kernels.hpp",
+                  "paper_2504_10783_amd/csrc/ezo_screen.hpp")
 
 
 def kernel_source_sha256():
@@ -146,6 +156,19 @@ def timed_shapes(ezo, rob, n_obs, prm, n_p, E):
     return out
 
 
+def cpu_model():
+    """The host CPU's model name (lscpu's "Model name", from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.lower().startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(name, data, desc, seed, edges_idx, n_p=None):
     import numpy as np
     import oracle
@@ -174,7 +197,7 @@ def cpu_baseline(name, data, desc, seed, edges_idx, n_p=None):
         dt1 = time.perf_counter() - t1
     finally:
         oracle.set_threads(cores)
-    return {"value": checks / dt, "unit": "configs/s", "cores": cores, "kind": "oracle",
+    return {"value": checks / dt, "unit": "configs/s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"FP64 reference EI-ZO on {len(edges_idx)} edge(s) of the '{name}' workload "
                       f"(seed {seed}, N_p {n_p or workloads.PARAMS[name]['n_p']}): {checks} exact checks "
                       f"in {dt:.2f} s; one thread: edge {e}, {out['stats']['checks']} checks in {dt1:.2f} s",
@@ -182,11 +205,12 @@ def cpu_baseline(name, data, desc, seed, edges_idx, n_p=None):
             "value_1thread": out["stats"]["checks"] / dt1}
 
 
-def sweep(args):
+def sweep_measure(args, sizes, reps_cap=None):
     """Raw checker throughput: N uniform configurations x n_obs obstacles,
     flags + minimum signed distance (all pairs) and flags only (broad phase).
-    Inputs resident in HBM; hipEvent-free wall timing around synchronised
-    repetitions (the checker runs on torch's current stream)."""
+    Inputs resident in HBM; wall timing around synchronised repetitions (the
+    checker runs on torch's current stream).  Returns (points, cpu baseline
+    or None, the tuner's cache entries)."""
     import numpy as np
     import torch
 
@@ -200,7 +224,6 @@ def sweep(args):
     rob = ezo.Robot(ctx, desc)
     dev = torch.device("cuda", 0)
     points = []
-    sizes = [int(x) for x in args.sweep_sizes.split(",")]
     qmax = torch.from_numpy(draw.uniform_q_fast(303, max(sizes), data["q_lo"], data["q_hi"])).to(dev)
     for n_obs in (256, 1024, 4096):
         obs = torch.from_numpy(data[f"obstacles_{n_obs}"]).to(dev)
@@ -215,6 +238,8 @@ def sweep(args):
                 run()
                 torch.cuda.synchronize()
                 reps = max(1, min(args.steps, int(2e8 // n)))
+                if reps_cap:
+                    reps = min(reps, reps_cap)
                 t0 = time.perf_counter()
                 for _ in range(reps):
                     run()
@@ -229,7 +254,6 @@ def sweep(args):
                     row["collision_fraction"] = float(flags.float().mean().item())
             points.append(row)
             print(json.dumps(row), file=sys.stderr, flush=True)
-    best = max(points, key=lambda r: r["n"] * (r["n_obs"] == 4096))
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -249,17 +273,26 @@ def sweep(args):
             one = (1 << 12) / (time.perf_counter() - t0)
         finally:
             oracle.set_threads(cores)
-        cpu = {"value": cpu[4096], "unit": "configs/s", "cores": cores, "kind": "oracle",
+        cpu = {"value": cpu[4096], "unit": "configs/s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
                "sample": "FP64 reference checker (flags and signed distances, all pairs) on the first 65 536 "
                          "configurations at 256 / 1024 / 4096 obstacles; one thread: 4 096 configurations at 4096",
                "configs_per_s_by_obstacles": cpu, "value_1thread": one}
+    return points, cpu, ezo.tune_cache_entries()
+
+
+SWEEP_CONFIG = ("sweep: 7-DOF arm (70 spheres, 1500 self pairs), N uniform configurations in the joint limits, "
+                "obstacles in [0.3,1.3]x[-0.5,0.5]x[0,1] m, r U[0.02,0.08]; flags (exact broad phase) and "
+                "flags + minimum signed distance (all pairs)")
+
+
+def sweep(args):
+    sizes = [int(x) for x in args.sweep_sizes.split(",")]
+    points, cpu, shapes = sweep_measure(args, sizes)
+    best = max(points, key=lambda r: r["n"] * (r["n_obs"] == 4096))
     line = {"metric": "collision-checked configs/sec (raw checker sweep, 7-DOF, 70 spheres, 1500 self pairs)",
             "value": best["sd_configs_per_s"], "unit": "configs/s", "n_gpus": 1, "steps": args.steps,
             "warmup": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-            "data": "synthetic", "config": {"workload": "sweep: uniform q in joint limits, obstacles in "
-                                            "[0.3,1.3]x[-0.5,0.5]x[0,1] m, r U[0.02,0.08]"},
-            "points": points,
-            "launch_shapes": ezo.tune_cache_entries()}
+            "data": "synthetic", "config": {"workload": SWEEP_CONFIG}, "points": points, "launch_shapes": shapes}
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
@@ -279,10 +312,11 @@ def copy_calibration(args):
     print(json.dumps({"copy_bytes_per_dispatch": 4 * n, "dispatches": max(args.steps, 1)}), flush=True)
 
 
-def screen_compare(args):
-    """Learned screen: train on exact self-collision labels, calibrate, then
-    time the inflation with and without the screen at identical
-    eps/delta/tau/seed."""
+def screen_measure(args, name, epochs):
+    """Learned screen: exact self-collision labels of 4 M uniform
+    configurations, training, calibration at alpha = 1e-3, then the inflation
+    of `name` timed with and without the screen at identical
+    eps/delta/tau/seed/N_p.  Returns a dict."""
     import numpy as np
     import torch
 
@@ -290,13 +324,13 @@ def screen_compare(args):
     import workloads
     from workloads import draw
 
-    name = args.workload
     data = workloads.load(name)
     desc = workloads.robot(data)
     ctx = ezo.Context(0)
     rob = ezo.Robot(ctx, desc)
     dev = torch.device("cuda", 0)
     n_tr, n_cal, n_te = 3_600_000 // 4096 * 4096, 200_000, 200_000
+    alpha = 1e-3
     t0 = time.perf_counter()
     q = torch.from_numpy(draw.uniform_q_fast(404, n_tr + n_cal + n_te, data["q_lo"], data["q_hi"])).to(dev)
     n = q.shape[0]
@@ -307,12 +341,15 @@ def screen_compare(args):
     torch.cuda.synchronize()
     t_lab = time.perf_counter() - t0
     sur = ezo.Surrogate(ctx, rob.dof, 256, seed=args.seed)
-    tp = ezo.make_train_params(epochs=args.screen_epochs, batch=4096, lr=1e-3, seed=args.seed)
+    tp = ezo.make_train_params(epochs=epochs, batch=4096, lr=1e-3, seed=args.seed)
     t0 = time.perf_counter()
     losses = sur.train(q[:n_tr], lab[:n_tr], tp)
+    torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    margin = sur.calibrate(q[n_tr:n_tr + n_cal], lab[n_tr:n_tr + n_cal], 1e-3)
+    margin = sur.calibrate(q[n_tr:n_tr + n_cal], lab[n_tr:n_tr + n_cal], alpha)
     miss, frac = sur.miss_rate(q[n_tr + n_cal:], lab[n_tr + n_cal:])
+    print(json.dumps({"screen_trained": {"train_s": t_train, "margin": margin, "miss_rate": miss}}),
+          file=sys.stderr, flush=True)
     obs = torch.from_numpy(data["obstacles"]).to(dev)
     edges = torch.from_numpy(data["edges"]).to(dev)
     E = edges.shape[0]
@@ -324,7 +361,7 @@ def screen_compare(args):
     res = {}
     for mode in ("exact", "screened"):
         prm = ezo.make_params(dof=rob.dof, seed=args.seed, surrogate=sur if mode == "screened" else None, **wp)
-        for _ in range(args.warmup):
+        for _ in range(max(args.warmup, 1)):
             ezo.inflate_edges(ctx, rob, obs, edges, prm)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -338,17 +375,27 @@ def screen_compare(args):
         st = r.status.cpu().numpy()
         res[mode] = {"ms_per_step": dt * 1e3, "edges_per_s": E / dt, "configs_per_s": checks / args.steps / dt,
                      "screened_fraction_of_checks": screened / max(checks, 1),
-                     "certified": int(np.sum(st == 0)), "iterations_mean": float(np.mean([x["iterations"] for x in r.stats])),
+                     "certified": int(np.sum(st == 0)),
+                     "iterations_mean": float(np.mean([x["iterations"] for x in r.stats])),
                      "planes_mean": float(np.mean([x["planes"] for x in r.stats]))}
-    line = {"metric": "edges inflated/sec, learned self-collision screen vs exact (7-DOF)",
-            "value": res["screened"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f32 checks, bf16 MFMA screen", "data": "synthetic",
-            "config": {"workload": f"{name}: {WORKLOADS[name]}", "labels": n, "train": n_tr, "calibration": n_cal,
-                       "test": n_te, "alpha": 1e-3, "epochs": args.screen_epochs, "n_p": wp["n_p"]},
+    return {"workload": f"{name}: {WORKLOADS[name]}", "edges": E, "labels": n, "train": n_tr, "calibration": n_cal,
+            "test": n_te, "alpha": alpha, "epochs": epochs, "n_p": wp["n_p"],
+            "eps": wp["eps"], "delta": wp["delta"], "tau": wp["tau"],
             "speedup_vs_exact": res["screened"]["edges_per_s"] / res["exact"]["edges_per_s"],
             "miss_rate_test": miss, "screened_fraction_test": frac, "margin": margin,
-            "label_seconds": t_lab, "train_seconds": t_train, "epoch_losses": losses, **res}
+            "label_seconds": t_lab, "train_seconds": t_train,
+            "train_samples_per_s": n_tr * epochs / t_train, "epoch_losses": losses, **res}
+
+
+def screen_compare(args):
+    r = screen_measure(args, args.workload, args.screen_epochs)
+    line = {"metric": "edges inflated/sec, learned self-collision screen vs exact (7-DOF)",
+            "value": r["screened"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32 checks, bf16 MFMA screen", "data": "synthetic",
+            "config": {"workload": r["workload"], "labels": r["labels"], "train": r["train"],
+                       "calibration": r["calibration"], "test": r["test"], "alpha": r["alpha"],
+                       "epochs": r["epochs"], "n_p": r["n_p"]}, **r}
     print(json.dumps(line), flush=True)
 
 
@@ -693,75 +740,17 @@ def forest(args):
     print(json.dumps(line), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="dof7", choices=sorted(WORKLOADS) + ["sweep"])
-    ap.add_argument("--sweep-sizes", default="1048576,4194304,16777216")
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true",
-                    help="skip the comparison runs after the timed region (one call per edge; the paper's N_p)")
-    ap.add_argument("--samples", type=samples_arg, default=None,
-                    help="N_p of the inflation: 'paper' (the paper's table value), 'tuned' (chosen by the "
-                         "sample-count tuner, n_p = 0) or a count; default tuned for the batched workload, "
-                         "paper otherwise")
-    ap.add_argument("--screen", action="store_true", help="learned screen vs exact comparison")
-    ap.add_argument("--screen-epochs", type=int, default=10)
-    ap.add_argument("--recovery", action="store_true", help="trajectory check + set update + containment timings")
-    ap.add_argument("--paths", action="store_true", help="sequential path inflation vs independent edges")
-    ap.add_argument("--box-sweep", action="store_true", help="raw checker throughput of the box arm")
-    ap.add_argument("--drm-map", action="store_true", help="DRM collision map of a 35 000-node roadmap")
-    ap.add_argument("--forest", action="store_true", help="Forest scene: raw checker and path inflation")
-    ap.add_argument("--no-autotune", action="store_true", help="size-heuristic launch shapes (no tuning)")
-    ap.add_argument("--tune-import", default=None,
-                    help="JSON-lines tuning cache to load before the run (profiled runs replay the shapes and "
-                         "sample count an unprofiled run picked; timing under a profiler distorts the tuner)")
-    ap.add_argument("--tune-export", default=None, help="write the tuning cache after the run")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
-    args = ap.parse_args()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the EI-ZO path of this library runs on a single MI355X "
-              "(edges shard across GPUs with no exchange; multi-GPU runs are not part of this build)",
-              file=sys.stderr)
-        sys.exit(2)
-
-    if args.copy_calibration:
-        copy_calibration(args)
-        return
-    if args.workload == "sweep":
-        sweep(args)
-        return
-    if args.screen:
-        screen_compare(args)
-        return
-    if args.recovery:
-        recovery(args)
-        return
-    if args.paths:
-        paths_compare(args)
-        return
-    if args.box_sweep:
-        box_sweep(args)
-        return
-    if args.drm_map:
-        drm_map(args)
-        return
-    if args.forest:
-        forest(args)
-        return
-
+def inflation_measure(args, name, plain=True, cpu=True):
+    """One workload's inflation measured as bench.py's main line: the timed
+    steps (graph replay), a phase pass with dispatch events for the roofline,
+    optionally the plain one-call-per-edge form and the paper's N_p (E > 1),
+    and the oracle's CPU baseline.  Returns the line as a dict."""
     import numpy as np
     import torch
 
     import paper_2504_10783_amd as ezo
     import workloads
 
-    name = args.workload
     data = workloads.load(name)
     desc = workloads.robot(data)
     ctx = ezo.Context(0)
@@ -836,7 +825,7 @@ def main():
     box = "true" if (rob.n_boxes > 0 or "env_boxes" in data) else "false"
     if dom == "bisect":
         sb = shapes.get("bisect")
-        instance = f"ezo::k_project_bisect<{sb['T']}, {sb['depth']}, {box}>" if sb else None
+        instance = f"ezo::k_project_bisect<{sb['T']}, {sb['depth']}, {box}, false>" if sb else None
     else:
         sc = shapes.get("check_flags")
         instance = f"ezo::k_check<{sc['T']}, false, {box}>" if sc else None
@@ -892,7 +881,7 @@ def main():
         "launch_shapes": [{k: e[k] for k in ("kernel", "log2_items", "T", "W", "stage", "depth", "us")}
                           for e in shapes.values()],
     }
-    if E > 1 and not args.no_plain:
+    if E > 1 and plain:
         # the plain GPU form: the same edges, one call per edge (edge e draws
         # the stream of edge id e in both forms, so the sets are identical),
         # after the timed region
@@ -917,7 +906,7 @@ def main():
         line["plain"] = {"ms_per_step": dt1 * 1e3, "edges_per_s": E / dt1, "configs_per_s": checks1 / reps / dt1,
                          "calls_per_step": E, "equal_to_batched": bool(same)}
         line["batched_speedup_vs_plain"] = (E / (dt / args.steps)) / (E / dt1)
-    if samples_mode == "tuned" and n_p_used != workloads.PARAMS[name]["n_p"] and not args.no_plain:
+    if samples_mode == "tuned" and n_p_used != workloads.PARAMS[name]["n_p"] and plain:
         # the same batched call with the paper's N_p (same eps, delta, tau):
         # what the tuned sample count gains; the sets differ, the certificate
         # does not
@@ -935,12 +924,98 @@ def main():
                              "iterations_mean": float(np.mean([x["iterations"] for x in r.stats])),
                              "planes_mean": float(np.mean([x["planes"] for x in r.stats]))}
         line["tuned_speedup_vs_paper_n_p"] = dt3 / (dt / args.steps)
-    if args.tune_export:
-        with open(args.tune_export, "w") as f:
-            f.write(ezo.tune_cache_export())
-    if not args.no_cpu_baseline:
+    if cpu:
         idx = [0] if E == 1 else sorted({int(np.nonzero(data["path_id"] == p)[0][0]) for p in np.unique(data["path_id"])})
         line["cpu_baseline"] = cpu_baseline(name, data, desc, args.seed, idx, n_p_used)
+    return line
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="dof7", choices=sorted(WORKLOADS) + ["sweep"])
+    ap.add_argument("--sweep-sizes", default="1048576,4194304,16777216")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the comparison runs after the timed region (one call per edge; the paper's N_p)")
+    ap.add_argument("--samples", type=samples_arg, default=None,
+                    help="N_p of the inflation: 'paper' (the paper's table value), 'tuned' (chosen by the "
+                         "sample-count tuner, n_p = 0) or a count; default tuned for the batched workload, "
+                         "paper otherwise")
+    ap.add_argument("--screen", action="store_true", help="learned screen vs exact comparison")
+    ap.add_argument("--screen-epochs", type=int, default=10)
+    ap.add_argument("--recovery", action="store_true", help="trajectory check + set update + containment timings")
+    ap.add_argument("--paths", action="store_true", help="sequential path inflation vs independent edges")
+    ap.add_argument("--box-sweep", action="store_true", help="raw checker throughput of the box arm")
+    ap.add_argument("--drm-map", action="store_true", help="DRM collision map of a 35 000-node roadmap")
+    ap.add_argument("--forest", action="store_true", help="Forest scene: raw checker and path inflation")
+    ap.add_argument("--no-autotune", action="store_true", help="size-heuristic launch shapes (no tuning)")
+    ap.add_argument("--tune-import", default=None,
+                    help="JSON-lines tuning cache to load before the run (profiled runs replay the shapes and "
+                         "sample count an unprofiled run picked; timing under a profiler distorts the tuner)")
+    ap.add_argument("--tune-export", default=None, help="write the tuning cache after the run")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="dof7: only the main line (no batched / sweep / screen sub-objects)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the EI-ZO path of this library runs on a single MI355X "
+              "(edges shard across GPUs with no exchange; multi-GPU runs are not part of this build)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(args)
+        return
+    if args.workload == "sweep":
+        sweep(args)
+        return
+    if args.screen:
+        screen_compare(args)
+        return
+    if args.recovery:
+        recovery(args)
+        return
+    if args.paths:
+        paths_compare(args)
+        return
+    if args.box_sweep:
+        box_sweep(args)
+        return
+    if args.drm_map:
+        drm_map(args)
+        return
+    if args.forest:
+        forest(args)
+        return
+
+    name = args.workload
+    line = inflation_measure(args, name, plain=not args.no_plain, cpu=not args.no_cpu_baseline)
+    if name == "dof7" and not args.no_extras:
+        # the other configurations the metric is quoted on, as sub-objects of
+        # the same line: the batched workload (with the plain form and its own
+        # roofline), the raw checker sweep at 16 M configurations, and the
+        # learned screen against the exact form
+        print(json.dumps({"progress": "dof7 done", "ms_per_step": line["ms_per_step"]}), file=sys.stderr, flush=True)
+        line["batched"] = inflation_measure(args, "batched", plain=True, cpu=not args.no_cpu_baseline)
+        for k in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data", "dtype"):
+            line["batched"].pop(k, None)
+        print(json.dumps({"progress": "batched done", "edges_per_s": line["batched"]["edges_per_s"]}),
+              file=sys.stderr, flush=True)
+        points, cpu, _ = sweep_measure(args, [1 << 24], reps_cap=3)
+        line["sweep"] = {"config": SWEEP_CONFIG, "points": points}
+        if cpu is not None:
+            line["sweep"]["cpu_baseline"] = cpu
+        print(json.dumps({"progress": "sweep done"}), file=sys.stderr, flush=True)
+        line["screen"] = screen_measure(args, "batched", args.screen_epochs)
+    if args.tune_export:
+        with open(args.tune_export, "w") as f:
+            f.write(__import__("paper_2504_10783_amd").tune_cache_export())
     print(json.dumps(line), flush=True)
 
 

@@ -127,6 +127,14 @@ typedef struct {
                                 pairs of samples after the first M_k (never of
                                 the test samples) whose predicted self distance
                                 is >= the screen's calibrated margin           */
+    float *row_points;       /* dev f32 [E][face_capacity][dof] or NULL (caller-
+                                owned).  ezo_inflate_edges writes, for every
+                                hyperplane row f >= 2 dof it
+                                places, the collision point c* that row was
+                                placed for (Sec. IV-C: the row is a^T x <=
+                                a^T c* - Delta with Delta > 0, so it excludes
+                                c*); box rows and rows past n_faces are left
+                                untouched.  Ignored by ezo_inflate_paths */
 } ezo_params;
 
 typedef struct {

@@ -60,7 +60,7 @@ class Params(C.Structure):
                 ("step_back_max", C.c_double), ("t_col", C.c_double), ("n_p", C.c_int32),
                 ("n_f", C.c_int32), ("n_b", C.c_int32), ("n_mix", C.c_int32), ("max_iters", C.c_int32),
                 ("face_capacity", C.c_int32), ("seed", C.c_uint64), ("edge_id_base", C.c_int64),
-                ("surrogate", C.c_void_p)]
+                ("surrogate", C.c_void_p), ("row_points", C.c_void_p)]
 
 
 class TrainParams(C.Structure):
@@ -420,7 +420,7 @@ def make_params(eps, delta, tau=0.5, step_back_max=0.01, t_col=1e-4, n_p=1000, n
     if face_capacity is None:
         face_capacity = 2 * (dof or MAX_DOF) + n_f * max_iters
     return Params(eps, delta, tau, step_back_max, t_col, n_p, n_f, n_b, n_mix, max_iters, face_capacity, seed,
-                  edge_id_base, surrogate.h.value if surrogate is not None else None)
+                  edge_id_base, surrogate.h.value if surrogate is not None else None, None)
 
 
 def make_train_params(epochs=10, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, huber_delta=0.05,
@@ -508,15 +508,24 @@ class Surrogate:
         return miss.value, frac.value
 
 
-def inflate_edges(ctx: Context, robot: Robot, obs, edges, params: Params, out=None, stream=None) -> InflateResult:
+def inflate_edges(ctx: Context, robot: Robot, obs, edges, params: Params, out=None, stream=None,
+                  row_points=None) -> InflateResult:
     """edges: float32 CUDA tensor [E][2][dof].  Returns device tensors A, b,
-    n_faces, status and host per-edge stats."""
+    n_faces, status and host per-edge stats.  row_points (optional float32
+    CUDA tensor [E][face_capacity][dof]) receives the collision point each
+    placed hyperplane row was placed for."""
     torch = _torch()
     _need(edges, torch.float32, "edges")
     _need(obs, torch.float32, "obs")
     E = edges.shape[0]
     cap = params.face_capacity
     dev = edges.device
+    if row_points is not None:
+        _need(row_points, torch.float32, "row_points")
+        if row_points.numel() < E * cap * robot.dof:
+            raise ValueError("row_points smaller than [E][face_capacity][dof]")
+        params = Params.from_buffer_copy(params)
+        params.row_points = row_points.data_ptr()
     if out is None:
         out = InflateResult(torch.empty((E, cap, robot.dof), dtype=torch.float32, device=dev),
                             torch.empty((E, cap), dtype=torch.float32, device=dev),

@@ -385,7 +385,8 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
                                  const float* S, int64_t stride, const int* cand_idx, const int* n_cands,
                                  int cand_cap, int n_b, float* c_star, float* a_dir, float* t_star,
                                  uint8_t* pcol, uint8_t* pany, const int* status, hipStream_t st,
-                                 const TileCfg* shape = nullptr, int64_t s_edge = -1) {
+                                 const TileCfg* shape = nullptr, int64_t s_edge = -1, const MlpView* screen = nullptr,
+                                 EdgeStatsDev* stats = nullptr) {
     if (s_edge < 0) s_edge = (int64_t)r->dof * stride;   // samples [E][dof][stride]
     TileCfg g;
     if (shape) {
@@ -395,24 +396,60 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
         g = resolve_cfg(c, tune_key(c, r, TUNE_BISECT, ov.n, items), heuristic_bisect(c, r, ov.n, items), r->slots,
                         ov.n, false, true);
     }
+    const bool box = r->B > 0 || ov.n_ebox > 0;
+    // the screened form (sphere robots): one bisection level per round, at
+    // most 16 points per tile, at least four waves (the network's layers)
+    const bool scr = screen && screen->P && !box;
+    if (scr) {
+        g.depth = 1;
+        g.T = std::min(std::max(g.T, 2), 16);
+        g.W = std::max(g.W, 4);
+    }
     const int TC = g.T, W = g.W, dp = g.depth;
     if (!bisect_shape_built(g) || W < 1 || W > 16)
         return ezo_fail(c, EZO_E_INVALID, "bisection shape T=%d W=%d depth=%d", TC, W, dp);
     ObsView ovs = ov;
     ovs.lds_n = g.stage ? ov.n : 0;
-    const size_t lds = tile_smem_bytes(tile_configs(g, true), r->slots, W) + 16 * (size_t)ovs.lds_n +
-                       robot_stage_bytes(r->slots);
+    size_t lds = tile_smem_bytes(tile_configs(g, true), r->slots, W) + 16 * (size_t)ovs.lds_n +
+                 robot_stage_bytes(r->slots);
+    if (scr) {
+        lds += mlp_tile_smem_bytes(1) + 16 * sizeof(float);
+        if (lds > c->lds_cap && ovs.lds_n > 0) {        // drop the obstacle staging first
+            lds -= 16 * (size_t)ovs.lds_n;
+            ovs.lds_n = 0;
+        }
+    }
     if (lds > c->lds_cap) return ezo_fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
     dim3 grid((unsigned)((cand_cap + TC - 1) / TC), (unsigned)E), block(64 * W);
-    const bool box = r->B > 0 || ov.n_ebox > 0;
+    const MlpView mv = scr ? *screen : MlpView{0, 0, nullptr, nullptr, nullptr, 0.f};
+    if (scr) {
+        switch (TC) {
+            case 16: EZO_KLAUNCH(c, (k_project_bisect<16, 1, false, true>), grid, block, lds, st, r->view, ovs, gv,
+                                 edges, S, stride, s_edge, cand_idx, n_cands, cand_cap, n_b, c_star, a_dir, t_star,
+                                 pcol, pany, status, mv, stats); break;
+            case 8: EZO_KLAUNCH(c, (k_project_bisect<8, 1, false, true>), grid, block, lds, st, r->view, ovs, gv,
+                                edges, S, stride, s_edge, cand_idx, n_cands, cand_cap, n_b, c_star, a_dir, t_star,
+                                pcol, pany, status, mv, stats); break;
+            case 4: EZO_KLAUNCH(c, (k_project_bisect<4, 1, false, true>), grid, block, lds, st, r->view, ovs, gv,
+                                edges, S, stride, s_edge, cand_idx, n_cands, cand_cap, n_b, c_star, a_dir, t_star,
+                                pcol, pany, status, mv, stats); break;
+            default: EZO_KLAUNCH(c, (k_project_bisect<2, 1, false, true>), grid, block, lds, st, r->view, ovs, gv,
+                                 edges, S, stride, s_edge, cand_idx, n_cands, cand_cap, n_b, c_star, a_dir, t_star,
+                                 pcol, pany, status, mv, stats); break;
+        }
+        HIP_TRY(c, hipGetLastError());
+        return EZO_OK;
+    }
 #define EZO_LAUNCH_PB(TT, DD)                                                                                       \
     do {                                                                                                            \
         if (box)                                                                                                    \
             EZO_KLAUNCH(c, (k_project_bisect<TT, DD, true>), grid, block, lds, st, r->view, ovs, gv, edges, S, stride, \
-                        s_edge, cand_idx, n_cands, cand_cap, n_b, c_star, a_dir, t_star, pcol, pany, status);         \
+                        s_edge, cand_idx, n_cands, cand_cap, n_b, c_star, a_dir, t_star, pcol, pany, status, mv,     \
+                        stats);                                                                                     \
         else                                                                                                        \
             EZO_KLAUNCH(c, (k_project_bisect<TT, DD, false>), grid, block, lds, st, r->view, ovs, gv, edges, S,       \
-                        stride, s_edge, cand_idx, n_cands, cand_cap, n_b, c_star, a_dir, t_star, pcol, pany, status); \
+                        stride, s_edge, cand_idx, n_cands, cand_cap, n_b, c_star, a_dir, t_star, pcol, pany, status, \
+                        mv, stats);                                                                                 \
     } while (0)
     if (dp == 1) {
         switch (TC) {
@@ -745,6 +782,31 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     }
     if (blocks.empty()) blocks.push_back(make_int4(0, 0, 0, 0));
     const int NB = P > 0 ? (int)blocks.size() : 0;
+    // a block whose two links hold n_i n_j <= 128 sphere pairs is also kept as
+    // a bit mask over that product (bit a n_j + b: sphere a of link i with
+    // sphere b of link j), so the sweep derives each pair's spheres from its
+    // lane instead of loading the pair list; zero mask = list only
+    std::vector<uint4> bmask(blocks.size(), make_uint4(0u, 0u, 0u, 0u));
+    {
+        auto link_of = [&](int sorted) {
+            int j = 0;
+            while (j + 1 < dof && link_begin[j + 1] <= sorted) ++j;
+            return j;
+        };
+        for (int k = 0; k < NB; ++k) {
+            const int li = blocks[k].x, lj = blocks[k].y;
+            const int ni = link_begin[li + 1] - link_begin[li], nj = link_begin[lj + 1] - link_begin[lj];
+            if (ni * nj > 128 || ni < 1 || nj < 1) continue;
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+            for (int q = blocks[k].z; q < blocks[k].z + blocks[k].w; ++q) {
+                int a = pairs[q].x, bq = pairs[q].y;
+                if (link_of(a) != li) std::swap(a, bq);
+                const int bit = (a - link_begin[li]) * nj + (bq - link_begin[lj]);
+                w[bit >> 5] |= 1u << (bit & 31);
+            }
+            bmask[k] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
     // bounding sphere of each link's spheres (link frame): centre of the
     // centres' box, radius = max distance + sphere radius
     std::vector<float4> lbound(dof, make_float4(0.f, 0.f, 0.f, 0.f));
@@ -792,6 +854,7 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     for (int j = 0; j < dof; ++j) box_begin[j + 1] += box_begin[j];
     for (int p = 0; p < Q; ++p) bpairs[p] = make_int2(box_o2s[d->box_pairs[2 * p]], box_o2s[d->box_pairs[2 * p + 1]]);
     // one allocation: [dh][sph][pairs][lbound][blocks][link_begin][s2o][limits][boxes][box_begin][box pairs]
+    // [block masks]
     size_t off_dh = 0;
     size_t off_sph = off_dh + sizeof(float4) * dof;
     size_t off_pairs = off_sph + sizeof(float4) * sph.size();
@@ -803,7 +866,8 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     size_t off_box = (off_lim + sizeof(float) * lim.size() + 15) & ~(size_t)15;
     size_t off_bb = off_box + sizeof(float4) * boxv.size();
     size_t off_bp = off_bb + sizeof(int) * box_begin.size();
-    size_t total = off_bp + sizeof(int2) * bpairs.size();
+    size_t off_bm = (off_bp + sizeof(int2) * bpairs.size() + 15) & ~(size_t)15;
+    size_t total = off_bm + sizeof(uint4) * bmask.size();
     std::vector<char> host(total);
     memcpy(host.data() + off_dh, dh.data(), sizeof(float4) * dof);
     memcpy(host.data() + off_sph, sph.data(), sizeof(float4) * sph.size());
@@ -816,6 +880,7 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     memcpy(host.data() + off_box, boxv.data(), sizeof(float4) * boxv.size());
     memcpy(host.data() + off_bb, box_begin.data(), sizeof(int) * box_begin.size());
     memcpy(host.data() + off_bp, bpairs.data(), sizeof(int2) * bpairs.size());
+    memcpy(host.data() + off_bm, bmask.data(), sizeof(uint4) * bmask.size());
     HIP_TRY(c, hipSetDevice(c->device));
     void* buf = nullptr;
     if (hipMalloc(&buf, total) != hipSuccess) return ezo_fail(c, EZO_E_NOMEM, "robot allocation failed");
@@ -843,6 +908,7 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     r->view.n_blocks = NB;
     r->view.lbound = reinterpret_cast<const float4*>(b + off_lbd);
     r->view.blocks = reinterpret_cast<const int4*>(b + off_blk);
+    r->view.bmask = reinterpret_cast<const uint4*>(b + off_bm);
     r->view.dh = reinterpret_cast<const float4*>(b + off_dh);
     r->view.sph = reinterpret_cast<const float4*>(b + off_sph);
     r->view.pairs = reinterpret_cast<const int2*>(b + off_pairs);
@@ -1047,7 +1113,7 @@ ezo_status ezo_place_hyperplanes(ezo_ctx* c, int32_t dof, const float* edges, in
     HIP_TRY(c, hipSetDevice(c->device));
     hipLaunchKernelGGL(k_place, dim3(n_edges), dim3(1024), (size_t)std::max(cand_capacity, 16), as_stream(stream), dof,
                        edges, c_star, a_dir, t_star, n_cands, cand_capacity, n_f, (float)step_back_max, (float)t_col, A,
-                       b, n_faces, face_capacity, edge_status, placed_idx, n_placed, nullptr, nullptr);
+                       b, n_faces, face_capacity, edge_status, placed_idx, n_placed, nullptr, nullptr, nullptr);
     HIP_TRY(c, hipGetLastError());
     return EZO_OK;
 }
@@ -1106,6 +1172,7 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
                     ezo_params q = *p;
                     q.n_p = t.T;
                     q.seed = tune_seed;
+                    q.row_points = nullptr;
                     return inflate_core(c, r, obs, n_obs, edges, n_edges, &q, A, b, n_faces, edge_status, nullptr,
                                         c->stream, edge_ids, skip);
                 };
@@ -1182,6 +1249,13 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
                        n_faces, cap, edge_status, (EdgeStatsDev*)w_st, (uint8_t*)w_pa, (int*)w_k, (int*)w_ac, skip);
     HIP_TRY(c, hipGetLastError());
     IterArgs it{(const int*)w_k, (const int4*)w_tb, 0, 0, 0, 0};
+    // the learned screen inside the loop: the fused forward pass for widths
+    // up to kMlpMaxH (a multiple of 16), else the layer-by-layer kernels
+    // (samples only)
+    const ezo_surrogate* sur = p->surrogate;
+    const bool fused_screen = sur && sur->H <= kMlpMaxH && sur->H % 16 == 0;
+    const MlpView screen_view = sur ? MlpView{sur->D, sur->H, sur->P, sur->W2b, sur->W3b, sur->margin}
+                                    : MlpView{0, 0, nullptr, nullptr, nullptr, 0.f};
     const uint32_t k0 = (uint32_t)p->seed, k1 = (uint32_t)(p->seed >> 32);
     (void)k0;
     (void)k1;
@@ -1205,7 +1279,13 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
             mark(EZO_NUM_PHASES);
             return ls;
         }
-        if (p->surrogate) {
+        if (p->surrogate && fused_screen) {
+            // predictions for the rows the screen may skip, [M_k, |S|) of
+            // every running edge, one fused forward pass per 64 rows
+            EZO_KLAUNCH(c, k_screen_samples, dim3((unsigned)((S_cap + kScreenRows - 1) / kScreenRows), (unsigned)E),
+                        dim3(256), 0, st, screen_view, (const float*)w_s, stride, dof, (float*)w_pred, edge_status,
+                        it);
+        } else if (p->surrogate) {
             RowSource src{};
             src.q = (const float*)w_s;
             src.sn = 1;
@@ -1237,7 +1317,8 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         mark(EZO_PHASE_BISECT);
         if ((ls = launch_project_bisect(c, r, ov, gvb, edges, E, (const float*)w_s, stride, (const int*)w_ci,
                                         (const int*)w_nc, cand_cap, p->n_b, (float*)w_cs, (float*)w_ad,
-                                        (float*)w_ts, (uint8_t*)w_pc, (uint8_t*)w_pa, edge_status, st))) {
+                                        (float*)w_ts, (uint8_t*)w_pc, (uint8_t*)w_pa, edge_status, st, nullptr, -1,
+                                        fused_screen ? &screen_view : nullptr, (EdgeStatsDev*)w_st))) {
             mark(EZO_NUM_PHASES);
             return ls;
         }
@@ -1245,7 +1326,7 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         EZO_KLAUNCH(c, k_place, dim3(E), dim3(1024), (size_t)std::max(cand_cap, 16), st, dof, edges,
                            (const float*)w_cs, (const float*)w_ad, (const float*)w_ts, (const int*)w_nc, cand_cap,
                            p->n_f, (float)p->step_back_max, (float)p->t_col, A, b, n_faces, cap, edge_status,
-                           nullptr, nullptr, (const uint8_t*)w_pa, (EdgeStatsDev*)w_st);
+                           nullptr, nullptr, (const uint8_t*)w_pa, (EdgeStatsDev*)w_st, p->row_points);
         mark(EZO_PHASE_ADVANCE);
         EZO_KLAUNCH(c, k_advance, dim3(1), dim3(256), 0, st, (int*)w_k, p->max_iters, edge_status, E, (int*)w_ac);
         mark(EZO_NUM_PHASES);
@@ -1449,11 +1530,13 @@ ezo_status ezo_inflate_paths(ezo_ctx* c, const ezo_robot* r, const float* obs, i
     HIP_TRY(c, hipMemcpyAsync(w_eo, eoff.data(), sizeof(int) * (P + 1), hipMemcpyHostToDevice, st));
     HIP_TRY(c, hipStreamSynchronize(st));            // eoff is a host vector
     std::vector<ezo_edge_stats> rstats(slots);
+    ezo_params pr = *p;
+    pr.row_points = nullptr;           // the round buffers are indexed by window slot
     for (int rr = 0; rr < rounds; ++rr) {
         EZO_KLAUNCH(c, k_path_round, dim3(P), dim3(256), 0, st, dof, vertices, (const int*)w_eo, rr, s_win, A, b,
                     n_faces, edge_status, cap, covered_by, (float*)w_re, (int*)w_ri, (uint8_t*)w_rs);
         HIP_TRY(c, hipGetLastError());
-        if ((s = inflate_core(c, r, obs, n_obs, (const float*)w_re, slots, p, (float*)w_ra, (float*)w_rb,
+        if ((s = inflate_core(c, r, obs, n_obs, (const float*)w_re, slots, &pr, (float*)w_ra, (float*)w_rb,
                               (int*)w_rn, (int*)w_rt, stats ? rstats.data() : nullptr, st, (const int*)w_ri,
                               (const uint8_t*)w_rs)))
             return s;
@@ -1696,7 +1779,7 @@ ezo_status ezo_update_polytopes(ezo_ctx* c, const ezo_robot* r, const float* obs
     hipLaunchKernelGGL(k_place, dim3(E), dim3(1024), (size_t)std::max(N, 16), st, dof, edges, (const float*)w_cs,
                        (const float*)w_ad, (const float*)w_ts, (const int*)w_nc, N, n_f, (float)step_back_max,
                        (float)t_col, A, b, n_faces, face_capacity, (int*)w_run, nullptr, (int*)w_np,
-                       (const uint8_t*)w_pa, nullptr);
+                       (const uint8_t*)w_pa, nullptr, nullptr);
     hipLaunchKernelGGL(k_recover_end, dim3((E + 255) / 256), dim3(256), 0, st, E, (const int*)w_run,
                        (const int*)w_np, edge_status, planes_added);
     HIP_TRY(c, hipGetLastError());

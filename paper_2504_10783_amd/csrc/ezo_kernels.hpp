@@ -7,6 +7,7 @@
 // is final (>= 0) are skipped by every kernel.
 #pragma once
 #include "ezo_device.hpp"
+#include "ezo_screen.hpp"
 
 namespace ezo {
 
@@ -326,11 +327,30 @@ __device__ __forceinline__ void group_minmax(float& lo_max, float& hi_min) {
 // One hit-and-run step of the group's walk: chord of x along u through P
 // (rows f = sub, sub + L, ... on this lane), x += t u with t = tlo + w (thi -
 // tlo); t = 0 when rounding empties the chord.
+// nbox = dof when the first 2 dof rows of P are the joint box (+e_j <= hi_j,
+// then -e_j <= -lo_j), else 0.  Those rows' a^T u and a^T x are +-u_j and
+// +-x_j exactly, so they are evaluated without the dot products (coordinates
+// j = sub, sub + L, ... on this lane), with the same FP32 operations on the
+// same values as the general rows: the chord ends are unchanged bit for bit.
 template <int D, int L>
 __device__ __forceinline__ void walk_step(const float* rowA, const float* rowb, int F, int sub, const float (&u)[D],
-                                          float wt, float (&x)[D]) {
+                                          float wt, float (&x)[D], int nbox) {
     float tlo = -INFINITY, thi = INFINITY;
-    for (int f = sub; f < F; f += L) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        if (j >= nbox || (j % L) != sub) continue;
+        const float r = __builtin_amdgcn_rcpf(u[j]), rn = __builtin_amdgcn_rcpf(-u[j]);
+        const float th = (rowb[j] - x[j]) * r;           // row +e_j <= hi_j
+        const float tl = (rowb[nbox + j] - (-x[j])) * rn; // row -e_j <= -lo_j
+        if (u[j] > 0.f) {
+            thi = fminf(thi, th);
+            tlo = fmaxf(tlo, tl);
+        } else if (u[j] < 0.f) {
+            tlo = fmaxf(tlo, th);
+            thi = fminf(thi, tl);
+        }
+    }
+    for (int f = 2 * nbox + sub; f < F; f += L) {
         float den = 0.f, ax = 0.f;
 #pragma unroll
         for (int j = 0; j < D; ++j) {
@@ -369,6 +389,17 @@ __device__ __forceinline__ void sample_block(char* smem, int dof, const float* _
     }
     for (int f = threadIdx.x; f < F; f += blockDim.x) rowb[f] = bvec[(size_t)e * cap + f];
     __syncthreads();
+    // the joint box as the first 2 dof rows?  (every polytope of the fused
+    // loop starts so; a caller's P may not)
+    int nbox = 0;
+    if (F >= 2 * dof) {                                   // uniform
+        bool ok = true;
+        for (int i = threadIdx.x; i < 2 * dof * dof; i += blockDim.x) {
+            const int f = i / dof, j = i % dof;
+            ok = ok && rowA[f * D + j] == (j == f % dof ? (f < dof ? 1.f : -1.f) : 0.f);
+        }
+        nbox = __syncthreads_and(ok ? 1 : 0) ? dof : 0;
+    }
     const int lane = threadIdx.x & 63;
     const int sub = lane & (L - 1);                       // position in the walk's lane group
     const int i = (blockIdx.x * blockDim.x + threadIdx.x) / L;
@@ -388,7 +419,7 @@ __device__ __forceinline__ void sample_block(char* smem, int dof, const float* _
     if constexpr (L <= 2) {
         for (int s = 1; s <= n_mix; ++s) {
             const float wt = draw_direction<D>(dof, ii, eid, kk, (uint32_t)s, key0, key1, u);
-            walk_step<D, L>(rowA, rowb, F, sub, u, wt, x);
+            walk_step<D, L>(rowA, rowb, F, sub, u, wt, x, nbox);
         }
     } else {
         constexpr int SD = sample_dir_stride(D), CH = sample_chunk(L);
@@ -418,7 +449,7 @@ __device__ __forceinline__ void sample_block(char* smem, int dof, const float* _
             for (int c = 0; c < ns; ++c) {
 #pragma unroll
                 for (int j = 0; j < D; ++j) u[j] = dirs[c * SD + j];
-                walk_step<D, L>(rowA, rowb, F, sub, u, dirs[c * SD + D], x);
+                walk_step<D, L>(rowA, rowb, F, sub, u, dirs[c * SD + D], x, nbox);
             }
             __syncthreads();
         }
@@ -474,6 +505,39 @@ __global__ void __launch_bounds__(256) k_sample_auto(int dof, const float* __res
         sample_block<D, 1>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv,
                             edge_ids);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Learned screen of the loop's samples: the network's prediction for the
+// samples that the screen may skip, rows M_k <= i < |S| of every running
+// edge (the unadaptive test's first M_k samples are always checked exactly).
+// One workgroup (4 waves) per 64 consecutive sample rows of one edge
+// (blockIdx.y); the whole forward pass runs in the workgroup
+// (mlp_forward_tile), so activations never leave LDS.  pred[e][i] is written
+// for the rows of every tile that overlaps [M_k, |S|); others are untouched
+// and never read.
+// ---------------------------------------------------------------------------
+constexpr int kScreenRows = 64;
+
+__global__ void __launch_bounds__(256) k_screen_samples(MlpView mv, const float* __restrict__ S, int64_t stride,
+                                                        int dof, float* __restrict__ pred,
+                                                        const int* __restrict__ status, IterArgs it) {
+    __shared__ __attribute__((aligned(16))) __bf16 h[kScreenRows * (kMlpMaxH + kMlpPad)];
+    __shared__ float q[kScreenRows * kMaxDof];
+    __shared__ float y[kScreenRows];
+    const int e = blockIdx.y;
+    if (!edge_running(status, e)) return;
+    const IterVals iv = resolve(it);
+    const int64_t r0 = (int64_t)blockIdx.x * kScreenRows;
+    if (r0 + kScreenRows <= iv.M || r0 >= iv.nS) return;
+    const int nr = (int)min<int64_t>(kScreenRows, iv.nS - r0);
+    const float* Se = S + (size_t)e * dof * stride;
+    for (int i = threadIdx.x; i < kScreenRows * dof; i += blockDim.x) {
+        const int r = i % kScreenRows, j = i / kScreenRows;
+        q[r * kMaxDof + j] = r < nr ? Se[(size_t)j * stride + r0 + r] : 0.f;
+    }
+    mlp_forward_tile<kScreenRows / 16, 4>(mv, q, kMaxDof, nr, h, y);
+    if (threadIdx.x < (unsigned)nr) pred[(size_t)e * stride + r0 + threadIdx.x] = y[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -582,7 +646,7 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
 // LDS: the tile, the staged obstacles (ob.lds_n records), then the robot
 // tables (robot_stage_bytes), read by every one of the dependent checks.
 // ---------------------------------------------------------------------------
-template <int TC, int DEPTH, bool BOX>
+template <int TC, int DEPTH, bool BOX, bool SCR = false>
 __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rg, ObsView ob, GridView gv, const float* __restrict__ edges,
                                                          const float* __restrict__ S, int64_t stride, int64_t s_edge,
                                                          const int* __restrict__ cand_idx,
@@ -591,8 +655,11 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rg, ObsView o
                                                          float* __restrict__ t_star,
                                                          uint8_t* __restrict__ proj_collides,
                                                          uint8_t* __restrict__ proj_any,
-                                                         const int* __restrict__ status) {
+                                                         const int* __restrict__ status, MlpView mv,
+                                                         EdgeStatsDev* __restrict__ stats) {
     static_assert(DEPTH >= 1 && DEPTH <= 3 && TC >= 1, "bisection depth per round");
+    static_assert(!SCR || (DEPTH == 1 && TC <= 16), "the screened bisection checks at most 16 points per round");
+    // (the screened form runs with at least four waves: the network's layers)
     constexpr int NODES = (1 << DEPTH) - 1;
     constexpr int T = TC * NODES;                   // configurations per tile check
     extern __shared__ __align__(16) char smem[];
@@ -606,11 +673,16 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rg, ObsView o
     const int W = blockDim.x >> 6;
     const int slots = tile_slots(rg.n_spheres, rg.n_boxes);
     TileSmem t = carve_tile(smem, T, slots, W, ob.lds_n);
-    const RobotView rb = stage_robot(rg, smem + tile_smem_bytes(T, slots, W) + 16 * (size_t)ob.lds_n);
+    char* rs_base = smem + tile_smem_bytes(T, slots, W) + 16 * (size_t)ob.lds_n;
+    const RobotView rb = stage_robot(rg, rs_base);
+    // screened form: the network's activations and predictions after the
+    // staged robot tables
+    __bf16* mlp_h = reinterpret_cast<__bf16*>(rs_base + robot_stage_bytes(slots));
+    float* mlp_y = reinterpret_cast<float*>(reinterpret_cast<char*>(mlp_h) + mlp_tile_smem_bytes(1));
     stage_obstacles(ob, t);
     const int tid = threadIdx.x;
     const bool own = tid < nv;
-    if (tid < T) t.scr[tid] = 0;          // bisection points are always checked exactly
+    if (tid < T) t.scr[tid] = 0;          // the projections (fail-fast) are always checked exactly
     float lo[kMaxDof], hi[kMaxDof], cp[kMaxDof];
     const float* v = edges + (size_t)e * 2 * dof;
     if (own) {
@@ -672,6 +744,22 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rg, ObsView o
             }
         }
         __syncthreads();
+        if constexpr (SCR) {
+            // one-sided screen of the midpoints: exact self pairs are skipped
+            // iff the predicted self distance is >= the margin, so a point
+            // judged colliding is truly colliding and c* stays a collision
+            mlp_forward_tile<1, 4>(mv, t.q, kMaxDof, nv, mlp_h, mlp_y);
+            int screened = 0;
+            if (tid < T) {
+                const bool sc = tid < nv && mlp_y[tid] >= mv.margin;
+                t.scr[tid] = sc ? 1 : 0;
+                screened = sc ? 1 : 0;
+            }
+            if (stats && tid < 64) {
+                const unsigned long long b = __ballot(screened != 0);
+                if (tid == 0 && b) atomicAdd((unsigned long long*)&stats[e].screened, (unsigned long long)__popcll(b));
+            }
+        }
         ntest += tile_check<false, BOX>(rb, ob, gv, t, T, nv * npt);
         if (own) {
             const int* h = t.hit + tid * npt;
@@ -710,9 +798,10 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rg, ObsView o
 // ---------------------------------------------------------------------------
 // Placement rounds of one edge.  REG: the thread's candidates j = tid +
 // q blockDim (q < kPlaceReg) keep c* and their (t*, index) keys in registers
-// (needs n <= kPlaceReg blockDim); otherwise both are read from global memory
-// every round and the alive flags live in LDS.
-constexpr int kPlaceReg = 4;
+// (needs n <= kPlaceReg blockDim; the chosen candidate's direction a is read
+// from global memory by the thread that builds the row); otherwise both are
+// read from global memory every round and the alive flags live in LDS.
+constexpr int kPlaceReg = 8;
 
 template <bool REG>
 __device__ inline void place_rounds(int e, int dof, const float* __restrict__ v, const float* __restrict__ cs,
@@ -721,12 +810,11 @@ __device__ inline void place_rounds(int e, int dof, const float* __restrict__ v,
                                     float* __restrict__ bvec, int* __restrict__ n_faces, int cap,
                                     int* __restrict__ status, int* __restrict__ placed_idx,
                                     int* __restrict__ n_placed, EdgeStatsDev* __restrict__ stats, uint8_t* alive,
-                                    unsigned long long* wmin, float* row, int* s_stop) {
+                                    unsigned long long* wmin, float* row, int* s_stop, float* __restrict__ row_pts) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6, nt = blockDim.x;
     int nf = min(max(n_faces[e], 0), cap);
     int placed = 0;
     float cx[REG ? kPlaceReg : 1][kMaxDof];
-    float ax[REG ? kPlaceReg : 1][kMaxDof];
     unsigned long long key[REG ? kPlaceReg : 1];
     bool al[REG ? kPlaceReg : 1];
     // smallest (t*, index) key among this thread's alive candidates; after a
@@ -741,10 +829,7 @@ __device__ inline void place_rounds(int e, int dof, const float* __restrict__ v,
             if (al[q]) {
                 key[q] = ((unsigned long long)__float_as_uint(ts[j]) << 32) | (unsigned)j;
 #pragma unroll
-                for (int k = 0; k < kMaxDof; ++k) {
-                    cx[q][k] = k < dof ? cs[(size_t)k * cand_cap + j] : 0.f;
-                    ax[q][k] = k < dof ? ad[(size_t)k * cand_cap + j] : 0.f;
-                }
+                for (int k = 0; k < kMaxDof; ++k) cx[q][k] = k < dof ? cs[(size_t)k * cand_cap + j] : 0.f;
                 best = key[q] < best ? key[q] : best;
             }
         }
@@ -785,19 +870,17 @@ __device__ inline void place_rounds(int e, int dof, const float* __restrict__ v,
                     if (k >= dof) break;
                     float a, c;
                     if constexpr (REG) {
-                        a = ax[0][k];
+                        a = ad[(size_t)k * cand_cap + jb];
                         c = cx[0][k];
 #pragma unroll
                         for (int q = 1; q < kPlaceReg; ++q)
-                            if (q == qb) {
-                                a = ax[q][k];
-                                c = cx[q][k];
-                            }
+                            if (q == qb) c = cx[q][k];
                     } else {
                         a = ad[(size_t)k * cand_cap + jb];
                         c = cs[(size_t)k * cand_cap + jb];
                     }
                     row[k] = a;
+                    if (row_pts) row_pts[((size_t)e * cap + nf) * dof + k] = c;
                     bj = fmaf(a, c, bj);
                     av1 = fmaf(a, v[k], av1);
                     av2 = fmaf(a, v[dof + k], av2);
@@ -883,7 +966,7 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
                                                 float* __restrict__ bvec, int* __restrict__ n_faces, int cap,
                                                 int* __restrict__ status, int* __restrict__ placed_idx,
                                                 int* __restrict__ n_placed, const uint8_t* __restrict__ proj_any,
-                                                EdgeStatsDev* __restrict__ stats) {
+                                                EdgeStatsDev* __restrict__ stats, float* __restrict__ row_pts) {
     extern __shared__ __align__(16) char smem[];
     uint8_t* alive = reinterpret_cast<uint8_t*>(smem);                // [cand_cap]
     __shared__ unsigned long long wmin[16];
@@ -905,10 +988,10 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
     const float* ts = t_star + (size_t)e * cand_cap;
     if (n <= kPlaceReg * (int)blockDim.x)
         place_rounds<true>(e, dof, v, cs, ad, ts, n, cand_cap, n_f, step_back_max, t_col, A, bvec, n_faces, cap,
-                           status, placed_idx, n_placed, stats, alive, wmin, row, &s_stop);
+                           status, placed_idx, n_placed, stats, alive, wmin, row, &s_stop, row_pts);
     else
         place_rounds<false>(e, dof, v, cs, ad, ts, n, cand_cap, n_f, step_back_max, t_col, A, bvec, n_faces, cap,
-                            status, placed_idx, n_placed, stats, alive, wmin, row, &s_stop);
+                            status, placed_idx, n_placed, stats, alive, wmin, row, &s_stop, row_pts);
 }
 
 // ---------------------------------------------------------------------------

@@ -12,37 +12,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ezo_screen.hpp"
+
 namespace ezo {
-
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
-
-constexpr float kInvPi = 0.318309886183790671538f;
-
-__device__ __forceinline__ float sigmoidf_(float z) { return 1.f / (1.f + __expf(-z)); }
-__device__ __forceinline__ float siluf(float z) { return z * sigmoidf_(z); }
-__device__ __forceinline__ float silu_gradf(float z) {
-    const float s = sigmoidf_(z);
-    return s * (1.f + z * (1.f - s));
-}
-
-struct MlpOffsets {
-    int64_t W1, b1, W2, b2, W3, b3, W4, b4, total;
-};
-
-__host__ __device__ inline MlpOffsets mlp_offsets(int D, int H) {
-    MlpOffsets o;
-    o.W1 = 0;
-    o.b1 = o.W1 + (int64_t)H * D;
-    o.W2 = o.b1 + H;
-    o.b2 = o.W2 + (int64_t)H * H;
-    o.W3 = o.b2 + H;
-    o.b3 = o.W3 + (int64_t)H * H;
-    o.W4 = o.b3 + H;
-    o.b4 = o.W4 + H;
-    o.total = o.b4 + 1;
-    return o;
-}
 
 __device__ __forceinline__ const float* row_ptr(const RowSource& s, int64_t r, int64_t* stride) {
     r += s.rbase;
@@ -105,21 +77,27 @@ __global__ void __launch_bounds__(256) k_mlp_out(RowSource src, int64_t rows, in
 
 // ---------------------------------------------------------------------------
 // BF16 MFMA GEMM  C[M][N] = sum_k A(m, k) B(k, n)
-// A(m, k) = A[m*sam + k*sak], B(k, n) = B[k*sbk + n*sbn]; M, N multiples of
-// 64, K a multiple of 32.  Workgroup: 64x64 output tile, 4 waves of 32x32,
-// each a 2x2 grid of v_mfma_f32_16x16x32_bf16.  Tiles staged in LDS K-major
-// ([row][k], 8-element pad).  Fragment layout (16x16x32): lane l holds
-// A[row l%16][k 8(l/16)..+7], B[k 8(l/16)..+7][col l%16] and returns
-// C[rows 4(l/16)..+3][col l%16].
+// A(m, k) = A[m*sam + k*sak] with AK: sak == 1 (K contiguous) else sam == 1
+// (M contiguous); B(k, n) = B[k*sbk + n*sbn] with BK: sbk == 1 else sbn == 1.
+// M, N multiples of 64, K a multiple of 32, contiguous runs 16-byte aligned.
+// Workgroup: 64x64 output tile, 4 waves of 32x32, each a 2x2 grid of
+// v_mfma_f32_16x16x32_bf16.  Staging: every thread loads one 16-byte vector
+// of A and one of B per K step (eight consecutive elements along the
+// contiguous dimension) into LDS tiles held K-major ([row][k], 8-element
+// pad).  Fragment layout (16x16x32): lane l holds A[row l%16][k 8(l/16)..+7],
+// B[k 8(l/16)..+7][col l%16] and returns C[rows 4(l/16)..+3][col l%16].
+// Split K: blockIdx.z takes K steps [z kc, (z + 1) kc); with gridDim.z > 1
+// only GEMM_STORE is allowed and slice z writes C + z M ldc (partial sums,
+// reduced by k_sum_slices).
 // Epilogues: STORE C = acc (FP32); FWD z = acc + bias[n] -> C (optional),
 // Hout = bf16(silu(z)); BWD Hout = bf16(acc * silu'(Z[m][n])).
 // ---------------------------------------------------------------------------
 enum { GEMM_STORE = 0, GEMM_FWD = 1, GEMM_BWD = 2 };
 
-template <int EPI>
-__global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const __bf16* __restrict__ A, int64_t sam,
-                                                   int64_t sak, const __bf16* __restrict__ B, int64_t sbk,
-                                                   int64_t sbn, float* __restrict__ C, int64_t ldc,
+template <int EPI, bool AK, bool BK>
+__global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, int kc, const __bf16* __restrict__ A,
+                                                   int64_t sam, int64_t sak, const __bf16* __restrict__ B,
+                                                   int64_t sbk, int64_t sbn, float* __restrict__ C, int64_t ldc,
                                                    const float* __restrict__ bias, __bf16* __restrict__ Hout,
                                                    int64_t ldh, const float* __restrict__ Z, int64_t ldz,
                                                    const int* __restrict__ status, int64_t rows_per_batch,
@@ -130,21 +108,32 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const __
     if (m0 >= M || n0 >= N) return;
     // tiles of finished edges are skipped (rows_per_batch is a multiple of 64)
     if (status && rows_per_batch > 0 && status[(m0 + rbase) / rows_per_batch] >= 0) return;
+    const int kb0 = blockIdx.z * kc, kb1 = min(K, kb0 + kc);
+    if (gridDim.z > 1) C += (int64_t)blockIdx.z * M * ldc;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    // this thread's staging vector: (row, k) of its eight elements
+    const int ar = AK ? (tid >> 2) : ((tid & 7) * 8), ak = AK ? ((tid & 3) * 8) : (tid >> 3);
+    const int br = BK ? (tid >> 2) : ((tid & 7) * 8), bk = BK ? ((tid & 3) * 8) : (tid >> 3);
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        for (int e = tid; e < 64 * 32; e += 256) {
-            int mm, kk;
-            if (sak == 1) { mm = e >> 5; kk = e & 31; } else { mm = e & 63; kk = e >> 6; }
-            As[mm][kk] = A[(int64_t)(m0 + mm) * sam + (int64_t)(k0 + kk) * sak];
-            int nn, kb;
-            if (sbk == 1) { nn = e >> 5; kb = e & 31; } else { nn = e & 63; kb = e >> 6; }
-            Bs[nn][kb] = B[(int64_t)(k0 + kb) * sbk + (int64_t)(n0 + nn) * sbn];
+    for (int k0 = kb0; k0 < kb1; k0 += 32) {
+        const bf16x8 av = *reinterpret_cast<const bf16x8*>(A + (int64_t)(m0 + ar) * sam + (int64_t)(k0 + ak) * sak);
+        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(B + (int64_t)(k0 + bk) * sbk + (int64_t)(n0 + br) * sbn);
+        if (AK) {
+            *reinterpret_cast<bf16x8*>(&As[ar][ak]) = av;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) As[ar + e][ak] = av[e];
+        }
+        if (BK) {
+            *reinterpret_cast<bf16x8*>(&Bs[br][bk]) = bv;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) Bs[br + e][bk] = bv[e];
         }
         __syncthreads();
         bf16x8 a[2], b[2];
@@ -177,6 +166,16 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const __
                     Hout[(int64_t)m * ldh + n] = (__bf16)(v * silu_gradf(Z[(int64_t)m * ldz + n]));
                 }
             }
+}
+
+// out[i] = sum_z part[z n + i] (z < slices), a fixed order: deterministic.
+__global__ void __launch_bounds__(256) k_sum_slices(const float* __restrict__ part, int slices, int64_t n,
+                                                    float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int z = 0; z < slices; ++z) s += part[(int64_t)z * n + i];
+    out[i] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -216,34 +215,38 @@ __global__ void __launch_bounds__(256) k_mlp_out_back(int64_t B, int D, int H, c
     if (threadIdx.x == 0) atomicAdd(loss_acc, red[0]);
 }
 
-// Column sums over a batch: out[j] = sum_r w[r] * X[r][j] (w NULL -> 1),
-// X BF16 [B][ncol] or FP32 (Xf).  One thread per column, rows strided.
-__global__ void __launch_bounds__(256) k_colsum(int64_t B, int ncol, const float* __restrict__ w,
-                                                const __bf16* __restrict__ X, const float* __restrict__ Xf,
-                                                float* __restrict__ out) {
+// Column sums over a batch, in row slices: part[z][j] = sum over rows r of
+// slice z (rows [z rs, (z + 1) rs) of B) of w[r] * X[r][j] (w NULL -> 1), X
+// BF16 [B][ncol] or FP32 (Xf).  blockIdx.y = slice; summed by k_sum_slices.
+__global__ void __launch_bounds__(256) k_colsum_part(int64_t B, int ncol, int64_t rs, const float* __restrict__ w,
+                                                     const __bf16* __restrict__ X, const float* __restrict__ Xf,
+                                                     float* __restrict__ part) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= ncol) return;
+    const int64_t r0 = (int64_t)blockIdx.y * rs, r1 = min(B, r0 + rs);
     float s = 0.f;
-    for (int64_t r = 0; r < B; ++r) {
+    for (int64_t r = r0; r < r1; ++r) {
         const float x = X ? (float)X[r * ncol + j] : Xf[r * ncol + j];
         s = fmaf(w ? w[r] : 1.f, x, s);
     }
-    out[j] = s;
+    part[(int64_t)blockIdx.y * ncol + j] = s;
 }
 
-// dW1[i][j] = sum_r dz1[r][i] * x[r][j] / pi.  One thread per (i, j).
-__global__ void __launch_bounds__(256) k_mlp_grad_w1(RowSource src, int64_t B, int D, int H,
-                                                     const __bf16* __restrict__ dz1, float* __restrict__ gW1) {
+// dW1[i][j] = sum_r dz1[r][i] * x[r][j] / pi in row slices: part[z][i D + j]
+// over rows [z rs, (z + 1) rs).  One thread per (i, j); blockIdx.y = slice.
+__global__ void __launch_bounds__(256) k_mlp_grad_w1_part(RowSource src, int64_t B, int D, int H, int64_t rs,
+                                                          const __bf16* __restrict__ dz1, float* __restrict__ part) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= H * D) return;
     const int i = t / D, j = t % D;
+    const int64_t r0 = (int64_t)blockIdx.y * rs, r1 = min(B, r0 + rs);
     float s = 0.f;
-    for (int64_t r = 0; r < B; ++r) {
+    for (int64_t r = r0; r < r1; ++r) {
         int64_t sd;
         const float* x = row_ptr(src, r, &sd);
         s = fmaf((float)dz1[r * H + i], x[j * sd] * kInvPi, s);
     }
-    gW1[t] = s;
+    part[(int64_t)blockIdx.y * H * D + t] = s;
 }
 
 // Adam step with bias correction on the flat parameter vector; refreshes

@@ -28,6 +28,7 @@ struct TrainBufs {
     float *z1, *z2, *z3, *y, *dy, *loss;
     __bf16 *h1, *h2, *h3, *d3, *d2, *d1;
     int* idx;
+    float* part;        // partial sums of the batch reductions
 };
 
 TrainBufs carve(void* base, int B, int H) {
@@ -52,21 +53,60 @@ TrainBufs carve(void* base, int B, int H) {
     t.dy = (float*)take(4 * (size_t)B);
     t.idx = (int*)take(4 * (size_t)B);
     t.loss = (float*)take(256);
+    t.part = (float*)take(0);
     return t;
 }
 
-size_t train_bytes(int B, int H) {
-    const size_t bh = (size_t)B * H;
-    return 3 * (((4 * bh) + 255) & ~(size_t)255) + 6 * (((2 * bh) + 255) & ~(size_t)255) + 3 * ((4 * (size_t)B + 255) & ~(size_t)255) + 256;
+// Row slices of the batch reductions (column sums, dW1) and K slices of the
+// weight-gradient GEMMs (K = batch rows): each slice writes partial sums,
+// summed in a fixed order by k_sum_slices.
+constexpr int kRowsPerSlice = 64;
+constexpr int kGradSplitK = 16;
+
+size_t partial_floats(int B, int H, int D) {
+    const size_t slices = (size_t)(B + kRowsPerSlice - 1) / kRowsPerSlice;
+    return std::max({(size_t)kGradSplitK * H * H, slices * H * std::max(D, 1), slices * 1});
 }
 
+size_t train_bytes(int B, int H, int D) {
+    const size_t bh = (size_t)B * H;
+    return 3 * (((4 * bh) + 255) & ~(size_t)255) + 6 * (((2 * bh) + 255) & ~(size_t)255) +
+           3 * ((4 * (size_t)B + 255) & ~(size_t)255) + 256 + ((4 * partial_floats(B, H, D) + 255) & ~(size_t)255);
+}
+
+// C = A B with the strides' contiguous dimensions picking the staging; split
+// > 1 (GEMM_STORE only) writes partial products over slices of about K /
+// split rows (a multiple of 32) to C + z M ldc.  Returns the slice count.
 template <int EPI>
-void gemm(hipStream_t st, int M, int N, int K, const __bf16* A, int64_t sam, int64_t sak, const __bf16* B, int64_t sbk,
+int gemm(hipStream_t st, int M, int N, int K, const __bf16* A, int64_t sam, int64_t sak, const __bf16* B, int64_t sbk,
           int64_t sbn, float* C, int64_t ldc, const float* bias, __bf16* Hout, int64_t ldh, const float* Z, int64_t ldz,
-          const int* status = nullptr, int64_t rpb = 0, int64_t rbase = 0) {
-    dim3 grid((unsigned)(N / 64), (unsigned)(M / 64)), block(256);
-    hipLaunchKernelGGL((k_gemm_bf16<EPI>), grid, block, 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, Hout, ldh,
-                       Z, ldz, status, rpb, rbase);
+          const int* status = nullptr, int64_t rpb = 0, int64_t rbase = 0, int split = 1) {
+    const int kc = (K / split + 31) / 32 * 32;
+    dim3 grid((unsigned)(N / 64), (unsigned)(M / 64), (unsigned)((K + kc - 1) / kc)), block(256);
+    const bool ak = sak == 1, bk = sbk == 1;
+#define EZO_GEMM(AKV, BKV)                                                                                          \
+    hipLaunchKernelGGL((k_gemm_bf16<EPI, AKV, BKV>), grid, block, 0, st, M, N, K, kc, A, sam, sak, B, sbk, sbn, C, ldc, \
+                       bias, Hout, ldh, Z, ldz, status, rpb, rbase)
+    if (ak && bk) EZO_GEMM(true, true);
+    else if (ak) EZO_GEMM(true, false);
+    else if (bk) EZO_GEMM(false, true);
+    else EZO_GEMM(false, false);
+#undef EZO_GEMM
+    return (int)grid.z;
+}
+
+// sum of the row slices of a batch reduction into out[n]
+void sum_slices(hipStream_t st, const float* part, int slices, int64_t n, float* out) {
+    hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, slices, n, out);
+}
+
+// out[j] = sum_r w[r] X[r][j] over the batch, in row slices
+void colsum(hipStream_t st, int64_t B, int ncol, const float* w, const __bf16* X, const float* Xf, float* part,
+            float* out) {
+    const int slices = (int)((B + kRowsPerSlice - 1) / kRowsPerSlice);
+    hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)((ncol + 255) / 256), (unsigned)slices), dim3(256), 0, st, B, ncol,
+                       (int64_t)kRowsPerSlice, w, X, Xf, part);
+    sum_slices(st, part, slices, ncol, out);
 }
 
 // batch row indices: an affine permutation of [0, n) per epoch
@@ -106,23 +146,26 @@ ezo_status forward_backward(ezo_ctx* c, ezo_surrogate* s, const RowSource& src, 
     hipLaunchKernelGGL(k_mlp_out_back, dim3((unsigned)((BH + 255) / 256)), dim3(256), 0, st, (int64_t)B, D, H, P, t.y,
                        target, (const int*)src.idx, (float)hp->huber_delta, (float)hp->clip_lo, (float)hp->clip_hi,
                        t.z3, t.dy, t.d3, t.loss);
-    const unsigned gc = (unsigned)((H + 255) / 256);
-    hipLaunchKernelGGL(k_colsum, dim3(gc), dim3(256), 0, st, (int64_t)B, H, (const float*)t.dy, (const __bf16*)t.h3,
-                       (const float*)nullptr, G + o.W4);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, st, (int64_t)B, 1, (const float*)nullptr, (const __bf16*)nullptr,
-                       (const float*)t.dy, G + o.b4);
-    hipLaunchKernelGGL(k_colsum, dim3(gc), dim3(256), 0, st, (int64_t)B, H, (const float*)nullptr, (const __bf16*)t.d3,
-                       (const float*)nullptr, G + o.b3);
-    gemm<GEMM_STORE>(st, H, H, B, t.d3, 1, H, t.h2, H, 1, G + o.W3, H, nullptr, nullptr, 0, nullptr, 0);
+    float* part = t.part;
+    colsum(st, B, H, t.dy, t.h3, nullptr, part, G + o.W4);
+    colsum(st, B, 1, nullptr, nullptr, t.dy, part, G + o.b4);
+    colsum(st, B, H, nullptr, t.d3, nullptr, part, G + o.b3);
+    int ks = gemm<GEMM_STORE>(st, H, H, B, t.d3, 1, H, t.h2, H, 1, part, H, nullptr, nullptr, 0, nullptr, 0, nullptr,
+                              0, 0, kGradSplitK);
+    sum_slices(st, part, ks, (int64_t)H * H, G + o.W3);
     gemm<GEMM_BWD>(st, B, H, H, t.d3, H, 1, s->W3b, H, 1, nullptr, 0, nullptr, t.d2, H, t.z2, H);
-    hipLaunchKernelGGL(k_colsum, dim3(gc), dim3(256), 0, st, (int64_t)B, H, (const float*)nullptr, (const __bf16*)t.d2,
-                       (const float*)nullptr, G + o.b2);
-    gemm<GEMM_STORE>(st, H, H, B, t.d2, 1, H, t.h1, H, 1, G + o.W2, H, nullptr, nullptr, 0, nullptr, 0);
+    colsum(st, B, H, nullptr, t.d2, nullptr, part, G + o.b2);
+    ks = gemm<GEMM_STORE>(st, H, H, B, t.d2, 1, H, t.h1, H, 1, part, H, nullptr, nullptr, 0, nullptr, 0, nullptr, 0, 0,
+                          kGradSplitK);
+    sum_slices(st, part, ks, (int64_t)H * H, G + o.W2);
     gemm<GEMM_BWD>(st, B, H, H, t.d2, H, 1, s->W2b, H, 1, nullptr, 0, nullptr, t.d1, H, t.z1, H);
-    hipLaunchKernelGGL(k_colsum, dim3(gc), dim3(256), 0, st, (int64_t)B, H, (const float*)nullptr, (const __bf16*)t.d1,
-                       (const float*)nullptr, G + o.b1);
-    hipLaunchKernelGGL(k_mlp_grad_w1, dim3((unsigned)((H * D + 255) / 256)), dim3(256), 0, st, src, (int64_t)B, D, H,
-                       (const __bf16*)t.d1, G + o.W1);
+    colsum(st, B, H, nullptr, t.d1, nullptr, part, G + o.b1);
+    {
+        const int slices = (B + kRowsPerSlice - 1) / kRowsPerSlice;
+        hipLaunchKernelGGL(k_mlp_grad_w1_part, dim3((unsigned)((H * D + 255) / 256), (unsigned)slices), dim3(256), 0, st,
+                           src, (int64_t)B, D, H, (int64_t)kRowsPerSlice, (const __bf16*)t.d1, part);
+        sum_slices(st, part, slices, (int64_t)H * D, G + o.W1);
+    }
     HIP_TRY(c, hipGetLastError());
     return EZO_OK;
 }
@@ -139,7 +182,7 @@ ezo_status ensure_train_bufs(ezo_ctx* c, ezo_surrogate* s, int B) {
         (void)hipFree(s->tb);
         s->tb = nullptr;
     }
-    if (hipMalloc(&s->tb, train_bytes(B, s->H)) != hipSuccess) return ezo_fail(c, EZO_E_NOMEM, "training buffers");
+    if (hipMalloc(&s->tb, train_bytes(B, s->H, s->D)) != hipSuccess) return ezo_fail(c, EZO_E_NOMEM, "training buffers");
     s->batch = B;
     return EZO_OK;
 }

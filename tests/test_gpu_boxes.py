@@ -8,12 +8,19 @@ geometries) against the oracle:
 * the obstacle-box call's errors, removal, and the inflation graph following
   a change of the obstacle boxes.
 
-Box-box values: the FK rotations carry FP32 rounding of about 1e-6, which a
-cross axis of edges at |A_i x B_j| >= 0.05 amplifies to at most about
-1e-6 x 2.5 m / 0.05 = 5e-5 m.  So flags must agree wherever the oracle's
-minimum lies outside +-5e-5 m and no box pair's sign rests on such a cross
-axis (fragile bit 1), and signed distances agree to 5e-5 m wherever no box
-pair near the minimum of its kind has such a value (fragile bit 0).
+Box-box values: the kernel evaluates every separating axis from products
+of the components of A_i x B_j, so its own arithmetic keeps full relative
+precision on nearly parallel edges; what remains is the conditioning of the
+problem itself.  The FP32 forward kinematics rotates each box by about 1e-7
+rad away from the FP64 pose, which turns a cross axis of |A_i x B_j| by
+about 1e-7 / |A_i x B_j| and moves its value by that times the centre
+distance (about 1 m): <= 1e-5 m for |A_i x B_j| >= WEAK_AXIS = 0.01.  The
+oracle marks configurations whose value (fragile bit 0) or sign (bit 1)
+rests on a weaker cross axis, and their fractions are printed; measured, the
+errors on them stay as small as elsewhere (a few 1e-7 m), so no
+configuration is excluded: flags must agree wherever the oracle's minimum
+lies outside +-1e-5 m (the band of the sphere checker), and signed distances
+agree to 1e-5 m everywhere.
 """
 import numpy as np
 import pytest
@@ -27,7 +34,15 @@ from gpu_common import bisection_agreement, f32_up, load, print_case
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-BOX_BAND = 5e-5
+BOX_BAND = 1e-5
+WEAK_AXIS = 0.01
+
+
+@pytest.fixture(scope="module", autouse=True)
+def fragility_thresholds():
+    oracle.set_fragility(WEAK_AXIS, BOX_BAND)
+    yield
+    oracle.set_fragility()
 
 
 @pytest.fixture(scope="module")
@@ -61,15 +76,17 @@ def compare(ezo, ctx, desc, obs_np, ebox, q, label):
     f, sd, se, ss, fr = oracle.check(oracle.Robot(desc), f32_up(obs_np), f32_up(q),
                                      env_boxes=None if ebox is None else f32_up(ebox), fragile=True)
     g, gs, gsd, gss = (x.cpu().numpy() for x in (flags, flags_sd, msd, mss))
-    ok = (np.abs(sd) >= BOX_BAND) & ((fr & 2) == 0)
-    vok = (fr & 1) == 0
+    ok = np.abs(sd) >= BOX_BAND
+    weak = (fr & 1) != 0
     print(f"{label}: {n} configs, collision {f.mean():.3f}, in band {np.mean(np.abs(sd) < BOX_BAND):.4f}, "
-          f"fragile value {np.mean(fr & 1):.4f} sign {np.mean((fr & 2) > 0):.4f}, "
-          f"max |sd err| {np.abs(gsd - sd)[vok].max():.2e}")
+          f"fragile value {np.mean(weak):.4f} sign {np.mean((fr & 2) > 0):.4f}, "
+          f"max |sd err| {np.abs(gsd - sd).max():.2e} (on fragile ones "
+          f"{np.abs(gsd - sd)[weak].max() if weak.any() else 0.0:.2e}), "
+          f"flags differing outside the band {int(np.sum((g != f) & ok))}")
     assert np.array_equal(g[ok], f[ok]) and np.array_equal(gs[ok], f[ok])
-    assert np.abs(gsd - sd)[vok].max() <= BOX_BAND
+    assert np.abs(gsd - sd).max() <= BOX_BAND
     fin = np.isfinite(ss)
-    assert np.abs(gss[fin] - ss[fin])[vok[fin]].max() <= BOX_BAND
+    assert np.abs(gss[fin] - ss[fin]).max() <= BOX_BAND
     assert np.all(np.isinf(gss[~fin]))
     return f
 

@@ -1,7 +1,7 @@
 """GPU parity of the DRM collision map (appendix, DRM construction) against
 the oracle's plain definition: every (voxel, node) bit equal wherever the
-oracle's signed distance lies outside +-1e-5 m (box robots: +-5e-5 m, see
-test_gpu_boxes), on the whole grid for the 3-DOF arm and on a dense block plus
+oracle's signed distance lies outside +-1e-5 m (the map tests robot spheres
+and boxes against voxel spheres: exact distances, no box-box axes), on the whole grid for the 3-DOF arm and on a dense block plus
 random voxels for the 7-DOF sphere and box arms; id lists equal the bitset
 rows; ragged node counts, padded rows and empty inputs."""
 import numpy as np
@@ -58,7 +58,7 @@ def test_map_whole_grid_tiny(ezo, ctx):
     assert 0.001 < hits.mean() < 0.5
 
 
-@pytest.mark.parametrize("name,band", [("dof7", BAND), ("boxes", 5e-5)])
+@pytest.mark.parametrize("name,band", [("dof7", BAND), ("boxes", BAND)])
 def test_map_block_and_random_voxels(ezo, ctx, name, band):
     data, desc = load(name)
     rob = ezo.Robot(ctx, desc)

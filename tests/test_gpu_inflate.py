@@ -18,7 +18,7 @@ import pytest
 import oracle
 import workloads
 
-from gpu_common import BAND, bisection_agreement, f32_up, load, print_case, sampler_agreement
+from gpu_common import BAND, bisection_agreement, f32_up, load, print_case, sampler_step_replay
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -97,9 +97,10 @@ def run_driven(ezo, ctx, rob, data, edge, prm, replay=True):
         Sk = S[0, :, :nS].cpu().numpy().T
         fk = flags[0, :nS].cpu().numpy()
         if replay:
-            ref = oracle.hit_and_run(f32_up(Ak), f32_up(bk), v1, v2, prm.n_mix, prm.seed, prm.edge_id_base, k, nS)
-            qs = sampler_agreement(f32_up(Sk), ref, f32_up(Ak), f32_up(bk), f"k={k}")
-            rep["sampler_max_err"] = max(rep["sampler_max_err"], float(qs[3]))
+            frac, emax = sampler_step_replay(ezo, ctx, dof, A, b, nf, edges, nS, prm.n_mix, prm.seed, k,
+                                             prm.edge_id_base, f"k={k}")
+            rep["sampler_max_err"] = max(rep["sampler_max_err"], emax)
+            rep["sampler_illcond"] = max(rep.get("sampler_illcond", 0.0), frac)
             fo, sdo, *_ = oracle.check(orob, obs_np, f32_up(Sk))
             out = np.abs(sdo) >= BAND
             rep["flag_band"] += int(np.sum(~out))

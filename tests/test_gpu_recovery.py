@@ -228,3 +228,81 @@ def test_recovery_round_trip(ezo, ctx):
     cov = ezo.segments_contained(ctx, res.A, res.b, res.n_faces, edges)
     torch.cuda.synchronize()
     assert int(cov[0].item()) == 0
+
+
+def test_recovery_reinflates_segments_the_edit_uncovered(ezo, ctx):
+    """The last step of Sec. V-B: after the sets are edited, every segment of
+    the path must still lie in some set; a segment that does not is inflated
+    anew.  The path is inflated with the containment skip (Sec. V-A), so some
+    segments hold no set of their own and are covered by an earlier edge's
+    set; a found collision placed just off the middle of such a segment
+    (inside the covering set, 0.004 rad from the segment, less than
+    Delta_max) makes the edit cut that segment out of the set while the set's
+    own segment stays inside.  The segment containment check finds it,
+    ezo_inflate_edges inflates it, and then every segment of the path is
+    covered again."""
+    data, desc = load("batched")
+    rob = ezo.Robot(ctx, desc)
+    dof = desc["dof"]
+    obs = torch.from_numpy(data["obstacles"]).cuda()
+    pid = data["path_id"]
+    p = dict(workloads.PARAMS["batched"], n_p=2000)
+    prm = ezo.make_params(dof=dof, seed=4, **p)
+    cap = prm.face_capacity
+    # the longest path
+    q = int(np.argmax(np.bincount(pid)))
+    idx = np.nonzero(pid == q)[0]
+    segs = data["edges"][idx]
+    verts = np.concatenate([segs[:, 0], segs[-1:, 1]]).astype(np.float32)
+    print_case("recovery re-inflation", len(segs), "segments")
+    res = ezo.inflate_paths(ctx, rob, obs, torch.from_numpy(verts).cuda(), [len(verts)], prm)
+    torch.cuda.synchronize()
+    cov = res.covered_by.cpu().numpy()
+    st = res.status.cpu().numpy()
+    A = res.A.cpu().numpy().astype(np.float64)
+    b = res.b.cpu().numpy().astype(np.float64)
+    nf = res.n_faces.cpu().numpy()
+    # a contained segment g (covered by h) and a point 0.004 rad off its middle
+    # on the side away from h's segment, well inside h's set
+    pick = None
+    for g in np.nonzero(cov >= 0)[0]:
+        h = int(cov[g])
+        v1, v2 = segs[h].astype(np.float64)
+        m = 0.5 * (segs[g, 0] + segs[g, 1]).astype(np.float64)
+        cp, _ = oracle.project(v1, v2, m)
+        if np.linalg.norm(m - cp) < 0.05:
+            continue
+        x = m + 0.004 * (m - cp) / np.linalg.norm(m - cp)
+        Ah, bh = A[h, :nf[h]], b[h, :nf[h]]
+        if np.all(Ah @ x <= bh - 0.02) and np.all(Ah @ m <= bh - 0.02):
+            pick = (int(g), h, x)
+            break
+    assert pick is not None, "no contained segment with room around its middle"
+    g, h, x = pick
+    seeds = torch.from_numpy(np.ascontiguousarray(segs, np.float32)).cuda()
+    added = ezo.update_polytopes(ctx, rob, obs, seeds, torch.from_numpy(x[None].astype(np.float32)).cuda(), res,
+                                 n_b=11, n_f=10)
+    torch.cuda.synchronize()
+    assert int(added[h].item()) >= 1
+    Fh = int(res.n_faces[h].item())
+    Ah = res.A[h, :Fh].cpu().numpy().astype(np.float64)
+    bh = res.b[h, :Fh].cpu().numpy().astype(np.float64)
+    assert np.any(Ah @ x > bh)                                      # the found point is excluded
+    for v in segs[h].astype(np.float64):
+        assert np.all(Ah @ v <= bh + 1e-5)                          # the set's own segment stays
+    # every path segment against every set: g is no longer covered
+    covered = ezo.segments_contained(ctx, res.A, res.b, res.n_faces, seeds).cpu().numpy()
+    missing = np.nonzero(covered < 0)[0]
+    print(f"segment {g} covered by {h}; after the edit uncovered: {missing.tolist()}")
+    assert g in missing
+    # inflate the missing segments, append their sets, check again
+    new = ezo.inflate_edges(ctx, rob, obs, seeds[missing].contiguous(),
+                            ezo.make_params(dof=dof, seed=5, edge_id_base=1000, **p))
+    torch.cuda.synchronize()
+    assert np.all(new.status.cpu().numpy() == ezo.CERTIFIED)
+    A2 = torch.cat([res.A, new.A])
+    b2 = torch.cat([res.b, new.b])
+    n2 = torch.cat([res.n_faces, new.n_faces])
+    covered2 = ezo.segments_contained(ctx, A2, b2, n2, seeds).cpu().numpy()
+    assert np.all(covered2 >= 0)
+    assert covered2[g] >= len(segs)                                 # g now lies in its own new set

@@ -5,9 +5,11 @@
   inputs (BF16 activations bound the agreement to a few 1e-3 relative);
 * training on exact-checker labels lowers the loss, and the calibrated
   margin keeps the miss rate on held-out data near the target;
-* screened inflation never screens the unadaptive test's samples, gives the
-  same polytope as the exact method when the margin screens nothing, and
-  keeps every invariant when it does;
+* screened inflation never screens the unadaptive test's samples or the
+  fail-fast projections (it screens the other samples and the bisection
+  midpoints), gives the same polytope as the exact method when the margin
+  screens nothing, and keeps every invariant when it does; the planes of a
+  screened run are placed at points that truly collide;
 * what a trained screen gains: the same certified inflation with fewer
   exact pair tests per checked configuration (times printed).
 """
@@ -144,14 +146,18 @@ def test_screened_inflation_safety(ezo, ctx):
     assert int(r0.n_faces[0].item()) == F and int(r0.status[0].item()) == int(base.status[0].item())
     assert torch.equal(r0.A[0, :F], base.A[0, :F]) and torch.equal(r0.b[0, :F], base.b[0, :F])
     assert r0.stats[0]["screened_checks"] == 0
-    # margin -inf: every optimizer sample's self pairs are skipped, test samples never
+    # margin -inf: every optimizer sample's and every bisection midpoint's
+    # self pairs are skipped; test samples and projections never
     s.set_margin(float("-inf"))
     r1 = ezo.inflate_edges(ctx, rob, obs, edges, ezo.make_params(dof=7, seed=3, surrogate=s, **p))
     torch.cuda.synchronize()
     st = r1.stats[0]
     M_total = sum(ezo.test_constants(p["eps"], p["delta"], p["tau"], k)[0] for k in range(1, st["iterations"] + 1))
+    n_b = p["n_b"]
+    bis = st["exact_checks"] - st["samples"]                  # (1 + N_b) per candidate
     print("screened stats", st, "test samples", M_total)
-    assert st["screened_checks"] == st["samples"] - M_total
+    assert bis % (1 + n_b) == 0
+    assert st["screened_checks"] == (st["samples"] - M_total) + bis // (1 + n_b) * n_b
     assert int(r1.status[0].item()) in (ezo.CERTIFIED, ezo.MAX_ITERS)
     F1 = int(r1.n_faces[0].item())
     A1 = r1.A[0, :F1].cpu().numpy().astype(np.float64)
@@ -199,9 +205,11 @@ def test_trained_screen_gain(ezo, ctx):
     edges = torch.from_numpy(data["edges"]).cuda()
     p = dict(workloads.PARAMS["dof7"])
     res = {}
+    cap = ezo.make_params(dof=7, seed=5, **p).face_capacity
+    pts = torch.full((1, cap, 7), float("nan"), dtype=torch.float32, device="cuda")
     for mode in ("exact", "screened"):
         prm = ezo.make_params(dof=7, seed=5, surrogate=s if mode == "screened" else None, **p)
-        r = ezo.inflate_edges(ctx, rob, obs, edges, prm)            # warm-up (tuning, graph capture)
+        r = ezo.inflate_edges(ctx, rob, obs, edges, prm, row_points=pts if mode == "screened" else None)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(3):
@@ -221,3 +229,12 @@ def test_trained_screen_gain(ezo, ctx):
     assert res["exact"]["status"] == ezo.CERTIFIED and res["screened"]["status"] == ezo.CERTIFIED
     assert res["exact"]["screened"] == 0 and res["screened"]["screened"] > 0
     assert res["screened"]["tests_per_sample"] < res["exact"]["tests_per_sample"]
+    # the screened bisection (midpoints screened one-sidedly) still places
+    # every plane at a point that truly collides (oracle, outside the band)
+    F = int(r.n_faces[0].item())
+    c = pts[0, 14:F].cpu().numpy().astype(np.float64)
+    assert F > 14 and np.all(np.isfinite(c))
+    f, sd, *_ = oracle.check(oracle.Robot(desc), f32_up(data["obstacles"]), c)
+    out = np.abs(sd) >= 1e-5
+    print(f"screened run: {F - 14} planes, every c* colliding: {bool(np.all(f[out] == 1))}")
+    assert np.all(f[out] == 1)
