@@ -406,6 +406,12 @@ ezo_status ezo_surrogate_predict(ezo_ctx *ctx, const ezo_surrogate *s, const flo
 ezo_status ezo_surrogate_calibrate(ezo_ctx *ctx, ezo_surrogate *s, const float *q, const float *target, int64_t n,
                                    double alpha, double *margin_out, void *stream);
 ezo_status ezo_surrogate_set_margin(ezo_surrogate *s, double margin);
+/* What an inflation screens (R22: always one-sided, never the unadaptive
+ * test's first M_k samples nor the projections onto L): EZO_SCREEN_SAMPLES,
+ * the samples after M_k; EZO_SCREEN_MIDPOINTS, the bisection midpoints; both
+ * by default.  EZO_E_INVALID for other bits. */
+enum { EZO_SCREEN_SAMPLES = 1, EZO_SCREEN_MIDPOINTS = 2 };
+ezo_status ezo_surrogate_set_scope(ezo_surrogate *s, int32_t scope);
 /* On held-out rows: miss rate = #{pred >= m and target < 0} / #{target < 0};
  * screened fraction = #{pred >= m} / n.  Blocks. */
 ezo_status ezo_surrogate_miss_rate(ezo_ctx *ctx, const ezo_surrogate *s, const float *q, const float *target,

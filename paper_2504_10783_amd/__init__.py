@@ -30,7 +30,8 @@ EXPORTS = (
     "ezo_set_phase_timing", "ezo_get_phase_timing",
     "ezo_surrogate_num_params", "ezo_surrogate_create", "ezo_surrogate_destroy", "ezo_surrogate_set_params",
     "ezo_surrogate_get_params", "ezo_surrogate_train", "ezo_surrogate_loss_grad", "ezo_surrogate_predict",
-    "ezo_surrogate_calibrate", "ezo_surrogate_set_margin", "ezo_surrogate_miss_rate",
+    "ezo_surrogate_calibrate", "ezo_surrogate_set_margin", "ezo_surrogate_set_scope",
+    "ezo_surrogate_miss_rate",
     "ezo_set_autotune", "ezo_tune_cache_export", "ezo_tune_cache_import", "ezo_tune_cache_clear",
     "ezo_check_path", "ezo_update_polytopes", "ezo_segments_contained",
     "ezo_collision_map", "ezo_collision_map_lists",
@@ -123,6 +124,7 @@ def lib():
         L.ezo_surrogate_predict.argtypes = [vp, vp, vp, i64, vp, vp]
         L.ezo_surrogate_calibrate.argtypes = [vp, vp, vp, vp, i64, dbl, C.POINTER(dbl), vp]
         L.ezo_surrogate_set_margin.argtypes = [vp, dbl]
+        L.ezo_surrogate_set_scope.argtypes = [vp, i32]
         L.ezo_surrogate_miss_rate.argtypes = [vp, vp, vp, vp, i64, C.POINTER(dbl), C.POINTER(dbl), vp]
         L.ezo_check_path.argtypes = [vp, vp, vp, i32, vp, i32, dbl, vp, i32, C.POINTER(i64), C.POINTER(i64), vp]
         L.ezo_update_polytopes.argtypes = [vp, vp, vp, i32, vp, i32, vp, i32, i32, i32, dbl, dbl, vp, vp, vp, i32,
@@ -500,6 +502,11 @@ class Surrogate:
     def set_margin(self, m):
         self.ctx._check(lib().ezo_surrogate_set_margin(self.h, float(m)))
         self.margin = float(m)
+
+    def set_scope(self, samples=True, midpoints=True):
+        """What an inflation screens: the samples after M_k and / or the
+        bisection midpoints (never the test's samples or the projections)."""
+        self.ctx._check(lib().ezo_surrogate_set_scope(self.h, (1 if samples else 0) | (2 if midpoints else 0)))
 
     def miss_rate(self, q, target, stream=None):
         miss, frac = C.c_double(), C.c_double()

@@ -782,31 +782,6 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     }
     if (blocks.empty()) blocks.push_back(make_int4(0, 0, 0, 0));
     const int NB = P > 0 ? (int)blocks.size() : 0;
-    // a block whose two links hold n_i n_j <= 128 sphere pairs is also kept as
-    // a bit mask over that product (bit a n_j + b: sphere a of link i with
-    // sphere b of link j), so the sweep derives each pair's spheres from its
-    // lane instead of loading the pair list; zero mask = list only
-    std::vector<uint4> bmask(blocks.size(), make_uint4(0u, 0u, 0u, 0u));
-    {
-        auto link_of = [&](int sorted) {
-            int j = 0;
-            while (j + 1 < dof && link_begin[j + 1] <= sorted) ++j;
-            return j;
-        };
-        for (int k = 0; k < NB; ++k) {
-            const int li = blocks[k].x, lj = blocks[k].y;
-            const int ni = link_begin[li + 1] - link_begin[li], nj = link_begin[lj + 1] - link_begin[lj];
-            if (ni * nj > 128 || ni < 1 || nj < 1) continue;
-            uint32_t w[4] = {0u, 0u, 0u, 0u};
-            for (int q = blocks[k].z; q < blocks[k].z + blocks[k].w; ++q) {
-                int a = pairs[q].x, bq = pairs[q].y;
-                if (link_of(a) != li) std::swap(a, bq);
-                const int bit = (a - link_begin[li]) * nj + (bq - link_begin[lj]);
-                w[bit >> 5] |= 1u << (bit & 31);
-            }
-            bmask[k] = make_uint4(w[0], w[1], w[2], w[3]);
-        }
-    }
     // bounding sphere of each link's spheres (link frame): centre of the
     // centres' box, radius = max distance + sphere radius
     std::vector<float4> lbound(dof, make_float4(0.f, 0.f, 0.f, 0.f));
@@ -854,7 +829,6 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     for (int j = 0; j < dof; ++j) box_begin[j + 1] += box_begin[j];
     for (int p = 0; p < Q; ++p) bpairs[p] = make_int2(box_o2s[d->box_pairs[2 * p]], box_o2s[d->box_pairs[2 * p + 1]]);
     // one allocation: [dh][sph][pairs][lbound][blocks][link_begin][s2o][limits][boxes][box_begin][box pairs]
-    // [block masks]
     size_t off_dh = 0;
     size_t off_sph = off_dh + sizeof(float4) * dof;
     size_t off_pairs = off_sph + sizeof(float4) * sph.size();
@@ -866,8 +840,7 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     size_t off_box = (off_lim + sizeof(float) * lim.size() + 15) & ~(size_t)15;
     size_t off_bb = off_box + sizeof(float4) * boxv.size();
     size_t off_bp = off_bb + sizeof(int) * box_begin.size();
-    size_t off_bm = (off_bp + sizeof(int2) * bpairs.size() + 15) & ~(size_t)15;
-    size_t total = off_bm + sizeof(uint4) * bmask.size();
+    size_t total = off_bp + sizeof(int2) * bpairs.size();
     std::vector<char> host(total);
     memcpy(host.data() + off_dh, dh.data(), sizeof(float4) * dof);
     memcpy(host.data() + off_sph, sph.data(), sizeof(float4) * sph.size());
@@ -880,7 +853,6 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     memcpy(host.data() + off_box, boxv.data(), sizeof(float4) * boxv.size());
     memcpy(host.data() + off_bb, box_begin.data(), sizeof(int) * box_begin.size());
     memcpy(host.data() + off_bp, bpairs.data(), sizeof(int2) * bpairs.size());
-    memcpy(host.data() + off_bm, bmask.data(), sizeof(uint4) * bmask.size());
     HIP_TRY(c, hipSetDevice(c->device));
     void* buf = nullptr;
     if (hipMalloc(&buf, total) != hipSuccess) return ezo_fail(c, EZO_E_NOMEM, "robot allocation failed");
@@ -908,7 +880,6 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     r->view.n_blocks = NB;
     r->view.lbound = reinterpret_cast<const float4*>(b + off_lbd);
     r->view.blocks = reinterpret_cast<const int4*>(b + off_blk);
-    r->view.bmask = reinterpret_cast<const uint4*>(b + off_bm);
     r->view.dh = reinterpret_cast<const float4*>(b + off_dh);
     r->view.sph = reinterpret_cast<const float4*>(b + off_sph);
     r->view.pairs = reinterpret_cast<const int2*>(b + off_pairs);
@@ -1254,6 +1225,8 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
     // (samples only)
     const ezo_surrogate* sur = p->surrogate;
     const bool fused_screen = sur && sur->H <= kMlpMaxH && sur->H % 16 == 0;
+    const bool screen_samples = sur && (sur->scope & EZO_SCREEN_SAMPLES);
+    const bool screen_mid = fused_screen && (sur->scope & EZO_SCREEN_MIDPOINTS);
     const MlpView screen_view = sur ? MlpView{sur->D, sur->H, sur->P, sur->W2b, sur->W3b, sur->margin}
                                     : MlpView{0, 0, nullptr, nullptr, nullptr, 0.f};
     const uint32_t k0 = (uint32_t)p->seed, k1 = (uint32_t)(p->seed >> 32);
@@ -1279,13 +1252,13 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
             mark(EZO_NUM_PHASES);
             return ls;
         }
-        if (p->surrogate && fused_screen) {
+        if (screen_samples && fused_screen) {
             // predictions for the rows the screen may skip, [M_k, |S|) of
             // every running edge, one fused forward pass per 64 rows
             EZO_KLAUNCH(c, k_screen_samples, dim3((unsigned)((S_cap + kScreenRows - 1) / kScreenRows), (unsigned)E),
                         dim3(256), 0, st, screen_view, (const float*)w_s, stride, dof, (float*)w_pred, edge_status,
                         it);
-        } else if (p->surrogate) {
+        } else if (screen_samples) {
             RowSource src{};
             src.q = (const float*)w_s;
             src.sn = 1;
@@ -1306,8 +1279,8 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         }
         if ((ls = launch_check<false>(c, r, ov, gvc, (const float*)w_s, S_cap, 1, stride, (int64_t)dof * stride,
                                       (uint8_t*)w_f, nullptr, nullptr, stride, E, edge_status, it, st,
-                                      p->surrogate ? (const float*)w_pred : nullptr,
-                                      p->surrogate ? p->surrogate->margin : 0.f, (EdgeStatsDev*)w_st))) {
+                                      screen_samples ? (const float*)w_pred : nullptr,
+                                      screen_samples ? p->surrogate->margin : 0.f, (EdgeStatsDev*)w_st))) {
             mark(EZO_NUM_PHASES);
             return ls;
         }
@@ -1318,7 +1291,7 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         if ((ls = launch_project_bisect(c, r, ov, gvb, edges, E, (const float*)w_s, stride, (const int*)w_ci,
                                         (const int*)w_nc, cand_cap, p->n_b, (float*)w_cs, (float*)w_ad,
                                         (float*)w_ts, (uint8_t*)w_pc, (uint8_t*)w_pa, edge_status, st, nullptr, -1,
-                                        fused_screen ? &screen_view : nullptr, (EdgeStatsDev*)w_st))) {
+                                        screen_mid ? &screen_view : nullptr, (EdgeStatsDev*)w_st))) {
             mark(EZO_NUM_PHASES);
             return ls;
         }
@@ -1380,6 +1353,7 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
             push(p->surrogate->W3b);
             key.push_back((uintptr_t)p->surrogate->D);
             key.push_back((uintptr_t)p->surrogate->H);
+            key.push_back((uintptr_t)p->surrogate->scope);
         }
         for (const DevBuf& wb : c->ws) push(wb.p);
         const TileCfg gc = resolve_cfg(c, tune_key(c, r, TUNE_CHECK_FLAGS, ov.n, (int64_t)S_cap * E),

@@ -21,8 +21,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <type_traits>
-
 namespace ezo {
 
 constexpr int kMaxDof = 8;
@@ -43,8 +41,6 @@ struct RobotView {
     const int2* pairs;         // [P] self pairs, indices into the sorted order, grouped by block
     const float4* lbound;      // [dof] bounding sphere of each link's spheres: local centre, radius
     const int4* blocks;        // [n_blocks] per link pair: (link i, link j, first pair, pair count)
-    const uint4* bmask;        // [n_blocks] 128-bit mask of the block's pairs over link i x link j
-                               // (bit a n_j + b), when n_i n_j <= 128; zero: use the pair list
     // boxes on links, sorted by link: box k = four float4 in the link frame,
     // (centre, h_x), (rotation row 0, h_y), (row 1, h_z), (row 2, bounding
     // radius |h|); the rotation's columns are the box axes
@@ -62,11 +58,11 @@ constexpr int kMaxLinkPairs = kMaxDof * (kMaxDof + 1) / 2;   // link pairs, same
 
 // Robot tables that a workgroup running many dependent tile checks (the
 // bisection) copies into LDS once: DH rows, link bounding spheres, self-pair
-// blocks and their masks, spheres and link sphere ranges; their reads in FK and in the
+// blocks, spheres and link sphere ranges; their reads in FK and in the
 // self-pair sweep then cost an LDS access instead of a cache access.  At
 // most this many bytes (slots >= spheres).
 __host__ __device__ inline size_t robot_stage_bytes(int slots) {
-    return 16 * (size_t)(2 * kMaxDof + 2 * kMaxLinkPairs + (slots > 0 ? slots : 1)) + 16 * ((kMaxDof + 4) / 4);
+    return 16 * (size_t)(2 * kMaxDof + kMaxLinkPairs + (slots > 0 ? slots : 1)) + 16 * ((kMaxDof + 4) / 4);
 }
 
 // Copies the tables into LDS at `base` (16-byte aligned, robot_stage_bytes
@@ -77,8 +73,7 @@ __device__ inline RobotView stage_robot(const RobotView& rb, char* base) {
     float4* dh = reinterpret_cast<float4*>(base);
     float4* lb = dh + kMaxDof;
     int4* blk = reinterpret_cast<int4*>(lb + kMaxDof);
-    uint4* bm = reinterpret_cast<uint4*>(blk + kMaxLinkPairs);
-    float4* sph = reinterpret_cast<float4*>(bm + kMaxLinkPairs);
+    float4* sph = reinterpret_cast<float4*>(blk + kMaxLinkPairs);
     int* lbeg = reinterpret_cast<int*>(sph + (rb.n_spheres > 0 ? rb.n_spheres : 1));
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int i = tid; i < rb.dof; i += nt) {
@@ -86,16 +81,12 @@ __device__ inline RobotView stage_robot(const RobotView& rb, char* base) {
         lb[i] = rb.lbound[i];
     }
     for (int i = tid; i <= rb.dof; i += nt) lbeg[i] = rb.link_begin[i];
-    for (int i = tid; i < rb.n_blocks; i += nt) {
-        blk[i] = rb.blocks[i];
-        bm[i] = rb.bmask[i];
-    }
+    for (int i = tid; i < rb.n_blocks; i += nt) blk[i] = rb.blocks[i];
     for (int i = tid; i < rb.n_spheres; i += nt) sph[i] = rb.sph[i];
     RobotView v = rb;
     v.dh = dh;
     v.lbound = lb;
     v.blocks = blk;
-    v.bmask = bm;
     v.sph = sph;
     v.link_begin = lbeg;
     return v;
@@ -265,85 +256,31 @@ struct ItemWalk {
     }
 };
 
-// DPP row shift: lane i reads lane i - N of its 16-lane row (lanes with
-// i % 16 < N read 0).  Every lane of the wave must execute it.
-template <int N>
-__device__ __forceinline__ float row_shr(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x110 + N, 0xF, 0xF, true));
-}
-
 // FK phase: t.q[c][j] (c < n_valid) -> t.cen[s][c].  Ends with a barrier.
 // Only the n_valid >= 1 configurations of the tile are computed.
 // BOX = false compiles the sphere-only path (no box code, fewer registers);
 // BOX = true adds the boxes of RobotView and ObsView.
-//
-// A configuration is carried by a group of kMaxDof consecutive lanes (groups
-// never straddle a 16-lane DPP row); lane j of the group builds link j's DH
-// transform A_j (its joint's sine and cosine included), and the group forms
-// the prefix products T_j = B A_0 A_1 ... A_j (B: the shift into the
-// obstacle frame) by an inclusive scan of log2(kMaxDof) steps, each lane
-// composing the transform of lane j - 2^s on the left (rows shifted across
-// lanes by DPP).  Lane j then places link j's bounding sphere, spheres and
-// boxes.  A chain of dof compositions becomes three dependent ones, and no
-// link's prefix is composed twice.
 template <bool BOX>
 __device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const TileSmem& t, int T, int n_valid) {
-    static_assert(kMaxDof == 8, "the scan below covers eight links");
     const int dof = rb.dof;
-    const int link = (int)threadIdx.x & (kMaxDof - 1);
-    const int ng = (int)blockDim.x / kMaxDof;
+    for (ItemWalk w(n_valid); w.k < dof; w.next(n_valid)) {
+        const int c = w.c, j = w.k;
+        float s = 0.f, co = 1.f;
+        if (!((rb.prismatic >> j) & 1u)) sincosf(t.q[c * kMaxDof + j], &s, &co);
+        t.trig[j * T + c] = make_float2(co, s);
+    }
+    __syncthreads();
     const float4 sh = ob.centre[0];
-    for (int c0 = 0; c0 < n_valid; c0 += ng) {           // uniform over the workgroup
-        const int c = c0 + (int)threadIdx.x / kMaxDof;
-        const bool live = c < n_valid && link < dof;
+    for (ItemWalk w(n_valid); w.k < dof; w.next(n_valid)) {
+        const int c = w.c, link = w.k;
         float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
-        float p[3] = {0.f, 0.f, 0.f};
-        if (live) {
-            // A = Rz(theta) Tz(d) Tx(a) Rx(alpha)
-            float4 dh = rb.dh[link];
-            float s = 0.f, co = 1.f;
-            const float qj = t.q[c * kMaxDof + link];
-            if ((rb.prismatic >> link) & 1u) dh.y += qj;
-            else sincosf(qj, &s, &co);
-            const float ca = dh.z, sa = dh.w;
-            R[0] = co; R[1] = -s * ca; R[2] = s * sa;
-            R[3] = s;  R[4] = co * ca; R[5] = -co * sa;
-            R[6] = 0.f; R[7] = sa;     R[8] = ca;
-            p[0] = dh.x * co;
-            p[1] = dh.x * s;
-            p[2] = dh.y;
+        float p[3] = {-sh.x, -sh.y, -sh.z};
+        for (int l = 0; l <= link; ++l) {
+            const float2 cs = t.trig[l * T + c];
+            float4 dh = rb.dh[l];
+            if ((rb.prismatic >> l) & 1u) dh.y += t.q[c * kMaxDof + l];
+            dh_compose(R, p, cs.x, cs.y, dh);
         }
-        if (link == 0) {
-            p[0] -= sh.x;
-            p[1] -= sh.y;
-            p[2] -= sh.z;
-        }
-        auto step = [&](auto nshift) {
-            constexpr int N = decltype(nshift)::value;
-            float Rm[9], pm[3];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) Rm[k] = row_shr<N>(R[k]);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) pm[k] = row_shr<N>(p[k]);
-            if (link >= N) {
-                float nR[9], np[3];
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-#pragma unroll
-                    for (int col = 0; col < 3; ++col)
-                        nR[3 * r + col] = fmaf(Rm[3 * r], R[col], fmaf(Rm[3 * r + 1], R[3 + col], Rm[3 * r + 2] * R[6 + col]));
-                    np[r] = fmaf(Rm[3 * r], p[0], fmaf(Rm[3 * r + 1], p[1], fmaf(Rm[3 * r + 2], p[2], pm[r])));
-                }
-#pragma unroll
-                for (int k = 0; k < 9; ++k) R[k] = nR[k];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) p[k] = np[k];
-            }
-        };
-        step(std::integral_constant<int, 1>{});
-        if (dof > 2) step(std::integral_constant<int, 2>{});
-        if (dof > 4) step(std::integral_constant<int, 4>{});
-        if (!live) continue;
         {
             const float4 lc = rb.lbound[link];
             float4 o;
@@ -720,40 +657,16 @@ __device__ inline unsigned tile_pairs_grid(const RobotView& rb, const ObsView& o
             const int item = t.wl[it];
             const int c = item & 255;
             if (hit[c]) continue;                          // wave-uniform
-            const int bk = item >> 8;
-            const int4 blk = rb.blocks[bk];
-            const uint4 mk = rb.bmask[bk];
+            const int4 blk = rb.blocks[item >> 8];
             bool found = false;
-            if ((mk.x | mk.y | mk.z | mk.w) != 0u) {
-                // dense block: lane p takes bit p of the mask, sphere a = p / n_j
-                // of link i and b = p % n_j of link j (the quotient from a
-                // rounded reciprocal is exact: p < 128, n_j <= 128)
-                const int si = rb.link_begin[blk.x], sj = rb.link_begin[blk.y];
-                const int nj = rb.link_begin[blk.y + 1] - sj;
-                const int nn = (rb.link_begin[blk.x + 1] - si) * nj;
-                const float inv = __builtin_amdgcn_rcpf((float)nj);
-                for (int p = lane; p < nn; p += 64) {
-                    const uint32_t word = p < 32 ? mk.x : (p < 64 ? mk.y : (p < 96 ? mk.z : mk.w));
-                    if (!((word >> (p & 31)) & 1u)) continue;
-                    const int a = (int)(((float)p + 0.5f) * inv);
-                    const int bb = p - a * nj;
-                    const float4 A = t.cen[(si + a) * T + c];
-                    const float4 B = t.cen[(sj + bb) * T + c];
-                    const float ex = A.x - B.x, ey = A.y - B.y, ez = A.z - B.z;
-                    const float Rr = A.w + B.w;
-                    ++ntest;
-                    found |= fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < Rr * Rr;
-                }
-            } else {
-                for (int p = lane; p < blk.w; p += 64) {
-                    const int2 pr = rb.pairs[blk.z + p];
-                    const float4 a = t.cen[pr.x * T + c];
-                    const float4 b = t.cen[pr.y * T + c];
-                    const float ex = a.x - b.x, ey = a.y - b.y, ez = a.z - b.z;
-                    const float Rr = a.w + b.w;
-                    ++ntest;
-                    found |= fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < Rr * Rr;
-                }
+            for (int p = lane; p < blk.w; p += 64) {
+                const int2 pr = rb.pairs[blk.z + p];
+                const float4 a = t.cen[pr.x * T + c];
+                const float4 b = t.cen[pr.y * T + c];
+                const float ex = a.x - b.x, ey = a.y - b.y, ez = a.z - b.z;
+                const float Rr = a.w + b.w;
+                ++ntest;
+                found |= fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < Rr * Rr;
             }
             if (found) hit[c] = 1;
         }
@@ -770,36 +683,20 @@ __device__ inline unsigned tile_pairs_grid(const RobotView& rb, const ObsView& o
             if (!(fx >= 0.f && fy >= 0.f && fz >= 0.f && fx < (float)G && fy < (float)G && fz < (float)G)) continue;
             const int cx = min((int)fx, G - 1), cy = min((int)fy, G - 1), cz = min((int)fz, G - 1);
             const int cell = (cz * G + cy) * G + cx;
-            // the count and the list's first eight entries are loaded together
-            // (a cell's list row of cap >= 8 entries always exists, 16-byte
-            // aligned), so the first record reads wait for one load, not two
-            const ushort4* lst4 = reinterpret_cast<const ushort4*>(gv.list + (size_t)cell * gv.cap);
-            const uint4 l8 = *reinterpret_cast<const uint4*>(lst4);
             const int cnt = gv.count[cell];
             const bool full = cnt > gv.cap;
             const int n = full ? ob.n : cnt;
             // list entries four at a time (cell lists are 8-byte aligned), the
             // four record reads issued together
+            const ushort4* lst4 = reinterpret_cast<const ushort4*>(gv.list + (size_t)cell * gv.cap);
             bool found = false;
             for (int k0 = 0; k0 < n && !found; k0 += 4) {
                 int oi[4];
                 if (full) {
                     oi[0] = k0; oi[1] = k0 + 1; oi[2] = k0 + 2; oi[3] = k0 + 3;
                 } else {
-                    uint32_t lo, hi;
-                    if (k0 == 0) {
-                        lo = l8.x;
-                        hi = l8.y;
-                    } else if (k0 == 4) {
-                        lo = l8.z;
-                        hi = l8.w;
-                    } else {
-                        const ushort4 v = lst4[k0 >> 2];
-                        lo = (uint32_t)v.x | ((uint32_t)v.y << 16);
-                        hi = (uint32_t)v.z | ((uint32_t)v.w << 16);
-                    }
-                    oi[0] = (int)(lo & 0xffffu); oi[1] = (int)(lo >> 16);
-                    oi[2] = (int)(hi & 0xffffu); oi[3] = (int)(hi >> 16);
+                    const ushort4 v = lst4[k0 >> 2];
+                    oi[0] = v.x; oi[1] = v.y; oi[2] = v.z; oi[3] = v.w;
                 }
                 float4 O[4];
 #pragma unroll

@@ -92,6 +92,7 @@ struct ezo_surrogate {
     int D = 0, H = 0;
     int64_t n_params = 0;
     float margin = INFINITY;            // screen threshold (calibrated); +inf screens nothing
+    int scope = EZO_SCREEN_SAMPLES | EZO_SCREEN_MIDPOINTS;   // what an inflation screens
     float* P = nullptr;                 // FP32 master parameters
     float* G = nullptr;                 // gradient
     float* m = nullptr;                 // Adam moments

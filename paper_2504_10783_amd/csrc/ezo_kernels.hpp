@@ -336,18 +336,29 @@ template <int D, int L>
 __device__ __forceinline__ void walk_step(const float* rowA, const float* rowb, int F, int sub, const float (&u)[D],
                                           float wt, float (&x)[D], int nbox) {
     float tlo = -INFINITY, thi = INFINITY;
+    // coordinate j = m L + sub of this lane: its u_j and x_j picked from the
+    // register arrays by selects (no divergent per-coordinate blocks)
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-        if (j >= nbox || (j % L) != sub) continue;
-        const float r = __builtin_amdgcn_rcpf(u[j]), rn = __builtin_amdgcn_rcpf(-u[j]);
-        const float th = (rowb[j] - x[j]) * r;           // row +e_j <= hi_j
-        const float tl = (rowb[nbox + j] - (-x[j])) * rn; // row -e_j <= -lo_j
-        if (u[j] > 0.f) {
-            thi = fminf(thi, th);
-            tlo = fmaxf(tlo, tl);
-        } else if (u[j] < 0.f) {
-            tlo = fmaxf(tlo, th);
-            thi = fminf(thi, tl);
+    for (int m = 0; m * L < D; ++m) {
+        float uj = 0.f, xj = 0.f;
+#pragma unroll
+        for (int s2 = 0; s2 < L && m * L + s2 < D; ++s2)
+            if (s2 == sub) {
+                uj = u[m * L + s2];
+                xj = x[m * L + s2];
+            }
+        const int j = m * L + sub;
+        if (j < nbox) {
+            const float r = __builtin_amdgcn_rcpf(uj), rn = __builtin_amdgcn_rcpf(-uj);
+            const float th = (rowb[j] - xj) * r;              // row +e_j <= hi_j
+            const float tl = (rowb[nbox + j] - (-xj)) * rn;   // row -e_j <= -lo_j
+            if (uj > 0.f) {
+                thi = fminf(thi, th);
+                tlo = fmaxf(tlo, tl);
+            } else if (uj < 0.f) {
+                tlo = fmaxf(tlo, th);
+                thi = fminf(thi, tl);
+            }
         }
     }
     for (int f = 2 * nbox + sub; f < F; f += L) {
@@ -390,7 +401,9 @@ __device__ __forceinline__ void sample_block(char* smem, int dof, const float* _
     for (int f = threadIdx.x; f < F; f += blockDim.x) rowb[f] = bvec[(size_t)e * cap + f];
     __syncthreads();
     // the joint box as the first 2 dof rows?  (every polytope of the fused
-    // loop starts so; a caller's P may not)
+    // loop starts so; a caller's P may not).  Used with at most four lanes
+    // per walk: with more, a lane holds one or two rows of P and the box
+    // rows' own path (a select of the lane's coordinate) is no cheaper.
     int nbox = 0;
     if (F >= 2 * dof) {                                   // uniform
         bool ok = true;
@@ -398,7 +411,7 @@ __device__ __forceinline__ void sample_block(char* smem, int dof, const float* _
             const int f = i / dof, j = i % dof;
             ok = ok && rowA[f * D + j] == (j == f % dof ? (f < dof ? 1.f : -1.f) : 0.f);
         }
-        nbox = __syncthreads_and(ok ? 1 : 0) ? dof : 0;
+        nbox = (__syncthreads_and(ok ? 1 : 0) && L <= 4) ? dof : 0;
     }
     const int lane = threadIdx.x & 63;
     const int sub = lane & (L - 1);                       // position in the walk's lane group
@@ -798,10 +811,9 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rg, ObsView o
 // ---------------------------------------------------------------------------
 // Placement rounds of one edge.  REG: the thread's candidates j = tid +
 // q blockDim (q < kPlaceReg) keep c* and their (t*, index) keys in registers
-// (needs n <= kPlaceReg blockDim; the chosen candidate's direction a is read
-// from global memory by the thread that builds the row); otherwise both are
-// read from global memory every round and the alive flags live in LDS.
-constexpr int kPlaceReg = 8;
+// (needs n <= kPlaceReg blockDim); otherwise both are read from global memory
+// every round and the alive flags live in LDS.
+constexpr int kPlaceReg = 4;
 
 template <bool REG>
 __device__ inline void place_rounds(int e, int dof, const float* __restrict__ v, const float* __restrict__ cs,
@@ -815,6 +827,7 @@ __device__ inline void place_rounds(int e, int dof, const float* __restrict__ v,
     int nf = min(max(n_faces[e], 0), cap);
     int placed = 0;
     float cx[REG ? kPlaceReg : 1][kMaxDof];
+    float ax[REG ? kPlaceReg : 1][kMaxDof];
     unsigned long long key[REG ? kPlaceReg : 1];
     bool al[REG ? kPlaceReg : 1];
     // smallest (t*, index) key among this thread's alive candidates; after a
@@ -829,7 +842,10 @@ __device__ inline void place_rounds(int e, int dof, const float* __restrict__ v,
             if (al[q]) {
                 key[q] = ((unsigned long long)__float_as_uint(ts[j]) << 32) | (unsigned)j;
 #pragma unroll
-                for (int k = 0; k < kMaxDof; ++k) cx[q][k] = k < dof ? cs[(size_t)k * cand_cap + j] : 0.f;
+                for (int k = 0; k < kMaxDof; ++k) {
+                    cx[q][k] = k < dof ? cs[(size_t)k * cand_cap + j] : 0.f;
+                    ax[q][k] = k < dof ? ad[(size_t)k * cand_cap + j] : 0.f;
+                }
                 best = key[q] < best ? key[q] : best;
             }
         }
@@ -870,11 +886,14 @@ __device__ inline void place_rounds(int e, int dof, const float* __restrict__ v,
                     if (k >= dof) break;
                     float a, c;
                     if constexpr (REG) {
-                        a = ad[(size_t)k * cand_cap + jb];
+                        a = ax[0][k];
                         c = cx[0][k];
 #pragma unroll
                         for (int q = 1; q < kPlaceReg; ++q)
-                            if (q == qb) c = cx[q][k];
+                            if (q == qb) {
+                                a = ax[q][k];
+                                c = cx[q][k];
+                            }
                     } else {
                         a = ad[(size_t)k * cand_cap + jb];
                         c = cs[(size_t)k * cand_cap + jb];

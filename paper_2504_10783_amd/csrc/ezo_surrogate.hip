@@ -467,6 +467,12 @@ ezo_status ezo_surrogate_set_margin(ezo_surrogate* s, double margin) {
     return EZO_OK;
 }
 
+ezo_status ezo_surrogate_set_scope(ezo_surrogate* s, int32_t scope) {
+    if (!s || (scope & ~(EZO_SCREEN_SAMPLES | EZO_SCREEN_MIDPOINTS)) != 0) return EZO_E_INVALID;
+    s->scope = scope;
+    return EZO_OK;
+}
+
 ezo_status ezo_surrogate_miss_rate(ezo_ctx* c, const ezo_surrogate* s, const float* q, const float* target, int64_t n,
                                    double* miss_rate, double* screened_fraction, void* stream) {
     if (!c || !s || n <= 0 || !q || !target) return c ? ezo_fail(c, EZO_E_INVALID, "bad argument") : EZO_E_INVALID;

@@ -158,6 +158,19 @@ def test_screened_inflation_safety(ezo, ctx):
     print("screened stats", st, "test samples", M_total)
     assert bis % (1 + n_b) == 0
     assert st["screened_checks"] == (st["samples"] - M_total) + bis // (1 + n_b) * n_b
+    # scope: the samples only, then the midpoints only
+    s.set_scope(samples=True, midpoints=False)
+    r2 = ezo.inflate_edges(ctx, rob, obs, edges, ezo.make_params(dof=7, seed=3, surrogate=s, **p))
+    torch.cuda.synchronize()
+    st2 = r2.stats[0]
+    M2 = sum(ezo.test_constants(p["eps"], p["delta"], p["tau"], k)[0] for k in range(1, st2["iterations"] + 1))
+    assert st2["screened_checks"] == st2["samples"] - M2
+    s.set_scope(samples=False, midpoints=True)
+    r3 = ezo.inflate_edges(ctx, rob, obs, edges, ezo.make_params(dof=7, seed=3, surrogate=s, **p))
+    torch.cuda.synchronize()
+    st3 = r3.stats[0]
+    assert st3["screened_checks"] == (st3["exact_checks"] - st3["samples"]) // (1 + n_b) * n_b
+    s.set_scope()
     assert int(r1.status[0].item()) in (ezo.CERTIFIED, ezo.MAX_ITERS)
     F1 = int(r1.n_faces[0].item())
     A1 = r1.A[0, :F1].cpu().numpy().astype(np.float64)
