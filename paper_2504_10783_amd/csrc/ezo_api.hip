@@ -332,9 +332,15 @@ ezo_status launch_sample(ezo_ctx* c, int dof, const float* A, const float* b, co
     if (active) {
         const size_t lds = sample_smem_bytes(D, 16, cap, 256);
         dim3 grid((unsigned)(((int64_t)max_samples * 16 + 255) / 256), (unsigned)E), block(256);
+        // a 7-DOF arm walks in exactly seven coordinates (the eighth of the
+        // padded width only adds zero terms: the samples are the same bits)
         if (D == 4)
             EZO_KLAUNCH(c, k_sample_auto<4>, grid, block, lds, st, dof, A, b, n_faces, cap, edges, key0, key1, eid0,
                         n_mix, S, stride, status, it, active, kSampleWalks16, kSampleWalks4, edge_ids);
+        else if (dof == 7)
+            EZO_KLAUNCH(c, k_sample_auto<7>, grid, block, sample_smem_bytes(7, 16, cap, 256), st, dof, A, b, n_faces,
+                        cap, edges, key0, key1, eid0, n_mix, S, stride, status, it, active, kSampleWalks16,
+                        kSampleWalks4, edge_ids);
         else
             EZO_KLAUNCH(c, k_sample_auto<8>, grid, block, lds, st, dof, A, b, n_faces, cap, edges, key0, key1, eid0,
                         n_mix, S, stride, status, it, active, kSampleWalks16, kSampleWalks4, edge_ids);
