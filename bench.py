@@ -326,7 +326,10 @@ def screen_measure(args, name, epochs):
 
     data = workloads.load(name)
     desc = workloads.robot(data)
+    if args.tune_import:
+        ezo.tune_cache_import(open(args.tune_import).read())
     ctx = ezo.Context(0)
+    ctx.set_autotune(not args.no_autotune)
     rob = ezo.Robot(ctx, desc)
     dev = torch.device("cuda", 0)
     n_tr, n_cal, n_te = 3_600_000 // 4096 * 4096, 200_000, 200_000
@@ -393,6 +396,10 @@ def screen_measure(args, name, epochs):
 
 def screen_compare(args):
     r = screen_measure(args, args.workload, args.screen_epochs)
+    if args.tune_export:
+        import paper_2504_10783_amd as ezo
+        with open(args.tune_export, "w") as f:
+            f.write(ezo.tune_cache_export())
     line = {"metric": "edges inflated/sec, learned self-collision screen vs exact (7-DOF)",
             "value": r["screened"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

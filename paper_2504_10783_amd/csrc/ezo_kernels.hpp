@@ -102,42 +102,48 @@ __global__ void __launch_bounds__(256) k_prep_obstacles(const float* __restrict_
     }
 }
 
-// Grid lists: one wave per cell; 64 obstacles per step tested by their
-// distance to the cell's box, survivors appended in index order by ballot
-// prefix.
-__global__ void __launch_bounds__(256) k_build_grid(const float4* __restrict__ rec, int n, const GridGeom* __restrict__ geom,
-                                                    int G, int cap, int* __restrict__ count,
-                                                    unsigned short* __restrict__ list) {
-    const int cell = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+// Grid lists, built from the obstacles' side: one wave per obstacle, its
+// lanes over the block of cells its reach can touch (the cell-index range of
+// [o - R, o + R] widened by one cell on each side, R = r_o + reach), each
+// cell kept by the same exact test of the distance from o to the cell's box;
+// a kept obstacle takes the next slot of the cell by an atomic count
+// (count[] must be zero on entry).  Which obstacles a cell lists is exactly
+// what a cell-by-cell scan of all obstacles lists; their order within the
+// list is whatever the atomics leave (the flags sweep only asks whether any
+// of them collides).  A count above cap marks an overflowing cell (the sweep
+// then scans every obstacle).
+__global__ void __launch_bounds__(256) k_grid_scatter(const float4* __restrict__ rec, int n,
+                                                      const GridGeom* __restrict__ geom, int G, int cap,
+                                                      int* __restrict__ count, unsigned short* __restrict__ list) {
+    const int o = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
-    if (cell >= G * G * G) return;
-    if (n > 65535) {                       // indices do not fit the list type: every cell scans all
-        if (lane == 0) count[cell] = cap + 1;
-        return;
-    }
+    if (o >= n) return;
     const GridGeom g = *geom;
-    const int cx = cell % G, cy = (cell / G) % G, cz = cell / (G * G);
-    const float lx = g.ox + cx * g.hx, ly = g.oy + cy * g.hy, lz = g.oz + cz * g.hz;
-    const float ux = lx + g.hx, uy = ly + g.hy, uz = lz + g.hz;
-    int total = 0;
-    unsigned short* lst = list + (size_t)cell * cap;
-    for (int o0 = 0; o0 < n; o0 += 64) {
-        const int o = o0 + lane;
-        bool in = false;
-        if (o < n) {
-            const float4 O = rec[o];
-            const float dx = fmaxf(fmaxf(lx - O.x, O.x - ux), 0.f);
-            const float dy = fmaxf(fmaxf(ly - O.y, O.y - uy), 0.f);
-            const float dz = fmaxf(fmaxf(lz - O.z, O.z - uz), 0.f);
-            const float R = O.w + g.reach;
-            in = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < R * R;
-        }
-        const unsigned long long m = __ballot(in);
-        const int pos = total + __popcll(m & ((1ull << lane) - 1ull));
-        if (in && pos < cap) lst[pos] = (unsigned short)o;
-        total += __popcll(m);
+    const float4 O = rec[o];
+    const float R = O.w + g.reach;
+    int lo[3], hi[3];
+    const float oc[3] = {O.x, O.y, O.z}, orig[3] = {g.ox, g.oy, g.oz}, inv[3] = {g.ihx, g.ihy, g.ihz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {           // clamped in FP32 (an infinite reach covers the grid)
+        lo[a] = (int)fmaxf(floorf((oc[a] - R - orig[a]) * inv[a]) - 1.f, 0.f);
+        hi[a] = (int)fminf(floorf((oc[a] + R - orig[a]) * inv[a]) + 1.f, (float)(G - 1));
     }
-    if (lane == 0) count[cell] = total;
+    const int nx = hi[0] - lo[0] + 1, ny = hi[1] - lo[1] + 1, nz = hi[2] - lo[2] + 1;
+    if (nx <= 0 || ny <= 0 || nz <= 0) return;
+    const int total = nx * ny * nz;
+    for (int k = lane; k < total; k += 64) {
+        const int cx = lo[0] + k % nx, cy = lo[1] + (k / nx) % ny, cz = lo[2] + k / (nx * ny);
+        const float lx = g.ox + cx * g.hx, ly = g.oy + cy * g.hy, lz = g.oz + cz * g.hz;
+        const float ux = lx + g.hx, uy = ly + g.hy, uz = lz + g.hz;
+        const float dx = fmaxf(fmaxf(lx - O.x, O.x - ux), 0.f);
+        const float dy = fmaxf(fmaxf(ly - O.y, O.y - uy), 0.f);
+        const float dz = fmaxf(fmaxf(lz - O.z, O.z - uz), 0.f);
+        if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < R * R) {
+            const int cell = (cz * G + cy) * G + cx;
+            const int pos = atomicAdd(&count[cell], 1);
+            if (pos < cap) list[(size_t)cell * cap + pos] = (unsigned short)o;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
