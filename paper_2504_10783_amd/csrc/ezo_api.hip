@@ -85,6 +85,7 @@ int pick_W(int n_obs) {
 }
 
 constexpr int kGridCap = 128;
+static_assert(kGridCap % 8 == 0, "the sweep loads cell lists eight entries (16 bytes) at a time");
 
 int grid_dim(int n_obs) { return n_obs >= 256 ? 32 : (n_obs >= 32 ? 16 : 8); }
 
@@ -184,11 +185,11 @@ bool bisect_shape_built(const TileCfg& g) {
 }
 
 // A shape is usable when its LDS fits and staging is possible where asked.
-bool cfg_valid(const ezo_ctx* c, const TileCfg& g, int S, int n_obs, bool sd, bool bisect = false) {
+bool cfg_valid(const ezo_ctx* c, const TileCfg& g, int S, int P, int n_obs, bool sd, bool bisect = false) {
     if (!pow2_tile(g.T) || g.W < 1 || g.W > 16 || g.depth < 1 || g.depth > 3) return false;
     if (bisect ? !bisect_shape_built(g) : g.depth != 1) return false;
     const int T = tile_configs(g, bisect);
-    const size_t rs = bisect ? robot_stage_bytes(S) : 0;
+    const size_t rs = bisect ? robot_stage_bytes(S, P) : 0;
     if (g.stage && (sd || !stage_fits(c, T, S, g.W, n_obs, rs))) return false;
     return tile_smem_bytes(T, S, g.W) + (g.stage ? 16 * (size_t)n_obs : 0) + rs <= c->lds_cap;
 }
@@ -220,23 +221,23 @@ TileCfg heuristic_bisect(const ezo_ctx* c, const ezo_robot* r, int n_obs, int64_
     TileCfg g;
     g.W = 4;
     g.depth = 1;
-    const size_t rs = robot_stage_bytes(r->slots);
+    const size_t rs = robot_stage_bytes(r->slots, r->P);
     g.T = std::max(std::min(pick_T(c, items, r->slots, g.W, rs), 64), 2);
     g.stage = stage_fits(c, g.T, r->slots, g.W, n_obs, rs) ? 1 : 0;
     return g;
 }
 
-TileCfg resolve_cfg(const ezo_ctx* c, const TuneKey& k, const TileCfg& fallback, int S, int n_obs, bool sd,
+TileCfg resolve_cfg(const ezo_ctx* c, const TuneKey& k, const TileCfg& fallback, int S, int P, int n_obs, bool sd,
                     bool bisect = false) {
     TileCfg g;
-    if (ezo_tune_lookup(k, &g) && cfg_valid(c, g, S, n_obs, sd, bisect)) return g;
+    if (ezo_tune_lookup(k, &g) && cfg_valid(c, g, S, P, n_obs, sd, bisect)) return g;
     return fallback;
 }
 
 // Candidate shapes: every fitting T x W x staging (x bisection depth 1..3);
 // T = configurations (check, 4..64) or candidates (bisection, 1..64) per
 // workgroup; items = configurations or candidate slots.
-std::vector<TileCfg> tile_candidates(const ezo_ctx* c, int S, int n_obs, bool sd, std::initializer_list<int> Ws,
+std::vector<TileCfg> tile_candidates(const ezo_ctx* c, int S, int P, int n_obs, bool sd, std::initializer_list<int> Ws,
                                      int64_t items, bool bisect = false) {
     std::vector<TileCfg> v;
     for (int dp = 1; dp <= (bisect ? 3 : 1); ++dp)
@@ -245,7 +246,7 @@ std::vector<TileCfg> tile_candidates(const ezo_ctx* c, int S, int n_obs, bool sd
             for (int W : Ws)
                 for (int st = 0; st <= (sd ? 0 : 1); ++st) {
                     TileCfg g{T, W, st, dp};
-                    if (cfg_valid(c, g, S, n_obs, sd, bisect)) v.push_back(g);
+                    if (cfg_valid(c, g, S, P, n_obs, sd, bisect)) v.push_back(g);
                 }
         }
     return v;
@@ -263,7 +264,7 @@ ezo_status launch_check(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const
     } else {
         const int64_t items = n * n_batch;
         g = resolve_cfg(c, tune_key(c, r, SD ? TUNE_CHECK_SD : TUNE_CHECK_FLAGS, ov.n, items),
-                        heuristic_check(c, r, ov.n, items, SD), r->slots, ov.n, SD);
+                        heuristic_check(c, r, ov.n, items, SD), r->slots, r->P, ov.n, SD);
     }
     const int T = g.T, W = g.W;
     if (T == 0) return ezo_fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
@@ -408,7 +409,7 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
         g = *shape;
     } else {
         const int64_t items = (int64_t)cand_cap * E;
-        g = resolve_cfg(c, tune_key(c, r, TUNE_BISECT, ov.n, items), heuristic_bisect(c, r, ov.n, items), r->slots,
+        g = resolve_cfg(c, tune_key(c, r, TUNE_BISECT, ov.n, items), heuristic_bisect(c, r, ov.n, items), r->slots, r->P,
                         ov.n, false, true);
     }
     const bool box = r->B > 0 || ov.n_ebox > 0;
@@ -426,7 +427,7 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
     ObsView ovs = ov;
     ovs.lds_n = g.stage ? ov.n : 0;
     size_t lds = tile_smem_bytes(tile_configs(g, true), r->slots, W) + 16 * (size_t)ovs.lds_n +
-                 robot_stage_bytes(r->slots);
+                 robot_stage_bytes(r->slots, r->P);
     if (scr) {
         lds += mlp_tile_smem_bytes(1) + 16 * sizeof(float);
         if (lds > c->lds_cap && ovs.lds_n > 0) {        // drop the obstacle staging first
@@ -513,8 +514,8 @@ ezo_status tune_check_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov,
     if (!c->autotune || ezo_tune_lookup(k, &g)) return EZO_OK;
     const int64_t n_t = SD ? std::min<int64_t>(n, std::max<int64_t>(65536, (1LL << 28) / std::max(ov.n, 256)))
                            : std::min<int64_t>(n, 1LL << 19);
-    const auto cands = SD ? tile_candidates(c, r->slots, ov.n, true, {1, 2, 4, 8, 16}, n_t)
-                          : tile_candidates(c, r->slots, ov.n, false, {1, 2, 4, 8}, n_t);
+    const auto cands = SD ? tile_candidates(c, r->slots, r->P, ov.n, true, {1, 2, 4, 8, 16}, n_t)
+                          : tile_candidates(c, r->slots, r->P, ov.n, false, {1, 2, 4, 8}, n_t);
     if (cands.empty()) return EZO_OK;
     IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
     auto run = [&](const TileCfg& cfg) {
@@ -532,7 +533,7 @@ ezo_status tune_bisect_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov
     const TuneKey k = tune_key(c, r, TUNE_BISECT, ov.n, (int64_t)cand_cap * E);
     TileCfg g;
     if (!c->autotune || ezo_tune_lookup(k, &g)) return EZO_OK;
-    const auto cands = tile_candidates(c, r->slots, ov.n, false, {1, 2, 4, 8}, (int64_t)cand_cap * E, true);
+    const auto cands = tile_candidates(c, r->slots, r->P, ov.n, false, {1, 2, 4, 8, 16}, (int64_t)cand_cap * E, true);
     if (cands.empty()) return EZO_OK;
     auto run = [&](const TileCfg& cfg) {
         return launch_project_bisect(c, r, ov, gv, edges, E, S, stride, cand_idx, n_cands, cand_cap, n_b, c_star,
@@ -543,10 +544,15 @@ ezo_status tune_bisect_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov
 
 // Fused inflation: the loop's workspace (and the caller's A, b, n_faces) are
 // free until the edges are initialised, so the shapes of the loop's check
-// and bisection launches are timed there on a stand-in for a typical
-// iteration (the loop's sampler picks its lanes per walk on the device): the joint box written as 2 dof + 2 n_f rows (box rows repeated),
-// |S| hit-and-run samples per edge from it, and as candidates the first n_p
-// of them in collision.
+// and bisection launches are timed there on a stand-in for the loop's
+// iterations (the loop's sampler picks its lanes per walk on the device):
+// the joint box written as 2 dof + 2 n_f rows (box rows repeated), |S|
+// hit-and-run samples per edge from it, and as candidates the first n_p of
+// them in collision.  The box collides widely, so these candidates stand for
+// a first iteration only; the loop goes on until about an eps fraction of
+// the samples collide, so a bisection shape is timed on the full candidate
+// lists once plus three times on their first max(16, 2 eps n_p) entries per
+// edge (the lighter iterations after the first).
 constexpr int kItersPerGraph = 4;        // iterations captured per replayed graph
 // Candidate sample counts N_p of the sample-count tuner, largest first (its
 // order of preference: more samples give more hyperplanes per iteration), the
@@ -589,7 +595,7 @@ ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, con
                                    stride, E, nullptr, it, st, nullptr, 0.f, nullptr, &cfg);
     };
     if (need_c) {
-        const auto cands = tile_candidates(c, r->slots, ov.n, false, {1, 2, 4, 8}, (int64_t)S_cap * E);
+        const auto cands = tile_candidates(c, r->slots, r->P, ov.n, false, {1, 2, 4, 8}, (int64_t)S_cap * E);
         if (!cands.empty() && (s = ezo_tune_search(c, kc, cands, st, run_c, &g))) return s;
     }
     if (!need_b) return EZO_OK;
@@ -598,13 +604,22 @@ ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, con
     hipLaunchKernelGGL(k_test_select, dim3(E), dim3(1024), 0, st, w_f, stride, p->n_p, p->n_b, w_ci, cand_cap, w_nc,
                        nullptr, nullptr, nullptr, nullptr, sel);
     HIP_TRY(c, hipGetLastError());
-    const auto cands = tile_candidates(c, r->slots, ov.n, false, {1, 2, 4, 8}, (int64_t)cand_cap * E, true);
+    const auto cands = tile_candidates(c, r->slots, r->P, ov.n, false, {1, 2, 4, 8, 16}, (int64_t)cand_cap * E, true);
     if (cands.empty()) return EZO_OK;
+    const int light = std::max(16, (int)std::ceil(2.0 * p->eps * cand_cap));
+    int* w_nc_light = reinterpret_cast<int*>(w_f);      // the flags are free once selected (E <= stride E / 4)
+    hipLaunchKernelGGL(k_cap_counts, dim3((E + 255) / 256), dim3(256), 0, st, (const int*)w_nc, w_nc_light, E, light);
+    HIP_TRY(c, hipGetLastError());
     auto run_b = [&](const TileCfg& cfg) {
-        return launch_project_bisect(c, r, ov, gv, edges, E, w_s, stride, w_ci, w_nc, cand_cap, p->n_b, w_cs, w_ad,
-                                     w_ts, w_pc, nullptr, nullptr, st, &cfg);
+        ezo_status e = launch_project_bisect(c, r, ov, gv, edges, E, w_s, stride, w_ci, w_nc, cand_cap, p->n_b, w_cs,
+                                             w_ad, w_ts, w_pc, nullptr, nullptr, st, &cfg);
+        for (int i = 0; i < 3 && e == EZO_OK; ++i)
+            e = launch_project_bisect(c, r, ov, gv, edges, E, w_s, stride, w_ci, w_nc_light, cand_cap, p->n_b, w_cs,
+                                      w_ad, w_ts, w_pc, nullptr, nullptr, st, &cfg);
+        return e;
     };
-    return ezo_tune_search(c, kb, cands, st, run_b, &g);
+    c->bisect_key = kb;
+    return ezo_tune_search(c, kb, cands, st, run_b, &g, kTuneSlack, c->shape_trial ? nullptr : &c->bisect_finalists);
 }
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
@@ -1231,6 +1246,35 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
                             (int*)w_ci, (int*)w_nc, (float*)w_cs, (float*)w_ad, (float*)w_ts, (uint8_t*)w_pc,
                             (const int*)w_ac, st)))
         return s;
+    if (c->bisect_finalists.size() > 1 && !c->shape_trial) {
+        // The stand-in's bisection finalists, timed on whole inflations of
+        // this call's edges: the loop's later iterations have fewer
+        // candidates than any stand-in, which favours larger tiles.  The runs
+        // draw from an independent random stream (seed ^ kTuneSeedMix) and
+        // use this call's outputs and workspace as scratch (same sizes, so the
+        // same buffers; the obstacles are prepared again identically); the
+        // inflation below overwrites them.  The timing, like every shape
+        // choice, changes no result.
+        std::vector<TileCfg> fin;
+        fin.swap(c->bisect_finalists);
+        const TuneKey kb = c->bisect_key;
+        struct Trial {
+            ezo_ctx* c;
+            ~Trial() { c->shape_trial = false; }
+        } trial{c};
+        c->shape_trial = true;
+        auto run = [&](const TileCfg& g) -> ezo_status {
+            ezo_tune_store(kb, g);
+            ezo_params q = *p;
+            q.seed = p->seed ^ kTuneSeedMix;
+            q.row_points = nullptr;
+            return inflate_core(c, r, obs, n_obs, edges, n_edges, &q, A, b, n_faces, edge_status, nullptr, st,
+                                edge_ids, skip);
+        };
+        TileCfg g;
+        if ((s = ezo_tune_search(c, kb, fin, st, run, &g))) return s;
+    }
+    c->bisect_finalists.clear();
     hipLaunchKernelGGL(k_init_edges, dim3((E + 63) / 64), dim3(64), 0, st, dof, r->q_lo, r->q_hi, edges, E, A, b,
                        n_faces, cap, edge_status, (EdgeStatsDev*)w_st, (uint8_t*)w_pa, (int*)w_k, (int*)w_ac, skip);
     HIP_TRY(c, hipGetLastError());
@@ -1372,9 +1416,9 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         }
         for (const DevBuf& wb : c->ws) push(wb.p);
         const TileCfg gc = resolve_cfg(c, tune_key(c, r, TUNE_CHECK_FLAGS, ov.n, (int64_t)S_cap * E),
-                                       heuristic_check(c, r, ov.n, (int64_t)S_cap * E, false), r->slots, ov.n, false);
+                                       heuristic_check(c, r, ov.n, (int64_t)S_cap * E, false), r->slots, r->P, ov.n, false);
         const TileCfg gb = resolve_cfg(c, tune_key(c, r, TUNE_BISECT, ov.n, (int64_t)cand_cap * E),
-                                       heuristic_bisect(c, r, ov.n, (int64_t)cand_cap * E), r->slots, ov.n, false, true);
+                                       heuristic_bisect(c, r, ov.n, (int64_t)cand_cap * E), r->slots, r->P, ov.n, false, true);
         for (const TileCfg& g : {gc, gb}) {
             key.push_back((uintptr_t)g.T);
             key.push_back((uintptr_t)g.W);

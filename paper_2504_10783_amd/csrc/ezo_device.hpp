@@ -58,23 +58,31 @@ constexpr int kMaxLinkPairs = kMaxDof * (kMaxDof + 1) / 2;   // link pairs, same
 
 // Robot tables that a workgroup running many dependent tile checks (the
 // bisection) copies into LDS once: DH rows, link bounding spheres, self-pair
-// blocks, spheres and link sphere ranges; their reads in FK and in the
-// self-pair sweep then cost an LDS access instead of a cache access.  At
-// most this many bytes (slots >= spheres).
-__host__ __device__ inline size_t robot_stage_bytes(int slots) {
-    return 16 * (size_t)(2 * kMaxDof + kMaxLinkPairs + (slots > 0 ? slots : 1)) + 16 * ((kMaxDof + 4) / 4);
+// blocks, spheres, link sphere ranges and, up to kStagePairs of them, the
+// self pairs; their reads in FK and in the self-pair sweep then cost an LDS
+// access instead of a cache access.  At most this many bytes (slots >=
+// spheres, n_self = self pairs).
+constexpr int kStagePairs = 2048;
+
+__host__ __device__ inline int robot_staged_pairs(int n_self) { return n_self <= kStagePairs ? n_self : 0; }
+
+__host__ __device__ inline size_t robot_stage_bytes(int slots, int n_self) {
+    return 16 * (size_t)(2 * kMaxDof + kMaxLinkPairs + (slots > 0 ? slots : 1)) + 16 * ((kMaxDof + 4) / 4) +
+           16 * (((size_t)robot_staged_pairs(n_self) + 1) / 2);
 }
 
 // Copies the tables into LDS at `base` (16-byte aligned, robot_stage_bytes
 // long) and returns a view whose table pointers address the copies (box
-// tables and self pairs stay in global memory).  The caller places a
-// barrier before the first use.
+// tables, and self pairs beyond kStagePairs, stay in global memory).  The
+// caller places a barrier before the first use.
 __device__ inline RobotView stage_robot(const RobotView& rb, char* base) {
     float4* dh = reinterpret_cast<float4*>(base);
     float4* lb = dh + kMaxDof;
     int4* blk = reinterpret_cast<int4*>(lb + kMaxDof);
     float4* sph = reinterpret_cast<float4*>(blk + kMaxLinkPairs);
     int* lbeg = reinterpret_cast<int*>(sph + (rb.n_spheres > 0 ? rb.n_spheres : 1));
+    int2* prs = reinterpret_cast<int2*>(lbeg + 4 * ((kMaxDof + 4) / 4));
+    const int np = robot_staged_pairs(rb.n_self);
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int i = tid; i < rb.dof; i += nt) {
         dh[i] = rb.dh[i];
@@ -83,12 +91,14 @@ __device__ inline RobotView stage_robot(const RobotView& rb, char* base) {
     for (int i = tid; i <= rb.dof; i += nt) lbeg[i] = rb.link_begin[i];
     for (int i = tid; i < rb.n_blocks; i += nt) blk[i] = rb.blocks[i];
     for (int i = tid; i < rb.n_spheres; i += nt) sph[i] = rb.sph[i];
+    for (int i = tid; i < np; i += nt) prs[i] = rb.pairs[i];
     RobotView v = rb;
     v.dh = dh;
     v.lbound = lb;
     v.blocks = blk;
     v.sph = sph;
     v.link_begin = lbeg;
+    if (np > 0) v.pairs = prs;
     return v;
 }
 
@@ -271,8 +281,15 @@ __device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const Til
     }
     __syncthreads();
     const float4 sh = ob.centre[0];
-    for (ItemWalk w(n_valid); w.k < dof; w.next(n_valid)) {
-        const int c = w.c, link = w.k;
+    // P lanes per (configuration, link), P the largest power of two (<= 16)
+    // with n_valid dof P items in one pass of the workgroup: each composes the
+    // link's frame and places every P-th sphere (and box) of the link, so a
+    // long link is spread over idle lanes instead of being placed by one
+    int lp = 0;
+    while (lp < 4 && n_valid * dof * (2 << lp) <= (int)blockDim.x) ++lp;
+    const int P = 1 << lp;
+    for (ItemWalk w(n_valid); w.k < dof * P; w.next(n_valid)) {
+        const int c = w.c, link = w.k >> lp, part = w.k & (P - 1);
         float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
         float p[3] = {-sh.x, -sh.y, -sh.z};
         for (int l = 0; l <= link; ++l) {
@@ -281,7 +298,7 @@ __device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const Til
             if ((rb.prismatic >> l) & 1u) dh.y += t.q[c * kMaxDof + l];
             dh_compose(R, p, cs.x, cs.y, dh);
         }
-        {
+        if (part == 0) {
             const float4 lc = rb.lbound[link];
             float4 o;
             o.x = fmaf(R[0], lc.x, fmaf(R[1], lc.y, fmaf(R[2], lc.z, p[0])));
@@ -291,7 +308,7 @@ __device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const Til
             t.lb[link * T + c] = o;
         }
         const int s1 = rb.link_begin[link + 1];
-        for (int s = rb.link_begin[link]; s < s1; ++s) {
+        for (int s = rb.link_begin[link] + part; s < s1; s += P) {
             const float4 ps = rb.sph[s];
             float4 o;
             o.x = fmaf(R[0], ps.x, fmaf(R[1], ps.y, fmaf(R[2], ps.z, p[0])));
@@ -303,7 +320,7 @@ __device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const Til
         if (BOX && rb.n_boxes > 0) {
             const int S = rb.n_spheres;
             const int k1 = rb.box_begin[link + 1];
-            for (int k = rb.box_begin[link]; k < k1; ++k) {
+            for (int k = rb.box_begin[link] + part; k < k1; k += P) {
                 const float4 b0 = rb.box[4 * k], b1 = rb.box[4 * k + 1], b2 = rb.box[4 * k + 2], b3 = rb.box[4 * k + 3];
                 const float L[9] = {b1.x, b1.y, b1.z, b2.x, b2.y, b2.z, b3.x, b3.y, b3.z};
                 float4* dst = t.cen + (size_t)(S + 4 * k) * T + c;
@@ -738,10 +755,11 @@ __device__ inline void flush_tests(unsigned long long* tests, unsigned n) {
 template <bool SD, bool BOX>
 __device__ inline unsigned tile_check(const RobotView& rb, const ObsView& ob, const GridView& gv, const TileSmem& t,
                                       int T, int n_valid) {
-    tile_fk<BOX>(rb, ob, t, T, n_valid);
+    // cleared here, published by FK's barriers (every reader of the previous
+    // check's flags and work list is behind a barrier the caller placed)
     if (threadIdx.x < (unsigned)T) t.hit[threadIdx.x] = (threadIdx.x < (unsigned)n_valid) ? 0 : 1;
     if (threadIdx.x == 0) *t.wl_n = 0;
-    __syncthreads();
+    tile_fk<BOX>(rb, ob, t, T, n_valid);
     if (SD) {
         tile_pairs_sd<BOX>(rb, ob, t, T, n_valid);
         return 0;

@@ -32,6 +32,32 @@ enum Slot {
     W_ROUND_EDGES, W_ROUND_IDS, W_ROUND_SKIP, W_ROUND_A, W_ROUND_B, W_ROUND_NF, W_ROUND_ST, W_MAP_COUNTS, W_NSLOTS
 };
 
+// ---------------------------------------------------------------------------
+// Launch shapes of the tile kernels and their tuning cache
+// ---------------------------------------------------------------------------
+// T configurations per workgroup, W waves per workgroup, obstacle records
+// staged in LDS (stage = 1) or read from global memory; for the bisection,
+// depth = bisection levels per round (T >> depth candidates per workgroup).
+// T = 0: not chosen.
+struct TileCfg {
+    int T = 0, W = 0, stage = 0, depth = 1;
+};
+
+// For the sampler, T = lanes per walk and W = waves per workgroup.
+// TUNE_SAMPLE_COUNT: T = the inflation's N_p (samples per iteration).
+enum TuneKind { TUNE_CHECK_FLAGS = 0, TUNE_CHECK_SD = 1, TUNE_BISECT = 2, TUNE_SAMPLE = 3, TUNE_SAMPLE_COUNT = 4,
+                TUNE_NKINDS };
+
+// A tuned shape applies to calls with the same device architecture, kernel,
+// robot size (dof, spheres, self pairs), obstacle count and work size
+// (bucket = floor(log2(items))).  Sampler keys hold the dof and the walk
+// count only (spheres = self pairs = obstacles = 0).
+struct TuneKey {
+    std::string arch;
+    int kind = 0, dof = 0, S = 0, P = 0, n_obs = 0, bucket = 0, B = 0;
+    bool operator<(const TuneKey& o) const;
+};
+
 struct ezo_ctx {
     int device = 0;
     hipStream_t stream = nullptr;      // internal stream (default priority)
@@ -56,6 +82,11 @@ struct ezo_ctx {
     float4* ebox = nullptr;               // obstacle boxes [n_ebox][4] (packed like robot boxes), world frame
     int n_ebox = 0;
     unsigned char* scratch = nullptr;     // device address of this device's fixed scratch (no-allocation calls)
+    // bisection shapes that the stand-in timing left as finalists, to be timed
+    // on whole inflations by the call that tuned them (see inflate_core)
+    std::vector<TileCfg> bisect_finalists;
+    TuneKey bisect_key;
+    bool shape_trial = false;             // inside such a timing run
 };
 
 struct ezo_robot {
@@ -105,32 +136,6 @@ struct ezo_surrogate {
     void* tb = nullptr;
 };
 
-// ---------------------------------------------------------------------------
-// Launch shapes of the tile kernels and their tuning cache
-// ---------------------------------------------------------------------------
-// T configurations per workgroup, W waves per workgroup, obstacle records
-// staged in LDS (stage = 1) or read from global memory; for the bisection,
-// depth = bisection levels per round (T >> depth candidates per workgroup).
-// T = 0: not chosen.
-struct TileCfg {
-    int T = 0, W = 0, stage = 0, depth = 1;
-};
-
-// For the sampler, T = lanes per walk and W = waves per workgroup.
-// TUNE_SAMPLE_COUNT: T = the inflation's N_p (samples per iteration).
-enum TuneKind { TUNE_CHECK_FLAGS = 0, TUNE_CHECK_SD = 1, TUNE_BISECT = 2, TUNE_SAMPLE = 3, TUNE_SAMPLE_COUNT = 4,
-                TUNE_NKINDS };
-
-// A tuned shape applies to calls with the same device architecture, kernel,
-// robot size (dof, spheres, self pairs), obstacle count and work size
-// (bucket = floor(log2(items))).  Sampler keys hold the dof and the walk
-// count only (spheres = self pairs = obstacles = 0).
-struct TuneKey {
-    std::string arch;
-    int kind = 0, dof = 0, S = 0, P = 0, n_obs = 0, bucket = 0, B = 0;
-    bool operator<(const TuneKey& o) const;
-};
-
 int ezo_tune_bucket(int64_t items);
 bool ezo_tune_lookup(const TuneKey& k, TileCfg* out);
 // Times every candidate once, then the fastest few over several launches
@@ -140,9 +145,13 @@ bool ezo_tune_lookup(const TuneKey& k, TileCfg* out);
 // repeated timings) lets repeated tunings of near-equal shapes agree.
 // Candidates whose launch fails are skipped.  Needs at least one candidate.
 constexpr double kTuneSlack = 0.03;
+// `finalists` (optional) receives the shapes timed over several launches,
+// fastest first.
 ezo_status ezo_tune_search(ezo_ctx* c, const TuneKey& k, const std::vector<TileCfg>& cands, hipStream_t st,
                            const std::function<ezo_status(const TileCfg&)>& run, TileCfg* best,
-                           double slack = kTuneSlack);
+                           double slack = kTuneSlack, std::vector<TileCfg>* finalists = nullptr);
+// Sets the cached shape of k (a shape on trial).
+void ezo_tune_store(const TuneKey& k, const TileCfg& g);
 
 // Records, for a cached entry, the Philox key that the timed runs drew from
 // (the sample-count tuner's own stream; exported as "tune_seed").

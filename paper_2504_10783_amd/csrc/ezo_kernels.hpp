@@ -696,7 +696,7 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rg, ObsView o
     const RobotView rb = stage_robot(rg, rs_base);
     // screened form: the network's activations and predictions after the
     // staged robot tables
-    __bf16* mlp_h = reinterpret_cast<__bf16*>(rs_base + robot_stage_bytes(slots));
+    __bf16* mlp_h = reinterpret_cast<__bf16*>(rs_base + robot_stage_bytes(slots, rg.n_self));
     float* mlp_y = reinterpret_cast<float*>(reinterpret_cast<char*>(mlp_h) + mlp_tile_smem_bytes(1));
     stage_obstacles(ob, t);
     const int tid = threadIdx.x;
@@ -1038,6 +1038,12 @@ __global__ void k_tune_polytope(int dof, const float* __restrict__ q_lo, const f
         bvec[(size_t)e * cap + f] = g < dof ? q_hi[j0] : -q_lo[j0];
     }
     n_faces[e] = F;
+}
+
+// The autotuner's lighter candidate counts: out[e] = min(in[e], cap).
+__global__ void k_cap_counts(const int* __restrict__ in, int* __restrict__ out, int n, int cap) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) out[e] = min(in[e], cap);
 }
 
 // Per edge: P = D (box rows), status RUNNING or INVALID, stats cleared; and

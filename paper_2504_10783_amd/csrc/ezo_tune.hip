@@ -116,7 +116,8 @@ static ezo_status time_shape(ezo_ctx* c, hipStream_t st, const std::function<ezo
 }
 
 ezo_status ezo_tune_search(ezo_ctx* c, const TuneKey& k, const std::vector<TileCfg>& cands, hipStream_t st,
-                           const std::function<ezo_status(const TileCfg&)>& run, TileCfg* best, double slack) {
+                           const std::function<ezo_status(const TileCfg&)>& run, TileCfg* best, double slack,
+                           std::vector<TileCfg>* finalists) {
     if (cands.empty()) return ezo_fail(c, EZO_E_INVALID, "no launch shape to tune");
     for (auto& ev : c->tune_ev)
         if (!ev) HIP_TRY(c, hipEventCreate(&ev));
@@ -141,6 +142,13 @@ ezo_status ezo_tune_search(ezo_ctx* c, const TuneKey& k, const std::vector<TileC
         best_ms = std::min(best_ms, ms);
     }
     if (!std::isfinite(best_ms)) return ezo_fail(c, EZO_E_HIP, "no launch shape ran during tuning");
+    if (finalists) {
+        std::vector<std::pair<double, int>> f = fin;
+        std::sort(f.begin(), f.end());
+        finalists->clear();
+        for (const auto& e : f)
+            if (std::isfinite(e.first)) finalists->push_back(cands[e.second]);
+    }
     // the earliest candidate (in the caller's order of preference) within
     // (1 + slack) of the fastest
     int pick_i = -1;
@@ -159,6 +167,11 @@ ezo_status ezo_tune_search(ezo_ctx* c, const TuneKey& k, const std::vector<TileC
     }
     *best = pick;
     return EZO_OK;
+}
+
+void ezo_tune_store(const TuneKey& k, const TileCfg& g) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_cache[k] = Entry{g, 0.0};
 }
 
 void ezo_tune_note_seed(const TuneKey& k, uint64_t seed) {
