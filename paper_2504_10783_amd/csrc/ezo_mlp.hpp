@@ -183,70 +183,109 @@ __global__ void __launch_bounds__(256) k_sum_slices(const float* __restrict__ pa
 // ---------------------------------------------------------------------------
 // Output layer backward for a batch of B rows with targets t (clipped):
 // dy = huber'(y - t) / B;  dz3[r][i] = dy W4[i] silu'(z3[r][i]) (BF16);
-// loss partial sums per block.
+// row r's Huber loss to row_loss[r] (summed by k_colsum).
 __global__ void __launch_bounds__(256) k_mlp_out_back(int64_t B, int D, int H, const float* __restrict__ P,
                                                       const float* __restrict__ y, const float* __restrict__ t,
                                                       const int* __restrict__ tidx, float huber, float clip_lo,
                                                       float clip_hi, const float* __restrict__ z3,
                                                       float* __restrict__ dy_out, __bf16* __restrict__ dz3,
-                                                      float* __restrict__ loss_acc) {
+                                                      float* __restrict__ row_loss) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const MlpOffsets o = mlp_offsets(D, H);
-    __shared__ float red[256];
-    float l = 0.f;
-    if (q < B * H) {
-        const int64_t r = q / H;
-        const int i = (int)(q % H);
-        const float tv = fminf(fmaxf(t[tidx ? tidx[r] : r], clip_lo), clip_hi);
-        const float res = y[r] - tv;
-        const float g = (fabsf(res) <= huber ? res : (res > 0.f ? huber : -huber)) / (float)B;
-        if (i == 0) {
-            dy_out[r] = g;
-            l = fabsf(res) <= huber ? 0.5f * res * res : huber * (fabsf(res) - 0.5f * huber);
-        }
-        dz3[q] = (__bf16)(g * P[o.W4 + i] * silu_gradf(z3[q]));
+    if (q >= B * H) return;
+    const int64_t r = q / H;
+    const int i = (int)(q % H);
+    const float tv = fminf(fmaxf(t[tidx ? tidx[r] : r], clip_lo), clip_hi);
+    const float res = y[r] - tv;
+    const float g = (fabsf(res) <= huber ? res : (res > 0.f ? huber : -huber)) / (float)B;
+    if (i == 0) {
+        dy_out[r] = g;
+        row_loss[r] = fabsf(res) <= huber ? 0.5f * res * res : huber * (fabsf(res) - 0.5f * huber);
     }
-    red[threadIdx.x] = l;
+    dz3[q] = (__bf16)(g * P[o.W4 + i] * silu_gradf(z3[q]));
+}
+
+// Single-launch batch reductions.  Every block of a group (blockIdx.x) sums
+// one slice of rows (blockIdx.y) into part[slice][...]; then the block that
+// finishes last in its group (the counter cnt[group] reaches the number of
+// slices) adds the slices in slice order -- deterministic, whichever block
+// that is -- and resets the counter: cnt[] is zero before and after a launch.
+// Called by every thread after its slice sums are written.
+__device__ inline bool last_slice(unsigned* cnt) {
+    __shared__ int last;
+    __threadfence();
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < (unsigned)s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        last = atomicAdd(&cnt[blockIdx.x], 1u) == gridDim.y - 1 ? 1 : 0;
+        if (last) cnt[blockIdx.x] = 0u;       // every block of the group has counted
     }
-    if (threadIdx.x == 0) atomicAdd(loss_acc, red[0]);
+    __syncthreads();
+    if (last) __threadfence();
+    return last != 0;
 }
 
-// Column sums over a batch, in row slices: part[z][j] = sum over rows r of
-// slice z (rows [z rs, (z + 1) rs) of B) of w[r] * X[r][j] (w NULL -> 1), X
-// BF16 [B][ncol] or FP32 (Xf).  blockIdx.y = slice; summed by k_sum_slices.
-__global__ void __launch_bounds__(256) k_colsum_part(int64_t B, int ncol, int64_t rs, const float* __restrict__ w,
-                                                     const __bf16* __restrict__ X, const float* __restrict__ Xf,
-                                                     float* __restrict__ part) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= ncol) return;
-    const int64_t r0 = (int64_t)blockIdx.y * rs, r1 = min(B, r0 + rs);
+// sum over the slices z < gridDim.y of part[z stride + i], read from L2
+__device__ inline float sum_slices_of(const float* part, int64_t stride, int64_t i) {
+    float tot = 0.f;
+    for (int z = 0; z < (int)gridDim.y; ++z)
+        tot += __hip_atomic_load(const_cast<float*>(&part[(int64_t)z * stride + i]), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+    return tot;
+}
+
+// Column sums: out[j] = sum_r w[r] X[r][j] (plus out[j] when accumulate),
+// j < ncol, w NULL -> 1, X BF16 [B][ncol] or FP32 Xf.  blockIdx.x = a group
+// of 64 columns, blockIdx.y = a slice of kColRows rows, four row groups of
+// one wave each summed in a fixed order.
+constexpr int kColRows = 256;
+
+__global__ void __launch_bounds__(256) k_colsum(int64_t B, int ncol, const float* __restrict__ w,
+                                                const __bf16* __restrict__ X, const float* __restrict__ Xf,
+                                                float* __restrict__ part, unsigned* __restrict__ cnt,
+                                                float* __restrict__ out, int accumulate) {
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
+    const int64_t r0 = (int64_t)blockIdx.y * kColRows, r1 = min(B, r0 + kColRows);
     float s = 0.f;
-    for (int64_t r = r0; r < r1; ++r) {
-        const float x = X ? (float)X[r * ncol + j] : Xf[r * ncol + j];
-        s = fmaf(w ? w[r] : 1.f, x, s);
+    if (j < ncol) {
+#pragma unroll 8
+        for (int64_t r = r0 + g; r < r1; r += 4) {
+            const float x = X ? (float)X[r * ncol + j] : Xf[r * ncol + j];
+            s = fmaf(w ? w[r] : 1.f, x, s);
+        }
     }
-    part[(int64_t)blockIdx.y * ncol + j] = s;
+    red[g][lane] = s;
+    __syncthreads();
+    if (g == 0 && j < ncol)
+        part[(int64_t)blockIdx.y * ncol + j] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    if (!last_slice(cnt)) return;
+    if (g == 0 && j < ncol) {
+        const float tot = sum_slices_of(part, ncol, j);
+        out[j] = accumulate ? out[j] + tot : tot;
+    }
 }
 
-// dW1[i][j] = sum_r dz1[r][i] * x[r][j] / pi in row slices: part[z][i D + j]
-// over rows [z rs, (z + 1) rs).  One thread per (i, j); blockIdx.y = slice.
-__global__ void __launch_bounds__(256) k_mlp_grad_w1_part(RowSource src, int64_t B, int D, int H, int64_t rs,
-                                                          const __bf16* __restrict__ dz1, float* __restrict__ part) {
+// dW1[i][j] = sum_r dz1[r][i] * x[r][j] / pi -> out[i D + j]: one thread
+// per (i, j), blockIdx.y = a slice of rs rows, slices summed as in k_colsum.
+__global__ void __launch_bounds__(256) k_mlp_grad_w1(RowSource src, int64_t B, int D, int H, int64_t rs,
+                                                     const __bf16* __restrict__ dz1, float* __restrict__ part,
+                                                     unsigned* __restrict__ cnt, float* __restrict__ out) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= H * D) return;
-    const int i = t / D, j = t % D;
-    const int64_t r0 = (int64_t)blockIdx.y * rs, r1 = min(B, r0 + rs);
-    float s = 0.f;
-    for (int64_t r = r0; r < r1; ++r) {
-        int64_t sd;
-        const float* x = row_ptr(src, r, &sd);
-        s = fmaf((float)dz1[r * H + i], x[j * sd] * kInvPi, s);
+    const bool ok = t < H * D;
+    if (ok) {
+        const int i = t / D, j = t % D;
+        const int64_t r0 = (int64_t)blockIdx.y * rs, r1 = min(B, r0 + rs);
+        float s = 0.f;
+        for (int64_t r = r0; r < r1; ++r) {
+            int64_t sd;
+            const float* x = row_ptr(src, r, &sd);
+            s = fmaf((float)dz1[r * H + i], x[j * sd] * kInvPi, s);
+        }
+        part[(int64_t)blockIdx.y * H * D + t] = s;
     }
-    part[(int64_t)blockIdx.y * H * D + t] = s;
+    if (!last_slice(cnt)) return;
+    if (ok) out[t] = sum_slices_of(part, (int64_t)H * D, t);
 }
 
 // Adam step with bias correction on the flat parameter vector; refreshes

@@ -23,13 +23,17 @@ uint64_t splitmix64(uint64_t& s) {
 double unit(uint64_t& s) { return (double)(splitmix64(s) >> 11) * (1.0 / 9007199254740992.0); }
 
 // Training batch buffers: z1 z2 z3 (FP32), h1 h2 h3 d3 d2 d1 (BF16) of
-// [B][H]; y dy (FP32 [B]); idx (int [B]); loss (FP32).
+// [B][H]; y dy rl (FP32 [B], rl = each row's loss); idx (int [B]); loss
+// (FP32); the column sums' counters (zero between launches).
 struct TrainBufs {
-    float *z1, *z2, *z3, *y, *dy, *loss;
+    float *z1, *z2, *z3, *y, *dy, *rl, *loss;
     __bf16 *h1, *h2, *h3, *d3, *d2, *d1;
     int* idx;
+    unsigned* cnt;
     float* part;        // partial sums of the batch reductions
 };
+
+constexpr int kColGroups = 128;         // groups of k_colsum (H / 64) and k_mlp_grad_w1 (H D / 256)
 
 TrainBufs carve(void* base, int B, int H) {
     TrainBufs t;
@@ -40,6 +44,7 @@ TrainBufs carve(void* base, int B, int H) {
         return q;
     };
     const size_t bh = (size_t)B * H;
+    t.cnt = (unsigned*)take(sizeof(unsigned) * kColGroups);     // first: the same place for every B
     t.z1 = (float*)take(4 * bh);
     t.z2 = (float*)take(4 * bh);
     t.z3 = (float*)take(4 * bh);
@@ -51,27 +56,29 @@ TrainBufs carve(void* base, int B, int H) {
     t.d1 = (__bf16*)take(2 * bh);
     t.y = (float*)take(4 * (size_t)B);
     t.dy = (float*)take(4 * (size_t)B);
+    t.rl = (float*)take(4 * (size_t)B);
     t.idx = (int*)take(4 * (size_t)B);
     t.loss = (float*)take(256);
     t.part = (float*)take(0);
     return t;
 }
 
-// Row slices of the batch reductions (column sums, dW1) and K slices of the
-// weight-gradient GEMMs (K = batch rows): each slice writes partial sums,
-// summed in a fixed order by k_sum_slices.
+// Row slices of dW1's batch reduction (summed in the same launch, like the
+// column sums) and K slices of the weight-gradient GEMMs (K = batch rows,
+// summed in a fixed order by k_sum_slices).
 constexpr int kRowsPerSlice = 64;
 constexpr int kGradSplitK = 16;
 
 size_t partial_floats(int B, int H, int D) {
     const size_t slices = (size_t)(B + kRowsPerSlice - 1) / kRowsPerSlice;
-    return std::max({(size_t)kGradSplitK * H * H, slices * H * std::max(D, 1), slices * 1});
+    const size_t col_slices = (size_t)(B + kColRows - 1) / kColRows;
+    return std::max({(size_t)kGradSplitK * H * H, slices * H * std::max(D, 1), col_slices * H});
 }
 
 size_t train_bytes(int B, int H, int D) {
     const size_t bh = (size_t)B * H;
     return 3 * (((4 * bh) + 255) & ~(size_t)255) + 6 * (((2 * bh) + 255) & ~(size_t)255) +
-           3 * ((4 * (size_t)B + 255) & ~(size_t)255) + 256 + ((4 * partial_floats(B, H, D) + 255) & ~(size_t)255);
+           4 * ((4 * (size_t)B + 255) & ~(size_t)255) + 256 + 512 + ((4 * partial_floats(B, H, D) + 255) & ~(size_t)255);
 }
 
 // C = A B with the strides' contiguous dimensions picking the staging; split
@@ -100,13 +107,12 @@ void sum_slices(hipStream_t st, const float* part, int slices, int64_t n, float*
     hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, slices, n, out);
 }
 
-// out[j] = sum_r w[r] X[r][j] over the batch, in row slices
-void colsum(hipStream_t st, int64_t B, int ncol, const float* w, const __bf16* X, const float* Xf, float* part,
-            float* out) {
-    const int slices = (int)((B + kRowsPerSlice - 1) / kRowsPerSlice);
-    hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)((ncol + 255) / 256), (unsigned)slices), dim3(256), 0, st, B, ncol,
-                       (int64_t)kRowsPerSlice, w, X, Xf, part);
-    sum_slices(st, part, slices, ncol, out);
+// out[j] (+)= sum_r w[r] X[r][j] over the batch, one launch
+void colsum(hipStream_t st, int64_t B, int ncol, const float* w, const __bf16* X, const float* Xf, const TrainBufs& t,
+            float* out, int accumulate = 0) {
+    const int slices = (int)((B + kColRows - 1) / kColRows);
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((ncol + 63) / 64), (unsigned)slices), dim3(256), 0, st, B, ncol, w, X,
+                       Xf, t.part, t.cnt, out, accumulate);
 }
 
 // batch row indices: an affine permutation of [0, n) per epoch
@@ -145,26 +151,26 @@ ezo_status forward_backward(ezo_ctx* c, ezo_surrogate* s, const RowSource& src, 
                        t.y, (const int*)nullptr);
     hipLaunchKernelGGL(k_mlp_out_back, dim3((unsigned)((BH + 255) / 256)), dim3(256), 0, st, (int64_t)B, D, H, P, t.y,
                        target, (const int*)src.idx, (float)hp->huber_delta, (float)hp->clip_lo, (float)hp->clip_hi,
-                       t.z3, t.dy, t.d3, t.loss);
+                       t.z3, t.dy, t.d3, t.rl);
     float* part = t.part;
-    colsum(st, B, H, t.dy, t.h3, nullptr, part, G + o.W4);
-    colsum(st, B, 1, nullptr, nullptr, t.dy, part, G + o.b4);
-    colsum(st, B, H, nullptr, t.d3, nullptr, part, G + o.b3);
+    colsum(st, B, H, t.dy, t.h3, nullptr, t, G + o.W4);
+    colsum(st, B, 1, nullptr, nullptr, t.dy, t, G + o.b4);
+    colsum(st, B, 1, nullptr, nullptr, t.rl, t, t.loss, 1);
+    colsum(st, B, H, nullptr, t.d3, nullptr, t, G + o.b3);
     int ks = gemm<GEMM_STORE>(st, H, H, B, t.d3, 1, H, t.h2, H, 1, part, H, nullptr, nullptr, 0, nullptr, 0, nullptr,
                               0, 0, kGradSplitK);
     sum_slices(st, part, ks, (int64_t)H * H, G + o.W3);
     gemm<GEMM_BWD>(st, B, H, H, t.d3, H, 1, s->W3b, H, 1, nullptr, 0, nullptr, t.d2, H, t.z2, H);
-    colsum(st, B, H, nullptr, t.d2, nullptr, part, G + o.b2);
+    colsum(st, B, H, nullptr, t.d2, nullptr, t, G + o.b2);
     ks = gemm<GEMM_STORE>(st, H, H, B, t.d2, 1, H, t.h1, H, 1, part, H, nullptr, nullptr, 0, nullptr, 0, nullptr, 0, 0,
                           kGradSplitK);
     sum_slices(st, part, ks, (int64_t)H * H, G + o.W2);
     gemm<GEMM_BWD>(st, B, H, H, t.d2, H, 1, s->W2b, H, 1, nullptr, 0, nullptr, t.d1, H, t.z1, H);
-    colsum(st, B, H, nullptr, t.d1, nullptr, part, G + o.b1);
+    colsum(st, B, H, nullptr, t.d1, nullptr, t, G + o.b1);
     {
         const int slices = (B + kRowsPerSlice - 1) / kRowsPerSlice;
-        hipLaunchKernelGGL(k_mlp_grad_w1_part, dim3((unsigned)((H * D + 255) / 256), (unsigned)slices), dim3(256), 0, st,
-                           src, (int64_t)B, D, H, (int64_t)kRowsPerSlice, (const __bf16*)t.d1, part);
-        sum_slices(st, part, slices, (int64_t)H * D, G + o.W1);
+        hipLaunchKernelGGL(k_mlp_grad_w1, dim3((unsigned)((H * D + 255) / 256), (unsigned)slices), dim3(256), 0, st,
+                           src, (int64_t)B, D, H, (int64_t)kRowsPerSlice, (const __bf16*)t.d1, part, t.cnt, G + o.W1);
     }
     HIP_TRY(c, hipGetLastError());
     return EZO_OK;
@@ -184,6 +190,7 @@ ezo_status ensure_train_bufs(ezo_ctx* c, ezo_surrogate* s, int B) {
     }
     if (hipMalloc(&s->tb, train_bytes(B, s->H, s->D)) != hipSuccess) return ezo_fail(c, EZO_E_NOMEM, "training buffers");
     s->batch = B;
+    HIP_TRY(c, hipMemset(carve(s->tb, B, s->H).cnt, 0, sizeof(unsigned) * kColGroups));
     return EZO_OK;
 }
 
