@@ -673,6 +673,7 @@ void ezo_ctx_destroy(ezo_ctx* c) {
     for (auto& b : c->ws)
         if (b.p) e = hipFree(b.p);
     if (c->pinned) e = hipHostFree(c->pinned);
+    if (c->pinned_stats) e = hipHostFree(c->pinned_stats);
     if (c->ev_in) e = hipEventDestroy(c->ev_in);
     if (c->ev_out) e = hipEventDestroy(c->ev_out);
     for (auto& ev : c->tev)
@@ -1459,6 +1460,19 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         exec = c->loop_exec;
         c->loop_key = key;
     }
+    // the statistics travel with every poll, so the last poll's copy is the
+    // final one and no further round trip follows the loop
+    const size_t stats_bytes = stats ? sizeof(EdgeStatsDev) * (size_t)E : 0;
+    if (stats_bytes > c->pinned_stats_bytes) {
+        if (c->pinned_stats) HIP_TRY(c, hipHostFree(c->pinned_stats));
+        c->pinned_stats = nullptr;
+        c->pinned_stats_bytes = 0;
+        if (hipHostMalloc(&c->pinned_stats, stats_bytes, hipHostMallocDefault) != hipSuccess) {
+            c->pinned_stats = nullptr;
+            return ezo_fail(c, EZO_E_NOMEM, "pinned statistics buffer");
+        }
+        c->pinned_stats_bytes = stats_bytes;
+    }
     ezo_status result = EZO_OK;
     for (int k = 1; k <= p->max_iters; k += per) {
         hipError_t e1 = hipSuccess;
@@ -1468,6 +1482,8 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
             break;
         }
         hipError_t e2 = hipMemcpyAsync(c->pinned, w_ac, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e2 == hipSuccess && stats)
+            e2 = hipMemcpyAsync(c->pinned_stats, w_st, stats_bytes, hipMemcpyDeviceToHost, st);
         hipError_t e3 = hipStreamSynchronize(st);
         if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
             result = ezo_fail(c, EZO_E_HIP, "iteration %d failed: %s", k,
@@ -1488,9 +1504,7 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
     }
     if (result) return result;
     if (stats) {
-        std::vector<EdgeStatsDev> hs(E);
-        HIP_TRY(c, hipMemcpyAsync(hs.data(), w_st, sizeof(EdgeStatsDev) * E, hipMemcpyDeviceToHost, st));
-        HIP_TRY(c, hipStreamSynchronize(st));
+        const EdgeStatsDev* hs = static_cast<const EdgeStatsDev*>(c->pinned_stats);
         for (int e = 0; e < E; ++e) {
             stats[e].iterations = (int32_t)hs[e].iterations;
             stats[e].planes = (int32_t)hs[e].planes;

@@ -66,6 +66,8 @@ struct ezo_ctx {
     std::string err;
     std::vector<DevBuf> ws;            // named workspace slots
     int* pinned = nullptr;             // host-pinned poll word
+    void* pinned_stats = nullptr;      // host-pinned copy of the edges' statistics (grown on demand)
+    size_t pinned_stats_bytes = 0;
     bool timing = false;               // per-phase timing of the fused loop
     hipEvent_t tev[2 * EZO_NUM_PHASES] = {};   // (start, stop) of each phase's kernel
     hipEvent_t ev_a = nullptr, ev_b = nullptr;   // events for the next kernel launch (timing mode)

@@ -224,12 +224,21 @@ __device__ inline bool last_slice(unsigned* cnt) {
     return last != 0;
 }
 
-// sum over the slices z < gridDim.y of part[z stride + i], read from L2
+// sum over the slices z < gridDim.y of part[z stride + i], in slice order;
+// the acquire fence in last_slice makes the other blocks' sums visible to
+// these plain loads (issued eight at a time)
 __device__ inline float sum_slices_of(const float* part, int64_t stride, int64_t i) {
     float tot = 0.f;
-    for (int z = 0; z < (int)gridDim.y; ++z)
-        tot += __hip_atomic_load(const_cast<float*>(&part[(int64_t)z * stride + i]), __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
+    const int nz = (int)gridDim.y;
+    int z = 0;
+    for (; z + 8 <= nz; z += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(z + u) * stride + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) tot += v[u];
+    }
+    for (; z < nz; ++z) tot += part[(int64_t)z * stride + i];
     return tot;
 }
 
@@ -267,21 +276,30 @@ __global__ void __launch_bounds__(256) k_colsum(int64_t B, int ncol, const float
 }
 
 // dW1[i][j] = sum_r dz1[r][i] * x[r][j] / pi -> out[i D + j]: one thread
-// per (i, j), blockIdx.y = a slice of rs rows, slices summed as in k_colsum.
+// per (i, j), blockIdx.y = a slice of rs <= kGradW1Rows rows whose inputs
+// (x / pi) the block first gathers into LDS, slices summed as in k_colsum.
+constexpr int kGradW1Rows = 64;
+
 __global__ void __launch_bounds__(256) k_mlp_grad_w1(RowSource src, int64_t B, int D, int H, int64_t rs,
                                                      const __bf16* __restrict__ dz1, float* __restrict__ part,
                                                      unsigned* __restrict__ cnt, float* __restrict__ out) {
+    __shared__ float xs[kGradW1Rows][kMaxDof];
+    const int64_t r0 = (int64_t)blockIdx.y * rs, r1 = min(B, r0 + rs);
+    const int nr = (int)(r1 - r0);
+    for (int q = threadIdx.x; q < nr * D; q += blockDim.x) {
+        const int rr = q / D, j = q % D;
+        int64_t sd;
+        const float* x = row_ptr(src, r0 + rr, &sd);
+        xs[rr][j] = x[j * sd] * kInvPi;
+    }
+    __syncthreads();
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const bool ok = t < H * D;
     if (ok) {
         const int i = t / D, j = t % D;
-        const int64_t r0 = (int64_t)blockIdx.y * rs, r1 = min(B, r0 + rs);
         float s = 0.f;
-        for (int64_t r = r0; r < r1; ++r) {
-            int64_t sd;
-            const float* x = row_ptr(src, r, &sd);
-            s = fmaf((float)dz1[r * H + i], x[j * sd] * kInvPi, s);
-        }
+#pragma unroll 8
+        for (int r = 0; r < nr; ++r) s = fmaf((float)dz1[(r0 + r) * H + i], xs[r][j], s);
         part[(int64_t)blockIdx.y * H * D + t] = s;
     }
     if (!last_slice(cnt)) return;

@@ -66,7 +66,7 @@ TrainBufs carve(void* base, int B, int H) {
 // Row slices of dW1's batch reduction (summed in the same launch, like the
 // column sums) and K slices of the weight-gradient GEMMs (K = batch rows,
 // summed in a fixed order by k_sum_slices).
-constexpr int kRowsPerSlice = 64;
+constexpr int kRowsPerSlice = kGradW1Rows;
 constexpr int kGradSplitK = 16;
 
 size_t partial_floats(int B, int H, int D) {
