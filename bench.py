@@ -374,8 +374,8 @@ def screen_measure(args, name, epochs):
         checks = screened = 0
         for _ in range(args.steps):
             r = ezo.inflate_edges(ctx, rob, obs, edges, prm)
-            checks += sum(x["exact_checks"] for x in r.stats)
-            screened += sum(x["screened_checks"] for x in r.stats)
+            checks += int(r.stats.array["exact_checks"].sum())
+            screened += int(r.stats.array["screened_checks"].sum())
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t1) / args.steps
         st = r.status.cpu().numpy()
@@ -734,7 +734,7 @@ def forest(args):
     checks = 0
     for _ in range(args.steps):
         r = ezo.inflate_edges(ctx, rob, obs, edges, prm)
-        checks += sum(x["exact_checks"] for x in r.stats)
+        checks += int(r.stats.array["exact_checks"].sum())
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     st = r.status.cpu().numpy()
@@ -803,10 +803,10 @@ def inflation_measure(args, name, plain=True, cpu=True):
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts_ = time.perf_counter()
-        st = step()                       # returns once the call's stream is done
+        st = step().array                 # returns once the call's stream is done
         step_ms.append((time.perf_counter() - ts_) * 1e3)
-        checks += sum(s["exact_checks"] for s in st)
-        samples += sum(s["samples"] for s in st)
+        checks += int(st["exact_checks"].sum())
+        samples += int(st["samples"].sum())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     status = out.status.cpu().numpy()

@@ -8,6 +8,7 @@ not need a GPU, but every compute call does, and a missing library raises.
 """
 from __future__ import annotations
 
+import collections.abc
 import ctypes as C
 import os
 from dataclasses import dataclass
@@ -74,6 +75,36 @@ class EdgeStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("planes", C.c_int32), ("final_m", C.c_int64),
                 ("test_collisions", C.c_int64), ("samples", C.c_int64), ("exact_checks", C.c_int64),
                 ("screened_checks", C.c_int64)]
+
+
+class EdgeStatsView(collections.abc.Sequence):
+    """Per-edge statistics of one call over the C array the library filled:
+    item e is a dict of the fields, built when it is read; `.array` is a
+    zero-copy numpy structured view (for sums over many edges)."""
+
+    def __init__(self, arr, n):
+        self._a, self._n = arr, n
+
+    def __len__(self):
+        return self._n
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self[j] for j in range(*i.indices(self._n))]
+        if i < 0:
+            i += self._n
+        if not 0 <= i < self._n:
+            raise IndexError(i)
+        e = self._a[i]
+        return {k: getattr(e, k) for k, _ in EdgeStats._fields_}
+
+    def __eq__(self, other):
+        return list(self) == list(other)
+
+    @property
+    def array(self):
+        dt = np.dtype([(k, np.int32 if t is C.c_int32 else np.int64) for k, t in EdgeStats._fields_], align=True)
+        return np.frombuffer(self._a, dtype=dt, count=self._n)
 
 
 _lib = None
@@ -542,7 +573,7 @@ def inflate_edges(ctx: Context, robot: Robot, obs, edges, params: Params, out=No
     ctx._check(lib().ezo_inflate_edges(ctx.h, robot.h, _ptr(obs), obs.numel() // 4, _ptr(edges), int(E),
                                        C.byref(params), _ptr(out.A), _ptr(out.b), _ptr(out.n_faces),
                                        _ptr(out.status), st, _stream(stream)))
-    out.stats = [{k: getattr(st[e], k) for k, _ in EdgeStats._fields_} for e in range(E)]
+    out.stats = EdgeStatsView(st, E)
     return out
 
 
@@ -579,7 +610,7 @@ def inflate_paths(ctx: Context, robot: Robot, obs, vertices, path_vertices, para
     ctx._check(lib().ezo_inflate_paths(ctx.h, robot.h, _ptr(obs), obs.numel() // 4, _ptr(vertices), pv,
                                        len(counts), C.byref(params), _ptr(out.A), _ptr(out.b), _ptr(out.n_faces),
                                        _ptr(out.status), _ptr(out.covered_by), st, _stream(stream)))
-    out.stats = [{k: getattr(st[e], k) for k, _ in EdgeStats._fields_} for e in range(E)]
+    out.stats = EdgeStatsView(st, E)
     return out
 
 

@@ -96,21 +96,14 @@ ezo_status prep_obstacles_into(ezo_ctx* c, const ezo_robot* r, const float* obs,
                                void* rec, void* centre, void* geom, void* count, void* list, ObsView* ov,
                                GridView* gv) {
     const int G = grid_dim(n_obs);
-    const size_t cells = (size_t)G * G * G;
+    // indices above 65535 do not fit the list type: then every cell scans all
+    const bool lists = n_obs <= 65535;
     hipLaunchKernelGGL(k_prep_obstacles, dim3(1), dim3(256), 0, st, obs, n_obs, (float4*)rec, (float4*)centre,
-                       (GridGeom*)geom, G, r ? r->r_max : 0.f);
-    if (n_obs > 65535) {
-        // indices do not fit the list type: every cell scans all
-        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, (uint32_t*)count,
-                           (int64_t)cells, (uint32_t)(kGridCap + 1));
-    } else {
-        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, (uint32_t*)count,
-                           (int64_t)cells, 0u);
-        if (n_obs > 0)
-            hipLaunchKernelGGL(k_grid_scatter, dim3((unsigned)(((int64_t)n_obs * 64 + 255) / 256)), dim3(256), 0, st,
-                               (const float4*)rec, n_obs, (const GridGeom*)geom, G, kGridCap, (int*)count,
-                               (unsigned short*)list);
-    }
+                       (GridGeom*)geom, G, r ? r->r_max : 0.f, (int*)count, lists ? 0 : kGridCap + 1);
+    if (lists && n_obs > 0)
+        hipLaunchKernelGGL(k_grid_scatter, dim3((unsigned)(((int64_t)n_obs * 64 + 255) / 256)), dim3(256), 0, st,
+                           (const float4*)rec, n_obs, (const GridGeom*)geom, G, kGridCap, (int*)count,
+                           (unsigned short*)list);
     HIP_TRY(c, hipGetLastError());
     ov->n = n_obs;
     ov->lds_n = 0;

@@ -52,7 +52,10 @@ constexpr float kGridSlack = 1e-4f;
 
 __global__ void __launch_bounds__(256) k_prep_obstacles(const float* __restrict__ obs, int n, float4* __restrict__ rec,
                                                         float4* __restrict__ centre, GridGeom* __restrict__ geom,
-                                                        int G, float r_sphere_max) {
+                                                        int G, float r_sphere_max, int* __restrict__ count,
+                                                        int count_init) {
+    // the grid's cell counts start at count_init (0 before k_grid_scatter)
+    for (int k = threadIdx.x; k < G * G * G; k += blockDim.x) count[k] = count_init;
     __shared__ float red[7][256];
     const int tid = threadIdx.x;
     float mn[3] = {kHuge, kHuge, kHuge}, mx[3] = {-kHuge, -kHuge, -kHuge}, rmax = 0.f;
