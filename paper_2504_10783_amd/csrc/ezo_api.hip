@@ -227,13 +227,17 @@ TileCfg resolve_cfg(const ezo_ctx* c, const TuneKey& k, const TileCfg& fallback,
     return fallback;
 }
 
-// Candidate shapes: every fitting T x W x staging (x bisection depth 1..3);
+// Candidate shapes: every fitting T x W x staging (x bisection depth 1..2);
 // T = configurations (check, 4..64) or candidates (bisection, 1..64) per
 // workgroup; items = configurations or candidate slots.
 std::vector<TileCfg> tile_candidates(const ezo_ctx* c, int S, int P, int n_obs, bool sd, std::initializer_list<int> Ws,
                                      int64_t items, bool bisect = false) {
     std::vector<TileCfg> v;
-    for (int dp = 1; dp <= (bisect ? 3 : 1); ++dp)
+    // (bisection: one or two levels per round; three, seven points per
+    // candidate and round, never came near the fastest and only lengthened
+    // the first call's search, so the kernel's depth-3 instances are reached
+    // only through a shape given explicitly)
+    for (int dp = 1; dp <= (bisect ? 2 : 1); ++dp)
         for (int T : {64, 32, 16, 8, 4, 2, 1}) {
             if ((!bisect && T < 4) || (T > 4 && items < 4LL * T)) continue;   // a handful of items: small tiles
             for (int W : Ws)
@@ -650,7 +654,8 @@ ezo_status ezo_ctx_create(int32_t device, ezo_ctx** out) {
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
-        hipHostMalloc((void**)&c->pinned, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&c->pinned, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&c->pinned_dev, c->pinned, 0) != hipSuccess) {
         ezo_ctx_destroy(c);
         return ezo_fail(nullptr, EZO_E_HIP, "stream/event/pinned allocation failed");
     }
@@ -1163,6 +1168,11 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
                     cands.push_back(t);
                 }
                 const uint64_t tune_seed = p->seed ^ kTuneSeedMix;
+                struct Search {
+                    ezo_ctx* c;
+                    ~Search() { c->np_search = false; }
+                } search{c};
+                c->np_search = true;
                 auto run = [&](const TileCfg& t) -> ezo_status {
                     ezo_params q = *p;
                     q.n_p = t.T;
@@ -1289,6 +1299,25 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
     // Normal mode: captured once into a hipGraph and replayed.  Timing mode:
     // launched directly with hipEvents recorded between the phases (event
     // records inside a captured graph do not time the kernels).
+    // Every k_advance writes the running-edge count and, when asked for, the
+    // edges' statistics straight into pinned host memory, so that a replay
+    // ends in one stream synchronisation and no copies; the last replay's
+    // values are the final ones.
+    const size_t stats_bytes = stats ? sizeof(EdgeStatsDev) * (size_t)E : 0;
+    if (stats_bytes > c->pinned_stats_bytes) {
+        if (c->pinned_stats) HIP_TRY(c, hipHostFree(c->pinned_stats));
+        c->pinned_stats = c->pinned_stats_dev = nullptr;
+        c->pinned_stats_bytes = 0;
+        if (hipHostMalloc(&c->pinned_stats, stats_bytes, hipHostMallocDefault) != hipSuccess ||
+            hipHostGetDevicePointer(&c->pinned_stats_dev, c->pinned_stats, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            if (c->pinned_stats) (void)hipHostFree(c->pinned_stats);
+            c->pinned_stats = c->pinned_stats_dev = nullptr;
+            return ezo_fail(c, EZO_E_NOMEM, "pinned statistics buffer");
+        }
+        c->pinned_stats_bytes = stats_bytes;
+    }
+    EdgeStatsDev* host_stats = stats ? static_cast<EdgeStatsDev*>(c->pinned_stats_dev) : nullptr;
     auto launch_iteration = [&](bool marks) -> ezo_status {
         ezo_status ls = EZO_OK;
         auto mark = [&](int i) {          // the next launch belongs to phase i
@@ -1354,7 +1383,8 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
                            p->n_f, (float)p->step_back_max, (float)p->t_col, A, b, n_faces, cap, edge_status,
                            nullptr, nullptr, (const uint8_t*)w_pa, (EdgeStatsDev*)w_st, p->row_points);
         mark(EZO_PHASE_ADVANCE);
-        EZO_KLAUNCH(c, k_advance, dim3(1), dim3(256), 0, st, (int*)w_k, p->max_iters, edge_status, E, (int*)w_ac);
+        EZO_KLAUNCH(c, k_advance, dim3(1), dim3(256), 0, st, (int*)w_k, p->max_iters, edge_status, E, (int*)w_ac,
+                    c->pinned_dev, (const EdgeStatsDev*)w_st, host_stats);
         mark(EZO_NUM_PHASES);
         if (ls == EZO_OK) {
             hipError_t le = hipGetLastError();
@@ -1369,10 +1399,15 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
     // arguments); instantiation happens only when the topology changes.
     hipGraphExec_t exec = nullptr;
     int per = 1;
+    // Tuning runs (the sample-count search and the bisection shape trials)
+    // launch their iterations directly, kItersPerGraph per poll: each would
+    // otherwise capture and instantiate a graph of its own (its seed or shape
+    // differs from the kept graph's), which costs more than the run.
+    const bool direct = c->timing || c->shape_trial || c->np_search;
     // Everything the captured launches depend on: when a call repeats the
     // previous one's key, the kept executable graph is replayed as it is.
     std::vector<uintptr_t> key;
-    if (!c->timing) {
+    if (!direct) {
         auto push = [&](const void* ptr) { key.push_back(reinterpret_cast<uintptr_t>(ptr)); };
         push(r);
         push(r->buf);
@@ -1386,6 +1421,8 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         push(edge_ids);
         push(skip);
         push(c->ebox);
+        push(c->pinned_dev);
+        push(host_stats);
         key.push_back((uintptr_t)(uint32_t)c->n_ebox);
         key.push_back((uintptr_t)(uint32_t)n_obs);
         key.push_back((uintptr_t)(uint32_t)E);
@@ -1420,10 +1457,12 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
             key.push_back((uintptr_t)g.depth);
         }
     }
-    if (!c->timing && c->loop_exec && key == c->loop_key) {
+    if (direct) {
+        per = c->timing ? 1 : kItersPerGraph;
+    } else if (c->loop_exec && key == c->loop_key) {
         per = kItersPerGraph;
         exec = c->loop_exec;
-    } else if (!c->timing) {
+    } else {
         per = kItersPerGraph;
         hipGraph_t graph = nullptr;
         HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -1453,37 +1492,22 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         exec = c->loop_exec;
         c->loop_key = key;
     }
-    // the statistics travel with every poll, so the last poll's copy is the
-    // final one and no further round trip follows the loop
-    const size_t stats_bytes = stats ? sizeof(EdgeStatsDev) * (size_t)E : 0;
-    if (stats_bytes > c->pinned_stats_bytes) {
-        if (c->pinned_stats) HIP_TRY(c, hipHostFree(c->pinned_stats));
-        c->pinned_stats = nullptr;
-        c->pinned_stats_bytes = 0;
-        if (hipHostMalloc(&c->pinned_stats, stats_bytes, hipHostMallocDefault) != hipSuccess) {
-            c->pinned_stats = nullptr;
-            return ezo_fail(c, EZO_E_NOMEM, "pinned statistics buffer");
-        }
-        c->pinned_stats_bytes = stats_bytes;
-    }
     ezo_status result = EZO_OK;
     for (int k = 1; k <= p->max_iters; k += per) {
         hipError_t e1 = hipSuccess;
         if (exec) {
             e1 = hipGraphLaunch(exec, st);
-        } else if ((result = launch_iteration(true))) {
-            break;
+        } else {
+            for (int i = 0; i < per && result == EZO_OK; ++i) result = launch_iteration(c->timing);
+            if (result) break;
         }
-        hipError_t e2 = hipMemcpyAsync(c->pinned, w_ac, sizeof(int), hipMemcpyDeviceToHost, st);
-        if (e2 == hipSuccess && stats)
-            e2 = hipMemcpyAsync(c->pinned_stats, w_st, stats_bytes, hipMemcpyDeviceToHost, st);
-        hipError_t e3 = hipStreamSynchronize(st);
-        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        const hipError_t e2 = hipStreamSynchronize(st);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
             result = ezo_fail(c, EZO_E_HIP, "iteration %d failed: %s", k,
-                          hipGetErrorString(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3)));
+                              hipGetErrorString(e1 != hipSuccess ? e1 : e2));
             break;
         }
-        if (!exec) {
+        if (c->timing) {
             for (int ph = 0; ph < EZO_NUM_PHASES; ++ph) {
                 float ms = 0.f;
                 if (hipEventElapsedTime(&ms, c->tev[2 * ph], c->tev[2 * ph + 1]) == hipSuccess)
@@ -1508,8 +1532,8 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
             stats[e].screened_checks = hs[e].screened;
         }
     }
-    HIP_TRY(c, hipEventRecord(c->ev_out, st));
-    HIP_TRY(c, hipStreamWaitEvent(as_stream(stream), c->ev_out, 0));
+    // (no event for the caller's stream: the host has already waited for
+    // every launch of this call, so later work on any stream follows it)
     return EZO_OK;
 }
 

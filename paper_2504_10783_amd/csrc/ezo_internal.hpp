@@ -65,8 +65,10 @@ struct ezo_ctx {
     size_t lds_cap = 65536;
     std::string err;
     std::vector<DevBuf> ws;            // named workspace slots
-    int* pinned = nullptr;             // host-pinned poll word
+    int* pinned = nullptr;             // host-pinned poll word, written by the device
+    int* pinned_dev = nullptr;         // its device address
     void* pinned_stats = nullptr;      // host-pinned copy of the edges' statistics (grown on demand)
+    void* pinned_stats_dev = nullptr;  // its device address
     size_t pinned_stats_bytes = 0;
     bool timing = false;               // per-phase timing of the fused loop
     hipEvent_t tev[2 * EZO_NUM_PHASES] = {};   // (start, stop) of each phase's kernel
@@ -89,6 +91,7 @@ struct ezo_ctx {
     std::vector<TileCfg> bisect_finalists;
     TuneKey bisect_key;
     bool shape_trial = false;             // inside such a timing run
+    bool np_search = false;               // inside the sample-count search's runs
 };
 
 struct ezo_robot {

@@ -1097,7 +1097,13 @@ __global__ void k_init_edges(int dof, const float* __restrict__ q_lo, const floa
 // End of an iteration: at k == max_iters every running edge becomes
 // MAX_ITERS (1); count running edges; k <- k + 1.  One workgroup.
 __global__ void __launch_bounds__(256) k_advance(int* __restrict__ k_dev, int max_iters, int* __restrict__ status,
-                                                 int n_edges, int* __restrict__ active_count) {
+                                                 int n_edges, int* __restrict__ active_count,
+                                                 int* __restrict__ host_active,
+                                                 const EdgeStatsDev* __restrict__ stats,
+                                                 EdgeStatsDev* __restrict__ host_stats) {
+    // the edges' statistics after this iteration, for the host (pinned)
+    if (host_stats)
+        for (int e = threadIdx.x; e < n_edges; e += blockDim.x) host_stats[e] = stats[e];
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
@@ -1114,6 +1120,7 @@ __global__ void __launch_bounds__(256) k_advance(int* __restrict__ k_dev, int ma
     if (threadIdx.x == 0) {
         *active_count = cnt;
         *k_dev = k + 1;
+        if (host_active) *host_active = cnt;
     }
 }
 
