@@ -109,3 +109,26 @@ def test_tuning_cache_rejects_malformed_lines(ezo, bad):
     with pytest.raises(ezo.EzoError):
         ezo.tune_cache_import(TUNE_LINE + "\n" + bad)
     assert ezo.tune_cache_entries() == []               # nothing imported from a rejected text
+
+
+def test_edge_stats_view_reads_the_c_array(ezo):
+    """The per-edge statistics of a call are a view of the C array the
+    library filled: dicts on access (indices, negative indices, slices),
+    equality with a list of dicts, and a zero-copy numpy view with the C
+    struct's layout."""
+    import ctypes as C
+    arr = (ezo.EdgeStats * 3)()
+    arr[0].iterations, arr[0].exact_checks = 2, 10
+    arr[2].planes, arr[2].exact_checks, arr[2].screened_checks = 7, 30, 4
+    v = ezo.EdgeStatsView(arr, 3)
+    assert len(v) == 3 and v[0]["iterations"] == 2 and v[-1]["planes"] == 7
+    assert [d["exact_checks"] for d in v] == [10, 0, 30]
+    assert v[1:] == [v[1], v[2]] and v == list(v)
+    with pytest.raises(IndexError):
+        v[3]
+    a = v.array
+    assert a.dtype.itemsize == C.sizeof(ezo.EdgeStats)
+    assert int(a["exact_checks"].sum()) == 40 and int(a["screened_checks"][2]) == 4
+    arr[1].samples = 5                                   # a view, not a copy
+    assert int(a["samples"][1]) == 5
+    assert len(ezo.EdgeStatsView(arr, 0).array) == 0
