@@ -276,7 +276,12 @@ __device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const Til
     for (ItemWalk w(n_valid); w.k < dof; w.next(n_valid)) {
         const int c = w.c, j = w.k;
         float s = 0.f, co = 1.f;
-        if (!((rb.prismatic >> j) & 1u)) sincosf(t.q[c * kMaxDof + j], &s, &co);
+        if (!((rb.prismatic >> j) & 1u)) {
+            // v_sin_f32 / v_cos_f32 take revolutions: q / (2 pi), rounded once
+            const float rev = t.q[c * kMaxDof + j] * 0.15915494309189535f;
+            s = __builtin_amdgcn_sinf(rev);
+            co = __builtin_amdgcn_cosf(rev);
+        }
         t.trig[j * T + c] = make_float2(co, s);
     }
     __syncthreads();
@@ -488,6 +493,8 @@ __device__ __forceinline__ bool wave_all(bool p) {
 
 // Signed-distance pair sweep.  Results: t.red[0][0][c] = overall minimum,
 // t.red[1][0][c] = self minimum; t.hit[c] = (overall < 0).  Barrier at exit.
+// Distances by v_sqrt_f32 (one instruction, within about 1 ulp; the
+// correctly rounded sqrtf takes several more per pair).
 template <bool BOX>
 __device__ inline void tile_pairs_sd(const RobotView& rb, const ObsView& ob, const TileSmem& t, int T,
                                      int n_valid) {
@@ -507,7 +514,7 @@ __device__ inline void tile_pairs_sd(const RobotView& rb, const ObsView& ob, con
             const float4 a = t.cen[pr.x * T + c];
             const float4 b = t.cen[pr.y * T + c];
             const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
-            const float d = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+            const float d = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
             self = fminf(self, d - a.w - b.w);
         }
     }
@@ -525,8 +532,8 @@ __device__ inline void tile_pairs_sd(const RobotView& rb, const ObsView& ob, con
                 const float4 P0 = cload4(rec + 4 * o);
                 const float ax = A.x - P0.x, ay = A.y - P0.y, az = A.z - P0.z;
                 const float bx = B.x - P0.x, by = B.y - P0.y, bz = B.z - P0.z;
-                const float dA = sqrtf(fmaf(ax, ax, fmaf(ay, ay, az * az)));
-                const float dB = sqrtf(fmaf(bx, bx, fmaf(by, by, bz * bz)));
+                const float dA = __builtin_amdgcn_sqrtf(fmaf(ax, ax, fmaf(ay, ay, az * az)));
+                const float dB = __builtin_amdgcn_sqrtf(fmaf(bx, bx, fmaf(by, by, bz * bz)));
                 bestA = fminf(bestA, dA - P0.w);
                 bestB = fminf(bestB, dB - P0.w);
             }
