@@ -178,11 +178,11 @@ bool bisect_shape_built(const TileCfg& g) {
 }
 
 // A shape is usable when its LDS fits and staging is possible where asked.
-bool cfg_valid(const ezo_ctx* c, const TileCfg& g, int S, int P, int n_obs, bool sd, bool bisect = false) {
+bool cfg_valid(const ezo_ctx* c, const TileCfg& g, int S, int P, int NB, int n_obs, bool sd, bool bisect = false) {
     if (!pow2_tile(g.T) || g.W < 1 || g.W > 16 || g.depth < 1 || g.depth > 3) return false;
     if (bisect ? !bisect_shape_built(g) : g.depth != 1) return false;
     const int T = tile_configs(g, bisect);
-    const size_t rs = bisect ? robot_stage_bytes(S, P) : 0;
+    const size_t rs = bisect ? robot_stage_bytes(S, P, NB) : 0;
     if (g.stage && (sd || !stage_fits(c, T, S, g.W, n_obs, rs))) return false;
     return tile_smem_bytes(T, S, g.W) + (g.stage ? 16 * (size_t)n_obs : 0) + rs <= c->lds_cap;
 }
@@ -214,23 +214,23 @@ TileCfg heuristic_bisect(const ezo_ctx* c, const ezo_robot* r, int n_obs, int64_
     TileCfg g;
     g.W = 4;
     g.depth = 1;
-    const size_t rs = robot_stage_bytes(r->slots, r->P);
+    const size_t rs = robot_stage_bytes(r->slots, r->P, r->view.n_blocks);
     g.T = std::max(std::min(pick_T(c, items, r->slots, g.W, rs), 64), 2);
     g.stage = stage_fits(c, g.T, r->slots, g.W, n_obs, rs) ? 1 : 0;
     return g;
 }
 
-TileCfg resolve_cfg(const ezo_ctx* c, const TuneKey& k, const TileCfg& fallback, int S, int P, int n_obs, bool sd,
+TileCfg resolve_cfg(const ezo_ctx* c, const TuneKey& k, const TileCfg& fallback, int S, int P, int NB, int n_obs, bool sd,
                     bool bisect = false) {
     TileCfg g;
-    if (ezo_tune_lookup(k, &g) && cfg_valid(c, g, S, P, n_obs, sd, bisect)) return g;
+    if (ezo_tune_lookup(k, &g) && cfg_valid(c, g, S, P, NB, n_obs, sd, bisect)) return g;
     return fallback;
 }
 
 // Candidate shapes: every fitting T x W x staging (x bisection depth 1..2);
 // T = configurations (check, 4..64) or candidates (bisection, 1..64) per
 // workgroup; items = configurations or candidate slots.
-std::vector<TileCfg> tile_candidates(const ezo_ctx* c, int S, int P, int n_obs, bool sd, std::initializer_list<int> Ws,
+std::vector<TileCfg> tile_candidates(const ezo_ctx* c, int S, int P, int NB, int n_obs, bool sd, std::initializer_list<int> Ws,
                                      int64_t items, bool bisect = false) {
     std::vector<TileCfg> v;
     // (bisection: one or two levels per round; three, seven points per
@@ -243,7 +243,7 @@ std::vector<TileCfg> tile_candidates(const ezo_ctx* c, int S, int P, int n_obs, 
             for (int W : Ws)
                 for (int st = 0; st <= (sd ? 0 : 1); ++st) {
                     TileCfg g{T, W, st, dp};
-                    if (cfg_valid(c, g, S, P, n_obs, sd, bisect)) v.push_back(g);
+                    if (cfg_valid(c, g, S, P, NB, n_obs, sd, bisect)) v.push_back(g);
                 }
         }
     return v;
@@ -261,7 +261,7 @@ ezo_status launch_check(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const
     } else {
         const int64_t items = n * n_batch;
         g = resolve_cfg(c, tune_key(c, r, SD ? TUNE_CHECK_SD : TUNE_CHECK_FLAGS, ov.n, items),
-                        heuristic_check(c, r, ov.n, items, SD), r->slots, r->P, ov.n, SD);
+                        heuristic_check(c, r, ov.n, items, SD), r->slots, r->P, r->view.n_blocks, ov.n, SD);
     }
     const int T = g.T, W = g.W;
     if (T == 0) return ezo_fail(c, EZO_E_UNSUPPORTED, "robot too large for one tile");
@@ -406,7 +406,7 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
         g = *shape;
     } else {
         const int64_t items = (int64_t)cand_cap * E;
-        g = resolve_cfg(c, tune_key(c, r, TUNE_BISECT, ov.n, items), heuristic_bisect(c, r, ov.n, items), r->slots, r->P,
+        g = resolve_cfg(c, tune_key(c, r, TUNE_BISECT, ov.n, items), heuristic_bisect(c, r, ov.n, items), r->slots, r->P, r->view.n_blocks,
                         ov.n, false, true);
     }
     const bool box = r->B > 0 || ov.n_ebox > 0;
@@ -424,7 +424,7 @@ ezo_status launch_project_bisect(ezo_ctx* c, const ezo_robot* r, const ObsView& 
     ObsView ovs = ov;
     ovs.lds_n = g.stage ? ov.n : 0;
     size_t lds = tile_smem_bytes(tile_configs(g, true), r->slots, W) + 16 * (size_t)ovs.lds_n +
-                 robot_stage_bytes(r->slots, r->P);
+                 robot_stage_bytes(r->slots, r->P, r->view.n_blocks);
     if (scr) {
         lds += mlp_tile_smem_bytes(1) + 16 * sizeof(float);
         if (lds > c->lds_cap && ovs.lds_n > 0) {        // drop the obstacle staging first
@@ -511,8 +511,8 @@ ezo_status tune_check_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov,
     if (!c->autotune || ezo_tune_lookup(k, &g)) return EZO_OK;
     const int64_t n_t = SD ? std::min<int64_t>(n, std::max<int64_t>(65536, (1LL << 28) / std::max(ov.n, 256)))
                            : std::min<int64_t>(n, 1LL << 19);
-    const auto cands = SD ? tile_candidates(c, r->slots, r->P, ov.n, true, {1, 2, 4, 8, 16}, n_t)
-                          : tile_candidates(c, r->slots, r->P, ov.n, false, {1, 2, 4, 8}, n_t);
+    const auto cands = SD ? tile_candidates(c, r->slots, r->P, r->view.n_blocks, ov.n, true, {1, 2, 4, 8, 16}, n_t)
+                          : tile_candidates(c, r->slots, r->P, r->view.n_blocks, ov.n, false, {1, 2, 4, 8}, n_t);
     if (cands.empty()) return EZO_OK;
     IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
     auto run = [&](const TileCfg& cfg) {
@@ -530,7 +530,7 @@ ezo_status tune_bisect_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov
     const TuneKey k = tune_key(c, r, TUNE_BISECT, ov.n, (int64_t)cand_cap * E);
     TileCfg g;
     if (!c->autotune || ezo_tune_lookup(k, &g)) return EZO_OK;
-    const auto cands = tile_candidates(c, r->slots, r->P, ov.n, false, {1, 2, 4, 8, 16}, (int64_t)cand_cap * E, true);
+    const auto cands = tile_candidates(c, r->slots, r->P, r->view.n_blocks, ov.n, false, {1, 2, 4, 8, 16}, (int64_t)cand_cap * E, true);
     if (cands.empty()) return EZO_OK;
     auto run = [&](const TileCfg& cfg) {
         return launch_project_bisect(c, r, ov, gv, edges, E, S, stride, cand_idx, n_cands, cand_cap, n_b, c_star,
@@ -592,7 +592,7 @@ ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, con
                                    stride, E, nullptr, it, st, nullptr, 0.f, nullptr, &cfg);
     };
     if (need_c) {
-        const auto cands = tile_candidates(c, r->slots, r->P, ov.n, false, {1, 2, 4, 8}, (int64_t)S_cap * E);
+        const auto cands = tile_candidates(c, r->slots, r->P, r->view.n_blocks, ov.n, false, {1, 2, 4, 8}, (int64_t)S_cap * E);
         if (!cands.empty() && (s = ezo_tune_search(c, kc, cands, st, run_c, &g))) return s;
     }
     if (!need_b) return EZO_OK;
@@ -601,7 +601,7 @@ ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, con
     hipLaunchKernelGGL(k_test_select, dim3(E), dim3(1024), 0, st, w_f, stride, p->n_p, p->n_b, w_ci, cand_cap, w_nc,
                        nullptr, nullptr, nullptr, nullptr, sel);
     HIP_TRY(c, hipGetLastError());
-    const auto cands = tile_candidates(c, r->slots, r->P, ov.n, false, {1, 2, 4, 8, 16}, (int64_t)cand_cap * E, true);
+    const auto cands = tile_candidates(c, r->slots, r->P, r->view.n_blocks, ov.n, false, {1, 2, 4, 8, 16}, (int64_t)cand_cap * E, true);
     if (cands.empty()) return EZO_OK;
     const int light = std::max(16, (int)std::ceil(2.0 * p->eps * cand_cap));
     int* w_nc_light = reinterpret_cast<int*>(w_f);      // the flags are free once selected (E <= stride E / 4)
@@ -793,12 +793,19 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
         link_begin[d->sphere_link[o] + 1]++;
     }
     for (int j = 0; j < dof; ++j) link_begin[j + 1] += link_begin[j];
-    // self pairs grouped into blocks by (lower link, higher link)
+    // parts: the first and second half of each link's (sorted) spheres, part
+    // 2 l + p; self pairs grouped into blocks by (lower part, higher part)
+    auto part_of = [&](int sorted) {
+        int l = 0;
+        while (sorted >= link_begin[l + 1]) ++l;
+        const int n = link_begin[l + 1] - link_begin[l];
+        return 2 * l + ((sorted - link_begin[l]) < n / 2 ? 0 : 1);
+    };
     std::vector<std::pair<std::pair<int, int>, int2>> keyed(P);
     for (int p = 0; p < P; ++p) {
         const int a = orig_to_sorted[d->self_pairs[2 * p]], bb = orig_to_sorted[d->self_pairs[2 * p + 1]];
-        const int la = d->sphere_link[d->self_pairs[2 * p]], lbk = d->sphere_link[d->self_pairs[2 * p + 1]];
-        keyed[p] = {{std::min(la, lbk), std::max(la, lbk)}, make_int2(a, bb)};
+        const int pa = part_of(a), pb = part_of(bb);
+        keyed[p] = {{std::min(pa, pb), std::max(pa, pb)}, make_int2(a, bb)};
     }
     std::stable_sort(keyed.begin(), keyed.end(),
                      [](const auto& x, const auto& y) { return x.first < y.first; });
@@ -811,12 +818,14 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     }
     if (blocks.empty()) blocks.push_back(make_int4(0, 0, 0, 0));
     const int NB = P > 0 ? (int)blocks.size() : 0;
-    // bounding sphere of each link's spheres (link frame): centre of the
+    // bounding sphere of each part's spheres (link frame): centre of the
     // centres' box, radius = max distance + sphere radius
-    std::vector<float4> lbound(dof, make_float4(0.f, 0.f, 0.f, 0.f));
+    std::vector<float4> lbound(2 * (size_t)dof, make_float4(0.f, 0.f, 0.f, 0.f));
     float r_max = 0.f;
-    for (int j = 0; j < dof; ++j) {
-        const int s0 = link_begin[j], s1 = link_begin[j + 1];
+    for (int j = 0; j < 2 * dof; ++j) {
+        const int l = j >> 1, half = (link_begin[l + 1] - link_begin[l]) / 2;
+        const int s0 = (j & 1) ? link_begin[l] + half : link_begin[l];
+        const int s1 = (j & 1) ? link_begin[l + 1] : link_begin[l] + half;
         if (s1 <= s0) continue;
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
         for (int s2 = s0; s2 < s1; ++s2) {
@@ -1447,9 +1456,9 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         }
         for (const DevBuf& wb : c->ws) push(wb.p);
         const TileCfg gc = resolve_cfg(c, tune_key(c, r, TUNE_CHECK_FLAGS, ov.n, (int64_t)S_cap * E),
-                                       heuristic_check(c, r, ov.n, (int64_t)S_cap * E, false), r->slots, r->P, ov.n, false);
+                                       heuristic_check(c, r, ov.n, (int64_t)S_cap * E, false), r->slots, r->P, r->view.n_blocks, ov.n, false);
         const TileCfg gb = resolve_cfg(c, tune_key(c, r, TUNE_BISECT, ov.n, (int64_t)cand_cap * E),
-                                       heuristic_bisect(c, r, ov.n, (int64_t)cand_cap * E), r->slots, r->P, ov.n, false, true);
+                                       heuristic_bisect(c, r, ov.n, (int64_t)cand_cap * E), r->slots, r->P, r->view.n_blocks, ov.n, false, true);
         for (const TileCfg& g : {gc, gb}) {
             key.push_back((uintptr_t)g.T);
             key.push_back((uintptr_t)g.W);

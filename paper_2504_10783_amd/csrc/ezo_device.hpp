@@ -39,8 +39,10 @@ struct RobotView {
     const int* link_begin;     // [dof + 1] spheres of link i: [link_begin[i], link_begin[i+1])
     const float4* sph;         // [S] local (x, y, z), r -- sorted by link
     const int2* pairs;         // [P] self pairs, indices into the sorted order, grouped by block
-    const float4* lbound;      // [dof] bounding sphere of each link's spheres: local centre, radius
-    const int4* blocks;        // [n_blocks] per link pair: (link i, link j, first pair, pair count)
+    const float4* lbound;      // [2 dof] bounding sphere of each part of a link (part p of link l
+                               // = index 2 l + p: the first and second half of the link's
+                               // spheres): centre in the link frame, radius
+    const int4* blocks;        // [n_blocks] per part pair: (part a, part b, first pair, pair count)
     // boxes on links, sorted by link: box k = four float4 in the link frame,
     // (centre, h_x), (rotation row 0, h_y), (row 1, h_z), (row 2, bounding
     // radius |h|); the rotation's columns are the box axes
@@ -54,21 +56,22 @@ struct RobotView {
 // LDS rows of a tile's pose array: one per sphere, four per box.
 __host__ __device__ inline int tile_slots(int n_spheres, int n_boxes) { return n_spheres + 4 * n_boxes; }
 
-constexpr int kMaxLinkPairs = kMaxDof * (kMaxDof + 1) / 2;   // link pairs, same-link pairs included
+constexpr int kMaxParts = 2 * kMaxDof;                           // two parts per link
+constexpr int kMaxPartPairs = kMaxParts * (kMaxParts + 1) / 2;   // part pairs, same-part pairs included
 
 // Robot tables that a workgroup running many dependent tile checks (the
-// bisection) copies into LDS once: DH rows, link bounding spheres, self-pair
-// blocks, spheres, link sphere ranges and, up to kStagePairs of them, the
-// self pairs; their reads in FK and in the self-pair sweep then cost an LDS
-// access instead of a cache access.  At most this many bytes (slots >=
-// spheres, n_self = self pairs).
+// bisection) copies into LDS once: DH rows, part bounding spheres, link
+// sphere ranges, spheres, self-pair blocks and, up to kStagePairs of them,
+// the self pairs; their reads in FK and in the self-pair sweep then cost an
+// LDS access instead of a cache access.  At most this many bytes (slots >=
+// spheres, n_self = self pairs, n_blocks = self-pair blocks).
 constexpr int kStagePairs = 2048;
 
 __host__ __device__ inline int robot_staged_pairs(int n_self) { return n_self <= kStagePairs ? n_self : 0; }
 
-__host__ __device__ inline size_t robot_stage_bytes(int slots, int n_self) {
-    return 16 * (size_t)(2 * kMaxDof + kMaxLinkPairs + (slots > 0 ? slots : 1)) + 16 * ((kMaxDof + 4) / 4) +
-           16 * (((size_t)robot_staged_pairs(n_self) + 1) / 2);
+__host__ __device__ inline size_t robot_stage_bytes(int slots, int n_self, int n_blocks) {
+    return 16 * (size_t)(kMaxDof + kMaxParts + (slots > 0 ? slots : 1) + (n_blocks > 0 ? n_blocks : 1)) +
+           16 * ((kMaxDof + 4) / 4) + 16 * (((size_t)robot_staged_pairs(n_self) + 1) / 2);
 }
 
 // Copies the tables into LDS at `base` (16-byte aligned, robot_stage_bytes
@@ -78,16 +81,14 @@ __host__ __device__ inline size_t robot_stage_bytes(int slots, int n_self) {
 __device__ inline RobotView stage_robot(const RobotView& rb, char* base) {
     float4* dh = reinterpret_cast<float4*>(base);
     float4* lb = dh + kMaxDof;
-    int4* blk = reinterpret_cast<int4*>(lb + kMaxDof);
-    float4* sph = reinterpret_cast<float4*>(blk + kMaxLinkPairs);
+    float4* sph = lb + kMaxParts;
     int* lbeg = reinterpret_cast<int*>(sph + (rb.n_spheres > 0 ? rb.n_spheres : 1));
-    int2* prs = reinterpret_cast<int2*>(lbeg + 4 * ((kMaxDof + 4) / 4));
+    int4* blk = reinterpret_cast<int4*>(lbeg + 4 * ((kMaxDof + 4) / 4));
+    int2* prs = reinterpret_cast<int2*>(blk + (rb.n_blocks > 0 ? rb.n_blocks : 1));
     const int np = robot_staged_pairs(rb.n_self);
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (int i = tid; i < rb.dof; i += nt) {
-        dh[i] = rb.dh[i];
-        lb[i] = rb.lbound[i];
-    }
+    for (int i = tid; i < rb.dof; i += nt) dh[i] = rb.dh[i];
+    for (int i = tid; i < 2 * rb.dof; i += nt) lb[i] = rb.lbound[i];
     for (int i = tid; i <= rb.dof; i += nt) lbeg[i] = rb.link_begin[i];
     for (int i = tid; i < rb.n_blocks; i += nt) blk[i] = rb.blocks[i];
     for (int i = tid; i < rb.n_spheres; i += nt) sph[i] = rb.sph[i];
@@ -201,11 +202,11 @@ struct TileSmem {
     float2* trig;      // [kMaxDof][T] (cos, sin) of each joint
     float4* cen;       // [S + 4B][T] sphere centres (shifted frame) and radius, then each
                        // box's world pose as four rows (packed like RobotView::box)
-    float4* lb;        // [kMaxDof][T] link bounding spheres (shifted frame)
+    float4* lb;        // [kMaxParts][T] part bounding spheres (shifted frame)
     int* hit;          // [T] collision flag (flags mode) / validity
     int* scr;          // [T] 1 = the learned screen cleared this configuration's self pairs
     float* red;        // [2][W][T] partial minima (signed-distance mode)
-    int* wl;           // [T][kMaxLinkPairs] work list: (configuration, link pair) whose bounds overlap
+    unsigned short* wl;  // [T][kMaxPartPairs] work list: (part pair << 8) | configuration, bounds overlapping
     int* wl_n;         // [1] work list length
     float4* obs;       // [lds_n] staged obstacle records (x, y, z, r), or NULL
 };
@@ -215,10 +216,10 @@ __host__ __device__ inline size_t tile_smem_bytes(int T, int S, int W) {
     b += sizeof(float) * (size_t)T * kMaxDof;
     b += sizeof(float2) * (size_t)kMaxDof * T;
     b += sizeof(float4) * (size_t)(S > 0 ? S : 1) * T;
-    b += sizeof(float4) * (size_t)kMaxDof * T;
+    b += sizeof(float4) * (size_t)kMaxParts * T;
     b += sizeof(int) * 2 * (size_t)T;
     b += sizeof(float) * 2 * (size_t)W * T;
-    b += sizeof(int) * ((size_t)T * kMaxLinkPairs + 1);
+    b += sizeof(unsigned short) * (size_t)T * kMaxPartPairs + sizeof(int);
     return (b + 15) & ~(size_t)15;
 }
 
@@ -228,13 +229,13 @@ __device__ inline TileSmem carve_tile(char* base, int T, int S, int W, int lds_n
     t.obs = lds_n > 0 ? reinterpret_cast<float4*>(base + tile_smem_bytes(T, S, W)) : nullptr;
     char* p = base;
     t.cen = reinterpret_cast<float4*>(p);   p += sizeof(float4) * (size_t)(S > 0 ? S : 1) * T;
-    t.lb = reinterpret_cast<float4*>(p);    p += sizeof(float4) * (size_t)kMaxDof * T;
+    t.lb = reinterpret_cast<float4*>(p);    p += sizeof(float4) * (size_t)kMaxParts * T;
     t.trig = reinterpret_cast<float2*>(p);  p += sizeof(float2) * (size_t)kMaxDof * T;
     t.q = reinterpret_cast<float*>(p);      p += sizeof(float) * (size_t)T * kMaxDof;
     t.red = reinterpret_cast<float*>(p);    p += sizeof(float) * 2 * (size_t)W * T;
     t.hit = reinterpret_cast<int*>(p);      p += sizeof(int) * (size_t)T;
     t.scr = reinterpret_cast<int*>(p);      p += sizeof(int) * (size_t)T;
-    t.wl = reinterpret_cast<int*>(p);       p += sizeof(int) * (size_t)T * kMaxLinkPairs;
+    t.wl = reinterpret_cast<unsigned short*>(p);  p += sizeof(unsigned short) * (size_t)T * kMaxPartPairs;
     t.wl_n = reinterpret_cast<int*>(p);
     return t;
 }
@@ -303,14 +304,16 @@ __device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const Til
             if ((rb.prismatic >> l) & 1u) dh.y += t.q[c * kMaxDof + l];
             dh_compose(R, p, cs.x, cs.y, dh);
         }
-        if (part == 0) {
-            const float4 lc = rb.lbound[link];
-            float4 o;
-            o.x = fmaf(R[0], lc.x, fmaf(R[1], lc.y, fmaf(R[2], lc.z, p[0])));
-            o.y = fmaf(R[3], lc.x, fmaf(R[4], lc.y, fmaf(R[5], lc.z, p[1])));
-            o.z = fmaf(R[6], lc.x, fmaf(R[7], lc.y, fmaf(R[8], lc.z, p[2])));
-            o.w = lc.w;
-            t.lb[link * T + c] = o;
+        if (part < 2) {                   // the link's two part bounds, one per lane when P >= 2
+            for (int pp = part; pp < 2; pp += P) {
+                const float4 lc = rb.lbound[2 * link + pp];
+                float4 o;
+                o.x = fmaf(R[0], lc.x, fmaf(R[1], lc.y, fmaf(R[2], lc.z, p[0])));
+                o.y = fmaf(R[3], lc.x, fmaf(R[4], lc.y, fmaf(R[5], lc.z, p[1])));
+                o.z = fmaf(R[6], lc.x, fmaf(R[7], lc.y, fmaf(R[8], lc.z, p[2])));
+                o.w = lc.w;
+                t.lb[(2 * link + pp) * T + c] = o;
+            }
         }
         const int s1 = rb.link_begin[link + 1];
         for (int s = rb.link_begin[link] + part; s < s1; s += P) {
@@ -672,18 +675,25 @@ __device__ inline unsigned tile_pairs_grid(const RobotView& rb, const ObsView& o
             const float dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;
             const float R = A.w + B.w;
             ++ntest;
-            if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < R * R) t.wl[atomicAdd(t.wl_n, 1)] = (bk << 8) | c;
+            if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < R * R)
+                t.wl[atomicAdd(t.wl_n, 1)] = (unsigned short)((bk << 8) | c);
         }
         __syncthreads();
+        // two work items per wave, one per half-wave of 32 lanes (a part
+        // pair of two half links holds about a quarter of the link pair's
+        // sphere pairs)
         const int n_items = *t.wl_n;
-        const int lane = threadIdx.x & 63;
-        for (int it = wave_id(); it < n_items; it += blockDim.x >> 6) {
+        const int lane = threadIdx.x & 63, half = lane >> 5, l32 = lane & 31;
+        const int nw = blockDim.x >> 6;
+        for (int it0 = 2 * wave_id(); it0 < n_items; it0 += 2 * nw) {
+            const int it = it0 + half;
+            if (it >= n_items) continue;
             const int item = t.wl[it];
             const int c = item & 255;
-            if (hit[c]) continue;                          // wave-uniform
+            if (hit[c]) continue;                          // uniform in the half-wave
             const int4 blk = rb.blocks[item >> 8];
             bool found = false;
-            for (int p = lane; p < blk.w; p += 64) {
+            for (int p = l32; p < blk.w; p += 32) {
                 const int2 pr = rb.pairs[blk.z + p];
                 const float4 a = t.cen[pr.x * T + c];
                 const float4 b = t.cen[pr.y * T + c];

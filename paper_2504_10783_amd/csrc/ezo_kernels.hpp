@@ -703,7 +703,7 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rg, ObsView o
     const RobotView rb = stage_robot(rg, rs_base);
     // screened form: the network's activations and predictions after the
     // staged robot tables
-    __bf16* mlp_h = reinterpret_cast<__bf16*>(rs_base + robot_stage_bytes(slots, rg.n_self));
+    __bf16* mlp_h = reinterpret_cast<__bf16*>(rs_base + robot_stage_bytes(slots, rg.n_self, rg.n_blocks));
     float* mlp_y = reinterpret_cast<float*>(reinterpret_cast<char*>(mlp_h) + mlp_tile_smem_bytes(1));
     stage_obstacles(ob, t);
     const int tid = threadIdx.x;
