@@ -793,13 +793,18 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
         link_begin[d->sphere_link[o] + 1]++;
     }
     for (int j = 0; j < dof; ++j) link_begin[j + 1] += link_begin[j];
-    // parts: the first and second half of each link's (sorted) spheres, part
-    // 2 l + p; self pairs grouped into blocks by (lower part, higher part)
+    // parts: kPartsPerLink consecutive runs of each link's (sorted) spheres,
+    // part p of link l = kPartsPerLink l + p covering local indices
+    // [p n / K, (p + 1) n / K); self pairs grouped into blocks by (lower
+    // part, higher part)
+    constexpr int K = kPartsPerLink;
     auto part_of = [&](int sorted) {
         int l = 0;
         while (sorted >= link_begin[l + 1]) ++l;
-        const int n = link_begin[l + 1] - link_begin[l];
-        return 2 * l + ((sorted - link_begin[l]) < n / 2 ? 0 : 1);
+        const int n = link_begin[l + 1] - link_begin[l], i = sorted - link_begin[l];
+        int p = 0;
+        while (p + 1 < K && i >= (p + 1) * n / K) ++p;
+        return K * l + p;
     };
     std::vector<std::pair<std::pair<int, int>, int2>> keyed(P);
     for (int p = 0; p < P; ++p) {
@@ -820,12 +825,11 @@ ezo_status ezo_robot_create(ezo_ctx* c, const ezo_robot_desc* d, ezo_robot** out
     const int NB = P > 0 ? (int)blocks.size() : 0;
     // bounding sphere of each part's spheres (link frame): centre of the
     // centres' box, radius = max distance + sphere radius
-    std::vector<float4> lbound(2 * (size_t)dof, make_float4(0.f, 0.f, 0.f, 0.f));
+    std::vector<float4> lbound((size_t)K * dof, make_float4(0.f, 0.f, 0.f, 0.f));
     float r_max = 0.f;
-    for (int j = 0; j < 2 * dof; ++j) {
-        const int l = j >> 1, half = (link_begin[l + 1] - link_begin[l]) / 2;
-        const int s0 = (j & 1) ? link_begin[l] + half : link_begin[l];
-        const int s1 = (j & 1) ? link_begin[l + 1] : link_begin[l] + half;
+    for (int j = 0; j < K * dof; ++j) {
+        const int l = j / K, p = j % K, n = link_begin[l + 1] - link_begin[l];
+        const int s0 = link_begin[l] + p * n / K, s1 = link_begin[l] + (p + 1) * n / K;
         if (s1 <= s0) continue;
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
         for (int s2 = s0; s2 < s1; ++s2) {

@@ -39,9 +39,9 @@ struct RobotView {
     const int* link_begin;     // [dof + 1] spheres of link i: [link_begin[i], link_begin[i+1])
     const float4* sph;         // [S] local (x, y, z), r -- sorted by link
     const int2* pairs;         // [P] self pairs, indices into the sorted order, grouped by block
-    const float4* lbound;      // [2 dof] bounding sphere of each part of a link (part p of link l
-                               // = index 2 l + p: the first and second half of the link's
-                               // spheres): centre in the link frame, radius
+    const float4* lbound;      // [kPartsPerLink dof] bounding sphere of each part of a link (part
+                               // p of link l = index kPartsPerLink l + p, a consecutive run of the
+                               // link's spheres): centre in the link frame, radius
     const int4* blocks;        // [n_blocks] per part pair: (part a, part b, first pair, pair count)
     // boxes on links, sorted by link: box k = four float4 in the link frame,
     // (centre, h_x), (rotation row 0, h_y), (row 1, h_z), (row 2, bounding
@@ -56,8 +56,14 @@ struct RobotView {
 // LDS rows of a tile's pose array: one per sphere, four per box.
 __host__ __device__ inline int tile_slots(int n_spheres, int n_boxes) { return n_spheres + 4 * n_boxes; }
 
-constexpr int kMaxParts = 2 * kMaxDof;                           // two parts per link
+// Self-pair broad phase: each link's spheres split into kPartsPerLink parts
+// (consecutive runs of its sphere list), each with its own bounding sphere;
+// a work item (configuration, part pair) is taken by kItemLanes lanes.
+constexpr int kPartsPerLink = 2;
+constexpr int kItemLanes = 16;
+constexpr int kMaxParts = kPartsPerLink * kMaxDof;
 constexpr int kMaxPartPairs = kMaxParts * (kMaxParts + 1) / 2;   // part pairs, same-part pairs included
+static_assert(kMaxPartPairs < 1024, "work items hold (part pair << 6) | configuration in 16 bits");
 
 // Robot tables that a workgroup running many dependent tile checks (the
 // bisection) copies into LDS once: DH rows, part bounding spheres, link
@@ -88,7 +94,7 @@ __device__ inline RobotView stage_robot(const RobotView& rb, char* base) {
     const int np = robot_staged_pairs(rb.n_self);
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int i = tid; i < rb.dof; i += nt) dh[i] = rb.dh[i];
-    for (int i = tid; i < 2 * rb.dof; i += nt) lb[i] = rb.lbound[i];
+    for (int i = tid; i < kPartsPerLink * rb.dof; i += nt) lb[i] = rb.lbound[i];
     for (int i = tid; i <= rb.dof; i += nt) lbeg[i] = rb.link_begin[i];
     for (int i = tid; i < rb.n_blocks; i += nt) blk[i] = rb.blocks[i];
     for (int i = tid; i < rb.n_spheres; i += nt) sph[i] = rb.sph[i];
@@ -206,7 +212,7 @@ struct TileSmem {
     int* hit;          // [T] collision flag (flags mode) / validity
     int* scr;          // [T] 1 = the learned screen cleared this configuration's self pairs
     float* red;        // [2][W][T] partial minima (signed-distance mode)
-    unsigned short* wl;  // [T][kMaxPartPairs] work list: (part pair << 8) | configuration, bounds overlapping
+    unsigned short* wl;  // [T][kMaxPartPairs] work list: (part pair << 6) | configuration, bounds overlapping
     int* wl_n;         // [1] work list length
     float4* obs;       // [lds_n] staged obstacle records (x, y, z, r), or NULL
 };
@@ -304,15 +310,15 @@ __device__ inline void tile_fk(const RobotView& rb, const ObsView& ob, const Til
             if ((rb.prismatic >> l) & 1u) dh.y += t.q[c * kMaxDof + l];
             dh_compose(R, p, cs.x, cs.y, dh);
         }
-        if (part < 2) {                   // the link's two part bounds, one per lane when P >= 2
-            for (int pp = part; pp < 2; pp += P) {
-                const float4 lc = rb.lbound[2 * link + pp];
+        if (part < kPartsPerLink) {       // the link's part bounds, spread over its P lanes
+            for (int pp = part; pp < kPartsPerLink; pp += P) {
+                const float4 lc = rb.lbound[kPartsPerLink * link + pp];
                 float4 o;
                 o.x = fmaf(R[0], lc.x, fmaf(R[1], lc.y, fmaf(R[2], lc.z, p[0])));
                 o.y = fmaf(R[3], lc.x, fmaf(R[4], lc.y, fmaf(R[5], lc.z, p[1])));
                 o.z = fmaf(R[6], lc.x, fmaf(R[7], lc.y, fmaf(R[8], lc.z, p[2])));
                 o.w = lc.w;
-                t.lb[(2 * link + pp) * T + c] = o;
+                t.lb[(kPartsPerLink * link + pp) * T + c] = o;
             }
         }
         const int s1 = rb.link_begin[link + 1];
@@ -676,24 +682,24 @@ __device__ inline unsigned tile_pairs_grid(const RobotView& rb, const ObsView& o
             const float R = A.w + B.w;
             ++ntest;
             if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < R * R)
-                t.wl[atomicAdd(t.wl_n, 1)] = (unsigned short)((bk << 8) | c);
+                t.wl[atomicAdd(t.wl_n, 1)] = (unsigned short)((bk << 6) | c);
         }
         __syncthreads();
-        // two work items per wave, one per half-wave of 32 lanes (a part
-        // pair of two half links holds about a quarter of the link pair's
-        // sphere pairs)
+        // 64 / kItemLanes work items per wave, kItemLanes lanes each (a part
+        // pair holds a fraction of its link pair's sphere pairs)
+        constexpr int IPW = 64 / kItemLanes;
         const int n_items = *t.wl_n;
-        const int lane = threadIdx.x & 63, half = lane >> 5, l32 = lane & 31;
+        const int lane = threadIdx.x & 63, sub = lane / kItemLanes, li = lane % kItemLanes;
         const int nw = blockDim.x >> 6;
-        for (int it0 = 2 * wave_id(); it0 < n_items; it0 += 2 * nw) {
-            const int it = it0 + half;
+        for (int it0 = IPW * wave_id(); it0 < n_items; it0 += IPW * nw) {
+            const int it = it0 + sub;
             if (it >= n_items) continue;
             const int item = t.wl[it];
-            const int c = item & 255;
-            if (hit[c]) continue;                          // uniform in the half-wave
-            const int4 blk = rb.blocks[item >> 8];
+            const int c = item & 63;
+            if (hit[c]) continue;                          // uniform in the lane group
+            const int4 blk = rb.blocks[item >> 6];
             bool found = false;
-            for (int p = l32; p < blk.w; p += 32) {
+            for (int p = li; p < blk.w; p += kItemLanes) {
                 const int2 pr = rb.pairs[blk.z + p];
                 const float4 a = t.cen[pr.x * T + c];
                 const float4 b = t.cen[pr.y * T + c];
