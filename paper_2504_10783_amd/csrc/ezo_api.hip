@@ -1122,7 +1122,7 @@ ezo_status ezo_place_hyperplanes(ezo_ctx* c, int32_t dof, const float* edges, in
     if (n_edges == 0) return EZO_OK;
     if (!edges || !c_star || !a_dir || !t_star || !n_cands || !A || !b || !n_faces || !edge_status)
         return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
-    if ((size_t)cand_capacity > c->lds_cap - 1024) return ezo_fail(c, EZO_E_UNSUPPORTED, "cand_capacity too large");
+    if ((size_t)cand_capacity > c->lds_cap - kPlaceStaticLds) return ezo_fail(c, EZO_E_UNSUPPORTED, "cand_capacity too large");
     HIP_TRY(c, hipSetDevice(c->device));
     hipLaunchKernelGGL(k_place, dim3(n_edges), dim3(1024), (size_t)std::max(cand_capacity, 16), as_stream(stream), dof,
                        edges, c_star, a_dir, t_star, n_cands, cand_capacity, n_f, (float)step_back_max, (float)t_col, A,
@@ -1207,7 +1207,7 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
     const int cap = p->face_capacity;
     if (sample_smem_bytes(dof <= 4 ? 4 : 8, 16, cap, 256) > c->lds_cap)
         return ezo_fail(c, EZO_E_UNSUPPORTED, "face_capacity %d too large", cap);
-    if ((size_t)p->n_p > c->lds_cap - 1024) return ezo_fail(c, EZO_E_UNSUPPORTED, "n_p %d too large", p->n_p);
+    if ((size_t)p->n_p > c->lds_cap - kPlaceStaticLds) return ezo_fail(c, EZO_E_UNSUPPORTED, "n_p %d too large", p->n_p);
     // per-iteration constants, FP64 on the host
     std::vector<int4> table(p->max_iters + 2, make_int4(0, 0, 0, 0));
     int S_cap = 0;
@@ -1815,8 +1815,8 @@ ezo_status ezo_update_polytopes(ezo_ctx* c, const ezo_robot* r, const float* obs
     if (n_edges == 0 || n_points == 0) return EZO_OK;
     if (!edges || !points || !A || !b || !n_faces || !edge_status || (n_obs > 0 && !obs))
         return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
-    if ((size_t)n_points > c->lds_cap - 1024)
-        return ezo_fail(c, EZO_E_UNSUPPORTED, "%d points: at most %zu per call", n_points, c->lds_cap - 1024);
+    if ((size_t)n_points > c->lds_cap - kPlaceStaticLds)
+        return ezo_fail(c, EZO_E_UNSUPPORTED, "%d points: at most %zu per call", n_points, c->lds_cap - kPlaceStaticLds);
     HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t st = as_stream(stream);
     const int dof = r->dof, E = n_edges, N = n_points;

@@ -819,176 +819,50 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rg, ObsView o
 
 // ---------------------------------------------------------------------------
 // Ordering and placing hyperplanes: one workgroup (1024 threads) per edge,
-// n_f rounds of (argmin over alive candidates by (t*, index), broadcast row,
-// discard).
+// up to n_f rounds of (argmin over the alive candidates by (t*, index), the
+// chosen candidate's row, discard of the candidates that row separates).
+//
+// Candidate j = tid + q blockDim with q < kPlaceReg keeps c*, a and t* in the
+// thread's registers; candidates past kPlaceReg blockDim (the tail) are read
+// from global memory in every round, their alive flags in LDS.  One barrier
+// per round: each wave takes its smallest (t*, index) key by DPP and readlane,
+// the lane holding that candidate publishes its c* and a in the wave's LDS
+// slot, and after the barrier every wave reduces the slots' keys the same way
+// (one slot per lane) and builds the row itself (the same FP32 operations on
+// the same values in every thread).  The chosen rows stay in LDS and are
+// written to global memory once, after the last round.
 // ---------------------------------------------------------------------------
-// Placement rounds of one edge.  REG: the thread's candidates j = tid +
-// q blockDim (q < kPlaceReg) keep c* and their (t*, index) keys in registers
-// (needs n <= kPlaceReg blockDim); otherwise both are read from global memory
-// every round and the alive flags live in LDS.
-constexpr int kPlaceReg = 4;
+constexpr int kPlaceReg = 4;       // candidates per thread held in registers
+constexpr int kPlaceHist = 64;     // chosen rows kept in LDS until the end
+constexpr int kPlaceWaves = 16;    // waves of the 1024-thread workgroup
 
-template <bool REG>
-__device__ inline void place_rounds(int e, int dof, const float* __restrict__ v, const float* __restrict__ cs,
-                                    const float* __restrict__ ad, const float* __restrict__ ts, int n, int cand_cap,
-                                    int n_f, float step_back_max, float t_col, float* __restrict__ A,
-                                    float* __restrict__ bvec, int* __restrict__ n_faces, int cap,
-                                    int* __restrict__ status, int* __restrict__ placed_idx,
-                                    int* __restrict__ n_placed, EdgeStatsDev* __restrict__ stats, uint8_t* alive,
-                                    unsigned long long* wmin, float* row, int* s_stop, float* __restrict__ row_pts) {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6, nt = blockDim.x;
-    int nf = min(max(n_faces[e], 0), cap);
-    int placed = 0;
-    float cx[REG ? kPlaceReg : 1][kMaxDof];
-    float ax[REG ? kPlaceReg : 1][kMaxDof];
-    unsigned long long key[REG ? kPlaceReg : 1];
-    bool al[REG ? kPlaceReg : 1];
-    // smallest (t*, index) key among this thread's alive candidates; after a
-    // plane is placed the discard pass and the next round's scan are one pass
-    unsigned long long best = ~0ull;
-    if constexpr (REG) {
-#pragma unroll
-        for (int q = 0; q < kPlaceReg; ++q) {
-            const int j = tid + q * nt;
-            al[q] = j < n;
-            key[q] = ~0ull;
-            if (al[q]) {
-                key[q] = ((unsigned long long)__float_as_uint(ts[j]) << 32) | (unsigned)j;
-#pragma unroll
-                for (int k = 0; k < kMaxDof; ++k) {
-                    cx[q][k] = k < dof ? cs[(size_t)k * cand_cap + j] : 0.f;
-                    ax[q][k] = k < dof ? ad[(size_t)k * cand_cap + j] : 0.f;
-                }
-                best = key[q] < best ? key[q] : best;
-            }
-        }
-    } else {
-        for (int j = tid; j < n; j += nt) {
-            alive[j] = 1;
-            const unsigned long long kj = ((unsigned long long)__float_as_uint(ts[j]) << 32) | (unsigned)j;
-            best = kj < best ? kj : best;
-        }
-    }
-    if (tid == 0) *s_stop = 0;
-    for (int round = 0; round < n_f; ++round) {
-        for (int off = 32; off > 0; off >>= 1) {
-            const unsigned long long o = __shfl_xor(best, off);
-            best = o < best ? o : best;
-        }
-        if (lane == 0) wmin[w] = best;
-        __syncthreads();
-        best = ~0ull;
-        for (int k = 0; k < nw; ++k) best = wmin[k] < best ? wmin[k] : best;
-        if (best == ~0ull) break;                         // no candidate left (uniform)
-        const int jb = (int)(best & 0xffffffffull);
-        // the row is built by the thread that holds candidate jb (REG) or by
-        // thread 0 from global memory
-        const bool builder = REG ? (jb % nt == tid) : (tid == 0);
-        if (builder) {
-            const float tsb = __uint_as_float((unsigned)(best >> 32));
-            if (tsb <= t_col) {
-                *s_stop = 1;
-                status[e] = 2;                            // EZO_EDGE_IN_COLLISION
-            } else if (nf >= cap) {
-                *s_stop = 1;
-            } else {
-                float bj = 0.f, av1 = 0.f, av2 = 0.f;
-                const int qb = jb / nt;
-#pragma unroll
-                for (int k = 0; k < kMaxDof; ++k) {
-                    if (k >= dof) break;
-                    float a, c;
-                    if constexpr (REG) {
-                        a = ax[0][k];
-                        c = cx[0][k];
-#pragma unroll
-                        for (int q = 1; q < kPlaceReg; ++q)
-                            if (q == qb) {
-                                a = ax[q][k];
-                                c = cx[q][k];
-                            }
-                    } else {
-                        a = ad[(size_t)k * cand_cap + jb];
-                        c = cs[(size_t)k * cand_cap + jb];
-                    }
-                    row[k] = a;
-                    if (row_pts) row_pts[((size_t)e * cap + nf) * dof + k] = c;
-                    bj = fmaf(a, c, bj);
-                    av1 = fmaf(a, v[k], av1);
-                    av2 = fmaf(a, v[dof + k], av2);
-                }
-                const float r = fmaxf(av1, av2) - bj + step_back_max;
-                const float delta = r > 0.f ? step_back_max - r : step_back_max;
-                const float rhs = bj - delta;
-                row[kMaxDof] = rhs;
-                for (int k = 0; k < dof; ++k) A[((size_t)e * cap + nf) * dof + k] = row[k];
-                bvec[(size_t)e * cap + nf] = rhs;
-                if (placed_idx) placed_idx[(size_t)e * n_f + placed] = jb;
-            }
-        }
-        __syncthreads();
-        if (*s_stop) break;
-        ++nf;
-        ++placed;
-        const float rhs = row[kMaxDof];
-        best = ~0ull;
-        if constexpr (REG) {
-            float rw[kMaxDof];
-#pragma unroll
-            for (int k = 0; k < kMaxDof; ++k) rw[k] = row[k];
-#pragma unroll
-            for (int q = 0; q < kPlaceReg; ++q) {
-                if (!al[q]) continue;
-                float ac = 0.f;
-#pragma unroll
-                for (int k = 0; k < kMaxDof; ++k)
-                    if (k < dof) ac = fmaf(rw[k], cx[q][k], ac);
-                if (ac > rhs) al[q] = false;
-                else best = key[q] < best ? key[q] : best;
-            }
-        } else {
-            // four candidates per thread at a time: their c* and t* loads are
-            // issued together, then tested (the same dot products, in the
-            // same order, as one candidate at a time)
-            constexpr int U = 4;
-            float rw[kMaxDof];
-#pragma unroll
-            for (int k = 0; k < kMaxDof; ++k) rw[k] = row[k];
-            for (int j0 = tid; j0 < n; j0 += U * nt) {
-                float cu[U][kMaxDof], tu[U];
-                bool live[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int j = j0 + u * nt;
-                    live[u] = j < n && alive[j];
-#pragma unroll
-                    for (int k = 0; k < kMaxDof; ++k)
-                        cu[u][k] = (live[u] && k < dof) ? cs[(size_t)k * cand_cap + j] : 0.f;
-                    tu[u] = live[u] ? ts[j] : 0.f;
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (!live[u]) continue;
-                    const int j = j0 + u * nt;
-                    float ac = 0.f;
-#pragma unroll
-                    for (int k = 0; k < kMaxDof; ++k)
-                        if (k < dof) ac = fmaf(rw[k], cu[u][k], ac);
-                    if (ac > rhs) {
-                        alive[j] = 0;
-                    } else {
-                        const unsigned long long kj = ((unsigned long long)__float_as_uint(tu[u]) << 32) | (unsigned)j;
-                        best = kj < best ? kj : best;
-                    }
-                }
-            }
-        }
-    }
-    if (tid == 0) {
-        n_faces[e] = nf;
-        if (n_placed) n_placed[e] = placed;
-        if (stats) stats[e].planes += placed;
-    }
+struct PlaceSlot {                 // a wave's smallest candidate of one round
+    float a[kMaxDof], c[kMaxDof];  // zero past dof
+};
+
+// Upper bound of k_place's static LDS; the rest of the workgroup's LDS holds
+// the tail's alive flags (one byte per candidate).
+constexpr size_t kPlaceStaticLds = 8192;
+static_assert(2 * kPlaceWaves * (sizeof(PlaceSlot) + 8) + kPlaceHist * (2 * kMaxDof + 2) * 4 + 256 <= kPlaceStaticLds,
+              "k_place static LDS");
+
+// Smallest value over the wave: DPP quad permutations (lane distance 1, 2),
+// the half-row and row mirrors (every lane of a 16-lane row ends with the
+// row's minimum), then the four rows' minima by readlane.  Every lane active.
+__device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
+    v = min(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true));   // quad_perm [1,0,3,2]
+    v = min(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true));   // quad_perm [2,3,0,1]
+    v = min(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true));  // row_half_mirror
+    v = min(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, true));  // row_mirror
+    const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+    const unsigned r1 = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+    const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)v, 32);
+    const unsigned r3 = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+    return min(min(r0, r1), min(r2, r3));
+}
+
+__device__ __forceinline__ unsigned long long place_key(unsigned t_bits, int j) {
+    return ((unsigned long long)t_bits << 32) | (unsigned)j;
 }
 
 __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict__ edges, const float* __restrict__ c_star,
@@ -1000,10 +874,12 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
                                                 int* __restrict__ n_placed, const uint8_t* __restrict__ proj_any,
                                                 EdgeStatsDev* __restrict__ stats, float* __restrict__ row_pts) {
     extern __shared__ __align__(16) char smem[];
-    uint8_t* alive = reinterpret_cast<uint8_t*>(smem);                // [cand_cap]
-    __shared__ unsigned long long wmin[16];
-    __shared__ float row[kMaxDof + 1];
-    __shared__ int s_stop;
+    uint8_t* alive = reinterpret_cast<uint8_t*>(smem);                // [cand_cap]: tail candidates
+    __shared__ PlaceSlot slot[2][kPlaceWaves];
+    __shared__ unsigned long long skey[2][kPlaceWaves];   // the slots' keys (~0: none)
+    __shared__ float hist_a[kPlaceHist][kMaxDof], hist_c[kPlaceHist][kMaxDof], hist_b[kPlaceHist];
+    __shared__ int hist_j[kPlaceHist];
+    __shared__ float sv[2][kMaxDof];                      // the edge's ends, zero past dof
     const int e = blockIdx.x;
     if (status[e] >= 0) return;
     if (proj_any && proj_any[e]) {
@@ -1018,12 +894,171 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
     const float* cs = c_star + (size_t)e * dof * cand_cap;
     const float* ad = a_dir + (size_t)e * dof * cand_cap;
     const float* ts = t_star + (size_t)e * cand_cap;
-    if (n <= kPlaceReg * (int)blockDim.x)
-        place_rounds<true>(e, dof, v, cs, ad, ts, n, cand_cap, n_f, step_back_max, t_col, A, bvec, n_faces, cap,
-                           status, placed_idx, n_placed, stats, alive, wmin, row, &s_stop, row_pts);
-    else
-        place_rounds<false>(e, dof, v, cs, ad, ts, n, cand_cap, n_f, step_back_max, t_col, A, bvec, n_faces, cap,
-                            status, placed_idx, n_placed, stats, alive, wmin, row, &s_stop, row_pts);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nt = blockDim.x, nw = nt >> 6;
+    const int nreg = min(n, kPlaceReg * nt);
+    const int nf0 = min(max(n_faces[e], 0), cap);
+    if (tid < 2 * kMaxDof) {
+        const int end = tid / kMaxDof, k = tid % kMaxDof;
+        sv[end][k] = k < dof ? v[end * dof + k] : 0.f;
+    }
+    float cx[kPlaceReg][kMaxDof], ax[kPlaceReg][kMaxDof];
+    unsigned tk[kPlaceReg];
+    bool al[kPlaceReg];
+    // smallest (t*, index) key among this thread's alive candidates; after a
+    // row is chosen the discard pass and the next round's scan are one pass
+    unsigned long long best = ~0ull;
+#pragma unroll
+    for (int q = 0; q < kPlaceReg; ++q) {
+        const int j = tid + q * nt;
+        al[q] = j < nreg;
+        tk[q] = ~0u;
+        if (al[q]) {
+            tk[q] = __float_as_uint(ts[j]);
+#pragma unroll
+            for (int k = 0; k < kMaxDof; ++k) {
+                cx[q][k] = k < dof ? cs[(size_t)k * cand_cap + j] : 0.f;
+                ax[q][k] = k < dof ? ad[(size_t)k * cand_cap + j] : 0.f;
+            }
+            const unsigned long long kj = place_key(tk[q], j);
+            best = kj < best ? kj : best;
+        }
+    }
+    for (int j = nreg + tid; j < n; j += nt) {
+        alive[j] = 1;
+        const unsigned long long kj = place_key(__float_as_uint(ts[j]), j);
+        best = kj < best ? kj : best;
+    }
+    int nf = nf0, placed = 0;
+    for (int round = 0; round < n_f; ++round) {
+        PlaceSlot* ps = slot[round & 1];
+        unsigned long long* pk = skey[round & 1];
+        // the wave's smallest key; the one lane holding it publishes c* and a
+        const unsigned whi = wave_min_u32((unsigned)(best >> 32));
+        const unsigned wlo = wave_min_u32((unsigned)(best >> 32) == whi ? (unsigned)best : ~0u);
+        const unsigned long long wkey = place_key(whi, (int)wlo);
+        if (lane == 0) pk[w] = wkey;
+        if (wkey != ~0ull && best == wkey) {
+            const int j = (int)wlo;
+            if (j < nreg) {
+                const int qb = j / nt;                    // j = tid + qb blockDim
+#pragma unroll
+                for (int k = 0; k < kMaxDof; ++k) {
+                    float a = ax[0][k], c = cx[0][k];
+#pragma unroll
+                    for (int q = 1; q < kPlaceReg; ++q)
+                        if (q == qb) {
+                            a = ax[q][k];
+                            c = cx[q][k];
+                        }
+                    ps[w].a[k] = a;
+                    ps[w].c[k] = c;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < kMaxDof; ++k) {
+                    ps[w].a[k] = k < dof ? ad[(size_t)k * cand_cap + j] : 0.f;
+                    ps[w].c[k] = k < dof ? cs[(size_t)k * cand_cap + j] : 0.f;
+                }
+            }
+        }
+        __syncthreads();
+        // the workgroup's smallest key (the same in every thread) and its slot
+        const unsigned long long kl = lane < nw ? pk[lane] : ~0ull;
+        const unsigned bhi = wave_min_u32((unsigned)(kl >> 32));
+        const unsigned blo = wave_min_u32((unsigned)(kl >> 32) == bhi ? (unsigned)kl : ~0u);
+        const unsigned long long bk = place_key(bhi, (int)blo);
+        if (bk == ~0ull) break;                           // no candidate left
+        const int bw = __builtin_ctzll(__ballot(kl == bk));
+        const int jb = (int)(unsigned)bk;
+        if (__uint_as_float((unsigned)(bk >> 32)) <= t_col) {
+            if (tid == 0) status[e] = 2;                  // EZO_EDGE_IN_COLLISION
+            break;
+        }
+        if (nf >= cap) break;
+        // the row a^T q <= b of candidate jb, with the relaxed step back.  The
+        // sums run over all kMaxDof entries: the zero entries past dof add
+        // +0, which can only turn a -0 sum into +0, and every sum below is
+        // compared with or offset by a nonzero value, so the row, its bound
+        // and every discard decision are those of the sums over dof entries.
+        float rw[kMaxDof], rc[kMaxDof];
+#pragma unroll
+        for (int k = 0; k < kMaxDof; ++k) {
+            rw[k] = ps[bw].a[k];
+            rc[k] = ps[bw].c[k];
+        }
+        float bj = 0.f, av1 = 0.f, av2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < kMaxDof; ++k) {
+            bj = fmaf(rw[k], rc[k], bj);
+            av1 = fmaf(rw[k], sv[0][k], av1);
+            av2 = fmaf(rw[k], sv[1][k], av2);
+        }
+        const float r = fmaxf(av1, av2) - bj + step_back_max;
+        const float delta = r > 0.f ? step_back_max - r : step_back_max;
+        const float rhs = bj - delta;
+        if (tid == 0) {
+            if (placed < kPlaceHist) {
+#pragma unroll
+                for (int k = 0; k < kMaxDof; ++k) {
+                    hist_a[placed][k] = rw[k];
+                    hist_c[placed][k] = rc[k];
+                }
+                hist_b[placed] = rhs;
+                hist_j[placed] = jb;
+            } else {
+                for (int k = 0; k < dof; ++k) {
+                    A[((size_t)e * cap + nf) * dof + k] = rw[k];
+                    if (row_pts) row_pts[((size_t)e * cap + nf) * dof + k] = rc[k];
+                }
+                bvec[(size_t)e * cap + nf] = rhs;
+                if (placed_idx) placed_idx[(size_t)e * n_f + placed] = jb;
+            }
+        }
+        ++nf;
+        ++placed;
+        best = ~0ull;
+#pragma unroll
+        for (int q = 0; q < kPlaceReg; ++q) {
+            if (!al[q]) continue;
+            float ac = 0.f;
+#pragma unroll
+            for (int k = 0; k < kMaxDof; ++k) ac = fmaf(rw[k], cx[q][k], ac);   // zero past dof
+            if (ac > rhs) {
+                al[q] = false;
+            } else {
+                const unsigned long long kj = place_key(tk[q], tid + q * nt);
+                best = kj < best ? kj : best;
+            }
+        }
+        for (int j = nreg + tid; j < n; j += nt) {
+            if (!alive[j]) continue;
+            float ac = 0.f;
+            for (int k = 0; k < dof; ++k) ac = fmaf(rw[k], cs[(size_t)k * cand_cap + j], ac);
+            if (ac > rhs) {
+                alive[j] = 0;
+            } else {
+                const unsigned long long kj = place_key(__float_as_uint(ts[j]), j);
+                best = kj < best ? kj : best;
+            }
+        }
+    }
+    __syncthreads();                                      // thread 0's rows in LDS
+    const int nh = min(placed, kPlaceHist);
+    for (int i = tid; i < nh * kMaxDof; i += nt) {
+        const int rr = i / kMaxDof, k = i % kMaxDof;
+        if (k >= dof) continue;
+        A[((size_t)e * cap + nf0 + rr) * dof + k] = hist_a[rr][k];
+        if (row_pts) row_pts[((size_t)e * cap + nf0 + rr) * dof + k] = hist_c[rr][k];
+    }
+    for (int rr = tid; rr < nh; rr += nt) {
+        bvec[(size_t)e * cap + nf0 + rr] = hist_b[rr];
+        if (placed_idx) placed_idx[(size_t)e * n_f + rr] = hist_j[rr];
+    }
+    if (tid == 0) {
+        n_faces[e] = nf;
+        if (n_placed) n_placed[e] = placed;
+        if (stats) stats[e].planes += placed;
+    }
 }
 
 // ---------------------------------------------------------------------------
