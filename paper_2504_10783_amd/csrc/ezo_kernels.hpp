@@ -822,17 +822,20 @@ __global__ void __launch_bounds__(1024) k_project_bisect(RobotView rg, ObsView o
 // up to n_f rounds of (argmin over the alive candidates by (t*, index), the
 // chosen candidate's row, discard of the candidates that row separates).
 //
-// Candidate j = tid + q blockDim with q < kPlaceReg keeps c*, a and t* in the
-// thread's registers; candidates past kPlaceReg blockDim (the tail) are read
-// from global memory in every round, their alive flags in LDS.  One barrier
-// per round: each wave takes its smallest (t*, index) key by DPP and readlane,
-// the lane holding that candidate publishes its c* and a in the wave's LDS
-// slot, and after the barrier every wave reduces the slots' keys the same way
-// (one slot per lane) and builds the row itself (the same FP32 operations on
-// the same values in every thread).  The chosen rows stay in LDS and are
-// written to global memory once, after the last round.
+// Candidate j = tid + q blockDim with q < NQ keeps c* and t* in the thread's
+// registers, and its direction a too when HOLD_A (NQ = kPlaceReg).  With more
+// candidates, NQ = 2 kPlaceReg holds c* only and a chosen candidate's a is
+// read from global memory (every candidate's a is loaded once at the start,
+// so those reads hit L2).  Candidates past NQ blockDim (the tail) are read
+// from global memory in every round, their alive flags in LDS.
+// One barrier per round: each wave takes its smallest (t*, index) key by DPP
+// and readlane, the lane holding that candidate publishes its c* and a in the
+// wave's LDS slot, and after the barrier every wave reduces the slots' keys
+// the same way (one slot per lane) and builds the row itself (the same FP32
+// operations on the same values in every thread).  The chosen rows stay in
+// LDS and are written to global memory once, after the last round.
 // ---------------------------------------------------------------------------
-constexpr int kPlaceReg = 4;       // candidates per thread held in registers
+constexpr int kPlaceReg = 4;       // candidates per thread held with their a
 constexpr int kPlaceHist = 64;     // chosen rows kept in LDS until the end
 constexpr int kPlaceWaves = 16;    // waves of the 1024-thread workgroup
 
@@ -840,11 +843,18 @@ struct PlaceSlot {                 // a wave's smallest candidate of one round
     float a[kMaxDof], c[kMaxDof];  // zero past dof
 };
 
+struct PlaceSmem {
+    PlaceSlot slot[2][kPlaceWaves];                 // by round parity
+    unsigned long long skey[2][kPlaceWaves];        // the slots' keys (~0: none)
+    float hist_a[kPlaceHist][kMaxDof], hist_c[kPlaceHist][kMaxDof], hist_b[kPlaceHist];
+    int hist_j[kPlaceHist];
+    float sv[2][kMaxDof];                           // the edge's ends, zero past dof
+};
+
 // Upper bound of k_place's static LDS; the rest of the workgroup's LDS holds
 // the tail's alive flags (one byte per candidate).
 constexpr size_t kPlaceStaticLds = 8192;
-static_assert(2 * kPlaceWaves * (sizeof(PlaceSlot) + 8) + kPlaceHist * (2 * kMaxDof + 2) * 4 + 256 <= kPlaceStaticLds,
-              "k_place static LDS");
+static_assert(sizeof(PlaceSmem) + 256 <= kPlaceStaticLds, "k_place static LDS");
 
 // Smallest value over the wave: DPP quad permutations (lane distance 1, 2),
 // the half-row and row mirrors (every lane of a 16-lane row ends with the
@@ -865,50 +875,26 @@ __device__ __forceinline__ unsigned long long place_key(unsigned t_bits, int j) 
     return ((unsigned long long)t_bits << 32) | (unsigned)j;
 }
 
-__global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict__ edges, const float* __restrict__ c_star,
-                                                const float* __restrict__ a_dir, const float* __restrict__ t_star,
-                                                const int* __restrict__ n_cands, int cand_cap, int n_f,
-                                                float step_back_max, float t_col, float* __restrict__ A,
-                                                float* __restrict__ bvec, int* __restrict__ n_faces, int cap,
-                                                int* __restrict__ status, int* __restrict__ placed_idx,
-                                                int* __restrict__ n_placed, const uint8_t* __restrict__ proj_any,
-                                                EdgeStatsDev* __restrict__ stats, float* __restrict__ row_pts) {
-    extern __shared__ __align__(16) char smem[];
-    uint8_t* alive = reinterpret_cast<uint8_t*>(smem);                // [cand_cap]: tail candidates
-    __shared__ PlaceSlot slot[2][kPlaceWaves];
-    __shared__ unsigned long long skey[2][kPlaceWaves];   // the slots' keys (~0: none)
-    __shared__ float hist_a[kPlaceHist][kMaxDof], hist_c[kPlaceHist][kMaxDof], hist_b[kPlaceHist];
-    __shared__ int hist_j[kPlaceHist];
-    __shared__ float sv[2][kMaxDof];                      // the edge's ends, zero past dof
-    const int e = blockIdx.x;
-    if (status[e] >= 0) return;
-    if (proj_any && proj_any[e]) {
-        if (threadIdx.x == 0) {
-            status[e] = 2;   // EZO_EDGE_IN_COLLISION
-            if (n_placed) n_placed[e] = 0;
-        }
-        return;
-    }
-    const int n = min(max(n_cands[e], 0), cand_cap);
-    const float* v = edges + (size_t)e * 2 * dof;
-    const float* cs = c_star + (size_t)e * dof * cand_cap;
-    const float* ad = a_dir + (size_t)e * dof * cand_cap;
-    const float* ts = t_star + (size_t)e * cand_cap;
+// The placement rounds of edge e (n > 0 candidates); returns the rows placed.
+template <int NQ, bool HOLD_A>
+__device__ __forceinline__ int place_edge(PlaceSmem& sm, uint8_t* alive, int e, int dof, int n, int nf0,
+                                          const float* __restrict__ cs, const float* __restrict__ ad,
+                                          const float* __restrict__ ts, int cand_cap, int n_f, float step_back_max,
+                                          float t_col, float* __restrict__ A, float* __restrict__ bvec, int cap,
+                                          int* __restrict__ status, int* __restrict__ placed_idx,
+                                          float* __restrict__ row_pts) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nt = blockDim.x, nw = nt >> 6;
-    const int nreg = min(n, kPlaceReg * nt);
-    const int nf0 = min(max(n_faces[e], 0), cap);
-    if (tid < 2 * kMaxDof) {
-        const int end = tid / kMaxDof, k = tid % kMaxDof;
-        sv[end][k] = k < dof ? v[end * dof + k] : 0.f;
-    }
-    float cx[kPlaceReg][kMaxDof], ax[kPlaceReg][kMaxDof];
-    unsigned tk[kPlaceReg];
-    bool al[kPlaceReg];
+    const int nreg = min(n, NQ * nt);
+    float cx[NQ][kMaxDof];
+    float ax[HOLD_A ? NQ : 1][kMaxDof];
+    unsigned tk[NQ];
+    bool al[NQ];
     // smallest (t*, index) key among this thread's alive candidates; after a
     // row is chosen the discard pass and the next round's scan are one pass
     unsigned long long best = ~0ull;
+    float touch = 0.f;
 #pragma unroll
-    for (int q = 0; q < kPlaceReg; ++q) {
+    for (int q = 0; q < NQ; ++q) {
         const int j = tid + q * nt;
         al[q] = j < nreg;
         tk[q] = ~0u;
@@ -917,12 +903,15 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
 #pragma unroll
             for (int k = 0; k < kMaxDof; ++k) {
                 cx[q][k] = k < dof ? cs[(size_t)k * cand_cap + j] : 0.f;
-                ax[q][k] = k < dof ? ad[(size_t)k * cand_cap + j] : 0.f;
+                const float a = k < dof ? ad[(size_t)k * cand_cap + j] : 0.f;
+                if constexpr (HOLD_A) ax[q][k] = a;
+                else touch += a;
             }
             const unsigned long long kj = place_key(tk[q], j);
             best = kj < best ? kj : best;
         }
     }
+    if constexpr (!HOLD_A) asm volatile("" : : "v"(touch));   // keeps the loads that bring a into L2
     for (int j = nreg + tid; j < n; j += nt) {
         alive[j] = 1;
         const unsigned long long kj = place_key(__float_as_uint(ts[j]), j);
@@ -930,8 +919,8 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
     }
     int nf = nf0, placed = 0;
     for (int round = 0; round < n_f; ++round) {
-        PlaceSlot* ps = slot[round & 1];
-        unsigned long long* pk = skey[round & 1];
+        PlaceSlot* ps = sm.slot[round & 1];
+        unsigned long long* pk = sm.skey[round & 1];
         // the wave's smallest key; the one lane holding it publishes c* and a
         const unsigned whi = wave_min_u32((unsigned)(best >> 32));
         const unsigned wlo = wave_min_u32((unsigned)(best >> 32) == whi ? (unsigned)best : ~0u);
@@ -943,15 +932,20 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
                 const int qb = j / nt;                    // j = tid + qb blockDim
 #pragma unroll
                 for (int k = 0; k < kMaxDof; ++k) {
-                    float a = ax[0][k], c = cx[0][k];
+                    float c = cx[0][k];
 #pragma unroll
-                    for (int q = 1; q < kPlaceReg; ++q)
-                        if (q == qb) {
-                            a = ax[q][k];
-                            c = cx[q][k];
-                        }
-                    ps[w].a[k] = a;
+                    for (int q = 1; q < NQ; ++q)
+                        if (q == qb) c = cx[q][k];
                     ps[w].c[k] = c;
+                    if constexpr (HOLD_A) {
+                        float a = ax[0][k];
+#pragma unroll
+                        for (int q = 1; q < NQ; ++q)
+                            if (q == qb) a = ax[q][k];
+                        ps[w].a[k] = a;
+                    } else {
+                        ps[w].a[k] = k < dof ? ad[(size_t)k * cand_cap + j] : 0.f;
+                    }
                 }
             } else {
 #pragma unroll
@@ -969,8 +963,8 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
         const unsigned long long bk = place_key(bhi, (int)blo);
         if (bk == ~0ull) break;                           // no candidate left
         const int bw = __builtin_ctzll(__ballot(kl == bk));
-        const int jb = (int)(unsigned)bk;
-        if (__uint_as_float((unsigned)(bk >> 32)) <= t_col) {
+        const int jb = (int)blo;
+        if (__uint_as_float(bhi) <= t_col) {
             if (tid == 0) status[e] = 2;                  // EZO_EDGE_IN_COLLISION
             break;
         }
@@ -990,8 +984,8 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
 #pragma unroll
         for (int k = 0; k < kMaxDof; ++k) {
             bj = fmaf(rw[k], rc[k], bj);
-            av1 = fmaf(rw[k], sv[0][k], av1);
-            av2 = fmaf(rw[k], sv[1][k], av2);
+            av1 = fmaf(rw[k], sm.sv[0][k], av1);
+            av2 = fmaf(rw[k], sm.sv[1][k], av2);
         }
         const float r = fmaxf(av1, av2) - bj + step_back_max;
         const float delta = r > 0.f ? step_back_max - r : step_back_max;
@@ -1000,11 +994,11 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
             if (placed < kPlaceHist) {
 #pragma unroll
                 for (int k = 0; k < kMaxDof; ++k) {
-                    hist_a[placed][k] = rw[k];
-                    hist_c[placed][k] = rc[k];
+                    sm.hist_a[placed][k] = rw[k];
+                    sm.hist_c[placed][k] = rc[k];
                 }
-                hist_b[placed] = rhs;
-                hist_j[placed] = jb;
+                sm.hist_b[placed] = rhs;
+                sm.hist_j[placed] = jb;
             } else {
                 for (int k = 0; k < dof; ++k) {
                     A[((size_t)e * cap + nf) * dof + k] = rw[k];
@@ -1018,7 +1012,7 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
         ++placed;
         best = ~0ull;
 #pragma unroll
-        for (int q = 0; q < kPlaceReg; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             if (!al[q]) continue;
             float ac = 0.f;
 #pragma unroll
@@ -1042,22 +1036,67 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
             }
         }
     }
+    return placed;
+}
+
+__global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict__ edges, const float* __restrict__ c_star,
+                                                const float* __restrict__ a_dir, const float* __restrict__ t_star,
+                                                const int* __restrict__ n_cands, int cand_cap, int n_f,
+                                                float step_back_max, float t_col, float* __restrict__ A,
+                                                float* __restrict__ bvec, int* __restrict__ n_faces, int cap,
+                                                int* __restrict__ status, int* __restrict__ placed_idx,
+                                                int* __restrict__ n_placed, const uint8_t* __restrict__ proj_any,
+                                                EdgeStatsDev* __restrict__ stats, float* __restrict__ row_pts) {
+    extern __shared__ __align__(16) char smem[];
+    uint8_t* alive = reinterpret_cast<uint8_t*>(smem);                // [cand_cap]: tail candidates
+    __shared__ PlaceSmem sm;
+    const int e = blockIdx.x;
+    // the edge's state, loaded together
+    const int st = status[e];
+    const int pany = proj_any ? proj_any[e] : 0;
+    const int nc = n_cands[e], nfa = n_faces[e];
+    if (st >= 0) return;
+    if (pany) {
+        if (threadIdx.x == 0) {
+            status[e] = 2;   // EZO_EDGE_IN_COLLISION
+            if (n_placed) n_placed[e] = 0;
+        }
+        return;
+    }
+    const int n = min(max(nc, 0), cand_cap);
+    const int nf0 = min(max(nfa, 0), cap);
+    const float* v = edges + (size_t)e * 2 * dof;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid < 2 * kMaxDof) {
+        const int end = tid / kMaxDof, k = tid % kMaxDof;
+        sm.sv[end][k] = k < dof ? v[end * dof + k] : 0.f;
+    }
+    const float* cs = c_star + (size_t)e * dof * cand_cap;
+    const float* ad = a_dir + (size_t)e * dof * cand_cap;
+    const float* ts = t_star + (size_t)e * cand_cap;
+    int placed;
+    if (n <= kPlaceReg * nt)
+        placed = place_edge<kPlaceReg, true>(sm, alive, e, dof, n, nf0, cs, ad, ts, cand_cap, n_f, step_back_max,
+                                             t_col, A, bvec, cap, status, placed_idx, row_pts);
+    else
+        placed = place_edge<2 * kPlaceReg, false>(sm, alive, e, dof, n, nf0, cs, ad, ts, cand_cap, n_f,
+                                                  step_back_max, t_col, A, bvec, cap, status, placed_idx, row_pts);
     __syncthreads();                                      // thread 0's rows in LDS
     const int nh = min(placed, kPlaceHist);
     for (int i = tid; i < nh * kMaxDof; i += nt) {
         const int rr = i / kMaxDof, k = i % kMaxDof;
         if (k >= dof) continue;
-        A[((size_t)e * cap + nf0 + rr) * dof + k] = hist_a[rr][k];
-        if (row_pts) row_pts[((size_t)e * cap + nf0 + rr) * dof + k] = hist_c[rr][k];
+        A[((size_t)e * cap + nf0 + rr) * dof + k] = sm.hist_a[rr][k];
+        if (row_pts) row_pts[((size_t)e * cap + nf0 + rr) * dof + k] = sm.hist_c[rr][k];
     }
     for (int rr = tid; rr < nh; rr += nt) {
-        bvec[(size_t)e * cap + nf0 + rr] = hist_b[rr];
-        if (placed_idx) placed_idx[(size_t)e * n_f + rr] = hist_j[rr];
+        bvec[(size_t)e * cap + nf0 + rr] = sm.hist_b[rr];
+        if (placed_idx) placed_idx[(size_t)e * n_f + rr] = sm.hist_j[rr];
     }
     if (tid == 0) {
-        n_faces[e] = nf;
+        n_faces[e] = nf0 + placed;
         if (n_placed) n_placed[e] = placed;
-        if (stats) stats[e].planes += placed;
+        if (stats) atomicAdd((unsigned long long*)&stats[e].planes, (unsigned long long)placed);
     }
 }
 
