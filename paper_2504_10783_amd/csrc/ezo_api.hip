@@ -514,7 +514,7 @@ ezo_status tune_check_inplace(ezo_ctx* c, const ezo_robot* r, const ObsView& ov,
     const auto cands = SD ? tile_candidates(c, r->slots, r->P, r->view.n_blocks, ov.n, true, {1, 2, 4, 8, 16}, n_t)
                           : tile_candidates(c, r->slots, r->P, r->view.n_blocks, ov.n, false, {1, 2, 4, 8}, n_t);
     if (cands.empty()) return EZO_OK;
-    IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
+    IterArgs it{nullptr, 0, 0, 0, 0};
     auto run = [&](const TileCfg& cfg) {
         return launch_check<SD>(c, r, ov, gv, q, n_t, sn, sd, 0, flags, min_sd, min_sd_self, 0, 1, nullptr, it, st,
                                 nullptr, 0.f, nullptr, &cfg);
@@ -581,12 +581,12 @@ ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, con
     hipLaunchKernelGGL(k_tune_polytope, dim3((E + 63) / 64), dim3(64), 0, st, dof, r->q_lo, r->q_hi, E, cap, F, A, b,
                        n_faces);
     HIP_TRY(c, hipGetLastError());
-    IterArgs its{nullptr, nullptr, 1, 0, 0, S_cap};
+    IterArgs its{nullptr, 1, 0, 0, S_cap};
     ezo_status s;
     if ((s = launch_sample(c, dof, A, b, n_faces, cap, edges, E, S_cap, p->n_mix, p->seed, p->edge_id_base, w_s,
                            stride, nullptr, its, st, nullptr, w_active)))
         return s;
-    IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
+    IterArgs it{nullptr, 0, 0, 0, 0};
     auto run_c = [&](const TileCfg& cfg) {
         return launch_check<false>(c, r, ov, gv, w_s, S_cap, 1, stride, (int64_t)dof * stride, w_f, nullptr, nullptr,
                                    stride, E, nullptr, it, st, nullptr, 0.f, nullptr, &cfg);
@@ -597,7 +597,7 @@ ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, con
     }
     if (!need_b) return EZO_OK;
     if ((s = run_c(heuristic_check(c, r, ov.n, (int64_t)S_cap * E, false)))) return s;
-    IterArgs sel{nullptr, nullptr, 0, S_cap, -1, S_cap};     // T = -1: never accept, always select
+    IterArgs sel{nullptr, 0, S_cap, -1, S_cap};     // T = -1: never accept, always select
     hipLaunchKernelGGL(k_test_select, dim3(E), dim3(1024), 0, st, w_f, stride, p->n_p, p->n_b, w_ci, cand_cap, w_nc,
                        nullptr, nullptr, nullptr, nullptr, sel);
     HIP_TRY(c, hipGetLastError());
@@ -972,7 +972,7 @@ ezo_status ezo_check_collisions(ezo_ctx* c, const ezo_robot* r, const float* obs
     GridView gv;
     ezo_status s = prep_obstacles(c, r, obs, n_obs, st, &ov, &gv);
     if (s) return s;
-    IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
+    IterArgs it{nullptr, 0, 0, 0, 0};
     if (min_sd || min_sd_self) {
         if ((s = tune_check_inplace<true>(c, r, ov, gv, q, n, stride_n, stride_d, flags, min_sd, min_sd_self, st)))
             return s;
@@ -1006,7 +1006,7 @@ ezo_status ezo_check_collisions_noalloc(ezo_ctx* c, const ezo_robot* r, const fl
     if (s) return s;
     // launch shapes: the tuning cache or the size heuristic (never a timing
     // search, which would write the outputs repeatedly)
-    IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
+    IterArgs it{nullptr, 0, 0, 0, 0};
     if (min_sd || min_sd_self)
         return launch_check<true>(c, r, ov, gv, q, n, stride_n, stride_d, 0, flags, min_sd, min_sd_self, 0, 1,
                                   nullptr, it, st);
@@ -1052,7 +1052,7 @@ ezo_status ezo_sample_polytopes(ezo_ctx* c, int32_t dof, const float* A, const f
     if (n_edges == 0 || n_samples == 0) return EZO_OK;
     if (!A || !b || !n_faces || !edges || !samples) return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
     HIP_TRY(c, hipSetDevice(c->device));
-    IterArgs it{nullptr, nullptr, iteration, 0, 0, n_samples};
+    IterArgs it{nullptr, iteration, 0, 0, n_samples};
     hipStream_t st = as_stream(stream);
     const TuneKey k = sample_key(c, dof, (int64_t)n_samples * n_edges);
     TileCfg g;
@@ -1080,7 +1080,7 @@ ezo_status ezo_test_and_select(ezo_ctx* c, const uint8_t* flags, int32_t n_edges
     if (n_edges == 0) return EZO_OK;
     if (!flags || !cand_idx || !n_cands) return ezo_fail(c, EZO_E_INVALID, "NULL buffer");
     HIP_TRY(c, hipSetDevice(c->device));
-    IterArgs it{nullptr, nullptr, 0, (int)M, (int)std::min<int64_t>(T, 0x7fffffff), n_samples};
+    IterArgs it{nullptr, 0, (int)M, (int)std::min<int64_t>(T, 0x7fffffff), n_samples};
     hipLaunchKernelGGL(k_test_select, dim3(n_edges), dim3(1024), 0, as_stream(stream), flags, sample_stride, n_p, 0,
                        cand_idx, cand_capacity, n_cands, accept, test_count, nullptr, nullptr, it);
     HIP_TRY(c, hipGetLastError());
@@ -1216,10 +1216,11 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         ezo_test_constants(p->eps, p->delta, p->tau, k, &M, &T);
         if (M > (1 << 28)) return ezo_fail(c, EZO_E_UNSUPPORTED, "M_%d = %lld samples is too many", k, (long long)M);
         const int nS = (int)std::max<int64_t>(p->n_p, M);
-        table[k] = make_int4((int)M, (int)std::min<int64_t>(T, 1 << 30), nS, 0);
+        table[k] = make_int4((int)M, (int)std::min<int64_t>(T, 1 << 30), nS, k);
         S_cap = std::max(S_cap, nS);
     }
     table[p->max_iters + 1] = table[p->max_iters];
+    table[p->max_iters + 1].w = p->max_iters + 1;
     HIP_TRY(c, hipSetDevice(c->device));
     const int E = n_edges;
     const int64_t stride = ((int64_t)S_cap + 63) / 64 * 64;
@@ -1235,7 +1236,7 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         (s = ezo_ws_get(c, W_TSTAR, sizeof(float) * (size_t)E * cand_cap, &w_ts)) ||
         (s = ezo_ws_get(c, W_PCOL, (size_t)E * cand_cap, &w_pc)) || (s = ezo_ws_get(c, W_PANY, (size_t)E, &w_pa)) ||
         (s = ezo_ws_get(c, W_STATS, sizeof(EdgeStatsDev) * (size_t)E, &w_st)) ||
-        (s = ezo_ws_get(c, W_TABLE, sizeof(int4) * table.size(), &w_tb)) || (s = ezo_ws_get(c, W_KDEV, sizeof(int), &w_k)) ||
+        (s = ezo_ws_get(c, W_TABLE, sizeof(int4) * table.size(), &w_tb)) || (s = ezo_ws_get(c, W_KDEV, sizeof(int4), &w_k)) ||
         (s = ezo_ws_get(c, W_ACTIVE, sizeof(int), &w_ac)))
         return s;
     if (p->surrogate) {
@@ -1293,9 +1294,10 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
     }
     c->bisect_finalists.clear();
     hipLaunchKernelGGL(k_init_edges, dim3((E + 63) / 64), dim3(64), 0, st, dof, r->q_lo, r->q_hi, edges, E, A, b,
-                       n_faces, cap, edge_status, (EdgeStatsDev*)w_st, (uint8_t*)w_pa, (int*)w_k, (int*)w_ac, skip);
+                       n_faces, cap, edge_status, (EdgeStatsDev*)w_st, (uint8_t*)w_pa, (int4*)w_k, (const int4*)w_tb,
+                       (int*)w_ac, skip);
     HIP_TRY(c, hipGetLastError());
-    IterArgs it{(const int*)w_k, (const int4*)w_tb, 0, 0, 0, 0};
+    IterArgs it{(const int4*)w_k, 0, 0, 0, 0};
     // the learned screen inside the loop: the fused forward pass for widths
     // up to kMlpMaxH (a multiple of 16), else the layer-by-layer kernels
     // (samples only)
@@ -1396,7 +1398,7 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
                            p->n_f, (float)p->step_back_max, (float)p->t_col, A, b, n_faces, cap, edge_status,
                            nullptr, nullptr, (const uint8_t*)w_pa, (EdgeStatsDev*)w_st, p->row_points);
         mark(EZO_PHASE_ADVANCE);
-        EZO_KLAUNCH(c, k_advance, dim3(1), dim3(256), 0, st, (int*)w_k, p->max_iters, edge_status, E, (int*)w_ac,
+        EZO_KLAUNCH(c, k_advance, dim3(1), dim3(256), 0, st, (int4*)w_k, (const int4*)w_tb, p->max_iters, edge_status, E, (int*)w_ac,
                     c->pinned_dev, (const EdgeStatsDev*)w_st, host_stats);
         mark(EZO_NUM_PHASES);
         if (ls == EZO_OK) {
@@ -1782,12 +1784,12 @@ ezo_status ezo_check_path(ezo_ctx* c, const ezo_robot* r, const float* obs, int3
     ObsView ov;
     GridView gv;
     if ((s = prep_obstacles(c, r, obs, n_obs, st, &ov, &gv))) return s;
-    IterArgs it{nullptr, nullptr, 0, 0, 0, 0};
+    IterArgs it{nullptr, 0, 0, 0, 0};
     if ((s = launch_check<false>(c, r, ov, gv, (const float*)wpts, N, dof, 1, 0, (uint8_t*)wflags, nullptr, nullptr,
                                  0, 1, nullptr, it, st)))
         return s;
     // colliding points in path order: the first point_capacity of them, and their count
-    IterArgs sel{nullptr, nullptr, 0, (int)std::min<int64_t>(N, 0x7fffffff), -1, (int)N};
+    IterArgs sel{nullptr, 0, (int)std::min<int64_t>(N, 0x7fffffff), -1, (int)N};
     int* cnt = (int*)wcnt;
     hipLaunchKernelGGL(k_test_select, dim3(1), dim3(1024), 0, st, (const uint8_t*)wflags, N,
                        std::max(point_capacity, 1), 0, (int*)widx, std::max(point_capacity, 1), cnt, nullptr, cnt + 1,
@@ -1838,7 +1840,7 @@ ezo_status ezo_update_polytopes(ezo_ctx* c, const ezo_robot* r, const float* obs
                        (float*)w_s);
     hipLaunchKernelGGL(k_points_in_sets, dim3((N + 255) / 256, E), dim3(256), 0, st, dof, A, b, n_faces,
                        face_capacity, edge_status, (const float*)w_s, (int64_t)N, (uint8_t*)w_f);
-    IterArgs sel{nullptr, nullptr, 0, 0, -1, N};
+    IterArgs sel{nullptr, 0, 0, -1, N};
     hipLaunchKernelGGL(k_test_select, dim3(E), dim3(1024), 0, st, (const uint8_t*)w_f, (int64_t)N, N, n_b,
                        (int*)w_ci, N, (int*)w_nc, nullptr, nullptr, nullptr, nullptr, sel);
     hipLaunchKernelGGL(k_recover_begin, dim3((E + 255) / 256), dim3(256), 0, st, E, (const int*)w_nc, (int*)w_run,

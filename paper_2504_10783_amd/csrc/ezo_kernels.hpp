@@ -11,11 +11,12 @@
 
 namespace ezo {
 
-// Per-iteration constants: either given directly, or looked up from
-// table[k] = (M_k, T_k, |S|_k, 0) with k = *k_dev.
+// Per-iteration constants: either given directly, or read from the loop's
+// current row *cur = table[k] = (M_k, T_k, |S|_k, k), which k_init_edges sets
+// to table[1] and k_advance moves to the next row (one load per kernel, issued
+// with the edge's status).
 struct IterArgs {
-    const int* k_dev;     // NULL => use k, M, T, nS below
-    const int4* table;    // [max_iters + 1]
+    const int4* cur;      // NULL => use k, M, T, nS below
     int k, M, T, nS;
 };
 
@@ -23,10 +24,9 @@ struct IterVals { int k, M, T, nS; };
 
 __device__ __forceinline__ IterVals resolve(const IterArgs& a) {
     IterVals v;
-    if (a.k_dev) {
-        v.k = *a.k_dev;
-        const int4 e = a.table[v.k];
-        v.M = e.x; v.T = e.y; v.nS = e.z;
+    if (a.cur) {
+        const int4 e = *a.cur;
+        v.k = e.w; v.M = e.x; v.T = e.y; v.nS = e.z;
     } else {
         v.k = a.k; v.M = a.M; v.T = a.T; v.nS = a.nS;
     }
@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(256) k_grid_scatter(const float4* __restrict__
 // ---------------------------------------------------------------------------
 // Batched collision check.  blockIdx.y = batch b (an edge in the fused loop),
 // blockIdx.x = tile.  q_b = q + b * q_batch; flags_b = flags + b * out_batch.
-// n = iteration's |S| when it.k_dev is set, else n_arg.
+// n = iteration's |S| when it.cur is set, else n_arg.
 // ---------------------------------------------------------------------------
 template <int T, bool SD, bool BOX>
 __global__ void __launch_bounds__(1024) k_check(RobotView rb, ObsView ob, GridView gv, const float* __restrict__ q, int64_t n_arg,
@@ -164,10 +164,10 @@ __global__ void __launch_bounds__(1024) k_check(RobotView rb, ObsView ob, GridVi
                                                 EdgeStatsDev* __restrict__ stats) {
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.y;
+    const IterVals iv = resolve(it);
     if (!edge_running(status, b)) return;
     int64_t n = n_arg, screen_from = n_arg;
-    if (it.k_dev) {
-        const IterVals iv = resolve(it);
+    if (it.cur) {
         n = iv.nS;
         screen_from = iv.M;               // the unadaptive test's samples are never screened
     }
@@ -494,8 +494,8 @@ __global__ void __launch_bounds__(256) k_sample(int dof, const float* __restrict
                                                 int64_t edge_id_base, int n_mix, float* __restrict__ S,
                                                 int64_t stride, const int* __restrict__ status, IterArgs it) {
     extern __shared__ __align__(16) char smem[];
-    if (!edge_running(status, blockIdx.y)) return;
     const IterVals iv = resolve(it);
+    if (!edge_running(status, blockIdx.y)) return;
     sample_block<D, L>(smem, dof, A, bvec, n_faces, cap, edges, key0, key1, edge_id_base, n_mix, S, stride, iv);
 }
 
@@ -515,8 +515,8 @@ __global__ void __launch_bounds__(256) k_sample_auto(int dof, const float* __res
                                                      const int* __restrict__ active, int64_t walks16, int64_t walks4,
                                                      const int* __restrict__ edge_ids) {
     extern __shared__ __align__(16) char smem[];
-    if (!edge_running(status, blockIdx.y)) return;
     const IterVals iv = resolve(it);
+    if (!edge_running(status, blockIdx.y)) return;
     const int64_t walks = (int64_t)max(*active, 1) * iv.nS;
     const int64_t wg_first = (int64_t)blockIdx.x * blockDim.x;     // first thread of this workgroup
     if (walks <= walks16) {
@@ -552,8 +552,8 @@ __global__ void __launch_bounds__(256) k_screen_samples(MlpView mv, const float*
     __shared__ float q[kScreenRows * kMaxDof];
     __shared__ float y[kScreenRows];
     const int e = blockIdx.y;
-    if (!edge_running(status, e)) return;
     const IterVals iv = resolve(it);
+    if (!edge_running(status, e)) return;
     const int64_t r0 = (int64_t)blockIdx.x * kScreenRows;
     if (r0 + kScreenRows <= iv.M || r0 >= iv.nS) return;
     const int nr = (int)min<int64_t>(kScreenRows, iv.nS - r0);
@@ -564,6 +564,18 @@ __global__ void __launch_bounds__(256) k_screen_samples(MlpView mv, const float*
     }
     mlp_forward_tile<kScreenRows / 16, 4>(mv, q, kMaxDof, nr, h, y);
     if (threadIdx.x < (unsigned)nr) pred[(size_t)e * stride + r0 + threadIdx.x] = y[threadIdx.x];
+}
+
+// Sum over the wave: DPP quad permutations (lane distance 1, 2), the half-row
+// and row mirrors (every lane of a 16-lane row ends with the row's sum), then
+// the four rows' sums by readlane.  Every lane active.
+__device__ __forceinline__ int wave_sum_i32(int v) {
+    v += __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);    // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);    // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);   // row_half_mirror
+    v += __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true);   // row_mirror
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) + __builtin_amdgcn_readlane(v, 32) +
+           __builtin_amdgcn_readlane(v, 48);
 }
 
 // ---------------------------------------------------------------------------
@@ -580,11 +592,11 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
     __shared__ int wsum[16];
     __shared__ int s_base;
     const int e = blockIdx.x;
+    const IterVals iv = resolve(it);
     if (!edge_running(status, e)) {
         if (threadIdx.x == 0 && n_cands) n_cands[e] = 0;
         return;
     }
-    const IterVals iv = resolve(it);
     const uint8_t* fe = flags + (size_t)e * stride;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
     // count over the first M samples (four consecutive flags per thread)
@@ -593,11 +605,12 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
     for (int i0 = 4 * tid; i0 < iv.M; i0 += nt4)
 #pragma unroll
         for (int q = 0; q < 4; ++q) cnt += (i0 + q < iv.M && fe[i0 + q]) ? 1 : 0;
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    cnt = wave_sum_i32(cnt);
     if (lane == 0) wsum[w] = cnt;
     __syncthreads();
     int total = 0;
-    for (int k = 0; k < nw; ++k) total += wsum[k];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) total += k < nw ? wsum[k] : 0;
     const bool accept = total <= iv.T;
     __syncthreads();
     int taken = 0;
@@ -620,10 +633,13 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
             const int before = __popcll(b0 & lt) + 2 * __popcll(b1 & lt) + 4 * __popcll(b2 & lt);
             if (lane == 0) wsum[w] = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
             __syncthreads();
-            int off = s_base;
-            for (int k = 0; k < w; ++k) off += wsum[k];
-            int chunk = 0;
-            for (int k = 0; k < nw; ++k) chunk += wsum[k];
+            int off = s_base, chunk = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int c = k < nw ? wsum[k] : 0;
+                chunk += c;
+                off += k < w ? c : 0;
+            }
             int pos = off + before;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
@@ -647,8 +663,8 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
             s.iterations = iv.k;
             s.final_m = iv.M;
             s.test_collisions = total;
-            s.samples += iv.nS;
-            s.exact_checks += (long long)iv.nS + (long long)taken * (1 + n_b);
+            atomicAdd((unsigned long long*)&s.samples, (unsigned long long)iv.nS);
+            atomicAdd((unsigned long long*)&s.exact_checks, (unsigned long long)iv.nS + (unsigned long long)taken * (1 + n_b));
         }
         if (status && accept) status[e] = 0;   // EZO_EDGE_CERTIFIED
     }
@@ -1128,15 +1144,17 @@ __global__ void k_cap_counts(const int* __restrict__ in, int* __restrict__ out, 
 }
 
 // Per edge: P = D (box rows), status RUNNING or INVALID, stats cleared; and
-// the loop's iteration counter k = 1 and running-edge count = n_edges.
+// the loop's current row *cur = table[1] (iteration 1) and running-edge
+// count = n_edges.
 __global__ void k_init_edges(int dof, const float* __restrict__ q_lo, const float* __restrict__ q_hi,
                              const float* __restrict__ edges, int n_edges, float* __restrict__ A,
                              float* __restrict__ bvec, int* __restrict__ n_faces, int cap, int* __restrict__ status,
                              EdgeStatsDev* __restrict__ stats, uint8_t* __restrict__ proj_any,
-                             int* __restrict__ k_dev, int* __restrict__ active, const uint8_t* __restrict__ skip) {
+                             int4* __restrict__ cur, const int4* __restrict__ table, int* __restrict__ active,
+                             const uint8_t* __restrict__ skip) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e == 0) {
-        *k_dev = 1;
+        *cur = table[1];
         *active = n_edges;
     }
     if (e >= n_edges) return;
@@ -1173,8 +1191,10 @@ __global__ void k_init_edges(int dof, const float* __restrict__ q_lo, const floa
 }
 
 // End of an iteration: at k == max_iters every running edge becomes
-// MAX_ITERS (1); count running edges; k <- k + 1.  One workgroup.
-__global__ void __launch_bounds__(256) k_advance(int* __restrict__ k_dev, int max_iters, int* __restrict__ status,
+// MAX_ITERS (1); count running edges; the current row moves to table[k + 1]
+// (table[max_iters + 1] at most).  One workgroup.
+__global__ void __launch_bounds__(256) k_advance(int4* __restrict__ cur, const int4* __restrict__ table, int max_iters,
+                                                 int* __restrict__ status,
                                                  int n_edges, int* __restrict__ active_count,
                                                  int* __restrict__ host_active,
                                                  const EdgeStatsDev* __restrict__ stats,
@@ -1185,7 +1205,7 @@ __global__ void __launch_bounds__(256) k_advance(int* __restrict__ k_dev, int ma
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
-    const int k = *k_dev;
+    const int k = cur->w;
     int local = 0;
     for (int e = threadIdx.x; e < n_edges; e += blockDim.x) {
         if (status[e] < 0) {
@@ -1197,7 +1217,7 @@ __global__ void __launch_bounds__(256) k_advance(int* __restrict__ k_dev, int ma
     __syncthreads();
     if (threadIdx.x == 0) {
         *active_count = cnt;
-        *k_dev = k + 1;
+        *cur = table[min(k + 1, max_iters + 1)];
         if (host_active) *host_active = cnt;
     }
 }
