@@ -180,11 +180,26 @@ def synthetic_candidates(rng, dof, n):
     return (v1.astype(f), v2.astype(f), np.array(cs, f), np.array(ad, f), np.array(ts, f))
 
 
-@pytest.mark.parametrize("dof,n,n_f", [(3, 50, 10), (7, 2000, 10), (7, 10000, 20), (2, 1, 10)])
-def test_place_parity(ezo, ctx, dof, n, n_f):
-    print_case("place", dof, n, n_f)
-    rng = np.random.default_rng(dof * 1000 + n)
-    v1, v2, cs, ad, ts = synthetic_candidates(rng, dof, n)
+def sphere_candidates(rng, dof, n):
+    """Collision points on the unit sphere around a short segment, all at
+    nearly the same distance t*: each placed row separates only a small cap
+    of them, so many rows are placed."""
+    v1, v2 = np.zeros(dof), np.zeros(dof)
+    v2[0] = 1e-3
+    cs, ad, ts = [], [], []
+    for _ in range(n):
+        u = rng.normal(size=dof)
+        x = 0.5 * (v1 + v2) + u / np.linalg.norm(u)
+        cp, _ = oracle.project(v1, v2, x)
+        cs.append(cp + rng.uniform(0.9, 1.0) * (x - cp))
+        ad.append((x - cp) / np.linalg.norm(x - cp))
+        ts.append(np.linalg.norm(cs[-1] - cp))
+    f = np.float32
+    return (v1.astype(f), v2.astype(f), np.array(cs, f), np.array(ad, f), np.array(ts, f))
+
+
+def place_parity(ezo, ctx, dof, n_f, v1, v2, cs, ad, ts):
+    n = len(ts)
     E, capc, capf = 1, n + 7, 2 * dof + n_f
     edges = torch.from_numpy(np.stack([v1, v2])[None]).cuda()
     cst = torch.zeros((E, dof, capc), dtype=torch.float32, device="cuda")
@@ -210,6 +225,25 @@ def test_place_parity(ezo, ctx, dof, n, n_f):
     assert np.array_equal(placed[0, :k].cpu().numpy(), idx)
     assert np.abs(A[0, 2 * dof:2 * dof + k].cpu().numpy() - Ao).max() <= 1e-6
     assert np.abs(b[0, 2 * dof:2 * dof + k].cpu().numpy() - bo).max() <= 1e-5
+    return k
+
+
+@pytest.mark.parametrize("dof,n,n_f", [(3, 50, 10), (7, 2000, 10), (7, 6000, 10), (7, 10000, 20), (2, 1, 10)])
+def test_place_parity(ezo, ctx, dof, n, n_f):
+    """Up to 4096 candidates are held with their directions in registers, up
+    to 8192 without them, the rest re-read from memory every round."""
+    print_case("place", dof, n, n_f)
+    rng = np.random.default_rng(dof * 1000 + n)
+    place_parity(ezo, ctx, dof, n_f, *synthetic_candidates(rng, dof, n))
+
+
+@pytest.mark.parametrize("dof,n,n_f", [(3, 5000, 100), (4, 6000, 100)])
+def test_place_many_rows_parity(ezo, ctx, dof, n, n_f):
+    """More rows in one call than the kernel keeps in LDS until its end (64):
+    the later rows are written as they are placed."""
+    print_case("place many rows", dof, n, n_f)
+    rng = np.random.default_rng(dof * 77 + n)
+    assert place_parity(ezo, ctx, dof, n_f, *sphere_candidates(rng, dof, n)) > 64
 
 
 def test_place_t_col_aborts_edge(ezo, ctx):
