@@ -302,6 +302,14 @@ __device__ __forceinline__ float draw_direction(int dof, uint32_t ii, uint32_t e
     return u01(word_of(rt, tword & 3));
 }
 
+// The chord's ends are reduced with IEEE 754-2019 minimum / maximum
+// (v_minimum3_f32 / v_maximum3_f32): a total order on the non-NaN values
+// they see (-0 below +0), so a group's result does not depend on how its rows
+// are split over lanes or on the order of the reduction, and, unlike fminf /
+// fmaxf, the operands need no canonicalising instruction each.
+__device__ __forceinline__ float tmin(float a, float b) { return __builtin_elementwise_minimum(a, b); }
+__device__ __forceinline__ float tmax(float a, float b) { return __builtin_elementwise_maximum(a, b); }
+
 // min / max over the L lanes of a group (groups aligned to L lanes): DPP
 // quad permutations for lane distances 1 and 2, the half-row mirror (lane i
 // with 7 - i) to join the two quads of an 8-lane group, the row mirror (lane
@@ -320,20 +328,20 @@ __device__ __forceinline__ void group_minmax(float& lo_max, float& hi_min) {
         return __builtin_bit_cast(float, r);
     };
     if constexpr (L >= 2) {
-        hi_min = fminf(hi_min, dpp(hi_min, 0));
-        lo_max = fmaxf(lo_max, dpp(lo_max, 0));
+        hi_min = tmin(hi_min, dpp(hi_min, 0));
+        lo_max = tmax(lo_max, dpp(lo_max, 0));
     }
     if constexpr (L >= 4) {
-        hi_min = fminf(hi_min, dpp(hi_min, 1));
-        lo_max = fmaxf(lo_max, dpp(lo_max, 1));
+        hi_min = tmin(hi_min, dpp(hi_min, 1));
+        lo_max = tmax(lo_max, dpp(lo_max, 1));
     }
     if constexpr (L >= 8) {
-        hi_min = fminf(hi_min, dpp(hi_min, 2));
-        lo_max = fmaxf(lo_max, dpp(lo_max, 2));
+        hi_min = tmin(hi_min, dpp(hi_min, 2));
+        lo_max = tmax(lo_max, dpp(lo_max, 2));
     }
     if constexpr (L >= 16) {
-        hi_min = fminf(hi_min, dpp(hi_min, 3));
-        lo_max = fmaxf(lo_max, dpp(lo_max, 3));
+        hi_min = tmin(hi_min, dpp(hi_min, 3));
+        lo_max = tmax(lo_max, dpp(lo_max, 3));
     }
 }
 
@@ -366,11 +374,11 @@ __device__ __forceinline__ void walk_step(const float* rowA, const float* rowb, 
             const float th = (rowb[j] - xj) * r;              // row +e_j <= hi_j
             const float tl = (rowb[nbox + j] - (-xj)) * rn;   // row -e_j <= -lo_j
             if (uj > 0.f) {
-                thi = fminf(thi, th);
-                tlo = fmaxf(tlo, tl);
+                thi = tmin(thi, th);
+                tlo = tmax(tlo, tl);
             } else if (uj < 0.f) {
-                tlo = fmaxf(tlo, th);
-                thi = fminf(thi, tl);
+                tlo = tmax(tlo, th);
+                thi = tmin(thi, tl);
             }
         }
     }
@@ -383,8 +391,8 @@ __device__ __forceinline__ void walk_step(const float* rowA, const float* rowb, 
             ax = fmaf(a, x[j], ax);
         }
         const float tt = (rowb[f] - ax) * __builtin_amdgcn_rcpf(den);
-        if (den > 0.f) thi = fminf(thi, tt);
-        else if (den < 0.f) tlo = fmaxf(tlo, tt);
+        if (den > 0.f) thi = tmin(thi, tt);
+        else if (den < 0.f) tlo = tmax(tlo, tt);
     }
     group_minmax<L>(tlo, thi);
     float tm = 0.f;
