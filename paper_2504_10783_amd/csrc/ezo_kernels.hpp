@@ -373,13 +373,10 @@ __device__ __forceinline__ void walk_step(const float* rowA, const float* rowb, 
             const float r = __builtin_amdgcn_rcpf(uj), rn = __builtin_amdgcn_rcpf(-uj);
             const float th = (rowb[j] - xj) * r;              // row +e_j <= hi_j
             const float tl = (rowb[nbox + j] - (-xj)) * rn;   // row -e_j <= -lo_j
-            if (uj > 0.f) {
-                thi = tmin(thi, th);
-                tlo = tmax(tlo, tl);
-            } else if (uj < 0.f) {
-                tlo = tmax(tlo, th);
-                thi = tmin(thi, tl);
-            }
+            // branch-free: a row that does not bound this side offers +-inf
+            const bool pos = uj > 0.f, neg = uj < 0.f;
+            thi = tmin(thi, pos ? th : (neg ? tl : INFINITY));
+            tlo = tmax(tlo, pos ? tl : (neg ? th : -INFINITY));
         }
     }
     for (int f = 2 * nbox + sub; f < F; f += L) {
@@ -391,8 +388,8 @@ __device__ __forceinline__ void walk_step(const float* rowA, const float* rowb, 
             ax = fmaf(a, x[j], ax);
         }
         const float tt = (rowb[f] - ax) * __builtin_amdgcn_rcpf(den);
-        if (den > 0.f) thi = tmin(thi, tt);
-        else if (den < 0.f) tlo = tmax(tlo, tt);
+        thi = tmin(thi, den > 0.f ? tt : INFINITY);     // branch-free, as above
+        tlo = tmax(tlo, den < 0.f ? tt : -INFINITY);
     }
     group_minmax<L>(tlo, thi);
     float tm = 0.f;
