@@ -23,6 +23,35 @@
 
 namespace ezo {
 
+// LDS (address space 3) views of generic pointers that point into the
+// workgroup's LDS.  Through a generic pointer -- one that may also point to
+// global memory, or any volatile access, which the compiler's address-space
+// inference leaves alone -- every access is a flat instruction followed by a
+// wait on both memory counters; through these it is a ds_* instruction.
+template <class T>
+using lds_ptr = __attribute__((address_space(3))) T*;
+template <class T>
+__device__ __forceinline__ lds_ptr<T> to_lds(T* p) { return (lds_ptr<T>)p; }
+
+// Element i of an LDS array of int4 / int2 / float4, read as the compiler's
+// native vectors (HIP's vector classes cannot be copied out of another
+// address space).
+typedef int lds_i4_t __attribute__((ext_vector_type(4)));
+typedef int lds_i2_t __attribute__((ext_vector_type(2)));
+typedef float lds_f4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int4 lds_load(lds_ptr<const int4> p, int i) {
+    const lds_i4_t v = ((lds_ptr<const lds_i4_t>)p)[i];
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ int2 lds_load(lds_ptr<const int2> p, int i) {
+    const lds_i2_t v = ((lds_ptr<const lds_i2_t>)p)[i];
+    return make_int2(v.x, v.y);
+}
+__device__ __forceinline__ float4 lds_load(lds_ptr<const float4> p, int i) {
+    const lds_f4_t v = ((lds_ptr<const lds_f4_t>)p)[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 constexpr int kMaxDof = 8;
 constexpr float kHuge = 3.0e38f;
 
@@ -51,6 +80,7 @@ struct RobotView {
     const float4* box;         // [B][4]
     const int* box_begin;      // [dof + 1] boxes of link i: [box_begin[i], box_begin[i+1])
     const int2* box_pairs;     // [Q] box self pairs (sorted indices)
+    int staged;                // set by stage_robot: bit 0 blocks, bit 1 pairs in LDS (else 0)
 };
 
 // LDS rows of a tile's pose array: one per sphere, four per box.
@@ -106,6 +136,7 @@ __device__ inline RobotView stage_robot(const RobotView& rb, char* base) {
     v.sph = sph;
     v.link_begin = lbeg;
     if (np > 0) v.pairs = prs;
+    v.staged = 1 | (np > 0 ? 2 : 0);
     return v;
 }
 
@@ -617,7 +648,7 @@ __device__ inline void tile_pairs_sd(const RobotView& rb, const ObsView& ob, con
 // prove apart cannot collide), then tested exactly.
 __device__ inline void tile_boxes_flags(const RobotView& rb, const ObsView& ob, const TileSmem& t, int T,
                                         int n_valid) {
-    volatile int* hit = t.hit;
+    const lds_ptr<volatile int> hit = to_lds((volatile int*)t.hit);
     const int S = rb.n_spheres, B = rb.n_boxes;
     const float4 shv = ob.centre[0];
     const float3 sh = make_float3(shv.x, shv.y, shv.z);
@@ -667,16 +698,98 @@ __device__ inline void tile_boxes_flags(const RobotView& rb, const ObsView& ob, 
     }
 }
 
+// Self-pair items of the work list (kItemLanes lanes each; blocks and pairs
+// from LDS when the robot tables are staged, else from global memory).
+template <class BlkF, class PairF>
+__device__ __forceinline__ void tile_self_items(BlkF block, PairF pair, const TileSmem& t, int T,
+                                                lds_ptr<volatile int> hit, unsigned& ntest) {
+    // 64 / kItemLanes work items per wave, kItemLanes lanes each (a part
+    // pair holds a fraction of its link pair's sphere pairs)
+    constexpr int IPW = 64 / kItemLanes;
+    const int n_items = *t.wl_n;
+    const int lane = threadIdx.x & 63, sub = lane / kItemLanes, li = lane % kItemLanes;
+    const int nw = blockDim.x >> 6;
+    for (int it0 = IPW * wave_id(); it0 < n_items; it0 += IPW * nw) {
+        const int it = it0 + sub;
+        if (it >= n_items) continue;
+        const int item = t.wl[it];
+        const int c = item & 63;
+        if (hit[c]) continue;                          // uniform in the lane group
+        const int4 blk = block(item >> 6);
+        bool found = false;
+        for (int p = li; p < blk.w; p += kItemLanes) {
+            const int2 pr = pair(blk.z + p);
+            const float4 a = t.cen[pr.x * T + c];
+            const float4 b = t.cen[pr.y * T + c];
+            const float ex = a.x - b.x, ey = a.y - b.y, ez = a.z - b.z;
+            const float Rr = a.w + b.w;
+            ++ntest;
+            found |= fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < Rr * Rr;
+        }
+        if (found) hit[c] = 1;
+    }
+}
+
+// Obstacle sweep: a (configuration, sphere) item tests the obstacles listed in
+// its grid cell (records from LDS when staged, else from global memory); the
+// four records of a list load are fetched together and tested branch-free.
+template <class RecF>
+__device__ __forceinline__ void tile_obstacle_items(RecF rec, const ObsView& ob, const GridView& gv, const TileSmem& t,
+                                                    int T, int n_valid, int S, lds_ptr<volatile int> hit,
+                                                    unsigned& ntest) {
+    const GridGeom g = *gv.geom;
+    const int G = gv.G;
+    for (ItemWalk w(n_valid); w.k < S; w.next(n_valid)) {
+        const int c = w.c, s = w.k;
+        if (hit[c]) continue;
+        const float4 C = t.cen[s * T + c];
+        const float fx = (C.x - g.ox) * g.ihx, fy = (C.y - g.oy) * g.ihy, fz = (C.z - g.oz) * g.ihz;
+        if (!(fx >= 0.f && fy >= 0.f && fz >= 0.f && fx < (float)G && fy < (float)G && fz < (float)G)) continue;
+        const int cx = min((int)fx, G - 1), cy = min((int)fy, G - 1), cz = min((int)fz, G - 1);
+        const int cell = (cz * G + cy) * G + cx;
+        const int cnt = gv.count[cell];
+        const bool full = cnt > gv.cap;
+        const int n = full ? ob.n : cnt;
+        // list entries four at a time (cell lists are 8-byte aligned)
+        const ushort4* lst4 = reinterpret_cast<const ushort4*>(gv.list + (size_t)cell * gv.cap);
+        bool found = false;
+        for (int k0 = 0; k0 < n && !found; k0 += 4) {
+            int oi[4];
+            if (full) {
+                oi[0] = k0; oi[1] = k0 + 1; oi[2] = k0 + 2; oi[3] = k0 + 3;
+            } else {
+                const ushort4 v = lst4[k0 >> 2];
+                oi[0] = v.x; oi[1] = v.y; oi[2] = v.z; oi[3] = v.w;
+            }
+            float4 O[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) O[e] = rec((k0 + e < n) ? oi[e] : oi[0]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool ok = k0 + e < n;
+                ntest += ok ? 1u : 0u;
+                const float ex = C.x - O[e].x, ey = C.y - O[e].y, ez = C.z - O[e].z;
+                const float Rr = C.w + O[e].w;
+                found |= ok && fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < Rr * Rr;
+            }
+        }
+        if (found) hit[c] = 1;
+    }
+}
+
 template <bool BOX>
 __device__ inline unsigned tile_pairs_grid(const RobotView& rb, const ObsView& ob, const GridView& gv,
                                            const TileSmem& t, int T, int n_valid) {
-    volatile int* hit = t.hit;
+    const lds_ptr<volatile int> hit = to_lds((volatile int*)t.hit);
     unsigned int ntest = 0;
     if (rb.n_blocks > 0) {
+        const bool lblk = (rb.staged & 1) != 0, lprs = (rb.staged & 2) != 0;
+        const lds_ptr<const int4> blocks_l = to_lds(rb.blocks);
+        const lds_ptr<const int2> pairs_l = to_lds(rb.pairs);
         for (ItemWalk w(n_valid); w.k < rb.n_blocks; w.next(n_valid)) {
             const int c = w.c, bk = w.k;
             if (hit[c] || t.scr[c]) continue;
-            const int4 blk = rb.blocks[bk];
+            const int4 blk = lblk ? lds_load(blocks_l, bk) : rb.blocks[bk];
             const float4 A = t.lb[blk.x * T + c], B = t.lb[blk.y * T + c];
             const float dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;
             const float R = A.w + B.w;
@@ -685,75 +798,20 @@ __device__ inline unsigned tile_pairs_grid(const RobotView& rb, const ObsView& o
                 t.wl[atomicAdd(t.wl_n, 1)] = (unsigned short)((bk << 6) | c);
         }
         __syncthreads();
-        // 64 / kItemLanes work items per wave, kItemLanes lanes each (a part
-        // pair holds a fraction of its link pair's sphere pairs)
-        constexpr int IPW = 64 / kItemLanes;
-        const int n_items = *t.wl_n;
-        const int lane = threadIdx.x & 63, sub = lane / kItemLanes, li = lane % kItemLanes;
-        const int nw = blockDim.x >> 6;
-        for (int it0 = IPW * wave_id(); it0 < n_items; it0 += IPW * nw) {
-            const int it = it0 + sub;
-            if (it >= n_items) continue;
-            const int item = t.wl[it];
-            const int c = item & 63;
-            if (hit[c]) continue;                          // uniform in the lane group
-            const int4 blk = rb.blocks[item >> 6];
-            bool found = false;
-            for (int p = li; p < blk.w; p += kItemLanes) {
-                const int2 pr = rb.pairs[blk.z + p];
-                const float4 a = t.cen[pr.x * T + c];
-                const float4 b = t.cen[pr.y * T + c];
-                const float ex = a.x - b.x, ey = a.y - b.y, ez = a.z - b.z;
-                const float Rr = a.w + b.w;
-                ++ntest;
-                found |= fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < Rr * Rr;
-            }
-            if (found) hit[c] = 1;
-        }
+        if (lblk && lprs)
+            tile_self_items([=](int i) { return lds_load(blocks_l, i); }, [=](int i) { return lds_load(pairs_l, i); },
+                            t, T, hit, ntest);
+        else
+            tile_self_items([=](int i) { return rb.blocks[i]; }, [=](int i) { return rb.pairs[i]; }, t, T, hit, ntest);
     }
     if (ob.n > 0) {
-        const GridGeom g = *gv.geom;
-        const int G = gv.G;
-        const int S = rb.n_spheres;
-        for (ItemWalk w(n_valid); w.k < S; w.next(n_valid)) {
-            const int c = w.c, s = w.k;
-            if (hit[c]) continue;
-            const float4 C = t.cen[s * T + c];
-            const float fx = (C.x - g.ox) * g.ihx, fy = (C.y - g.oy) * g.ihy, fz = (C.z - g.oz) * g.ihz;
-            if (!(fx >= 0.f && fy >= 0.f && fz >= 0.f && fx < (float)G && fy < (float)G && fz < (float)G)) continue;
-            const int cx = min((int)fx, G - 1), cy = min((int)fy, G - 1), cz = min((int)fz, G - 1);
-            const int cell = (cz * G + cy) * G + cx;
-            const int cnt = gv.count[cell];
-            const bool full = cnt > gv.cap;
-            const int n = full ? ob.n : cnt;
-            // list entries four at a time (cell lists are 8-byte aligned), the
-            // four record reads issued together
-            const ushort4* lst4 = reinterpret_cast<const ushort4*>(gv.list + (size_t)cell * gv.cap);
-            bool found = false;
-            for (int k0 = 0; k0 < n && !found; k0 += 4) {
-                int oi[4];
-                if (full) {
-                    oi[0] = k0; oi[1] = k0 + 1; oi[2] = k0 + 2; oi[3] = k0 + 3;
-                } else {
-                    const ushort4 v = lst4[k0 >> 2];
-                    oi[0] = v.x; oi[1] = v.y; oi[2] = v.z; oi[3] = v.w;
-                }
-                float4 O[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int o = (k0 + e < n) ? oi[e] : oi[0];
-                    O[e] = t.obs ? t.obs[o] : ob.rec[o];
-                }
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (k0 + e >= n) break;
-                    ++ntest;
-                    const float ex = C.x - O[e].x, ey = C.y - O[e].y, ez = C.z - O[e].z;
-                    const float Rr = C.w + O[e].w;
-                    if (fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < Rr * Rr) found = true;
-                }
-            }
-            if (found) hit[c] = 1;
+        if (t.obs) {
+            const lds_ptr<const float4> rl = to_lds((const float4*)t.obs);
+            tile_obstacle_items([=](int o) { return lds_load(rl, o); }, ob, gv, t, T, n_valid, rb.n_spheres, hit,
+                                ntest);
+        } else {
+            const float4* rg = ob.rec;
+            tile_obstacle_items([=](int o) { return rg[o]; }, ob, gv, t, T, n_valid, rb.n_spheres, hit, ntest);
         }
     }
     if (BOX && (rb.n_boxes > 0 || ob.n_ebox > 0)) tile_boxes_flags(rb, ob, t, T, n_valid);
