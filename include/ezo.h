@@ -426,7 +426,9 @@ enum {
     EZO_PHASE_TEST = 2,          /* unadaptive test + candidate selection     */
     EZO_PHASE_BISECT = 3,        /* projection, fail-fast check, bisection    */
     EZO_PHASE_PLACE = 4,         /* ordering and placing hyperplanes          */
-    EZO_PHASE_ADVANCE = 5,       /* iteration bookkeeping                     */
+    EZO_PHASE_ADVANCE = 5,       /* iteration bookkeeping (a call with one
+                                    edge does it inside the placement kernel:
+                                    0 ms)                                     */
     EZO_NUM_PHASES = 6
 };
 

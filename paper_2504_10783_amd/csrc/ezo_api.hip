@@ -1126,7 +1126,8 @@ ezo_status ezo_place_hyperplanes(ezo_ctx* c, int32_t dof, const float* edges, in
     HIP_TRY(c, hipSetDevice(c->device));
     hipLaunchKernelGGL(k_place, dim3(n_edges), dim3(1024), (size_t)std::max(cand_capacity, 16), as_stream(stream), dof,
                        edges, c_star, a_dir, t_star, n_cands, cand_capacity, n_f, (float)step_back_max, (float)t_col, A,
-                       b, n_faces, face_capacity, edge_status, placed_idx, n_placed, nullptr, nullptr, nullptr);
+                       b, n_faces, face_capacity, edge_status, placed_idx, n_placed, nullptr, nullptr, nullptr,
+                       IterEnd{});
     HIP_TRY(c, hipGetLastError());
     return EZO_OK;
 }
@@ -1393,13 +1394,19 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
             return ls;
         }
         mark(EZO_PHASE_PLACE);
+        // one edge: the placement's single workgroup ends the iteration itself
+        // (no k_advance launch; its phase then times nothing)
+        const IterEnd ie = E == 1 ? IterEnd{(int4*)w_k, (const int4*)w_tb, p->max_iters, (int*)w_ac, c->pinned_dev,
+                                            host_stats}
+                                  : IterEnd{};
         EZO_KLAUNCH(c, k_place, dim3(E), dim3(1024), (size_t)std::max(cand_cap, 16), st, dof, edges,
                            (const float*)w_cs, (const float*)w_ad, (const float*)w_ts, (const int*)w_nc, cand_cap,
                            p->n_f, (float)p->step_back_max, (float)p->t_col, A, b, n_faces, cap, edge_status,
-                           nullptr, nullptr, (const uint8_t*)w_pa, (EdgeStatsDev*)w_st, p->row_points);
+                           nullptr, nullptr, (const uint8_t*)w_pa, (EdgeStatsDev*)w_st, p->row_points, ie);
         mark(EZO_PHASE_ADVANCE);
-        EZO_KLAUNCH(c, k_advance, dim3(1), dim3(256), 0, st, (int4*)w_k, (const int4*)w_tb, p->max_iters, edge_status, E, (int*)w_ac,
-                    c->pinned_dev, (const EdgeStatsDev*)w_st, host_stats);
+        if (E != 1)
+            EZO_KLAUNCH(c, k_advance, dim3(1), dim3(256), 0, st, (int4*)w_k, (const int4*)w_tb, p->max_iters,
+                        edge_status, E, (int*)w_ac, c->pinned_dev, (const EdgeStatsDev*)w_st, host_stats);
         mark(EZO_NUM_PHASES);
         if (ls == EZO_OK) {
             hipError_t le = hipGetLastError();
@@ -1524,6 +1531,7 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         }
         if (c->timing) {
             for (int ph = 0; ph < EZO_NUM_PHASES; ++ph) {
+                if (ph == EZO_PHASE_ADVANCE && E == 1) continue;   // done inside the placement
                 float ms = 0.f;
                 if (hipEventElapsedTime(&ms, c->tev[2 * ph], c->tev[2 * ph + 1]) == hipSuccess)
                     c->phase_ms[ph] += ms;
@@ -1858,7 +1866,7 @@ ezo_status ezo_update_polytopes(ezo_ctx* c, const ezo_robot* r, const float* obs
     hipLaunchKernelGGL(k_place, dim3(E), dim3(1024), (size_t)std::max(N, 16), st, dof, edges, (const float*)w_cs,
                        (const float*)w_ad, (const float*)w_ts, (const int*)w_nc, N, n_f, (float)step_back_max,
                        (float)t_col, A, b, n_faces, face_capacity, (int*)w_run, nullptr, (int*)w_np,
-                       (const uint8_t*)w_pa, nullptr, nullptr);
+                       (const uint8_t*)w_pa, nullptr, nullptr, IterEnd{});
     hipLaunchKernelGGL(k_recover_end, dim3((E + 255) / 256), dim3(256), 0, st, E, (const int*)w_run,
                        (const int*)w_np, edge_status, planes_added);
     HIP_TRY(c, hipGetLastError());

@@ -1060,6 +1060,20 @@ __device__ __forceinline__ int place_edge(PlaceSmem& sm, uint8_t* alive, int e, 
     return placed;
 }
 
+// The end of a fused-loop iteration (the work of k_advance below) for a call
+// with one edge, done by k_place's single workgroup after its own writes:
+// at k == max_iters a running edge becomes MAX_ITERS (1); the running-edge
+// count; the current row moves to table[k + 1]; the edge's statistics and
+// the count for the host.  cur == NULL: k_advance does it.
+struct IterEnd {
+    int4* cur;
+    const int4* table;
+    int max_iters;
+    int* active_count;
+    int* host_active;                 // pinned, or NULL
+    EdgeStatsDev* host_stats;         // pinned, or NULL
+};
+
 __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict__ edges, const float* __restrict__ c_star,
                                                 const float* __restrict__ a_dir, const float* __restrict__ t_star,
                                                 const int* __restrict__ n_cands, int cand_cap, int n_f,
@@ -1067,57 +1081,76 @@ __global__ void __launch_bounds__(1024) k_place(int dof, const float* __restrict
                                                 float* __restrict__ bvec, int* __restrict__ n_faces, int cap,
                                                 int* __restrict__ status, int* __restrict__ placed_idx,
                                                 int* __restrict__ n_placed, const uint8_t* __restrict__ proj_any,
-                                                EdgeStatsDev* __restrict__ stats, float* __restrict__ row_pts) {
+                                                EdgeStatsDev* __restrict__ stats, float* __restrict__ row_pts,
+                                                IterEnd ie) {
     extern __shared__ __align__(16) char smem[];
     uint8_t* alive = reinterpret_cast<uint8_t*>(smem);                // [cand_cap]: tail candidates
     __shared__ PlaceSmem sm;
     const int e = blockIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
     // the edge's state, loaded together
     const int st = status[e];
     const int pany = proj_any ? proj_any[e] : 0;
     const int nc = n_cands[e], nfa = n_faces[e];
-    if (st >= 0) return;
-    if (pany) {
-        if (threadIdx.x == 0) {
+    int placed = 0;
+    if (st < 0 && pany) {
+        if (tid == 0) {
             status[e] = 2;   // EZO_EDGE_IN_COLLISION
             if (n_placed) n_placed[e] = 0;
         }
-        return;
+    } else if (st < 0) {
+        const int n = min(max(nc, 0), cand_cap);
+        const int nf0 = min(max(nfa, 0), cap);
+        const float* v = edges + (size_t)e * 2 * dof;
+        if (tid < 2 * kMaxDof) {
+            const int end = tid / kMaxDof, k = tid % kMaxDof;
+            sm.sv[end][k] = k < dof ? v[end * dof + k] : 0.f;
+        }
+        const float* cs = c_star + (size_t)e * dof * cand_cap;
+        const float* ad = a_dir + (size_t)e * dof * cand_cap;
+        const float* ts = t_star + (size_t)e * cand_cap;
+        if (n <= kPlaceReg * nt)
+            placed = place_edge<kPlaceReg, true>(sm, alive, e, dof, n, nf0, cs, ad, ts, cand_cap, n_f, step_back_max,
+                                                 t_col, A, bvec, cap, status, placed_idx, row_pts);
+        else
+            placed = place_edge<2 * kPlaceReg, false>(sm, alive, e, dof, n, nf0, cs, ad, ts, cand_cap, n_f,
+                                                      step_back_max, t_col, A, bvec, cap, status, placed_idx,
+                                                      row_pts);
+        __syncthreads();                                  // thread 0's rows in LDS
+        const int nh = min(placed, kPlaceHist);
+        for (int i = tid; i < nh * kMaxDof; i += nt) {
+            const int rr = i / kMaxDof, k = i % kMaxDof;
+            if (k >= dof) continue;
+            A[((size_t)e * cap + nf0 + rr) * dof + k] = sm.hist_a[rr][k];
+            if (row_pts) row_pts[((size_t)e * cap + nf0 + rr) * dof + k] = sm.hist_c[rr][k];
+        }
+        for (int rr = tid; rr < nh; rr += nt) {
+            bvec[(size_t)e * cap + nf0 + rr] = sm.hist_b[rr];
+            if (placed_idx) placed_idx[(size_t)e * n_f + rr] = sm.hist_j[rr];
+        }
+        if (tid == 0) {
+            n_faces[e] = nf0 + placed;
+            if (n_placed) n_placed[e] = placed;
+            if (stats && !ie.cur) atomicAdd((unsigned long long*)&stats[e].planes, (unsigned long long)placed);
+        }
     }
-    const int n = min(max(nc, 0), cand_cap);
-    const int nf0 = min(max(nfa, 0), cap);
-    const float* v = edges + (size_t)e * 2 * dof;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    if (tid < 2 * kMaxDof) {
-        const int end = tid / kMaxDof, k = tid % kMaxDof;
-        sm.sv[end][k] = k < dof ? v[end * dof + k] : 0.f;
-    }
-    const float* cs = c_star + (size_t)e * dof * cand_cap;
-    const float* ad = a_dir + (size_t)e * dof * cand_cap;
-    const float* ts = t_star + (size_t)e * cand_cap;
-    int placed;
-    if (n <= kPlaceReg * nt)
-        placed = place_edge<kPlaceReg, true>(sm, alive, e, dof, n, nf0, cs, ad, ts, cand_cap, n_f, step_back_max,
-                                             t_col, A, bvec, cap, status, placed_idx, row_pts);
-    else
-        placed = place_edge<2 * kPlaceReg, false>(sm, alive, e, dof, n, nf0, cs, ad, ts, cand_cap, n_f,
-                                                  step_back_max, t_col, A, bvec, cap, status, placed_idx, row_pts);
-    __syncthreads();                                      // thread 0's rows in LDS
-    const int nh = min(placed, kPlaceHist);
-    for (int i = tid; i < nh * kMaxDof; i += nt) {
-        const int rr = i / kMaxDof, k = i % kMaxDof;
-        if (k >= dof) continue;
-        A[((size_t)e * cap + nf0 + rr) * dof + k] = sm.hist_a[rr][k];
-        if (row_pts) row_pts[((size_t)e * cap + nf0 + rr) * dof + k] = sm.hist_c[rr][k];
-    }
-    for (int rr = tid; rr < nh; rr += nt) {
-        bvec[(size_t)e * cap + nf0 + rr] = sm.hist_b[rr];
-        if (placed_idx) placed_idx[(size_t)e * n_f + rr] = sm.hist_j[rr];
-    }
-    if (tid == 0) {
-        n_faces[e] = nf0 + placed;
-        if (n_placed) n_placed[e] = placed;
-        if (stats) atomicAdd((unsigned long long*)&stats[e].planes, (unsigned long long)placed);
+    if (ie.cur && tid == 0) {                 // one edge: every status write above was this thread's
+        EdgeStatsDev s{};
+        if (stats) {
+            s = stats[e];
+            s.planes += placed;
+            if (placed) stats[e] = s;
+        }
+        if (ie.host_stats) ie.host_stats[e] = s;
+        const int k = ie.cur->w;
+        int running = 0;
+        if (status[e] < 0) {
+            if (k >= ie.max_iters) status[e] = 1;   // EZO_EDGE_MAX_ITERS
+            else running = 1;
+        }
+        *ie.active_count = running;
+        *ie.cur = ie.table[min(k + 1, ie.max_iters + 1)];
+        if (ie.host_active) *ie.host_active = running;
     }
 }
 

@@ -252,7 +252,10 @@ def test_deterministic_repeat_and_timing_mode(ezo, ctx):
     for r in (r2, r3):
         assert r[2][0] == r1[2][0] and r[3][0] == r1[3][0]
         assert np.array_equal(r[0][0, :F], r1[0][0, :F]) and np.array_equal(r[1][0, :F], r1[1][0, :F])
-    assert iters == r1[4][0]["iterations"] and all(v > 0 for v in ms.values())
+    # one edge: the placement kernel ends each iteration itself, so the
+    # bookkeeping phase launches nothing
+    assert iters == r1[4][0]["iterations"] and ms["advance"] == 0
+    assert all(v > 0 for k, v in ms.items() if k != "advance")
     print("phase ms", ms)
 
 
