@@ -604,12 +604,33 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
     }
     const uint8_t* fe = flags + (size_t)e * stride;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
-    // count over the first M samples (four consecutive flags per thread)
     const int nt4 = 4 * (int)blockDim.x;
-    int cnt = 0;
-    for (int i0 = 4 * tid; i0 < iv.M; i0 += nt4)
+    // the thread's four consecutive flags of each of the first kTestPre
+    // passes, loaded together up front (one memory latency instead of one per
+    // pass); flag i of pass c is bit 8 (i - c nt4 - 4 tid) of pre[c]
+    constexpr int kTestPre = 4;
+    uint32_t pre[kTestPre];
+    const bool words = (reinterpret_cast<uintptr_t>(fe) & 3) == 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) cnt += (i0 + q < iv.M && fe[i0 + q]) ? 1 : 0;
+    for (int c = 0; c < kTestPre; ++c) {
+        const int i0 = c * nt4 + 4 * tid;
+        pre[c] = 0;
+        if (words && i0 + 4 <= iv.nS) {
+            pre[c] = *reinterpret_cast<const uint32_t*>(fe + i0);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (i0 + q < iv.nS) pre[c] |= (uint32_t)fe[i0 + q] << (8 * q);
+        }
+    }
+    auto flag_at = [&](int c, int i0, int q) -> bool {       // flag i0 + q of pass c (i0 + q < nS)
+        return c < kTestPre ? ((pre[c] >> (8 * q)) & 0xFFu) != 0 : fe[i0 + q] != 0;
+    };
+    // count over the first M samples (four consecutive flags per thread)
+    int cnt = 0;
+    for (int i0 = 4 * tid, c = 0; i0 < iv.M; i0 += nt4, ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cnt += (i0 + q < iv.M && flag_at(c, i0, q)) ? 1 : 0;
     cnt = wave_sum_i32(cnt);
     if (lane == 0) wsum[w] = cnt;
     __syncthreads();
@@ -623,7 +644,7 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
         if (tid == 0) s_base = 0;
         __syncthreads();
         const unsigned long long lt = (1ull << lane) - 1ull;
-        for (int c0 = 0; c0 < iv.nS; c0 += nt4) {
+        for (int c0 = 0, c = 0; c0 < iv.nS; c0 += nt4, ++c) {
             // flags i0 .. i0 + 3 of this thread; the wave's exclusive prefix of
             // the per-thread counts (0..4) from one ballot per count bit
             const int i0 = c0 + 4 * tid;
@@ -631,7 +652,7 @@ __global__ void __launch_bounds__(1024) k_test_select(const uint8_t* __restrict_
             int lc = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                f[q] = (i0 + q < iv.nS) && fe[i0 + q];
+                f[q] = (i0 + q < iv.nS) && flag_at(c, i0, q);
                 lc += f[q] ? 1 : 0;
             }
             const unsigned long long b0 = __ballot(lc & 1), b1 = __ballot(lc & 2), b2 = __ballot(lc & 4);
