@@ -94,12 +94,15 @@ int grid_dim(int n_obs) { return n_obs >= 256 ? 32 : (n_obs >= 32 ? 16 : 8); }
 // rewritten here: nothing needs to start at zero).
 ezo_status prep_obstacles_into(ezo_ctx* c, const ezo_robot* r, const float* obs, int n_obs, hipStream_t st,
                                void* rec, void* centre, void* geom, void* count, void* list, ObsView* ov,
-                               GridView* gv) {
+                               GridView* gv, const EdgeInit* ei = nullptr) {
     const int G = grid_dim(n_obs);
     // indices above 65535 do not fit the list type: then every cell scans all
     const bool lists = n_obs <= 65535;
-    hipLaunchKernelGGL(k_prep_obstacles, dim3(1), dim3(256), 0, st, obs, n_obs, (float4*)rec, (float4*)centre,
-                       (GridGeom*)geom, G, r ? r->r_max : 0.f, (int*)count, lists ? 0 : kGridCap + 1);
+    // the fused loop's edge start rides along as extra workgroups (ei)
+    const int init_wg = (ei && ei->n_edges > 0) ? (ei->n_edges + 255) / 256 : 0;
+    hipLaunchKernelGGL(k_prep_obstacles, dim3(1 + init_wg), dim3(256), 0, st, obs, n_obs, (float4*)rec,
+                       (float4*)centre, (GridGeom*)geom, G, r ? r->r_max : 0.f, (int*)count, lists ? 0 : kGridCap + 1,
+                       init_wg ? *ei : EdgeInit{});
     if (lists && n_obs > 0)
         hipLaunchKernelGGL(k_grid_scatter, dim3((unsigned)(((int64_t)n_obs * 64 + 255) / 256)), dim3(256), 0, st,
                            (const float4*)rec, n_obs, (const GridGeom*)geom, G, kGridCap, (int*)count,
@@ -122,7 +125,7 @@ ezo_status prep_obstacles_into(ezo_ctx* c, const ezo_robot* r, const float* obs,
 
 // The same in the context's workspace.
 ezo_status prep_obstacles(ezo_ctx* c, const ezo_robot* r, const float* obs, int n_obs, hipStream_t st,
-                          ObsView* ov, GridView* gv) {
+                          ObsView* ov, GridView* gv, const EdgeInit* ei = nullptr) {
     ezo_status s;
     void *rec, *centre, *geom, *count, *list;
     const size_t cells = (size_t)grid_dim(n_obs) * grid_dim(n_obs) * grid_dim(n_obs);
@@ -131,7 +134,7 @@ ezo_status prep_obstacles(ezo_ctx* c, const ezo_robot* r, const float* obs, int 
     if ((s = ezo_ws_get(c, W_GRID_GEOM, sizeof(GridGeom), &geom)) != EZO_OK) return s;
     if ((s = ezo_ws_get(c, W_GRID_COUNT, sizeof(int) * cells, &count)) != EZO_OK) return s;
     if ((s = ezo_ws_get(c, W_GRID_LIST, sizeof(unsigned short) * cells * kGridCap, &list)) != EZO_OK) return s;
-    return prep_obstacles_into(c, r, obs, n_obs, st, rec, centre, geom, count, list, ov, gv);
+    return prep_obstacles_into(c, r, obs, n_obs, st, rec, centre, geom, count, list, ov, gv, ei);
 }
 
 // ---------------------------------------------------------------------------
@@ -566,7 +569,7 @@ constexpr int kPathBatch = 128;
 ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, const GridView& gv, const float* edges,
                           int E, const ezo_params* p, int S_cap, int64_t stride, float* A, float* b, int* n_faces,
                           float* w_s, uint8_t* w_f, int* w_ci, int* w_nc, float* w_cs, float* w_ad, float* w_ts,
-                          uint8_t* w_pc, const int* w_active, hipStream_t st) {
+                          uint8_t* w_pc, const int* w_active, hipStream_t st, bool* launched) {
     if (!c->autotune) return EZO_OK;
     const int dof = r->dof, cap = p->face_capacity, cand_cap = p->n_p;
     const TuneKey kc = tune_key(c, r, TUNE_CHECK_FLAGS, ov.n, (int64_t)S_cap * E);
@@ -574,6 +577,7 @@ ezo_status tune_inflation(ezo_ctx* c, const ezo_robot* r, const ObsView& ov, con
     TileCfg g;
     const bool need_c = !ezo_tune_lookup(kc, &g), need_b = !ezo_tune_lookup(kb, &g);
     if (!need_c && !need_b) return EZO_OK;
+    *launched = true;                         // the runs below overwrite A, b, n_faces and the loop's state
     const int n_run = E;                      // the sampler's running-edge count during tuning
     HIP_TRY(c, hipMemcpyAsync((void*)w_active, &n_run, sizeof(int), hipMemcpyHostToDevice, st));
     HIP_TRY(c, hipStreamSynchronize(st));
@@ -1260,12 +1264,19 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
     }
     ObsView ov;
     GridView gv;
-    if ((s = prep_obstacles(c, r, obs, n_obs, st, &ov, &gv))) return s;
+    // the edges' start (P = D, statuses, statistics, the loop's row and
+    // count) is launched with the obstacle preparation; a tuning run in
+    // between overwrites it, and then it is launched again below
+    const EdgeInit ei{dof, r->q_lo, r->q_hi, edges, E, A, b, n_faces, cap, edge_status, (EdgeStatsDev*)w_st,
+                      (uint8_t*)w_pa, (int4*)w_k, (const int4*)w_tb, (int*)w_ac, skip};
+    if ((s = prep_obstacles(c, r, obs, n_obs, st, &ov, &gv, &ei))) return s;
+    bool tuned = false;
     if ((s = tune_inflation(c, r, ov, gv, edges, E, p, S_cap, stride, A, b, n_faces, (float*)w_s, (uint8_t*)w_f,
                             (int*)w_ci, (int*)w_nc, (float*)w_cs, (float*)w_ad, (float*)w_ts, (uint8_t*)w_pc,
-                            (const int*)w_ac, st)))
+                            (const int*)w_ac, st, &tuned)))
         return s;
     if (c->bisect_finalists.size() > 1 && !c->shape_trial) {
+        tuned = true;
         // The stand-in's bisection finalists, timed on whole inflations of
         // this call's edges: the loop's later iterations have fewer
         // candidates than any stand-in, which favours larger tiles.  The runs
@@ -1294,9 +1305,7 @@ static ezo_status inflate_core(ezo_ctx* c, const ezo_robot* r, const float* obs,
         if ((s = ezo_tune_search(c, kb, fin, st, run, &g))) return s;
     }
     c->bisect_finalists.clear();
-    hipLaunchKernelGGL(k_init_edges, dim3((E + 63) / 64), dim3(64), 0, st, dof, r->q_lo, r->q_hi, edges, E, A, b,
-                       n_faces, cap, edge_status, (EdgeStatsDev*)w_st, (uint8_t*)w_pa, (int4*)w_k, (const int4*)w_tb,
-                       (int*)w_ac, skip);
+    if (tuned) hipLaunchKernelGGL(k_init_edges, dim3((E + 63) / 64), dim3(64), 0, st, ei);
     HIP_TRY(c, hipGetLastError());
     IterArgs it{(const int4*)w_k, 0, 0, 0, 0};
     // the learned screen inside the loop: the fused forward pass for widths

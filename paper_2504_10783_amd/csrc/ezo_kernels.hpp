@@ -43,7 +43,72 @@ __device__ __forceinline__ bool edge_running(const int* status, int e) {
 }
 
 // ---------------------------------------------------------------------------
-// Obstacle preparation (one workgroup): bounding box of the obstacle centres
+// Start of the fused loop for edge e: P_e = D (box rows: +e_j <= hi_j, then
+// -e_j <= -lo_j), status RUNNING (-1), or INVALID (3) when a vertex is outside
+// D or not finite, or CONTAINED (4) with no rows when skip[e]; statistics
+// cleared.  Edge 0 also sets the loop's current row *cur = table[1]
+// (iteration 1) and the running-edge count *active = n_edges.
+// ---------------------------------------------------------------------------
+struct EdgeInit {
+    int dof;
+    const float* q_lo;
+    const float* q_hi;
+    const float* edges;
+    int n_edges;                       // 0: nothing to initialise
+    float* A;
+    float* bvec;
+    int* n_faces;
+    int cap;
+    int* status;
+    EdgeStatsDev* stats;
+    uint8_t* proj_any;
+    int4* cur;
+    const int4* table;
+    int* active;
+    const uint8_t* skip;
+};
+
+__device__ inline void init_edge(const EdgeInit& a, int e) {
+    const int dof = a.dof, cap = a.cap;
+    if (e == 0) {
+        *a.cur = a.table[1];
+        *a.active = a.n_edges;
+    }
+    if (e >= a.n_edges) return;
+    if (a.skip && a.skip[e]) {                  // not inflated: final from the start, no rows
+        a.n_faces[e] = 0;
+        a.status[e] = 4;                        // EZO_EDGE_CONTAINED
+        a.stats[e] = EdgeStatsDev{0, 0, 0, 0, 0, 0, 0};
+        a.proj_any[e] = 0;
+        return;
+    }
+    float* Ae = a.A + (size_t)e * cap * dof;
+    float* be = a.bvec + (size_t)e * cap;
+    for (int f = 0; f < 2 * dof; ++f) {
+        for (int j = 0; j < dof; ++j) Ae[(size_t)f * dof + j] = 0.f;
+        if (f < dof) {
+            Ae[(size_t)f * dof + f] = 1.f;
+            be[f] = a.q_hi[f];
+        } else {
+            Ae[(size_t)f * dof + (f - dof)] = -1.f;
+            be[f] = -a.q_lo[f - dof];
+        }
+    }
+    a.n_faces[e] = 2 * dof;
+    bool ok = true;
+    const float* v = a.edges + (size_t)e * 2 * dof;
+    for (int j = 0; j < 2 * dof; ++j) {
+        const float x = v[j];
+        const int jj = j % dof;
+        if (!(x == x) || isinf(x) || x < a.q_lo[jj] || x > a.q_hi[jj]) ok = false;
+    }
+    a.status[e] = ok ? -1 : 3;
+    a.stats[e] = EdgeStatsDev{0, 0, 0, 0, 0, 0, 0};
+    a.proj_any[e] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Obstacle preparation (workgroup 0): bounding box of the obstacle centres
 // and largest obstacle radius; records (o', r) with o' = o - centre of the
 // box; geometry of a G^3 grid over the box grown by
 // r_sphere_max + r_obstacle_max + slack.
@@ -53,7 +118,13 @@ constexpr float kGridSlack = 1e-4f;
 __global__ void __launch_bounds__(256) k_prep_obstacles(const float* __restrict__ obs, int n, float4* __restrict__ rec,
                                                         float4* __restrict__ centre, GridGeom* __restrict__ geom,
                                                         int G, float r_sphere_max, int* __restrict__ count,
-                                                        int count_init) {
+                                                        int count_init, EdgeInit ei) {
+    // workgroups past the first start the fused loop's edges (independent work
+    // that would otherwise take a launch of its own)
+    if (blockIdx.x > 0) {
+        init_edge(ei, (int)((blockIdx.x - 1) * blockDim.x + threadIdx.x));
+        return;
+    }
     // the grid's cell counts start at count_init (0 before k_grid_scatter)
     for (int k = threadIdx.x; k < G * G * G; k += blockDim.x) count[k] = count_init;
     __shared__ float red[7][256];
@@ -1202,52 +1273,8 @@ __global__ void k_cap_counts(const int* __restrict__ in, int* __restrict__ out, 
     if (e < n) out[e] = min(in[e], cap);
 }
 
-// Per edge: P = D (box rows), status RUNNING or INVALID, stats cleared; and
-// the loop's current row *cur = table[1] (iteration 1) and running-edge
-// count = n_edges.
-__global__ void k_init_edges(int dof, const float* __restrict__ q_lo, const float* __restrict__ q_hi,
-                             const float* __restrict__ edges, int n_edges, float* __restrict__ A,
-                             float* __restrict__ bvec, int* __restrict__ n_faces, int cap, int* __restrict__ status,
-                             EdgeStatsDev* __restrict__ stats, uint8_t* __restrict__ proj_any,
-                             int4* __restrict__ cur, const int4* __restrict__ table, int* __restrict__ active,
-                             const uint8_t* __restrict__ skip) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e == 0) {
-        *cur = table[1];
-        *active = n_edges;
-    }
-    if (e >= n_edges) return;
-    if (skip && skip[e]) {                      // not inflated: final from the start, no rows
-        n_faces[e] = 0;
-        status[e] = 4;                          // EZO_EDGE_CONTAINED
-        stats[e] = EdgeStatsDev{0, 0, 0, 0, 0, 0, 0};
-        proj_any[e] = 0;
-        return;
-    }
-    float* Ae = A + (size_t)e * cap * dof;
-    float* be = bvec + (size_t)e * cap;
-    for (int f = 0; f < 2 * dof; ++f) {
-        for (int j = 0; j < dof; ++j) Ae[(size_t)f * dof + j] = 0.f;
-        if (f < dof) {
-            Ae[(size_t)f * dof + f] = 1.f;
-            be[f] = q_hi[f];
-        } else {
-            Ae[(size_t)f * dof + (f - dof)] = -1.f;
-            be[f] = -q_lo[f - dof];
-        }
-    }
-    n_faces[e] = 2 * dof;
-    bool ok = true;
-    const float* v = edges + (size_t)e * 2 * dof;
-    for (int j = 0; j < 2 * dof; ++j) {
-        const float x = v[j];
-        const int jj = j % dof;
-        if (!(x == x) || isinf(x) || x < q_lo[jj] || x > q_hi[jj]) ok = false;
-    }
-    status[e] = ok ? -1 : 3;
-    stats[e] = EdgeStatsDev{0, 0, 0, 0, 0, 0, 0};
-    proj_any[e] = 0;
-}
+// The fused loop's start, one thread per edge (init_edge above).
+__global__ void k_init_edges(EdgeInit ei) { init_edge(ei, blockIdx.x * blockDim.x + threadIdx.x); }
 
 // End of an iteration: at k == max_iters every running edge becomes
 // MAX_ITERS (1); count running edges; the current row moves to table[k + 1]
