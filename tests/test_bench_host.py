@@ -6,6 +6,7 @@ for the same kernel sources, N_p and kernel instance."""
 import argparse
 import json
 import os
+import re
 import sys
 from types import SimpleNamespace
 
@@ -94,3 +95,17 @@ def test_committed_summaries_match_only_their_own_run():
         assert bench.measured_traffic(w, inst, rec["n_p"] + 1) is None
         assert bench.measured_traffic(w, "ezo::k_project_bisect<3, 9, false>", rec["n_p"]) is None
         assert bench.measured_valu(w, inst, rec["n_p"] + 1) is None
+
+
+def test_committed_summaries_have_per_launch_rows():
+    """Every per-launch summary of the two inflation workloads lists the
+    bisection among its rows, and the trace splits its dispatches into the
+    bench's calls (one warm-up, then as many timed as phase-timed)."""
+    for w in ("dof7", "batched"):
+        for kind in ("hbm_traffic", "valu_fp32", "stall", "kernel_trace"):
+            text = open(os.path.join(ROOT, "profiles", f"{kind}__{w}_inflate.md")).read()
+            rows = [l for l in text.splitlines() if l.startswith("| ") and "k_project_bisect" in l]
+            assert rows, (kind, w)
+        text = open(os.path.join(ROOT, "profiles", f"kernel_trace__{w}_inflate.md")).read()
+        m = re.search(r"\((\d+) inflation calls: 1 warm-up, (\d+) timed graph replays, (\d+) phase-timed\)", text)
+        assert m and int(m.group(2)) > 0 and int(m.group(2)) == int(m.group(3)) and int(m.group(1)) == 1 + 2 * int(m.group(2))
