@@ -98,11 +98,13 @@ ezo_status prep_obstacles_into(ezo_ctx* c, const ezo_robot* r, const float* obs,
     const int G = grid_dim(n_obs);
     // indices above 65535 do not fit the list type: then every cell scans all
     const bool lists = n_obs <= 65535;
-    // the fused loop's edge start rides along as extra workgroups (ei)
+    // the cell counts are cleared by extra workgroups (2048 cells each), and
+    // the fused loop's edge start rides along as further workgroups (ei)
+    const int clear_wg = (G * G * G + 2047) / 2048;
     const int init_wg = (ei && ei->n_edges > 0) ? (ei->n_edges + 255) / 256 : 0;
-    hipLaunchKernelGGL(k_prep_obstacles, dim3(1 + init_wg), dim3(256), 0, st, obs, n_obs, (float4*)rec,
+    hipLaunchKernelGGL(k_prep_obstacles, dim3(1 + clear_wg + init_wg), dim3(256), 0, st, obs, n_obs, (float4*)rec,
                        (float4*)centre, (GridGeom*)geom, G, r ? r->r_max : 0.f, (int*)count, lists ? 0 : kGridCap + 1,
-                       init_wg ? *ei : EdgeInit{});
+                       clear_wg, init_wg ? *ei : EdgeInit{});
     if (lists && n_obs > 0)
         hipLaunchKernelGGL(k_grid_scatter, dim3((unsigned)(((int64_t)n_obs * 64 + 255) / 256)), dim3(256), 0, st,
                            (const float4*)rec, n_obs, (const GridGeom*)geom, G, kGridCap, (int*)count,

@@ -118,15 +118,23 @@ constexpr float kGridSlack = 1e-4f;
 __global__ void __launch_bounds__(256) k_prep_obstacles(const float* __restrict__ obs, int n, float4* __restrict__ rec,
                                                         float4* __restrict__ centre, GridGeom* __restrict__ geom,
                                                         int G, float r_sphere_max, int* __restrict__ count,
-                                                        int count_init, EdgeInit ei) {
-    // workgroups past the first start the fused loop's edges (independent work
-    // that would otherwise take a launch of its own)
-    if (blockIdx.x > 0) {
-        init_edge(ei, (int)((blockIdx.x - 1) * blockDim.x + threadIdx.x));
+                                                        int count_init, int clear_wg, EdgeInit ei) {
+    // Workgroups 1 .. clear_wg set the grid's cell counts to count_init (0
+    // before k_grid_scatter), the ones after them start the fused loop's edges
+    // (independent work that would otherwise take launches of its own);
+    // workgroup 0 does the rest (and the counts too when clear_wg is 0).
+    const int cells = G * G * G;
+    if (blockIdx.x > 0 && (int)blockIdx.x <= clear_wg) {
+        for (int k = (blockIdx.x - 1) * blockDim.x + threadIdx.x; k < cells; k += clear_wg * blockDim.x)
+            count[k] = count_init;
         return;
     }
-    // the grid's cell counts start at count_init (0 before k_grid_scatter)
-    for (int k = threadIdx.x; k < G * G * G; k += blockDim.x) count[k] = count_init;
+    if ((int)blockIdx.x > clear_wg) {
+        init_edge(ei, (int)((blockIdx.x - 1 - clear_wg) * blockDim.x + threadIdx.x));
+        return;
+    }
+    if (clear_wg == 0)
+        for (int k = threadIdx.x; k < cells; k += blockDim.x) count[k] = count_init;
     __shared__ float red[7][256];
     const int tid = threadIdx.x;
     float mn[3] = {kHuge, kHuge, kHuge}, mx[3] = {-kHuge, -kHuge, -kHuge}, rmax = 0.f;
