@@ -328,13 +328,20 @@ __global__ void __launch_bounds__(256) k_centres(RobotView rb, ObsView ob, const
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int sample_chunk(int L) { return 2 * L; }        // steps drawn ahead (L >= 4)
 __host__ __device__ constexpr int sample_dir_stride(int D) { return D + 4; }   // u[D], chord word, pad
+// Words per walk group's block of drawn steps: one more than the steps' words,
+// so that the groups of a wave, each reading its own block, start on distinct
+// LDS banks (an even block size put them on the same banks).
+__host__ __device__ constexpr int sample_group_words(int D, int L) { return sample_chunk(L) * sample_dir_stride(D) + 1; }
 
-// LDS bytes of k_sample: rows, then (L >= 4) the drawn directions (the same
-// size for every L >= 4).
+// LDS bytes of k_sample: rows, then (L >= 4) the drawn directions, sized for
+// the most walk groups (L = 4) so that one size serves every L >= 4 (the fused
+// loop's sampler picks L at run time).
 __host__ __device__ inline size_t sample_smem_bytes(int D, int L, int cap, int threads) {
     const size_t rows = (sizeof(float) * (size_t)cap * (D + 1) + 15) & ~(size_t)15;
-    return rows + (L >= 4 ? sizeof(float) * (size_t)(threads / L) * sample_chunk(L) * sample_dir_stride(D) : 0);
+    return rows + (L >= 4 ? sizeof(float) * (size_t)(threads / 4) * sample_group_words(D, 4) : 0);
 }
+static_assert(16 * sample_group_words(7, 16) <= 64 * sample_group_words(7, 4) &&
+              32 * sample_group_words(7, 8) <= 64 * sample_group_words(7, 4), "directions fit the L = 4 size");
 
 // Normalised direction u (zero beyond dof) and chord word of one step.
 template <int D>
@@ -534,7 +541,7 @@ __device__ __forceinline__ void sample_block(char* smem, int dof, const float* _
     } else {
         constexpr int SD = sample_dir_stride(D), CH = sample_chunk(L);
         float* dirs = reinterpret_cast<float*>(smem + sample_smem_bytes(D, 1, cap, 0)) +
-                      (size_t)(threadIdx.x / L) * CH * SD;
+                      (size_t)(threadIdx.x / L) * sample_group_words(D, L);
         for (int s0 = 1; s0 <= n_mix; s0 += CH) {
             const int ns = min(CH, n_mix - s0 + 1);
             // this lane's two steps of the chunk, drawn side by side (independent
